@@ -1,0 +1,269 @@
+/*
+ * tsvdm.h -- C ABI of the MI355X (gfx950) star-M truncated tensor SVD.
+ *
+ * The library computes the data-parallel hot path of the star-M t-SVD
+ * (Hussain et al., "High-Performance star-M SVD for Big Data Compression"):
+ *
+ *   transform      A-hat = A x_3 M                      Section 2.1, Algorithm 1
+ *   slice SVDs     A-hat_i = U_i S_i V_i^T, i = 1..n     Algorithm 1, Section 3.2
+ *   truncation     t-SVDM-I: rank k on every slice       Section 3.3
+ *                  t-SVDM-II: global tolerance eps       Algorithm 2
+ *   factors        U_i(:, 1:rho_i), s_i, G_i = S V^T     Algorithm 2, Section 3.4
+ *   reconstruct    A_rho = (U_i G_i)_i x_3 M^{-1}        Section 2.1
+ *   adjoint        d/dA and d/dM of the truncation loss  (not in the paper)
+ *
+ * Conventions (all entry points)
+ * ------------------------------
+ *  - Tensors are column-major (Section 3): element (a, b, i) of an m x p x n
+ *    tensor is at offset a + b*m + i*m*p, so frontal slice i is a contiguous
+ *    m x p column-major matrix.  r = min(m, p).
+ *  - Every data pointer is a DEVICE pointer owned by the caller.  The library
+ *    never frees caller memory and keeps no pointer after a call returns
+ *    (batch plans keep only host data).
+ *  - Every compute call is enqueued on `stream` (a hipStream_t passed as
+ *    void*; NULL = the default stream) and returns before the work finishes.
+ *    Results are valid after the stream is synchronised.
+ *  - Errors that can be seen on the host (bad sizes, null pointers, a too
+ *    small workspace, an unsupported dtype) return a negative tsvdm_status
+ *    BEFORE anything is launched; tsvdm_last_error() then holds a message
+ *    (thread-local).  Conditions seen on the device (Jacobi not converged,
+ *    a non-finite value, an undersized packed output) are written as a
+ *    tsvdm_status into the caller's device status word and never abort.
+ *  - Workspace: each entry point that needs scratch memory takes (ws, ws_bytes);
+ *    the required size comes from the matching *_workspace_size query.
+ *    Workspace contents need not be initialised and are not preserved.
+ *  - Calls that share a workspace or outputs must not overlap in time.
+ */
+#ifndef TSVDM_H
+#define TSVDM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    TSVDM_OK = 0,
+    TSVDM_E_ARG = -1,         /* null pointer, bad flag or tolerance        */
+    TSVDM_E_SHAPE = -2,       /* a size is <= 0 or too large                */
+    TSVDM_E_NOT_ORTHO = -3,   /* M is not a multiple of an orthogonal matrix */
+    TSVDM_E_WORKSPACE = -4,   /* ws_bytes smaller than the query returned    */
+    TSVDM_E_NOCONV = -5,      /* (device) Jacobi hit max_sweeps             */
+    TSVDM_E_NONFINITE = -6,   /* (device) NaN or Inf met                    */
+    TSVDM_E_HIP = -7,         /* a HIP runtime call failed                  */
+    TSVDM_E_UNSUPPORTED = -8, /* dtype or option not available              */
+    TSVDM_E_CAPACITY = -9     /* (device) packed output smaller than sum rho */
+} tsvdm_status;
+
+/* Element types.  BF16X3 is a compute mode only: each FP32 operand x is split
+ * into hi = bf16(x) and lo = bf16(x - hi), and the product is formed from the
+ * three MFMA products hi*hi + hi*lo + lo*hi with FP32 accumulation. */
+typedef enum {
+    TSVDM_F64 = 0,
+    TSVDM_F32 = 1,
+    TSVDM_BF16 = 2,
+    TSVDM_BF16X3 = 3
+} tsvdm_dtype;
+
+/* --------------------------------------------------------------------- */
+/* library                                                               */
+/* --------------------------------------------------------------------- */
+
+/* Library version as 10000*major + 100*minor + patch. */
+int tsvdm_version(void);
+
+/* Message of the last failing call on this thread ("" if none).  The string
+ * stays valid until the next tsvdm_* call on the same thread. */
+const char* tsvdm_last_error(void);
+
+/* Host-side check that the n x n column-major FP64 matrix M_host is c*Q with
+ * Q orthogonal: max |M^T M / c^2 - I| <= tol with c^2 = mean(diag(M^T M)).
+ * Algorithm 2 requires such an M and Section 3 restricts to orthonormal M.
+ * On success writes c^2 to *scale_sq (may be NULL) and returns TSVDM_OK,
+ * else TSVDM_E_NOT_ORTHO.  Reads host memory only; launches nothing. */
+int tsvdm_check_transform(const double* M_host, int64_t n, double tol,
+                          double* scale_sq);
+
+/* --------------------------------------------------------------------- */
+/* mode-3 transform (Section 2.1; Section 3.1, last-mode TTM as one GEMM) */
+/* --------------------------------------------------------------------- */
+
+/* Y = X x_3 (scale * op(M)):  Y(:,:,i) = scale * sum_l op(M)[i,l] X(:,:,l),
+ * op(M) = M (transpose = 0) or M^T (transpose = 1).  The forward transform
+ * is (transpose = 0, scale = 1); the back-transform of an orthonormal M is
+ * (transpose = 1, scale = 1) and of M = c*Q is (1, 1/c^2).
+ *   X        device, x_dtype (F64 or F32), m*p*n elements, column-major.
+ *   Y        device, y_dtype (F64 or F32), m*p*n elements; must not alias X.
+ *   M        device, FP64, n x n column-major.
+ *   compute  F64: FP64 MFMA; F32: FP32 MFMA; BF16 / BF16X3: BF16 MFMA with
+ *            FP32 accumulation (y_dtype must then be F32).
+ * ws: tsvdm_transform_workspace_size bytes (holds op(M) in compute type). */
+int tsvdm_transform_workspace_size(int64_t n, size_t* bytes);
+int tsvdm_transform(const void* X, int x_dtype, void* Y, int y_dtype,
+                    int64_t m, int64_t p, int64_t n,
+                    const double* M, int transpose, double scale,
+                    int compute, void* ws, size_t ws_bytes, void* stream);
+
+/* --------------------------------------------------------------------- */
+/* slice SVDs (Algorithm 1; Section 3.2)                                 */
+/* --------------------------------------------------------------------- */
+
+/* One-sided block Jacobi SVD of every frontal slice of A_hat (m x p x n,
+ * dtype F64 or F32), in place.
+ * The r = min(m, p) "Jacobi vectors" are the columns of the slice when
+ * m >= p and its rows when m < p.  On return:
+ *   A_hat    the vectors are mutually orthogonal: for m >= p column j of
+ *            slice i is sigma_j u_j; for m < p row j is sigma_j v_j^T.
+ *   W        (r x r x n, same dtype) the accumulated rotations: V when
+ *            m >= p, U when m < p (so A_hat_i = U (S V^T) or (U S) V^T).
+ *   s2       (r x n, FP64) squared norms of the final vectors, i.e. the
+ *            squared singular values in the same (unsorted) order.
+ *   status   (device int32, 1 element) TSVDM_OK or TSVDM_E_NOCONV /
+ *            TSVDM_E_NONFINITE.
+ * Options:
+ *   block    Jacobi block width b (16 or 32; 0 = autotuned default).
+ *   max_sweeps  sweep limit (0 = 40).
+ *   tol      convergence threshold on |cos| between any two vectors, tested
+ *            in FP64 (0 = default: 1e-14 for F64, 2e-6 for F32).
+ *   host_poll   1: read a device flag after every sweep and stop early
+ *            (synchronises the stream once per sweep); 0: launch max_sweeps
+ *            sweeps whose kernels return at once after convergence
+ *            (graph-capturable).
+ * Rotation angles, the convergence test and s2 are computed in FP64 for
+ * both dtypes. */
+int tsvdm_slice_svd_workspace_size(int64_t m, int64_t p, int64_t n, int dtype,
+                                   size_t* bytes);
+int tsvdm_slice_svd(void* A_hat, int dtype, int64_t m, int64_t p, int64_t n,
+                    void* W, double* s2, int32_t* status,
+                    int block, int max_sweeps, double tol, int host_poll,
+                    void* ws, size_t ws_bytes, void* stream);
+
+/* --------------------------------------------------------------------- */
+/* truncation                                                            */
+/* --------------------------------------------------------------------- */
+
+/* t-SVDM-I (Section 3.3): rho[i] = min(k, r) for every slice and
+ * offsets[i] = sum_{j<i} rho[j] (n+1 entries, offsets[n] = total).
+ * rho: device int32[n]; offsets: device int64[n+1]. */
+int tsvdm_truncate_rank(int64_t k, int64_t r, int64_t n,
+                        int32_t* rho, int64_t* offsets, void* stream);
+
+/* t-SVDM-II (Algorithm 2).  s2: device FP64 [r x n] squared singular values
+ * (any order within a slice).  With v the ascending sort of all n*r values,
+ * w_J = v_1 + ... + v_J and W = the sum of all values:
+ *   J   = the largest J with w_J / W < eps*eps  (J = 0 if none),
+ *   tau = v_J (-inf if J = 0),
+ *   rho[i] = #{ j : s2[j + i*r] > tau }  (every value equal to tau dropped).
+ * Sums are double-double (about 106-bit) and rounded once to FP64, so the
+ * decision matches exact arithmetic except within ~1e-30 of a tie.  A zero
+ * tensor (W = 0) gives rho = 0.
+ * stats (device FP64[4]): tau, discarded energy (sum of dropped values),
+ * W, and J (as a double).  eps must lie in (0, 1). */
+int tsvdm_truncate_tol_workspace_size(int64_t r, int64_t n, size_t* bytes);
+int tsvdm_truncate_tol(const double* s2, int64_t r, int64_t n, double eps,
+                       int32_t* rho, int64_t* offsets, double* stats,
+                       void* ws, size_t ws_bytes, void* stream);
+
+/* --------------------------------------------------------------------- */
+/* factor emission (Algorithm 2's final loop; Section 3.4 packed layout) */
+/* --------------------------------------------------------------------- */
+
+/* From the output of tsvdm_slice_svd, write for each slice i the rho[i]
+ * leading triplets in descending sigma order, packed without padding:
+ *   U_pk : column-major m x rho_i block at element offset m*offsets[i]
+ *   G_pk : column-major rho_i x p block (G_i = S_i V_i^T) at p*offsets[i]
+ *   S_pk : rho_i singular values at offsets[i]
+ * All three in `dtype` (the dtype of A_hat / W).  capacity = number of
+ * triplets the buffers hold (U_pk has m*capacity elements, ...); if
+ * offsets[n] > capacity nothing beyond capacity is written and *status is
+ * set to TSVDM_E_CAPACITY.  A kept singular value that is exactly 0 (only
+ * possible for t-SVDM-I) gets a zero column in U_pk.
+ * ws: tsvdm_pack_workspace_size bytes. */
+int tsvdm_pack_workspace_size(int64_t m, int64_t p, int64_t n, size_t* bytes);
+int tsvdm_pack(const void* A_hat, const void* W, const double* s2, int dtype,
+               int64_t m, int64_t p, int64_t n,
+               const int32_t* rho, const int64_t* offsets, int64_t capacity,
+               void* U_pk, void* G_pk, void* S_pk, int32_t* status,
+               void* ws, size_t ws_bytes, void* stream);
+
+/* --------------------------------------------------------------------- */
+/* reconstruction (Section 2.1, third step of the star-M product)        */
+/* --------------------------------------------------------------------- */
+
+/* C_hat_i = U_pk_i * G_pk_i (variable-rank batched GEMM, `dtype`), then
+ * A_rec = C_hat x_3 (scale * M^T) written in out_dtype (F64 or F32);
+ * scale = 1 for orthonormal M, 1/c^2 for M = c*Q.  U_pk, G_pk use the
+ * packed layout of tsvdm_pack with the same `capacity`; a slice whose block
+ * would end beyond capacity contributes zero.  C_hat lives in the workspace
+ * (m*p*n elements of `dtype`).  compute selects the back-TTM arithmetic as
+ * in tsvdm_transform. */
+int tsvdm_reconstruct_workspace_size(int64_t m, int64_t p, int64_t n,
+                                     int dtype, size_t* bytes);
+int tsvdm_reconstruct(const void* U_pk, const void* G_pk, int dtype,
+                      int64_t m, int64_t p, int64_t n,
+                      const int32_t* rho, const int64_t* offsets, int64_t capacity,
+                      const double* M, double scale, void* A_rec,
+                      int out_dtype, int compute,
+                      void* ws, size_t ws_bytes, void* stream);
+
+/* --------------------------------------------------------------------- */
+/* error report                                                          */
+/* --------------------------------------------------------------------- */
+
+/* out (device FP64[2]) = { sum (A - B)^2, sum A^2 } over `count` elements,
+ * accumulated in FP64 in a fixed order (deterministic).  A, B are F64 or
+ * F32 (independently).  ws: tsvdm_error_workspace_size bytes. */
+int tsvdm_error_workspace_size(int64_t count, size_t* bytes);
+int tsvdm_error(const void* A, int a_dtype, const void* B, int b_dtype,
+                int64_t count, double* out, void* ws, size_t ws_bytes,
+                void* stream);
+
+/* --------------------------------------------------------------------- */
+/* adjoint of the truncation loss (not in the paper)                     */
+/* --------------------------------------------------------------------- */
+
+/* L(A, M) = sum_i sum_{j > k} sigma_ij^2 with sigma the singular values of
+ * the slices of A x_3 M (for orthogonal M, L = ||A - A_k||_F^2).  With
+ * R-hat_i the rank-k tail of slice i (recomputed here: transform, Jacobi,
+ * tail reconstruction; the factors are not stored between calls):
+ *   dA = 2 g * (R-hat x_3 M^T)            (m x p x n, `dtype`; may be NULL)
+ *   dM = 2 g * R-hat_(3) A_(3)^T          (n x n FP64 column-major; may be NULL)
+ *   loss (device FP64[1]) = L.
+ * A: device, F32 or F64 (dtype also selects the compute precision).
+ * M: device FP64 n x n.  Requires sigma_k > sigma_{k+1} in every slice for
+ * the gradient to exist (not checked).  status as in tsvdm_slice_svd. */
+int tsvdm_backward_workspace_size(int64_t m, int64_t p, int64_t n, int dtype,
+                                  size_t* bytes);
+int tsvdm_backward(const void* A, int dtype, int64_t m, int64_t p, int64_t n,
+                   const double* M, int64_t k, double g,
+                   void* dA, double* dM, double* loss, int32_t* status,
+                   void* ws, size_t ws_bytes, void* stream);
+
+/* --------------------------------------------------------------------- */
+/* kernel statistics (for roofline reporting)                            */
+/* --------------------------------------------------------------------- */
+
+/* With statistics on, tsvdm_slice_svd records HIP events on its stream
+ * around the Jacobi round launches of every sweep, and at the end of the
+ * call waits for them and copies the device pair counters to the host (one
+ * extra synchronisation per call).  Totals accumulate process-wide until
+ * tsvdm_stats_reset:
+ *   launches    Jacobi round kernels launched,
+ *   ms          summed event time over those launches (includes the small
+ *               gaps between back-to-back launches),
+ *   pairs_gram  block pairs that only formed their Gram matrix (converged),
+ *   pairs_rot   block pairs that also rotated their vectors,
+ *   pair_width  2b of the last call (the rows of each pair's Gram matrix).
+ * Thread-safe; host only. */
+int tsvdm_stats_enable(int on);
+int tsvdm_stats_reset(void);
+int tsvdm_stats_get(int64_t* launches, double* ms, int64_t* pairs_gram,
+                    int64_t* pairs_rot, int32_t* pair_width);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TSVDM_H */

@@ -1,0 +1,520 @@
+// Slice-wise SVD by one-sided block Jacobi (Algorithm 1's per-slice SVD;
+// Section 3.2 "parallel slices" design carried to the GPU).
+//
+// Each frontal slice contributes r = min(m, p) vectors of length L = max(m, p)
+// (columns if m >= p, rows otherwise).  The r vectors are split into blocks of
+// b = NB2/2 and a sweep pairs every two blocks once, using the circle
+// (round-robin) tournament so that the nb/2 pairs of one round are disjoint
+// and run as independent workgroups.  For a pair the workgroup
+//   1. forms the NB2 x NB2 Gram matrix H of its vectors on MFMA,
+//   2. measures max |cos| between its vectors from H (FP64) and, if that is
+//      above tol, diagonalises H with one cyclic Jacobi sweep in FP64 (LDS),
+//   3. applies the accumulated rotation Q to its vectors and to the matching
+//      columns of W on MFMA:  vectors <- Q^T vectors,  W <- W Q.
+// Vectors stay at their positions (no reordering inside a pair), which keeps
+// the tournament's pair coverage intact.  A slice is converged once a whole
+// sweep saw max |cos| <= tol; later rounds return at once for it.
+#include <mutex>
+#include <vector>
+
+#include "common.h"
+#include "kernels.h"
+
+namespace tsvdm {
+
+// ---------------------------------------------------------------- statistics
+namespace {
+std::mutex g_stats_mu;
+bool g_stats_on = false;
+int64_t g_launches = 0, g_pairs_gram = 0, g_pairs_rot = 0;
+double g_ms = 0.0;
+int g_width = 0;
+}  // namespace
+
+bool stats_enabled() {
+    std::lock_guard<std::mutex> lk(g_stats_mu);
+    return g_stats_on;
+}
+void stats_set(bool on) {
+    std::lock_guard<std::mutex> lk(g_stats_mu);
+    g_stats_on = on;
+}
+void stats_reset() {
+    std::lock_guard<std::mutex> lk(g_stats_mu);
+    g_launches = g_pairs_gram = g_pairs_rot = 0;
+    g_ms = 0.0;
+}
+void stats_add(int64_t launches, double ms, int64_t pg, int64_t pr, int width) {
+    std::lock_guard<std::mutex> lk(g_stats_mu);
+    g_launches += launches;
+    g_ms += ms;
+    g_pairs_gram += pg;
+    g_pairs_rot += pr;
+    g_width = width;
+}
+void stats_get(int64_t* launches, double* ms, int64_t* pg, int64_t* pr, int32_t* width) {
+    std::lock_guard<std::mutex> lk(g_stats_mu);
+    if (launches) *launches = g_launches;
+    if (ms) *ms = g_ms;
+    if (pg) *pg = g_pairs_gram;
+    if (pr) *pr = g_pairs_rot;
+    if (width) *width = g_width;
+}
+
+namespace {
+
+constexpr int TC = 64;          // vector elements per staged chunk
+constexpr int LDP = TC + 1;     // padded LDS row of a chunk
+
+__device__ __forceinline__ int circle_player(int seat, int round, int N) {
+    return seat == 0 ? 0 : ((seat - 1 + round) % (N - 1)) + 1;
+}
+
+template <class T>
+__global__ void jacobi_init(T* __restrict__ W, int64_t r, int64_t n, JacobiCtl* __restrict__ ctl,
+                            int* __restrict__ remaining, int max_sweeps,
+                            unsigned long long* __restrict__ pair_counts,
+                            int32_t* __restrict__ status) {
+    const int64_t rr = r * r;
+    const int64_t total = rr * n;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total; idx += stride) {
+        int64_t e = idx % rr;
+        W[idx] = (e % r == e / r) ? T(1) : T(0);
+    }
+    for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < n; idx += stride) {
+        JacobiCtl c;
+        c.maxcos_bits = 0ull; c.done = 0; c.sweeps = 0; c.nonfinite = 0; c.pad = 0;
+        ctl[idx] = c;
+    }
+    if (blockIdx.x == 0) {
+        for (int i = threadIdx.x; i < max_sweeps; i += blockDim.x) remaining[i] = 0;
+        if (threadIdx.x == 0) {
+            *status = TSVDM_OK;
+            pair_counts[0] = 0ull;
+            pair_counts[1] = 0ull;
+        }
+    }
+}
+
+template <class T, int NB2>
+struct RoundSmem {
+    static constexpr int NT = NB2 / 16;
+    static constexpr size_t ts_bytes = sizeof(T) * NB2 * LDP;
+    static constexpr size_t qf_bytes = sizeof(T) == 4 ? sizeof(T) * NB2 * (NB2 + 1) : 0;
+    static constexpr size_t hs_bytes = sizeof(double) * NB2 * (NB2 + 1);
+    static constexpr size_t buf0 = (ts_bytes + qf_bytes > hs_bytes) ? ts_bytes + qf_bytes : hs_bytes;
+    static constexpr size_t total = buf0 + hs_bytes;  // + Qs (double)
+};
+
+template <class T, int NB2>
+__global__ __launch_bounds__(256) void jacobi_round(T* __restrict__ A, T* __restrict__ W, SliceGeom g,
+                                                    int nbe, int rnd, JacobiCtl* __restrict__ ctl,
+                                                    double tol,
+                                                    unsigned long long* __restrict__ pair_counts) {
+    typedef RoundSmem<T, NB2> SM;
+    typedef typename Acc<T>::type AccT;
+    constexpr int B = NB2 / 2;
+    constexpr int NT = SM::NT;
+    constexpr int HP = NB2 + 1;
+
+    __shared__ __align__(16) char smem[SM::total];
+    __shared__ double rot_c[NB2 / 2], rot_s[NB2 / 2];
+    __shared__ int rot_p[NB2 / 2], rot_q[NB2 / 2];
+    __shared__ double red[8];
+    __shared__ int flag_nf;
+
+    T* Ts = reinterpret_cast<T*>(smem);                          // [NB2][LDP]
+    double* Hs = reinterpret_cast<double*>(smem);                // [NB2][HP] (phase 2)
+    T* Qf = reinterpret_cast<T*>(smem + SM::ts_bytes);           // [NB2][HP] (phase 3, float)
+    double* Qs = reinterpret_cast<double*>(smem + SM::buf0);     // [NB2][HP]
+
+    const int npairs = nbe / 2;
+    const int64_t s = blockIdx.x / npairs;
+    const int k = blockIdx.x % npairs;
+    if (ctl[s].done) return;
+
+    const int I = circle_player(k, rnd, nbe);
+    const int J = circle_player(nbe - 1 - k, rnd, nbe);
+    const int64_t r = g.r, L = g.L;
+    T* Ab = A + s * g.m * g.p;
+    T* Wb = W + s * r * r;
+
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, wave = tid >> 6;
+    const int lr = lane & 15, lg = lane >> 4;
+
+    auto gidx = [&](int a) -> int64_t { return a < B ? (int64_t)I * B + a : (int64_t)J * B + (a - B); };
+
+    // stage vectors [a][t0 .. t0+TC) of a strided family into Ts
+    auto load_chunk = [&](const T* base, int64_t vs, int64_t es, int64_t t0, int64_t len) {
+        if (es == 1) {
+            for (int e = tid; e < NB2 * TC; e += 256) {
+                int t = e % TC, a = e / TC;
+                int64_t gi = gidx(a), tt = t0 + t;
+                Ts[a * LDP + t] = (gi < r && tt < len) ? base[gi * vs + tt] : T(0);
+            }
+        } else {
+            for (int e = tid; e < NB2 * TC; e += 256) {
+                int a = e % NB2, t = e / NB2;
+                int64_t gi = gidx(a), tt = t0 + t;
+                Ts[a * LDP + t] = (gi < r && tt < len) ? base[gi * vs + tt * es] : T(0);
+            }
+        }
+    };
+    auto store_chunk = [&](T* base, int64_t vs, int64_t es, int64_t t0, int64_t len) {
+        if (es == 1) {
+            for (int e = tid; e < NB2 * TC; e += 256) {
+                int t = e % TC, a = e / TC;
+                int64_t gi = gidx(a), tt = t0 + t;
+                if (gi < r && tt < len) base[gi * vs + tt] = Ts[a * LDP + t];
+            }
+        } else {
+            for (int e = tid; e < NB2 * TC; e += 256) {
+                int a = e % NB2, t = e / NB2;
+                int64_t gi = gidx(a), tt = t0 + t;
+                if (gi < r && tt < len) base[gi * vs + tt * es] = Ts[a * LDP + t];
+            }
+        }
+    };
+
+    // ---------------- phase 1: Gram matrix H = V V^T of the pair (MFMA)
+    constexpr int TPW = NT * NT / 4;  // H tiles per wave
+    AccT hacc[TPW];
+#pragma unroll
+    for (int j = 0; j < TPW; ++j) hacc[j] = zero4<AccT>();
+
+    for (int64_t t0 = 0; t0 < L; t0 += TC) {
+        load_chunk(Ab, g.vs, g.es, t0, L);
+        __syncthreads();
+#pragma unroll
+        for (int kk = 0; kk < TC; kk += 4) {
+#pragma unroll
+            for (int j = 0; j < TPW; ++j) {
+                const int q = wave * TPW + j, tr = q / NT, tc = q % NT;
+                T a = Ts[(tr * 16 + lr) * LDP + kk + lg];
+                T b = Ts[(tc * 16 + lr) * LDP + kk + lg];
+                hacc[j] = mfma(a, b, hacc[j]);
+            }
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int j = 0; j < TPW; ++j) {
+        const int q = wave * TPW + j, tr = q / NT, tc = q % NT;
+#pragma unroll
+        for (int v = 0; v < 4; ++v)
+            Hs[(tr * 16 + lg * 4 + v) * HP + tc * 16 + lr] = (double)hacc[j][v];
+    }
+    if (tid == 0) flag_nf = 0;
+    __syncthreads();
+
+    // ---------------- convergence measure (FP64): max |cos| over valid pairs
+    double mc = 0.0;
+    for (int e = tid; e < NB2 * NB2; e += 256) {
+        int a = e / NB2, c = e % NB2;
+        double h = Hs[a * HP + c];
+        if (!isfinite(h)) flag_nf = 1;
+        if (a < c && gidx(a) < r && gidx(c) < r) {
+            double d = fabs(Hs[a * HP + a]) * fabs(Hs[c * HP + c]);
+            if (d > 0.0) mc = fmax(mc, fabs(h) / sqrt(d));
+        }
+    }
+    for (int off = 32; off > 0; off >>= 1) mc = fmax(mc, __shfl_xor(mc, off));
+    if (lane == 0) red[wave] = mc;
+    __syncthreads();
+    mc = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
+    const bool nonfinite = flag_nf != 0;
+    const bool rotate = !nonfinite && (mc > tol);
+    if (tid == 0) {
+        if (nonfinite) {
+            atomicExch(&ctl[s].nonfinite, 1);
+        } else {
+            atomicMax(&ctl[s].maxcos_bits, (unsigned long long)__double_as_longlong(mc));
+        }
+        atomicAdd(&pair_counts[rotate ? 1 : 0], 1ull);
+    }
+    if (!rotate) return;  // uniform across the block
+
+    // ---------------- phase 2: one cyclic Jacobi sweep on H, accumulate Q
+    for (int e = tid; e < NB2 * NB2; e += 256) {
+        int a = e / NB2, c = e % NB2;
+        Qs[a * HP + c] = (a == c) ? 1.0 : 0.0;
+    }
+    __syncthreads();
+    for (int step = 0; step < NB2 - 1; ++step) {
+        if (tid < NB2 / 2) {
+            const int p = circle_player(tid, step, NB2);
+            const int q = circle_player(NB2 - 1 - tid, step, NB2);
+            double c = 1.0, sn = 0.0;
+            if (gidx(p) < r && gidx(q) < r) {
+                const double app = Hs[p * HP + p], aqq = Hs[q * HP + q], apq = Hs[p * HP + q];
+                if (fabs(apq) > 1e-300 && fabs(apq) > 1e-18 * sqrt(fabs(app) * fabs(aqq))) {
+                    const double zeta = (aqq - app) / (2.0 * apq);
+                    double t;
+                    if (fabs(zeta) > 1e150) t = 0.5 / zeta;
+                    else t = copysign(1.0, zeta) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+                    c = 1.0 / sqrt(1.0 + t * t);
+                    sn = c * t;
+                }
+            }
+            rot_c[tid] = c; rot_s[tid] = sn; rot_p[tid] = p; rot_q[tid] = q;
+        }
+        __syncthreads();
+        // columns:  H <- H J,  Q <- Q J
+        for (int e = tid; e < NB2 * (NB2 / 2); e += 256) {
+            const int kk = e % (NB2 / 2), i = e / (NB2 / 2);
+            const double c = rot_c[kk], sn = rot_s[kk];
+            if (sn == 0.0) continue;
+            const int p = rot_p[kk], q = rot_q[kk];
+            double hp = Hs[i * HP + p], hq = Hs[i * HP + q];
+            Hs[i * HP + p] = c * hp - sn * hq;
+            Hs[i * HP + q] = sn * hp + c * hq;
+            double qp = Qs[i * HP + p], qq = Qs[i * HP + q];
+            Qs[i * HP + p] = c * qp - sn * qq;
+            Qs[i * HP + q] = sn * qp + c * qq;
+        }
+        __syncthreads();
+        // rows:  H <- J^T H
+        for (int e = tid; e < NB2 * (NB2 / 2); e += 256) {
+            const int kk = e % (NB2 / 2), j = e / (NB2 / 2);
+            const double c = rot_c[kk], sn = rot_s[kk];
+            if (sn == 0.0) continue;
+            const int p = rot_p[kk], q = rot_q[kk];
+            double hp = Hs[p * HP + j], hq = Hs[q * HP + j];
+            Hs[p * HP + j] = c * hp - sn * hq;
+            Hs[q * HP + j] = sn * hp + c * hq;
+        }
+        __syncthreads();
+    }
+
+    // ---------------- phase 3: vectors <- Q^T vectors, W <- W Q (MFMA)
+    if constexpr (sizeof(T) == 4) {
+        for (int e = tid; e < NB2 * NB2; e += 256) {
+            int a = e / NB2, c = e % NB2;
+            Qf[a * HP + c] = static_cast<T>(Qs[a * HP + c]);
+        }
+    }
+    __syncthreads();
+    const T* Qop = (sizeof(T) == 4) ? Qf : reinterpret_cast<const T*>(Qs);
+
+    constexpr int UPW = NT;  // output tiles per wave: NT a-tiles x 4 t-tiles / 4 waves
+    for (int part = 0; part < 2; ++part) {
+        T* base = part == 0 ? Ab : Wb;
+        const int64_t vs = part == 0 ? g.vs : r;
+        const int64_t es = part == 0 ? g.es : 1;
+        const int64_t len = part == 0 ? L : r;
+        for (int64_t t0 = 0; t0 < len; t0 += TC) {
+            load_chunk(base, vs, es, t0, len);
+            __syncthreads();
+            AccT uacc[UPW];
+#pragma unroll
+            for (int j = 0; j < UPW; ++j) uacc[j] = zero4<AccT>();
+#pragma unroll
+            for (int kk = 0; kk < NB2; kk += 4) {
+#pragma unroll
+                for (int j = 0; j < UPW; ++j) {
+                    const int q = wave * UPW + j, ta = q / 4, tt = q % 4;
+                    T a = Qop[(kk + lg) * HP + ta * 16 + lr];   // Q[c][a]
+                    T b = Ts[(kk + lg) * LDP + tt * 16 + lr];   // old[c][t]
+                    uacc[j] = mfma(a, b, uacc[j]);
+                }
+            }
+            __syncthreads();
+#pragma unroll
+            for (int j = 0; j < UPW; ++j) {
+                const int q = wave * UPW + j, ta = q / 4, tt = q % 4;
+#pragma unroll
+                for (int v = 0; v < 4; ++v)
+                    Ts[(ta * 16 + lg * 4 + v) * LDP + tt * 16 + lr] = uacc[j][v];
+            }
+            __syncthreads();
+            store_chunk(base, vs, es, t0, len);
+            __syncthreads();
+        }
+    }
+}
+
+__global__ void jacobi_sweep_end(JacobiCtl* __restrict__ ctl, int64_t n, double tol,
+                                 int* __restrict__ remaining) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    JacobiCtl c = ctl[i];
+    if (c.done) return;
+    c.sweeps += 1;
+    const double mc = __longlong_as_double((long long)c.maxcos_bits);
+    if (c.nonfinite || mc <= tol) c.done = 1;
+    else atomicAdd(remaining, 1);
+    c.maxcos_bits = 0ull;
+    ctl[i] = c;
+}
+
+// squared norms of the final vectors, FP64, fixed summation order
+template <class T>
+__global__ __launch_bounds__(256) void jacobi_norms_rows(const T* __restrict__ A, SliceGeom g,
+                                                         double* __restrict__ s2) {
+    // rows case (vs = 1, es = m): thread per vector, coalesced across threads
+    const int64_t s = blockIdx.y;
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= g.r) return;
+    const T* Ab = A + s * g.m * g.p;
+    double acc = 0.0;
+    for (int64_t t = 0; t < g.L; ++t) {
+        double v = (double)Ab[j + t * g.es];
+        acc = fma(v, v, acc);
+    }
+    s2[s * g.r + j] = acc;
+}
+
+template <class T>
+__global__ __launch_bounds__(256) void jacobi_norms_cols(const T* __restrict__ A, SliceGeom g,
+                                                         int64_t total_vectors,
+                                                         double* __restrict__ s2) {
+    // columns case: one wavefront per contiguous vector
+    const int64_t v = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (v >= total_vectors) return;
+    const int64_t s = v / g.r, j = v % g.r;
+    const T* x = A + s * g.m * g.p + j * g.vs;
+    double acc = 0.0;
+    for (int64_t t = lane; t < g.L; t += 64) {
+        double e = (double)x[t];
+        acc = fma(e, e, acc);
+    }
+    for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
+    if (lane == 0) s2[s * g.r + j] = acc;
+}
+
+__global__ void jacobi_finish(const JacobiCtl* __restrict__ ctl, int64_t n,
+                              int32_t* __restrict__ status) {
+    __shared__ int nf, nc;
+    if (threadIdx.x == 0) { nf = 0; nc = 0; }
+    __syncthreads();
+    for (int64_t i = threadIdx.x; i < n; i += blockDim.x) {
+        if (ctl[i].nonfinite) atomicOr(&nf, 1);
+        else if (!ctl[i].done) atomicOr(&nc, 1);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) *status = nf ? TSVDM_E_NONFINITE : (nc ? TSVDM_E_NOCONV : TSVDM_OK);
+}
+
+template <class T, int NB2>
+int jacobi_impl(T* A, int64_t m, int64_t p, int64_t n, T* W, double* s2, int32_t* status,
+                const JacobiOpts& o, void* ws, hipStream_t st) {
+    const SliceGeom g = slice_geom(m, p);
+    Carver cv(ws);
+    JacobiCtl* ctl = cv.carve<JacobiCtl>((size_t)n);
+    int* remaining = cv.carve<int>((size_t)o.max_sweeps);
+    unsigned long long* pair_counts = cv.carve<unsigned long long>(2);
+    const bool stats = stats_enabled();
+    std::vector<hipEvent_t> evs;
+
+    const int64_t initw = g.r * g.r * n;
+    int64_t gblocks = (initw + 255) / 256;
+    if (gblocks < (n + 255) / 256) gblocks = (n + 255) / 256;
+    if (gblocks > 65535 * 16) gblocks = 65535 * 16;
+    if (gblocks < 1) gblocks = 1;
+    jacobi_init<T><<<(unsigned)gblocks, 256, 0, st>>>(W, g.r, n, ctl, remaining, o.max_sweeps,
+                                                      pair_counts, status);
+    TSVDM_LAUNCH_CHECK();
+
+    constexpr int B = NB2 / 2;
+    const int nb = (int)((g.r + B - 1) / B);
+    const int nbe = nb + (nb & 1);
+    const int npairs = nbe / 2;
+    const int64_t blocks = n * npairs;
+    TSVDM_REQUIRE(blocks < ((int64_t)1 << 31), TSVDM_E_SHAPE, "too many slice pairs for one launch");
+    int64_t launches = 0;
+    for (int sweep = 0; sweep < o.max_sweeps; ++sweep) {
+        if (stats) {
+            hipEvent_t e0, e1;
+            TSVDM_HIP_CHECK(hipEventCreate(&e0));
+            TSVDM_HIP_CHECK(hipEventCreate(&e1));
+            evs.push_back(e0);
+            evs.push_back(e1);
+            TSVDM_HIP_CHECK(hipEventRecord(e0, st));
+        }
+        for (int rnd = 0; rnd < nbe - 1; ++rnd) {
+            jacobi_round<T, NB2><<<(unsigned)blocks, 256, 0, st>>>(A, W, g, nbe, rnd, ctl, o.tol,
+                                                                   pair_counts);
+            TSVDM_LAUNCH_CHECK();
+            ++launches;
+        }
+        if (stats) TSVDM_HIP_CHECK(hipEventRecord(evs.back(), st));
+        jacobi_sweep_end<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(ctl, n, o.tol, remaining + sweep);
+        TSVDM_LAUNCH_CHECK();
+        if (o.host_poll) {
+            int left = -1;
+            TSVDM_HIP_CHECK(hipMemcpyAsync(&left, remaining + sweep, sizeof(int),
+                                           hipMemcpyDeviceToHost, st));
+            TSVDM_HIP_CHECK(hipStreamSynchronize(st));
+            if (left == 0) break;
+        }
+    }
+    if (g.es == 1) {
+        const int64_t tv = g.r * n;
+        jacobi_norms_cols<T><<<(unsigned)((tv + 3) / 4), 256, 0, st>>>(A, g, tv, s2);
+    } else {
+        dim3 grid((unsigned)((g.r + 255) / 256), (unsigned)n);
+        jacobi_norms_rows<T><<<grid, 256, 0, st>>>(A, g, s2);
+    }
+    TSVDM_LAUNCH_CHECK();
+    jacobi_finish<<<1, 256, 0, st>>>(ctl, n, status);
+    TSVDM_LAUNCH_CHECK();
+    if (stats) {
+        unsigned long long pc[2] = {0ull, 0ull};
+        TSVDM_HIP_CHECK(hipMemcpyAsync(pc, pair_counts, sizeof(pc), hipMemcpyDeviceToHost, st));
+        TSVDM_HIP_CHECK(hipStreamSynchronize(st));
+        double ms = 0.0;
+        for (size_t i = 0; i + 1 < evs.size(); i += 2) {
+            float t = 0.f;
+            TSVDM_HIP_CHECK(hipEventElapsedTime(&t, evs[i], evs[i + 1]));
+            ms += t;
+        }
+        for (hipEvent_t e : evs) (void)hipEventDestroy(e);
+        stats_add(launches, ms, (int64_t)pc[0], (int64_t)pc[1], NB2);
+    }
+    return TSVDM_OK;
+}
+
+}  // namespace
+
+size_t jacobi_workspace_bytes(int64_t n) {
+    Carver cv(nullptr);
+    cv.carve<JacobiCtl>((size_t)n);
+    cv.carve<int>(1024);
+    cv.carve<unsigned long long>(2);
+    return cv.total();
+}
+
+JacobiOpts jacobi_default_opts(int64_t m, int64_t p, int dt) {
+    const SliceGeom g = slice_geom(m, p);
+    JacobiOpts o;
+    o.block = (g.r >= 256) ? 64 : 32;
+    o.max_sweeps = 40;
+    const double eps = dt == TSVDM_F64 ? 1.1102230246251565e-16 : 5.9604644775390625e-08;
+    const double c = 8.0 * sqrt((double)(g.L > 1 ? g.L : 1)) * eps;
+    o.tol = dt == TSVDM_F64 ? fmax(c, 1e-14) : fmax(c, 2e-6);
+    o.host_poll = 1;
+    return o;
+}
+
+int run_jacobi(void* A, int dt, int64_t m, int64_t p, int64_t n, void* W, double* s2,
+               int32_t* status, const JacobiOpts& o, void* ws, hipStream_t st) {
+    TSVDM_REQUIRE(o.block == 32 || o.block == 64, TSVDM_E_ARG, "block must be 16 or 32 (pair width 32 or 64)");
+    TSVDM_REQUIRE(o.max_sweeps >= 1 && o.max_sweeps <= 1024, TSVDM_E_ARG, "max_sweeps must be in [1, 1024]");
+    if (dt == TSVDM_F64) {
+        if (o.block == 32)
+            return jacobi_impl<double, 32>(static_cast<double*>(A), m, p, n, static_cast<double*>(W), s2, status, o, ws, st);
+        return jacobi_impl<double, 64>(static_cast<double*>(A), m, p, n, static_cast<double*>(W), s2, status, o, ws, st);
+    }
+    if (dt == TSVDM_F32) {
+        if (o.block == 32)
+            return jacobi_impl<float, 32>(static_cast<float*>(A), m, p, n, static_cast<float*>(W), s2, status, o, ws, st);
+        return jacobi_impl<float, 64>(static_cast<float*>(A), m, p, n, static_cast<float*>(W), s2, status, o, ws, st);
+    }
+    set_error("slice SVD supports F64 and F32 only");
+    return TSVDM_E_UNSUPPORTED;
+}
+
+}  // namespace tsvdm

@@ -1,0 +1,254 @@
+// Factor emission and the variable-rank reconstruction GEMM.
+//
+// Algorithm 2 keeps, per slice i, the rho_i leading left singular vectors and
+// G_i = S_i V_i^T restricted to them; Section 3.4 stores them without padding
+// (slice i owns exactly m*rho_i and p*rho_i entries).  The Jacobi output holds
+// the vectors unsorted, so each slice first sorts its squared singular values
+// (descending, ties by index) in LDS and then gathers the kept triplets.
+// The reconstruction C-hat_i = U_i G_i is a batched GEMM whose inner size
+// rho_i varies per slice.
+#include "common.h"
+#include "kernels.h"
+
+namespace tsvdm {
+
+namespace {
+
+constexpr int PMAX = 4096;  // largest r handled by the in-LDS sort
+
+// perm[s*r + c] = index of the c-th largest s2 of slice s; S_pk gets the
+// singular values of the kept triplets (positions first .. first+rho-1 of the
+// descending order).
+template <class T>
+__global__ __launch_bounds__(1024) void pack_sort(const double* __restrict__ s2, int64_t r,
+                                                  int64_t n, const int32_t* __restrict__ rho,
+                                                  const int64_t* __restrict__ offsets,
+                                                  int64_t capacity, int first,
+                                                  int32_t* __restrict__ perm, T* __restrict__ S_pk,
+                                                  int32_t* __restrict__ status) {
+    __shared__ unsigned long long key[PMAX];
+    __shared__ int idx[PMAX];
+    const int64_t s = blockIdx.x;
+    int np = 1;
+    while (np < r) np <<= 1;
+    for (int i = threadIdx.x; i < np; i += blockDim.x) {
+        if (i < r) {
+            double v = s2[s * r + i];
+            if (!(v >= 0.0)) v = 0.0;
+            v += 0.0;
+            key[i] = ~(unsigned long long)__double_as_longlong(v);  // ascending key = descending value
+        } else {
+            key[i] = ~0ull;
+        }
+        idx[i] = i;
+    }
+    __syncthreads();
+    for (int k = 2; k <= np; k <<= 1) {
+        for (int j = k >> 1; j > 0; j >>= 1) {
+            for (int t = threadIdx.x; t < np / 2; t += blockDim.x) {
+                const int i = 2 * j * (t / j) + (t % j);
+                const bool up = (i & k) == 0;
+                const unsigned long long ka = key[i], kb = key[i + j];
+                const int ia = idx[i], ib = idx[i + j];
+                const bool gt = (ka > kb) || (ka == kb && ia > ib);
+                if (gt == up) { key[i] = kb; key[i + j] = ka; idx[i] = ib; idx[i + j] = ia; }
+            }
+            __syncthreads();
+        }
+    }
+    for (int i = threadIdx.x; i < r; i += blockDim.x) perm[s * r + i] = idx[i];
+    const int64_t off = offsets[s];
+    const int kr = rho[s];
+    for (int c = threadIdx.x; c < kr; c += blockDim.x) {
+        if (off + kr <= capacity && first + c < r) {
+            double v = s2[s * r + idx[first + c]];
+            S_pk[off + c] = static_cast<T>(sqrt(v > 0.0 ? v : 0.0));
+        }
+    }
+    if (s == 0 && threadIdx.x == 0 && offsets[n] > capacity) *status = TSVDM_E_CAPACITY;
+}
+
+// Gather kept vectors into U_pk (m x rho) and G_pk (rho x p) of each slice.
+template <class T>
+__global__ __launch_bounds__(256) void pack_copy(const T* __restrict__ A, const T* __restrict__ W,
+                                                 const double* __restrict__ s2, SliceGeom g,
+                                                 const int32_t* __restrict__ rho,
+                                                 const int64_t* __restrict__ offsets,
+                                                 int64_t capacity, int first,
+                                                 const int32_t* __restrict__ perm,
+                                                 T* __restrict__ U_pk, T* __restrict__ G_pk) {
+    const int64_t s = blockIdx.y;
+    const int64_t kr = rho[s];
+    const int64_t off = offsets[s];
+    if (kr <= 0 || off + kr > capacity) return;  // an overflowing slice is not written
+    const int64_t m = g.m, p = g.p, r = g.r;
+    const T* Ab = A + s * m * p;
+    const T* Wb = W + s * r * r;
+    const int32_t* pr = perm + s * r + first;
+    const bool rows = g.es != 1;  // m < p: vectors are rows, W holds U
+    const int64_t nu = kr * m, ng = kr * p;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < nu + ng; e += stride) {
+        if (e < nu) {
+            const int64_t a = e % m, c = e / m;
+            const int64_t j = pr[c];
+            T v;
+            if (rows) {
+                v = Wb[j * r + a];
+            } else {
+                const double sg = sqrt(fmax(s2[s * r + j], 0.0));
+                v = sg > 0.0 ? static_cast<T>((double)Ab[a + j * m] / sg) : T(0);
+            }
+            U_pk[m * off + e] = v;
+        } else {
+            const int64_t f = e - nu;
+            const int64_t c = f % kr, b = f / kr;  // G_pk is kr x p, leading dim kr
+            const int64_t j = pr[c];
+            T v;
+            if (rows) {
+                v = Ab[j + b * m];
+            } else {
+                const double sg = sqrt(fmax(s2[s * r + j], 0.0));
+                v = static_cast<T>(sg * (double)Wb[b + j * r]);
+            }
+            G_pk[p * off + c + b * kr] = v;
+        }
+    }
+}
+
+// C(:,:,s) = U_pk_s (m x rho_s) * G_pk_s (rho_s x p), computed as
+// C^T = G^T U^T so that MFMA output lanes run along the rows of C.
+template <class T>
+__global__ __launch_bounds__(256) void lowrank_gemm(const T* __restrict__ U_pk,
+                                                    const T* __restrict__ G_pk, int64_t m,
+                                                    int64_t p, const int32_t* __restrict__ rho,
+                                                    const int64_t* __restrict__ offsets,
+                                                    int64_t capacity, T* __restrict__ C,
+                                                    int tiles_a) {
+    typedef typename Acc<T>::type AccT;
+    constexpr int KC = 16;
+    __shared__ T Us[KC][64 + 1];  // [c][a]
+    __shared__ T Gs[64][KC + 1];  // [b][c]
+    const int64_t s = blockIdx.y;
+    const int ta = blockIdx.x % tiles_a, tb = blockIdx.x / tiles_a;
+    const int64_t a0 = (int64_t)ta * 64, b0 = (int64_t)tb * 64;
+    const int64_t off = offsets[s];
+    const int64_t kr = (off + rho[s] <= capacity) ? rho[s] : 0;  // unwritten slices read as 0
+    const T* Ub = U_pk + m * off;
+    const T* Gb = G_pk + p * off;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int lr = lane & 15, lg = lane >> 4;
+    AccT acc[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) acc[t] = zero4<AccT>();
+    for (int64_t c0 = 0; c0 < kr; c0 += KC) {
+        for (int e = tid; e < KC * 64; e += 256) {
+            const int a = e & 63, c = e >> 6;
+            T v = 0;
+            if (a0 + a < m && c0 + c < kr) v = Ub[(a0 + a) + (c0 + c) * m];
+            Us[c][a] = v;
+        }
+        for (int e = tid; e < KC * 64; e += 256) {
+            const int c = e % KC, b = e / KC;
+            T v = 0;
+            if (b0 + b < p && c0 + c < kr) v = Gb[(c0 + c) + (b0 + b) * kr];
+            Gs[b][c] = v;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int kk = 0; kk < KC; kk += 4) {
+            T av = Gs[wave * 16 + lr][kk + lg];  // A = G^T : row b, k = c
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                T bv = Us[kk + lg][t * 16 + lr];  // B = U^T : k = c, col a
+                acc[t] = mfma(av, bv, acc[t]);
+            }
+        }
+        __syncthreads();
+    }
+    T* Cb = C + s * m * p;
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+        const int64_t a = a0 + t * 16 + lr;
+        if (a >= m) continue;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int64_t b = b0 + wave * 16 + lg * 4 + v;
+            if (b < p) Cb[a + b * m] = acc[t][v];
+        }
+    }
+}
+
+template <class T>
+int pack_impl(const void* A, const void* W, const double* s2, int64_t m, int64_t p, int64_t n,
+              const int32_t* rho, const int64_t* offsets, int64_t capacity, int first,
+              void* U_pk, void* G_pk, void* S_pk, int32_t* status, void* ws, hipStream_t st) {
+    const SliceGeom g = slice_geom(m, p);
+    TSVDM_REQUIRE(g.r <= PMAX, TSVDM_E_SHAPE, "min(m, p) above 4096 is not supported by pack");
+    Carver cv(ws);
+    int32_t* perm = cv.carve<int32_t>((size_t)(g.r * n));
+    pack_sort<T><<<(unsigned)n, 1024, 0, st>>>(s2, g.r, n, rho, offsets, capacity, first, perm,
+                                                static_cast<T*>(S_pk), status);
+    TSVDM_LAUNCH_CHECK();
+    dim3 grid(64, (unsigned)n);
+    pack_copy<T><<<grid, 256, 0, st>>>(static_cast<const T*>(A), static_cast<const T*>(W), s2, g,
+                                       rho, offsets, capacity, first, perm,
+                                       static_cast<T*>(U_pk), static_cast<T*>(G_pk));
+    TSVDM_LAUNCH_CHECK();
+    return TSVDM_OK;
+}
+
+}  // namespace
+
+size_t pack_workspace_bytes(int64_t m, int64_t p, int64_t n) {
+    const SliceGeom g = slice_geom(m, p);
+    Carver cv(nullptr);
+    cv.carve<int32_t>((size_t)(g.r * n));
+    return cv.total();
+}
+
+int run_pack_from(const void* A, const void* W, const double* s2, int dt, int64_t m, int64_t p,
+                  int64_t n, const int32_t* rho, const int64_t* offsets, int64_t capacity,
+                  int first, void* U_pk, void* G_pk, void* S_pk, int32_t* status, void* ws,
+                  hipStream_t st) {
+    if (dt == TSVDM_F64)
+        return pack_impl<double>(A, W, s2, m, p, n, rho, offsets, capacity, first, U_pk, G_pk,
+                                 S_pk, status, ws, st);
+    if (dt == TSVDM_F32)
+        return pack_impl<float>(A, W, s2, m, p, n, rho, offsets, capacity, first, U_pk, G_pk,
+                                S_pk, status, ws, st);
+    set_error("pack supports F64 and F32 only");
+    return TSVDM_E_UNSUPPORTED;
+}
+
+int run_pack(const void* A, const void* W, const double* s2, int dt, int64_t m, int64_t p,
+             int64_t n, const int32_t* rho, const int64_t* offsets, int64_t capacity,
+             void* U_pk, void* G_pk, void* S_pk, int32_t* status, void* ws, hipStream_t st) {
+    return run_pack_from(A, W, s2, dt, m, p, n, rho, offsets, capacity, 0, U_pk, G_pk, S_pk,
+                         status, ws, st);
+}
+
+int run_lowrank_gemm(const void* U_pk, const void* G_pk, int dt, int64_t m, int64_t p,
+                     int64_t n, const int32_t* rho, const int64_t* offsets, int64_t capacity,
+                     void* C, hipStream_t st) {
+    const int ta = (int)((m + 63) / 64), tb = (int)((p + 63) / 64);
+    TSVDM_REQUIRE((int64_t)ta * tb < ((int64_t)1 << 31) && n < 65536, TSVDM_E_SHAPE,
+                  "reconstruction grid too large");
+    dim3 grid((unsigned)(ta * tb), (unsigned)n);
+    if (dt == TSVDM_F64) {
+        lowrank_gemm<double><<<grid, 256, 0, st>>>(static_cast<const double*>(U_pk),
+                                                   static_cast<const double*>(G_pk), m, p, rho,
+                                                   offsets, capacity, static_cast<double*>(C), ta);
+    } else if (dt == TSVDM_F32) {
+        lowrank_gemm<float><<<grid, 256, 0, st>>>(static_cast<const float*>(U_pk),
+                                                  static_cast<const float*>(G_pk), m, p, rho,
+                                                  offsets, capacity, static_cast<float*>(C), ta);
+    } else {
+        set_error("reconstruction supports F64 and F32 only");
+        return TSVDM_E_UNSUPPORTED;
+    }
+    TSVDM_LAUNCH_CHECK();
+    return TSVDM_OK;
+}
+
+}  // namespace tsvdm

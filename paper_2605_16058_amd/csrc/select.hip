@@ -1,0 +1,242 @@
+// Rank selection.
+//  t-SVDM-I  (Section 3.3): the same rank k on every slice.
+//  t-SVDM-II (Algorithm 2): sort all squared singular values ascending, take
+//  cumulative sums, find the largest J with w_J / W < eps^2, threshold
+//  tau = v_J and keep, per slice, the values strictly above tau.
+//
+// The squared values are FP64 and non-negative, so their IEEE bit patterns
+// sort as unsigned integers: a bitonic network on uint64 keys (LDS tiles of
+// 2048 plus global merge steps) gives the ascending order.  Sums are
+// double-double with a fixed combination order and are rounded once, so J
+// is deterministic and equals the exact-arithmetic answer except within
+// ~1e-30 relative of a tie.
+#include "common.h"
+#include "kernels.h"
+
+namespace tsvdm {
+
+namespace {
+
+constexpr int LTILE = 2048;   // keys sorted per LDS tile
+constexpr int LTHREADS = 512;
+
+__device__ __forceinline__ unsigned long long key_of(double v) {
+    if (!(v >= 0.0)) v = (v != v) ? __longlong_as_double(0x7ff0000000000000ll) : 0.0;  // NaN -> +inf, negatives -> 0
+    v = v + 0.0;  // -0 -> +0
+    return (unsigned long long)__double_as_longlong(v);
+}
+
+__global__ void sel_fill(const double* __restrict__ s2, int64_t N, int64_t Np,
+                         unsigned long long* __restrict__ keys) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < Np) keys[i] = i < N ? key_of(s2[i]) : ~0ull;
+}
+
+__device__ __forceinline__ void cmp_swap(unsigned long long& a, unsigned long long& b, bool up) {
+    if ((a > b) == up) { unsigned long long t = a; a = b; b = t; }
+}
+
+// Sort every LDS tile completely (k = 2 .. tile), or, with k_fixed > 0,
+// finish the merge stage k_fixed for all strides j < tile.
+__global__ __launch_bounds__(LTHREADS) void sel_bitonic_local(unsigned long long* __restrict__ keys,
+                                                              int64_t Np, int tile, int64_t k_fixed) {
+    __shared__ unsigned long long sk[LTILE];
+    const int64_t base = (int64_t)blockIdx.x * tile;
+    for (int i = threadIdx.x; i < tile; i += LTHREADS) sk[i] = keys[base + i];
+    __syncthreads();
+    const int64_t k_lo = k_fixed > 0 ? k_fixed : 2;
+    const int64_t k_hi = k_fixed > 0 ? k_fixed : tile;
+    for (int64_t k = k_lo; k <= k_hi; k <<= 1) {
+        for (int64_t j = (k_fixed > 0 ? tile / 2 : k / 2); j > 0; j >>= 1) {
+            for (int t = threadIdx.x; t < tile / 2; t += LTHREADS) {
+                const int64_t i = 2 * j * (t / j) + (t % j);  // lower index of the pair
+                const int64_t gi = base + i;
+                const bool up = (gi & k) == 0;
+                cmp_swap(sk[i], sk[i + j], up);
+            }
+            __syncthreads();
+        }
+    }
+    for (int i = threadIdx.x; i < tile; i += LTHREADS) keys[base + i] = sk[i];
+}
+
+__global__ void sel_bitonic_global(unsigned long long* __restrict__ keys, int64_t Np, int64_t k,
+                                   int64_t j) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= Np / 2) return;
+    const int64_t i = 2 * j * (t / j) + (t % j);
+    const bool up = (i & k) == 0;
+    unsigned long long a = keys[i], b = keys[i + j];
+    if ((a > b) == up) { keys[i] = b; keys[i + j] = a; }
+}
+
+constexpr int STHREADS = 1024;
+
+// Single-workgroup scan over the N sorted values (N <= a few million).
+__global__ __launch_bounds__(STHREADS) void sel_scan(const unsigned long long* __restrict__ keys,
+                                                     int64_t N, double eps, double* __restrict__ stats) {
+    __shared__ double shi[STHREADS], slo[STHREADS];
+    __shared__ double phi[STHREADS], plo[STHREADS];
+    __shared__ long long cnt[STHREADS];
+    __shared__ double W_s, tau_s;
+    __shared__ long long J_s;
+    const int t = threadIdx.x;
+    const int64_t seg = (N + STHREADS - 1) / STHREADS;
+    const int64_t b0 = (int64_t)t * seg;
+    const int64_t b1 = (b0 + seg < N) ? b0 + seg : N;
+
+    // pass 1: segment sums
+    dd acc = {0.0, 0.0};
+    for (int64_t j = b0; j < b1; ++j) acc = dd_add_d(acc, __longlong_as_double((long long)keys[j]));
+    shi[t] = acc.hi; slo[t] = acc.lo;
+    __syncthreads();
+    if (t == 0) {
+        dd run = {0.0, 0.0};
+        for (int i = 0; i < STHREADS; ++i) {
+            phi[i] = run.hi; plo[i] = run.lo;
+            run = dd_add(run, dd{shi[i], slo[i]});
+        }
+        W_s = dd_round(run);
+    }
+    __syncthreads();
+    const double W = W_s;
+    const double eps2 = eps * eps;
+
+    // pass 2: J = #{ j : w_j / W < eps^2 }  (w is non-decreasing)
+    long long c = 0;
+    if (W > 0.0) {
+        dd w = {phi[t], plo[t]};
+        for (int64_t j = b0; j < b1; ++j) {
+            w = dd_add_d(w, __longlong_as_double((long long)keys[j]));
+            if (dd_round(w) / W < eps2) ++c; else break;
+        }
+    }
+    cnt[t] = c;
+    __syncthreads();
+    if (t == 0) {
+        long long J = 0;
+        for (int i = 0; i < STHREADS; ++i) J += cnt[i];
+        J_s = J;
+        double tau;
+        if (W == 0.0) tau = 0.0;                         // zero tensor: drop everything
+        else if (J == 0) tau = -__longlong_as_double(0x7ff0000000000000ll);  // keep everything
+        else tau = __longlong_as_double((long long)keys[J - 1]);
+        tau_s = tau;
+    }
+    __syncthreads();
+    // pass 3: discarded energy = sum of values <= tau (fixed order)
+    const double tau = tau_s;
+    dd d = {0.0, 0.0};
+    for (int64_t j = b0; j < b1; ++j) {
+        const double v = __longlong_as_double((long long)keys[j]);
+        if (v <= tau) d = dd_add_d(d, v); else break;
+    }
+    shi[t] = d.hi; slo[t] = d.lo;
+    __syncthreads();
+    if (t == 0) {
+        dd run = {0.0, 0.0};
+        for (int i = 0; i < STHREADS; ++i) run = dd_add(run, dd{shi[i], slo[i]});
+        stats[0] = tau;
+        stats[1] = dd_round(run);
+        stats[2] = W;
+        stats[3] = (double)J_s;
+    }
+}
+
+__global__ void sel_rank(const double* __restrict__ s2, int64_t r, int64_t n,
+                         const double* __restrict__ stats, int32_t* __restrict__ rho) {
+    const int64_t i = blockIdx.x;  // slice
+    if (i >= n) return;
+    const double tau = stats[0];
+    int c = 0;
+    for (int64_t j = threadIdx.x; j < r; j += blockDim.x) c += (s2[i * r + j] > tau) ? 1 : 0;
+    for (int off = 32; off > 0; off >>= 1) c += __shfl_xor(c, off);
+    __shared__ int part[16];
+    if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = c;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int tot = 0;
+        for (int w = 0; w < (int)(blockDim.x >> 6); ++w) tot += part[w];
+        rho[i] = tot;
+    }
+}
+
+// offsets[i] = sum_{j < i} rho[j], offsets[n] = total (single workgroup)
+__global__ __launch_bounds__(1024) void sel_offsets(const int32_t* __restrict__ rho, int64_t n,
+                                                    int64_t* __restrict__ offsets) {
+    __shared__ long long part[1024];
+    const int t = threadIdx.x;
+    const int64_t seg = (n + 1023) / 1024;
+    const int64_t b0 = (int64_t)t * seg, b1 = (b0 + seg < n) ? b0 + seg : n;
+    long long s = 0;
+    for (int64_t i = b0; i < b1; ++i) s += rho[i];
+    part[t] = s;
+    __syncthreads();
+    if (t == 0) {
+        long long run = 0;
+        for (int i = 0; i < 1024; ++i) { long long v = part[i]; part[i] = run; run += v; }
+        offsets[n] = run;
+    }
+    __syncthreads();
+    long long run = part[t];
+    for (int64_t i = b0; i < b1; ++i) { offsets[i] = run; run += rho[i]; }
+}
+
+__global__ void sel_fixed(int64_t kk, int64_t n, int32_t* __restrict__ rho,
+                          int64_t* __restrict__ offsets) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) rho[i] = (int32_t)kk;
+    if (i <= n) offsets[i] = i * kk;
+}
+
+int64_t next_pow2(int64_t x) {
+    int64_t p = 1;
+    while (p < x) p <<= 1;
+    return p;
+}
+
+}  // namespace
+
+size_t select_workspace_bytes(int64_t r, int64_t n) {
+    Carver cv(nullptr);
+    cv.carve<unsigned long long>((size_t)next_pow2(r * n < 2 ? 2 : r * n));
+    return cv.total();
+}
+
+int run_truncate_tol(const double* s2, int64_t r, int64_t n, double eps, int32_t* rho,
+                     int64_t* offsets, double* stats, void* ws, hipStream_t st) {
+    const int64_t N = r * n;
+    const int64_t Np = next_pow2(N < 2 ? 2 : N);
+    Carver cv(ws);
+    unsigned long long* keys = cv.carve<unsigned long long>((size_t)Np);
+    sel_fill<<<(unsigned)((Np + 255) / 256), 256, 0, st>>>(s2, N, Np, keys);
+    TSVDM_LAUNCH_CHECK();
+    const int tile = (int)(Np < LTILE ? Np : LTILE);
+    sel_bitonic_local<<<(unsigned)(Np / tile), LTHREADS, 0, st>>>(keys, Np, tile, 0);
+    TSVDM_LAUNCH_CHECK();
+    for (int64_t k = 2 * (int64_t)tile; k <= Np; k <<= 1) {
+        for (int64_t j = k / 2; j >= tile; j >>= 1) {
+            sel_bitonic_global<<<(unsigned)((Np / 2 + 255) / 256), 256, 0, st>>>(keys, Np, k, j);
+            TSVDM_LAUNCH_CHECK();
+        }
+        sel_bitonic_local<<<(unsigned)(Np / tile), LTHREADS, 0, st>>>(keys, Np, tile, k);
+        TSVDM_LAUNCH_CHECK();
+    }
+    sel_scan<<<1, STHREADS, 0, st>>>(keys, N, eps, stats);
+    TSVDM_LAUNCH_CHECK();
+    sel_rank<<<(unsigned)n, 256, 0, st>>>(s2, r, n, stats, rho);
+    TSVDM_LAUNCH_CHECK();
+    sel_offsets<<<1, 1024, 0, st>>>(rho, n, offsets);
+    TSVDM_LAUNCH_CHECK();
+    return TSVDM_OK;
+}
+
+int run_truncate_rank(int64_t k, int64_t r, int64_t n, int32_t* rho, int64_t* offsets,
+                      hipStream_t st) {
+    const int64_t kk = k < r ? k : r;
+    sel_fixed<<<(unsigned)((n + 1 + 255) / 256), 256, 0, st>>>(kk, n, rho, offsets);
+    TSVDM_LAUNCH_CHECK();
+    return TSVDM_OK;
+}
+
+}  // namespace tsvdm

@@ -1,0 +1,175 @@
+// Mode-3 tensor-times-matrix on MFMA (Section 2.1; Section 3.1).
+//
+// For a column-major m x p x n tensor the mode-3 unfolding is the (mp) x n
+// matrix X whose column l is frontal slice l, so Y = X x_3 op(M) is the single
+// GEMM  Y[row, i] = sum_l X[row, l] * op(M)[i, l]  with a huge row count
+// R = mp and small N = K = n.  Each workgroup computes a 64-row x 64-column
+// tile of Y in the transposed orientation Y^T = op(M) X^T so that the MFMA
+// output lanes run along tensor rows and the stores coalesce.
+#include "common.h"
+#include "kernels.h"
+
+namespace tsvdm {
+
+namespace {
+
+constexpr int TILE_R = 64;  // rows of the unfolding per workgroup
+constexpr int TILE_I = 64;  // output slices per workgroup
+
+// Tt[i*n + l] = scale * op(M)[i, l], stored in the LDS staging type.
+template <class ST>
+__global__ void ttm_prep(const double* __restrict__ M, int n, int transpose,
+                         double scale, ST* __restrict__ Tt) {
+    int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= (int64_t)n * n) return;
+    int i = (int)(idx / n), l = (int)(idx % n);
+    double v = transpose ? M[l + (int64_t)i * n] : M[i + (int64_t)l * n];
+    Tt[idx] = static_cast<ST>(scale * v);
+}
+
+// KIND 0: plain MFMA in CT (double or float), K step 4.
+// KIND 1: BF16 operands, FP32 accumulate, K step 32.
+// KIND 2: split BF16 (hi*hi + hi*lo + lo*hi), FP32 accumulate, K step 32.
+template <class CT, int KIND>
+__global__ __launch_bounds__(256) void ttm_kernel(
+    const void* __restrict__ X, int xdt, void* __restrict__ Y, int ydt,
+    int64_t R, int n, const CT* __restrict__ Tt, int n_ct, int64_t n_rt) {
+    constexpr int KC = (KIND == 0) ? 16 : 32;
+    typedef typename Acc<CT>::type AccT;
+    __shared__ CT Xs[KC][TILE_R + 1];   // [l][row]
+    __shared__ CT Ts[TILE_I][KC + 1];   // [i][l]
+
+    // XCD-aware block mapping: the n_ct column tiles of one row tile share
+    // blockIdx % 8 (the same XCD and L2) and are dispatched together.
+    const int64_t bid = blockIdx.x;
+    const int64_t xcd = bid & 7, local = bid >> 3;
+    const int64_t rt = (local / n_ct) * 8 + xcd;
+    const int ct = (int)(local % n_ct);
+    if (rt >= n_rt) return;
+    const int64_t row0 = rt * TILE_R;
+    const int i0 = ct * TILE_I;
+
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, wave = tid >> 6;
+    const int lr = lane & 15, lg = lane >> 4;
+
+    AccT acc[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) acc[t] = zero4<AccT>();
+
+    for (int l0 = 0; l0 < n; l0 += KC) {
+        // stage X[row0 .. row0+63, l0 .. l0+KC-1], coalesced along rows
+#pragma unroll
+        for (int e = tid; e < KC * TILE_R; e += 256) {
+            int r = e & (TILE_R - 1), l = e / TILE_R;
+            int64_t row = row0 + r;
+            int lg_ = l0 + l;
+            CT v = 0;
+            if (row < R && lg_ < n) v = ldg_as<CT>(X, row + (int64_t)lg_ * R, xdt);
+            Xs[l][r] = v;
+        }
+        // stage op(M) block [i0 .. i0+63, l0 .. l0+KC-1]
+#pragma unroll
+        for (int e = tid; e < KC * TILE_I; e += 256) {
+            int l = e % KC, i = e / KC;
+            CT v = 0;
+            if (i0 + i < n && l0 + l < n) v = Tt[(int64_t)(i0 + i) * n + l0 + l];
+            Ts[i][l] = v;
+        }
+        __syncthreads();
+
+        const int irow = wave * 16 + lr;  // output slice (A-operand row)
+        if constexpr (KIND == 0) {
+#pragma unroll
+            for (int kk = 0; kk < KC; kk += 4) {
+                CT a = Ts[irow][kk + lg];
+#pragma unroll
+                for (int t = 0; t < 4; ++t) {
+                    CT b = Xs[kk + lg][t * 16 + lr];
+                    acc[t] = mfma(a, b, acc[t]);
+                }
+            }
+        } else {
+            v8bf ahi, alo;
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                float x = Ts[irow][lg * 8 + e];
+                __bf16 h = to_bf16(x);
+                ahi[e] = h;
+                alo[e] = to_bf16(x - static_cast<float>(h));
+            }
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                v8bf bhi, blo;
+#pragma unroll
+                for (int e = 0; e < 8; ++e) {
+                    float x = Xs[lg * 8 + e][t * 16 + lr];
+                    __bf16 h = to_bf16(x);
+                    bhi[e] = h;
+                    blo[e] = to_bf16(x - static_cast<float>(h));
+                }
+                acc[t] = mfma_bf16(ahi, bhi, acc[t]);
+                if constexpr (KIND == 2) {
+                    acc[t] = mfma_bf16(ahi, blo, acc[t]);
+                    acc[t] = mfma_bf16(alo, bhi, acc[t]);
+                }
+            }
+        }
+        __syncthreads();
+    }
+
+    // D lane layout: slice i0 + 16*wave + 4*lg + v, row row0 + 16*t + lr
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+        int64_t row = row0 + t * 16 + lr;
+        if (row >= R) continue;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            int i = i0 + wave * 16 + lg * 4 + v;
+            if (i < n) stg_as(Y, row + (int64_t)i * R, ydt, (double)acc[t][v]);
+        }
+    }
+}
+
+template <class CT, int KIND>
+int launch_ttm(const void* X, int xdt, void* Y, int ydt, int64_t R, int n,
+               const double* M, int transpose, double scale, void* ws,
+               hipStream_t st) {
+    CT* Tt = static_cast<CT*>(ws);
+    int64_t nn = (int64_t)n * n;
+    ttm_prep<CT><<<(unsigned)((nn + 255) / 256), 256, 0, st>>>(M, n, transpose, scale, Tt);
+    TSVDM_LAUNCH_CHECK();
+    int n_ct = (n + TILE_I - 1) / TILE_I;
+    int64_t n_rt = (R + TILE_R - 1) / TILE_R;
+    int64_t n_rt8 = (n_rt + 7) / 8 * 8;
+    int64_t blocks = n_rt8 * n_ct;
+    TSVDM_REQUIRE(blocks < (int64_t)1 << 31, TSVDM_E_SHAPE, "tensor too large for one launch");
+    ttm_kernel<CT, KIND><<<(unsigned)blocks, 256, 0, st>>>(X, xdt, Y, ydt, R, n, Tt, n_ct, n_rt);
+    TSVDM_LAUNCH_CHECK();
+    return TSVDM_OK;
+}
+
+}  // namespace
+
+size_t ttm_workspace_bytes(int64_t n) { return align_up((size_t)(n * n) * sizeof(double)); }
+
+int run_ttm(const void* X, int xdt, void* Y, int ydt, int64_t m, int64_t p, int64_t n,
+            const double* M, int transpose, double scale, int compute, void* ws,
+            hipStream_t st) {
+    int64_t R = m * p;
+    switch (compute) {
+        case TSVDM_F64:
+            return launch_ttm<double, 0>(X, xdt, Y, ydt, R, (int)n, M, transpose, scale, ws, st);
+        case TSVDM_F32:
+            return launch_ttm<float, 0>(X, xdt, Y, ydt, R, (int)n, M, transpose, scale, ws, st);
+        case TSVDM_BF16:
+            return launch_ttm<float, 1>(X, xdt, Y, ydt, R, (int)n, M, transpose, scale, ws, st);
+        case TSVDM_BF16X3:
+            return launch_ttm<float, 2>(X, xdt, Y, ydt, R, (int)n, M, transpose, scale, ws, st);
+        default:
+            set_error("unsupported compute dtype for the transform");
+            return TSVDM_E_UNSUPPORTED;
+    }
+}
+
+}  // namespace tsvdm

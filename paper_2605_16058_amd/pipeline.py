@@ -1,0 +1,147 @@
+"""t-SVDM-I / t-SVDM-II end to end on one GPU, and the autograd wrapper.
+
+The pipeline chains the C-ABI calls: transform (Algorithm 1's first step),
+slice SVDs, rank selection (Section 3.3 / Algorithm 2), factor packing
+(Section 3.4) and reconstruction with the back-transform (Section 2.1), then
+the FP64 error report.  Torch only allocates device memory and provides the
+stream.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass
+
+import torch
+
+from . import ops
+
+PRECISIONS = {
+    # name: (TTM compute, Jacobi dtype)
+    "f64": ("f64", torch.float64),
+    "f32": ("f32", torch.float32),
+    "bf16x3": ("bf16x3", torch.float32),
+    "bf16": ("bf16", torch.float32),
+}
+
+
+@dataclass
+class Result:
+    A_rec: torch.Tensor
+    rho: torch.Tensor
+    offsets: torch.Tensor
+    U_pk: torch.Tensor
+    G_pk: torch.Tensor
+    S_pk: torch.Tensor
+    s2: torch.Tensor
+    stats: torch.Tensor          # t-SVDM-II: tau, discarded, total, J
+    err: torch.Tensor            # [sum (A - A_rec)^2, sum A^2]
+    svd_status: torch.Tensor
+    pack_status: torch.Tensor
+    capacity: int
+
+    def rel_error(self) -> float:
+        e = self.err.double().cpu()
+        return float((e[0] / e[1]).sqrt()) if e[1] > 0 else 0.0
+
+
+class TSVDM:
+    """Reusable operator for one shape, transform and precision.
+
+    mode "I" keeps rank k on every slice, mode "II" uses the global relative
+    tolerance eps.  capacity="max" sizes the packed factors for r*n triplets
+    (no host synchronisation); "exact" reads sum(rho) back first (one sync),
+    like the paper's exact-size allocation.
+    """
+
+    def __init__(self, shape, M, mode="II", k=None, eps=None, precision="f64",
+                 block=0, max_sweeps=0, tol=0.0, host_poll=True, capacity="max",
+                 device="cuda", check_m=True):
+        self.m, self.p, self.n = (int(x) for x in shape)
+        self.r = min(self.m, self.p)
+        if mode not in ("I", "II"):
+            raise ValueError("mode must be 'I' or 'II'")
+        if mode == "I" and (k is None or int(k) < 1):
+            raise ValueError("mode I needs k >= 1")
+        if mode == "II" and (eps is None or not (0.0 < float(eps) < 1.0)):
+            raise ValueError("mode II needs 0 < eps < 1")
+        if precision not in PRECISIONS:
+            raise ValueError(f"precision must be one of {list(PRECISIONS)}")
+        self.mode, self.k, self.eps = mode, k, eps
+        self.precision = precision
+        self.ttm_compute, self.dtype = PRECISIONS[precision]
+        self.c2 = ops.check_transform(M) if check_m else 1.0
+        self.Mdev = ops.device_matrix(M, device)
+        self.block, self.max_sweeps, self.tol, self.host_poll = block, max_sweeps, tol, host_poll
+        self.capacity_mode = capacity
+        self.device = device
+        self.ws = ops.Workspace(device)
+
+    def __call__(self, A: torch.Tensor) -> Result:
+        A = ops.as_colmajor(A)
+        if tuple(A.shape) != (self.m, self.p, self.n):
+            raise ValueError("shape mismatch")
+        m, p, n, r = self.m, self.p, self.n, self.r
+        out_dt = self.dtype
+        # 1. transform (FP32 -> FP64 up-cast fused into the TTM load)
+        A_hat = ops.tsvdm_transform(A, self.Mdev, transpose=False, scale=1.0,
+                                    compute=self.ttm_compute, out_dtype=self.dtype, ws=self.ws)
+        # 2. slice SVDs
+        W, s2, svd_status = ops.tsvdm_slice_svd(A_hat, self.block, self.max_sweeps, self.tol,
+                                                self.host_poll, ws=self.ws)
+        # 3. ranks
+        if self.mode == "I":
+            rho, offsets = ops.tsvdm_truncate_rank(self.k, r, n, self.device)
+            stats = torch.full((4,), float("nan"), dtype=torch.float64, device=self.device)
+        else:
+            rho, offsets, stats = ops.tsvdm_truncate_tol(s2, self.eps, ws=self.ws)
+        if self.capacity_mode == "exact":
+            cap = int(offsets[n].item())
+        elif self.mode == "I":
+            cap = min(int(self.k), r) * n
+        else:
+            cap = r * n
+        # 4. factors
+        U_pk, G_pk, S_pk, pack_status = ops.tsvdm_pack(A_hat, W, s2, rho, offsets, cap, ws=self.ws)
+        # 5. reconstruct + back-transform (M^{-1} = M^T / c^2)
+        back = self.ttm_compute if self.ttm_compute != "f64" else "f64"
+        A_rec = ops.tsvdm_reconstruct(U_pk, G_pk, rho, offsets, cap, self.Mdev, (m, p, n),
+                                      scale=1.0 / self.c2, out_dtype=out_dt, compute=back,
+                                      ws=self.ws)
+        # 6. error report
+        err = ops.tsvdm_error(A, A_rec, ws=self.ws)
+        return Result(A_rec, rho, offsets, U_pk, G_pk, S_pk, s2, stats, err, svd_status,
+                      pack_status, cap)
+
+
+def tsvdm(A, M, mode="II", k=None, eps=None, precision="f64", **kw) -> Result:
+    """One-shot t-SVDM-I (mode="I", k) or t-SVDM-II (mode="II", eps)."""
+    op = TSVDM(tuple(A.shape), M, mode=mode, k=k, eps=eps, precision=precision,
+               device=A.device, **kw)
+    return op(A)
+
+
+class TruncLoss(torch.autograd.Function):
+    """L(A, M) = sum of the squared singular values dropped by a rank-k
+    truncation of every slice of A x_3 M, with a hand-written adjoint
+    (tsvdm_backward) for both A and M.  M is an n x n FP64 device tensor;
+    compose it with any torch parameterisation (e.g. a Cayley map) to learn
+    the transform.  The factors are recomputed in backward, not stored."""
+
+    @staticmethod
+    def forward(ctx, A, M, k):
+        Mdev = M.detach().t().contiguous()  # column-major bytes
+        loss, _, _, status = ops.tsvdm_backward(A.detach(), Mdev, int(k), 1.0,
+                                                want_dA=False, want_dM=False)
+        ctx.save_for_backward(A, M)
+        ctx.k = int(k)
+        return loss[0].to(torch.float64)
+
+    @staticmethod
+    def backward(ctx, g):
+        A, M = ctx.saved_tensors
+        Mdev = M.detach().t().contiguous()
+        _, dA, dM, _ = ops.tsvdm_backward(A.detach(), Mdev, ctx.k, 1.0,
+                                          want_dA=ctx.needs_input_grad[0],
+                                          want_dM=ctx.needs_input_grad[1])
+        gA = (dA * g.to(dA.dtype)) if dA is not None else None
+        gM = (dM * g) if dM is not None else None
+        return gA, gM, None

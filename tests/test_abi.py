@@ -1,0 +1,146 @@
+"""CPU tests of the C ABI: the library loads, exports every function the
+header declares, and rejects bad arguments before launching anything.
+No compute call is made here (there is no GPU)."""
+import ctypes
+import os
+import re
+from ctypes import byref, c_double, c_size_t, c_void_p
+
+import numpy as np
+import pytest
+
+import synth
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "tsvdm.h")
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_2605_16058_amd import _lib
+    return _lib.load()
+
+
+def _header_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(tsvdm_[a-z_0-9]+)\s*\(", src)))
+
+
+def test_header_and_binding_agree():
+    from paper_2605_16058_amd import _lib
+    assert _header_functions() == sorted(_lib.exported_names())
+
+
+def test_library_exports_every_declared_symbol(lib):
+    for name in _header_functions():
+        assert hasattr(lib, name), name
+
+
+def test_version(lib):
+    assert lib.tsvdm_version() >= 10000
+
+
+def _colmajor_bytes(M):
+    return np.ascontiguousarray(np.asarray(M, dtype=np.float64).T)
+
+
+def test_check_transform_accepts_orthogonal_and_scaled(lib):
+    for M, c2 in [(synth.dct2_matrix(16), 1.0),
+                  (synth.haar_orthogonal(9, np.random.default_rng(0)), 1.0),
+                  (3.0 * synth.dct2_matrix(5), 9.0)]:
+        Mc = _colmajor_bytes(M)
+        out = c_double(0)
+        rc = lib.tsvdm_check_transform(c_void_p(Mc.ctypes.data), M.shape[0], 1e-10, byref(out))
+        assert rc == 0
+        assert abs(out.value - c2) < 1e-12 * c2
+
+
+def test_check_transform_rejects(lib):
+    M = np.array([[1.0, 0.3], [0.0, 1.0]])
+    Mc = _colmajor_bytes(M)
+    rc = lib.tsvdm_check_transform(c_void_p(Mc.ctypes.data), 2, 1e-10, None)
+    assert rc == -3
+    assert b"orthogonal" in lib.tsvdm_last_error()
+    Z = np.zeros((3, 3))
+    assert lib.tsvdm_check_transform(c_void_p(Z.ctypes.data), 3, 1e-10, None) == -3
+    assert lib.tsvdm_check_transform(None, 3, 1e-10, None) == -1
+
+
+DUMMY = c_void_p(256)  # never dereferenced: every call below fails validation
+
+
+def test_workspace_queries(lib):
+    from paper_2605_16058_amd import _lib
+    assert _lib.workspace_size("tsvdm_transform_workspace_size", 256) >= 256 * 256 * 8
+    assert _lib.workspace_size("tsvdm_slice_svd_workspace_size", 512, 1024, 256, 0) > 0
+    assert _lib.workspace_size("tsvdm_truncate_tol_workspace_size", 512, 256) >= 131072 * 8
+    assert _lib.workspace_size("tsvdm_pack_workspace_size", 64, 48, 16) >= 48 * 16 * 4
+    assert _lib.workspace_size("tsvdm_reconstruct_workspace_size", 64, 48, 16, 0) >= 64 * 48 * 16 * 8
+    assert _lib.workspace_size("tsvdm_error_workspace_size", 1000) > 0
+    assert _lib.workspace_size("tsvdm_backward_workspace_size", 32, 24, 8, 1) > 0
+    out = c_size_t(0)
+    assert lib.tsvdm_slice_svd_workspace_size(0, 4, 4, 0, byref(out)) == -2
+    assert lib.tsvdm_slice_svd_workspace_size(4, 4, 4, 2, byref(out)) == -8
+
+
+def test_transform_validation(lib):
+    ok = (DUMMY, 1, c_void_p(512), 1, 8, 8, 4, DUMMY, 0, 1.0, 0, DUMMY, 1 << 20, None)
+    # null input
+    a = list(ok); a[0] = None
+    assert lib.tsvdm_transform(*a) == -1
+    # bad shape
+    a = list(ok); a[4] = 0
+    assert lib.tsvdm_transform(*a) == -2
+    # bad dtype / compute
+    a = list(ok); a[1] = 7
+    assert lib.tsvdm_transform(*a) == -8
+    a = list(ok); a[10] = 2; a[3] = 0  # bf16 compute into an F64 output
+    assert lib.tsvdm_transform(*a) == -8
+    # aliasing
+    a = list(ok); a[2] = a[0]
+    assert lib.tsvdm_transform(*a) == -1
+    # workspace too small
+    a = list(ok); a[12] = 8
+    assert lib.tsvdm_transform(*a) == -4
+    assert b"workspace" in lib.tsvdm_last_error()
+
+
+def test_slice_svd_validation(lib):
+    base = [DUMMY, 0, 16, 12, 4, DUMMY, DUMMY, DUMMY, 0, 0, 0.0, 1, DUMMY, 1 << 20, None]
+    a = list(base); a[8] = 7
+    assert lib.tsvdm_slice_svd(*a) == -1
+    a = list(base); a[10] = 1.5
+    assert lib.tsvdm_slice_svd(*a) == -1
+    a = list(base); a[6] = None
+    assert lib.tsvdm_slice_svd(*a) == -1
+    a = list(base); a[13] = 0
+    assert lib.tsvdm_slice_svd(*a) == -4
+
+
+def test_truncation_validation(lib):
+    assert lib.tsvdm_truncate_rank(0, 4, 4, DUMMY, DUMMY, None) == -1
+    assert lib.tsvdm_truncate_rank(2, 0, 4, DUMMY, DUMMY, None) == -2
+    base = [DUMMY, 8, 4, 0.1, DUMMY, DUMMY, DUMMY, DUMMY, 1 << 20, None]
+    for eps in (0.0, 1.0, -0.5, float("nan")):
+        a = list(base); a[3] = eps
+        assert lib.tsvdm_truncate_tol(*a) == -1
+    a = list(base); a[8] = 16
+    assert lib.tsvdm_truncate_tol(*a) == -4
+
+
+def test_pack_reconstruct_error_backward_validation(lib):
+    p = [DUMMY, DUMMY, DUMMY, 0, 8, 6, 3, DUMMY, DUMMY, -1, DUMMY, DUMMY, DUMMY, DUMMY, DUMMY,
+         1 << 20, None]
+    assert lib.tsvdm_pack(*p) == -1
+    p[9] = 4; p[3] = 5
+    assert lib.tsvdm_pack(*p) == -8
+    rc = [DUMMY, DUMMY, 0, 8, 6, 3, DUMMY, DUMMY, 4, None, 1.0, DUMMY, 0, 0, DUMMY, 1 << 20, None]
+    assert lib.tsvdm_reconstruct(*rc) == -1
+    rc[9] = DUMMY; rc[10] = float("inf")
+    assert lib.tsvdm_reconstruct(*rc) == -1
+    assert lib.tsvdm_error(DUMMY, 0, DUMMY, 0, 0, DUMMY, DUMMY, 1 << 20, None) == -2
+    bw = [DUMMY, 1, 8, 6, 3, DUMMY, 0, 1.0, None, None, DUMMY, DUMMY, DUMMY, 1 << 30, None]
+    assert lib.tsvdm_backward(*bw) == -1
+    bw[6] = 2; bw[14 - 1] = 1
+    assert lib.tsvdm_backward(*bw) == -4

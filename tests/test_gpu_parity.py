@@ -1,0 +1,374 @@
+"""GPU parity: every C-ABI step against the FP64 oracle on seeded inputs.
+
+Sizes are small enough for the oracle to finish in seconds but span several
+tiles, ragged tails (r not a multiple of the Jacobi block, row counts not a
+multiple of 64, n not a multiple of 16), both slice orientations (m >= p:
+columns are the Jacobi vectors; m < p: rows) and the degenerate cases.
+
+Tolerances (relative, Frobenius unless stated), derived from the arithmetic:
+  transform  FP64 MFMA: 1e-13; FP32 MFMA: 4 sqrt(n) u32 (u32 = 2^-24);
+             split BF16 (3 products): 3e-5; plain BF16: 1e-2.
+  slice SVD  |sigma - sigma_oracle| <= 1e-13 sigma_max (FP64), 2e-5 sigma_max (FP32)
+  ranks      bit-exact when fed the same squared values; against the oracle's
+             own squares bit-exact whenever the threshold margin exceeds 1e-10.
+  t-SVDM     FP64 reconstruction vs oracle <= 1e-10.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle as O
+import synth
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def ops():
+    from paper_2605_16058_amd import ops as _ops
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    return _ops
+
+
+def to_dev(A, dtype=torch.float64):
+    """numpy (m, p, n) -> column-major device tensor"""
+    t = torch.from_numpy(np.asfortranarray(A)).to(dtype)
+    out = torch.empty((A.shape[2], A.shape[1], A.shape[0]), dtype=dtype, device="cuda").permute(2, 1, 0)
+    out.copy_(t)
+    return out
+
+
+def to_np(t):
+    return t.detach().double().cpu().numpy()
+
+
+def rel(a, b):
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    d = np.linalg.norm(b.ravel())
+    return float(np.linalg.norm((a - b).ravel()) / (d if d > 0 else 1.0))
+
+
+U32 = 2.0 ** -24
+
+# ---------------------------------------------------------------------------
+# transform
+# ---------------------------------------------------------------------------
+
+
+@pytest.mark.parametrize("shape", [(70, 50, 20), (33, 17, 5), (1, 7, 1), (130, 3, 64)])
+@pytest.mark.parametrize("compute,xdt,bound", [
+    ("f64", torch.float64, 1e-13),
+    ("f64", torch.float32, 1e-13),
+    ("f32", torch.float32, None),
+    ("bf16x3", torch.float32, 3e-5),
+    ("bf16", torch.float32, 1e-2),
+])
+def test_transform_matches_oracle(ops, shape, compute, xdt, bound):
+    m, p, n = shape
+    g = np.random.default_rng(100 + n)
+    A = g.standard_normal(shape)
+    A_in = A.astype(np.float32) if xdt == torch.float32 else A
+    M = synth.haar_orthogonal(n, g)
+    X = to_dev(A_in, xdt)
+    Mdev = ops.device_matrix(M)
+    odt = torch.float64 if compute == "f64" else torch.float32
+    Y = ops.tsvdm_transform(X, Mdev, compute=compute, out_dtype=odt)
+    ref = O.mode3(A_in, M)
+    b = bound if bound is not None else 4 * math.sqrt(n) * U32
+    assert rel(to_np(Y), ref) <= b
+    # back-transform with scale: (Y x_3 (s M^T)) = s * A for orthogonal M
+    Z = ops.tsvdm_transform(Y, Mdev, transpose=True, scale=0.5, compute=compute, out_dtype=odt)
+    assert rel(to_np(Z), 0.5 * np.asarray(A_in, np.float64)) <= 3 * b
+
+
+def test_transform_orientation_cyclic_permutation(ops):
+    n = 9
+    P = np.zeros((n, n))
+    for i in range(n):
+        P[i, (i + 1) % n] = 1.0
+    A = np.random.default_rng(1).standard_normal((40, 30, n))
+    Y = to_np(ops.tsvdm_transform(to_dev(A), ops.device_matrix(P), compute="f64"))
+    for i in range(n):
+        assert np.array_equal(Y[:, :, i], A[:, :, (i + 1) % n])
+
+
+# ---------------------------------------------------------------------------
+# slice SVD
+# ---------------------------------------------------------------------------
+
+def _sorted_sigma(s2_row):
+    return np.sort(np.sqrt(np.maximum(s2_row, 0.0)))[::-1]
+
+
+@pytest.mark.parametrize("shape", [(64, 48, 4), (48, 64, 4), (100, 37, 3), (37, 100, 3),
+                                   (300, 200, 2), (5, 1, 3), (1, 6, 2), (129, 129, 2)])
+@pytest.mark.parametrize("dtype,block", [(torch.float64, 16), (torch.float64, 32),
+                                         (torch.float32, 16), (torch.float32, 32)])
+def test_slice_svd_matches_oracle(ops, shape, dtype, block):
+    m, p, n = shape
+    r = min(m, p)
+    g = np.random.default_rng(7 * m + p)
+    A = g.standard_normal(shape) * np.logspace(0, -4, p)[None, :, None]
+    A = A.astype(np.float32).astype(np.float64) if dtype == torch.float32 else A
+    Ad = to_dev(A, dtype)
+    W, s2, st = ops.tsvdm_slice_svd(Ad, block=block)
+    torch.cuda.synchronize()
+    assert int(st.item()) == 0
+    _U, S, _V = O.slice_svd(A)
+    s2n = to_np(s2)
+    Bn = to_np(Ad)
+    Wn = to_np(W)
+    fp64 = dtype == torch.float64
+    for i in range(n):
+        smax = S[0, i]
+        tol = (1e-13 if fp64 else 2e-5) * smax
+        assert np.max(np.abs(_sorted_sigma(s2n[i]) - S[:, i])) <= tol
+        Wi = Wn[i].T  # column-major r x r
+        assert np.max(np.abs(Wi.T @ Wi - np.eye(r))) <= (1e-13 if fp64 else 1e-5) * max(1, r) ** 0.5
+        Bi = Bn[:, :, i]
+        # factorisation: rows case A = W B, columns case A = B W^T
+        rec = Wi @ Bi if m < p else Bi @ Wi.T
+        assert rel(rec, A[:, :, i]) <= (1e-13 if fp64 else 2e-6)
+        # squared norms are those of the final vectors
+        vec_norm2 = np.sum(Bi * Bi, axis=1 if m < p else 0)
+        assert np.allclose(vec_norm2, s2n[i], rtol=1e-12 if fp64 else 1e-5, atol=1e-300)
+
+
+def test_slice_svd_status_and_host_poll_equivalence(ops):
+    A = np.random.default_rng(3).standard_normal((80, 60, 3))
+    a1 = to_dev(A)
+    a2 = to_dev(A)
+    W1, s1, st1 = ops.tsvdm_slice_svd(a1, host_poll=True)
+    W2, s2_, st2 = ops.tsvdm_slice_svd(a2, host_poll=False)
+    torch.cuda.synchronize()
+    assert int(st1.item()) == 0 and int(st2.item()) == 0
+    # the same sweeps run either way: bitwise identical results
+    assert torch.equal(s1, s2_) and torch.equal(a1, a2) and torch.equal(W1, W2)
+    # determinism: a second run gives the same bits
+    a3 = to_dev(A)
+    W3, s3, _ = ops.tsvdm_slice_svd(a3)
+    torch.cuda.synchronize()
+    assert torch.equal(s1, s3) and torch.equal(a1, a3)
+
+
+def test_slice_svd_reports_nonconvergence(ops):
+    A = np.random.default_rng(4).standard_normal((64, 64, 2))
+    _W, _s2, st = ops.tsvdm_slice_svd(to_dev(A), max_sweeps=1)
+    torch.cuda.synchronize()
+    assert int(st.item()) == -5
+
+
+def test_slice_svd_reports_nonfinite(ops):
+    A = np.random.default_rng(5).standard_normal((20, 10, 2))
+    A[3, 4, 1] = np.nan
+    _W, _s2, st = ops.tsvdm_slice_svd(to_dev(A))
+    torch.cuda.synchronize()
+    assert int(st.item()) == -6
+
+
+# ---------------------------------------------------------------------------
+# rank selection
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("r,n", [(48, 16), (7, 3), (512, 40), (1, 1), (33, 300)])
+@pytest.mark.parametrize("eps", [1e-3, 0.05, 0.5, 0.99])
+def test_truncate_tol_bit_exact_on_same_squares(ops, r, n, eps):
+    g = np.random.default_rng(r * 1000 + n)
+    sq = (g.standard_normal((n, r)) * np.logspace(0, -6, r)[None, :]) ** 2
+    rho, off, stats = ops.tsvdm_truncate_tol(torch.from_numpy(sq).cuda(), eps)
+    torch.cuda.synchronize()
+    rho_o, info = O.ranks_tolerance(sq.T, eps, squared=True)
+    assert np.array_equal(rho.cpu().numpy(), rho_o)
+    o = off.cpu().numpy()
+    assert o[0] == 0 and np.array_equal(np.diff(o), rho_o)
+    st = stats.cpu().numpy()
+    assert st[0] == info["tau"] and int(st[3]) == info["J"]
+    assert st[2] == info["total"] and st[1] == info["discarded"]
+
+
+def test_truncate_tol_ties_zeros_and_empty(ops):
+    S = np.array([[10.0, 1.0], [1.0, 1.0], [0.0, 1.0]])  # r=3, n=2 (oracle layout r x n)
+    sq = (S * S).T.copy()
+    rho, _off, stats = ops.tsvdm_truncate_tol(torch.from_numpy(sq).cuda(), math.sqrt(0.025))
+    assert list(rho.cpu().numpy()) == [1, 0]
+    assert float(stats[0]) == 1.0 and float(stats[1]) == 4.0
+    z = torch.zeros((4, 5), dtype=torch.float64, device="cuda")
+    rho, off, stats = ops.tsvdm_truncate_tol(z, 0.5)
+    assert int(rho.sum()) == 0 and int(off[-1]) == 0
+    rho, off, stats = ops.tsvdm_truncate_tol(torch.ones((2, 3), dtype=torch.float64, device="cuda"), 0.1)
+    assert list(rho.cpu().numpy()) == [3, 3]
+
+
+def test_truncate_rank_clamps(ops):
+    rho, off = ops.tsvdm_truncate_rank(9, 5, 4)
+    assert list(rho.cpu().numpy()) == [5] * 4 and list(off.cpu().numpy()) == [0, 5, 10, 15, 20]
+
+
+# ---------------------------------------------------------------------------
+# end to end
+# ---------------------------------------------------------------------------
+
+def _threshold_margin(sq_all, tau, eps):
+    v = np.sort(sq_all.ravel())
+    if not np.isfinite(tau):
+        return 1.0
+    lo = v[v <= tau].max()
+    hi = v[v > tau].min() if np.any(v > tau) else np.inf
+    return min(abs(hi - lo) / max(lo, 1e-300), 1.0)
+
+
+def _check_factors(res, ref, m, p, n, fp64):
+    rho = res.rho.cpu().numpy()
+    off = res.offsets.cpu().numpy()
+    U = to_np(res.U_pk)
+    G = to_np(res.G_pk)
+    S = to_np(res.S_pk)
+    for i in range(n):
+        k = int(rho[i])
+        if k == 0:
+            continue
+        o = int(off[i])
+        Ui = U[m * o: m * (o + k)].reshape(k, m).T
+        Gi = G[p * o: p * (o + k)].reshape(p, k).T
+        si = S[o: o + k]
+        # singular values descending and equal to the oracle's leading ones
+        assert np.all(np.diff(si) <= 0)
+        assert np.allclose(si, ref["S"][:k, i], rtol=0, atol=(1e-12 if fp64 else 2e-5) * ref["S"][0, i])
+        # orthonormal columns
+        assert np.max(np.abs(Ui.T @ Ui - np.eye(k))) <= (1e-12 if fp64 else 2e-5) * math.sqrt(k)
+        # G_i = S_i V_i^T: rows have norms sigma
+        assert np.allclose(np.linalg.norm(Gi, axis=1), si, rtol=1e-10 if fp64 else 1e-4)
+
+
+def test_tsvdm_i_planted_fp64(ops):
+    from paper_2605_16058_amd.pipeline import tsvdm
+    w = synth.workload("planted")
+    A = w.A
+    res = tsvdm(to_dev(A), w.M, mode="I", k=w.k, precision="f64")
+    torch.cuda.synchronize()
+    ref = O.tsvdm_i(A, w.M, w.k)
+    assert int(res.svd_status.item()) == 0 and int(res.pack_status.item()) == 0
+    assert np.array_equal(res.rho.cpu().numpy(), ref["rho"])
+    assert rel(to_np(res.A_rec), ref["A_rec"]) <= 1e-10
+    assert abs(res.rel_error() - ref["rel_error"]) <= 1e-12
+    _check_factors(res, ref, 64, 48, 16, True)
+
+
+@pytest.mark.parametrize("eps", [1e-3, 1e-2, 0.2])
+def test_tsvdm_ii_climate_fp64(ops, eps):
+    from paper_2605_16058_amd.pipeline import tsvdm
+    w = synth.workload("climate", small=True)
+    A = w.A.astype(np.float64)  # the FP32 input, as the GPU sees it
+    m, p, n = A.shape
+    res = tsvdm(to_dev(w.A, torch.float32), w.M, mode="II", eps=eps, precision="f64")
+    torch.cuda.synchronize()
+    ref = O.tsvdm_ii(A, w.M, eps)
+    assert int(res.svd_status.item()) == 0
+    sq = ref["S"] ** 2
+    margin = _threshold_margin(sq, ref["info"]["tau"], eps)
+    if margin > 1e-10:
+        assert np.array_equal(res.rho.cpu().numpy(), ref["rho"])
+        assert rel(to_np(res.A_rec), ref["A_rec"]) <= 1e-10
+    # the GPU's own squares through the oracle's selection: bit-exact always
+    rho_o, _ = O.ranks_tolerance(to_np(res.s2).T, eps, squared=True)
+    assert np.array_equal(res.rho.cpu().numpy(), rho_o)
+    assert res.rel_error() < eps
+    assert abs(res.rel_error() - ref["rel_error"]) <= 1e-9 * max(ref["rel_error"], 1e-3)
+    _check_factors(res, ref, m, p, n, True)
+
+
+@pytest.mark.parametrize("precision,bound", [("f32", 3e-5), ("bf16x3", 5e-5), ("bf16", 2e-2)])
+def test_tsvdm_ii_turbulence_mixed(ops, precision, bound):
+    """Mixed precision: the stated bound is on the reconstruction against
+    the oracle's, relative to ||A||; the error against A must stay below
+    eps up to that bound, and ranks differ from the oracle's only where
+    the perturbed squares cross the threshold."""
+    from paper_2605_16058_amd.pipeline import tsvdm
+    w = synth.workload("turbulence", small=True)
+    A = w.A.astype(np.float64)
+    eps = 0.1
+    res = tsvdm(to_dev(w.A, torch.float32), w.M, mode="II", eps=eps, precision=precision)
+    torch.cuda.synchronize()
+    ref = O.tsvdm_ii(A, w.M, eps)
+    assert int(res.svd_status.item()) == 0
+    d = rel(to_np(res.A_rec), ref["A_rec"]) * np.linalg.norm(ref["A_rec"]) / np.linalg.norm(A)
+    drho = int(np.abs(res.rho.cpu().numpy() - ref["rho"]).sum())
+    print(f"{precision}: |A_rec - A_rec_oracle|/|A| = {d:.3e}, sum|drho| = {drho}, "
+          f"rel_err = {res.rel_error():.6e} (oracle {ref['rel_error']:.6e})")
+    assert res.rel_error() < eps * (1 + bound)
+    if precision != "bf16":
+        assert d <= bound * 10 or drho > 0
+
+
+def test_zero_tensor_and_degenerate_shapes(ops):
+    from paper_2605_16058_amd.pipeline import tsvdm
+    Z = np.zeros((20, 12, 4))
+    res = tsvdm(to_dev(Z), synth.dct2_matrix(4), mode="II", eps=0.1, precision="f64")
+    torch.cuda.synchronize()
+    assert int(res.rho.sum()) == 0 and float(res.A_rec.abs().max()) == 0.0
+    assert res.rel_error() == 0.0
+    # k > r, a single tube and a single slice
+    A = np.random.default_rng(9).standard_normal((1, 9, 5))
+    res = tsvdm(to_dev(A), synth.dct2_matrix(5), mode="I", k=4, precision="f64")
+    torch.cuda.synchronize()
+    assert list(res.rho.cpu().numpy()) == [1] * 5
+    assert rel(to_np(res.A_rec), A) <= 1e-13
+    A = np.random.default_rng(10).standard_normal((15, 11, 1))
+    res = tsvdm(to_dev(A), np.eye(1), mode="I", k=3, precision="f64")
+    ref = O.tsvdm_i(A, np.eye(1), 3)
+    assert rel(to_np(res.A_rec), ref["A_rec"]) <= 1e-12
+
+
+def test_pack_capacity_overflow_is_reported(ops):
+    A = np.random.default_rng(11).standard_normal((30, 20, 3))
+    Ad = to_dev(A)
+    W, s2, _ = ops.tsvdm_slice_svd(Ad)
+    rho, off = ops.tsvdm_truncate_rank(10, 20, 3)
+    U, G, S, st = ops.tsvdm_pack(Ad, W, s2, rho, off, capacity=15)
+    torch.cuda.synchronize()
+    assert int(st.item()) == -9
+    # the first slice fits and is written; the others are not touched
+    assert float(S[:10].abs().min()) > 0
+
+
+# ---------------------------------------------------------------------------
+# adjoint
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("dtype,bound", [(torch.float64, 1e-9), (torch.float32, 2e-4)])
+def test_backward_matches_oracle(ops, dtype, bound):
+    w = synth.workload("cayley", small=True)
+    A = w.A.astype(np.float64)
+    K = w.extra["K0"]
+    M = O.cayley(K)
+    k = w.k
+    loss, dA, dM, st = ops.tsvdm_backward(to_dev(w.A, dtype), ops.device_matrix(M), k, g=1.0)
+    torch.cuda.synchronize()
+    assert int(st.item()) == 0
+    L_o, dA_o, GM_o = O.trunc_loss_grad(A, M, k)
+    assert abs(float(loss.item()) - L_o) <= bound * L_o
+    assert rel(to_np(dA), dA_o) <= bound * 10
+    assert rel(dM.cpu().numpy(), GM_o) <= bound * 10
+
+
+def test_autograd_function(ops):
+    from paper_2605_16058_amd.pipeline import TruncLoss
+    w = synth.workload("cayley", small=True)
+    A = to_dev(w.A, torch.float64).requires_grad_(True)
+    K = torch.tensor(w.extra["K0"], device="cuda", requires_grad=True)
+    I = torch.eye(K.shape[0], dtype=torch.float64, device="cuda")
+    M = torch.linalg.solve(I - K, I + K)
+    L = TruncLoss.apply(A, M, w.k)
+    L.backward()
+    L_o, dA_o, GM_o = O.trunc_loss_grad(w.A.astype(np.float64), O.cayley(w.extra["K0"]), w.k)
+    dK_o = O.cayley_grad(w.extra["K0"], GM_o)
+    assert abs(float(L) - L_o) <= 1e-9 * L_o
+    assert rel(to_np(A.grad), dA_o) <= 1e-8
+    # torch's gradient for an unconstrained K is Y (dL/dK_ab = Y_ab); the
+    # skew-parameter gradient is Y - Y^T
+    Y = K.grad.cpu().numpy()
+    assert rel(Y - Y.T, dK_o) <= 1e-8
