@@ -59,7 +59,7 @@ __global__ __launch_bounds__(256) void tsmm_partial(const T* __restrict__ P, con
         if (l >= n) continue;
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
-            const int i = i0 + wave * 16 + lg * 4 + v;
+            const int i = i0 + wave * 16 + mfma_row<T>(lg, v);
             if (i < n) out[i + (int64_t)l * n] = (double)acc[t][v];
         }
     }

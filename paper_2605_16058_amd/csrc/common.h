@@ -71,6 +71,12 @@ typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
 // For the 16x16x4 shapes a k-group is one k; for 16x16x32 bf16 it is eight
 // consecutive k.  A and B always use the same k mapping, so any permutation
 // of k inside a group is harmless.
+// The D row of element v differs by type (measured on gfx950):
+//   f32 / bf16 (FP32 accumulators): row 4*(L/16) + v
+//   f64:                            row (L/16) + 4*v
+template <class T> __device__ __forceinline__ int mfma_row(int lg, int v);
+template <> __device__ __forceinline__ int mfma_row<float>(int lg, int v) { return 4 * lg + v; }
+template <> __device__ __forceinline__ int mfma_row<double>(int lg, int v) { return lg + 4 * v; }
 __device__ __forceinline__ v4d mfma_f64(double a, double b, v4d c) {
     return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }
@@ -145,14 +151,17 @@ __device__ __forceinline__ double dd_round(dd a) { return a.hi + a.lo; }
 
 // Slice geometry: r = min(m, p) Jacobi vectors of length L = max(m, p).
 // Element t of vector j of a slice lives at j*vs + t*es.
+// `rows` says which orientation holds (it cannot be inferred from es: for
+// m = 1 the rows have element stride 1).
 struct SliceGeom {
     int64_t m, p, r, L, vs, es;
+    int rows;
 };
 __host__ __device__ inline SliceGeom slice_geom(int64_t m, int64_t p) {
     SliceGeom g;
     g.m = m; g.p = p;
-    if (m >= p) { g.r = p; g.L = m; g.vs = m; g.es = 1; }   // columns
-    else        { g.r = m; g.L = p; g.vs = 1; g.es = m; }   // rows
+    if (m >= p) { g.r = p; g.L = m; g.vs = m; g.es = 1; g.rows = 0; }   // columns
+    else        { g.r = m; g.L = p; g.vs = 1; g.es = m; g.rows = 1; }   // rows
     return g;
 }
 

@@ -204,7 +204,7 @@ __global__ __launch_bounds__(256) void jacobi_round(T* __restrict__ A, T* __rest
         const int q = wave * TPW + j, tr = q / NT, tc = q % NT;
 #pragma unroll
         for (int v = 0; v < 4; ++v)
-            Hs[(tr * 16 + lg * 4 + v) * HP + tc * 16 + lr] = (double)hacc[j][v];
+            Hs[(tr * 16 + mfma_row<T>(lg, v)) * HP + tc * 16 + lr] = (double)hacc[j][v];
     }
     if (tid == 0) flag_nf = 0;
     __syncthreads();
@@ -326,7 +326,7 @@ __global__ __launch_bounds__(256) void jacobi_round(T* __restrict__ A, T* __rest
                 const int q = wave * UPW + j, ta = q / 4, tt = q % 4;
 #pragma unroll
                 for (int v = 0; v < 4; ++v)
-                    Ts[(ta * 16 + lg * 4 + v) * LDP + tt * 16 + lr] = uacc[j][v];
+                    Ts[(ta * 16 + mfma_row<T>(lg, v)) * LDP + tt * 16 + lr] = uacc[j][v];
             }
             __syncthreads();
             store_chunk(base, vs, es, t0, len);

@@ -85,7 +85,7 @@ __global__ __launch_bounds__(256) void pack_copy(const T* __restrict__ A, const 
     const T* Ab = A + s * m * p;
     const T* Wb = W + s * r * r;
     const int32_t* pr = perm + s * r + first;
-    const bool rows = g.es != 1;  // m < p: vectors are rows, W holds U
+    const bool rows = g.rows != 0;  // m < p: vectors are rows, W holds U
     const int64_t nu = kr * m, ng = kr * p;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < nu + ng; e += stride) {
@@ -173,7 +173,7 @@ __global__ __launch_bounds__(256) void lowrank_gemm(const T* __restrict__ U_pk,
         if (a >= m) continue;
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
-            const int64_t b = b0 + wave * 16 + lg * 4 + v;
+            const int64_t b = b0 + wave * 16 + mfma_row<T>(lg, v);
             if (b < p) Cb[a + b * m] = acc[t][v];
         }
     }

@@ -125,7 +125,7 @@ __global__ __launch_bounds__(256) void ttm_kernel(
         if (row >= R) continue;
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
-            int i = i0 + wave * 16 + lg * 4 + v;
+            int i = i0 + wave * 16 + mfma_row<CT>(lg, v);
             if (i < n) stg_as(Y, row + (int64_t)i * R, ydt, (double)acc[t][v]);
         }
     }
