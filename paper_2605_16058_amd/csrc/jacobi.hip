@@ -63,9 +63,6 @@ void stats_get(int64_t* launches, double* ms, int64_t* pg, int64_t* pr, int32_t*
 
 namespace {
 
-constexpr int TC = 64;          // vector elements per staged chunk
-constexpr int LDP = TC + 1;     // padded LDS row of a chunk
-
 __device__ __forceinline__ int circle_player(int seat, int round, int N) {
     return seat == 0 ? 0 : ((seat - 1 + round) % (N - 1)) + 1;
 }
@@ -97,37 +94,46 @@ __global__ void jacobi_init(T* __restrict__ W, int64_t r, int64_t n, JacobiCtl* 
     }
 }
 
+// Chunk geometry: every staged chunk is 16 KB (NB2 vectors x TC elements),
+// i.e. four 16-byte vector loads per thread.
 template <class T, int NB2>
-struct RoundSmem {
-    static constexpr int NT = NB2 / 16;
+struct RoundCfg {
+    static constexpr int VW = 16 / sizeof(T);                  // elements per 16-byte access
+    static constexpr int TC = 16384 / (NB2 * (int)sizeof(T));  // chunk length
+    static constexpr int LDP = TC + VW;                        // padded LDS row (16-byte aligned)
+    static constexpr int NV = NB2 * TC / VW / 256;             // vector accesses per thread
+    static constexpr int NT = NB2 / 16;                        // 16x16 tiles per dimension
+    static constexpr int HP = NB2 + 1;
     static constexpr size_t ts_bytes = sizeof(T) * NB2 * LDP;
-    static constexpr size_t qf_bytes = sizeof(T) == 4 ? sizeof(T) * NB2 * (NB2 + 1) : 0;
-    static constexpr size_t hs_bytes = sizeof(double) * NB2 * (NB2 + 1);
-    static constexpr size_t buf0 = (ts_bytes + qf_bytes > hs_bytes) ? ts_bytes + qf_bytes : hs_bytes;
-    static constexpr size_t total = buf0 + hs_bytes;  // + Qs (double)
+    static constexpr size_t hs_bytes = sizeof(double) * NB2 * HP;
+    static constexpr size_t r1 = (2 * ts_bytes > hs_bytes) ? 2 * ts_bytes : hs_bytes;
+    static constexpr size_t q_bytes = sizeof(T) * NB2 * HP;
+    static constexpr size_t total = r1 + q_bytes;
 };
 
-template <class T, int NB2>
+// One round of the block tournament for every (slice, pair).
+//   ROWS: the Jacobi vectors are slice rows (m < p), else columns.
+//   vec_a / vec_w: 16-byte accesses are legal for the slice / for W.
+template <class T, int NB2, bool ROWS>
 __global__ __launch_bounds__(256) void jacobi_round(T* __restrict__ A, T* __restrict__ W, SliceGeom g,
                                                     int nbe, int rnd, JacobiCtl* __restrict__ ctl,
-                                                    double tol,
+                                                    double tol, int vec_a, int vec_w,
                                                     unsigned long long* __restrict__ pair_counts) {
-    typedef RoundSmem<T, NB2> SM;
+    typedef RoundCfg<T, NB2> C;
     typedef typename Acc<T>::type AccT;
-    constexpr int B = NB2 / 2;
-    constexpr int NT = SM::NT;
-    constexpr int HP = NB2 + 1;
+    constexpr int B = NB2 / 2, VW = C::VW, TC = C::TC, LDP = C::LDP, NV = C::NV;
+    constexpr int NT = C::NT, HP = C::HP;
 
-    __shared__ __align__(16) char smem[SM::total];
+    __shared__ __align__(16) char smem[C::total];
     __shared__ double rot_c[NB2 / 2], rot_s[NB2 / 2];
     __shared__ int rot_p[NB2 / 2], rot_q[NB2 / 2];
-    __shared__ double red[8];
+    __shared__ double red[4], redw[4];
     __shared__ int flag_nf;
 
-    T* Ts = reinterpret_cast<T*>(smem);                          // [NB2][LDP]
-    double* Hs = reinterpret_cast<double*>(smem);                // [NB2][HP] (phase 2)
-    T* Qf = reinterpret_cast<T*>(smem + SM::ts_bytes);           // [NB2][HP] (phase 3, float)
-    double* Qs = reinterpret_cast<double*>(smem + SM::buf0);     // [NB2][HP]
+    T* Ts = reinterpret_cast<T*>(smem);                           // [NB2][LDP] staged input
+    T* Ts2 = reinterpret_cast<T*>(smem + C::ts_bytes);            // [NB2][LDP] staged output
+    double* Hs = reinterpret_cast<double*>(smem);                 // [NB2][HP]  (phase 2 only)
+    T* Qs = reinterpret_cast<T*>(smem + C::r1);                   // [NB2][HP]  Q[c][a]
 
     const int npairs = nbe / 2;
     const int64_t s = blockIdx.x / npairs;
@@ -146,59 +152,133 @@ __global__ __launch_bounds__(256) void jacobi_round(T* __restrict__ A, T* __rest
 
     auto gidx = [&](int a) -> int64_t { return a < B ? (int64_t)I * B + a : (int64_t)J * B + (a - B); };
 
-    // stage vectors [a][t0 .. t0+TC) of a strided family into Ts
-    auto load_chunk = [&](const T* base, int64_t vs, int64_t es, int64_t t0, int64_t len) {
-        if (es == 1) {
-            for (int e = tid; e < NB2 * TC; e += 256) {
-                int t = e % TC, a = e / TC;
-                int64_t gi = gidx(a), tt = t0 + t;
-                Ts[a * LDP + t] = (gi < r && tt < len) ? base[gi * vs + tt] : T(0);
-            }
-        } else {
-            for (int e = tid; e < NB2 * TC; e += 256) {
-                int a = e % NB2, t = e / NB2;
-                int64_t gi = gidx(a), tt = t0 + t;
-                Ts[a * LDP + t] = (gi < r && tt < len) ? base[gi * vs + tt * es] : T(0);
+    // ---- global <-> register <-> LDS streaming of one chunk [t0, t0 + TC)
+    // Access e of a thread covers VW consecutive elements along the
+    // contiguous direction: t for column families, the vector index a for
+    // row families (a block of B rows is contiguous, B % VW == 0).
+    T regs[NV][VW];
+    auto gload = [&](const T* base, int64_t vs, int64_t es, bool rows, bool vec, int64_t t0,
+                     int64_t len) {
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+            const int e = tid + 256 * v;
+            if (!rows) {
+                const int a = e / (TC / VW), tt = (e % (TC / VW)) * VW;
+                const int64_t gi = gidx(a), t = t0 + tt;
+                const T* src = base + gi * vs + t;
+                if (gi < r && vec && t + VW <= len) {
+                    if constexpr (sizeof(T) == 4) {
+                        float4 x = *reinterpret_cast<const float4*>(src);
+                        regs[v][0] = x.x; regs[v][1] = x.y; regs[v][2] = x.z; regs[v][3] = x.w;
+                    } else {
+                        double2 x = *reinterpret_cast<const double2*>(src);
+                        regs[v][0] = x.x; regs[v][1] = x.y;
+                    }
+                } else {
+#pragma unroll
+                    for (int j = 0; j < VW; ++j) regs[v][j] = (gi < r && t + j < len) ? src[j] : T(0);
+                }
+            } else {
+                const int a4 = (e % (NB2 / VW)) * VW, tt = e / (NB2 / VW);
+                const int64_t gi = gidx(a4), t = t0 + tt;
+                const T* src = base + gi + t * es;
+                if (t < len && vec && gi + VW <= r) {
+                    if constexpr (sizeof(T) == 4) {
+                        float4 x = *reinterpret_cast<const float4*>(src);
+                        regs[v][0] = x.x; regs[v][1] = x.y; regs[v][2] = x.z; regs[v][3] = x.w;
+                    } else {
+                        double2 x = *reinterpret_cast<const double2*>(src);
+                        regs[v][0] = x.x; regs[v][1] = x.y;
+                    }
+                } else {
+#pragma unroll
+                    for (int j = 0; j < VW; ++j) regs[v][j] = (t < len && gi + j < r) ? src[j] : T(0);
+                }
             }
         }
     };
-    auto store_chunk = [&](T* base, int64_t vs, int64_t es, int64_t t0, int64_t len) {
-        if (es == 1) {
-            for (int e = tid; e < NB2 * TC; e += 256) {
-                int t = e % TC, a = e / TC;
-                int64_t gi = gidx(a), tt = t0 + t;
-                if (gi < r && tt < len) base[gi * vs + tt] = Ts[a * LDP + t];
+    auto regs_to_lds = [&](bool rows) {
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+            const int e = tid + 256 * v;
+            if (!rows) {
+                const int a = e / (TC / VW), tt = (e % (TC / VW)) * VW;
+#pragma unroll
+                for (int j = 0; j < VW; ++j) Ts[a * LDP + tt + j] = regs[v][j];
+            } else {
+                const int a4 = (e % (NB2 / VW)) * VW, tt = e / (NB2 / VW);
+#pragma unroll
+                for (int j = 0; j < VW; ++j) Ts[(a4 + j) * LDP + tt] = regs[v][j];
             }
-        } else {
-            for (int e = tid; e < NB2 * TC; e += 256) {
-                int a = e % NB2, t = e / NB2;
-                int64_t gi = gidx(a), tt = t0 + t;
-                if (gi < r && tt < len) base[gi * vs + tt * es] = Ts[a * LDP + t];
+        }
+    };
+    auto gstore = [&](T* base, int64_t vs, int64_t es, bool rows, bool vec, int64_t t0,
+                      int64_t len) {
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+            const int e = tid + 256 * v;
+            if (!rows) {
+                const int a = e / (TC / VW), tt = (e % (TC / VW)) * VW;
+                const int64_t gi = gidx(a), t = t0 + tt;
+                if (gi >= r) continue;
+                T* dst = base + gi * vs + t;
+                const T* src = Ts2 + a * LDP + tt;
+                if (vec && t + VW <= len) {
+                    if constexpr (sizeof(T) == 4)
+                        *reinterpret_cast<float4*>(dst) = make_float4(src[0], src[1], src[2], src[3]);
+                    else
+                        *reinterpret_cast<double2*>(dst) = make_double2(src[0], src[1]);
+                } else {
+#pragma unroll
+                    for (int j = 0; j < VW; ++j)
+                        if (t + j < len) dst[j] = src[j];
+                }
+            } else {
+                const int a4 = (e % (NB2 / VW)) * VW, tt = e / (NB2 / VW);
+                const int64_t gi = gidx(a4), t = t0 + tt;
+                if (t >= len) continue;
+                T* dst = base + gi + t * es;
+                T x[VW];
+#pragma unroll
+                for (int j = 0; j < VW; ++j) x[j] = Ts2[(a4 + j) * LDP + tt];
+                if (vec && gi + VW <= r) {
+                    if constexpr (sizeof(T) == 4)
+                        *reinterpret_cast<float4*>(dst) = make_float4(x[0], x[1], x[2], x[3]);
+                    else
+                        *reinterpret_cast<double2*>(dst) = make_double2(x[0], x[1]);
+                } else {
+#pragma unroll
+                    for (int j = 0; j < VW; ++j)
+                        if (gi + j < r) dst[j] = x[j];
+                }
             }
         }
     };
 
-    // ---------------- phase 1: Gram matrix H = V V^T of the pair (MFMA)
-    constexpr int TPW = NT * NT / 4;  // H tiles per wave
+    // ---------------- phase 1: Gram matrix H of the pair (MFMA), prefetched
+    constexpr int TPW = NT * NT / 4;
     AccT hacc[TPW];
 #pragma unroll
     for (int j = 0; j < TPW; ++j) hacc[j] = zero4<AccT>();
-
-    for (int64_t t0 = 0; t0 < L; t0 += TC) {
-        load_chunk(Ab, g.vs, g.es, t0, L);
+    const int64_t nch = (L + TC - 1) / TC;
+    gload(Ab, g.vs, g.es, ROWS, vec_a != 0, 0, L);
+    for (int64_t c = 0; c < nch; ++c) {
         __syncthreads();
-#pragma unroll
+        regs_to_lds(ROWS);
+        __syncthreads();
+        if (c + 1 < nch) gload(Ab, g.vs, g.es, ROWS, vec_a != 0, (c + 1) * TC, L);
+#pragma unroll 4
         for (int kk = 0; kk < TC; kk += 4) {
 #pragma unroll
             for (int j = 0; j < TPW; ++j) {
                 const int q = wave * TPW + j, tr = q / NT, tc = q % NT;
-                T a = Ts[(tr * 16 + lr) * LDP + kk + lg];
-                T b = Ts[(tc * 16 + lr) * LDP + kk + lg];
+                const T a = Ts[(tr * 16 + lr) * LDP + kk + lg];
+                const T b = Ts[(tc * 16 + lr) * LDP + kk + lg];
                 hacc[j] = mfma(a, b, hacc[j]);
             }
         }
-        __syncthreads();
     }
+    __syncthreads();
 #pragma unroll
     for (int j = 0; j < TPW; ++j) {
         const int q = wave * TPW + j, tr = q / NT, tc = q % NT;
@@ -209,43 +289,61 @@ __global__ __launch_bounds__(256) void jacobi_round(T* __restrict__ A, T* __rest
     if (tid == 0) flag_nf = 0;
     __syncthreads();
 
-    // ---------------- convergence measure (FP64): max |cos| over valid pairs
-    double mc = 0.0;
+    // ---------------- convergence measure (FP64): max |cos| over valid pairs,
+    // separately for pairs inside one block and pairs across the two blocks
+    double mcx = 0.0, mcw = 0.0;
     for (int e = tid; e < NB2 * NB2; e += 256) {
-        int a = e / NB2, c = e % NB2;
-        double h = Hs[a * HP + c];
+        const int a = e / NB2, c = e % NB2;
+        const double h = Hs[a * HP + c];
         if (!isfinite(h)) flag_nf = 1;
         if (a < c && gidx(a) < r && gidx(c) < r) {
-            double d = fabs(Hs[a * HP + a]) * fabs(Hs[c * HP + c]);
-            if (d > 0.0) mc = fmax(mc, fabs(h) / sqrt(d));
+            const double d = fabs(Hs[a * HP + a]) * fabs(Hs[c * HP + c]);
+            if (d > 0.0) {
+                const double cs = fabs(h) / sqrt(d);
+                if ((a < B) != (c < B)) mcx = fmax(mcx, cs);
+                else mcw = fmax(mcw, cs);
+            }
         }
     }
-    for (int off = 32; off > 0; off >>= 1) mc = fmax(mc, __shfl_xor(mc, off));
-    if (lane == 0) red[wave] = mc;
+    for (int off = 32; off > 0; off >>= 1) {
+        mcx = fmax(mcx, __shfl_xor(mcx, off));
+        mcw = fmax(mcw, __shfl_xor(mcw, off));
+    }
+    if (lane == 0) { red[wave] = mcx; redw[wave] = mcw; }
     __syncthreads();
-    mc = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
+    mcx = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
+    mcw = fmax(fmax(redw[0], redw[1]), fmax(redw[2], redw[3]));
+    const double mc = fmax(mcx, mcw);
     const bool nonfinite = flag_nf != 0;
     const bool rotate = !nonfinite && (mc > tol);
+    // Both blocks already orthogonal inside: a sweep over the b*b cross pairs
+    // (b steps of b disjoint rotations) replaces the full 2b-1 step sweep.
+    const bool cross_only = !(mcw > tol);
     if (tid == 0) {
-        if (nonfinite) {
-            atomicExch(&ctl[s].nonfinite, 1);
-        } else {
-            atomicMax(&ctl[s].maxcos_bits, (unsigned long long)__double_as_longlong(mc));
-        }
+        if (nonfinite) atomicExch(&ctl[s].nonfinite, 1);
+        else atomicMax(&ctl[s].maxcos_bits, (unsigned long long)__double_as_longlong(mc));
         atomicAdd(&pair_counts[rotate ? 1 : 0], 1ull);
     }
     if (!rotate) return;  // uniform across the block
 
-    // ---------------- phase 2: one cyclic Jacobi sweep on H, accumulate Q
+    // prefetch the first update chunk; its latency hides behind phase 2
+    gload(Ab, g.vs, g.es, ROWS, vec_a != 0, 0, L);
+
+    // ---------------- phase 2: one cyclic Jacobi sweep on H (FP64 angles)
     for (int e = tid; e < NB2 * NB2; e += 256) {
-        int a = e / NB2, c = e % NB2;
-        Qs[a * HP + c] = (a == c) ? 1.0 : 0.0;
+        const int a = e / NB2, c = e % NB2;
+        Qs[a * HP + c] = (a == c) ? T(1) : T(0);
     }
-    __syncthreads();
-    for (int step = 0; step < NB2 - 1; ++step) {
-        if (tid < NB2 / 2) {
-            const int p = circle_player(tid, step, NB2);
-            const int q = circle_player(NB2 - 1 - tid, step, NB2);
+    constexpr int NPH = NB2 / 2;                       // rotations per step
+    constexpr int HB = (NPH * NPH + 255) / 256;        // 2x2 H blocks per thread
+    constexpr int QI = (NB2 * NPH + 255) / 256;        // Q items per thread
+    const int nsteps = cross_only ? B : NB2 - 1;
+    for (int step = 0; step < nsteps; ++step) {
+        if (tid < NPH) {
+            // full sweep: circle tournament over all NB2 vectors; cross sweep:
+            // vector i of the first block meets vector (i + step) mod b of the second
+            const int p = cross_only ? tid : circle_player(tid, step, NB2);
+            const int q = cross_only ? B + (tid + step) % B : circle_player(NB2 - 1 - tid, step, NB2);
             double c = 1.0, sn = 0.0;
             if (gidx(p) < r && gidx(q) < r) {
                 const double app = Hs[p * HP + p], aqq = Hs[q * HP + q], apq = Hs[p * HP + q];
@@ -261,76 +359,101 @@ __global__ __launch_bounds__(256) void jacobi_round(T* __restrict__ A, T* __rest
             rot_c[tid] = c; rot_s[tid] = sn; rot_p[tid] = p; rot_q[tid] = q;
         }
         __syncthreads();
-        // columns:  H <- H J,  Q <- Q J
-        for (int e = tid; e < NB2 * (NB2 / 2); e += 256) {
-            const int kk = e % (NB2 / 2), i = e / (NB2 / 2);
-            const double c = rot_c[kk], sn = rot_s[kk];
-            if (sn == 0.0) continue;
-            const int p = rot_p[kk], q = rot_q[kk];
-            double hp = Hs[i * HP + p], hq = Hs[i * HP + q];
-            Hs[i * HP + p] = c * hp - sn * hq;
-            Hs[i * HP + q] = sn * hp + c * hq;
-            double qp = Qs[i * HP + p], qq = Qs[i * HP + q];
-            Qs[i * HP + p] = c * qp - sn * qq;
-            Qs[i * HP + q] = sn * qp + c * qq;
+        // H <- J^T H J, one disjoint 2x2 block per (k1, k2): loads first, then math
+        double hv[HB][4];
+        int hp1[HB], hq1[HB], hp2[HB], hq2[HB];
+        double c1[HB], s1[HB], c2[HB], s2_[HB];
+#pragma unroll
+        for (int b = 0; b < HB; ++b) {
+            const int blk = tid + 256 * b;
+            if (blk < NPH * NPH) {
+                const int k1 = blk / NPH, k2 = blk % NPH;
+                hp1[b] = rot_p[k1]; hq1[b] = rot_q[k1]; hp2[b] = rot_p[k2]; hq2[b] = rot_q[k2];
+                c1[b] = rot_c[k1]; s1[b] = rot_s[k1]; c2[b] = rot_c[k2]; s2_[b] = rot_s[k2];
+                hv[b][0] = Hs[hp1[b] * HP + hp2[b]];
+                hv[b][1] = Hs[hp1[b] * HP + hq2[b]];
+                hv[b][2] = Hs[hq1[b] * HP + hp2[b]];
+                hv[b][3] = Hs[hq1[b] * HP + hq2[b]];
+            }
         }
-        __syncthreads();
-        // rows:  H <- J^T H
-        for (int e = tid; e < NB2 * (NB2 / 2); e += 256) {
-            const int kk = e % (NB2 / 2), j = e / (NB2 / 2);
-            const double c = rot_c[kk], sn = rot_s[kk];
-            if (sn == 0.0) continue;
-            const int p = rot_p[kk], q = rot_q[kk];
-            double hp = Hs[p * HP + j], hq = Hs[q * HP + j];
-            Hs[p * HP + j] = c * hp - sn * hq;
-            Hs[q * HP + j] = sn * hp + c * hq;
+        // Q <- Q J (column pairs), in place: loads first
+        T qv[QI][2];
+        int qi_[QI], qp_[QI], qq_[QI];
+        T qc[QI], qs[QI];
+#pragma unroll
+        for (int b = 0; b < QI; ++b) {
+            const int it = tid + 256 * b;
+            if (it < NB2 * NPH) {
+                const int kk = it % NPH, i = it / NPH;
+                qi_[b] = i; qp_[b] = rot_p[kk]; qq_[b] = rot_q[kk];
+                qc[b] = (T)rot_c[kk]; qs[b] = (T)rot_s[kk];
+                qv[b][0] = Qs[i * HP + qp_[b]];
+                qv[b][1] = Qs[i * HP + qq_[b]];
+            }
+        }
+#pragma unroll
+        for (int b = 0; b < HB; ++b) {
+            const int blk = tid + 256 * b;
+            if (blk < NPH * NPH) {
+                const double t0 = c2[b] * hv[b][0] - s2_[b] * hv[b][1];
+                const double t1 = s2_[b] * hv[b][0] + c2[b] * hv[b][1];
+                const double t2 = c2[b] * hv[b][2] - s2_[b] * hv[b][3];
+                const double t3 = s2_[b] * hv[b][2] + c2[b] * hv[b][3];
+                Hs[hp1[b] * HP + hp2[b]] = c1[b] * t0 - s1[b] * t2;
+                Hs[hp1[b] * HP + hq2[b]] = c1[b] * t1 - s1[b] * t3;
+                Hs[hq1[b] * HP + hp2[b]] = s1[b] * t0 + c1[b] * t2;
+                Hs[hq1[b] * HP + hq2[b]] = s1[b] * t1 + c1[b] * t3;
+            }
+        }
+#pragma unroll
+        for (int b = 0; b < QI; ++b) {
+            const int it = tid + 256 * b;
+            if (it < NB2 * NPH) {
+                Qs[qi_[b] * HP + qp_[b]] = qc[b] * qv[b][0] - qs[b] * qv[b][1];
+                Qs[qi_[b] * HP + qq_[b]] = qs[b] * qv[b][0] + qc[b] * qv[b][1];
+            }
         }
         __syncthreads();
     }
 
-    // ---------------- phase 3: vectors <- Q^T vectors, W <- W Q (MFMA)
-    if constexpr (sizeof(T) == 4) {
-        for (int e = tid; e < NB2 * NB2; e += 256) {
-            int a = e / NB2, c = e % NB2;
-            Qf[a * HP + c] = static_cast<T>(Qs[a * HP + c]);
-        }
-    }
-    __syncthreads();
-    const T* Qop = (sizeof(T) == 4) ? Qf : reinterpret_cast<const T*>(Qs);
-
-    constexpr int UPW = NT;  // output tiles per wave: NT a-tiles x 4 t-tiles / 4 waves
+    // ---------------- phase 3: vectors <- Q^T vectors, W <- W Q (MFMA), prefetched
+    constexpr int UPW = NT * (TC / 16) / 4;  // output tiles per wave
     for (int part = 0; part < 2; ++part) {
         T* base = part == 0 ? Ab : Wb;
         const int64_t vs = part == 0 ? g.vs : r;
         const int64_t es = part == 0 ? g.es : 1;
         const int64_t len = part == 0 ? L : r;
-        for (int64_t t0 = 0; t0 < len; t0 += TC) {
-            load_chunk(base, vs, es, t0, len);
+        const bool rows = part == 0 ? ROWS : false;
+        const bool vec = part == 0 ? vec_a != 0 : vec_w != 0;
+        const int64_t nc = (len + TC - 1) / TC;
+        if (part == 1) gload(Wb, r, 1, false, vec_w != 0, 0, r);
+        for (int64_t c = 0; c < nc; ++c) {
             __syncthreads();
+            regs_to_lds(rows);
+            __syncthreads();
+            if (c + 1 < nc) gload(base, vs, es, rows, vec, (c + 1) * TC, len);
             AccT uacc[UPW];
 #pragma unroll
             for (int j = 0; j < UPW; ++j) uacc[j] = zero4<AccT>();
-#pragma unroll
+#pragma unroll 4
             for (int kk = 0; kk < NB2; kk += 4) {
 #pragma unroll
                 for (int j = 0; j < UPW; ++j) {
-                    const int q = wave * UPW + j, ta = q / 4, tt = q % 4;
-                    T a = Qop[(kk + lg) * HP + ta * 16 + lr];   // Q[c][a]
-                    T b = Ts[(kk + lg) * LDP + tt * 16 + lr];   // old[c][t]
+                    const int q = wave * UPW + j, ta = q / (TC / 16), tt = q % (TC / 16);
+                    const T a = Qs[(kk + lg) * HP + ta * 16 + lr];   // Q[c][a]
+                    const T b = Ts[(kk + lg) * LDP + tt * 16 + lr];  // old[c][t]
                     uacc[j] = mfma(a, b, uacc[j]);
                 }
             }
-            __syncthreads();
 #pragma unroll
             for (int j = 0; j < UPW; ++j) {
-                const int q = wave * UPW + j, ta = q / 4, tt = q % 4;
+                const int q = wave * UPW + j, ta = q / (TC / 16), tt = q % (TC / 16);
 #pragma unroll
                 for (int v = 0; v < 4; ++v)
-                    Ts[(ta * 16 + mfma_row<T>(lg, v)) * LDP + tt * 16 + lr] = uacc[j][v];
+                    Ts2[(ta * 16 + mfma_row<T>(lg, v)) * LDP + tt * 16 + lr] = uacc[j][v];
             }
             __syncthreads();
-            store_chunk(base, vs, es, t0, len);
-            __syncthreads();
+            gstore(base, vs, es, rows, vec, c * TC, len);
         }
     }
 }
@@ -423,6 +546,11 @@ int jacobi_impl(T* A, int64_t m, int64_t p, int64_t n, T* W, double* s2, int32_t
     const int nbe = nb + (nb & 1);
     const int npairs = nbe / 2;
     const int64_t blocks = n * npairs;
+    constexpr int VW = 16 / (int)sizeof(T);
+    // 16-byte accesses need every vector (columns) / every row stride (rows)
+    // to start on a multiple of VW elements
+    const int vec_a = (g.m % VW == 0) ? 1 : 0;
+    const int vec_w = (g.r % VW == 0) ? 1 : 0;
     TSVDM_REQUIRE(blocks < ((int64_t)1 << 31), TSVDM_E_SHAPE, "too many slice pairs for one launch");
     int64_t launches = 0;
     for (int sweep = 0; sweep < o.max_sweeps; ++sweep) {
@@ -435,8 +563,12 @@ int jacobi_impl(T* A, int64_t m, int64_t p, int64_t n, T* W, double* s2, int32_t
             TSVDM_HIP_CHECK(hipEventRecord(e0, st));
         }
         for (int rnd = 0; rnd < nbe - 1; ++rnd) {
-            jacobi_round<T, NB2><<<(unsigned)blocks, 256, 0, st>>>(A, W, g, nbe, rnd, ctl, o.tol,
-                                                                   pair_counts);
+            if (g.rows)
+                jacobi_round<T, NB2, true><<<(unsigned)blocks, 256, 0, st>>>(
+                    A, W, g, nbe, rnd, ctl, o.tol, vec_a, vec_w, pair_counts);
+            else
+                jacobi_round<T, NB2, false><<<(unsigned)blocks, 256, 0, st>>>(
+                    A, W, g, nbe, rnd, ctl, o.tol, vec_a, vec_w, pair_counts);
             TSVDM_LAUNCH_CHECK();
             ++launches;
         }
@@ -451,7 +583,7 @@ int jacobi_impl(T* A, int64_t m, int64_t p, int64_t n, T* W, double* s2, int32_t
             if (left == 0) break;
         }
     }
-    if (g.es == 1) {
+    if (!g.rows) {
         const int64_t tv = g.r * n;
         jacobi_norms_cols<T><<<(unsigned)((tv + 3) / 4), 256, 0, st>>>(A, g, tv, s2);
     } else {
