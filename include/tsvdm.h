@@ -242,6 +242,62 @@ int tsvdm_backward(const void* A, int dtype, int64_t m, int64_t p, int64_t n,
                    void* ws, size_t ws_bytes, void* stream);
 
 /* --------------------------------------------------------------------- */
+/* batches of independent tensors of any shapes                          */
+/* --------------------------------------------------------------------- */
+
+/* One tensor of a batch: t-SVDM-I (mode 1, rank k) or t-SVDM-II (mode 2,
+ * tolerance eps) end to end.  All pointers are device pointers owned by the
+ * caller; outputs use the layouts of tsvdm_pack / tsvdm_reconstruct and are
+ * written in the batch's compute dtype (A_rec, U_pk, G_pk, S_pk). */
+typedef struct {
+    int64_t m, p, n;
+    const void* A;        /* input tensor, in_dtype, column-major              */
+    const double* M;      /* n x n FP64 column-major, a multiple of orthogonal  */
+    double inv_scale;     /* back-transform scale 1/c^2 (1 for orthonormal M)   */
+    int32_t mode;         /* 1 = t-SVDM-I, 2 = t-SVDM-II                        */
+    int32_t reserved;     /* must be 0                                          */
+    int64_t k;            /* mode 1 rank (>= 1, clamped to r)                   */
+    double eps;           /* mode 2 tolerance, in (0, 1)                        */
+    int32_t* rho;         /* out: int32[n] ranks                                */
+    int64_t* offsets;     /* out: int64[n+1] packed offsets                     */
+    double* stats;        /* out: FP64[4] (tau, discarded, total, J) or NULL    */
+    void* U_pk;           /* out: packed factors; NULL = kept in the workspace  */
+    void* G_pk;
+    void* S_pk;
+    int64_t capacity;     /* triplets U_pk/G_pk/S_pk hold (ignored when NULL)   */
+    void* A_rec;          /* out: reconstruction m*p*n, or NULL to skip it      */
+    double* err;          /* out: FP64[2] {sum (A-A_rec)^2, sum A^2} or NULL    */
+} tsvdm_batch_item;
+
+typedef struct tsvdm_batch_plan_s* tsvdm_batch_plan;
+
+/* Build a plan for `count` items: validates every item, lays out the
+ * workspace (returned in *ws_bytes) and the per-stage task tables (transform
+ * tiles, Jacobi (slice, block-pair) tasks, per-tensor selection, per-slice
+ * packing, reconstruction tiles), which the plan keeps in device memory it
+ * owns.  in_dtype: F32 or F64 input; dtype: F64 or F32 Jacobi / factor /
+ * output type; ttm_compute as in tsvdm_transform; block as in
+ * tsvdm_slice_svd (one width for the whole batch, 0 = default);
+ * max_sweeps 0 = 40.  Host errors return before anything is launched. */
+int tsvdm_batch_plan_create(const tsvdm_batch_item* items, int32_t count, int in_dtype,
+                            int dtype, int ttm_compute, int block, int max_sweeps,
+                            tsvdm_batch_plan* plan, size_t* ws_bytes);
+
+/* Run the whole batch on `stream`: one launch per stage covers every tensor
+ * (the Jacobi stage launches once per step of a global round counter; each
+ * slice follows its own tournament).  host_poll = 1 reads a device counter
+ * every 4 rounds and stops when all slices converged; host_poll = 0 runs the
+ * fixed number of steps (kernels of converged slices return at once).
+ * use_graph = 1 captures the run (host_poll forced to 0) into a hipGraph on
+ * the first call for this (workspace, stream) and replays it afterwards.
+ * status (device int32[1]): TSVDM_OK or the first device-side condition. */
+int tsvdm_batch_run(tsvdm_batch_plan plan, void* ws, size_t ws_bytes, int host_poll,
+                    int use_graph, int32_t* status, void* stream);
+
+/* Release the plan, its device tables and any captured graph. */
+int tsvdm_batch_plan_destroy(tsvdm_batch_plan plan);
+
+/* --------------------------------------------------------------------- */
 /* kernel statistics (for roofline reporting)                            */
 /* --------------------------------------------------------------------- */
 

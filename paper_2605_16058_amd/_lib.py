@@ -44,10 +44,25 @@ _SIGS = {
     "tsvdm_backward_workspace_size": (c_int, [c_int64, c_int64, c_int64, c_int, POINTER(c_size_t)]),
     "tsvdm_backward": (c_int, [_P, c_int, c_int64, c_int64, c_int64, _P, c_int64, c_double, _P, _P,
                                _P, _P, _P, c_size_t, _P]),
+    "tsvdm_batch_plan_create": (c_int, [_P, c_int32, c_int, c_int, c_int, c_int, c_int, _P, _P]),
+    "tsvdm_batch_run": (c_int, [_P, _P, c_size_t, c_int, c_int, _P, _P]),
+    "tsvdm_batch_plan_destroy": (c_int, [_P]),
     "tsvdm_stats_enable": (c_int, [c_int]),
     "tsvdm_stats_reset": (c_int, []),
     "tsvdm_stats_get": (c_int, [_P, _P, _P, _P, _P]),
 }
+
+
+class BatchItem(ctypes.Structure):
+    """tsvdm_batch_item of include/tsvdm.h."""
+    _fields_ = [
+        ("m", c_int64), ("p", c_int64), ("n", c_int64),
+        ("A", c_void_p), ("M", c_void_p), ("inv_scale", c_double),
+        ("mode", c_int32), ("reserved", c_int32), ("k", c_int64), ("eps", c_double),
+        ("rho", c_void_p), ("offsets", c_void_p), ("stats", c_void_p),
+        ("U_pk", c_void_p), ("G_pk", c_void_p), ("S_pk", c_void_p), ("capacity", c_int64),
+        ("A_rec", c_void_p), ("err", c_void_p),
+    ]
 
 
 class TsvdmError(RuntimeError):

@@ -22,7 +22,7 @@ LIB = os.path.join(HERE, "libtsvdm.so")
 ROOT = os.path.dirname(HERE)
 
 SOURCES = ["api.cpp", "ttm.hip", "jacobi.hip", "select.hip", "pack.hip", "reduce.hip",
-           "backward.hip"]
+           "backward.hip", "batch.cpp"]
 
 ARCH = "gfx950"
 FLAGS = [

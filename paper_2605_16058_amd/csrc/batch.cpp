@@ -1,0 +1,439 @@
+// Batches of independent tensors of any shapes through the whole hot path.
+//
+// A plan turns the items into per-stage task tables that live in device
+// memory owned by the plan, so every stage is one launch over all tensors:
+// transform tiles, Jacobi (slice, block pair) tasks driven by one global round
+// counter (each slice follows its own tournament of nb_s - 1 rounds per
+// sweep), per-tensor rank selection, per-slice packing, reconstruction tiles,
+// back-transform tiles and per-tensor error sums.  Descriptor tables hold
+// workspace addresses, so they are rebuilt when the workspace moves.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "common.h"
+#include "kernels.h"
+
+using namespace tsvdm;
+
+struct tsvdm_batch_plan_s {
+    std::vector<tsvdm_batch_item> items;
+    int in_dt = TSVDM_F32, dt = TSVDM_F32, ttm_compute = TSVDM_F32;
+    int nb2 = 32, max_sweeps = 40, max_steps = 0;
+    // workspace layout (byte offsets)
+    std::vector<size_t> off_ahat, off_w, off_s2, off_tf, off_tb, off_keys, off_stats, off_part,
+        off_upk, off_gpk, off_spk;
+    std::vector<int64_t> cap;  // effective capacity per item
+    size_t off_ctl = 0, ws_total = 0;
+    int64_t nslices = 0;
+    // host tables (addresses filled per workspace)
+    std::vector<int4> ttm_tasks, lr_tasks;
+    std::vector<int2> jtasks;
+    // device tables
+    char* dtab = nullptr;
+    size_t dtab_bytes = 0;
+    size_t o_fwd = 0, o_back = 0, o_ttm = 0, o_bt = 0, o_sl = 0, o_jt = 0, o_ps = 0, o_lr = 0,
+           o_sel = 0, o_err = 0;
+    int64_t n_back_tasks = 0;
+    int n_err = 0;
+    void* tables_ws = nullptr;
+    // captured graph
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t gexec = nullptr;
+    void* graph_ws = nullptr;
+    hipStream_t graph_stream = nullptr;
+    int32_t* graph_status = nullptr;
+};
+
+namespace {
+
+size_t esz(int dt) { return dt == TSVDM_F64 ? 8 : 4; }
+
+int validate_item(const tsvdm_batch_item& it, int idx) {
+    const std::string where = "batch item " + std::to_string(idx) + ": ";
+    if (!(it.m > 0 && it.p > 0 && it.n > 0 && it.m < (1 << 30) && it.p < (1 << 30) && it.n < 65536)) {
+        set_error(where + "m, p, n must be positive (n < 65536)");
+        return TSVDM_E_SHAPE;
+    }
+    if (std::min(it.m, it.p) > 4096) {
+        set_error(where + "min(m, p) must be <= 4096");
+        return TSVDM_E_SHAPE;
+    }
+    if (!it.A || !it.M || !it.rho || !it.offsets) {
+        set_error(where + "A, M, rho and offsets must be non-NULL");
+        return TSVDM_E_ARG;
+    }
+    if (it.reserved != 0) {
+        set_error(where + "reserved must be 0");
+        return TSVDM_E_ARG;
+    }
+    if (it.mode == 1) {
+        if (it.k < 1) { set_error(where + "k must be >= 1"); return TSVDM_E_ARG; }
+    } else if (it.mode == 2) {
+        if (!(it.eps > 0.0 && it.eps < 1.0)) { set_error(where + "eps must lie in (0, 1)"); return TSVDM_E_ARG; }
+    } else {
+        set_error(where + "mode must be 1 or 2");
+        return TSVDM_E_ARG;
+    }
+    if (!std::isfinite(it.inv_scale)) { set_error(where + "inv_scale must be finite"); return TSVDM_E_ARG; }
+    if (it.U_pk && (!it.G_pk || !it.S_pk || it.capacity < 0)) {
+        set_error(where + "U_pk, G_pk, S_pk must be given together with capacity >= 0");
+        return TSVDM_E_ARG;
+    }
+    if (it.err && !it.A_rec) { set_error(where + "err needs A_rec"); return TSVDM_E_ARG; }
+    return TSVDM_OK;
+}
+
+// Fill the device tables for workspace base `ws`.
+int build_tables(tsvdm_batch_plan_s* P, char* ws) {
+    const int cnt = (int)P->items.size();
+    std::vector<TtmProblem> fwd(cnt), back;
+    std::vector<BatchSlice> sl;
+    std::vector<PackSlice> ps;
+    std::vector<SelTensor> sel(cnt);
+    std::vector<ErrJob> err;
+    std::vector<int4> back_tasks;
+    sl.reserve(P->nslices);
+    ps.reserve(P->nslices);
+    const size_t e = esz(P->dt);
+    const int VW = 16 / (int)e;
+    int64_t slice = 0;
+    for (int t = 0; t < cnt; ++t) {
+        const tsvdm_batch_item& it = P->items[t];
+        const SliceGeom g = slice_geom(it.m, it.p);
+        char* ahat = ws + P->off_ahat[t];
+        char* w = ws + P->off_w[t];
+        double* s2 = reinterpret_cast<double*>(ws + P->off_s2[t]);
+        fwd[t] = TtmProblem{it.A, ahat, it.M, ws + P->off_tf[t], it.m * it.p, (int)it.n, 0, 1.0};
+        void* upk = it.U_pk ? it.U_pk : ws + P->off_upk[t];
+        void* gpk = it.U_pk ? it.G_pk : ws + P->off_gpk[t];
+        void* spk = it.U_pk ? it.S_pk : ws + P->off_spk[t];
+        const int b = P->nb2 / 2;
+        const int nb = (int)((g.r + b - 1) / b);
+        const int nbe = nb + (nb & 1);
+        const double ueps = P->dt == TSVDM_F64 ? 1.1102230246251565e-16 : 5.9604644775390625e-08;
+        double tol = 8.0 * std::sqrt((double)std::max<int64_t>(g.L, 1)) * ueps;
+        tol = P->dt == TSVDM_F64 ? std::max(tol, 1e-14) : std::max(tol, 2e-6);
+        for (int64_t i = 0; i < it.n; ++i, ++slice) {
+            BatchSlice d;
+            d.A = ahat + (size_t)(i * it.m * it.p) * e;
+            d.W = w + (size_t)(i * g.r * g.r) * e;
+            d.s2 = s2 + i * g.r;
+            d.g = g;
+            d.nbe = nbe;
+            d.vec_a = (g.m % VW == 0) ? 1 : 0;
+            d.vec_w = (g.r % VW == 0) ? 1 : 0;
+            d.tensor = t;
+            d.tol = tol;
+            sl.push_back(d);
+            PackSlice q;
+            q.A = d.A;
+            q.W = d.W;
+            q.s2 = d.s2;
+            q.g = g;
+            q.rho = it.rho + i;
+            q.off = it.offsets + i;
+            q.U_pk = upk;
+            q.G_pk = gpk;
+            q.S_pk = spk;
+            q.capacity = P->cap[t];
+            q.C = d.A;  // the reconstruction overwrites A-hat, no longer needed
+            q.status = nullptr;
+            ps.push_back(q);
+        }
+        SelTensor s;
+        s.s2 = s2;
+        s.rho = it.rho;
+        s.offsets = it.offsets;
+        s.stats = it.stats ? it.stats : reinterpret_cast<double*>(ws + P->off_stats[t]);
+        s.keys = reinterpret_cast<unsigned long long*>(ws + P->off_keys[t]);
+        s.r = g.r;
+        s.n = it.n;
+        s.np2 = select_np2(g.r * it.n);
+        s.mode = it.mode;
+        s.pad = 0;
+        s.k = it.k;
+        s.eps = it.eps;
+        sel[t] = s;
+        if (it.A_rec) {
+            TtmProblem bk{ahat, it.A_rec, it.M, ws + P->off_tb[t], it.m * it.p, (int)it.n, 0,
+                          it.inv_scale};
+            const int bi = (int)back.size();
+            back.push_back(bk);
+            int64_t n_rt;
+            int n_ct;
+            ttm_tile_counts(it.m * it.p, it.n, &n_rt, &n_ct);
+            for (int64_t rt = 0; rt < n_rt; ++rt)
+                for (int ct = 0; ct < n_ct; ++ct) back_tasks.push_back(int4{bi, (int)rt, ct, 0});
+            if (it.err) {
+                ErrJob j;
+                j.A = it.A;
+                j.B = it.A_rec;
+                j.count = it.m * it.p * it.n;
+                j.out = it.err;
+                j.part = reinterpret_cast<double*>(ws + P->off_part[t]);
+                err.push_back(j);
+            }
+        }
+    }
+    P->n_back_tasks = (int64_t)back_tasks.size();
+    P->n_err = (int)err.size();
+    // pack the tables into one device allocation
+    size_t off = 0;
+    auto place = [&](size_t bytes) { off = align_up(off); size_t o = off; off += bytes; return o; };
+    P->o_fwd = place(sizeof(TtmProblem) * fwd.size());
+    P->o_back = place(sizeof(TtmProblem) * std::max<size_t>(back.size(), 1));
+    P->o_ttm = place(sizeof(int4) * P->ttm_tasks.size());
+    P->o_bt = place(sizeof(int4) * std::max<size_t>(back_tasks.size(), 1));
+    P->o_sl = place(sizeof(BatchSlice) * sl.size());
+    P->o_jt = place(sizeof(int2) * P->jtasks.size());
+    P->o_ps = place(sizeof(PackSlice) * ps.size());
+    P->o_lr = place(sizeof(int4) * std::max<size_t>(P->lr_tasks.size(), 1));
+    P->o_sel = place(sizeof(SelTensor) * sel.size());
+    P->o_err = place(sizeof(ErrJob) * std::max<size_t>(err.size(), 1));
+    const size_t total = align_up(off);
+    if (total > P->dtab_bytes) {
+        if (P->dtab) (void)hipFree(P->dtab);
+        P->dtab = nullptr;
+        TSVDM_HIP_CHECK(hipMalloc(reinterpret_cast<void**>(&P->dtab), total));
+        P->dtab_bytes = total;
+    }
+    std::vector<char> host(total, 0);
+    auto put = [&](size_t o, const void* src, size_t bytes) { if (bytes) memcpy(host.data() + o, src, bytes); };
+    put(P->o_fwd, fwd.data(), sizeof(TtmProblem) * fwd.size());
+    put(P->o_back, back.data(), sizeof(TtmProblem) * back.size());
+    put(P->o_ttm, P->ttm_tasks.data(), sizeof(int4) * P->ttm_tasks.size());
+    put(P->o_bt, back_tasks.data(), sizeof(int4) * back_tasks.size());
+    put(P->o_sl, sl.data(), sizeof(BatchSlice) * sl.size());
+    put(P->o_jt, P->jtasks.data(), sizeof(int2) * P->jtasks.size());
+    put(P->o_ps, ps.data(), sizeof(PackSlice) * ps.size());
+    put(P->o_lr, P->lr_tasks.data(), sizeof(int4) * P->lr_tasks.size());
+    put(P->o_sel, sel.data(), sizeof(SelTensor) * sel.size());
+    put(P->o_err, err.data(), sizeof(ErrJob) * err.size());
+    TSVDM_HIP_CHECK(hipMemcpy(P->dtab, host.data(), total, hipMemcpyHostToDevice));
+    P->tables_ws = ws;
+    return TSVDM_OK;
+}
+
+// The status word of each PackSlice is set per run (it is the caller's).
+__global__ void set_pack_status(PackSlice* ps, int64_t n, int32_t* status) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) ps[i].status = status;
+}
+
+__global__ void merge_status(int32_t* status, const int32_t* jacobi_status) {
+    if (threadIdx.x == 0 && blockIdx.x == 0 && *status == TSVDM_OK) *status = *jacobi_status;
+}
+
+// a fill kernel rather than a memset, so that graph replays stay exact
+__global__ void clear_status(int32_t* status) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) *status = TSVDM_OK;
+}
+
+int run_stages(tsvdm_batch_plan_s* P, char* ws, int host_poll, int32_t* status, hipStream_t st) {
+    char* D = P->dtab;
+    const int cnt = (int)P->items.size();
+    int rc;
+    int32_t* jstatus = reinterpret_cast<int32_t*>(ws + P->off_ctl);
+    void* ctl_ws = ws + P->off_ctl + 256;
+    clear_status<<<1, 64, 0, st>>>(status);
+    TSVDM_LAUNCH_CHECK();
+    // 1. transform
+    rc = run_ttm_batch(reinterpret_cast<const TtmProblem*>(D + P->o_fwd), cnt,
+                       reinterpret_cast<const int4*>(D + P->o_ttm), (int64_t)P->ttm_tasks.size(),
+                       P->in_dt, P->dt, P->ttm_compute, 0, st);
+    if (rc) return rc;
+    // 2. slice SVDs
+    rc = run_jacobi_batch(P->dt, P->nb2, reinterpret_cast<const BatchSlice*>(D + P->o_sl),
+                          P->nslices, reinterpret_cast<const int2*>(D + P->o_jt),
+                          (int64_t)P->jtasks.size(), P->max_steps, host_poll, ctl_ws, jstatus, st);
+    if (rc) return rc;
+    // 3. ranks
+    rc = run_select_batch(reinterpret_cast<const SelTensor*>(D + P->o_sel), cnt, st);
+    if (rc) return rc;
+    // 4. factors (the caller's status word collects capacity overflows)
+    set_pack_status<<<(unsigned)((P->nslices + 255) / 256), 256, 0, st>>>(
+        reinterpret_cast<PackSlice*>(D + P->o_ps), P->nslices, status);
+    TSVDM_LAUNCH_CHECK();
+    rc = run_pack_batch(P->dt, reinterpret_cast<const PackSlice*>(D + P->o_ps), P->nslices, st);
+    if (rc) return rc;
+    // 5. reconstruction and back-transform
+    if (!P->lr_tasks.empty()) {
+        rc = run_lowrank_batch(P->dt, reinterpret_cast<const PackSlice*>(D + P->o_ps),
+                               reinterpret_cast<const int4*>(D + P->o_lr),
+                               (int64_t)P->lr_tasks.size(), st);
+        if (rc) return rc;
+        int nback = 0;
+        for (const auto& it : P->items) nback += it.A_rec ? 1 : 0;
+        rc = run_ttm_batch(reinterpret_cast<const TtmProblem*>(D + P->o_back), nback,
+                           reinterpret_cast<const int4*>(D + P->o_bt), P->n_back_tasks, P->dt,
+                           P->dt, P->ttm_compute, 1, st);
+        if (rc) return rc;
+    }
+    // 6. error sums
+    if (P->n_err > 0) {
+        rc = run_error_batch(P->in_dt, P->dt, reinterpret_cast<const ErrJob*>(D + P->o_err),
+                             P->n_err, st);
+        if (rc) return rc;
+    }
+    merge_status<<<1, 64, 0, st>>>(status, jstatus);
+    TSVDM_LAUNCH_CHECK();
+    return TSVDM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int tsvdm_batch_plan_create(const tsvdm_batch_item* items, int32_t count, int in_dtype, int dtype,
+                            int ttm_compute, int block, int max_sweeps, tsvdm_batch_plan* plan,
+                            size_t* ws_bytes) {
+    clear_error();
+    TSVDM_REQUIRE(items && plan && ws_bytes, TSVDM_E_ARG, "items, plan and ws_bytes must be non-NULL");
+    TSVDM_REQUIRE(count >= 1 && count < 65536, TSVDM_E_SHAPE, "count must be in [1, 65535]");
+    TSVDM_REQUIRE(in_dtype == TSVDM_F64 || in_dtype == TSVDM_F32, TSVDM_E_UNSUPPORTED, "in_dtype must be F64 or F32");
+    TSVDM_REQUIRE(dtype == TSVDM_F64 || dtype == TSVDM_F32, TSVDM_E_UNSUPPORTED, "dtype must be F64 or F32");
+    TSVDM_REQUIRE(ttm_compute >= TSVDM_F64 && ttm_compute <= TSVDM_BF16X3, TSVDM_E_UNSUPPORTED, "unknown ttm_compute");
+    TSVDM_REQUIRE(!(ttm_compute >= TSVDM_BF16 && dtype != TSVDM_F32), TSVDM_E_UNSUPPORTED,
+                  "BF16 transforms need dtype F32");
+    TSVDM_REQUIRE(block == 0 || block == 16 || block == 32, TSVDM_E_ARG, "block must be 0, 16 or 32");
+    TSVDM_REQUIRE(max_sweeps >= 0 && max_sweeps <= 200, TSVDM_E_ARG, "max_sweeps must be in [0, 200]");
+    for (int t = 0; t < count; ++t) {
+        const int rc = validate_item(items[t], t);
+        if (rc) return rc;
+    }
+    tsvdm_batch_plan_s* P = new tsvdm_batch_plan_s();
+    P->items.assign(items, items + count);
+    P->in_dt = in_dtype;
+    P->dt = dtype;
+    P->ttm_compute = ttm_compute;
+    P->max_sweeps = max_sweeps ? max_sweeps : 40;
+    int64_t rmax = 0;
+    for (const auto& it : P->items) rmax = std::max(rmax, std::min(it.m, it.p));
+    P->nb2 = block ? 2 * block : (rmax >= 256 ? 64 : 32);
+    const size_t e = esz(dtype);
+    size_t wsoff = 0;
+    auto take = [&](size_t bytes) {
+        wsoff = align_up(wsoff);
+        const size_t o = wsoff;
+        wsoff += bytes;
+        return o;
+    };
+    int max_rounds = 1;
+    for (int t = 0; t < count; ++t) {
+        const tsvdm_batch_item& it = P->items[t];
+        const SliceGeom g = slice_geom(it.m, it.p);
+        P->off_ahat.push_back(take((size_t)(it.m * it.p * it.n) * e));
+        P->off_w.push_back(take((size_t)(g.r * g.r * it.n) * e));
+        P->off_s2.push_back(take((size_t)(g.r * it.n) * 8));
+        P->off_tf.push_back(take((size_t)(it.n * it.n) * 8));
+        P->off_tb.push_back(take((size_t)(it.n * it.n) * 8));
+        P->off_keys.push_back(take(it.mode == 2 ? (size_t)select_np2(g.r * it.n) * 8 : 8));
+        P->off_stats.push_back(take(32));
+        P->off_part.push_back(take(sizeof(double) * 2 * ERR_SEGS));
+        int64_t cap = it.capacity;
+        if (!it.U_pk) {
+            cap = (it.mode == 1 ? std::min<int64_t>(it.k, g.r) : g.r) * it.n;
+            P->off_upk.push_back(take((size_t)(it.m * cap) * e));
+            P->off_gpk.push_back(take((size_t)(it.p * cap) * e));
+            P->off_spk.push_back(take((size_t)cap * e));
+        } else {
+            P->off_upk.push_back(0);
+            P->off_gpk.push_back(0);
+            P->off_spk.push_back(0);
+        }
+        P->cap.push_back(cap);
+        const int b = P->nb2 / 2;
+        const int nb = (int)((g.r + b - 1) / b);
+        const int nbe = nb + (nb & 1);
+        max_rounds = std::max(max_rounds, nbe - 1);
+        // task tables
+        int64_t n_rt;
+        int n_ct;
+        ttm_tile_counts(it.m * it.p, it.n, &n_rt, &n_ct);
+        for (int64_t rt = 0; rt < n_rt; ++rt)
+            for (int ct = 0; ct < n_ct; ++ct) P->ttm_tasks.push_back(int4{t, (int)rt, ct, 0});
+        const int ta = (int)((it.m + 63) / 64), tb = (int)((it.p + 63) / 64);
+        for (int64_t i = 0; i < it.n; ++i) {
+            const int s = (int)(P->nslices + i);
+            for (int k = 0; k < nbe / 2; ++k) P->jtasks.push_back(int2{s, k});
+            if (it.A_rec)
+                for (int y = 0; y < tb; ++y)
+                    for (int x = 0; x < ta; ++x) P->lr_tasks.push_back(int4{s, x, y, 0});
+        }
+        P->nslices += it.n;
+    }
+    P->max_steps = P->max_sweeps * max_rounds;
+    if (P->max_steps > 100000) P->max_steps = 100000;
+    P->off_ctl = take(256 + jacobi_batch_ctl_bytes(P->nslices, P->max_steps));
+    P->ws_total = align_up(wsoff);
+    if ((int64_t)P->jtasks.size() >= ((int64_t)1 << 31) || (int64_t)P->ttm_tasks.size() >= ((int64_t)1 << 31) ||
+        (int64_t)P->lr_tasks.size() >= ((int64_t)1 << 31)) {
+        delete P;
+        set_error("batch too large for one launch per stage");
+        return TSVDM_E_SHAPE;
+    }
+    *plan = P;
+    *ws_bytes = P->ws_total;
+    return TSVDM_OK;
+}
+
+int tsvdm_batch_run(tsvdm_batch_plan P, void* ws, size_t ws_bytes, int host_poll, int use_graph,
+                    int32_t* status, void* stream) {
+    clear_error();
+    TSVDM_REQUIRE(P != nullptr, TSVDM_E_ARG, "plan is NULL");
+    TSVDM_REQUIRE(ws != nullptr && status != nullptr, TSVDM_E_ARG, "ws and status must be non-NULL");
+    TSVDM_REQUIRE(host_poll == 0 || host_poll == 1, TSVDM_E_ARG, "host_poll must be 0 or 1");
+    TSVDM_REQUIRE(use_graph == 0 || use_graph == 1, TSVDM_E_ARG, "use_graph must be 0 or 1");
+    if (ws_bytes < P->ws_total) {
+        set_error("workspace too small: " + std::to_string(ws_bytes) + " < " + std::to_string(P->ws_total));
+        return TSVDM_E_WORKSPACE;
+    }
+    hipStream_t st = as_stream(stream);
+    char* base = static_cast<char*>(ws);
+    if (P->tables_ws != ws) {
+        // tables embed workspace addresses; a captured graph of another
+        // workspace is stale
+        if (P->gexec) { (void)hipGraphExecDestroy(P->gexec); P->gexec = nullptr; }
+        if (P->graph) { (void)hipGraphDestroy(P->graph); P->graph = nullptr; }
+        const int rc = build_tables(P, base);
+        if (rc) return rc;
+    }
+    if (!use_graph) return run_stages(P, base, host_poll, status, st);
+    TSVDM_REQUIRE(st != nullptr, TSVDM_E_ARG, "graph capture needs a non-default stream");
+    TSVDM_REQUIRE(!stats_enabled(), TSVDM_E_ARG, "kernel statistics cannot be captured in a graph");
+    if (!P->gexec || P->graph_ws != ws || P->graph_stream != st || P->graph_status != status) {
+        if (P->gexec) { (void)hipGraphExecDestroy(P->gexec); P->gexec = nullptr; }
+        if (P->graph) { (void)hipGraphDestroy(P->graph); P->graph = nullptr; }
+        TSVDM_HIP_CHECK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+        const int rc = run_stages(P, base, 0, status, st);
+        hipGraph_t g = nullptr;
+        const hipError_t ec = hipStreamEndCapture(st, &g);
+        if (rc) { if (g) (void)hipGraphDestroy(g); return rc; }
+        if (ec != hipSuccess) {
+            set_error(std::string("graph capture failed: ") + hipGetErrorString(ec));
+            return TSVDM_E_HIP;
+        }
+        P->graph = g;
+        TSVDM_HIP_CHECK(hipGraphInstantiate(&P->gexec, g, nullptr, nullptr, 0));
+        P->graph_ws = ws;
+        P->graph_stream = st;
+        P->graph_status = status;
+    }
+    TSVDM_HIP_CHECK(hipGraphLaunch(P->gexec, st));
+    return TSVDM_OK;
+}
+
+int tsvdm_batch_plan_destroy(tsvdm_batch_plan P) {
+    clear_error();
+    if (!P) return TSVDM_OK;
+    if (P->gexec) (void)hipGraphExecDestroy(P->gexec);
+    if (P->graph) (void)hipGraphDestroy(P->graph);
+    if (P->dtab) (void)hipFree(P->dtab);
+    delete P;
+    return TSVDM_OK;
+}
+
+}  // extern "C"

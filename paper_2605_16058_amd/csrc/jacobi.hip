@@ -111,40 +111,47 @@ struct RoundCfg {
     static constexpr size_t total = r1 + q_bytes;
 };
 
-// One round of the block tournament for every (slice, pair).
+// One block pair (pair k of round rnd) of one slice: Ab / Wb are the slice
+// and its rotation accumulator, ctl_s its control word.
 //   ROWS: the Jacobi vectors are slice rows (m < p), else columns.
 //   vec_a / vec_w: 16-byte accesses are legal for the slice / for W.
+template <class T, int NB2>
+struct RoundShared {
+    __align__(16) char smem[RoundCfg<T, NB2>::total];
+    double rot_c[NB2 / 2], rot_s[NB2 / 2];
+    int rot_p[NB2 / 2], rot_q[NB2 / 2];
+    double red[4], redw[4];
+    int flag_nf;
+};
+
 template <class T, int NB2, bool ROWS>
-__global__ __launch_bounds__(256) void jacobi_round(T* __restrict__ A, T* __restrict__ W, SliceGeom g,
-                                                    int nbe, int rnd, JacobiCtl* __restrict__ ctl,
-                                                    double tol, int vec_a, int vec_w,
-                                                    unsigned long long* __restrict__ pair_counts) {
+__device__ __forceinline__ void round_body(RoundShared<T, NB2>& sh, T* __restrict__ Ab,
+                                           T* __restrict__ Wb, const SliceGeom& g, int nbe, int rnd,
+                                           int k, JacobiCtl* __restrict__ ctl_s, double tol,
+                                           int vec_a, int vec_w,
+                                           unsigned long long* __restrict__ pair_counts) {
     typedef RoundCfg<T, NB2> C;
     typedef typename Acc<T>::type AccT;
     constexpr int B = NB2 / 2, VW = C::VW, TC = C::TC, LDP = C::LDP, NV = C::NV;
     constexpr int NT = C::NT, HP = C::HP;
 
-    __shared__ __align__(16) char smem[C::total];
-    __shared__ double rot_c[NB2 / 2], rot_s[NB2 / 2];
-    __shared__ int rot_p[NB2 / 2], rot_q[NB2 / 2];
-    __shared__ double red[4], redw[4];
-    __shared__ int flag_nf;
+    char* smem = sh.smem;
+    double* rot_c = sh.rot_c;
+    double* rot_s = sh.rot_s;
+    int* rot_p = sh.rot_p;
+    int* rot_q = sh.rot_q;
+    double* red = sh.red;
+    double* redw = sh.redw;
+    int& flag_nf = sh.flag_nf;
 
     T* Ts = reinterpret_cast<T*>(smem);                           // [NB2][LDP] staged input
     T* Ts2 = reinterpret_cast<T*>(smem + C::ts_bytes);            // [NB2][LDP] staged output
     double* Hs = reinterpret_cast<double*>(smem);                 // [NB2][HP]  (phase 2 only)
     T* Qs = reinterpret_cast<T*>(smem + C::r1);                   // [NB2][HP]  Q[c][a]
 
-    const int npairs = nbe / 2;
-    const int64_t s = blockIdx.x / npairs;
-    const int k = blockIdx.x % npairs;
-    if (ctl[s].done) return;
-
     const int I = circle_player(k, rnd, nbe);
     const int J = circle_player(nbe - 1 - k, rnd, nbe);
     const int64_t r = g.r, L = g.L;
-    T* Ab = A + s * g.m * g.p;
-    T* Wb = W + s * r * r;
 
     const int tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6;
@@ -320,8 +327,8 @@ __global__ __launch_bounds__(256) void jacobi_round(T* __restrict__ A, T* __rest
     // (b steps of b disjoint rotations) replaces the full 2b-1 step sweep.
     const bool cross_only = !(mcw > tol);
     if (tid == 0) {
-        if (nonfinite) atomicExch(&ctl[s].nonfinite, 1);
-        else atomicMax(&ctl[s].maxcos_bits, (unsigned long long)__double_as_longlong(mc));
+        if (nonfinite) atomicExch(&ctl_s->nonfinite, 1);
+        else atomicMax(&ctl_s->maxcos_bits, (unsigned long long)__double_as_longlong(mc));
         atomicAdd(&pair_counts[rotate ? 1 : 0], 1ull);
     }
     if (!rotate) return;  // uniform across the block
@@ -454,6 +461,118 @@ __global__ __launch_bounds__(256) void jacobi_round(T* __restrict__ A, T* __rest
             }
             __syncthreads();
             gstore(base, vs, es, rows, vec, c * TC, len);
+        }
+    }
+}
+
+// One round for every (slice, pair) of a tensor of identical slices.
+template <class T, int NB2, bool ROWS>
+__global__ __launch_bounds__(256) void jacobi_round(T* __restrict__ A, T* __restrict__ W, SliceGeom g,
+                                                    int nbe, int rnd, JacobiCtl* __restrict__ ctl,
+                                                    double tol, int vec_a, int vec_w,
+                                                    unsigned long long* __restrict__ pair_counts) {
+    __shared__ RoundShared<T, NB2> sh;
+    const int npairs = nbe / 2;
+    const int64_t s = blockIdx.x / npairs;
+    const int k = blockIdx.x % npairs;
+    if (ctl[s].done) return;
+    round_body<T, NB2, ROWS>(sh, A + s * g.m * g.p, W + s * g.r * g.r, g, nbe, rnd, k, ctl + s, tol,
+                             vec_a, vec_w, pair_counts);
+}
+
+// One step of the global round counter t for a batch of slices of any
+// shapes: task = (slice, pair); slice s is in round t mod (nbe_s - 1) of its
+// own tournament, so slices with fewer blocks simply run more sweeps.
+template <class T, int NB2>
+__global__ __launch_bounds__(256) void jacobi_round_batch(const BatchSlice* __restrict__ sl,
+                                                          const int2* __restrict__ tasks, int t,
+                                                          JacobiCtl* __restrict__ ctl,
+                                                          unsigned long long* __restrict__ pair_counts) {
+    __shared__ RoundShared<T, NB2> sh;
+    const int2 tk = tasks[blockIdx.x];
+    if (ctl[tk.x].done) return;
+    const BatchSlice d = sl[tk.x];
+    const int rnd = t % (d.nbe - 1);
+    if (d.g.rows)
+        round_body<T, NB2, true>(sh, static_cast<T*>(d.A), static_cast<T*>(d.W), d.g, d.nbe, rnd,
+                                 tk.y, ctl + tk.x, d.tol, d.vec_a, d.vec_w, pair_counts);
+    else
+        round_body<T, NB2, false>(sh, static_cast<T*>(d.A), static_cast<T*>(d.W), d.g, d.nbe, rnd,
+                                  tk.y, ctl + tk.x, d.tol, d.vec_a, d.vec_w, pair_counts);
+}
+
+// end of a sweep for the slices whose tournament finished a sweep at step t;
+// remaining counts the slices still running after step t
+__global__ void jacobi_sweep_end_batch(const BatchSlice* __restrict__ sl, int64_t nslices, int t,
+                                       JacobiCtl* __restrict__ ctl, int* __restrict__ remaining) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nslices) return;
+    const int nr = sl[i].nbe - 1;
+    JacobiCtl c = ctl[i];
+    if (c.done) return;
+    if (t % nr != nr - 1) {
+        atomicAdd(remaining, 1);
+        return;
+    }
+    c.sweeps += 1;
+    const double mc = __longlong_as_double((long long)c.maxcos_bits);
+    if (c.nonfinite || mc <= sl[i].tol) c.done = 1;
+    else atomicAdd(remaining, 1);
+    c.maxcos_bits = 0ull;
+    ctl[i] = c;
+}
+
+// W = I and a clean control word for every slice of a batch
+template <class T>
+__global__ void jacobi_init_batch(const BatchSlice* __restrict__ sl, JacobiCtl* __restrict__ ctl,
+                                  int* __restrict__ remaining, int max_steps,
+                                  unsigned long long* __restrict__ pair_counts,
+                                  int32_t* __restrict__ status) {
+    const BatchSlice d = sl[blockIdx.x];
+    const int64_t r = d.g.r;
+    T* W = static_cast<T*>(d.W);
+    for (int64_t e = threadIdx.x; e < r * r; e += blockDim.x) W[e] = (e % r == e / r) ? T(1) : T(0);
+    if (threadIdx.x == 0) {
+        JacobiCtl c;
+        c.maxcos_bits = 0ull; c.done = 0; c.sweeps = 0; c.nonfinite = 0; c.pad = 0;
+        ctl[blockIdx.x] = c;
+    }
+    if (blockIdx.x == 0) {
+        for (int i = threadIdx.x; i < max_steps; i += blockDim.x) remaining[i] = 0;
+        if (threadIdx.x == 0) {
+            *status = TSVDM_OK;
+            pair_counts[0] = 0ull;
+            pair_counts[1] = 0ull;
+        }
+    }
+}
+
+// squared norms of every slice's final vectors, one workgroup per slice
+template <class T>
+__global__ __launch_bounds__(256) void jacobi_norms_batch(const BatchSlice* __restrict__ sl) {
+    const BatchSlice d = sl[blockIdx.x];
+    const T* A = static_cast<const T*>(d.A);
+    const SliceGeom g = d.g;
+    if (g.rows) {
+        for (int64_t j = threadIdx.x; j < g.r; j += blockDim.x) {
+            double acc = 0.0;
+            for (int64_t t = 0; t < g.L; ++t) {
+                const double v = (double)A[j + t * g.es];
+                acc = fma(v, v, acc);
+            }
+            d.s2[j] = acc;
+        }
+    } else {
+        const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+        for (int64_t j = wave; j < g.r; j += 4) {
+            const T* x = A + j * g.vs;
+            double acc = 0.0;
+            for (int64_t t = lane; t < g.L; t += 64) {
+                const double e = (double)x[t];
+                acc = fma(e, e, acc);
+            }
+            for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
+            if (lane == 0) d.s2[j] = acc;
         }
     }
 }
@@ -609,7 +728,81 @@ int jacobi_impl(T* A, int64_t m, int64_t p, int64_t n, T* W, double* s2, int32_t
     return TSVDM_OK;
 }
 
+template <class T, int NB2>
+int jacobi_batch_impl(const BatchSlice* sl, int64_t nslices, const int2* tasks, int64_t ntasks,
+                      int max_steps, int host_poll, void* ctl_ws, int32_t* status, hipStream_t st) {
+    Carver cv(ctl_ws);
+    JacobiCtl* ctl = cv.carve<JacobiCtl>((size_t)nslices);
+    int* remaining = cv.carve<int>((size_t)max_steps);
+    unsigned long long* pair_counts = cv.carve<unsigned long long>(2);
+    TSVDM_REQUIRE(nslices < ((int64_t)1 << 31) && ntasks < ((int64_t)1 << 31), TSVDM_E_SHAPE,
+                  "batch too large for one launch");
+    jacobi_init_batch<T><<<(unsigned)nslices, 256, 0, st>>>(sl, ctl, remaining, max_steps,
+                                                           pair_counts, status);
+    TSVDM_LAUNCH_CHECK();
+    const bool stats = stats_enabled();
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (stats) {
+        TSVDM_HIP_CHECK(hipEventCreate(&e0));
+        TSVDM_HIP_CHECK(hipEventCreate(&e1));
+        TSVDM_HIP_CHECK(hipEventRecord(e0, st));
+    }
+    int64_t launches = 0;
+    const unsigned sblocks = (unsigned)((nslices + 255) / 256);
+    for (int t = 0; t < max_steps; ++t) {
+        jacobi_round_batch<T, NB2><<<(unsigned)ntasks, 256, 0, st>>>(sl, tasks, t, ctl, pair_counts);
+        TSVDM_LAUNCH_CHECK();
+        ++launches;
+        jacobi_sweep_end_batch<<<sblocks, 256, 0, st>>>(sl, nslices, t, ctl, remaining + t);
+        TSVDM_LAUNCH_CHECK();
+        // poll every 4 steps: one synchronisation per few rounds
+        if (host_poll && (t % 4 == 3)) {
+            int left = -1;
+            TSVDM_HIP_CHECK(hipMemcpyAsync(&left, remaining + t, sizeof(int), hipMemcpyDeviceToHost, st));
+            TSVDM_HIP_CHECK(hipStreamSynchronize(st));
+            if (left == 0) break;
+        }
+    }
+    if (stats) TSVDM_HIP_CHECK(hipEventRecord(e1, st));
+    jacobi_norms_batch<T><<<(unsigned)nslices, 256, 0, st>>>(sl);
+    TSVDM_LAUNCH_CHECK();
+    jacobi_finish<<<1, 256, 0, st>>>(ctl, nslices, status);
+    TSVDM_LAUNCH_CHECK();
+    if (stats) {
+        unsigned long long pc[2] = {0ull, 0ull};
+        TSVDM_HIP_CHECK(hipMemcpyAsync(pc, pair_counts, sizeof(pc), hipMemcpyDeviceToHost, st));
+        TSVDM_HIP_CHECK(hipStreamSynchronize(st));
+        float ms = 0.f;
+        TSVDM_HIP_CHECK(hipEventElapsedTime(&ms, e0, e1));
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        stats_add(launches, ms, (int64_t)pc[0], (int64_t)pc[1], NB2);
+    }
+    return TSVDM_OK;
+}
+
 }  // namespace
+
+size_t jacobi_batch_ctl_bytes(int64_t nslices, int max_steps) {
+    Carver cv(nullptr);
+    cv.carve<JacobiCtl>((size_t)nslices);
+    cv.carve<int>((size_t)max_steps);
+    cv.carve<unsigned long long>(2);
+    return cv.total();
+}
+
+int run_jacobi_batch(int dt, int nb2, const BatchSlice* sl, int64_t nslices, const int2* tasks,
+                     int64_t ntasks, int max_steps, int host_poll, void* ctl_ws, int32_t* status,
+                     hipStream_t st) {
+    if (dt == TSVDM_F64) {
+        if (nb2 == 32)
+            return jacobi_batch_impl<double, 32>(sl, nslices, tasks, ntasks, max_steps, host_poll, ctl_ws, status, st);
+        return jacobi_batch_impl<double, 64>(sl, nslices, tasks, ntasks, max_steps, host_poll, ctl_ws, status, st);
+    }
+    if (nb2 == 32)
+        return jacobi_batch_impl<float, 32>(sl, nslices, tasks, ntasks, max_steps, host_poll, ctl_ws, status, st);
+    return jacobi_batch_impl<float, 64>(sl, nslices, tasks, ntasks, max_steps, host_poll, ctl_ws, status, st);
+}
 
 size_t jacobi_workspace_bytes(int64_t n) {
     Carver cv(nullptr);

@@ -5,8 +5,83 @@
 
 namespace tsvdm {
 
+// ---- batch descriptors (device-resident tables built by the batch plan)
+struct TtmProblem {       // Y = X x_3 (scale * op(M)) for one tensor
+    const void* X;
+    void* Y;
+    const double* M;
+    void* Tt;             // n*n staging of scale*op(M) in the compute type
+    int64_t R;            // m*p
+    int n;
+    int pad;
+    double scale;
+};
+
+struct BatchSlice {       // one frontal slice for the batched Jacobi
+    void* A;              // slice base (m*p elements)
+    void* W;              // r*r rotation accumulator
+    double* s2;           // r squared singular values
+    SliceGeom g;
+    int nbe;              // block count padded to even
+    int vec_a, vec_w;
+    int tensor;
+    double tol;           // convergence threshold on |cos|
+};
+
+struct PackSlice {        // one slice for batched packing and reconstruction
+    const void* A;        // orthogonalised vectors (Jacobi output)
+    const void* W;        // rotation accumulator
+    const double* s2;     // r squared singular values
+    SliceGeom g;
+    const int32_t* rho;   // &rho[i] of its tensor
+    const int64_t* off;   // &offsets[i] of its tensor
+    void* U_pk;           // tensor-level packed outputs
+    void* G_pk;
+    void* S_pk;
+    int64_t capacity;
+    void* C;              // reconstruction target slice (m*p)
+    int32_t* status;
+};
+
+int run_pack_batch(int dt, const PackSlice* ps, int64_t nslices, hipStream_t st);
+int run_lowrank_batch(int dt, const PackSlice* ps, const int4* tasks, int64_t ntasks,
+                      hipStream_t st);
+
+struct SelTensor {        // one tensor's rank selection
+    const double* s2;     // r*n squared singular values (slice-major)
+    int32_t* rho;
+    int64_t* offsets;     // n+1
+    double* stats;        // 4 or NULL
+    unsigned long long* keys;  // np2 scratch (t-SVDM-II)
+    int64_t r, n, np2;
+    int mode;             // 1: fixed rank k, 2: tolerance eps
+    int pad;
+    int64_t k;
+    double eps;
+};
+int run_select_batch(const SelTensor* st_dev, int ntensors, hipStream_t st);
+int64_t select_np2(int64_t N);
+
+struct ErrJob {           // sum (A - B)^2 and sum A^2 of one tensor
+    const void* A;
+    const void* B;
+    int64_t count;
+    double* out;          // 2 doubles
+    double* part;         // 2 * ERR_SEGS doubles
+};
+constexpr int ERR_SEGS = 64;
+int run_error_batch(int adt, int bdt, const ErrJob* jobs, int njobs, hipStream_t st);
+
+size_t jacobi_batch_ctl_bytes(int64_t nslices, int max_steps);
+int run_jacobi_batch(int dt, int nb2, const BatchSlice* sl, int64_t nslices, const int2* tasks,
+                     int64_t ntasks, int max_steps, int host_poll, void* ctl_ws,
+                     int32_t* status, hipStream_t st);
+
 // ---- transform (ttm.hip)
 size_t ttm_workspace_bytes(int64_t n);
+void ttm_tile_counts(int64_t R, int64_t n, int64_t* n_rt, int* n_ct);
+int run_ttm_batch(const TtmProblem* probs, int nprob, const int4* tasks, int64_t ntasks, int xdt,
+                  int ydt, int compute, int transpose, hipStream_t st);
 int run_ttm(const void* X, int xdt, void* Y, int ydt, int64_t m, int64_t p, int64_t n,
             const double* M, int transpose, double scale, int compute, void* ws,
             hipStream_t st);

@@ -119,23 +119,21 @@ __global__ __launch_bounds__(256) void pack_copy(const T* __restrict__ A, const 
 // C(:,:,s) = U_pk_s (m x rho_s) * G_pk_s (rho_s x p), computed as
 // C^T = G^T U^T so that MFMA output lanes run along the rows of C.
 template <class T>
-__global__ __launch_bounds__(256) void lowrank_gemm(const T* __restrict__ U_pk,
-                                                    const T* __restrict__ G_pk, int64_t m,
-                                                    int64_t p, const int32_t* __restrict__ rho,
-                                                    const int64_t* __restrict__ offsets,
-                                                    int64_t capacity, T* __restrict__ C,
-                                                    int tiles_a) {
+struct LowrankShared {
+    T Us[16][64 + 1];  // [c][a]
+    T Gs[64][16 + 1];  // [b][c]
+};
+
+// Output tile (ta, tb) of one slice: Cb (m x p) = Ub (m x kr) * Gb (kr x p).
+template <class T>
+__device__ __forceinline__ void lowrank_tile(LowrankShared<T>& sh, const T* __restrict__ Ub,
+                                             const T* __restrict__ Gb, int64_t m, int64_t p,
+                                             int64_t kr, T* __restrict__ Cb, int ta, int tb) {
     typedef typename Acc<T>::type AccT;
     constexpr int KC = 16;
-    __shared__ T Us[KC][64 + 1];  // [c][a]
-    __shared__ T Gs[64][KC + 1];  // [b][c]
-    const int64_t s = blockIdx.y;
-    const int ta = blockIdx.x % tiles_a, tb = blockIdx.x / tiles_a;
+    auto& Us = sh.Us;
+    auto& Gs = sh.Gs;
     const int64_t a0 = (int64_t)ta * 64, b0 = (int64_t)tb * 64;
-    const int64_t off = offsets[s];
-    const int64_t kr = (off + rho[s] <= capacity) ? rho[s] : 0;  // unwritten slices read as 0
-    const T* Ub = U_pk + m * off;
-    const T* Gb = G_pk + p * off;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int lr = lane & 15, lg = lane >> 4;
     AccT acc[4];
@@ -166,7 +164,6 @@ __global__ __launch_bounds__(256) void lowrank_gemm(const T* __restrict__ U_pk,
         }
         __syncthreads();
     }
-    T* Cb = C + s * m * p;
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
         const int64_t a = a0 + t * 16 + lr;
@@ -176,6 +173,110 @@ __global__ __launch_bounds__(256) void lowrank_gemm(const T* __restrict__ U_pk,
             const int64_t b = b0 + wave * 16 + mfma_row<T>(lg, v);
             if (b < p) Cb[a + b * m] = acc[t][v];
         }
+    }
+}
+
+template <class T>
+__global__ __launch_bounds__(256) void lowrank_gemm(const T* __restrict__ U_pk,
+                                                    const T* __restrict__ G_pk, int64_t m,
+                                                    int64_t p, const int32_t* __restrict__ rho,
+                                                    const int64_t* __restrict__ offsets,
+                                                    int64_t capacity, T* __restrict__ C,
+                                                    int tiles_a) {
+    __shared__ LowrankShared<T> sh;
+    const int64_t s = blockIdx.y;
+    const int ta = blockIdx.x % tiles_a, tb = blockIdx.x / tiles_a;
+    const int64_t off = offsets[s];
+    const int64_t kr = (off + rho[s] <= capacity) ? rho[s] : 0;  // unwritten slices read as 0
+    lowrank_tile<T>(sh, U_pk + m * off, G_pk + p * off, m, p, kr, C + s * m * p, ta, tb);
+}
+
+// Batched form: task = (slice, tile a, tile b) over PackSlice descriptors.
+template <class T>
+__global__ __launch_bounds__(256) void lowrank_gemm_batch(const PackSlice* __restrict__ ps,
+                                                          const int4* __restrict__ tasks) {
+    __shared__ LowrankShared<T> sh;
+    const int4 tk = tasks[blockIdx.x];
+    const PackSlice d = ps[tk.x];
+    const int64_t m = d.g.m, p = d.g.p;
+    const int64_t off = *d.off;
+    const int64_t kr = (off + *d.rho <= d.capacity) ? *d.rho : 0;
+    lowrank_tile<T>(sh, static_cast<const T*>(d.U_pk) + m * off,
+                    static_cast<const T*>(d.G_pk) + p * off, m, p, kr, static_cast<T*>(d.C),
+                    tk.y, tk.z);
+}
+
+// Batched pack, one workgroup per slice: sort the slice's squared singular
+// values (descending, ties by index) in LDS, then gather its kept triplets.
+template <class T>
+__global__ __launch_bounds__(1024) void pack_batch(const PackSlice* __restrict__ ps) {
+    __shared__ unsigned long long key[PMAX];
+    __shared__ int idx[PMAX];
+    const PackSlice d = ps[blockIdx.x];
+    const SliceGeom g = d.g;
+    const int64_t r = g.r, m = g.m, p = g.p;
+    int np = 1;
+    while (np < r) np <<= 1;
+    for (int i = threadIdx.x; i < np; i += blockDim.x) {
+        if (i < r) {
+            double v = d.s2[i];
+            if (!(v >= 0.0)) v = 0.0;
+            v += 0.0;
+            key[i] = ~(unsigned long long)__double_as_longlong(v);
+        } else {
+            key[i] = ~0ull;
+        }
+        idx[i] = i;
+    }
+    __syncthreads();
+    for (int k = 2; k <= np; k <<= 1) {
+        for (int j = k >> 1; j > 0; j >>= 1) {
+            for (int t = threadIdx.x; t < np / 2; t += blockDim.x) {
+                const int i = 2 * j * (t / j) + (t % j);
+                const bool up = (i & k) == 0;
+                const unsigned long long ka = key[i], kb = key[i + j];
+                const int ia = idx[i], ib = idx[i + j];
+                const bool gt = (ka > kb) || (ka == kb && ia > ib);
+                if (gt == up) { key[i] = kb; key[i + j] = ka; idx[i] = ib; idx[i + j] = ia; }
+            }
+            __syncthreads();
+        }
+    }
+    const int64_t kr = *d.rho, off = *d.off;
+    if (kr <= 0) return;
+    if (off + kr > d.capacity) {
+        if (threadIdx.x == 0) atomicExch(d.status, (int32_t)TSVDM_E_CAPACITY);
+        return;
+    }
+    const T* Ab = static_cast<const T*>(d.A);
+    const T* Wb = static_cast<const T*>(d.W);
+    T* U = static_cast<T*>(d.U_pk) + m * off;
+    T* G = static_cast<T*>(d.G_pk) + p * off;
+    T* S = static_cast<T*>(d.S_pk) + off;
+    for (int c = threadIdx.x; c < kr; c += blockDim.x)
+        S[c] = static_cast<T>(sqrt(fmax(d.s2[idx[c]], 0.0)));
+    const bool rows = g.rows != 0;
+    for (int64_t e = threadIdx.x; e < kr * m; e += blockDim.x) {
+        const int64_t a = e % m, c = e / m, j = idx[c];
+        T v;
+        if (rows) {
+            v = Wb[j * r + a];
+        } else {
+            const double sg = sqrt(fmax(d.s2[j], 0.0));
+            v = sg > 0.0 ? static_cast<T>((double)Ab[a + j * m] / sg) : T(0);
+        }
+        U[e] = v;
+    }
+    for (int64_t e = threadIdx.x; e < kr * p; e += blockDim.x) {
+        const int64_t c = e % kr, b = e / kr, j = idx[c];
+        T v;
+        if (rows) {
+            v = Ab[j + b * m];
+        } else {
+            const double sg = sqrt(fmax(d.s2[j], 0.0));
+            v = static_cast<T>(sg * (double)Wb[b + j * r]);
+        }
+        G[e] = v;
     }
 }
 
@@ -247,6 +348,23 @@ int run_lowrank_gemm(const void* U_pk, const void* G_pk, int dt, int64_t m, int6
         set_error("reconstruction supports F64 and F32 only");
         return TSVDM_E_UNSUPPORTED;
     }
+    TSVDM_LAUNCH_CHECK();
+    return TSVDM_OK;
+}
+
+int run_pack_batch(int dt, const PackSlice* ps, int64_t nslices, hipStream_t st) {
+    TSVDM_REQUIRE(nslices < ((int64_t)1 << 31), TSVDM_E_SHAPE, "too many slices");
+    if (dt == TSVDM_F64) pack_batch<double><<<(unsigned)nslices, 1024, 0, st>>>(ps);
+    else pack_batch<float><<<(unsigned)nslices, 1024, 0, st>>>(ps);
+    TSVDM_LAUNCH_CHECK();
+    return TSVDM_OK;
+}
+
+int run_lowrank_batch(int dt, const PackSlice* ps, const int4* tasks, int64_t ntasks,
+                      hipStream_t st) {
+    TSVDM_REQUIRE(ntasks < ((int64_t)1 << 31), TSVDM_E_SHAPE, "too many reconstruction tiles");
+    if (dt == TSVDM_F64) lowrank_gemm_batch<double><<<(unsigned)ntasks, 256, 0, st>>>(ps, tasks);
+    else lowrank_gemm_batch<float><<<(unsigned)ntasks, 256, 0, st>>>(ps, tasks);
     TSVDM_LAUNCH_CHECK();
     return TSVDM_OK;
 }

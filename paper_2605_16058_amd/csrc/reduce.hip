@@ -76,4 +76,62 @@ int run_error(const void* A, int adt, const void* B, int bdt, int64_t count, dou
     return TSVDM_OK;
 }
 
+namespace {
+
+// task = (job, segment): segment s of job j covers [s*seg, (s+1)*seg)
+template <class TA, class TB>
+__global__ __launch_bounds__(RTHREADS) void err_partial_batch(const ErrJob* __restrict__ jobs) {
+    const ErrJob jb = jobs[blockIdx.y];
+    const TA* A = static_cast<const TA*>(jb.A);
+    const TB* B = static_cast<const TB*>(jb.B);
+    const int64_t seg = (jb.count + ERR_SEGS - 1) / ERR_SEGS;
+    const int64_t b0 = (int64_t)blockIdx.x * seg;
+    const int64_t b1 = (b0 + seg < jb.count) ? b0 + seg : jb.count;
+    double d2 = 0.0, a2 = 0.0;
+    for (int64_t i = b0 + threadIdx.x; i < b1; i += RTHREADS) {
+        const double a = (double)A[i];
+        const double d = a - (double)B[i];
+        d2 = fma(d, d, d2);
+        a2 = fma(a, a, a2);
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+        d2 += __shfl_xor(d2, off);
+        a2 += __shfl_xor(a2, off);
+    }
+    __shared__ double sd[RTHREADS / 64], sa[RTHREADS / 64];
+    const int w = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) { sd[w] = d2; sa[w] = a2; }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double x = 0.0, y = 0.0;
+        for (int i = 0; i < RTHREADS / 64; ++i) { x += sd[i]; y += sa[i]; }
+        jb.part[2 * blockIdx.x] = x;
+        jb.part[2 * blockIdx.x + 1] = y;
+    }
+}
+
+__global__ void err_final_batch(const ErrJob* __restrict__ jobs, int njobs) {
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= njobs) return;
+    const ErrJob jb = jobs[j];
+    double x = 0.0, y = 0.0;
+    for (int i = 0; i < ERR_SEGS; ++i) { x += jb.part[2 * i]; y += jb.part[2 * i + 1]; }
+    jb.out[0] = x;
+    jb.out[1] = y;
+}
+
+}  // namespace
+
+int run_error_batch(int adt, int bdt, const ErrJob* jobs, int njobs, hipStream_t st) {
+    dim3 grid(ERR_SEGS, (unsigned)njobs);
+    if (adt == TSVDM_F64 && bdt == TSVDM_F64) err_partial_batch<double, double><<<grid, RTHREADS, 0, st>>>(jobs);
+    else if (adt == TSVDM_F64) err_partial_batch<double, float><<<grid, RTHREADS, 0, st>>>(jobs);
+    else if (bdt == TSVDM_F64) err_partial_batch<float, double><<<grid, RTHREADS, 0, st>>>(jobs);
+    else err_partial_batch<float, float><<<grid, RTHREADS, 0, st>>>(jobs);
+    TSVDM_LAUNCH_CHECK();
+    err_final_batch<<<(unsigned)((njobs + 63) / 64), 64, 0, st>>>(jobs, njobs);
+    TSVDM_LAUNCH_CHECK();
+    return TSVDM_OK;
+}
+
 }  // namespace tsvdm

@@ -73,8 +73,10 @@ __global__ void sel_bitonic_global(unsigned long long* __restrict__ keys, int64_
 constexpr int STHREADS = 1024;
 
 // Single-workgroup scan over the N sorted values (N <= a few million).
-__global__ __launch_bounds__(STHREADS) void sel_scan(const unsigned long long* __restrict__ keys,
-                                                     int64_t N, double eps, double* __restrict__ stats) {
+// Scan of N ascending keys by one workgroup of STHREADS threads; writes
+// stats = {tau, discarded, W, J}.
+__device__ void sel_scan_body(const unsigned long long* __restrict__ keys, int64_t N, double eps,
+                              double* __restrict__ stats) {
     __shared__ double shi[STHREADS], slo[STHREADS];
     __shared__ double phi[STHREADS], plo[STHREADS];
     __shared__ long long cnt[STHREADS];
@@ -140,6 +142,55 @@ __global__ __launch_bounds__(STHREADS) void sel_scan(const unsigned long long* _
         stats[1] = dd_round(run);
         stats[2] = W;
         stats[3] = (double)J_s;
+    }
+    __syncthreads();
+}
+
+__global__ __launch_bounds__(STHREADS) void sel_scan(const unsigned long long* __restrict__ keys,
+                                                     int64_t N, double eps, double* __restrict__ stats) {
+    sel_scan_body(keys, N, eps, stats);
+}
+
+// Batched selection, one workgroup per tensor: t-SVDM-I writes the fixed
+// ranks; t-SVDM-II sorts the tensor's squared values with a bitonic network
+// in its global scratch, scans them and counts per slice.
+__global__ __launch_bounds__(STHREADS) void sel_batch(const SelTensor* __restrict__ jobs) {
+    const SelTensor j = jobs[blockIdx.x];
+    const int t = threadIdx.x;
+    const int64_t r = j.r, n = j.n;
+    if (j.mode == 1) {
+        const int64_t kk = j.k < r ? j.k : r;
+        for (int64_t i = t; i < n; i += STHREADS) j.rho[i] = (int32_t)kk;
+        for (int64_t i = t; i <= n; i += STHREADS) j.offsets[i] = i * kk;
+        return;
+    }
+    const int64_t N = r * n, Np = j.np2;
+    unsigned long long* keys = j.keys;
+    for (int64_t i = t; i < Np; i += STHREADS) keys[i] = i < N ? key_of(j.s2[i]) : ~0ull;
+    __syncthreads();
+    for (int64_t k = 2; k <= Np; k <<= 1) {
+        for (int64_t jj = k >> 1; jj > 0; jj >>= 1) {
+            for (int64_t q = t; q < Np / 2; q += STHREADS) {
+                const int64_t i = 2 * jj * (q / jj) + (q % jj);
+                const bool up = (i & k) == 0;
+                const unsigned long long a = keys[i], b = keys[i + jj];
+                if ((a > b) == up) { keys[i] = b; keys[i + jj] = a; }
+            }
+            __syncthreads();
+        }
+    }
+    sel_scan_body(keys, N, j.eps, j.stats);
+    const double tau = j.stats[0];
+    for (int64_t i = t; i < n; i += STHREADS) {
+        int c = 0;
+        for (int64_t q = 0; q < r; ++q) c += (j.s2[i * r + q] > tau) ? 1 : 0;
+        j.rho[i] = c;
+    }
+    __syncthreads();
+    if (t == 0) {
+        int64_t run = 0;
+        for (int64_t i = 0; i < n; ++i) { j.offsets[i] = run; run += j.rho[i]; }
+        j.offsets[n] = run;
     }
 }
 
@@ -238,5 +289,13 @@ int run_truncate_rank(int64_t k, int64_t r, int64_t n, int32_t* rho, int64_t* of
     TSVDM_LAUNCH_CHECK();
     return TSVDM_OK;
 }
+
+int run_select_batch(const SelTensor* jobs, int ntensors, hipStream_t st) {
+    sel_batch<<<(unsigned)ntensors, STHREADS, 0, st>>>(jobs);
+    TSVDM_LAUNCH_CHECK();
+    return TSVDM_OK;
+}
+
+int64_t select_np2(int64_t N) { return next_pow2(N < 2 ? 2 : N); }
 
 }  // namespace tsvdm

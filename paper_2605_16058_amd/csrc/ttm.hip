@@ -31,21 +31,21 @@ __global__ void ttm_prep(const double* __restrict__ M, int n, int transpose,
 // KIND 1: BF16 operands, FP32 accumulate, K step 32.
 // KIND 2: split BF16 (hi*hi + hi*lo + lo*hi), FP32 accumulate, K step 32.
 template <class CT, int KIND>
-__global__ __launch_bounds__(256) void ttm_kernel(
-    const void* __restrict__ X, int xdt, void* __restrict__ Y, int ydt,
-    int64_t R, int n, const CT* __restrict__ Tt, int n_ct, int64_t n_rt) {
-    constexpr int KC = (KIND == 0) ? 16 : 32;
-    typedef typename Acc<CT>::type AccT;
-    __shared__ CT Xs[KC][TILE_R + 1];   // [l][row]
-    __shared__ CT Ts[TILE_I][KC + 1];   // [i][l]
+struct TtmShared {
+    static constexpr int KC = (KIND == 0) ? 16 : 32;
+    CT Xs[KC][TILE_R + 1];   // [l][row]
+    CT Ts[TILE_I][KC + 1];   // [i][l]
+};
 
-    // XCD-aware block mapping: the n_ct column tiles of one row tile share
-    // blockIdx % 8 (the same XCD and L2) and are dispatched together.
-    const int64_t bid = blockIdx.x;
-    const int64_t xcd = bid & 7, local = bid >> 3;
-    const int64_t rt = (local / n_ct) * 8 + xcd;
-    const int ct = (int)(local % n_ct);
-    if (rt >= n_rt) return;
+// Output tile (row tile rt, slice tile ct) of Y = X x_3 op(M).
+template <class CT, int KIND>
+__device__ __forceinline__ void ttm_tile(TtmShared<CT, KIND>& sh, const void* __restrict__ X, int xdt,
+                                         void* __restrict__ Y, int ydt, int64_t R, int n,
+                                         const CT* __restrict__ Tt, int64_t rt, int ct) {
+    constexpr int KC = TtmShared<CT, KIND>::KC;
+    typedef typename Acc<CT>::type AccT;
+    auto& Xs = sh.Xs;
+    auto& Ts = sh.Ts;
     const int64_t row0 = rt * TILE_R;
     const int i0 = ct * TILE_I;
 
@@ -132,6 +132,45 @@ __global__ __launch_bounds__(256) void ttm_kernel(
 }
 
 template <class CT, int KIND>
+__global__ __launch_bounds__(256) void ttm_kernel(
+    const void* __restrict__ X, int xdt, void* __restrict__ Y, int ydt,
+    int64_t R, int n, const CT* __restrict__ Tt, int n_ct, int64_t n_rt) {
+    __shared__ TtmShared<CT, KIND> sh;
+    // XCD-aware block mapping: the n_ct column tiles of one row tile share
+    // blockIdx % 8 (the same XCD and L2) and are dispatched together.
+    const int64_t bid = blockIdx.x;
+    const int64_t xcd = bid & 7, local = bid >> 3;
+    const int64_t rt = (local / n_ct) * 8 + xcd;
+    const int ct = (int)(local % n_ct);
+    if (rt >= n_rt) return;
+    ttm_tile<CT, KIND>(sh, X, xdt, Y, ydt, R, n, Tt, rt, ct);
+}
+
+// Batched form: task = (problem, row tile, slice tile).
+template <class CT, int KIND>
+__global__ __launch_bounds__(256) void ttm_kernel_batch(const TtmProblem* __restrict__ probs,
+                                                        const int4* __restrict__ tasks,
+                                                        int xdt, int ydt) {
+    __shared__ TtmShared<CT, KIND> sh;
+    const int4 tk = tasks[blockIdx.x];
+    const TtmProblem pr = probs[tk.x];
+    ttm_tile<CT, KIND>(sh, pr.X, xdt, pr.Y, ydt, pr.R, pr.n,
+                       static_cast<const CT*>(pr.Tt), (int64_t)tk.y, tk.z);
+}
+
+template <class ST>
+__global__ void ttm_prep_batch(const TtmProblem* __restrict__ probs, int nprob, int transpose) {
+    const TtmProblem pr = probs[blockIdx.x];
+    const int n = pr.n;
+    ST* Tt = static_cast<ST*>(pr.Tt);
+    for (int64_t idx = threadIdx.x; idx < (int64_t)n * n; idx += blockDim.x) {
+        const int i = (int)(idx / n), l = (int)(idx % n);
+        const double v = transpose ? pr.M[l + (int64_t)i * n] : pr.M[i + (int64_t)l * n];
+        Tt[idx] = static_cast<ST>(pr.scale * v);
+    }
+}
+
+template <class CT, int KIND>
 int launch_ttm(const void* X, int xdt, void* Y, int ydt, int64_t R, int n,
                const double* M, int transpose, double scale, void* ws,
                hipStream_t st) {
@@ -170,6 +209,43 @@ int run_ttm(const void* X, int xdt, void* Y, int ydt, int64_t m, int64_t p, int6
             set_error("unsupported compute dtype for the transform");
             return TSVDM_E_UNSUPPORTED;
     }
+}
+
+void ttm_tile_counts(int64_t R, int64_t n, int64_t* n_rt, int* n_ct) {
+    *n_rt = (R + TILE_R - 1) / TILE_R;
+    *n_ct = (int)((n + TILE_I - 1) / TILE_I);
+}
+
+int run_ttm_batch(const TtmProblem* probs, int nprob, const int4* tasks, int64_t ntasks, int xdt,
+                  int ydt, int compute, int transpose, hipStream_t st) {
+    TSVDM_REQUIRE(ntasks < ((int64_t)1 << 31), TSVDM_E_SHAPE, "too many transform tiles");
+    switch (compute) {
+        case TSVDM_F64:
+            ttm_prep_batch<double><<<nprob, 256, 0, st>>>(probs, nprob, transpose);
+            TSVDM_LAUNCH_CHECK();
+            ttm_kernel_batch<double, 0><<<(unsigned)ntasks, 256, 0, st>>>(probs, tasks, xdt, ydt);
+            break;
+        case TSVDM_F32:
+            ttm_prep_batch<float><<<nprob, 256, 0, st>>>(probs, nprob, transpose);
+            TSVDM_LAUNCH_CHECK();
+            ttm_kernel_batch<float, 0><<<(unsigned)ntasks, 256, 0, st>>>(probs, tasks, xdt, ydt);
+            break;
+        case TSVDM_BF16:
+            ttm_prep_batch<float><<<nprob, 256, 0, st>>>(probs, nprob, transpose);
+            TSVDM_LAUNCH_CHECK();
+            ttm_kernel_batch<float, 1><<<(unsigned)ntasks, 256, 0, st>>>(probs, tasks, xdt, ydt);
+            break;
+        case TSVDM_BF16X3:
+            ttm_prep_batch<float><<<nprob, 256, 0, st>>>(probs, nprob, transpose);
+            TSVDM_LAUNCH_CHECK();
+            ttm_kernel_batch<float, 2><<<(unsigned)ntasks, 256, 0, st>>>(probs, tasks, xdt, ydt);
+            break;
+        default:
+            set_error("unsupported compute dtype for the transform");
+            return TSVDM_E_UNSUPPORTED;
+    }
+    TSVDM_LAUNCH_CHECK();
+    return TSVDM_OK;
 }
 
 }  // namespace tsvdm

@@ -119,6 +119,107 @@ def tsvdm(A, M, mode="II", k=None, eps=None, precision="f64", **kw) -> Result:
     return op(A)
 
 
+class BatchTSVDM:
+    """Many independent tensors of any shapes through one batch plan.
+
+    tensors: list of column-major device tensors (m_t, p_t, n_t), all of one
+    dtype; Ms: list of n_t x n_t transforms; modes: "I"/"II" per tensor with
+    ks / epss.  Each stage of the hot path is one launch over all tensors
+    (see tsvdm_batch_plan_create); run() returns the device status word.
+    keep_factors=True allocates packed factors per tensor (worst-case
+    capacity) so they can be read back; otherwise they stay in the workspace.
+    """
+
+    def __init__(self, tensors, Ms, modes, ks=None, epss=None, precision="f32", block=0,
+                 max_sweeps=0, keep_factors=False, reconstruct=True, device="cuda"):
+        import ctypes
+
+        from . import _lib
+        if precision not in PRECISIONS:
+            raise ValueError(f"precision must be one of {list(PRECISIONS)}")
+        ttm_compute, dtype = PRECISIONS[precision]
+        self.dtype = dtype
+        cnt = len(tensors)
+        ks = ks or [None] * cnt
+        epss = epss or [None] * cnt
+        self.tensors = [ops.as_colmajor(t) for t in tensors]
+        in_dt = self.tensors[0].dtype
+        if any(t.dtype != in_dt for t in self.tensors):
+            raise TypeError("all tensors of a batch must share one dtype")
+        self.Mdev, self.rho, self.offsets, self.stats, self.A_rec, self.err = [], [], [], [], [], []
+        self.U_pk, self.G_pk, self.S_pk, self.capacity = [], [], [], []
+        items = (_lib.BatchItem * cnt)()
+        for t, (A, M, mode) in enumerate(zip(self.tensors, Ms, modes)):
+            m, p, n = A.shape
+            r = min(m, p)
+            c2 = ops.check_transform(M)
+            Md = ops.device_matrix(M, device)
+            rho = torch.empty(n, dtype=torch.int32, device=device)
+            off = torch.empty(n + 1, dtype=torch.int64, device=device)
+            stats = torch.zeros(4, dtype=torch.float64, device=device)
+            Arec = ops.colmajor_empty(m, p, n, dtype, device) if reconstruct else None
+            err = torch.zeros(2, dtype=torch.float64, device=device) if reconstruct else None
+            it = items[t]
+            it.m, it.p, it.n = m, p, n
+            it.A = A.data_ptr()
+            it.M = Md.data_ptr()
+            it.inv_scale = 1.0 / c2
+            it.mode = 1 if mode == "I" else 2
+            it.reserved = 0
+            it.k = int(ks[t] or 1)
+            it.eps = float(epss[t] or 0.5)
+            it.rho, it.offsets, it.stats = rho.data_ptr(), off.data_ptr(), stats.data_ptr()
+            if keep_factors:
+                cap = (min(int(ks[t]), r) if mode == "I" else r) * n
+                U = torch.empty(m * cap, dtype=dtype, device=device)
+                G = torch.empty(p * cap, dtype=dtype, device=device)
+                S = torch.empty(cap, dtype=dtype, device=device)
+                it.U_pk, it.G_pk, it.S_pk, it.capacity = U.data_ptr(), G.data_ptr(), S.data_ptr(), cap
+                self.U_pk.append(U); self.G_pk.append(G); self.S_pk.append(S)
+                self.capacity.append(cap)
+            else:
+                it.U_pk = it.G_pk = it.S_pk = None
+                it.capacity = 0
+            it.A_rec = Arec.data_ptr() if Arec is not None else None
+            it.err = err.data_ptr() if err is not None else None
+            self.Mdev.append(Md); self.rho.append(rho); self.offsets.append(off)
+            self.stats.append(stats); self.A_rec.append(Arec); self.err.append(err)
+        self._items = items
+        plan = ctypes.c_void_p()
+        wsb = ctypes.c_size_t(0)
+        _lib.call("tsvdm_batch_plan_create", ctypes.cast(items, ctypes.c_void_p), cnt,
+                  ops._DT[in_dt], ops._DT[dtype], ops._COMPUTE[ttm_compute], int(block),
+                  int(max_sweeps), ctypes.byref(plan), ctypes.byref(wsb))
+        self.plan = plan
+        self.ws = torch.empty(max(int(wsb.value), 256), dtype=torch.uint8, device=device)
+        self.status = torch.zeros(1, dtype=torch.int32, device=device)
+
+    def run(self, host_poll=True, use_graph=False):
+        import ctypes
+
+        from . import _lib
+        _lib.call("tsvdm_batch_run", self.plan, ctypes.c_void_p(self.ws.data_ptr()),
+                  self.ws.numel(), int(bool(host_poll)), int(bool(use_graph)),
+                  ctypes.c_void_p(self.status.data_ptr()), ops._stream())
+        return self.status
+
+    def rel_errors(self):
+        out = []
+        for e in self.err:
+            e = e.double().cpu()
+            out.append(float((e[0] / e[1]).sqrt()) if e[1] > 0 else 0.0)
+        return out
+
+    def __del__(self):
+        try:
+            from . import _lib
+            if getattr(self, "plan", None) is not None and self.plan.value:
+                _lib.load().tsvdm_batch_plan_destroy(self.plan)
+                self.plan = None
+        except Exception:
+            pass
+
+
 class TruncLoss(torch.autograd.Function):
     """L(A, M) = sum of the squared singular values dropped by a rank-k
     truncation of every slice of A x_3 M, with a hand-written adjoint

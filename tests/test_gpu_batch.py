@@ -1,0 +1,122 @@
+"""GPU parity of the batch path (many ragged tensors through one plan).
+
+The batch kernels are the single-tensor kernels driven by task tables, so
+with the same Jacobi block width a batch must reproduce the single-tensor
+results bit for bit (ranks, reconstruction); the error sums use another
+reduction split and agree to rounding.  Against the FP64 oracle the FP64
+batch meets the same bounds as the single-tensor path; hipGraph replays must
+equal the eager run exactly.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle as O
+import synth
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def to_dev(A, dtype):
+    out = torch.empty((A.shape[2], A.shape[1], A.shape[0]), dtype=dtype, device="cuda").permute(2, 1, 0)
+    out.copy_(torch.from_numpy(np.asfortranarray(A)).to(dtype))
+    return out
+
+
+def rel(a, b):
+    a = np.asarray(a, np.float64)
+    b = np.asarray(b, np.float64)
+    d = np.linalg.norm(b.ravel())
+    return float(np.linalg.norm((a - b).ravel()) / (d if d > 0 else 1.0))
+
+
+@pytest.fixture(scope="module")
+def ragged():
+    return synth.workload("ragged", small=True)
+
+
+@pytest.mark.parametrize("precision,dtype", [("f64", torch.float64), ("f32", torch.float32)])
+def test_batch_equals_single_tensor_calls(ragged, precision, dtype):
+    from paper_2605_16058_amd.pipeline import BatchTSVDM, tsvdm
+    w = ragged
+    Ts = [to_dev(A, torch.float32) for A in w.A]
+    b = BatchTSVDM(Ts, w.M, w.mode, ks=w.k, epss=w.eps, precision=precision, block=16)
+    st = b.run(host_poll=True)
+    torch.cuda.synchronize()
+    assert int(st.item()) == 0
+    for t, A in enumerate(Ts):
+        res = tsvdm(A, w.M[t], mode=w.mode[t], k=w.k[t], eps=w.eps[t], precision=precision, block=16)
+        torch.cuda.synchronize()
+        assert torch.equal(res.rho, b.rho[t]), t
+        assert torch.equal(res.offsets, b.offsets[t]), t
+        assert torch.equal(res.A_rec, b.A_rec[t]), t
+        e1, e2 = res.err.cpu().numpy(), b.err[t].cpu().numpy()
+        assert np.allclose(e1, e2, rtol=1e-12, atol=1e-300), t
+
+
+def test_batch_fp64_matches_oracle(ragged):
+    from paper_2605_16058_amd.pipeline import BatchTSVDM
+    w = ragged
+    Ts = [to_dev(A, torch.float32) for A in w.A]
+    b = BatchTSVDM(Ts, w.M, w.mode, ks=w.k, epss=w.eps, precision="f64", keep_factors=True)
+    st = b.run()
+    torch.cuda.synchronize()
+    assert int(st.item()) == 0
+    errs = b.rel_errors()
+    for t, A in enumerate(w.A):
+        A64 = A.astype(np.float64)
+        ref = O.tsvdm_i(A64, w.M[t], w.k[t]) if w.mode[t] == "I" else O.tsvdm_ii(A64, w.M[t], w.eps[t])
+        rho = b.rho[t].cpu().numpy()
+        if w.mode[t] == "I":
+            assert np.array_equal(rho, ref["rho"])
+        sq = np.sort((ref["S"] ** 2).ravel())
+        tau = ref["info"].get("tau", None)
+        margin_ok = True
+        if w.mode[t] == "II" and tau is not None and np.isfinite(tau):
+            lo = sq[sq <= tau].max()
+            hi = sq[sq > tau].min() if np.any(sq > tau) else np.inf
+            margin_ok = (hi - lo) / max(lo, 1e-300) > 1e-10
+        if margin_ok:
+            assert np.array_equal(rho, ref["rho"]), t
+            assert rel(b.A_rec[t].cpu().numpy(), ref["A_rec"]) <= 1e-10, t
+            assert abs(errs[t] - ref["rel_error"]) <= 1e-9 * max(ref["rel_error"], 1e-6), t
+        # packed singular values are the oracle's leading ones
+        off = b.offsets[t].cpu().numpy()
+        S = b.S_pk[t].cpu().numpy()
+        for i in range(A.shape[2]):
+            k = int(rho[i])
+            assert np.allclose(S[off[i]: off[i] + k], ref["S"][:k, i], rtol=0,
+                               atol=1e-12 * max(ref["S"][0, i], 1e-300))
+
+
+def test_batch_graph_replays_equal_eager(ragged):
+    from paper_2605_16058_amd.pipeline import BatchTSVDM
+    w = ragged
+    Ts = [to_dev(A, torch.float32) for A in w.A[:8]]
+    b = BatchTSVDM(Ts, w.M[:8], w.mode[:8], ks=w.k[:8], epss=w.eps[:8], precision="f32")
+    b.run(host_poll=True)
+    torch.cuda.synchronize()
+    ref = [a.clone() for a in b.A_rec]
+    ref_rho = [r.clone() for r in b.rho]
+    junk = torch.randn(1 << 20, device="cuda")
+    side = torch.cuda.Stream()  # graphs are captured on a non-default stream
+    for rep in range(3):
+        for a in b.A_rec:
+            a.zero_()
+        torch.cuda.synchronize()
+        with torch.cuda.stream(side):
+            st = b.run(use_graph=True)
+        torch.cuda.synchronize()
+        assert int(st.item()) == 0
+        for t in range(len(Ts)):
+            assert torch.equal(b.A_rec[t], ref[t]), (rep, t)
+            assert torch.equal(b.rho[t], ref_rho[t]), (rep, t)
+        # eager work between replays
+        junk.mul_(1.0001).add_(0.5)
+        b.run(host_poll=True)
+        torch.cuda.synchronize()
+        for t in range(len(Ts)):
+            assert torch.equal(b.A_rec[t], ref[t]), (rep, t)
