@@ -1,20 +1,23 @@
 #!/usr/bin/env python3
-"""Throughput of the star-M t-SVDM-II hot path on one MI355X.
+"""Throughput of the star-M t-SVDM hot path on one MI355X.
 
-Workload (default): the climate-like tensor 512 (lat) x 1024 (lon) x 256
-(time), FP32 in HBM, M = orthonormal DCT-II along time, t-SVDM-II with
-relative tolerance 1e-3.  One step = transform -> slice SVDs -> rank
-selection -> factor packing -> reconstruction with back-transform -> FP64
-error report.  The mixed-precision path (FP32 MFMA transform, FP32 Jacobi
-with FP64 angles/convergence/energies) is the reported value; the plain FP64
-path is timed beside it on the same FP32 input (its up-cast is inside the
-step).  Metric: input GB/s = m*p*n*4 bytes / step time.
+Default workload (the reported line): the climate-like tensor 512 (lat) x
+1024 (lon) x 256 (time), FP32 in HBM, M = orthonormal DCT-II along time,
+t-SVDM-II with relative tolerance 1e-3.  One step = transform -> slice SVDs ->
+rank selection -> factor packing -> reconstruction with back-transform -> FP64
+error report.  The mixed-precision path (FP32 MFMA transform, FP32 Jacobi with
+FP64 angles/convergence/energies) gives the value; the plain FP64 path is
+timed beside it on the same FP32 input (its up-cast is inside the step).
+Metric: input GB/s = m*p*n*4 bytes / step time.
 
-Prints one JSON line (see the design doc for every field).
+Other workloads (--workload): ragged (512 uneven tensors through one batch
+plan), turbulence (2048x1024x256, transform precision sweep), cayley
+(gradient steps on a Cayley-parameterised M).  Each prints one JSON line.
 """
 from __future__ import annotations
 
 import argparse
+import ctypes
 import hashlib
 import json
 import math
@@ -42,46 +45,34 @@ def kernel_src_sha():
     return h.hexdigest()[:16]
 
 
-def time_steps(op, A, steps, warmup, torch):
-    for _ in range(warmup):
-        res = op(A)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(steps):
-        res = op(A)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    return res, (t1 - t0) * 1e3 / steps
+def read_stats(lib):
+    v = [ctypes.c_int64(), ctypes.c_double(), ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int32(),
+         ctypes.c_double(), ctypes.c_double()]
+    lib.tsvdm_stats_get(*[ctypes.byref(x) for x in v])
+    k = ["launches", "ms", "pairs_gram", "pairs_rot", "pair_width", "flops", "bytes"]
+    return dict(zip(k, [x.value for x in v]))
 
 
-def jacobi_roofline(stats, m, p, esize, dtype_peak_tf):
-    launches, ms, pg, pr, width = stats
-    L, r = max(m, p), min(m, p)
-    Wd = width
-    f_gram = 2.0 * Wd * Wd * L
-    f_rot = f_gram + 2.0 * Wd * Wd * (L + r)
-    b_gram = Wd * L * esize
-    b_rot = b_gram + 2.0 * Wd * (L + r) * esize
-    flops = pg * f_gram + pr * f_rot
-    nbytes = pg * b_gram + pr * b_rot
-    t = ms * 1e-3
-    ai = flops / max(nbytes, 1.0)
-    ridge = dtype_peak_tf * 1e12 / (PEAK["hbm_GBs"] * 1e9)
-    per_launch_ms = ms / max(launches, 1)
+def jacobi_roofline(st, peak_tf):
+    """Roofline entry of the dominant kernel (jacobi_round) from the
+    library's event timing and per-pair algorithmic counters."""
+    t = st["ms"] * 1e-3
+    launches = max(st["launches"], 1)
+    ai = st["flops"] / max(st["bytes"], 1.0)
+    ridge = peak_tf * 1e12 / (PEAK["hbm_GBs"] * 1e9)
+    common = {"traffic": None, "kernel": "jacobi_round", "launches": int(st["launches"]),
+              "avg_launch_ms": round(st["ms"] / launches, 4),
+              "flops_per_launch": st["flops"] / launches,
+              "bytes_per_launch": st["bytes"] / launches, "ai_flop_per_byte": round(ai, 2),
+              "pair_width": st["pair_width"], "pairs_rotating": st["pairs_rot"],
+              "pairs_gram_only": st["pairs_gram"]}
     if ai >= ridge:
-        ach = flops / t / 1e12
-        return {"bound": "mfma", "achieved": round(ach, 3), "peak": dtype_peak_tf,
-                "unit": "TFLOP/s", "frac": round(ach / dtype_peak_tf, 4), "traffic": None,
-                "kernel": "jacobi_round", "launches": int(launches),
-                "avg_launch_ms": round(per_launch_ms, 4),
-                "flops_per_launch": flops / max(launches, 1),
-                "bytes_per_launch": nbytes / max(launches, 1), "ai_flop_per_byte": round(ai, 2)}
-    ach = nbytes / t / 1e9
+        ach = st["flops"] / t / 1e12
+        return {"bound": "mfma", "achieved": round(ach, 3), "peak": peak_tf, "unit": "TFLOP/s",
+                "frac": round(ach / peak_tf, 4), **common}
+    ach = st["bytes"] / t / 1e9
     return {"bound": "hbm", "achieved": round(ach, 1), "peak": PEAK["hbm_GBs"], "unit": "GB/s",
-            "frac": round(ach / PEAK["hbm_GBs"], 4), "traffic": None, "kernel": "jacobi_round",
-            "launches": int(launches), "avg_launch_ms": round(per_launch_ms, 4),
-            "flops_per_launch": flops / max(launches, 1),
-            "bytes_per_launch": nbytes / max(launches, 1), "ai_flop_per_byte": round(ai, 2)}
+            "frac": round(ach / PEAK["hbm_GBs"], 4), **common}
 
 
 def load_traffic(key, sha):
@@ -98,11 +89,35 @@ def load_traffic(key, sha):
     return d.get("bytes_per_launch")
 
 
-def cpu_baseline(m, p, n_sample, eps):
+def blas_threads():
+    import threadpoolctl
+    return max((i.get("num_threads", 1) for i in threadpoolctl.threadpool_info()), default=1)
+
+
+def to_device(A, torch):
+    """(m, p, n) Fortran-ordered numpy array -> column-major device tensor."""
+    import numpy as np
+    return torch.from_numpy(np.ascontiguousarray(A.transpose(2, 1, 0))).cuda().permute(2, 1, 0)
+
+
+def timed(fn, steps, torch):
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    out = None
+    for _ in range(steps):
+        out = fn()
+    torch.cuda.synchronize()
+    return out, (time.perf_counter() - t0) * 1e3 / steps
+
+
+# ---------------------------------------------------------------------------
+# climate (default)
+# ---------------------------------------------------------------------------
+
+def cpu_baseline_climate(m, p, n_sample, eps):
     """The FP64 oracle, as it stands, on the first n_sample time steps of the
     same recipe (a bounded sample of the workload)."""
     import numpy as np
-    import threadpoolctl
 
     import oracle
     import synth
@@ -112,13 +127,264 @@ def cpu_baseline(m, p, n_sample, eps):
     t0 = time.perf_counter()
     res = oracle.tsvdm_ii(A.astype(np.float64), M, eps)
     dt = time.perf_counter() - t0
-    threads = max((i.get("num_threads", 1) for i in threadpoolctl.threadpool_info()), default=1)
-    gbs = m * p * n_sample * 4 / dt / 1e9
-    return {"value": round(gbs, 5), "unit": "GB/s", "cores": int(threads), "kind": "oracle",
+    return {"value": round(m * p * n_sample * 4 / dt / 1e9, 5), "unit": "GB/s",
+            "cores": int(blas_threads()), "kind": "oracle",
             "sample": f"climate-like {m}x{p}x{n_sample} (first {n_sample} of 256 time steps), "
                       f"DCT-II {n_sample}, t-SVDM-II tol {eps}, FP64 NumPy/LAPACK; "
                       f"{dt:.2f} s wall, rel_err {res['rel_error']:.3e}",
             "seconds": round(dt, 3)}
+
+
+def bench_climate(a, torch, lib):
+    import numpy as np
+
+    import synth
+    from paper_2605_16058_amd import ops
+    from paper_2605_16058_amd.pipeline import TSVDM
+
+    m, p, n = (int(x) for x in a.shape.split(","))
+    log(f"generating climate-like {m}x{p}x{n} FP32")
+    A = synth.climate_like(m, p, n, rng=np.random.default_rng(2))
+    M = synth.dct2_matrix(n)
+    Ad = to_device(A, torch)
+    del A
+    in_bytes = m * p * n * 4
+
+    op_mix = TSVDM((m, p, n), M, mode="II", eps=a.eps, precision=a.precision, block=a.block)
+    log(f"mixed ({a.precision}) warmup {a.warmup}, steps {a.steps}")
+    for _ in range(a.warmup):
+        op_mix(Ad)
+    lib.tsvdm_stats_reset()
+    lib.tsvdm_stats_enable(1)
+    res_mix, ms_mix = timed(lambda: op_mix(Ad), a.steps, torch)
+    lib.tsvdm_stats_enable(0)
+    st = read_stats(lib)
+    log(f"mixed: {ms_mix:.2f} ms/step; jacobi stats {st}")
+    roof = jacobi_roofline(st, PEAK["f32_TF"])
+    sha = kernel_src_sha()
+    roof["src_sha"] = sha
+    tr = load_traffic(f"jacobi_round_f32_{m}x{p}x{n}", sha)
+    if tr is not None:
+        roof["traffic"] = tr
+
+    out_f64 = {}
+    if not a.no_f64:
+        op64 = TSVDM((m, p, n), M, mode="II", eps=a.eps, precision="f64", block=a.block)
+        log(f"fp64 warmup {a.warmup}, steps {a.steps}")
+        for _ in range(a.warmup):
+            op64(Ad)
+        res64, ms64 = timed(lambda: op64(Ad), a.steps, torch)
+        log(f"fp64: {ms64:.2f} ms/step")
+        d = ops.tsvdm_error(res64.A_rec, res_mix.A_rec).double().cpu()
+        nA = float(res64.err[1].cpu())
+        out_f64 = {
+            "fp64_GBs": round(in_bytes / (ms64 * 1e-3) / 1e9, 3),
+            "fp64_ms_per_step": round(ms64, 3),
+            "speedup_vs_fp64": round(ms64 / ms_mix, 3),
+            "fp64_rel_error": res64.rel_error(),
+            "fp64_sum_rho": int(res64.offsets[-1].item()),
+            "fp64_svd_status": int(res64.svd_status.item()),
+            "mixed_vs_fp64_rel_diff": math.sqrt(float(d[0]) / nA) if nA > 0 else 0.0,
+        }
+        del res64, op64
+        torch.cuda.empty_cache()
+
+    cpu = None
+    if not a.no_cpu_baseline:
+        log(f"cpu baseline: oracle on {m}x{p}x{a.cpu_sample_n}")
+        cpu = cpu_baseline_climate(m, p, a.cpu_sample_n, a.eps)
+
+    return {
+        "metric": METRIC,
+        "value": round(in_bytes / (ms_mix * 1e-3) / 1e9, 3),
+        "unit": "GB/s", "n_gpus": 1, "steps": a.steps, "warmup": a.warmup,
+        "ms_per_step": round(ms_mix, 3), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32" if a.precision == "f32" else a.precision,
+        "data": "synthetic",
+        "config": {"workload": f"climate-like {m}x{p}x{n} FP32, DCT-II, t-SVDM-II tol {a.eps}",
+                   "m": m, "p": p, "n": n, "eps": a.eps, "precision": a.precision},
+        "rel_error": res_mix.rel_error(),
+        "sum_rho": int(res_mix.offsets[-1].item()),
+        "svd_status": int(res_mix.svd_status.item()),
+        **out_f64,
+        "roofline": roof,
+        "cpu_baseline": cpu,
+    }
+
+
+# ---------------------------------------------------------------------------
+# ragged batch
+# ---------------------------------------------------------------------------
+
+def bench_ragged(a, torch, lib):
+    import numpy as np
+
+    import synth
+    from paper_2605_16058_amd.pipeline import BatchTSVDM
+
+    log(f"generating ragged batch ({a.batch_count} tensors)")
+    w = synth.ragged_batch(count=a.batch_count)
+    in_bytes = sum(x.size for x in w.A) * 4
+    Ts = [to_device(x, torch) for x in w.A]
+    nslices = sum(x.shape[2] for x in w.A)
+    out = {}
+    res = {}
+    for prec in ([a.precision] + ([] if a.no_f64 else ["f64"])):
+        b = BatchTSVDM(Ts, w.M, w.mode, ks=w.k, epss=w.eps, precision=prec, block=a.block)
+        for _ in range(a.warmup):
+            b.run()
+        if prec == a.precision:
+            lib.tsvdm_stats_reset()
+            lib.tsvdm_stats_enable(1)
+        _, ms = timed(lambda: b.run(), a.steps, torch)
+        if prec == a.precision:
+            lib.tsvdm_stats_enable(0)
+            st = read_stats(lib)
+            out["roofline"] = jacobi_roofline(st, PEAK["f32_TF"])
+            out["roofline"]["src_sha"] = kernel_src_sha()
+        log(f"ragged {prec}: {ms:.2f} ms/step")
+        status = int(b.status.item())
+        errs = b.rel_errors()
+        res[prec] = (ms, status, errs, [r.clone() for r in b.rho])
+        del b
+        torch.cuda.empty_cache()
+    ms_mix, status, errs, rho_mix = res[a.precision]
+    line = {
+        "metric": "input GB/s through a batch of t-SVDM-I/II on uneven tensors",
+        "value": round(in_bytes / (ms_mix * 1e-3) / 1e9, 3), "unit": "GB/s", "n_gpus": 1,
+        "steps": a.steps, "warmup": a.warmup, "ms_per_step": round(ms_mix, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": a.precision, "data": "synthetic",
+        "config": {"workload": f"{a.batch_count} tensors, m,p~U[32,384], n~U[8,96], CP rank 2..32 "
+                               "+ 1e-2 noise, Haar M, even: t-SVDM-I k=16, odd: t-SVDM-II tol 1e-2",
+                   "tensors": a.batch_count, "slices": nslices, "input_GB": round(in_bytes / 1e9, 3)},
+        "status": status,
+        "max_rel_error_modeII": max(e for e, md in zip(errs, w.mode) if md == "II"),
+        "mean_rel_error_modeI": float(np.mean([e for e, md in zip(errs, w.mode) if md == "I"])),
+        "roofline": out.get("roofline"),
+        "cpu_baseline": None,
+    }
+    if "f64" in res:
+        ms64, st64, errs64, rho64 = res["f64"]
+        line["fp64_GBs"] = round(in_bytes / (ms64 * 1e-3) / 1e9, 3)
+        line["fp64_ms_per_step"] = round(ms64, 3)
+        line["speedup_vs_fp64"] = round(ms64 / ms_mix, 3)
+        line["sum_abs_rank_diff_vs_fp64"] = int(sum(int((r1.long() - r2.long()).abs().sum())
+                                                    for r1, r2 in zip(rho_mix, rho64)))
+    if not a.no_cpu_baseline:
+        import oracle
+        k = a.cpu_sample_tensors
+        t0 = time.perf_counter()
+        for A, M, md, kk, ee in list(zip(w.A, w.M, w.mode, w.k, w.eps))[:k]:
+            if md == "I":
+                oracle.tsvdm_i(A.astype(np.float64), M, kk)
+            else:
+                oracle.tsvdm_ii(A.astype(np.float64), M, ee)
+        dt = time.perf_counter() - t0
+        sb = sum(x.size for x in w.A[:k]) * 4
+        line["cpu_baseline"] = {"value": round(sb / dt / 1e9, 5), "unit": "GB/s",
+                                "cores": int(blas_threads()), "kind": "oracle",
+                                "sample": f"first {k} of the {a.batch_count} tensors "
+                                          f"({sb / 1e9:.3f} GB FP32), {dt:.2f} s"}
+    return line
+
+
+# ---------------------------------------------------------------------------
+# turbulence: transform precision sweep
+# ---------------------------------------------------------------------------
+
+def bench_turbulence(a, torch, lib):
+    import numpy as np
+
+    import synth
+    from paper_2605_16058_amd import ops
+    from paper_2605_16058_amd.pipeline import TSVDM
+
+    shape = (2048, 1024, 256) if not a.small else (192, 128, 32)
+    log(f"generating turbulence-like {shape}")
+    w = synth.workload("turbulence", small=a.small)
+    Ad = to_device(np.asfortranarray(w.A), torch)
+    in_bytes = Ad.numel() * 4
+    results = {}
+    ref = None
+    for prec in ["f64", "f32", "bf16x3", "bf16"]:
+        op = TSVDM(shape, w.M, mode="II", eps=w.eps, precision=prec, block=a.block)
+        for _ in range(a.warmup):
+            op(Ad)
+        res, ms = timed(lambda: op(Ad), a.steps, torch)
+        rec = {"ms_per_step": round(ms, 2), "GBs": round(in_bytes / (ms * 1e-3) / 1e9, 3),
+               "rel_error": res.rel_error(), "sum_rho": int(res.offsets[-1].item()),
+               "svd_status": int(res.svd_status.item())}
+        if prec == "f64":
+            ref = res
+        else:
+            d = ops.tsvdm_error(ref.A_rec, res.A_rec).double().cpu()
+            nA = float(ref.err[1].cpu())
+            rec["rel_diff_vs_fp64"] = math.sqrt(float(d[0]) / nA)
+        results[prec] = rec
+        log(f"turbulence {prec}: {rec}")
+        if prec != "f64":
+            del res
+        del op
+        torch.cuda.empty_cache()
+    return {"metric": "input GB/s through t-SVDM-II per transform precision",
+            "value": results["f32"]["GBs"], "unit": "GB/s", "n_gpus": 1, "steps": a.steps,
+            "warmup": a.warmup, "ms_per_step": results["f32"]["ms_per_step"],
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+            "data": "synthetic",
+            "config": {"workload": f"turbulence-like {shape[0]}x{shape[1]}x{shape[2]} k^-5/3 "
+                                   "field, Haar M, t-SVDM-II tol 1e-2"},
+            "precisions": results, "roofline": None, "cpu_baseline": None}
+
+
+# ---------------------------------------------------------------------------
+# cayley: gradient steps on the transform
+# ---------------------------------------------------------------------------
+
+def bench_cayley(a, torch, lib):
+    import numpy as np
+
+    import synth
+    from paper_2605_16058_amd.pipeline import TruncLoss
+
+    w = synth.workload("cayley", small=a.small)
+    A = to_device(np.asfortranarray(w.A), torch)
+    n = A.shape[2]
+    K = torch.tensor(w.extra["K0"], device="cuda", dtype=torch.float64)
+    I = torch.eye(n, dtype=torch.float64, device="cuda")
+
+    def loss_and_grad(Kv):
+        Kp = Kv.detach().clone().requires_grad_(True)
+        Ks = 0.5 * (Kp - Kp.t())
+        M = torch.linalg.solve(I - Ks, I + Ks)
+        L = TruncLoss.apply(A, M, w.k)
+        L.backward()
+        return float(L.detach()), Kp.grad.detach()
+
+    L0, g0 = loss_and_grad(K)
+    eta = 0.05 / float(g0.norm())
+    losses = [L0]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(a.grad_steps):
+        L, g = loss_and_grad(K)
+        K = K - eta * g
+        losses.append(L)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / a.grad_steps
+    Ks = 0.5 * (K - K.t())
+    M = torch.linalg.solve(I - Ks, I + Ks)
+    ortho = float((M.t() @ M - I).abs().max())
+    return {"metric": "gradient steps per second on the Cayley-parameterised transform",
+            "value": round(1e3 / ms, 3), "unit": "steps/s", "n_gpus": 1,
+            "steps": a.grad_steps, "warmup": 1, "ms_per_step": round(ms, 3),
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+            "dtype": "f32", "data": "synthetic",
+            "config": {"workload": f"{tuple(A.shape)} CP rank 24 + 5% noise, k={w.k}, "
+                                   "M = Cayley(K), lr 0.05/|grad0|"},
+            "loss_first": losses[0], "loss_last": losses[-1],
+            "loss_curve": [round(x, 6) for x in losses[:: max(1, len(losses) // 10)]],
+            "max_orthogonality_drift": ortho, "roofline": None, "cpu_baseline": None}
 
 
 def main(argv=None):
@@ -126,12 +392,18 @@ def main(argv=None):
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="climate",
+                    choices=["climate", "ragged", "turbulence", "cayley"])
     ap.add_argument("--precision", default="f32", choices=["f32", "bf16x3", "bf16"])
     ap.add_argument("--eps", type=float, default=1e-3)
     ap.add_argument("--shape", default="512,1024,256")
     ap.add_argument("--no-f64", action="store_true", help="skip the FP64 comparison path")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-n", type=int, default=32)
+    ap.add_argument("--cpu-sample-tensors", type=int, default=16)
+    ap.add_argument("--batch-count", type=int, default=512)
+    ap.add_argument("--grad-steps", type=int, default=50)
+    ap.add_argument("--small", action="store_true", help="test-size turbulence / cayley inputs")
     ap.add_argument("--block", type=int, default=0)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB device copy (for scaling HBM counters)")
@@ -153,97 +425,14 @@ def main(argv=None):
               file=sys.stderr)
         return 2
 
-    import numpy as np
     import torch
 
-    import synth
-    from paper_2605_16058_amd import _lib, ops
-    from paper_2605_16058_amd.pipeline import TSVDM
-
-    m, p, n = (int(x) for x in a.shape.split(","))
-    log(f"generating climate-like {m}x{p}x{n} FP32")
-    A = synth.climate_like(m, p, n, rng=np.random.default_rng(2))
-    M = synth.dct2_matrix(n)
-    Ad = torch.from_numpy(np.ascontiguousarray(A.transpose(2, 1, 0))).cuda().permute(2, 1, 0)
-    del A
-    in_bytes = m * p * n * 4
+    from paper_2605_16058_amd import _lib
 
     lib = _lib.load()
-    op_mix = TSVDM((m, p, n), M, mode="II", eps=a.eps, precision=a.precision, block=a.block)
-    log(f"mixed ({a.precision}) warmup {a.warmup}, steps {a.steps}")
-    for _ in range(a.warmup):
-        op_mix(Ad)
-    torch.cuda.synchronize()
-    lib.tsvdm_stats_reset()
-    lib.tsvdm_stats_enable(1)
-    res_mix, ms_mix = time_steps(op_mix, Ad, a.steps, 0, torch)
-    lib.tsvdm_stats_enable(0)
-    import ctypes
-    launches, ms, pg, pr, width = (ctypes.c_int64(), ctypes.c_double(), ctypes.c_int64(),
-                                   ctypes.c_int64(), ctypes.c_int32())
-    lib.tsvdm_stats_get(ctypes.byref(launches), ctypes.byref(ms), ctypes.byref(pg),
-                        ctypes.byref(pr), ctypes.byref(width))
-    stats = (launches.value, ms.value, pg.value, pr.value, width.value)
-    log(f"mixed: {ms_mix:.2f} ms/step; jacobi stats {stats}")
-    roof = jacobi_roofline(stats, m, p, 4, PEAK["f32_TF"])
-    sha = kernel_src_sha()
-    roof["src_sha"] = sha
-    tr = load_traffic(f"jacobi_round_f32_{m}x{p}x{n}", sha)
-    if tr is not None:
-        roof["traffic"] = tr
-    status_mix = int(res_mix.svd_status.item())
-    rel_mix = res_mix.rel_error()
-    sum_rho_mix = int(res_mix.offsets[-1].item())
-
-    out_f64 = {}
-    if not a.no_f64:
-        op64 = TSVDM((m, p, n), M, mode="II", eps=a.eps, precision="f64", block=a.block)
-        log(f"fp64 warmup {a.warmup}, steps {a.steps}")
-        res64, ms64 = time_steps(op64, Ad, a.steps, a.warmup, torch)
-        log(f"fp64: {ms64:.2f} ms/step")
-        d = ops.tsvdm_error(res64.A_rec, res_mix.A_rec)
-        e = d.double().cpu()
-        nA = float(res64.err[1].cpu())
-        out_f64 = {
-            "fp64_GBs": round(in_bytes / (ms64 * 1e-3) / 1e9, 3),
-            "fp64_ms_per_step": round(ms64, 3),
-            "speedup_vs_fp64": round(ms64 / ms_mix, 3),
-            "fp64_rel_error": res64.rel_error(),
-            "fp64_sum_rho": int(res64.offsets[-1].item()),
-            "fp64_svd_status": int(res64.svd_status.item()),
-            "mixed_vs_fp64_rel_diff": math.sqrt(float(e[0]) / nA) if nA > 0 else 0.0,
-        }
-        del res64, op64
-        torch.cuda.empty_cache()
-
-    cpu = None
-    if not a.no_cpu_baseline:
-        log(f"cpu baseline: oracle on {m}x{p}x{a.cpu_sample_n}")
-        cpu = cpu_baseline(m, p, a.cpu_sample_n, a.eps)
-
-    value = in_bytes / (ms_mix * 1e-3) / 1e9
-    line = {
-        "metric": METRIC,
-        "value": round(value, 3),
-        "unit": "GB/s",
-        "n_gpus": 1,
-        "steps": a.steps,
-        "warmup": a.warmup,
-        "ms_per_step": round(ms_mix, 3),
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f32" if a.precision == "f32" else a.precision,
-        "data": "synthetic",
-        "config": {"workload": f"climate-like {m}x{p}x{n} FP32, DCT-II, t-SVDM-II tol {a.eps}",
-                   "m": m, "p": p, "n": n, "eps": a.eps, "precision": a.precision},
-        "rel_error": rel_mix,
-        "sum_rho": sum_rho_mix,
-        "svd_status": status_mix,
-        **out_f64,
-        "roofline": roof,
-        "cpu_baseline": cpu,
-    }
+    fn = {"climate": bench_climate, "ragged": bench_ragged, "turbulence": bench_turbulence,
+          "cayley": bench_cayley}[a.workload]
+    line = fn(a, torch, lib)
     print(json.dumps(line), flush=True)
     return 0
 

@@ -311,12 +311,16 @@ int tsvdm_batch_plan_destroy(tsvdm_batch_plan plan);
  *               gaps between back-to-back launches),
  *   pairs_gram  block pairs that only formed their Gram matrix (converged),
  *   pairs_rot   block pairs that also rotated their vectors,
- *   pair_width  2b of the last call (the rows of each pair's Gram matrix).
- * Thread-safe; host only. */
+ *   pair_width  2b of the last call (the rows of each pair's Gram matrix),
+ *   flops       algorithmic flops of those pairs over their w valid vectors:
+ *               2 w^2 L (Gram) + 2 w^2 (L + r) (rotation, when rotating),
+ *   bytes       algorithmic bytes: w L e (Gram read) + 2 w (L + r) e
+ *               (rotation read and write), e = element size.
+ * Any pointer may be NULL.  Thread-safe; host only. */
 int tsvdm_stats_enable(int on);
 int tsvdm_stats_reset(void);
 int tsvdm_stats_get(int64_t* launches, double* ms, int64_t* pairs_gram,
-                    int64_t* pairs_rot, int32_t* pair_width);
+                    int64_t* pairs_rot, int32_t* pair_width, double* flops, double* bytes);
 
 #ifdef __cplusplus
 }

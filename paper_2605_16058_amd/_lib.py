@@ -49,7 +49,7 @@ _SIGS = {
     "tsvdm_batch_plan_destroy": (c_int, [_P]),
     "tsvdm_stats_enable": (c_int, [c_int]),
     "tsvdm_stats_reset": (c_int, []),
-    "tsvdm_stats_get": (c_int, [_P, _P, _P, _P, _P]),
+    "tsvdm_stats_get": (c_int, [_P, _P, _P, _P, _P, _P, _P]),
 }
 
 

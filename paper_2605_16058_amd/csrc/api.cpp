@@ -324,9 +324,9 @@ int tsvdm_stats_reset(void) {
 }
 
 int tsvdm_stats_get(int64_t* launches, double* ms, int64_t* pairs_gram, int64_t* pairs_rot,
-                    int32_t* pair_width) {
+                    int32_t* pair_width, double* flops, double* bytes) {
     clear_error();
-    stats_get(launches, ms, pairs_gram, pairs_rot, pair_width);
+    stats_get(launches, ms, pairs_gram, pairs_rot, pair_width, flops, bytes);
     return TSVDM_OK;
 }
 

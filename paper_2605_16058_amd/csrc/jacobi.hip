@@ -27,7 +27,7 @@ namespace {
 std::mutex g_stats_mu;
 bool g_stats_on = false;
 int64_t g_launches = 0, g_pairs_gram = 0, g_pairs_rot = 0;
-double g_ms = 0.0;
+double g_ms = 0.0, g_flops = 0.0, g_bytes = 0.0;
 int g_width = 0;
 }  // namespace
 
@@ -42,23 +42,29 @@ void stats_set(bool on) {
 void stats_reset() {
     std::lock_guard<std::mutex> lk(g_stats_mu);
     g_launches = g_pairs_gram = g_pairs_rot = 0;
-    g_ms = 0.0;
+    g_ms = g_flops = g_bytes = 0.0;
 }
-void stats_add(int64_t launches, double ms, int64_t pg, int64_t pr, int width) {
+// counters: {gram-only pairs, rotating pairs, flops, bytes} as read back
+static void stats_add_counters(int64_t launches, double ms, const unsigned long long* c, int width) {
     std::lock_guard<std::mutex> lk(g_stats_mu);
     g_launches += launches;
     g_ms += ms;
-    g_pairs_gram += pg;
-    g_pairs_rot += pr;
+    g_pairs_gram += (int64_t)c[0];
+    g_pairs_rot += (int64_t)c[1];
+    g_flops += (double)c[2];
+    g_bytes += (double)c[3];
     g_width = width;
 }
-void stats_get(int64_t* launches, double* ms, int64_t* pg, int64_t* pr, int32_t* width) {
+void stats_get(int64_t* launches, double* ms, int64_t* pg, int64_t* pr, int32_t* width,
+               double* flops, double* bytes) {
     std::lock_guard<std::mutex> lk(g_stats_mu);
     if (launches) *launches = g_launches;
     if (ms) *ms = g_ms;
     if (pg) *pg = g_pairs_gram;
     if (pr) *pr = g_pairs_rot;
     if (width) *width = g_width;
+    if (flops) *flops = g_flops;
+    if (bytes) *bytes = g_bytes;
 }
 
 namespace {
@@ -90,6 +96,8 @@ __global__ void jacobi_init(T* __restrict__ W, int64_t r, int64_t n, JacobiCtl* 
             *status = TSVDM_OK;
             pair_counts[0] = 0ull;
             pair_counts[1] = 0ull;
+            pair_counts[2] = 0ull;
+            pair_counts[3] = 0ull;
         }
     }
 }
@@ -329,7 +337,21 @@ __device__ __forceinline__ void round_body(RoundShared<T, NB2>& sh, T* __restric
     if (tid == 0) {
         if (nonfinite) atomicExch(&ctl_s->nonfinite, 1);
         else atomicMax(&ctl_s->maxcos_bits, (unsigned long long)__double_as_longlong(mc));
+        // algorithmic work of this pair over its w valid vectors: Gram
+        // 2 w^2 L flops and w L elements read; rotation 2 w^2 (L + r) flops
+        // and 2 w (L + r) elements read and written
+        const int64_t nI = (int64_t)I * B < r ? ((int64_t)I * B + B <= r ? B : r - (int64_t)I * B) : 0;
+        const int64_t nJ = (int64_t)J * B < r ? ((int64_t)J * B + B <= r ? B : r - (int64_t)J * B) : 0;
+        const unsigned long long w = (unsigned long long)(nI + nJ);
+        unsigned long long fl = 2ull * w * w * (unsigned long long)L;
+        unsigned long long by = w * (unsigned long long)L * sizeof(T);
+        if (rotate) {
+            fl += 2ull * w * w * (unsigned long long)(L + r);
+            by += 2ull * w * (unsigned long long)(L + r) * sizeof(T);
+        }
         atomicAdd(&pair_counts[rotate ? 1 : 0], 1ull);
+        atomicAdd(&pair_counts[2], fl);
+        atomicAdd(&pair_counts[3], by);
     }
     if (!rotate) return;  // uniform across the block
 
@@ -543,6 +565,8 @@ __global__ void jacobi_init_batch(const BatchSlice* __restrict__ sl, JacobiCtl* 
             *status = TSVDM_OK;
             pair_counts[0] = 0ull;
             pair_counts[1] = 0ull;
+            pair_counts[2] = 0ull;
+            pair_counts[3] = 0ull;
         }
     }
 }
@@ -647,7 +671,7 @@ int jacobi_impl(T* A, int64_t m, int64_t p, int64_t n, T* W, double* s2, int32_t
     Carver cv(ws);
     JacobiCtl* ctl = cv.carve<JacobiCtl>((size_t)n);
     int* remaining = cv.carve<int>((size_t)o.max_sweeps);
-    unsigned long long* pair_counts = cv.carve<unsigned long long>(2);
+    unsigned long long* pair_counts = cv.carve<unsigned long long>(4);
     const bool stats = stats_enabled();
     std::vector<hipEvent_t> evs;
 
@@ -713,7 +737,7 @@ int jacobi_impl(T* A, int64_t m, int64_t p, int64_t n, T* W, double* s2, int32_t
     jacobi_finish<<<1, 256, 0, st>>>(ctl, n, status);
     TSVDM_LAUNCH_CHECK();
     if (stats) {
-        unsigned long long pc[2] = {0ull, 0ull};
+        unsigned long long pc[4] = {0ull, 0ull, 0ull, 0ull};
         TSVDM_HIP_CHECK(hipMemcpyAsync(pc, pair_counts, sizeof(pc), hipMemcpyDeviceToHost, st));
         TSVDM_HIP_CHECK(hipStreamSynchronize(st));
         double ms = 0.0;
@@ -723,7 +747,7 @@ int jacobi_impl(T* A, int64_t m, int64_t p, int64_t n, T* W, double* s2, int32_t
             ms += t;
         }
         for (hipEvent_t e : evs) (void)hipEventDestroy(e);
-        stats_add(launches, ms, (int64_t)pc[0], (int64_t)pc[1], NB2);
+        stats_add_counters(launches, ms, pc, NB2);
     }
     return TSVDM_OK;
 }
@@ -734,7 +758,7 @@ int jacobi_batch_impl(const BatchSlice* sl, int64_t nslices, const int2* tasks, 
     Carver cv(ctl_ws);
     JacobiCtl* ctl = cv.carve<JacobiCtl>((size_t)nslices);
     int* remaining = cv.carve<int>((size_t)max_steps);
-    unsigned long long* pair_counts = cv.carve<unsigned long long>(2);
+    unsigned long long* pair_counts = cv.carve<unsigned long long>(4);
     TSVDM_REQUIRE(nslices < ((int64_t)1 << 31) && ntasks < ((int64_t)1 << 31), TSVDM_E_SHAPE,
                   "batch too large for one launch");
     jacobi_init_batch<T><<<(unsigned)nslices, 256, 0, st>>>(sl, ctl, remaining, max_steps,
@@ -769,14 +793,14 @@ int jacobi_batch_impl(const BatchSlice* sl, int64_t nslices, const int2* tasks, 
     jacobi_finish<<<1, 256, 0, st>>>(ctl, nslices, status);
     TSVDM_LAUNCH_CHECK();
     if (stats) {
-        unsigned long long pc[2] = {0ull, 0ull};
+        unsigned long long pc[4] = {0ull, 0ull, 0ull, 0ull};
         TSVDM_HIP_CHECK(hipMemcpyAsync(pc, pair_counts, sizeof(pc), hipMemcpyDeviceToHost, st));
         TSVDM_HIP_CHECK(hipStreamSynchronize(st));
         float ms = 0.f;
         TSVDM_HIP_CHECK(hipEventElapsedTime(&ms, e0, e1));
         (void)hipEventDestroy(e0);
         (void)hipEventDestroy(e1);
-        stats_add(launches, ms, (int64_t)pc[0], (int64_t)pc[1], NB2);
+        stats_add_counters(launches, ms, pc, NB2);
     }
     return TSVDM_OK;
 }
@@ -787,7 +811,7 @@ size_t jacobi_batch_ctl_bytes(int64_t nslices, int max_steps) {
     Carver cv(nullptr);
     cv.carve<JacobiCtl>((size_t)nslices);
     cv.carve<int>((size_t)max_steps);
-    cv.carve<unsigned long long>(2);
+    cv.carve<unsigned long long>(4);
     return cv.total();
 }
 
@@ -808,7 +832,7 @@ size_t jacobi_workspace_bytes(int64_t n) {
     Carver cv(nullptr);
     cv.carve<JacobiCtl>((size_t)n);
     cv.carve<int>(1024);
-    cv.carve<unsigned long long>(2);
+    cv.carve<unsigned long long>(4);
     return cv.total();
 }
 

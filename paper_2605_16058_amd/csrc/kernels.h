@@ -106,9 +106,8 @@ size_t jacobi_workspace_bytes(int64_t n);
 bool stats_enabled();
 void stats_set(bool on);
 void stats_reset();
-void stats_add(int64_t launches, double ms, int64_t pairs_gram, int64_t pairs_rot, int width);
 void stats_get(int64_t* launches, double* ms, int64_t* pairs_gram, int64_t* pairs_rot,
-               int32_t* width);
+               int32_t* width, double* flops, double* bytes);
 int run_jacobi(void* A, int dt, int64_t m, int64_t p, int64_t n, void* W, double* s2,
                int32_t* status, const JacobiOpts& o, void* ws, hipStream_t st);
 JacobiOpts jacobi_default_opts(int64_t m, int64_t p, int dt);
