@@ -114,6 +114,21 @@ def timed(fn, steps, torch):
 # climate (default)
 # ---------------------------------------------------------------------------
 
+def tune_single(a, Ad, M, precision, tuned):
+    """(block, tile) for one tensor: --block if given, else the autotuner's."""
+    if a.block or a.no_tune:
+        return a.block, 0
+    from paper_2605_16058_amd import autotune
+    t0 = time.perf_counter()
+    ch = autotune.tune_tsvdm(Ad, M, mode="II", eps=a.eps, precision=precision)
+    tuned[precision] = {"block": ch.block, "tile": ch.tile,
+                        "seconds": round(time.perf_counter() - t0, 2),
+                        "measured_ms": {k: {str(c): round(v, 3) for c, v in t.items()}
+                                        for k, t in ch.times.items()}}
+    log(f"autotune {precision}: {tuned[precision]}")
+    return ch.block, ch.tile
+
+
 def cpu_baseline_climate(m, p, n_sample, eps):
     """The FP64 oracle, as it stands, on the first n_sample time steps of the
     same recipe (a bounded sample of the workload)."""
@@ -150,7 +165,10 @@ def bench_climate(a, torch, lib):
     del A
     in_bytes = m * p * n * 4
 
-    op_mix = TSVDM((m, p, n), M, mode="II", eps=a.eps, precision=a.precision, block=a.block)
+    tuned = {}
+    ch = tune_single(a, Ad, M, a.precision, tuned)
+    op_mix = TSVDM((m, p, n), M, mode="II", eps=a.eps, precision=a.precision, block=ch[0],
+                   tile=ch[1])
     log(f"mixed ({a.precision}) warmup {a.warmup}, steps {a.steps}")
     for _ in range(a.warmup):
         op_mix(Ad)
@@ -169,7 +187,9 @@ def bench_climate(a, torch, lib):
 
     out_f64 = {}
     if not a.no_f64:
-        op64 = TSVDM((m, p, n), M, mode="II", eps=a.eps, precision="f64", block=a.block)
+        ch64 = tune_single(a, Ad, M, "f64", tuned)
+        op64 = TSVDM((m, p, n), M, mode="II", eps=a.eps, precision="f64", block=ch64[0],
+                     tile=ch64[1])
         log(f"fp64 warmup {a.warmup}, steps {a.steps}")
         for _ in range(a.warmup):
             op64(Ad)
@@ -202,7 +222,8 @@ def bench_climate(a, torch, lib):
         "vs_baseline": None, "dtype": "f32" if a.precision == "f32" else a.precision,
         "data": "synthetic",
         "config": {"workload": f"climate-like {m}x{p}x{n} FP32, DCT-II, t-SVDM-II tol {a.eps}",
-                   "m": m, "p": p, "n": n, "eps": a.eps, "precision": a.precision},
+                   "m": m, "p": p, "n": n, "eps": a.eps, "precision": a.precision,
+                   "autotune": tuned},
         "rel_error": res_mix.rel_error(),
         "sum_rho": int(res_mix.offsets[-1].item()),
         "svd_status": int(res_mix.svd_status.item()),
@@ -229,8 +250,22 @@ def bench_ragged(a, torch, lib):
     nslices = sum(x.shape[2] for x in w.A)
     out = {}
     res = {}
+    tuned = {}
     for prec in ([a.precision] + ([] if a.no_f64 else ["f64"])):
-        b = BatchTSVDM(Ts, w.M, w.mode, ks=w.k, epss=w.eps, precision=prec, block=a.block)
+        blocks = tiles = None
+        if not a.no_tune and not a.block:
+            from paper_2605_16058_amd import autotune
+            t0 = time.perf_counter()
+            blocks, tiles, rep = autotune.tune_batch(Ts, w.M, w.mode, ks=w.k, epss=w.eps,
+                                                     precision=prec)
+            tuned[prec] = {"seconds": round(time.perf_counter() - t0, 2),
+                           "blocks": {str(bw): blocks.count(bw) for bw in sorted(set(blocks))},
+                           "tiles": {str(tl): tiles.count(tl) for tl in sorted(set(tiles))},
+                           "measured_ms": {k: {str(c): round(v, 3) for c, v in t.items()}
+                                           for k, t in rep.items()}}
+            log(f"autotune {prec}: {tuned[prec]}")
+        b = BatchTSVDM(Ts, w.M, w.mode, ks=w.k, epss=w.eps, precision=prec, block=a.block,
+                       blocks=blocks, tiles=tiles)
         for _ in range(a.warmup):
             b.run()
         if prec == a.precision:
@@ -257,7 +292,8 @@ def bench_ragged(a, torch, lib):
         "dtype": a.precision, "data": "synthetic",
         "config": {"workload": f"{a.batch_count} tensors, m,p~U[32,384], n~U[8,96], CP rank 2..32 "
                                "+ 1e-2 noise, Haar M, even: t-SVDM-I k=16, odd: t-SVDM-II tol 1e-2",
-                   "tensors": a.batch_count, "slices": nslices, "input_GB": round(in_bytes / 1e9, 3)},
+                   "tensors": a.batch_count, "slices": nslices, "input_GB": round(in_bytes / 1e9, 3),
+                   "autotune": tuned},
         "status": status,
         "max_rel_error_modeII": max(e for e, md in zip(errs, w.mode) if md == "II"),
         "mean_rel_error_modeI": float(np.mean([e for e, md in zip(errs, w.mode) if md == "I"])),
@@ -404,7 +440,8 @@ def main(argv=None):
     ap.add_argument("--batch-count", type=int, default=512)
     ap.add_argument("--grad-steps", type=int, default=50)
     ap.add_argument("--small", action="store_true", help="test-size turbulence / cayley inputs")
-    ap.add_argument("--block", type=int, default=0)
+    ap.add_argument("--block", type=int, default=0, help="fixed Jacobi block width (skips tuning)")
+    ap.add_argument("--no-tune", action="store_true", help="library defaults, no autotuner")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB device copy (for scaling HBM counters)")
     a = ap.parse_args(argv)

@@ -99,12 +99,22 @@ int tsvdm_check_transform(const double* M_host, int64_t n, double tol,
  *   M        device, FP64, n x n column-major.
  *   compute  F64: FP64 MFMA; F32: FP32 MFMA; BF16 / BF16X3: BF16 MFMA with
  *            FP32 accumulation (y_dtype must then be F32).
+ *   tile     workgroup tile of the (mp) x n output: TSVDM_TILE_64x64,
+ *            TSVDM_TILE_128x32, TSVDM_TILE_256x16 (rows x slices), or
+ *            TSVDM_TILE_AUTO (by n: <= 16, <= 32, else 64 slices).  Every
+ *            tile gives the same result; only the speed differs.
  * ws: tsvdm_transform_workspace_size bytes (holds op(M) in compute type). */
+enum {
+    TSVDM_TILE_AUTO = 0,
+    TSVDM_TILE_64x64 = 1,
+    TSVDM_TILE_128x32 = 2,
+    TSVDM_TILE_256x16 = 3
+};
 int tsvdm_transform_workspace_size(int64_t n, size_t* bytes);
 int tsvdm_transform(const void* X, int x_dtype, void* Y, int y_dtype,
                     int64_t m, int64_t p, int64_t n,
                     const double* M, int transpose, double scale,
-                    int compute, void* ws, size_t ws_bytes, void* stream);
+                    int compute, int tile, void* ws, size_t ws_bytes, void* stream);
 
 /* --------------------------------------------------------------------- */
 /* slice SVDs (Algorithm 1; Section 3.2)                                 */
@@ -123,7 +133,8 @@ int tsvdm_transform(const void* X, int x_dtype, void* Y, int y_dtype,
  *   status   (device int32, 1 element) TSVDM_OK or TSVDM_E_NOCONV /
  *            TSVDM_E_NONFINITE.
  * Options:
- *   block    Jacobi block width b (16 or 32; 0 = autotuned default).
+ *   block    Jacobi block width b (16 or 32; 0 = 32 when min(m, p) >= 256,
+ *            else 16).
  *   max_sweeps  sweep limit (0 = 40).
  *   tol      convergence threshold on |cos| between any two vectors, tested
  *            in FP64 (0 = default: 1e-14 for F64, 2e-6 for F32).
@@ -197,15 +208,15 @@ int tsvdm_pack(const void* A_hat, const void* W, const double* s2, int dtype,
  * scale = 1 for orthonormal M, 1/c^2 for M = c*Q.  U_pk, G_pk use the
  * packed layout of tsvdm_pack with the same `capacity`; a slice whose block
  * would end beyond capacity contributes zero.  C_hat lives in the workspace
- * (m*p*n elements of `dtype`).  compute selects the back-TTM arithmetic as
- * in tsvdm_transform. */
+ * (m*p*n elements of `dtype`).  compute and tile select the back-TTM
+ * arithmetic and tile shape as in tsvdm_transform. */
 int tsvdm_reconstruct_workspace_size(int64_t m, int64_t p, int64_t n,
                                      int dtype, size_t* bytes);
 int tsvdm_reconstruct(const void* U_pk, const void* G_pk, int dtype,
                       int64_t m, int64_t p, int64_t n,
                       const int32_t* rho, const int64_t* offsets, int64_t capacity,
                       const double* M, double scale, void* A_rec,
-                      int out_dtype, int compute,
+                      int out_dtype, int compute, int tile,
                       void* ws, size_t ws_bytes, void* stream);
 
 /* --------------------------------------------------------------------- */
@@ -255,7 +266,8 @@ typedef struct {
     const double* M;      /* n x n FP64 column-major, a multiple of orthogonal  */
     double inv_scale;     /* back-transform scale 1/c^2 (1 for orthonormal M)   */
     int32_t mode;         /* 1 = t-SVDM-I, 2 = t-SVDM-II                        */
-    int32_t reserved;     /* must be 0                                          */
+    int32_t block;        /* Jacobi block width of its slices: 16, 32, or 0 to  */
+                          /* take the plan's (see tsvdm_batch_plan_create)      */
     int64_t k;            /* mode 1 rank (>= 1, clamped to r)                   */
     double eps;           /* mode 2 tolerance, in (0, 1)                        */
     int32_t* rho;         /* out: int32[n] ranks                                */
@@ -267,6 +279,8 @@ typedef struct {
     int64_t capacity;     /* triplets U_pk/G_pk/S_pk hold (ignored when NULL)   */
     void* A_rec;          /* out: reconstruction m*p*n, or NULL to skip it      */
     double* err;          /* out: FP64[2] {sum (A-A_rec)^2, sum A^2} or NULL    */
+    int32_t ttm_tile;     /* transform tile shape (TSVDM_TILE_*) of both TTMs   */
+    int32_t reserved;     /* must be 0                                          */
 } tsvdm_batch_item;
 
 typedef struct tsvdm_batch_plan_s* tsvdm_batch_plan;
@@ -276,9 +290,12 @@ typedef struct tsvdm_batch_plan_s* tsvdm_batch_plan;
  * tiles, Jacobi (slice, block-pair) tasks, per-tensor selection, per-slice
  * packing, reconstruction tiles), which the plan keeps in device memory it
  * owns.  in_dtype: F32 or F64 input; dtype: F64 or F32 Jacobi / factor /
- * output type; ttm_compute as in tsvdm_transform; block as in
- * tsvdm_slice_svd (one width for the whole batch, 0 = default);
- * max_sweeps 0 = 40.  Host errors return before anything is launched. */
+ * output type; ttm_compute as in tsvdm_transform; block: the Jacobi block
+ * width (16 or 32) of items whose own block is 0; block 0 leaves those
+ * items at the default (32 when the largest min(m, p) of the batch is at
+ * least 256, else 16).  Items of different widths run as two launches per
+ * round step.  max_sweeps 0 = 40.  Host errors return before anything is
+ * launched. */
 int tsvdm_batch_plan_create(const tsvdm_batch_item* items, int32_t count, int in_dtype,
                             int dtype, int ttm_compute, int block, int max_sweeps,
                             tsvdm_batch_plan* plan, size_t* ws_bytes);
@@ -311,7 +328,8 @@ int tsvdm_batch_plan_destroy(tsvdm_batch_plan plan);
  *               gaps between back-to-back launches),
  *   pairs_gram  block pairs that only formed their Gram matrix (converged),
  *   pairs_rot   block pairs that also rotated their vectors,
- *   pair_width  2b of the last call (the rows of each pair's Gram matrix),
+ *   pair_width  2b of the last call (the rows of each pair's Gram matrix;
+ *               0 after a batch that mixed both widths),
  *   flops       algorithmic flops of those pairs over their w valid vectors:
  *               2 w^2 L (Gram) + 2 w^2 (L + r) (rotation, when rotating),
  *   bytes       algorithmic bytes: w L e (Gram read) + 2 w (L + r) e

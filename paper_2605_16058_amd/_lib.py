@@ -14,6 +14,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libtsvdm.so")
 
 F64, F32, BF16, BF16X3 = 0, 1, 2, 3
+TILE_AUTO, TILE_64x64, TILE_128x32, TILE_256x16 = 0, 1, 2, 3
 STATUS = {
     0: "OK", -1: "E_ARG", -2: "E_SHAPE", -3: "E_NOT_ORTHO", -4: "E_WORKSPACE",
     -5: "E_NOCONV", -6: "E_NONFINITE", -7: "E_HIP", -8: "E_UNSUPPORTED", -9: "E_CAPACITY",
@@ -26,7 +27,7 @@ _SIGS = {
     "tsvdm_check_transform": (c_int, [_P, c_int64, c_double, POINTER(c_double)]),
     "tsvdm_transform_workspace_size": (c_int, [c_int64, POINTER(c_size_t)]),
     "tsvdm_transform": (c_int, [_P, c_int, _P, c_int, c_int64, c_int64, c_int64, _P, c_int,
-                                c_double, c_int, _P, c_size_t, _P]),
+                                c_double, c_int, c_int, _P, c_size_t, _P]),
     "tsvdm_slice_svd_workspace_size": (c_int, [c_int64, c_int64, c_int64, c_int, POINTER(c_size_t)]),
     "tsvdm_slice_svd": (c_int, [_P, c_int, c_int64, c_int64, c_int64, _P, _P, _P, c_int, c_int,
                                 c_double, c_int, _P, c_size_t, _P]),
@@ -38,7 +39,7 @@ _SIGS = {
                            _P, _P, _P, c_size_t, _P]),
     "tsvdm_reconstruct_workspace_size": (c_int, [c_int64, c_int64, c_int64, c_int, POINTER(c_size_t)]),
     "tsvdm_reconstruct": (c_int, [_P, _P, c_int, c_int64, c_int64, c_int64, _P, _P, c_int64, _P,
-                                  c_double, _P, c_int, c_int, _P, c_size_t, _P]),
+                                  c_double, _P, c_int, c_int, c_int, _P, c_size_t, _P]),
     "tsvdm_error_workspace_size": (c_int, [c_int64, POINTER(c_size_t)]),
     "tsvdm_error": (c_int, [_P, c_int, _P, c_int, c_int64, _P, _P, c_size_t, _P]),
     "tsvdm_backward_workspace_size": (c_int, [c_int64, c_int64, c_int64, c_int, POINTER(c_size_t)]),
@@ -58,10 +59,10 @@ class BatchItem(ctypes.Structure):
     _fields_ = [
         ("m", c_int64), ("p", c_int64), ("n", c_int64),
         ("A", c_void_p), ("M", c_void_p), ("inv_scale", c_double),
-        ("mode", c_int32), ("reserved", c_int32), ("k", c_int64), ("eps", c_double),
+        ("mode", c_int32), ("block", c_int32), ("k", c_int64), ("eps", c_double),
         ("rho", c_void_p), ("offsets", c_void_p), ("stats", c_void_p),
         ("U_pk", c_void_p), ("G_pk", c_void_p), ("S_pk", c_void_p), ("capacity", c_int64),
-        ("A_rec", c_void_p), ("err", c_void_p),
+        ("A_rec", c_void_p), ("err", c_void_p), ("ttm_tile", c_int32), ("reserved", c_int32),
     ]
 
 

@@ -113,7 +113,7 @@ int tsvdm_transform_workspace_size(int64_t n, size_t* bytes) {
 
 int tsvdm_transform(const void* X, int x_dtype, void* Y, int y_dtype, int64_t m, int64_t p,
                     int64_t n, const double* M, int transpose, double scale, int compute,
-                    void* ws, size_t ws_bytes, void* stream) {
+                    int tile, void* ws, size_t ws_bytes, void* stream) {
     clear_error();
     TSVDM_TRY(check_shape(m, p, n));
     TSVDM_REQUIRE(X && Y && M, TSVDM_E_ARG, "X, Y and M must be non-NULL");
@@ -126,8 +126,9 @@ int tsvdm_transform(const void* X, int x_dtype, void* Y, int y_dtype, int64_t m,
                   "BF16 compute writes F32 output only");
     TSVDM_REQUIRE(transpose == 0 || transpose == 1, TSVDM_E_ARG, "transpose must be 0 or 1");
     TSVDM_REQUIRE(std::isfinite(scale), TSVDM_E_ARG, "scale must be finite");
+    TSVDM_REQUIRE(tile >= 0 && tile <= 3, TSVDM_E_ARG, "tile must be 0, 1, 2 or 3");
     TSVDM_TRY(check_ws(ws, ws_bytes, ttm_workspace_bytes(n)));
-    return run_ttm(X, x_dtype, Y, y_dtype, m, p, n, M, transpose, scale, compute, ws,
+    return run_ttm(X, x_dtype, Y, y_dtype, m, p, n, M, transpose, scale, compute, tile, ws,
                    as_stream(stream));
 }
 
@@ -237,7 +238,7 @@ int tsvdm_reconstruct_workspace_size(int64_t m, int64_t p, int64_t n, int dtype,
 int tsvdm_reconstruct(const void* U_pk, const void* G_pk, int dtype, int64_t m, int64_t p,
                       int64_t n, const int32_t* rho, const int64_t* offsets, int64_t capacity,
                       const double* M, double scale, void* A_rec, int out_dtype, int compute,
-                      void* ws, size_t ws_bytes, void* stream) {
+                      int tile, void* ws, size_t ws_bytes, void* stream) {
     clear_error();
     TSVDM_TRY(check_shape(m, p, n));
     TSVDM_REQUIRE(rho && offsets && M && A_rec, TSVDM_E_ARG,
@@ -252,6 +253,7 @@ int tsvdm_reconstruct(const void* U_pk, const void* G_pk, int dtype, int64_t m, 
     TSVDM_REQUIRE(!(compute >= TSVDM_BF16 && out_dtype != TSVDM_F32), TSVDM_E_UNSUPPORTED,
                   "BF16 compute writes F32 output only");
     TSVDM_REQUIRE(std::isfinite(scale), TSVDM_E_ARG, "scale must be finite");
+    TSVDM_REQUIRE(tile >= 0 && tile <= 3, TSVDM_E_ARG, "tile must be 0, 1, 2 or 3");
     const size_t need = reconstruct_bytes(m, p, n, dtype);
     TSVDM_TRY(check_ws(ws, ws_bytes, need));
     Carver cv(ws);
@@ -259,7 +261,7 @@ int tsvdm_reconstruct(const void* U_pk, const void* G_pk, int dtype, int64_t m, 
     void* tws = cv.carve<char>(ttm_workspace_bytes(n));
     hipStream_t st = as_stream(stream);
     TSVDM_TRY(run_lowrank_gemm(U_pk, G_pk, dtype, m, p, n, rho, offsets, capacity, C, st));
-    return run_ttm(C, dtype, A_rec, out_dtype, m, p, n, M, 1, scale, compute, tws, st);
+    return run_ttm(C, dtype, A_rec, out_dtype, m, p, n, M, 1, scale, compute, tile, tws, st);
 }
 
 // ------------------------------------------------------------- error report

@@ -146,7 +146,7 @@ int run_backward(const void* A, int dt, int64_t m, int64_t p, int64_t n, const d
     const int64_t kk = k < geo.r ? k : geo.r;
     const int64_t tail = geo.r - kk;
     int rc;
-    rc = run_ttm(A, dt, L.Ahat, dt, m, p, n, M, 0, 1.0, dt, L.Mt, st);
+    rc = run_ttm(A, dt, L.Ahat, dt, m, p, n, M, 0, 1.0, dt, 0, L.Mt, st);
     if (rc) return rc;
     JacobiOpts o = jacobi_default_opts(m, p, dt);
     rc = run_jacobi(L.Ahat, dt, m, p, n, L.W, L.s2, status, o, L.jws, st);
@@ -166,7 +166,7 @@ int run_backward(const void* A, int dt, int64_t m, int64_t p, int64_t n, const d
     rc = run_lowrank_gemm(L.Upk, L.Gpk, dt, m, p, n, L.rho, L.offsets, tail * n, L.Rhat, st);
     if (rc) return rc;
     if (dA) {
-        rc = run_ttm(L.Rhat, dt, dA, dt, m, p, n, M, 1, 2.0 * g, dt, L.Mt, st);
+        rc = run_ttm(L.Rhat, dt, dA, dt, m, p, n, M, 1, 2.0 * g, dt, 0, L.Mt, st);
         if (rc) return rc;
     }
     if (dM) {

@@ -21,16 +21,19 @@ using namespace tsvdm;
 struct tsvdm_batch_plan_s {
     std::vector<tsvdm_batch_item> items;
     int in_dt = TSVDM_F32, dt = TSVDM_F32, ttm_compute = TSVDM_F32;
-    int nb2 = 32, max_sweeps = 40, max_steps = 0;
+    int max_sweeps = 40, max_steps = 0;
+    std::vector<int> nb2;  // pair width 2b per item
     // workspace layout (byte offsets)
     std::vector<size_t> off_ahat, off_w, off_s2, off_tf, off_tb, off_keys, off_stats, off_part,
         off_upk, off_gpk, off_spk;
     std::vector<int64_t> cap;  // effective capacity per item
     size_t off_ctl = 0, ws_total = 0;
     int64_t nslices = 0;
-    // host tables (addresses filled per workspace)
+    // host tables (addresses filled per workspace); transform tasks are
+    // sorted by tile shape and Jacobi tasks by pair width
     std::vector<int4> ttm_tasks, lr_tasks;
     std::vector<int2> jtasks;
+    int64_t ttm_group[3] = {0, 0, 0}, back_group[3] = {0, 0, 0}, jgroup[2] = {0, 0};
     // device tables
     char* dtab = nullptr;
     size_t dtab_bytes = 0;
@@ -69,6 +72,14 @@ int validate_item(const tsvdm_batch_item& it, int idx) {
         set_error(where + "reserved must be 0");
         return TSVDM_E_ARG;
     }
+    if (!(it.block == 0 || it.block == 16 || it.block == 32)) {
+        set_error(where + "block must be 0, 16 or 32");
+        return TSVDM_E_ARG;
+    }
+    if (it.ttm_tile < 0 || it.ttm_tile > 3) {
+        set_error(where + "ttm_tile must be 0, 1, 2 or 3");
+        return TSVDM_E_ARG;
+    }
     if (it.mode == 1) {
         if (it.k < 1) { set_error(where + "k must be >= 1"); return TSVDM_E_ARG; }
     } else if (it.mode == 2) {
@@ -94,7 +105,7 @@ int build_tables(tsvdm_batch_plan_s* P, char* ws) {
     std::vector<PackSlice> ps;
     std::vector<SelTensor> sel(cnt);
     std::vector<ErrJob> err;
-    std::vector<int4> back_tasks;
+    std::vector<int4> back_by[3];
     sl.reserve(P->nslices);
     ps.reserve(P->nslices);
     const size_t e = esz(P->dt);
@@ -110,7 +121,7 @@ int build_tables(tsvdm_batch_plan_s* P, char* ws) {
         void* upk = it.U_pk ? it.U_pk : ws + P->off_upk[t];
         void* gpk = it.U_pk ? it.G_pk : ws + P->off_gpk[t];
         void* spk = it.U_pk ? it.S_pk : ws + P->off_spk[t];
-        const int b = P->nb2 / 2;
+        const int b = P->nb2[t] / 2;
         const int nb = (int)((g.r + b - 1) / b);
         const int nbe = nb + (nb & 1);
         const double ueps = P->dt == TSVDM_F64 ? 1.1102230246251565e-16 : 5.9604644775390625e-08;
@@ -164,9 +175,10 @@ int build_tables(tsvdm_batch_plan_s* P, char* ws) {
             back.push_back(bk);
             int64_t n_rt;
             int n_ct;
-            ttm_tile_counts(it.m * it.p, it.n, &n_rt, &n_ct);
+            const int shp = ttm_resolve_tile(it.ttm_tile, it.n);
+            ttm_tile_counts(shp, it.m * it.p, it.n, &n_rt, &n_ct);
             for (int64_t rt = 0; rt < n_rt; ++rt)
-                for (int ct = 0; ct < n_ct; ++ct) back_tasks.push_back(int4{bi, (int)rt, ct, 0});
+                for (int ct = 0; ct < n_ct; ++ct) back_by[shp - 1].push_back(int4{bi, (int)rt, ct, 0});
             if (it.err) {
                 ErrJob j;
                 j.A = it.A;
@@ -177,6 +189,11 @@ int build_tables(tsvdm_batch_plan_s* P, char* ws) {
                 err.push_back(j);
             }
         }
+    }
+    std::vector<int4> back_tasks;
+    for (int q = 0; q < 3; ++q) {
+        P->back_group[q] = (int64_t)back_by[q].size();
+        back_tasks.insert(back_tasks.end(), back_by[q].begin(), back_by[q].end());
     }
     P->n_back_tasks = (int64_t)back_tasks.size();
     P->n_err = (int)err.size();
@@ -242,13 +259,13 @@ int run_stages(tsvdm_batch_plan_s* P, char* ws, int host_poll, int32_t* status, 
     TSVDM_LAUNCH_CHECK();
     // 1. transform
     rc = run_ttm_batch(reinterpret_cast<const TtmProblem*>(D + P->o_fwd), cnt,
-                       reinterpret_cast<const int4*>(D + P->o_ttm), (int64_t)P->ttm_tasks.size(),
+                       reinterpret_cast<const int4*>(D + P->o_ttm), P->ttm_group,
                        P->in_dt, P->dt, P->ttm_compute, 0, st);
     if (rc) return rc;
     // 2. slice SVDs
-    rc = run_jacobi_batch(P->dt, P->nb2, reinterpret_cast<const BatchSlice*>(D + P->o_sl),
-                          P->nslices, reinterpret_cast<const int2*>(D + P->o_jt),
-                          (int64_t)P->jtasks.size(), P->max_steps, host_poll, ctl_ws, jstatus, st);
+    rc = run_jacobi_batch(P->dt, reinterpret_cast<const BatchSlice*>(D + P->o_sl), P->nslices,
+                          reinterpret_cast<const int2*>(D + P->o_jt), P->jgroup, P->max_steps,
+                          host_poll, ctl_ws, jstatus, st);
     if (rc) return rc;
     // 3. ranks
     rc = run_select_batch(reinterpret_cast<const SelTensor*>(D + P->o_sel), cnt, st);
@@ -268,7 +285,7 @@ int run_stages(tsvdm_batch_plan_s* P, char* ws, int host_poll, int32_t* status, 
         int nback = 0;
         for (const auto& it : P->items) nback += it.A_rec ? 1 : 0;
         rc = run_ttm_batch(reinterpret_cast<const TtmProblem*>(D + P->o_back), nback,
-                           reinterpret_cast<const int4*>(D + P->o_bt), P->n_back_tasks, P->dt,
+                           reinterpret_cast<const int4*>(D + P->o_bt), P->back_group, P->dt,
                            P->dt, P->ttm_compute, 1, st);
         if (rc) return rc;
     }
@@ -312,7 +329,8 @@ int tsvdm_batch_plan_create(const tsvdm_batch_item* items, int32_t count, int in
     P->max_sweeps = max_sweeps ? max_sweeps : 40;
     int64_t rmax = 0;
     for (const auto& it : P->items) rmax = std::max(rmax, std::min(it.m, it.p));
-    P->nb2 = block ? 2 * block : (rmax >= 256 ? 64 : 32);
+    const int plan_block = block ? block : (rmax >= 256 ? 32 : 16);
+    for (const auto& it : P->items) P->nb2.push_back(2 * (it.block ? it.block : plan_block));
     const size_t e = esz(dtype);
     size_t wsoff = 0;
     auto take = [&](size_t bytes) {
@@ -322,6 +340,8 @@ int tsvdm_batch_plan_create(const tsvdm_batch_item* items, int32_t count, int in
         return o;
     };
     int max_rounds = 1;
+    std::vector<int4> ttm_by[3];
+    std::vector<int2> jt_by[2];
     for (int t = 0; t < count; ++t) {
         const tsvdm_batch_item& it = P->items[t];
         const SliceGeom g = slice_geom(it.m, it.p);
@@ -345,25 +365,35 @@ int tsvdm_batch_plan_create(const tsvdm_batch_item* items, int32_t count, int in
             P->off_spk.push_back(0);
         }
         P->cap.push_back(cap);
-        const int b = P->nb2 / 2;
+        const int b = P->nb2[t] / 2;
         const int nb = (int)((g.r + b - 1) / b);
         const int nbe = nb + (nb & 1);
         max_rounds = std::max(max_rounds, nbe - 1);
         // task tables
         int64_t n_rt;
         int n_ct;
-        ttm_tile_counts(it.m * it.p, it.n, &n_rt, &n_ct);
+        const int shp = ttm_resolve_tile(it.ttm_tile, it.n);
+        ttm_tile_counts(shp, it.m * it.p, it.n, &n_rt, &n_ct);
         for (int64_t rt = 0; rt < n_rt; ++rt)
-            for (int ct = 0; ct < n_ct; ++ct) P->ttm_tasks.push_back(int4{t, (int)rt, ct, 0});
+            for (int ct = 0; ct < n_ct; ++ct) ttm_by[shp - 1].push_back(int4{t, (int)rt, ct, 0});
         const int ta = (int)((it.m + 63) / 64), tb = (int)((it.p + 63) / 64);
+        std::vector<int2>& jt = jt_by[P->nb2[t] == 64 ? 1 : 0];
         for (int64_t i = 0; i < it.n; ++i) {
             const int s = (int)(P->nslices + i);
-            for (int k = 0; k < nbe / 2; ++k) P->jtasks.push_back(int2{s, k});
+            for (int k = 0; k < nbe / 2; ++k) jt.push_back(int2{s, k});
             if (it.A_rec)
                 for (int y = 0; y < tb; ++y)
                     for (int x = 0; x < ta; ++x) P->lr_tasks.push_back(int4{s, x, y, 0});
         }
         P->nslices += it.n;
+    }
+    for (int q = 0; q < 3; ++q) {
+        P->ttm_group[q] = (int64_t)ttm_by[q].size();
+        P->ttm_tasks.insert(P->ttm_tasks.end(), ttm_by[q].begin(), ttm_by[q].end());
+    }
+    for (int q = 0; q < 2; ++q) {
+        P->jgroup[q] = (int64_t)jt_by[q].size();
+        P->jtasks.insert(P->jtasks.end(), jt_by[q].begin(), jt_by[q].end());
     }
     P->max_steps = P->max_sweeps * max_rounds;
     if (P->max_steps > 100000) P->max_steps = 100000;

@@ -752,15 +752,17 @@ int jacobi_impl(T* A, int64_t m, int64_t p, int64_t n, T* W, double* s2, int32_t
     return TSVDM_OK;
 }
 
-template <class T, int NB2>
-int jacobi_batch_impl(const BatchSlice* sl, int64_t nslices, const int2* tasks, int64_t ntasks,
-                      int max_steps, int host_poll, void* ctl_ws, int32_t* status, hipStream_t st) {
+template <class T>
+int jacobi_batch_impl(const BatchSlice* sl, int64_t nslices, const int2* tasks,
+                      const int64_t* group, int max_steps, int host_poll, void* ctl_ws,
+                      int32_t* status, hipStream_t st) {
     Carver cv(ctl_ws);
     JacobiCtl* ctl = cv.carve<JacobiCtl>((size_t)nslices);
     int* remaining = cv.carve<int>((size_t)max_steps);
     unsigned long long* pair_counts = cv.carve<unsigned long long>(4);
-    TSVDM_REQUIRE(nslices < ((int64_t)1 << 31) && ntasks < ((int64_t)1 << 31), TSVDM_E_SHAPE,
-                  "batch too large for one launch");
+    TSVDM_REQUIRE(nslices < ((int64_t)1 << 31) && group[0] < ((int64_t)1 << 31) &&
+                      group[1] < ((int64_t)1 << 31),
+                  TSVDM_E_SHAPE, "batch too large for one launch");
     jacobi_init_batch<T><<<(unsigned)nslices, 256, 0, st>>>(sl, ctl, remaining, max_steps,
                                                            pair_counts, status);
     TSVDM_LAUNCH_CHECK();
@@ -774,9 +776,18 @@ int jacobi_batch_impl(const BatchSlice* sl, int64_t nslices, const int2* tasks, 
     int64_t launches = 0;
     const unsigned sblocks = (unsigned)((nslices + 255) / 256);
     for (int t = 0; t < max_steps; ++t) {
-        jacobi_round_batch<T, NB2><<<(unsigned)ntasks, 256, 0, st>>>(sl, tasks, t, ctl, pair_counts);
-        TSVDM_LAUNCH_CHECK();
-        ++launches;
+        // both pair widths see the same round counter t
+        if (group[0] > 0) {
+            jacobi_round_batch<T, 32><<<(unsigned)group[0], 256, 0, st>>>(sl, tasks, t, ctl, pair_counts);
+            TSVDM_LAUNCH_CHECK();
+            ++launches;
+        }
+        if (group[1] > 0) {
+            jacobi_round_batch<T, 64><<<(unsigned)group[1], 256, 0, st>>>(sl, tasks + group[0], t, ctl,
+                                                                         pair_counts);
+            TSVDM_LAUNCH_CHECK();
+            ++launches;
+        }
         jacobi_sweep_end_batch<<<sblocks, 256, 0, st>>>(sl, nslices, t, ctl, remaining + t);
         TSVDM_LAUNCH_CHECK();
         // poll every 4 steps: one synchronisation per few rounds
@@ -800,7 +811,9 @@ int jacobi_batch_impl(const BatchSlice* sl, int64_t nslices, const int2* tasks, 
         TSVDM_HIP_CHECK(hipEventElapsedTime(&ms, e0, e1));
         (void)hipEventDestroy(e0);
         (void)hipEventDestroy(e1);
-        stats_add_counters(launches, ms, pc, NB2);
+        // one pair width for the statistics only when the batch has one
+        const int width = group[0] > 0 && group[1] > 0 ? 0 : (group[1] > 0 ? 64 : 32);
+        stats_add_counters(launches, ms, pc, width);
     }
     return TSVDM_OK;
 }
@@ -815,17 +828,12 @@ size_t jacobi_batch_ctl_bytes(int64_t nslices, int max_steps) {
     return cv.total();
 }
 
-int run_jacobi_batch(int dt, int nb2, const BatchSlice* sl, int64_t nslices, const int2* tasks,
-                     int64_t ntasks, int max_steps, int host_poll, void* ctl_ws, int32_t* status,
-                     hipStream_t st) {
-    if (dt == TSVDM_F64) {
-        if (nb2 == 32)
-            return jacobi_batch_impl<double, 32>(sl, nslices, tasks, ntasks, max_steps, host_poll, ctl_ws, status, st);
-        return jacobi_batch_impl<double, 64>(sl, nslices, tasks, ntasks, max_steps, host_poll, ctl_ws, status, st);
-    }
-    if (nb2 == 32)
-        return jacobi_batch_impl<float, 32>(sl, nslices, tasks, ntasks, max_steps, host_poll, ctl_ws, status, st);
-    return jacobi_batch_impl<float, 64>(sl, nslices, tasks, ntasks, max_steps, host_poll, ctl_ws, status, st);
+int run_jacobi_batch(int dt, const BatchSlice* sl, int64_t nslices, const int2* tasks,
+                     const int64_t* group, int max_steps, int host_poll, void* ctl_ws,
+                     int32_t* status, hipStream_t st) {
+    if (dt == TSVDM_F64)
+        return jacobi_batch_impl<double>(sl, nslices, tasks, group, max_steps, host_poll, ctl_ws, status, st);
+    return jacobi_batch_impl<float>(sl, nslices, tasks, group, max_steps, host_poll, ctl_ws, status, st);
 }
 
 size_t jacobi_workspace_bytes(int64_t n) {

@@ -73,17 +73,21 @@ constexpr int ERR_SEGS = 64;
 int run_error_batch(int adt, int bdt, const ErrJob* jobs, int njobs, hipStream_t st);
 
 size_t jacobi_batch_ctl_bytes(int64_t nslices, int max_steps);
-int run_jacobi_batch(int dt, int nb2, const BatchSlice* sl, int64_t nslices, const int2* tasks,
-                     int64_t ntasks, int max_steps, int host_poll, void* ctl_ws,
+// tasks sorted by pair width: group[0] tasks of width 32, then group[1] of 64
+int run_jacobi_batch(int dt, const BatchSlice* sl, int64_t nslices, const int2* tasks,
+                     const int64_t* group, int max_steps, int host_poll, void* ctl_ws,
                      int32_t* status, hipStream_t st);
 
 // ---- transform (ttm.hip)
 size_t ttm_workspace_bytes(int64_t n);
-void ttm_tile_counts(int64_t R, int64_t n, int64_t* n_rt, int* n_ct);
-int run_ttm_batch(const TtmProblem* probs, int nprob, const int4* tasks, int64_t ntasks, int xdt,
-                  int ydt, int compute, int transpose, hipStream_t st);
+// tile: 1 = 64 rows x 64 slices, 2 = 128 x 32, 3 = 256 x 16, 0 = by n
+int ttm_resolve_tile(int tile, int64_t n);
+void ttm_tile_counts(int tile, int64_t R, int64_t n, int64_t* n_rt, int* n_ct);
+// tasks sorted by tile shape; group[s] = task count of shape s + 1
+int run_ttm_batch(const TtmProblem* probs, int nprob, const int4* tasks, const int64_t* group,
+                  int xdt, int ydt, int compute, int transpose, hipStream_t st);
 int run_ttm(const void* X, int xdt, void* Y, int ydt, int64_t m, int64_t p, int64_t n,
-            const double* M, int transpose, double scale, int compute, void* ws,
+            const double* M, int transpose, double scale, int compute, int tile, void* ws,
             hipStream_t st);
 
 // ---- slice SVD (jacobi.hip)

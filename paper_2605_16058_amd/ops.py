@@ -104,8 +104,9 @@ def device_matrix(M, device="cuda") -> torch.Tensor:
 # ---------------------------------------------------------------- entry points
 
 def tsvdm_transform(X, Mdev, transpose=False, scale=1.0, compute="f64", out_dtype=None,
-                    out=None, ws=None):
-    """Y = X x_3 (scale * op(M)); Mdev from device_matrix()."""
+                    out=None, ws=None, tile=0):
+    """Y = X x_3 (scale * op(M)); Mdev from device_matrix().  tile: 0 = by n,
+    1/2/3 = 64x64, 128x32, 256x16 (rows x slices)."""
     X = as_colmajor(X)
     m, p, n = X.shape
     odt = out_dtype or (torch.float64 if compute == "f64" else torch.float32)
@@ -113,7 +114,7 @@ def tsvdm_transform(X, Mdev, transpose=False, scale=1.0, compute="f64", out_dtyp
     w = _ws(ws)
     wp, wn = w.args(_lib.workspace_size("tsvdm_transform_workspace_size", n))
     _lib.call("tsvdm_transform", _ptr(X), _dt(X), _ptr(Y), _dt(Y), m, p, n, _ptr(Mdev),
-              int(bool(transpose)), float(scale), _COMPUTE[compute], wp, wn, _stream())
+              int(bool(transpose)), float(scale), _COMPUTE[compute], int(tile), wp, wn, _stream())
     return Y
 
 
@@ -171,7 +172,7 @@ def tsvdm_pack(A_hat, W, s2, rho, offsets, capacity, ws=None):
 
 
 def tsvdm_reconstruct(U_pk, G_pk, rho, offsets, capacity, Mdev, shape, scale=1.0,
-                      out_dtype=None, compute=None, out=None, ws=None):
+                      out_dtype=None, compute=None, out=None, ws=None, tile=0):
     m, p, n = shape
     dt = U_pk.dtype
     odt = out_dtype or dt
@@ -181,7 +182,7 @@ def tsvdm_reconstruct(U_pk, G_pk, rho, offsets, capacity, Mdev, shape, scale=1.0
     wp, wn = w.args(_lib.workspace_size("tsvdm_reconstruct_workspace_size", m, p, n, _DT[dt]))
     _lib.call("tsvdm_reconstruct", _ptr(U_pk), _ptr(G_pk), _DT[dt], m, p, n, _ptr(rho),
               _ptr(offsets), int(capacity), _ptr(Mdev), float(scale), _ptr(A_rec), _dt(A_rec),
-              _COMPUTE[comp], wp, wn, _stream())
+              _COMPUTE[comp], int(tile), wp, wn, _stream())
     return A_rec
 
 

@@ -54,7 +54,7 @@ class TSVDM:
 
     def __init__(self, shape, M, mode="II", k=None, eps=None, precision="f64",
                  block=0, max_sweeps=0, tol=0.0, host_poll=True, capacity="max",
-                 device="cuda", check_m=True):
+                 device="cuda", check_m=True, tile=0):
         self.m, self.p, self.n = (int(x) for x in shape)
         self.r = min(self.m, self.p)
         if mode not in ("I", "II"):
@@ -71,6 +71,7 @@ class TSVDM:
         self.c2 = ops.check_transform(M) if check_m else 1.0
         self.Mdev = ops.device_matrix(M, device)
         self.block, self.max_sweeps, self.tol, self.host_poll = block, max_sweeps, tol, host_poll
+        self.tile = tile
         self.capacity_mode = capacity
         self.device = device
         self.ws = ops.Workspace(device)
@@ -83,7 +84,8 @@ class TSVDM:
         out_dt = self.dtype
         # 1. transform (FP32 -> FP64 up-cast fused into the TTM load)
         A_hat = ops.tsvdm_transform(A, self.Mdev, transpose=False, scale=1.0,
-                                    compute=self.ttm_compute, out_dtype=self.dtype, ws=self.ws)
+                                    compute=self.ttm_compute, out_dtype=self.dtype, ws=self.ws,
+                                    tile=self.tile)
         # 2. slice SVDs
         W, s2, svd_status = ops.tsvdm_slice_svd(A_hat, self.block, self.max_sweeps, self.tol,
                                                 self.host_poll, ws=self.ws)
@@ -105,7 +107,7 @@ class TSVDM:
         back = self.ttm_compute if self.ttm_compute != "f64" else "f64"
         A_rec = ops.tsvdm_reconstruct(U_pk, G_pk, rho, offsets, cap, self.Mdev, (m, p, n),
                                       scale=1.0 / self.c2, out_dtype=out_dt, compute=back,
-                                      ws=self.ws)
+                                      ws=self.ws, tile=self.tile)
         # 6. error report
         err = ops.tsvdm_error(A, A_rec, ws=self.ws)
         return Result(A_rec, rho, offsets, U_pk, G_pk, S_pk, s2, stats, err, svd_status,
@@ -128,10 +130,13 @@ class BatchTSVDM:
     (see tsvdm_batch_plan_create); run() returns the device status word.
     keep_factors=True allocates packed factors per tensor (worst-case
     capacity) so they can be read back; otherwise they stay in the workspace.
+    blocks / tiles: optional per-tensor Jacobi block widths and transform
+    tile shapes (0 = the plan's choice), e.g. from autotune.tune_batch().
     """
 
     def __init__(self, tensors, Ms, modes, ks=None, epss=None, precision="f32", block=0,
-                 max_sweeps=0, keep_factors=False, reconstruct=True, device="cuda"):
+                 max_sweeps=0, keep_factors=False, reconstruct=True, device="cuda",
+                 blocks=None, tiles=None):
         import ctypes
 
         from . import _lib
@@ -142,6 +147,8 @@ class BatchTSVDM:
         cnt = len(tensors)
         ks = ks or [None] * cnt
         epss = epss or [None] * cnt
+        blocks = blocks or [0] * cnt
+        tiles = tiles or [0] * cnt
         self.tensors = [ops.as_colmajor(t) for t in tensors]
         in_dt = self.tensors[0].dtype
         if any(t.dtype != in_dt for t in self.tensors):
@@ -165,6 +172,8 @@ class BatchTSVDM:
             it.M = Md.data_ptr()
             it.inv_scale = 1.0 / c2
             it.mode = 1 if mode == "I" else 2
+            it.block = int(blocks[t])
+            it.ttm_tile = int(tiles[t])
             it.reserved = 0
             it.k = int(ks[t] or 1)
             it.eps = float(epss[t] or 0.5)

@@ -85,7 +85,7 @@ def test_workspace_queries(lib):
 
 
 def test_transform_validation(lib):
-    ok = (DUMMY, 1, c_void_p(512), 1, 8, 8, 4, DUMMY, 0, 1.0, 0, DUMMY, 1 << 20, None)
+    ok = (DUMMY, 1, c_void_p(512), 1, 8, 8, 4, DUMMY, 0, 1.0, 0, 0, DUMMY, 1 << 20, None)
     # null input
     a = list(ok); a[0] = None
     assert lib.tsvdm_transform(*a) == -1
@@ -100,8 +100,13 @@ def test_transform_validation(lib):
     # aliasing
     a = list(ok); a[2] = a[0]
     assert lib.tsvdm_transform(*a) == -1
+    # unknown tile shape
+    for tile in (-1, 4):
+        a = list(ok); a[11] = tile
+        assert lib.tsvdm_transform(*a) == -1
+        assert b"tile" in lib.tsvdm_last_error()
     # workspace too small
-    a = list(ok); a[12] = 8
+    a = list(ok); a[13] = 8
     assert lib.tsvdm_transform(*a) == -4
     assert b"workspace" in lib.tsvdm_last_error()
 
@@ -135,12 +140,97 @@ def test_pack_reconstruct_error_backward_validation(lib):
     assert lib.tsvdm_pack(*p) == -1
     p[9] = 4; p[3] = 5
     assert lib.tsvdm_pack(*p) == -8
-    rc = [DUMMY, DUMMY, 0, 8, 6, 3, DUMMY, DUMMY, 4, None, 1.0, DUMMY, 0, 0, DUMMY, 1 << 20, None]
+    rc = [DUMMY, DUMMY, 0, 8, 6, 3, DUMMY, DUMMY, 4, None, 1.0, DUMMY, 0, 0, 0, DUMMY, 1 << 20, None]
     assert lib.tsvdm_reconstruct(*rc) == -1
     rc[9] = DUMMY; rc[10] = float("inf")
+    assert lib.tsvdm_reconstruct(*rc) == -1
+    rc[10] = 1.0; rc[14] = 9
     assert lib.tsvdm_reconstruct(*rc) == -1
     assert lib.tsvdm_error(DUMMY, 0, DUMMY, 0, 0, DUMMY, DUMMY, 1 << 20, None) == -2
     bw = [DUMMY, 1, 8, 6, 3, DUMMY, 0, 1.0, None, None, DUMMY, DUMMY, DUMMY, 1 << 30, None]
     assert lib.tsvdm_backward(*bw) == -1
     bw[6] = 2; bw[14 - 1] = 1
     assert lib.tsvdm_backward(*bw) == -4
+
+
+def _header_struct_fields(name):
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    body = re.search(r"typedef struct \{(.*?)\}\s*" + name + r"\s*;", src, flags=re.S).group(1)
+    fields = []
+    for decl in body.split(";"):
+        decl = decl.strip()
+        if not decl:
+            continue
+        names = decl.split(None, 1)[1] if not decl.startswith("const") else decl.split(None, 2)[2]
+        for nm in names.split(","):
+            fields.append(nm.strip().lstrip("*").strip())
+    return fields
+
+
+def test_batch_item_layout_matches_header(tmp_path):
+    """Field names and every offset agree with what a C compiler makes of the header."""
+    import shutil
+    import subprocess
+    from paper_2605_16058_amd import _lib
+    names = [f for f, _ in _lib.BatchItem._fields_]
+    assert _header_struct_fields("tsvdm_batch_item") == names
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    src = tmp_path / "layout.c"
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "tsvdm.h"', "int main(void) {",
+             '  printf("%zu\\n", sizeof(tsvdm_batch_item));']
+    lines += [f'  printf("%zu\\n", offsetof(tsvdm_batch_item, {f}));' for f in names]
+    lines += ["  return 0;", "}"]
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run([cc, "-std=c99", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)],
+                   check=True)
+    got = [int(x) for x in subprocess.run([str(exe)], check=True, capture_output=True,
+                                          text=True).stdout.split()]
+    assert got[0] == ctypes.sizeof(_lib.BatchItem)
+    assert got[1:] == [getattr(_lib.BatchItem, f).offset for f in names]
+
+
+def _item(m=40, p=30, n=6, mode=2):
+    from paper_2605_16058_amd import _lib
+    it = _lib.BatchItem()
+    it.m, it.p, it.n = m, p, n
+    it.A = it.M = it.rho = it.offsets = 256
+    it.inv_scale = 1.0
+    it.mode = mode
+    it.k = 4
+    it.eps = 0.1
+    return it
+
+
+def test_batch_plan_validation_and_layout(lib):
+    """Plan creation only validates and lays out host tables: no device call."""
+    from paper_2605_16058_amd import _lib
+
+    def create(items, block=0):
+        arr = (_lib.BatchItem * len(items))(*items)
+        plan, wsb = c_void_p(), c_size_t(0)
+        rc = lib.tsvdm_batch_plan_create(ctypes.cast(arr, c_void_p), len(items), 1, 1, 1, block, 0,
+                                         byref(plan), byref(wsb))
+        if rc == 0:
+            assert wsb.value > 0
+            assert lib.tsvdm_batch_plan_destroy(plan) == 0
+        return rc, wsb.value
+
+    assert create([_item(), _item(300, 280, 12, 1)])[0] == 0
+    # per-item widths and tiles
+    a, b = _item(), _item(300, 280, 12, 1)
+    a.block, b.block, a.ttm_tile, b.ttm_tile = 16, 32, 3, 1
+    assert create([a, b])[0] == 0
+    for field, bad in (("block", 8), ("block", 64), ("ttm_tile", 4), ("ttm_tile", -1), ("reserved", 1)):
+        it = _item()
+        setattr(it, field, bad)
+        assert create([it])[0] == -1, field
+        assert field.encode() in lib.tsvdm_last_error()
+    assert create([_item()], block=8)[0] == -1
+    bad = _item(); bad.eps = 1.0
+    assert create([bad])[0] == -1
+    bad = _item(); bad.n = 0
+    assert create([bad])[0] == -2
