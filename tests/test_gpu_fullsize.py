@@ -1,0 +1,247 @@
+"""GPU parity at the full benchmark sizes, in the configuration bench.py times.
+
+The oracle cannot run the whole 512x1024x256, 2048x1024x256 or 512-tensor
+workloads in test time, so each test checks
+  * sampled outputs the oracle computes one by one: the singular values of
+    sampled slices (transform of just those slices, LAPACK values), the
+    best rank-rho approximation of those slices (Eckart-Young tail energy),
+    every output of sampled tensors of the batch;
+  * properties that hold at any size: ranks from the GPU's own squares
+    through the oracle's exact selection (bit-exact), the discarded energy
+    and total the GPU reports against the oracle's exact sums of the same
+    squares, the measured error against the predicted one and against eps,
+    the mixed-precision reconstruction against the FP64 one.
+Bounds are those of the small parity tests (FP64: 1e-12 sigma_max for
+values, 1e-10 for reconstructions; FP32: 2e-5 sigma_max, 3e-5 relative).
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle as O
+import synth
+
+pytestmark = [pytest.mark.gpu, pytest.mark.slow]
+
+torch = pytest.importorskip("torch")
+
+
+def to_dev(A, dtype=torch.float32):
+    out = torch.empty((A.shape[2], A.shape[1], A.shape[0]), dtype=dtype, device="cuda").permute(2, 1, 0)
+    out.copy_(torch.from_numpy(np.asfortranarray(A)).to(dtype))
+    return out
+
+
+def sampled_slices(A, M, idx):
+    """A x_3 M restricted to the slices idx (the oracle's mode-3 product with the rows idx of M)."""
+    return O.mode3(A, np.asarray(M, np.float64)[idx, :])
+
+
+def packed_slice(res, i, m, p):
+    """U_i G_i of slice i from the packed factors (M domain)."""
+    k = int(res.rho[i].item())
+    o = int(res.offsets[i].item())
+    if k == 0:
+        return np.zeros((m, p))
+    U = res.U_pk[m * o: m * (o + k)].double().cpu().numpy().reshape(k, m).T
+    G = res.G_pk[p * o: p * (o + k)].double().cpu().numpy().reshape(p, k).T
+    return U @ G
+
+
+def gpu_sampled_slices(Ad, M, idx, precision):
+    """The GPU transform of the run's own configuration, restricted to idx."""
+    from paper_2605_16058_amd import ops
+    from paper_2605_16058_amd.pipeline import PRECISIONS
+    compute, dtype = PRECISIONS[precision]
+    Y = ops.tsvdm_transform(Ad, ops.device_matrix(M), compute=compute, out_dtype=dtype)
+    out = np.stack([Y[:, :, i].double().cpu().numpy() for i in idx], axis=2)
+    del Y
+    return out
+
+
+def check_single(res, A64, Ad, M, eps, idx, precision):
+    """Sampled-slice and global checks of one t-SVDM-II result.
+
+    Singular values obey Weyl's bound: |sigma_gpu - sigma_oracle| <= e_i + c
+    sigma_max, with e_i = ||A-hat_i(GPU transform) - A-hat_i(oracle)||_F the
+    measured transform error of slice i and c the Jacobi bound of the slice
+    SVD (FP64 1e-12, FP32 2e-5).  The packed rank-rho_i factors are a best
+    approximation: their tail is at least the oracle's (Eckart-Young) and at
+    most the oracle's plus e_i + c ||A-hat_i||_F."""
+    m, p, n = A64.shape
+    fp64 = precision == "f64"
+    c = 1e-12 if fp64 else 2e-5
+    assert int(res.svd_status.item()) == 0 and int(res.pack_status.item()) == 0
+    s2 = res.s2.double().cpu().numpy()               # (n, r)
+    rho = res.rho.cpu().numpy()
+    # 1. ranks: the GPU's squares through the oracle's exact selection
+    rho_o, info = O.ranks_tolerance(s2.T, eps, squared=True)
+    assert np.array_equal(rho, rho_o)
+    st = res.stats.cpu().numpy()                     # tau, discarded, total, J
+    assert st[0] == info["tau"] and int(st[3]) == info["J"]
+    assert abs(st[1] - info["discarded"]) <= 1e-15 * info["total"]
+    assert abs(st[2] - info["total"]) <= 1e-15 * info["total"]
+    # 2. the measured error against the predicted one (Eckart-Young) and eps
+    rel_e = res.rel_error()
+    pred = math.sqrt(info["discarded"] / info["total"])
+    assert rel_e < eps
+    assert abs(rel_e - pred) <= (1e-9 if fp64 else 1e-2) * pred
+    # 3. sampled slices against the oracle
+    Ah = sampled_slices(A64, M, idx)
+    Ag = gpu_sampled_slices(Ad, M, idx, precision)
+    for j, i in enumerate(idx):
+        e_i = float(np.linalg.norm((Ag[:, :, j] - Ah[:, :, j]).ravel()))
+        nrm = float(np.linalg.norm(Ah[:, :, j].ravel()))
+        so = np.linalg.svd(Ah[:, :, j], compute_uv=False)
+        sg = np.sqrt(np.sort(np.maximum(s2[i], 0.0))[::-1])
+        assert np.max(np.abs(sg - so)) <= e_i + c * so[0], (i, np.max(np.abs(sg - so)), e_i)
+        C = packed_slice(res, i, m, p)
+        k = int(rho[i])
+        tail_o = math.sqrt(float(np.sum(so[k:] ** 2)))
+        tail_g = float(np.linalg.norm((Ah[:, :, j] - C).ravel()))
+        assert tail_g >= tail_o * (1 - 1e-12) - 1e-14 * nrm, i
+        assert tail_g <= tail_o + e_i + c * nrm, (i, tail_g, tail_o, e_i)
+    return rho, info
+
+
+@pytest.fixture(scope="module")
+def climate():
+    w = synth.workload("climate")
+    return w.A, w.M, w.eps
+
+
+def test_climate_full_size(climate):
+    """512x1024x256 climate-like, DCT-II, t-SVDM-II tol 1e-3: FP32 mixed and FP64."""
+    from paper_2605_16058_amd import ops
+    from paper_2605_16058_amd.pipeline import TSVDM
+    A, M, eps = climate
+    Ad = to_dev(A)
+    A64 = A.astype(np.float64)
+    idx = [0, 1, 2, 100, 255]
+    out = {}
+    for prec in ("f32", "f64"):
+        op = TSVDM(A.shape, M, mode="II", eps=eps, precision=prec)
+        res = op(Ad)
+        torch.cuda.synchronize()
+        rho, info = check_single(res, A64, Ad, M, eps, idx, prec)
+        out[prec] = (res, rho, info)
+        print(f"{prec}: sum rho {int(rho.sum())}, rel error {res.rel_error():.6e}")
+    r64, rho64, info64 = out["f64"]
+    r32, rho32, _ = out["f32"]
+    # FP64 ranks equal the oracle's whenever the threshold margin of the
+    # squares exceeds their error bound (1e-12 relative, checked on samples)
+    v = np.sort(r64.s2.double().cpu().numpy().ravel())
+    tau = info64["tau"]
+    lo, hi = v[v <= tau].max(), v[v > tau].min()
+    margin = (hi - lo) / lo
+    print(f"threshold margin {margin:.3e}, sum |rho32 - rho64| = {int(np.abs(rho32 - rho64).sum())}")
+    d = ops.tsvdm_error(r64.A_rec, r32.A_rec).double().cpu().numpy()
+    nA = float(r64.err[1].cpu())
+    if np.array_equal(rho32, rho64):
+        assert math.sqrt(d[0] / nA) <= 3e-5
+
+
+@pytest.fixture(scope="module")
+def ragged():
+    return synth.workload("ragged")
+
+
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+def test_ragged_batch_full_size(ragged, precision):
+    """All 512 tensors in one plan; every mode-II tensor's error below its
+    tolerance, 8 evenly spaced tensors checked in full against the oracle."""
+    from paper_2605_16058_amd.pipeline import BatchTSVDM
+    w = ragged
+    Ts = [to_dev(A) for A in w.A]
+    b = BatchTSVDM(Ts, w.M, w.mode, ks=w.k, epss=w.eps, precision=precision, keep_factors=False)
+    st = b.run()
+    torch.cuda.synchronize()
+    assert int(st.item()) == 0
+    errs = b.rel_errors()
+    for t, md in enumerate(w.mode):
+        if md == "II":
+            assert errs[t] < w.eps[t], t
+    fp64 = precision == "f64"
+    for t in range(0, len(Ts), len(Ts) // 8):
+        A64 = w.A[t].astype(np.float64)
+        ref = O.tsvdm_i(A64, w.M[t], w.k[t]) if w.mode[t] == "I" else O.tsvdm_ii(A64, w.M[t], w.eps[t])
+        rho = b.rho[t].cpu().numpy()
+        # the error against A is the oracle's (Eckart-Young: the tail energy)
+        assert abs(errs[t] - ref["rel_error"]) <= (1e-9 if fp64 else 1e-3) * ref["rel_error"], t
+        if not fp64:
+            continue
+        S = ref["S"]
+        if w.mode[t] == "II":
+            v = np.sort((S ** 2).ravel())
+            tau = ref["info"]["tau"]
+            if np.isfinite(tau) and np.any(v > tau):
+                margin = (v[v > tau].min() - v[v <= tau].max()) / v[v <= tau].max()
+                if margin <= 1e-10:
+                    continue
+        assert np.array_equal(rho, ref["rho"]), t
+        # the truncation is unique when every slice has a gap at its rank
+        gaps = [(S[k - 1, i] - S[k, i]) / S[0, i] for i, k in enumerate(rho) if 0 < k < S.shape[0]]
+        if not gaps or min(gaps) > 1e-6:
+            Arec = b.A_rec[t].double().cpu().numpy()
+            d = np.linalg.norm((Arec - ref["A_rec"]).ravel()) / np.linalg.norm(A64.ravel())
+            assert d <= 1e-10, (t, d)
+
+
+@pytest.fixture(scope="module")
+def turbulence():
+    w = synth.workload("turbulence")
+    return w.A, w.M, w.eps
+
+
+def test_turbulence_full_size(turbulence):
+    """2048x1024x256 turbulence-like, Haar M, t-SVDM-II tol 1e-2 with the
+    transform in FP64, FP32, split BF16 and plain BF16."""
+    from paper_2605_16058_amd import ops
+    from paper_2605_16058_amd.pipeline import TSVDM
+    A, M, eps = turbulence
+    Ad = to_dev(A)
+    A64 = A.astype(np.float64)
+    idx = [0, 130]
+    ref = None
+    for prec, bound in (("f64", None), ("f32", 3e-5), ("bf16x3", 1e-4), ("bf16", None)):
+        op = TSVDM(A.shape, M, mode="II", eps=eps, precision=prec)
+        res = op(Ad)
+        torch.cuda.synchronize()
+        assert int(res.svd_status.item()) == 0
+        s2 = res.s2.double().cpu().numpy()
+        rho_o, _ = O.ranks_tolerance(s2.T, eps, squared=True)
+        assert np.array_equal(res.rho.cpu().numpy(), rho_o)
+        if prec in ("f64", "f32"):
+            check_single(res, A64, Ad, M, eps, idx, prec)
+        if ref is None:
+            ref = res
+            continue
+        d = ops.tsvdm_error(ref.A_rec, res.A_rec).double().cpu().numpy()
+        diff = math.sqrt(d[0] / float(ref.err[1].cpu()))
+        drho = int((res.rho.long() - ref.rho.long()).abs().sum())
+        print(f"{prec}: |A_rec - A_rec_f64| / |A| = {diff:.3e}, sum |drho| = {drho}, "
+              f"rel error {res.rel_error():.6e}")
+        if bound is not None:
+            assert diff <= bound or drho > 0
+            assert res.rel_error() < eps * (1 + bound)
+        del res, op
+        torch.cuda.empty_cache()
+
+
+def test_cayley_full_size_gradient():
+    """256x256x64, k = 16, M = Cayley(K0): loss and both gradients against the
+    oracle's, computed in full."""
+    from paper_2605_16058_amd import ops
+    w = synth.workload("cayley")
+    A64 = w.A.astype(np.float64)
+    M = O.cayley(w.extra["K0"])
+    L_o, dA_o, GM_o = O.trunc_loss_grad(A64, M, w.k)
+    for dtype, bound in ((torch.float64, 1e-9), (torch.float32, 2e-4)):
+        loss, dA, dM, st = ops.tsvdm_backward(to_dev(w.A, dtype), ops.device_matrix(M), w.k, g=1.0)
+        torch.cuda.synchronize()
+        assert int(st.item()) == 0
+        assert abs(float(loss.item()) - L_o) <= bound * L_o
+        dAg = dA.double().cpu().numpy()
+        assert np.linalg.norm((dAg - dA_o).ravel()) <= bound * 10 * np.linalg.norm(dA_o.ravel())
+        assert np.linalg.norm(dM.cpu().numpy() - GM_o) <= bound * 10 * np.linalg.norm(GM_o)
