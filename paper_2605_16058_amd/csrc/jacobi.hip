@@ -73,6 +73,94 @@ __device__ __forceinline__ int circle_player(int seat, int round, int N) {
     return seat == 0 ? 0 : ((seat - 1 + round) % (N - 1)) + 1;
 }
 
+// Inner sweep orderings over the NB2 vectors of a block pair, in seat
+// order: pair k always sits on seats (k, partner_seat(k)) and the vectors
+// move between seats after every step.  Full sweep: circle tournament, seat
+// k meets seat NB2-1-k, seat 0 fixed, the others advance one seat (the
+// vector on seat j >= 2 moves to j-1, seat 1 to NB2-1).  Cross sweep (both
+// blocks already orthogonal inside): seat k (vector k of the first block)
+// meets seat b+k, the second block's vectors advance cyclically.
+template <int NB2>
+__device__ __forceinline__ int partner_seat(bool cross, int k) {
+    return cross ? NB2 / 2 + k : NB2 - 1 - k;
+}
+// seat after one step of the vector on seat j
+template <int NB2>
+__device__ __forceinline__ int next_seat(bool cross, int j) {
+    constexpr int B = NB2 / 2;
+    if (cross) return j < B ? j : (j == B ? NB2 - 1 : j - 1);
+    return j == 0 ? 0 : (j == 1 ? NB2 - 1 : j - 1);
+}
+// seat one step earlier of the vector on seat j
+template <int NB2>
+__device__ __forceinline__ int prev_seat(bool cross, int j) {
+    constexpr int B = NB2 / 2;
+    if (cross) return j < B ? j : (j == NB2 - 1 ? B : j + 1);
+    return j == 0 ? 0 : (j == NB2 - 1 ? 1 : j + 1);
+}
+// pair on seat j and whether j is its first seat
+template <int NB2>
+__device__ __forceinline__ int seat_pair(bool cross, int j, bool& first) {
+    constexpr int B = NB2 / 2;
+    first = j < B;
+    return first ? j : (cross ? j - B : NB2 - 1 - j);
+}
+// vector on seat j at step `step`
+template <int NB2>
+__device__ __forceinline__ int seat_vector(bool cross, int j, int step) {
+    constexpr int B = NB2 / 2;
+    if (cross) return j < B ? j : B + (j - B + step) % B;
+    return circle_player(j, step, NB2);
+}
+
+// FP64 reciprocal and reciprocal square root: the hardware estimates
+// refined by two Newton steps each (quadratic convergence from about 23
+// correct bits), for arguments in [1, 4] where no scaling is needed.
+__device__ __forceinline__ double rcp_nr(double x) {
+    double y = __builtin_amdgcn_rcp(x);
+    y = fma(fma(-x, y, 1.0), y, y);
+    return fma(fma(-x, y, 1.0), y, y);
+}
+__device__ __forceinline__ double rsq_nr(double x) {
+    const double h = 0.5 * x;
+    double y = __builtin_amdgcn_rsq(x);
+    y = y * fma(-h * y, y, 1.5);
+    return y * fma(-h * y, y, 1.5);
+}
+
+// Rotation (c, s) annihilating apq of the symmetric 2x2 [app apq; apq aqq]
+// in FP64 (the classical Jacobi angle, tan 2theta = 2 apq / (aqq - app),
+// smaller root): with d = aqq - app and e = 2 apq scaled by max(|d|, |e|),
+//   t = sign(d) e / (|d| + sqrt(d^2 + e^2)),  c = 1 / sqrt(1 + t^2),  s = c t,
+// so every square root and reciprocal has an argument in [1, 2] and
+// c^2 + s^2 = 1 to rounding.  new_p = c p - s q, new_q = s p + c q.
+// Identity when invalid or when |apq| <= 1e-18 sqrt(|app aqq|).
+__device__ __forceinline__ void jacobi_angle(double app, double aqq, double apq, bool valid,
+                                             double& c, double& s) {
+    c = 1.0;
+    s = 0.0;
+    // the threshold needs no accuracy: unrefined hardware square roots
+    const double a = fmax(fabs(app), 1e-300), b = fmax(fabs(aqq), 1e-300);
+    const double thr = 1e-18 * (a * __builtin_amdgcn_rsq(a)) * (b * __builtin_amdgcn_rsq(b));
+    if (valid && fabs(apq) > thr) {
+        const double d = aqq - app, e = 2.0 * apq;
+        const double inv = rcp_nr(fmax(fabs(d), fabs(e)));
+        const double dn = d * inv, en = e * inv;     // max(|dn|, |en|) = 1
+        const double q2 = fma(dn, dn, en * en);      // in [1, 2]
+        const double h = q2 * rsq_nr(q2);
+        const double t = copysign(1.0, dn) * en * rcp_nr(fabs(dn) + h);
+        c = rsq_nr(fma(t, t, 1.0));
+        s = c * t;
+    }
+}
+
+// Packed symmetric storage of the pair Gram matrix: (a, b) and (b, a) share
+// one slot.
+__device__ __forceinline__ int sym_idx(int a, int b) {
+    const int lo = a < b ? a : b, hi = a < b ? b : a;
+    return hi * (hi + 1) / 2 + lo;
+}
+
 template <class T>
 __global__ void jacobi_init(T* __restrict__ W, int64_t r, int64_t n, JacobiCtl* __restrict__ ctl,
                             int* __restrict__ remaining, int max_sweeps,
@@ -103,7 +191,11 @@ __global__ void jacobi_init(T* __restrict__ W, int64_t r, int64_t n, JacobiCtl* 
 }
 
 // Chunk geometry: every staged chunk is 16 KB (NB2 vectors x TC elements),
-// i.e. four 16-byte vector loads per thread.
+// i.e. four 16-byte vector loads per thread.  The pair Gram matrix H lives
+// in the staging region as two packed symmetric FP64 buffers (one per
+// parity of the inner step); Q is stored transposed (row a = column a of Q)
+// with the 16-byte groups of row a XOR-swizzled by a, so that row accesses
+// are 16-byte vectors and column reads of 16 rows hit distinct banks.
 template <class T, int NB2>
 struct RoundCfg {
     static constexpr int VW = 16 / sizeof(T);                  // elements per 16-byte access
@@ -111,12 +203,16 @@ struct RoundCfg {
     static constexpr int LDP = TC + VW;                        // padded LDS row (16-byte aligned)
     static constexpr int NV = NB2 * TC / VW / 256;             // vector accesses per thread
     static constexpr int NT = NB2 / 16;                        // 16x16 tiles per dimension
-    static constexpr int HP = NB2 + 1;
+    static constexpr int NPH = NB2 / 2;                        // rotations per inner step
+    static constexpr int NH = NB2 * (NB2 + 1) / 2;             // packed symmetric H
+    static constexpr int SWM = (NB2 / VW < 16 ? NB2 / VW : 16) - 1;  // Q swizzle mask
     static constexpr size_t ts_bytes = sizeof(T) * NB2 * LDP;
-    static constexpr size_t hs_bytes = sizeof(double) * NB2 * HP;
+    static constexpr size_t hs_bytes = sizeof(double) * 2 * NH;
     static constexpr size_t r1 = (2 * ts_bytes > hs_bytes) ? 2 * ts_bytes : hs_bytes;
-    static constexpr size_t q_bytes = sizeof(T) * NB2 * HP;
+    static constexpr size_t q_bytes = sizeof(T) * NB2 * NB2;
     static constexpr size_t total = r1 + q_bytes;
+    // Q^T[a][c] = Q[c][a]
+    static __device__ __forceinline__ int q_idx(int a, int c) { return a * NB2 + (c ^ ((a & SWM) * VW)); }
 };
 
 // One block pair (pair k of round rnd) of one slice: Ab / Wb are the slice
@@ -126,8 +222,7 @@ struct RoundCfg {
 template <class T, int NB2>
 struct RoundShared {
     __align__(16) char smem[RoundCfg<T, NB2>::total];
-    double rot_c[NB2 / 2], rot_s[NB2 / 2];
-    int rot_p[NB2 / 2], rot_q[NB2 / 2];
+    double2 rot_cs[2][NB2 / 2];   // (c, s) of each rotation, per parity of the inner step
     double red[4], redw[4];
     int flag_nf;
 };
@@ -141,21 +236,17 @@ __device__ __forceinline__ void round_body(RoundShared<T, NB2>& sh, T* __restric
     typedef RoundCfg<T, NB2> C;
     typedef typename Acc<T>::type AccT;
     constexpr int B = NB2 / 2, VW = C::VW, TC = C::TC, LDP = C::LDP, NV = C::NV;
-    constexpr int NT = C::NT, HP = C::HP;
+    constexpr int NT = C::NT, NH = C::NH;
 
     char* smem = sh.smem;
-    double* rot_c = sh.rot_c;
-    double* rot_s = sh.rot_s;
-    int* rot_p = sh.rot_p;
-    int* rot_q = sh.rot_q;
     double* red = sh.red;
     double* redw = sh.redw;
     int& flag_nf = sh.flag_nf;
 
     T* Ts = reinterpret_cast<T*>(smem);                           // [NB2][LDP] staged input
     T* Ts2 = reinterpret_cast<T*>(smem + C::ts_bytes);            // [NB2][LDP] staged output
-    double* Hs = reinterpret_cast<double*>(smem);                 // [NB2][HP]  (phase 2 only)
-    T* Qs = reinterpret_cast<T*>(smem + C::r1);                   // [NB2][HP]  Q[c][a]
+    double* H0 = reinterpret_cast<double*>(smem);                 // [2][NH] packed H (phase 2)
+    T* Qs = reinterpret_cast<T*>(smem + C::r1);                   // [NB2][NB2] Q^T, swizzled
 
     const int I = circle_player(k, rnd, nbe);
     const int J = circle_player(nbe - 1 - k, rnd, nbe);
@@ -298,8 +389,10 @@ __device__ __forceinline__ void round_body(RoundShared<T, NB2>& sh, T* __restric
     for (int j = 0; j < TPW; ++j) {
         const int q = wave * TPW + j, tr = q / NT, tc = q % NT;
 #pragma unroll
-        for (int v = 0; v < 4; ++v)
-            Hs[(tr * 16 + mfma_row<T>(lg, v)) * HP + tc * 16 + lr] = (double)hacc[j][v];
+        for (int v = 0; v < 4; ++v) {
+            const int a = tr * 16 + mfma_row<T>(lg, v), c = tc * 16 + lr;
+            if (a <= c) H0[sym_idx(a, c)] = (double)hacc[j][v];
+        }
     }
     if (tid == 0) flag_nf = 0;
     __syncthreads();
@@ -309,10 +402,11 @@ __device__ __forceinline__ void round_body(RoundShared<T, NB2>& sh, T* __restric
     double mcx = 0.0, mcw = 0.0;
     for (int e = tid; e < NB2 * NB2; e += 256) {
         const int a = e / NB2, c = e % NB2;
-        const double h = Hs[a * HP + c];
+        if (a > c) continue;
+        const double h = H0[sym_idx(a, c)];
         if (!isfinite(h)) flag_nf = 1;
         if (a < c && gidx(a) < r && gidx(c) < r) {
-            const double d = fabs(Hs[a * HP + a]) * fabs(Hs[c * HP + c]);
+            const double d = fabs(H0[sym_idx(a, a)]) * fabs(H0[sym_idx(c, c)]);
             if (d > 0.0) {
                 const double cs = fabs(h) / sqrt(d);
                 if ((a < B) != (c < B)) mcx = fmax(mcx, cs);
@@ -355,97 +449,146 @@ __device__ __forceinline__ void round_body(RoundShared<T, NB2>& sh, T* __restric
     }
     if (!rotate) return;  // uniform across the block
 
-    // prefetch the first update chunk; its latency hides behind phase 2
-    gload(Ab, g.vs, g.es, ROWS, vec_a != 0, 0, L);
-
     // ---------------- phase 2: one cyclic Jacobi sweep on H (FP64 angles)
+    // H is kept in seat order (pair k on seats (k, partner_seat(k)) at every
+    // step), double-buffered: step s reads buffer s&1 and writes
+    // H_{s+1} = J_s^T H_s J_s into the other buffer, each element already on
+    // the seats its vectors take at step s+1.  Every LDS index of the sweep is
+    // therefore fixed per thread, and one barrier per step suffices.  The last
+    // NPH threads compute the rotations of step s+1 meanwhile: the three
+    // entries of H_{s+1} they need follow from H_s and the rotations of step
+    // s.  The other threads rotate the 2x2 seat blocks (k1 <= k2); every thread
+    // rotates a segment of two rows of Q^T (rows in vector order).  Padding
+    // vectors are zero, so their rotations are the identity.
+    constexpr int NPH = C::NPH;
+    constexpr int NBT = 256 - NPH;                     // threads rotating H blocks
+    constexpr int NBLK = NPH * (NPH + 1) / 2;
+    constexpr int HB = (NBLK + NBT - 1) / NBT;
+    constexpr int TPP = 256 / NPH;                     // threads per Q row pair
+    constexpr int EPT = NB2 / TPP;                     // Q entries per thread and row
+    constexpr int GW = EPT < VW ? EPT : VW;            // Q entries per LDS access
+    constexpr int NG = EPT / GW;
+    typedef T QVec __attribute__((ext_vector_type(GW)));
     for (int e = tid; e < NB2 * NB2; e += 256) {
         const int a = e / NB2, c = e % NB2;
-        Qs[a * HP + c] = (a == c) ? T(1) : T(0);
+        Qs[C::q_idx(a, c)] = (a == c) ? T(1) : T(0);
     }
-    constexpr int NPH = NB2 / 2;                       // rotations per step
-    constexpr int HB = (NPH * NPH + 255) / 256;        // 2x2 H blocks per thread
-    constexpr int QI = (NB2 * NPH + 255) / 256;        // Q items per thread
-    const int nsteps = cross_only ? B : NB2 - 1;
+    const bool cross = cross_only;
+    const bool angle_thread = tid >= NBT;
+    const int ka = tid - NBT;
+    // this thread's H blocks: pairs k1 <= k2, read slot | write slot << 16
+    int bk1[HB], bk2[HB], rw[HB][4];
+#pragma unroll
+    for (int b = 0; b < HB; ++b) {
+        const int bi = tid + NBT * b;
+        int k2 = (int)((sqrtf(8.0f * (float)bi + 1.0f) - 1.0f) * 0.5f);
+        while (k2 > 0 && k2 * (k2 + 1) / 2 > bi) --k2;
+        while ((k2 + 1) * (k2 + 2) / 2 <= bi) ++k2;
+        const bool use = !angle_thread && bi < NBLK;
+        const int k1 = use ? bi - k2 * (k2 + 1) / 2 : 0;
+        if (!use) k2 = 0;
+        bk1[b] = use ? k1 : -1;
+        bk2[b] = k2;
+        const int u0 = k1, u1 = partner_seat<NB2>(cross, k1);
+        const int v0 = k2, v1 = partner_seat<NB2>(cross, k2);
+        const int nu0 = next_seat<NB2>(cross, u0), nu1 = next_seat<NB2>(cross, u1);
+        const int nv0 = next_seat<NB2>(cross, v0), nv1 = next_seat<NB2>(cross, v1);
+        rw[b][0] = sym_idx(u0, v0) | (sym_idx(nu0, nv0) << 16);
+        rw[b][1] = sym_idx(u0, v1) | (sym_idx(nu0, nv1) << 16);
+        rw[b][2] = sym_idx(u1, v0) | (sym_idx(nu1, nv0) << 16);
+        rw[b][3] = sym_idx(u1, v1) | (sym_idx(nu1, nv1) << 16);
+    }
+    // angle threads: where the two vectors of pair ka at step s+1 sat at step s
+    int ai[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0}, akp = 0, akq = 0;
+    bool afp = true, afq = true;
+    if (angle_thread) {
+        const int sa = prev_seat<NB2>(cross, ka), sb = prev_seat<NB2>(cross, partner_seat<NB2>(cross, ka));
+        akp = seat_pair<NB2>(cross, sa, afp);
+        akq = seat_pair<NB2>(cross, sb, afq);
+        const int xa = akp, xb = partner_seat<NB2>(cross, akp);
+        const int ya = akq, yb = partner_seat<NB2>(cross, akq);
+        ai[0] = sym_idx(xa, xa); ai[1] = sym_idx(xa, xb); ai[2] = sym_idx(xb, xb);
+        ai[3] = sym_idx(ya, ya); ai[4] = sym_idx(ya, yb); ai[5] = sym_idx(yb, yb);
+        ai[6] = sym_idx(xa, ya); ai[7] = sym_idx(xa, yb); ai[8] = sym_idx(xb, ya); ai[9] = sym_idx(xb, yb);
+        const int p = ka, q = partner_seat<NB2>(cross, ka);
+        double c, sn;
+        jacobi_angle(H0[sym_idx(p, p)], H0[sym_idx(q, q)], H0[sym_idx(p, q)], true, c, sn);
+        sh.rot_cs[0][ka] = make_double2(c, sn);
+    }
+    // Q rows of pair qk: the vectors on its seats, advanced every step
+    const int qk = tid / TPP, qc0 = (tid % TPP) * EPT;
+    const int qsa = qk, qsb = partner_seat<NB2>(cross, qk);
+    int qp = qsa, qq = qsb;   // step 0: vector = seat
+    const int nsteps = cross ? B : NB2 - 1;
+    __syncthreads();
     for (int step = 0; step < nsteps; ++step) {
-        if (tid < NPH) {
-            // full sweep: circle tournament over all NB2 vectors; cross sweep:
-            // vector i of the first block meets vector (i + step) mod b of the second
-            const int p = cross_only ? tid : circle_player(tid, step, NB2);
-            const int q = cross_only ? B + (tid + step) % B : circle_player(NB2 - 1 - tid, step, NB2);
-            double c = 1.0, sn = 0.0;
-            if (gidx(p) < r && gidx(q) < r) {
-                const double app = Hs[p * HP + p], aqq = Hs[q * HP + q], apq = Hs[p * HP + q];
-                if (fabs(apq) > 1e-300 && fabs(apq) > 1e-18 * sqrt(fabs(app) * fabs(aqq))) {
-                    const double zeta = (aqq - app) / (2.0 * apq);
-                    double t;
-                    if (fabs(zeta) > 1e150) t = 0.5 / zeta;
-                    else t = copysign(1.0, zeta) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-                    c = 1.0 / sqrt(1.0 + t * t);
-                    sn = c * t;
-                }
-            }
-            rot_c[tid] = c; rot_s[tid] = sn; rot_p[tid] = p; rot_q[tid] = q;
-        }
-        __syncthreads();
-        // H <- J^T H J, one disjoint 2x2 block per (k1, k2): loads first, then math
+        const int cb = step & 1;
+        const double* __restrict__ Hc = H0 + cb * NH;
+        double* __restrict__ Hn = H0 + (cb ^ 1) * NH;
+        const double2* rcs = sh.rot_cs[cb];
+        // ---- loads of the whole step
         double hv[HB][4];
-        int hp1[HB], hq1[HB], hp2[HB], hq2[HB];
-        double c1[HB], s1[HB], c2[HB], s2_[HB];
+        double2 r1[HB], r2[HB];
 #pragma unroll
         for (int b = 0; b < HB; ++b) {
-            const int blk = tid + 256 * b;
-            if (blk < NPH * NPH) {
-                const int k1 = blk / NPH, k2 = blk % NPH;
-                hp1[b] = rot_p[k1]; hq1[b] = rot_q[k1]; hp2[b] = rot_p[k2]; hq2[b] = rot_q[k2];
-                c1[b] = rot_c[k1]; s1[b] = rot_s[k1]; c2[b] = rot_c[k2]; s2_[b] = rot_s[k2];
-                hv[b][0] = Hs[hp1[b] * HP + hp2[b]];
-                hv[b][1] = Hs[hp1[b] * HP + hq2[b]];
-                hv[b][2] = Hs[hq1[b] * HP + hp2[b]];
-                hv[b][3] = Hs[hq1[b] * HP + hq2[b]];
-            }
-        }
-        // Q <- Q J (column pairs), in place: loads first
-        T qv[QI][2];
-        int qi_[QI], qp_[QI], qq_[QI];
-        T qc[QI], qs[QI];
+            if (bk1[b] >= 0) {
 #pragma unroll
-        for (int b = 0; b < QI; ++b) {
-            const int it = tid + 256 * b;
-            if (it < NB2 * NPH) {
-                const int kk = it % NPH, i = it / NPH;
-                qi_[b] = i; qp_[b] = rot_p[kk]; qq_[b] = rot_q[kk];
-                qc[b] = (T)rot_c[kk]; qs[b] = (T)rot_s[kk];
-                qv[b][0] = Qs[i * HP + qp_[b]];
-                qv[b][1] = Qs[i * HP + qq_[b]];
+                for (int e = 0; e < 4; ++e) hv[b][e] = Hc[rw[b][e] & 0xffff];
+                r1[b] = rcs[bk1[b]];
+                r2[b] = rcs[bk2[b]];
             }
         }
+        QVec vp[NG], vq[NG];
+#pragma unroll
+        for (int g = 0; g < NG; ++g) {
+            vp[g] = *reinterpret_cast<const QVec*>(&Qs[C::q_idx(qp, qc0 + g * GW)]);
+            vq[g] = *reinterpret_cast<const QVec*>(&Qs[C::q_idx(qq, qc0 + g * GW)]);
+        }
+        const double2 rq = rcs[qk];
+        // ---- rotations of step s+1 (angle threads)
+        if (angle_thread && step + 1 < nsteps) {
+            double h[10];
+#pragma unroll
+            for (int e = 0; e < 10; ++e) h[e] = Hc[ai[e]];
+            const double2 rx = rcs[akp], ry = rcs[akq];
+            // new vector = a0 * (first of its pair) + a1 * (second)
+            const double a0 = afp ? rx.x : rx.y, a1 = afp ? -rx.y : rx.x;
+            const double b0 = afq ? ry.x : ry.y, b1 = afq ? -ry.y : ry.x;
+            const double app = a0 * (a0 * h[0] + a1 * h[1]) + a1 * (a0 * h[1] + a1 * h[2]);
+            const double aqq = b0 * (b0 * h[3] + b1 * h[4]) + b1 * (b0 * h[4] + b1 * h[5]);
+            const double apq = a0 * (b0 * h[6] + b1 * h[7]) + a1 * (b0 * h[8] + b1 * h[9]);
+            double c, sn;
+            jacobi_angle(app, aqq, apq, true, c, sn);
+            sh.rot_cs[cb ^ 1][ka] = make_double2(c, sn);
+        }
+        // ---- H <- J^T H J on this thread's 2x2 blocks, written on the next seats
 #pragma unroll
         for (int b = 0; b < HB; ++b) {
-            const int blk = tid + 256 * b;
-            if (blk < NPH * NPH) {
-                const double t0 = c2[b] * hv[b][0] - s2_[b] * hv[b][1];
-                const double t1 = s2_[b] * hv[b][0] + c2[b] * hv[b][1];
-                const double t2 = c2[b] * hv[b][2] - s2_[b] * hv[b][3];
-                const double t3 = s2_[b] * hv[b][2] + c2[b] * hv[b][3];
-                Hs[hp1[b] * HP + hp2[b]] = c1[b] * t0 - s1[b] * t2;
-                Hs[hp1[b] * HP + hq2[b]] = c1[b] * t1 - s1[b] * t3;
-                Hs[hq1[b] * HP + hp2[b]] = s1[b] * t0 + c1[b] * t2;
-                Hs[hq1[b] * HP + hq2[b]] = s1[b] * t1 + c1[b] * t3;
-            }
+            if (bk1[b] < 0) continue;
+            const double c1 = r1[b].x, s1 = r1[b].y, c2 = r2[b].x, s2 = r2[b].y;
+            const double t0 = c2 * hv[b][0] - s2 * hv[b][1], t1 = s2 * hv[b][0] + c2 * hv[b][1];
+            const double t2 = c2 * hv[b][2] - s2 * hv[b][3], t3 = s2 * hv[b][2] + c2 * hv[b][3];
+            Hn[rw[b][0] >> 16] = c1 * t0 - s1 * t2;
+            Hn[rw[b][1] >> 16] = c1 * t1 - s1 * t3;
+            if (bk1[b] != bk2[b]) Hn[rw[b][2] >> 16] = s1 * t0 + c1 * t2;
+            Hn[rw[b][3] >> 16] = s1 * t1 + c1 * t3;
         }
+        // ---- Q <- Q J: rows qp, qq of Q^T, entries [qc0, qc0 + EPT)
+        {
+            const T c = (T)rq.x, sn = (T)rq.y;
 #pragma unroll
-        for (int b = 0; b < QI; ++b) {
-            const int it = tid + 256 * b;
-            if (it < NB2 * NPH) {
-                Qs[qi_[b] * HP + qp_[b]] = qc[b] * qv[b][0] - qs[b] * qv[b][1];
-                Qs[qi_[b] * HP + qq_[b]] = qs[b] * qv[b][0] + qc[b] * qv[b][1];
+            for (int g = 0; g < NG; ++g) {
+                *reinterpret_cast<QVec*>(&Qs[C::q_idx(qp, qc0 + g * GW)]) = c * vp[g] - sn * vq[g];
+                *reinterpret_cast<QVec*>(&Qs[C::q_idx(qq, qc0 + g * GW)]) = sn * vp[g] + c * vq[g];
             }
+            qp = seat_vector<NB2>(cross, qsa, step + 1);
+            qq = seat_vector<NB2>(cross, qsb, step + 1);
         }
         __syncthreads();
     }
 
     // ---------------- phase 3: vectors <- Q^T vectors, W <- W Q (MFMA), prefetched
+    gload(Ab, g.vs, g.es, ROWS, vec_a != 0, 0, L);
     constexpr int UPW = NT * (TC / 16) / 4;  // output tiles per wave
     for (int part = 0; part < 2; ++part) {
         T* base = part == 0 ? Ab : Wb;
@@ -469,7 +612,7 @@ __device__ __forceinline__ void round_body(RoundShared<T, NB2>& sh, T* __restric
 #pragma unroll
                 for (int j = 0; j < UPW; ++j) {
                     const int q = wave * UPW + j, ta = q / (TC / 16), tt = q % (TC / 16);
-                    const T a = Qs[(kk + lg) * HP + ta * 16 + lr];   // Q[c][a]
+                    const T a = Qs[C::q_idx(ta * 16 + lr, kk + lg)];  // Q[c][a]
                     const T b = Ts[(kk + lg) * LDP + tt * 16 + lr];  // old[c][t]
                     uacc[j] = mfma(a, b, uacc[j]);
                 }
@@ -486,6 +629,9 @@ __device__ __forceinline__ void round_body(RoundShared<T, NB2>& sh, T* __restric
         }
     }
 }
+
+// FP32 pairs of 64 vectors keep three workgroups per 160 KB compute unit.
+static_assert(sizeof(RoundShared<float, 64>) <= 160 * 1024 / 3, "LDS budget of jacobi_round<float, 64>");
 
 // One round for every (slice, pair) of a tensor of identical slices.
 template <class T, int NB2, bool ROWS>
