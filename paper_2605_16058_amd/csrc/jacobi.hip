@@ -15,6 +15,7 @@
 // the tournament's pair coverage intact.  A slice is converged once a whole
 // sweep saw max |cos| <= tol; later rounds return at once for it.
 #include <mutex>
+#include <type_traits>
 #include <vector>
 
 #include "common.h"
@@ -257,6 +258,14 @@ __device__ __forceinline__ void round_body(RoundShared<T, NB2>& sh, T* __restric
     const int lr = lane & 15, lg = lane >> 4;
 
     auto gidx = [&](int a) -> int64_t { return a < B ? (int64_t)I * B + a : (int64_t)J * B + (a - B); };
+    // Staging layout: element (vector a, position t) at a * LDP + sw(a, t).
+    // Row families are transposed on the way into LDS (scalar stores down a
+    // column); in FP32 the 4-element groups of row a are XOR-swizzled by
+    // bits 2..4 of a so those stores spread over the banks.  Groups of 4
+    // stay contiguous, so the MFMA operand reads are unaffected in shape.
+    auto sw = [&](bool rows, int a, int t) -> int {
+        return (rows && sizeof(T) == 4) ? (t ^ (((a >> 2) & 7) << 2)) : t;
+    };
 
     // ---- global <-> register <-> LDS streaming of one chunk [t0, t0 + TC)
     // Access e of a thread covers VW consecutive elements along the
@@ -314,7 +323,7 @@ __device__ __forceinline__ void round_body(RoundShared<T, NB2>& sh, T* __restric
             } else {
                 const int a4 = (e % (NB2 / VW)) * VW, tt = e / (NB2 / VW);
 #pragma unroll
-                for (int j = 0; j < VW; ++j) Ts[(a4 + j) * LDP + tt] = regs[v][j];
+                for (int j = 0; j < VW; ++j) Ts[(a4 + j) * LDP + sw(true, a4 + j, tt)] = regs[v][j];
             }
         }
     };
@@ -346,7 +355,7 @@ __device__ __forceinline__ void round_body(RoundShared<T, NB2>& sh, T* __restric
                 T* dst = base + gi + t * es;
                 T x[VW];
 #pragma unroll
-                for (int j = 0; j < VW; ++j) x[j] = Ts2[(a4 + j) * LDP + tt];
+                for (int j = 0; j < VW; ++j) x[j] = Ts2[(a4 + j) * LDP + sw(true, a4 + j, tt)];
                 if (vec && gi + VW <= r) {
                     if constexpr (sizeof(T) == 4)
                         *reinterpret_cast<float4*>(dst) = make_float4(x[0], x[1], x[2], x[3]);
@@ -378,8 +387,9 @@ __device__ __forceinline__ void round_body(RoundShared<T, NB2>& sh, T* __restric
 #pragma unroll
             for (int j = 0; j < TPW; ++j) {
                 const int q = wave * TPW + j, tr = q / NT, tc = q % NT;
-                const T a = Ts[(tr * 16 + lr) * LDP + kk + lg];
-                const T b = Ts[(tc * 16 + lr) * LDP + kk + lg];
+                const int ra = tr * 16 + lr, rb = tc * 16 + lr;
+                const T a = Ts[ra * LDP + sw(ROWS, ra, kk + lg)];
+                const T b = Ts[rb * LDP + sw(ROWS, rb, kk + lg)];
                 hacc[j] = mfma(a, b, hacc[j]);
             }
         }
@@ -588,22 +598,16 @@ __device__ __forceinline__ void round_body(RoundShared<T, NB2>& sh, T* __restric
     }
 
     // ---------------- phase 3: vectors <- Q^T vectors, W <- W Q (MFMA), prefetched
-    gload(Ab, g.vs, g.es, ROWS, vec_a != 0, 0, L);
+    // (the layout flag is a compile-time constant in each of the two parts)
     constexpr int UPW = NT * (TC / 16) / 4;  // output tiles per wave
-    for (int part = 0; part < 2; ++part) {
-        T* base = part == 0 ? Ab : Wb;
-        const int64_t vs = part == 0 ? g.vs : r;
-        const int64_t es = part == 0 ? g.es : 1;
-        const int64_t len = part == 0 ? L : r;
-        const bool rows = part == 0 ? ROWS : false;
-        const bool vec = part == 0 ? vec_a != 0 : vec_w != 0;
+    auto update = [&](auto rows_tag, T* base, int64_t vs, int64_t es, int64_t len, bool vec) {
+        constexpr bool RW = decltype(rows_tag)::value;
         const int64_t nc = (len + TC - 1) / TC;
-        if (part == 1) gload(Wb, r, 1, false, vec_w != 0, 0, r);
         for (int64_t c = 0; c < nc; ++c) {
             __syncthreads();
-            regs_to_lds(rows);
+            regs_to_lds(RW);
             __syncthreads();
-            if (c + 1 < nc) gload(base, vs, es, rows, vec, (c + 1) * TC, len);
+            if (c + 1 < nc) gload(base, vs, es, RW, vec, (c + 1) * TC, len);
             AccT uacc[UPW];
 #pragma unroll
             for (int j = 0; j < UPW; ++j) uacc[j] = zero4<AccT>();
@@ -613,7 +617,8 @@ __device__ __forceinline__ void round_body(RoundShared<T, NB2>& sh, T* __restric
                 for (int j = 0; j < UPW; ++j) {
                     const int q = wave * UPW + j, ta = q / (TC / 16), tt = q % (TC / 16);
                     const T a = Qs[C::q_idx(ta * 16 + lr, kk + lg)];  // Q[c][a]
-                    const T b = Ts[(kk + lg) * LDP + tt * 16 + lr];  // old[c][t]
+                    const int rc = kk + lg;
+                    const T b = Ts[rc * LDP + sw(RW, rc, tt * 16 + lr)];  // old[c][t]
                     uacc[j] = mfma(a, b, uacc[j]);
                 }
             }
@@ -621,13 +626,19 @@ __device__ __forceinline__ void round_body(RoundShared<T, NB2>& sh, T* __restric
             for (int j = 0; j < UPW; ++j) {
                 const int q = wave * UPW + j, ta = q / (TC / 16), tt = q % (TC / 16);
 #pragma unroll
-                for (int v = 0; v < 4; ++v)
-                    Ts2[(ta * 16 + mfma_row<T>(lg, v)) * LDP + tt * 16 + lr] = uacc[j][v];
+                for (int v = 0; v < 4; ++v) {
+                    const int ro = ta * 16 + mfma_row<T>(lg, v);
+                    Ts2[ro * LDP + sw(RW, ro, tt * 16 + lr)] = uacc[j][v];
+                }
             }
             __syncthreads();
-            gstore(base, vs, es, rows, vec, c * TC, len);
+            gstore(base, vs, es, RW, vec, c * TC, len);
         }
-    }
+    };
+    gload(Ab, g.vs, g.es, ROWS, vec_a != 0, 0, L);
+    update(std::integral_constant<bool, ROWS>(), Ab, g.vs, g.es, L, vec_a != 0);
+    gload(Wb, r, 1, false, vec_w != 0, 0, r);
+    update(std::integral_constant<bool, false>(), Wb, r, 1, r, vec_w != 0);
 }
 
 // FP32 pairs of 64 vectors keep three workgroups per 160 KB compute unit.
