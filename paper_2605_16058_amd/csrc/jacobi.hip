@@ -312,18 +312,18 @@ __device__ __forceinline__ void round_body(RoundShared<T, NB2>& sh, T* __restric
             }
         }
     };
-    auto regs_to_lds = [&](bool rows) {
+    auto regs_to_lds = [&](bool rows, T* dst) {
 #pragma unroll
         for (int v = 0; v < NV; ++v) {
             const int e = tid + 256 * v;
             if (!rows) {
                 const int a = e / (TC / VW), tt = (e % (TC / VW)) * VW;
 #pragma unroll
-                for (int j = 0; j < VW; ++j) Ts[a * LDP + tt + j] = regs[v][j];
+                for (int j = 0; j < VW; ++j) dst[a * LDP + tt + j] = regs[v][j];
             } else {
                 const int a4 = (e % (NB2 / VW)) * VW, tt = e / (NB2 / VW);
 #pragma unroll
-                for (int j = 0; j < VW; ++j) Ts[(a4 + j) * LDP + sw(true, a4 + j, tt)] = regs[v][j];
+                for (int j = 0; j < VW; ++j) dst[(a4 + j) * LDP + sw(true, a4 + j, tt)] = regs[v][j];
             }
         }
     };
@@ -371,6 +371,8 @@ __device__ __forceinline__ void round_body(RoundShared<T, NB2>& sh, T* __restric
     };
 
     // ---------------- phase 1: Gram matrix H of the pair (MFMA), prefetched
+    // Chunks alternate between the two staging buffers, so one barrier per
+    // chunk suffices.
     constexpr int TPW = NT * NT / 4;
     AccT hacc[TPW];
 #pragma unroll
@@ -378,8 +380,8 @@ __device__ __forceinline__ void round_body(RoundShared<T, NB2>& sh, T* __restric
     const int64_t nch = (L + TC - 1) / TC;
     gload(Ab, g.vs, g.es, ROWS, vec_a != 0, 0, L);
     for (int64_t c = 0; c < nch; ++c) {
-        __syncthreads();
-        regs_to_lds(ROWS);
+        T* const buf = (c & 1) ? Ts2 : Ts;
+        regs_to_lds(ROWS, buf);
         __syncthreads();
         if (c + 1 < nch) gload(Ab, g.vs, g.es, ROWS, vec_a != 0, (c + 1) * TC, L);
 #pragma unroll 4
@@ -388,8 +390,8 @@ __device__ __forceinline__ void round_body(RoundShared<T, NB2>& sh, T* __restric
             for (int j = 0; j < TPW; ++j) {
                 const int q = wave * TPW + j, tr = q / NT, tc = q % NT;
                 const int ra = tr * 16 + lr, rb = tc * 16 + lr;
-                const T a = Ts[ra * LDP + sw(ROWS, ra, kk + lg)];
-                const T b = Ts[rb * LDP + sw(ROWS, rb, kk + lg)];
+                const T a = buf[ra * LDP + sw(ROWS, ra, kk + lg)];
+                const T b = buf[rb * LDP + sw(ROWS, rb, kk + lg)];
                 hacc[j] = mfma(a, b, hacc[j]);
             }
         }
@@ -604,8 +606,9 @@ __device__ __forceinline__ void round_body(RoundShared<T, NB2>& sh, T* __restric
         constexpr bool RW = decltype(rows_tag)::value;
         const int64_t nc = (len + TC - 1) / TC;
         for (int64_t c = 0; c < nc; ++c) {
-            __syncthreads();
-            regs_to_lds(RW);
+            // Ts was last read by the previous chunk's MFMA, which ended
+            // before the barrier ahead of its stores
+            regs_to_lds(RW, Ts);
             __syncthreads();
             if (c + 1 < nc) gload(base, vs, es, RW, vec, (c + 1) * TC, len);
             AccT uacc[UPW];
