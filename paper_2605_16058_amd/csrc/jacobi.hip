@@ -212,6 +212,9 @@ struct RoundCfg {
     static constexpr size_t r1 = (2 * ts_bytes > hs_bytes) ? 2 * ts_bytes : hs_bytes;
     static constexpr size_t q_bytes = sizeof(T) * NB2 * NB2;
     static constexpr size_t total = r1 + q_bytes;
+    // waves per SIMD the kernel is compiled for: three workgroups per compute
+    // unit when the LDS allows it (FP32), else two
+    static constexpr int WAVES = (3 * (total + 2048) <= 160 * 1024) ? 3 : 2;
     // Q^T[a][c] = Q[c][a]
     static __device__ __forceinline__ int q_idx(int a, int c) { return a * NB2 + (c ^ ((a & SWM) * VW)); }
 };
@@ -384,15 +387,21 @@ __device__ __forceinline__ void round_body(RoundShared<T, NB2>& sh, T* __restric
         regs_to_lds(ROWS, buf);
         __syncthreads();
         if (c + 1 < nch) gload(Ab, g.vs, g.es, ROWS, vec_a != 0, (c + 1) * TC, L);
-#pragma unroll 4
-        for (int kk = 0; kk < TC; kk += 4) {
+        // The Gram matrix sums over positions in any order: lane group lg
+        // reads VW consecutive positions with one 16-byte load and MFMA i of
+        // the group takes element i, so 4*VW positions cost one load per
+        // operand fragment instead of VW.
+        typedef T KVec __attribute__((ext_vector_type(VW)));
+#pragma unroll 2
+        for (int kb = 0; kb < TC; kb += 4 * VW) {
 #pragma unroll
             for (int j = 0; j < TPW; ++j) {
                 const int q = wave * TPW + j, tr = q / NT, tc = q % NT;
                 const int ra = tr * 16 + lr, rb = tc * 16 + lr;
-                const T a = buf[ra * LDP + sw(ROWS, ra, kk + lg)];
-                const T b = buf[rb * LDP + sw(ROWS, rb, kk + lg)];
-                hacc[j] = mfma(a, b, hacc[j]);
+                const KVec a = *reinterpret_cast<const KVec*>(&buf[ra * LDP + sw(ROWS, ra, kb + lg * VW)]);
+                const KVec b = *reinterpret_cast<const KVec*>(&buf[rb * LDP + sw(ROWS, rb, kb + lg * VW)]);
+#pragma unroll
+                for (int i = 0; i < VW; ++i) hacc[j] = mfma(a[i], b[i], hacc[j]);
             }
         }
     }
@@ -473,7 +482,7 @@ __device__ __forceinline__ void round_body(RoundShared<T, NB2>& sh, T* __restric
     // rotates a segment of two rows of Q^T (rows in vector order).  Padding
     // vectors are zero, so their rotations are the identity.
     constexpr int NPH = C::NPH;
-    constexpr int NBT = 256 - NPH;                     // threads rotating H blocks
+    constexpr int NBT = 192;                           // threads rotating H blocks (waves 0-2)
     constexpr int NBLK = NPH * (NPH + 1) / 2;
     constexpr int HB = (NBLK + NBT - 1) / NBT;
     constexpr int TPP = 256 / NPH;                     // threads per Q row pair
@@ -486,8 +495,8 @@ __device__ __forceinline__ void round_body(RoundShared<T, NB2>& sh, T* __restric
         Qs[C::q_idx(a, c)] = (a == c) ? T(1) : T(0);
     }
     const bool cross = cross_only;
-    const bool angle_thread = tid >= NBT;
-    const int ka = tid - NBT;
+    const bool angle_thread = tid >= 256 - NPH;        // the upper lanes of wave 3
+    const int ka = tid - (256 - NPH);
     // this thread's H blocks: pairs k1 <= k2, read slot | write slot << 16
     int bk1[HB], bk2[HB], rw[HB][4];
 #pragma unroll
@@ -496,7 +505,7 @@ __device__ __forceinline__ void round_body(RoundShared<T, NB2>& sh, T* __restric
         int k2 = (int)((sqrtf(8.0f * (float)bi + 1.0f) - 1.0f) * 0.5f);
         while (k2 > 0 && k2 * (k2 + 1) / 2 > bi) --k2;
         while ((k2 + 1) * (k2 + 2) / 2 <= bi) ++k2;
-        const bool use = !angle_thread && bi < NBLK;
+        const bool use = tid < NBT && bi < NBLK;
         const int k1 = use ? bi - k2 * (k2 + 1) / 2 : 0;
         if (!use) k2 = 0;
         bk1[b] = use ? k1 : -1;
@@ -511,17 +520,12 @@ __device__ __forceinline__ void round_body(RoundShared<T, NB2>& sh, T* __restric
         rw[b][3] = sym_idx(u1, v1) | (sym_idx(nu1, nv1) << 16);
     }
     // angle threads: where the two vectors of pair ka at step s+1 sat at step s
-    int ai[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0}, akp = 0, akq = 0;
+    int akp = 0, akq = 0;
     bool afp = true, afq = true;
     if (angle_thread) {
         const int sa = prev_seat<NB2>(cross, ka), sb = prev_seat<NB2>(cross, partner_seat<NB2>(cross, ka));
         akp = seat_pair<NB2>(cross, sa, afp);
         akq = seat_pair<NB2>(cross, sb, afq);
-        const int xa = akp, xb = partner_seat<NB2>(cross, akp);
-        const int ya = akq, yb = partner_seat<NB2>(cross, akq);
-        ai[0] = sym_idx(xa, xa); ai[1] = sym_idx(xa, xb); ai[2] = sym_idx(xb, xb);
-        ai[3] = sym_idx(ya, ya); ai[4] = sym_idx(ya, yb); ai[5] = sym_idx(yb, yb);
-        ai[6] = sym_idx(xa, ya); ai[7] = sym_idx(xa, yb); ai[8] = sym_idx(xb, ya); ai[9] = sym_idx(xb, yb);
         const int p = ka, q = partner_seat<NB2>(cross, ka);
         double c, sn;
         jacobi_angle(H0[sym_idx(p, p)], H0[sym_idx(q, q)], H0[sym_idx(p, q)], true, c, sn);
@@ -538,30 +542,16 @@ __device__ __forceinline__ void round_body(RoundShared<T, NB2>& sh, T* __restric
         const double* __restrict__ Hc = H0 + cb * NH;
         double* __restrict__ Hn = H0 + (cb ^ 1) * NH;
         const double2* rcs = sh.rot_cs[cb];
-        // ---- loads of the whole step
-        double hv[HB][4];
-        double2 r1[HB], r2[HB];
-#pragma unroll
-        for (int b = 0; b < HB; ++b) {
-            if (bk1[b] >= 0) {
-#pragma unroll
-                for (int e = 0; e < 4; ++e) hv[b][e] = Hc[rw[b][e] & 0xffff];
-                r1[b] = rcs[bk1[b]];
-                r2[b] = rcs[bk2[b]];
-            }
-        }
-        QVec vp[NG], vq[NG];
-#pragma unroll
-        for (int g = 0; g < NG; ++g) {
-            vp[g] = *reinterpret_cast<const QVec*>(&Qs[C::q_idx(qp, qc0 + g * GW)]);
-            vq[g] = *reinterpret_cast<const QVec*>(&Qs[C::q_idx(qq, qc0 + g * GW)]);
-        }
-        const double2 rq = rcs[qk];
-        // ---- rotations of step s+1 (angle threads)
+        // ---- rotations of step s+1 (angle threads, wave 3): first, so that
+        // their registers are free again for the H blocks of waves 0-2
         if (angle_thread && step + 1 < nsteps) {
+            const int xa = akp, xb = partner_seat<NB2>(cross, akp);
+            const int ya = akq, yb = partner_seat<NB2>(cross, akq);
             double h[10];
-#pragma unroll
-            for (int e = 0; e < 10; ++e) h[e] = Hc[ai[e]];
+            h[0] = Hc[sym_idx(xa, xa)]; h[1] = Hc[sym_idx(xa, xb)]; h[2] = Hc[sym_idx(xb, xb)];
+            h[3] = Hc[sym_idx(ya, ya)]; h[4] = Hc[sym_idx(ya, yb)]; h[5] = Hc[sym_idx(yb, yb)];
+            h[6] = Hc[sym_idx(xa, ya)]; h[7] = Hc[sym_idx(xa, yb)];
+            h[8] = Hc[sym_idx(xb, ya)]; h[9] = Hc[sym_idx(xb, yb)];
             const double2 rx = rcs[akp], ry = rcs[akq];
             // new vector = a0 * (first of its pair) + a1 * (second)
             const double a0 = afp ? rx.x : rx.y, a1 = afp ? -rx.y : rx.x;
@@ -573,25 +563,48 @@ __device__ __forceinline__ void round_body(RoundShared<T, NB2>& sh, T* __restric
             jacobi_angle(app, aqq, apq, true, c, sn);
             sh.rot_cs[cb ^ 1][ka] = make_double2(c, sn);
         }
-        // ---- H <- J^T H J on this thread's 2x2 blocks, written on the next seats
+        // ---- H <- J^T H J on this thread's 2x2 blocks, written on the next
+        // seats; two blocks in flight at a time (register budget)
+        constexpr int HG = 2;
 #pragma unroll
-        for (int b = 0; b < HB; ++b) {
-            if (bk1[b] < 0) continue;
-            const double c1 = r1[b].x, s1 = r1[b].y, c2 = r2[b].x, s2 = r2[b].y;
-            const double t0 = c2 * hv[b][0] - s2 * hv[b][1], t1 = s2 * hv[b][0] + c2 * hv[b][1];
-            const double t2 = c2 * hv[b][2] - s2 * hv[b][3], t3 = s2 * hv[b][2] + c2 * hv[b][3];
-            Hn[rw[b][0] >> 16] = c1 * t0 - s1 * t2;
-            Hn[rw[b][1] >> 16] = c1 * t1 - s1 * t3;
-            if (bk1[b] != bk2[b]) Hn[rw[b][2] >> 16] = s1 * t0 + c1 * t2;
-            Hn[rw[b][3] >> 16] = s1 * t1 + c1 * t3;
+        for (int b0 = 0; b0 < HB; b0 += HG) {
+            double hv[HG][4];
+            double2 r1[HG], r2[HG];
+#pragma unroll
+            for (int u = 0; u < HG; ++u) {
+                const int b = b0 + u;
+                if (b < HB && bk1[b] >= 0) {
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) hv[u][e] = Hc[rw[b][e] & 0xffff];
+                    r1[u] = rcs[bk1[b]];
+                    r2[u] = rcs[bk2[b]];
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < HG; ++u) {
+                const int b = b0 + u;
+                if (b >= HB || bk1[b] < 0) continue;
+                const double c1 = r1[u].x, s1 = r1[u].y, c2 = r2[u].x, s2 = r2[u].y;
+                const double t0 = c2 * hv[u][0] - s2 * hv[u][1], t1 = s2 * hv[u][0] + c2 * hv[u][1];
+                const double t2 = c2 * hv[u][2] - s2 * hv[u][3], t3 = s2 * hv[u][2] + c2 * hv[u][3];
+                Hn[rw[b][0] >> 16] = c1 * t0 - s1 * t2;
+                Hn[rw[b][1] >> 16] = c1 * t1 - s1 * t3;
+                if (bk1[b] != bk2[b]) Hn[rw[b][2] >> 16] = s1 * t0 + c1 * t2;
+                Hn[rw[b][3] >> 16] = s1 * t1 + c1 * t3;
+            }
         }
-        // ---- Q <- Q J: rows qp, qq of Q^T, entries [qc0, qc0 + EPT)
+        // ---- Q <- Q J: rows qp, qq of Q^T, entries [qc0, qc0 + EPT), one
+        // 16-byte group at a time (register budget)
         {
+            const double2 rq = rcs[qk];
             const T c = (T)rq.x, sn = (T)rq.y;
 #pragma unroll
             for (int g = 0; g < NG; ++g) {
-                *reinterpret_cast<QVec*>(&Qs[C::q_idx(qp, qc0 + g * GW)]) = c * vp[g] - sn * vq[g];
-                *reinterpret_cast<QVec*>(&Qs[C::q_idx(qq, qc0 + g * GW)]) = sn * vp[g] + c * vq[g];
+                QVec* const pp = reinterpret_cast<QVec*>(&Qs[C::q_idx(qp, qc0 + g * GW)]);
+                QVec* const pq = reinterpret_cast<QVec*>(&Qs[C::q_idx(qq, qc0 + g * GW)]);
+                const QVec vp = *pp, vq = *pq;
+                *pp = c * vp - sn * vq;
+                *pq = sn * vp + c * vq;
             }
             qp = seat_vector<NB2>(cross, qsa, step + 1);
             qq = seat_vector<NB2>(cross, qsb, step + 1);
@@ -649,7 +662,8 @@ static_assert(sizeof(RoundShared<float, 64>) <= 160 * 1024 / 3, "LDS budget of j
 
 // One round for every (slice, pair) of a tensor of identical slices.
 template <class T, int NB2, bool ROWS>
-__global__ __launch_bounds__(256) void jacobi_round(T* __restrict__ A, T* __restrict__ W, SliceGeom g,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(RoundCfg<T, NB2>::WAVES)))
+void jacobi_round(T* __restrict__ A, T* __restrict__ W, SliceGeom g,
                                                     int nbe, int rnd, JacobiCtl* __restrict__ ctl,
                                                     double tol, int vec_a, int vec_w,
                                                     unsigned long long* __restrict__ pair_counts) {
@@ -666,7 +680,8 @@ __global__ __launch_bounds__(256) void jacobi_round(T* __restrict__ A, T* __rest
 // shapes: task = (slice, pair); slice s is in round t mod (nbe_s - 1) of its
 // own tournament, so slices with fewer blocks simply run more sweeps.
 template <class T, int NB2>
-__global__ __launch_bounds__(256) void jacobi_round_batch(const BatchSlice* __restrict__ sl,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(RoundCfg<T, NB2>::WAVES)))
+void jacobi_round_batch(const BatchSlice* __restrict__ sl,
                                                           const int2* __restrict__ tasks, int t,
                                                           JacobiCtl* __restrict__ ctl,
                                                           unsigned long long* __restrict__ pair_counts) {
