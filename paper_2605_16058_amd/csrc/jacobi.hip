@@ -387,21 +387,19 @@ __device__ __forceinline__ void round_body(RoundShared<T, NB2>& sh, T* __restric
         regs_to_lds(ROWS, buf);
         __syncthreads();
         if (c + 1 < nch) gload(Ab, g.vs, g.es, ROWS, vec_a != 0, (c + 1) * TC, L);
-        // The Gram matrix sums over positions in any order: lane group lg
-        // reads VW consecutive positions with one 16-byte load and MFMA i of
-        // the group takes element i, so 4*VW positions cost one load per
-        // operand fragment instead of VW.
-        typedef T KVec __attribute__((ext_vector_type(VW)));
-#pragma unroll 2
-        for (int kb = 0; kb < TC; kb += 4 * VW) {
+        // (Each MFMA sums four consecutive positions.  Reading four positions
+        // per lane with one 16-byte load, i.e. summing positions in a strided
+        // order, was measured 2% faster but left the FP32 results 8x further
+        // from the FP64 ones on smooth inputs, so the plain order is kept.)
+#pragma unroll 4
+        for (int kk = 0; kk < TC; kk += 4) {
 #pragma unroll
             for (int j = 0; j < TPW; ++j) {
                 const int q = wave * TPW + j, tr = q / NT, tc = q % NT;
                 const int ra = tr * 16 + lr, rb = tc * 16 + lr;
-                const KVec a = *reinterpret_cast<const KVec*>(&buf[ra * LDP + sw(ROWS, ra, kb + lg * VW)]);
-                const KVec b = *reinterpret_cast<const KVec*>(&buf[rb * LDP + sw(ROWS, rb, kb + lg * VW)]);
-#pragma unroll
-                for (int i = 0; i < VW; ++i) hacc[j] = mfma(a[i], b[i], hacc[j]);
+                const T a = buf[ra * LDP + sw(ROWS, ra, kk + lg)];
+                const T b = buf[rb * LDP + sw(ROWS, rb, kk + lg)];
+                hacc[j] = mfma(a, b, hacc[j]);
             }
         }
     }
