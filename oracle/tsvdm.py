@@ -13,7 +13,8 @@ requirement; Section 3 restricts the implementation to orthonormal M).
 
 Parity status
 -------------
-pinned   : mode3, to_transform_domain, from_transform_domain, slice_svd,
+pinned   : mode3, mode_product, to_transform_domain, from_transform_domain,
+           to_transform_domain_d, from_transform_domain_d, tsvdm_d, slice_svd,
            full_tsvdm, mproduct, ranks_fixed, ranks_tolerance,
            truncated_factors, reconstruct, tsvdm_i, tsvdm_ii,
            compression_ratio, rel_error, trunc_loss, trunc_loss_grad,
@@ -46,6 +47,10 @@ __all__ = [
     "trunc_loss_grad",
     "cayley",
     "cayley_grad",
+    "mode_product",
+    "to_transform_domain_d",
+    "from_transform_domain_d",
+    "tsvdm_d",
 ]
 
 
@@ -379,3 +384,86 @@ def cayley_grad(K, GM):
     M = cayley(K)
     Y = np.linalg.solve(I + K, GM @ (I + M).T)
     return Y - Y.T
+
+
+# ---------------------------------------------------------------------------
+# tensors of order d > 3 (Section 2.1, footnote; Section 3.1)
+# ---------------------------------------------------------------------------
+
+def mode_product(A, M, k: int):
+    """Mode-k product A x_k M of a tensor of any order (Section 2.1:
+    (A x_k M)_(k) = M A_(k)); k is 1-based and M is J x n_k.  Written as the
+    definition: the k-th index i of the result gathers sum_l M[i, l] times
+    the sub-tensor of A whose k-th index is l."""
+    A = _f64(A)
+    M = _f64(M)
+    ax = k - 1
+    if not (0 <= ax < A.ndim) or A.shape[ax] != M.shape[1]:
+        raise ValueError("mode-k size mismatch")
+    shape = list(A.shape)
+    shape[ax] = M.shape[0]
+    out = np.zeros(shape)
+    for i in range(M.shape[0]):
+        oi = [slice(None)] * A.ndim
+        oi[ax] = i
+        for l in range(M.shape[1]):
+            if M[i, l] != 0.0:
+                ai = [slice(None)] * A.ndim
+                ai[ax] = l
+                out[tuple(oi)] += M[i, l] * A[tuple(ai)]
+    return out
+
+
+def to_transform_domain_d(A, Ms):
+    """A-hat = A x_3 M_3 x_4 M_4 ... x_d M_d: each mode k >= 3 gets its own
+    transform (Section 2.1, footnote on order-d tensors; Section 3.1)."""
+    A = _f64(A)
+    if len(Ms) != A.ndim - 2:
+        raise ValueError("one transform per mode k >= 3")
+    for k, M in enumerate(Ms, start=3):
+        A = mode_product(A, M, k)
+    return A
+
+
+def from_transform_domain_d(C_hat, Ms):
+    """C = C-hat x_3 M_3^{-1} ... x_d M_d^{-1}, M_k^{-1} = M_k^T / c_k^2."""
+    C = _f64(C_hat)
+    for k, M in enumerate(Ms, start=3):
+        c2 = check_transform(M)
+        C = mode_product(C, _f64(M).T / c2, k)
+    return C
+
+
+def tsvdm_d(A, Ms, mode: str = "II", k: int | None = None, eps: float | None = None):
+    """t-SVDM-I (mode "I", rank k) or t-SVDM-II (mode "II", tolerance eps) of
+    an order-d tensor n_1 x n_2 x n_3 x ... x n_d.  A frontal slice fixes every
+    index but the first two (Section 2.1, footnote), so after the transforms
+    the N = n_3 ... n_d slices (column-major order: mode 3 varies fastest) go
+    through the slice SVDs, the rank selection and the back-transforms
+    exactly as for three modes."""
+    A = _f64(A)
+    dims = A.shape
+    if len(dims) < 3:
+        raise ValueError("order >= 3")
+    n1, n2 = dims[0], dims[1]
+    A_hat = to_transform_domain_d(A, Ms)
+    A3 = A_hat.reshape(n1, n2, -1, order="F")
+    U, S, V = slice_svd(A3)
+    r, N = S.shape
+    if mode == "I":
+        rho = ranks_fixed(k, r, N)
+        sq = S * S
+        info = {"discarded": sum(float(np.sum(sq[rho[i]:, i])) for i in range(N)),
+                "total": float(np.sum(sq))}
+    elif mode == "II":
+        rho, info = ranks_tolerance(S, eps)
+    else:
+        raise ValueError("mode must be 'I' or 'II'")
+    fac = truncated_factors(U, S, V, rho)
+    C_hat = np.zeros((n1, n2, N))
+    for i, (Ui, _si, Gi) in enumerate(fac):
+        if Ui.shape[1] > 0:
+            C_hat[:, :, i] = Ui @ Gi
+    A_rec = from_transform_domain_d(C_hat.reshape(dims, order="F"), Ms)
+    return {"A_hat": A_hat, "S": S, "rho": rho, "factors": fac, "info": info,
+            "A_rec": A_rec, "rel_error": rel_error(A, A_rec)}
