@@ -116,6 +116,21 @@ int tsvdm_transform(const void* X, int x_dtype, void* Y, int y_dtype,
                     const double* M, int transpose, double scale,
                     int compute, int tile, void* ws, size_t ws_bytes, void* stream);
 
+/* Mode-k transform of an order-d tensor (Section 2.1, footnote: every mode
+ * k >= 3 has its own transform; Section 3.1, middle-mode TTM):
+ * Y = X x_k (scale * op(M)) for 3 <= k <= d, where dims (host, d entries)
+ * holds n_1 ... n_d and X, Y (device, column-major, prod(dims) elements,
+ * no aliasing) keep mode 1 fastest.  The tensor is the P = n_{k+1}...n_d
+ * contiguous blocks of the (n_1...n_{k-1}) x n_k matrix; all blocks run as
+ * one launch (k = d is the last-mode case, P = 1).  M: device FP64 n_k x n_k
+ * column-major.  x_dtype, y_dtype, transpose, scale, compute and tile as in
+ * tsvdm_transform; ws: tsvdm_transform_workspace_size(n_k) bytes.  A 3-way
+ * tensor with k = 3 is exactly tsvdm_transform. */
+int tsvdm_transform_mode(const void* X, int x_dtype, void* Y, int y_dtype,
+                         int32_t d, const int64_t* dims, int32_t k,
+                         const double* M, int transpose, double scale,
+                         int compute, int tile, void* ws, size_t ws_bytes, void* stream);
+
 /* --------------------------------------------------------------------- */
 /* slice SVDs (Algorithm 1; Section 3.2)                                 */
 /* --------------------------------------------------------------------- */
@@ -218,6 +233,17 @@ int tsvdm_reconstruct(const void* U_pk, const void* G_pk, int dtype,
                       const double* M, double scale, void* A_rec,
                       int out_dtype, int compute, int tile,
                       void* ws, size_t ws_bytes, void* stream);
+
+/* C (device, m*p*n elements of dtype, column-major) with slice i equal to
+ * U_pk_i * G_pk_i (variable-rank batched GEMM, Section 2.1 third step in
+ * the transform domain), i.e. the first half of tsvdm_reconstruct without
+ * the back-transform: order-d tensors apply their back-transforms mode by
+ * mode with tsvdm_transform_mode.  Arguments as in tsvdm_reconstruct; no
+ * workspace. */
+int tsvdm_lowrank(const void* U_pk, const void* G_pk, int dtype,
+                  int64_t m, int64_t p, int64_t n,
+                  const int32_t* rho, const int64_t* offsets, int64_t capacity,
+                  void* C, void* stream);
 
 /* --------------------------------------------------------------------- */
 /* error report                                                          */

@@ -132,6 +132,42 @@ int tsvdm_transform(const void* X, int x_dtype, void* Y, int y_dtype, int64_t m,
                    as_stream(stream));
 }
 
+int tsvdm_transform_mode(const void* X, int x_dtype, void* Y, int y_dtype, int32_t d,
+                         const int64_t* dims, int32_t k, const double* M, int transpose,
+                         double scale, int compute, int tile, void* ws, size_t ws_bytes,
+                         void* stream) {
+    clear_error();
+    TSVDM_REQUIRE(dims != nullptr, TSVDM_E_ARG, "dims is NULL");
+    TSVDM_REQUIRE(d >= 3 && d <= 32, TSVDM_E_SHAPE, "d must be in [3, 32]");
+    TSVDM_REQUIRE(k >= 3 && k <= d, TSVDM_E_ARG, "k must be in [3, d]");
+    int64_t R = 1, P = 1;
+    for (int i = 0; i < d; ++i) {
+        TSVDM_REQUIRE(dims[i] >= 1 && dims[i] < ((int64_t)1 << 31), TSVDM_E_SHAPE,
+                      "every dimension must be in [1, 2^31)");
+        int64_t& acc = (i + 1 < k) ? R : P;
+        if (i + 1 == k) continue;
+        TSVDM_REQUIRE(acc <= (((int64_t)1 << 46) / dims[i]), TSVDM_E_SHAPE, "tensor too large");
+        acc *= dims[i];
+    }
+    const int64_t n = dims[k - 1];
+    TSVDM_REQUIRE(n < 65536, TSVDM_E_SHAPE, "n_k must be below 65536");
+    TSVDM_REQUIRE(R <= (((int64_t)1 << 46) / n) / P, TSVDM_E_SHAPE, "tensor too large");
+    TSVDM_REQUIRE(X && Y && M, TSVDM_E_ARG, "X, Y and M must be non-NULL");
+    TSVDM_REQUIRE(X != Y, TSVDM_E_ARG, "Y must not alias X");
+    TSVDM_REQUIRE(io_dtype(x_dtype) && io_dtype(y_dtype), TSVDM_E_UNSUPPORTED,
+                  "x_dtype and y_dtype must be F64 or F32");
+    TSVDM_REQUIRE(compute >= TSVDM_F64 && compute <= TSVDM_BF16X3, TSVDM_E_UNSUPPORTED,
+                  "unknown compute dtype");
+    TSVDM_REQUIRE(!(compute >= TSVDM_BF16 && y_dtype != TSVDM_F32), TSVDM_E_UNSUPPORTED,
+                  "BF16 compute writes F32 output only");
+    TSVDM_REQUIRE(transpose == 0 || transpose == 1, TSVDM_E_ARG, "transpose must be 0 or 1");
+    TSVDM_REQUIRE(std::isfinite(scale), TSVDM_E_ARG, "scale must be finite");
+    TSVDM_REQUIRE(tile >= 0 && tile <= 3, TSVDM_E_ARG, "tile must be 0, 1, 2 or 3");
+    TSVDM_TRY(check_ws(ws, ws_bytes, ttm_workspace_bytes(n)));
+    return run_ttm_mode(X, x_dtype, Y, y_dtype, R, n, P, M, transpose, scale, compute, tile, ws,
+                        as_stream(stream));
+}
+
 // ------------------------------------------------------------- slice SVD
 
 int tsvdm_slice_svd_workspace_size(int64_t m, int64_t p, int64_t n, int dtype, size_t* bytes) {
@@ -262,6 +298,19 @@ int tsvdm_reconstruct(const void* U_pk, const void* G_pk, int dtype, int64_t m, 
     hipStream_t st = as_stream(stream);
     TSVDM_TRY(run_lowrank_gemm(U_pk, G_pk, dtype, m, p, n, rho, offsets, capacity, C, st));
     return run_ttm(C, dtype, A_rec, out_dtype, m, p, n, M, 1, scale, compute, tile, tws, st);
+}
+
+int tsvdm_lowrank(const void* U_pk, const void* G_pk, int dtype, int64_t m, int64_t p, int64_t n,
+                  const int32_t* rho, const int64_t* offsets, int64_t capacity, void* C,
+                  void* stream) {
+    clear_error();
+    TSVDM_TRY(check_shape(m, p, n));
+    TSVDM_REQUIRE(rho && offsets && C, TSVDM_E_ARG, "rho, offsets and C must be non-NULL");
+    TSVDM_REQUIRE(capacity >= 0, TSVDM_E_ARG, "capacity must be >= 0");
+    TSVDM_REQUIRE(capacity == 0 || (U_pk && G_pk), TSVDM_E_ARG,
+                  "U_pk and G_pk must be non-NULL when capacity > 0");
+    TSVDM_REQUIRE(io_dtype(dtype), TSVDM_E_UNSUPPORTED, "dtype must be F64 or F32");
+    return run_lowrank_gemm(U_pk, G_pk, dtype, m, p, n, rho, offsets, capacity, C, as_stream(stream));
 }
 
 // ------------------------------------------------------------- error report

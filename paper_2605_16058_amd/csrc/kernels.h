@@ -89,6 +89,10 @@ int run_ttm_batch(const TtmProblem* probs, int nprob, const int4* tasks, const i
 int run_ttm(const void* X, int xdt, void* Y, int ydt, int64_t m, int64_t p, int64_t n,
             const double* M, int transpose, double scale, int compute, int tile, void* ws,
             hipStream_t st);
+// P consecutive blocks of R x n elements, each Y_b = X_b x_last (scale * op(M))
+int run_ttm_mode(const void* X, int xdt, void* Y, int ydt, int64_t R, int64_t n, int64_t P,
+                 const double* M, int transpose, double scale, int compute, int tile, void* ws,
+                 hipStream_t st);
 
 // ---- slice SVD (jacobi.hip)
 struct JacobiCtl {

@@ -3,7 +3,10 @@
 // For a column-major m x p x n tensor the mode-3 unfolding is the (mp) x n
 // matrix X whose column l is frontal slice l, so Y = X x_3 op(M) is the single
 // GEMM  Y[row, i] = sum_l X[row, l] * op(M)[i, l]  with a huge row count
-// R = mp and small N = K = n.  Each workgroup computes a TR-row x TI-slice
+// R = mp and small N = K = n.  For a mode k of an order-d tensor the same
+// GEMM runs on each of the P = n_{k+1} ... n_d contiguous blocks of
+// R = n_1 ... n_{k-1} rows (Section 3.1, middle-mode TTM), blockIdx.y
+// selecting the block.  Each workgroup computes a TR-row x TI-slice
 // tile of Y in the transposed orientation Y^T = op(M) X^T so that the MFMA
 // output lanes run along tensor rows and the stores coalesce.  Three tile
 // shapes share one body (64x64, 128x32, 256x16: every wave owns 16 slices
@@ -149,6 +152,10 @@ __global__ __launch_bounds__(256) void ttm_kernel(
     const void* __restrict__ X, int xdt, void* __restrict__ Y, int ydt,
     int64_t R, int n, const CT* __restrict__ Tt, int n_ct, int64_t n_rt) {
     __shared__ TtmShared<CT, KIND, SHAPE> sh;
+    // block blockIdx.y of R x n elements
+    const int64_t boff = (int64_t)blockIdx.y * R * n;
+    X = static_cast<const char*>(X) + boff * (xdt == TSVDM_F64 ? 8 : 4);
+    Y = static_cast<char*>(Y) + boff * (ydt == TSVDM_F64 ? 8 : 4);
     // XCD-aware block mapping: the n_ct column tiles of one row tile share
     // blockIdx % 8 (the same XCD and L2) and are dispatched together.
     const int64_t bid = blockIdx.x;
@@ -184,21 +191,28 @@ __global__ void ttm_prep_batch(const TtmProblem* __restrict__ probs, int nprob, 
 }
 
 template <class CT, int KIND, int SHAPE>
-int launch_tiles(const void* X, int xdt, void* Y, int ydt, int64_t R, int n, const CT* Tt,
-                 hipStream_t st) {
+int launch_tiles(const void* X, int xdt, void* Y, int ydt, int64_t R, int n, int64_t P,
+                 const CT* Tt, hipStream_t st) {
     constexpr int TR = TileShape<SHAPE>::TR, TI = TileShape<SHAPE>::TI;
     int n_ct = (n + TI - 1) / TI;
     int64_t n_rt = (R + TR - 1) / TR;
     int64_t n_rt8 = (n_rt + 7) / 8 * 8;
     int64_t blocks = n_rt8 * n_ct;
     TSVDM_REQUIRE(blocks < (int64_t)1 << 31, TSVDM_E_SHAPE, "tensor too large for one launch");
-    ttm_kernel<CT, KIND, SHAPE><<<(unsigned)blocks, 256, 0, st>>>(X, xdt, Y, ydt, R, n, Tt, n_ct, n_rt);
-    TSVDM_LAUNCH_CHECK();
+    const size_t xes = xdt == TSVDM_F64 ? 8 : 4, yes = ydt == TSVDM_F64 ? 8 : 4;
+    for (int64_t p0 = 0; p0 < P; p0 += 65535) {
+        const int64_t pc = P - p0 < 65535 ? P - p0 : 65535;
+        const void* Xp = static_cast<const char*>(X) + (size_t)(p0 * R * n) * xes;
+        void* Yp = static_cast<char*>(Y) + (size_t)(p0 * R * n) * yes;
+        ttm_kernel<CT, KIND, SHAPE><<<dim3((unsigned)blocks, (unsigned)pc), 256, 0, st>>>(
+            Xp, xdt, Yp, ydt, R, n, Tt, n_ct, n_rt);
+        TSVDM_LAUNCH_CHECK();
+    }
     return TSVDM_OK;
 }
 
 template <class CT, int KIND>
-int launch_ttm(const void* X, int xdt, void* Y, int ydt, int64_t R, int n,
+int launch_ttm(const void* X, int xdt, void* Y, int ydt, int64_t R, int n, int64_t P,
                const double* M, int transpose, double scale, int tile, void* ws,
                hipStream_t st) {
     CT* Tt = static_cast<CT*>(ws);
@@ -206,9 +220,9 @@ int launch_ttm(const void* X, int xdt, void* Y, int ydt, int64_t R, int n,
     ttm_prep<CT><<<(unsigned)((nn + 255) / 256), 256, 0, st>>>(M, n, transpose, scale, Tt);
     TSVDM_LAUNCH_CHECK();
     switch (tile ? tile : default_tile(n)) {
-        case 1: return launch_tiles<CT, KIND, 1>(X, xdt, Y, ydt, R, n, Tt, st);
-        case 2: return launch_tiles<CT, KIND, 2>(X, xdt, Y, ydt, R, n, Tt, st);
-        case 3: return launch_tiles<CT, KIND, 3>(X, xdt, Y, ydt, R, n, Tt, st);
+        case 1: return launch_tiles<CT, KIND, 1>(X, xdt, Y, ydt, R, n, P, Tt, st);
+        case 2: return launch_tiles<CT, KIND, 2>(X, xdt, Y, ydt, R, n, P, Tt, st);
+        case 3: return launch_tiles<CT, KIND, 3>(X, xdt, Y, ydt, R, n, P, Tt, st);
         default: set_error("unknown transform tile shape"); return TSVDM_E_ARG;
     }
 }
@@ -234,23 +248,28 @@ int launch_batch(const TtmProblem* probs, const int4* tasks, const int64_t* grou
 
 size_t ttm_workspace_bytes(int64_t n) { return align_up((size_t)(n * n) * sizeof(double)); }
 
-int run_ttm(const void* X, int xdt, void* Y, int ydt, int64_t m, int64_t p, int64_t n,
-            const double* M, int transpose, double scale, int compute, int tile, void* ws,
-            hipStream_t st) {
-    int64_t R = m * p;
+int run_ttm_mode(const void* X, int xdt, void* Y, int ydt, int64_t R, int64_t n, int64_t P,
+                 const double* M, int transpose, double scale, int compute, int tile, void* ws,
+                 hipStream_t st) {
     switch (compute) {
         case TSVDM_F64:
-            return launch_ttm<double, 0>(X, xdt, Y, ydt, R, (int)n, M, transpose, scale, tile, ws, st);
+            return launch_ttm<double, 0>(X, xdt, Y, ydt, R, (int)n, P, M, transpose, scale, tile, ws, st);
         case TSVDM_F32:
-            return launch_ttm<float, 0>(X, xdt, Y, ydt, R, (int)n, M, transpose, scale, tile, ws, st);
+            return launch_ttm<float, 0>(X, xdt, Y, ydt, R, (int)n, P, M, transpose, scale, tile, ws, st);
         case TSVDM_BF16:
-            return launch_ttm<float, 1>(X, xdt, Y, ydt, R, (int)n, M, transpose, scale, tile, ws, st);
+            return launch_ttm<float, 1>(X, xdt, Y, ydt, R, (int)n, P, M, transpose, scale, tile, ws, st);
         case TSVDM_BF16X3:
-            return launch_ttm<float, 2>(X, xdt, Y, ydt, R, (int)n, M, transpose, scale, tile, ws, st);
+            return launch_ttm<float, 2>(X, xdt, Y, ydt, R, (int)n, P, M, transpose, scale, tile, ws, st);
         default:
             set_error("unsupported compute dtype for the transform");
             return TSVDM_E_UNSUPPORTED;
     }
+}
+
+int run_ttm(const void* X, int xdt, void* Y, int ydt, int64_t m, int64_t p, int64_t n,
+            const double* M, int transpose, double scale, int compute, int tile, void* ws,
+            hipStream_t st) {
+    return run_ttm_mode(X, xdt, Y, ydt, m * p, n, 1, M, transpose, scale, compute, tile, ws, st);
 }
 
 int ttm_resolve_tile(int tile, int64_t n) { return tile ? tile : default_tile(n); }

@@ -39,6 +39,30 @@ def colmajor_empty(m: int, p: int, n: int, dtype, device="cuda") -> torch.Tensor
     return torch.empty((n, p, m), dtype=dtype, device=device).permute(2, 1, 0)
 
 
+def colmajor_empty_nd(dims, dtype, device="cuda") -> torch.Tensor:
+    """Uninitialised tensor of shape dims with column-major strides (mode 1 fastest)."""
+    d = len(dims)
+    return torch.empty(tuple(reversed(dims)), dtype=dtype, device=device).permute(*range(d - 1, -1, -1))
+
+
+def is_colmajor_nd(t: torch.Tensor) -> bool:
+    stride = 1
+    for size, st in zip(t.shape, t.stride()):
+        if size != 1 and st != stride:
+            return False
+        stride *= size
+    return True
+
+
+def as_colmajor_nd(t: torch.Tensor) -> torch.Tensor:
+    """t itself if column-major, else a column-major copy."""
+    if is_colmajor_nd(t):
+        return t
+    out = colmajor_empty_nd(tuple(t.shape), t.dtype, t.device)
+    out.copy_(t)
+    return out
+
+
 def is_colmajor(t: torch.Tensor) -> bool:
     m, p, n = t.shape
     return t.stride() == (1, m, m * p) or t.numel() <= 1
@@ -116,6 +140,35 @@ def tsvdm_transform(X, Mdev, transpose=False, scale=1.0, compute="f64", out_dtyp
     _lib.call("tsvdm_transform", _ptr(X), _dt(X), _ptr(Y), _dt(Y), m, p, n, _ptr(Mdev),
               int(bool(transpose)), float(scale), _COMPUTE[compute], int(tile), wp, wn, _stream())
     return Y
+
+
+def tsvdm_transform_mode(X, k, Mdev, transpose=False, scale=1.0, compute="f64", out_dtype=None,
+                         out=None, ws=None, tile=0):
+    """Y = X x_k (scale * op(M)) for a column-major order-d tensor X (3 <= k <= d)."""
+    X = as_colmajor_nd(X)
+    dims = tuple(int(x) for x in X.shape)
+    odt = out_dtype or (torch.float64 if compute == "f64" else torch.float32)
+    Y = out if out is not None else colmajor_empty_nd(dims, odt, X.device)
+    if tuple(Y.shape) != dims or not is_colmajor_nd(Y):
+        raise ValueError("out must be a column-major tensor of the input's shape")
+    d = len(dims)
+    dims_c = (ctypes.c_int64 * d)(*dims)
+    w = _ws(ws)
+    wp, wn = w.args(_lib.workspace_size("tsvdm_transform_workspace_size", dims[k - 1]))
+    _lib.call("tsvdm_transform_mode", _ptr(X), _dt(X), _ptr(Y), _dt(Y), d, dims_c, int(k),
+              _ptr(Mdev), int(bool(transpose)), float(scale), _COMPUTE[compute], int(tile), wp, wn,
+              _stream())
+    return Y
+
+
+def tsvdm_lowrank(U_pk, G_pk, rho, offsets, capacity, shape, out=None):
+    """C-hat with slice i = U_i G_i (transform domain, no back-transform)."""
+    m, p, n = shape
+    dt = U_pk.dtype
+    C = out if out is not None else colmajor_empty(m, p, n, dt, U_pk.device)
+    _lib.call("tsvdm_lowrank", _ptr(U_pk), _ptr(G_pk), _DT[dt], m, p, n, _ptr(rho), _ptr(offsets),
+              int(capacity), _ptr(C), _stream())
+    return C
 
 
 def tsvdm_slice_svd(A_hat, block=0, max_sweeps=0, tol=0.0, host_poll=True, ws=None):

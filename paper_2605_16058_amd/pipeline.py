@@ -121,6 +121,93 @@ def tsvdm(A, M, mode="II", k=None, eps=None, precision="f64", **kw) -> Result:
     return op(A)
 
 
+class TSVDMd:
+    """t-SVDM-I / t-SVDM-II of an order-d tensor n_1 x n_2 x n_3 x ... x n_d
+    (Section 2.1, footnote; Section 3.1): one transform M_k per mode k >= 3,
+    applied mode by mode (tsvdm_transform_mode, one launch per mode), then the
+    slice SVDs, rank selection and packing over the N = n_3...n_d frontal
+    slices as for three modes, the transform-domain low-rank product
+    (tsvdm_lowrank) and the back-transforms mode by mode.  For d = 3 it runs
+    the same kernels as TSVDM.  Result: as TSVDM (s2, rho, offsets over the
+    N slices in column-major order; A_rec of shape dims).
+    """
+
+    def __init__(self, dims, Ms, mode="II", k=None, eps=None, precision="f64", block=0,
+                 max_sweeps=0, tol=0.0, host_poll=True, device="cuda", tile=0):
+        self.dims = tuple(int(x) for x in dims)
+        if len(self.dims) < 3:
+            raise ValueError("order d >= 3")
+        if len(Ms) != len(self.dims) - 2:
+            raise ValueError("one transform per mode k >= 3")
+        if mode not in ("I", "II"):
+            raise ValueError("mode must be 'I' or 'II'")
+        if mode == "I" and (k is None or int(k) < 1):
+            raise ValueError("mode I needs k >= 1")
+        if mode == "II" and (eps is None or not (0.0 < float(eps) < 1.0)):
+            raise ValueError("mode II needs 0 < eps < 1")
+        if precision not in PRECISIONS:
+            raise ValueError(f"precision must be one of {list(PRECISIONS)}")
+        self.mode, self.k, self.eps, self.precision = mode, k, eps, precision
+        self.ttm_compute, self.dtype = PRECISIONS[precision]
+        self.c2 = [ops.check_transform(M) for M in Ms]
+        self.Mdev = [ops.device_matrix(M, device) for M in Ms]
+        self.block, self.max_sweeps, self.tol, self.host_poll = block, max_sweeps, tol, host_poll
+        self.tile, self.device = tile, device
+        self.m, self.p = self.dims[0], self.dims[1]
+        self.N = 1
+        for x in self.dims[2:]:
+            self.N *= x
+        self.r = min(self.m, self.p)
+        self.ws = ops.Workspace(device)
+
+    def __call__(self, A: torch.Tensor) -> Result:
+        A = ops.as_colmajor_nd(A)
+        if tuple(A.shape) != self.dims:
+            raise ValueError("shape mismatch")
+        d, m, p, N, r = len(self.dims), self.m, self.p, self.N, self.r
+        dt, comp = self.dtype, self.ttm_compute
+        bufs = [ops.colmajor_empty_nd(self.dims, dt, self.device) for _ in range(2 if d > 3 else 1)]
+        # 1. transforms along modes 3..d
+        cur = A
+        for j, kk in enumerate(range(3, d + 1)):
+            out = bufs[j % len(bufs)]
+            ops.tsvdm_transform_mode(cur, kk, self.Mdev[j], transpose=False, scale=1.0, compute=comp,
+                                     out_dtype=dt, out=out, ws=self.ws, tile=self.tile)
+            cur = out
+        A_hat = cur.permute(*range(d - 1, -1, -1)).reshape(N, p, m).permute(2, 1, 0)
+        # 2. slice SVDs over the N frontal slices
+        W, s2, svd_status = ops.tsvdm_slice_svd(A_hat, self.block, self.max_sweeps, self.tol,
+                                                self.host_poll, ws=self.ws)
+        # 3. ranks
+        if self.mode == "I":
+            rho, offsets = ops.tsvdm_truncate_rank(self.k, r, N, self.device)
+            stats = torch.full((4,), float("nan"), dtype=torch.float64, device=self.device)
+            cap = min(int(self.k), r) * N
+        else:
+            rho, offsets, stats = ops.tsvdm_truncate_tol(s2, self.eps, ws=self.ws)
+            cap = r * N
+        # 4. factors
+        U_pk, G_pk, S_pk, pack_status = ops.tsvdm_pack(A_hat, W, s2, rho, offsets, cap, ws=self.ws)
+        # 5. transform-domain low-rank product, then back-transforms mode by mode
+        other = bufs[1] if (d > 3 and cur.data_ptr() == bufs[0].data_ptr()) else bufs[0]
+        C3 = other.permute(*range(d - 1, -1, -1)).reshape(N, p, m).permute(2, 1, 0)
+        ops.tsvdm_lowrank(U_pk, G_pk, rho, offsets, cap, (m, p, N), out=C3)
+        A_rec = ops.colmajor_empty_nd(self.dims, dt, self.device)
+        cur = other
+        back = list(range(3, d + 1))
+        for j, kk in enumerate(back):
+            last = j == len(back) - 1
+            out = A_rec if last else (bufs[0] if cur.data_ptr() == bufs[-1].data_ptr() else bufs[-1])
+            ops.tsvdm_transform_mode(cur, kk, self.Mdev[kk - 3], transpose=True,
+                                     scale=1.0 / self.c2[kk - 3], compute=comp, out_dtype=dt, out=out,
+                                     ws=self.ws, tile=self.tile)
+            cur = out
+        # 6. error report
+        err = ops.tsvdm_error(A, A_rec, ws=self.ws)
+        return Result(A_rec, rho, offsets, U_pk, G_pk, S_pk, s2, stats, err, svd_status,
+                      pack_status, cap)
+
+
 class BatchTSVDM:
     """Many independent tensors of any shapes through one batch plan.
 

@@ -234,3 +234,24 @@ def test_batch_plan_validation_and_layout(lib):
     assert create([bad])[0] == -1
     bad = _item(); bad.n = 0
     assert create([bad])[0] == -2
+
+
+def test_transform_mode_validation(lib):
+    from ctypes import c_int64
+    dims = (c_int64 * 4)(5, 4, 3, 2)
+    ok = [DUMMY, 1, c_void_p(512), 1, 4, dims, 3, DUMMY, 0, 1.0, 1, 0, DUMMY, 1 << 20, None]
+    a = list(ok); a[6] = 2           # mode 2 is never transformed
+    assert lib.tsvdm_transform_mode(*a) == -1
+    a = list(ok); a[6] = 5           # k > d
+    assert lib.tsvdm_transform_mode(*a) == -1
+    a = list(ok); a[4] = 2           # d < 3
+    assert lib.tsvdm_transform_mode(*a) == -2
+    bad = (c_int64 * 4)(5, 0, 3, 2)
+    a = list(ok); a[5] = bad
+    assert lib.tsvdm_transform_mode(*a) == -2
+    a = list(ok); a[5] = None
+    assert lib.tsvdm_transform_mode(*a) == -1
+    a = list(ok); a[13] = 8          # workspace
+    assert lib.tsvdm_transform_mode(*a) == -4
+    assert lib.tsvdm_lowrank(DUMMY, DUMMY, 0, 8, 6, 3, DUMMY, DUMMY, -1, DUMMY, None) == -1
+    assert lib.tsvdm_lowrank(DUMMY, DUMMY, 5, 8, 6, 3, DUMMY, DUMMY, 4, DUMMY, None) == -8
