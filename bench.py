@@ -374,6 +374,138 @@ def bench_turbulence(a, torch, lib):
 
 
 # ---------------------------------------------------------------------------
+# order-6 climate tensor (Section 4.1's reshaped time axis)
+# ---------------------------------------------------------------------------
+
+def to_device_nd(A, torch):
+    """Fortran-ordered numpy array of any order -> column-major device tensor."""
+    import numpy as np
+    d = A.ndim
+    rev = tuple(range(d - 1, -1, -1))
+    return torch.from_numpy(np.ascontiguousarray(A.transpose(rev))).cuda().permute(*rev)
+
+
+def bench_climate6(a, torch, lib):
+    import numpy as np
+
+    import synth
+    from paper_2605_16058_amd import ops
+    from paper_2605_16058_amd.pipeline import TSVDMd
+
+    log("generating the order-6 climate-like tensor")
+    w = synth.workload("climate6", small=a.small)
+    dims = w.A.shape
+    Ad = to_device_nd(w.A, torch)
+    in_bytes = Ad.numel() * 4
+    eps = w.eps
+    n1, n2 = dims[0], dims[1]
+    flat_dims = (n1, n2, dims[2], int(np.prod(dims[3:])))
+    flat_M = [w.M[0], synth.dct2_matrix(flat_dims[3])]
+    block = a.block
+    tuned = {}
+    if not block and not a.no_tune:
+        t = {}
+        for b in (16, 32):
+            op = TSVDMd(dims, w.M, mode="II", eps=eps, precision="f32", block=b)
+            op(Ad)
+            torch.cuda.synchronize()
+            _, ms = timed(lambda: op(Ad), 1, torch)
+            t[b] = round(ms, 2)
+            del op
+        block = min(t, key=t.get)
+        tuned = {"block": block, "measured_ms": t}
+        log(f"block widths {t}: using {block}")
+
+    def run(d_, Ms, prec, stats=False):
+        op = TSVDMd(d_, Ms, mode="II", eps=eps, precision=prec, block=block)
+        # the same bytes viewed with other dimensions (column-major reshape)
+        X = Ad.permute(*range(len(dims) - 1, -1, -1)).reshape(*reversed(d_)).permute(
+            *range(len(d_) - 1, -1, -1))
+        for _ in range(a.warmup):
+            op(X)
+        if stats:
+            lib.tsvdm_stats_reset()
+            lib.tsvdm_stats_enable(1)
+        res, ms = timed(lambda: op(X), a.steps, torch)
+        st = None
+        if stats:
+            lib.tsvdm_stats_enable(0)
+            st = read_stats(lib)
+        # the forward transforms alone
+        Mdev = [ops.device_matrix(M) for M in Ms]
+        comp, dt = ("f64", torch.float64) if prec == "f64" else ("f32", torch.float32)
+        bufs = [ops.colmajor_empty_nd(d_, dt, "cuda") for _ in range(2)]
+
+        def fwd():
+            cur = X
+            for j, kk in enumerate(range(3, len(d_) + 1)):
+                out = bufs[j % 2]
+                ops.tsvdm_transform_mode(cur, kk, Mdev[j], compute=comp, out_dtype=dt, out=out)
+                cur = out
+        fwd()
+        _, ttm_ms = timed(fwd, a.steps, torch)
+        del bufs
+        return res, ms, ttm_ms, st
+
+    log(f"order 6 {dims}, FP32 mixed")
+    r6, ms6, ttm6, st = run(dims, w.M, "f32", stats=True)
+    roof = jacobi_roofline(st, PEAK["f32_TF"])
+    roof["src_sha"] = kernel_src_sha()
+    out = {}
+    if not a.no_f64:
+        log("order 6, FP64")
+        r64, ms64, ttm64, _ = run(dims, w.M, "f64")
+        d = ops.tsvdm_error(r64.A_rec, r6.A_rec).double().cpu()
+        nA = float(r64.err[1].cpu())
+        out = {"fp64_GBs": round(in_bytes / (ms64 * 1e-3) / 1e9, 3),
+               "fp64_ms_per_step": round(ms64, 3), "speedup_vs_fp64": round(ms64 / ms6, 3),
+               "fp64_rel_error": r64.rel_error(), "fp64_sum_rho": int(r64.offsets[-1].item()),
+               "mixed_vs_fp64_rel_diff": math.sqrt(float(d[0]) / nA) if nA > 0 else 0.0}
+        del r64
+        torch.cuda.empty_cache()
+    log(f"flat order 4 {flat_dims}, FP32 mixed")
+    r4, ms4, ttm4, _ = run(flat_dims, flat_M, "f32")
+    nslices = int(np.prod(dims[2:]))
+    rho6 = int(r6.offsets[-1].item())
+    rho4 = int(r4.offsets[-1].item())
+    cpu = None
+    if not a.no_cpu_baseline:
+        import oracle
+        days = min(30, dims[4])
+        sample = np.ascontiguousarray(w.A[:, :, :, :, :days, :1]).astype(np.float64)
+        sample = np.asfortranarray(sample)
+        Ms = [w.M[0], w.M[1], synth.dct2_matrix(days), np.eye(1)]
+        t0 = time.perf_counter()
+        oracle.tsvdm_d(sample, Ms, mode="II", eps=eps)
+        dt_ = time.perf_counter() - t0
+        sb = sample.size * 4
+        cpu = {"value": round(sb / dt_ / 1e9, 5), "unit": "GB/s", "cores": int(blas_threads()),
+               "kind": "oracle", "sample": f"the first {days} days of year 1 ({sample.shape}, DCT-II "
+               f"along each mode >= 3, tol {eps}), {dt_:.2f} s"}
+    return {
+        "metric": "input GB/s through t-SVDM-II of an order-6 tensor (mixed-prec vs FP64 GPU)",
+        "value": round(in_bytes / (ms6 * 1e-3) / 1e9, 3), "unit": "GB/s", "n_gpus": 1,
+        "steps": a.steps, "warmup": a.warmup, "ms_per_step": round(ms6, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"order-6 climate-like {'x'.join(map(str, dims))} (lat, lon, level, "
+                               f"time of day, day, year), DCT-II along modes 3-6, t-SVDM-II tol {eps}",
+                   "slices": nslices, "autotune": tuned},
+        "rel_error": r6.rel_error(), "sum_rho": rho6,
+        "compression_ratio": round(float(np.prod(dims)) / max(rho6 * (n1 + n2 + 1), 1), 3),
+        "ttm_forward_ms": round(ttm6, 3),
+        **out,
+        "flat_order4": {"dims": list(flat_dims), "GBs": round(in_bytes / (ms4 * 1e-3) / 1e9, 3),
+                        "ms_per_step": round(ms4, 3), "ttm_forward_ms": round(ttm4, 3),
+                        "rel_error": r4.rel_error(), "sum_rho": rho4,
+                        "compression_ratio": round(float(np.prod(dims)) / max(rho4 * (n1 + n2 + 1), 1), 3),
+                        "ttm_flop_ratio_vs_order6": round((flat_dims[2] + flat_dims[3]) / sum(dims[2:]), 2)},
+        "roofline": roof,
+        "cpu_baseline": cpu,
+    }
+
+
+# ---------------------------------------------------------------------------
 # cayley: gradient steps on the transform
 # ---------------------------------------------------------------------------
 
@@ -429,7 +561,7 @@ def main(argv=None):
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="climate",
-                    choices=["climate", "ragged", "turbulence", "cayley"])
+                    choices=["climate", "ragged", "turbulence", "cayley", "climate6"])
     ap.add_argument("--precision", default="f32", choices=["f32", "bf16x3", "bf16"])
     ap.add_argument("--eps", type=float, default=1e-3)
     ap.add_argument("--shape", default="512,1024,256")
@@ -439,7 +571,7 @@ def main(argv=None):
     ap.add_argument("--cpu-sample-tensors", type=int, default=16)
     ap.add_argument("--batch-count", type=int, default=512)
     ap.add_argument("--grad-steps", type=int, default=50)
-    ap.add_argument("--small", action="store_true", help="test-size turbulence / cayley inputs")
+    ap.add_argument("--small", action="store_true", help="test-size turbulence / cayley / climate6 inputs")
     ap.add_argument("--block", type=int, default=0, help="fixed Jacobi block width (skips tuning)")
     ap.add_argument("--no-tune", action="store_true", help="library defaults, no autotuner")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -468,7 +600,7 @@ def main(argv=None):
 
     lib = _lib.load()
     fn = {"climate": bench_climate, "ragged": bench_ragged, "turbulence": bench_turbulence,
-          "cayley": bench_cayley}[a.workload]
+          "cayley": bench_cayley, "climate6": bench_climate6}[a.workload]
     line = fn(a, torch, lib)
     print(json.dumps(line), flush=True)
     return 0

@@ -160,6 +160,57 @@ def climate_like(m: int = 512, p: int = 1024, n: int = 256, terms: int = 40,
     return A
 
 
+def climate6_like(lat: int = 73, lon: int = 144, levels: int = 17, days: int = 365,
+                  years: int = 2, terms: int = 40, noise: float = 0.01,
+                  rng: np.random.Generator | None = None, dtype=np.float32) -> np.ndarray:
+    """Order-6 climate-like field lat x lon x level x time-of-day (4) x
+    day-of-year x year, the layout of the paper's 6-way reanalysis tensor
+    (Section 4.1: the 6-hourly time axis split into time of day, day and
+    year).  Term l is a_l * cos(theta)^|m_l| cos(j_l theta + g_l)
+    * cos(m_l phi + al_l) * cos(pi k_l z + d_l) * cos(2 pi t / T_l + b_l), with z
+    the level in [0, 1], k_l ~ U{0..3}, t = tod + 4 (day + days * year) the
+    6-hourly time index and T_l in {4, 1460} steps as in climate_like; plus
+    `noise` * RMS Gaussian noise.  Column-major (Fortran) order."""
+    rng = np.random.default_rng(12) if rng is None else rng
+    nt = 4 * days * years
+    theta = np.linspace(-np.pi / 2, np.pi / 2, lat)
+    phi = np.arange(lon) * (2 * np.pi / lon)
+    z = np.linspace(0.0, 1.0, levels) if levels > 1 else np.zeros(1)
+    t = np.arange(nt, dtype=np.float64)
+    F_lat = np.empty((lat, terms))
+    F_lon = np.empty((lon, terms))
+    F_lev = np.empty((levels, terms))
+    F_t = np.empty((nt, terms))
+    for l in range(terms):
+        ml = int(rng.integers(0, 13))
+        jl = int(rng.integers(0, 9))
+        kl = int(rng.integers(0, 4))
+        T = 4.0 if rng.random() < 0.5 else 1460.0
+        g, al, dl, be = rng.uniform(0, 2 * np.pi, 4)
+        amp = 1.0 / (1.0 + ml + jl)
+        F_lat[:, l] = amp * np.cos(theta) ** ml * np.cos(jl * theta + g)
+        F_lon[:, l] = np.cos(ml * phi + al)
+        F_lev[:, l] = np.cos(np.pi * kl * z + dl)
+        F_t[:, l] = np.cos(2 * np.pi * t / T + be)
+    # (lat lon) x terms Khatri-Rao factor and (level time) x terms coefficients
+    KR = (F_lat[:, None, :] * F_lon[None, :, :]).reshape(lat * lon, terms, order="F")
+    N = levels * nt
+    gram = (F_lat.T @ F_lat) * (F_lon.T @ F_lon) * (F_lev.T @ F_lev) * (F_t.T @ F_t)
+    rms = math.sqrt(max(gram.sum(), 1e-300) / (lat * lon * N))
+    sigma = noise * rms
+    A = np.empty((lat * lon, N), dtype=dtype, order="F")
+    chunk = max(1, (1 << 24) // (lat * lon))
+    for s0 in range(0, N, chunk):
+        s1 = min(N, s0 + chunk)
+        idx = np.arange(s0, s1)
+        C = F_lev[idx % levels] * F_t[idx // levels]          # (s1-s0) x terms
+        block = KR @ C.T
+        if sigma > 0:
+            block += sigma * rng.standard_normal(block.shape)
+        A[:, s0:s1] = block
+    return A.reshape((lat, lon, levels, 4, days, years), order="F")
+
+
 def turbulence_like(m: int = 2048, p: int = 1024, n: int = 256,
                     rng: np.random.Generator | None = None,
                     dtype=np.float32, workers: int = -1) -> np.ndarray:
@@ -252,6 +303,8 @@ def workload(name: str, small: bool = False) -> Workload:
     ragged      : 512 uneven tensors (see ragged_batch).
     turbulence  : 2048x1024x256 k^-5/3 random field, Haar M, t-SVDM-II tol 1e-2.
     cayley      : 256x256x64 CP rank-24 + 5% noise, k=16, M = Cayley(K0).
+    climate6    : 73x144x17x4x365x2 order-6 climate-like field, DCT-II along
+                  every mode >= 3 (M is a list), t-SVDM-II tol 1e-2.
 
     `small=True` returns the same recipe at reduced size for quick tests.
     """
@@ -266,6 +319,10 @@ def workload(name: str, small: bool = False) -> Workload:
     if name == "ragged":
         return ragged_batch(count=24 if small else 512,
                             size_scale=0.35 if small else 1.0)
+    if name == "climate6":
+        dims = (24, 36, 5, 4, 12, 2) if small else (73, 144, 17, 4, 365, 2)
+        A = climate6_like(*dims[:3], days=dims[4], years=dims[5], rng=np.random.default_rng(12))
+        return Workload(name, A, [dct2_matrix(n) for n in dims[2:]], "II", eps=1e-2)
     if name == "turbulence":
         m, p, n = (192, 128, 32) if small else (2048, 1024, 256)
         rng = np.random.default_rng(4)

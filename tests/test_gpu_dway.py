@@ -123,3 +123,24 @@ def test_tsvdmd_matches_oracle(dims, mode, arg):
                 np.linalg.norm(ref["A_rec"]) / np.linalg.norm(A) <= 3e-5
         if mode == "II":
             assert res.rel_error() < arg
+
+
+def test_climate6_small_matches_oracle():
+    """The order-6 climate recipe at test size, FP64 and FP32, against tsvdm_d."""
+    from paper_2605_16058_amd.pipeline import TSVDMd
+    w = synth.workload("climate6", small=True)
+    A64 = w.A.astype(np.float64)
+    ref = O.tsvdm_d(A64, w.M, mode="II", eps=w.eps)
+    for prec, bound in (("f64", 1e-10), ("f32", 3e-5)):
+        res = TSVDMd(w.A.shape, w.M, mode="II", eps=w.eps, precision=prec)(to_dev_nd(w.A, torch.float32))
+        torch.cuda.synchronize()
+        rho = res.rho.cpu().numpy()
+        rho_o, _ = O.ranks_tolerance(res.s2.cpu().numpy().T, w.eps, squared=True)
+        assert np.array_equal(rho, rho_o)
+        if np.array_equal(rho, ref["rho"]):
+            d = rel(res.A_rec.double().cpu().numpy(), ref["A_rec"]) * \
+                np.linalg.norm(ref["A_rec"]) / np.linalg.norm(A64)
+            assert d <= bound, (prec, d)
+        else:
+            assert prec == "f32" or _margin(ref["S"], ref["info"]["tau"]) <= 1e-10
+        assert res.rel_error() < w.eps

@@ -245,3 +245,65 @@ def test_cayley_full_size_gradient():
         dAg = dA.double().cpu().numpy()
         assert np.linalg.norm((dAg - dA_o).ravel()) <= bound * 10 * np.linalg.norm(dA_o.ravel())
         assert np.linalg.norm(dM.cpu().numpy() - GM_o) <= bound * 10 * np.linalg.norm(GM_o)
+
+
+def test_climate6_full_size():
+    """73x144x17x4x365x2 order-6 climate-like tensor, DCT-II along modes 3-6,
+    tol 1e-2 (FP32 and FP64): ranks from the GPU's squares through the
+    oracle's exact selection, measured vs predicted error, and four sampled
+    slices: each transform-domain slice is the oracle's mode products with
+    one row of every M_k, its singular values within Weyl's bound of the
+    measured transform error and its packed factors' Eckart-Young tail."""
+    from paper_2605_16058_amd import ops
+    from paper_2605_16058_amd.pipeline import PRECISIONS, TSVDMd
+    w = synth.workload("climate6")
+    dims = w.A.shape
+    n1, n2 = dims[:2]
+    A64 = w.A.astype(np.float64)
+    Ad = ops.colmajor_empty_nd(dims, torch.float32, "cuda")
+    Ad.copy_(torch.from_numpy(np.asfortranarray(w.A)))
+    picks = [(0, 0, 0, 0), (3, 1, 17, 0), (16, 3, 364, 1), (8, 2, 100, 1)]
+    ref = {}
+    for idx in picks:
+        X = A64
+        for k in (5, 6, 4, 3):   # mode products commute; the longest mode first is cheapest
+            X = O.mode_product(X, np.asarray(w.M[k - 3])[idx[k - 3]:idx[k - 3] + 1, :], k)
+        ref[idx] = X.reshape(n1, n2)
+    del A64
+    for prec in ("f32", "f64"):
+        res = TSVDMd(dims, w.M, mode="II", eps=w.eps, precision=prec)(Ad)
+        torch.cuda.synchronize()
+        assert int(res.svd_status.item()) == 0 and int(res.pack_status.item()) == 0
+        s2 = res.s2.double().cpu().numpy()
+        rho = res.rho.cpu().numpy()
+        rho_o, info = O.ranks_tolerance(s2.T, w.eps, squared=True)
+        assert np.array_equal(rho, rho_o)
+        rel_e = res.rel_error()
+        pred = math.sqrt(info["discarded"] / info["total"])
+        assert rel_e < w.eps
+        assert abs(rel_e - pred) <= (1e-9 if prec == "f64" else 1e-2) * pred
+        # the run's own transforms, for the measured transform error of each sample
+        comp, dt = PRECISIONS[prec]
+        cur = Ad
+        bufs = [ops.colmajor_empty_nd(dims, dt, "cuda") for _ in range(2)]
+        for j, kk in enumerate(range(3, 7)):
+            ops.tsvdm_transform_mode(cur, kk, ops.device_matrix(w.M[j]), compute=comp, out_dtype=dt,
+                                     out=bufs[j % 2])
+            cur = bufs[j % 2]
+        c = 1e-12 if prec == "f64" else 2e-5
+        for idx in picks:
+            s = idx[0] + dims[2] * (idx[1] + dims[3] * (idx[2] + dims[4] * idx[3]))
+            Ah = ref[idx]
+            Ag = cur[:, :, idx[0], idx[1], idx[2], idx[3]].double().cpu().numpy()
+            e_i = float(np.linalg.norm((Ag - Ah).ravel()))
+            nrm = float(np.linalg.norm(Ah.ravel()))
+            so = np.linalg.svd(Ah, compute_uv=False)
+            sg = np.sqrt(np.sort(np.maximum(s2[s], 0.0))[::-1])
+            assert np.max(np.abs(sg - so)) <= e_i + c * so[0], (prec, idx)
+            k = int(rho[s])
+            tail_o = math.sqrt(float(np.sum(so[k:] ** 2)))
+            tail_g = float(np.linalg.norm((Ah - packed_slice(res, s, n1, n2)).ravel()))
+            assert tail_g >= tail_o * (1 - 1e-12) - 1e-14 * nrm, (prec, idx)
+            assert tail_g <= tail_o + e_i + c * nrm, (prec, idx, tail_g, tail_o, e_i)
+        del bufs, res
+        torch.cuda.empty_cache()
