@@ -610,48 +610,111 @@ __device__ __forceinline__ void round_body(RoundShared<T, NB2>& sh, T* __restric
         __syncthreads();
     }
 
-    // ---------------- phase 3: vectors <- Q^T vectors, W <- W Q (MFMA), prefetched
-    // (the layout flag is a compile-time constant in each of the two parts)
-    constexpr int UPW = NT * (TC / 16) / 4;  // output tiles per wave
+    // ---------------- phase 3: vectors <- Q^T vectors, W <- W Q (MFMA)
+    // Each wave owns the 16-position tiles wave, wave+4, ... of the vectors:
+    // it stages the 2b values of a tile in its own LDS region, multiplies by
+    // Q (shared, read-only here) and stores the result straight back to the
+    // same positions, so the waves never wait for each other.  Column
+    // families give D = Q^T old (MFMA lanes along positions), row families
+    // D^T = old^T Q (lanes along the contiguous vector index); either way
+    // 16 lanes store 64 contiguous bytes.
+    constexpr int PT = 16;                                    // positions per tile
+    constexpr int NA = NB2 * PT / (VW * 64);                  // 16-byte loads per lane and tile
     auto update = [&](auto rows_tag, T* base, int64_t vs, int64_t es, int64_t len, bool vec) {
         constexpr bool RW = decltype(rows_tag)::value;
-        const int64_t nc = (len + TC - 1) / TC;
-        for (int64_t c = 0; c < nc; ++c) {
-            // Ts was last read by the previous chunk's MFMA, which ended
-            // before the barrier ahead of its stores
-            regs_to_lds(RW, Ts);
-            __syncthreads();
-            if (c + 1 < nc) gload(base, vs, es, RW, vec, (c + 1) * TC, len);
-            AccT uacc[UPW];
+        constexpr int PLD = RW ? PT + 1 : PT;                  // odd stride spreads transposed stores
+        T* const stg = Ts + wave * NB2 * (PT + 1);
+        const int64_t ntile = (len + PT - 1) / PT;
+        T pre[NA][VW];
+        auto load_tile = [&](int64_t t0) {
 #pragma unroll
-            for (int j = 0; j < UPW; ++j) uacc[j] = zero4<AccT>();
+            for (int u = 0; u < NA; ++u) {
+                const int e = lane + 64 * u;
+                if (!RW) {
+                    const int c = e / (PT / VW), tt = (e % (PT / VW)) * VW;
+                    const int64_t gi = gidx(c), t = t0 + tt;
+                    const T* src = base + gi * vs + t;
+                    if (gi < r && vec && t + VW <= len) {
+                        if constexpr (sizeof(T) == 4) {
+                            const float4 x = *reinterpret_cast<const float4*>(src);
+                            pre[u][0] = x.x; pre[u][1] = x.y; pre[u][2] = x.z; pre[u][3] = x.w;
+                        } else {
+                            const double2 x = *reinterpret_cast<const double2*>(src);
+                            pre[u][0] = x.x; pre[u][1] = x.y;
+                        }
+                    } else {
+#pragma unroll
+                        for (int q = 0; q < VW; ++q) pre[u][q] = (gi < r && t + q < len) ? src[q] : T(0);
+                    }
+                } else {
+                    const int c = (e % (NB2 / VW)) * VW, tt = e / (NB2 / VW);
+                    const int64_t gi = gidx(c), t = t0 + tt;
+                    const T* src = base + gi + t * es;
+                    if (t < len && vec && gi + VW <= r) {
+                        if constexpr (sizeof(T) == 4) {
+                            const float4 x = *reinterpret_cast<const float4*>(src);
+                            pre[u][0] = x.x; pre[u][1] = x.y; pre[u][2] = x.z; pre[u][3] = x.w;
+                        } else {
+                            const double2 x = *reinterpret_cast<const double2*>(src);
+                            pre[u][0] = x.x; pre[u][1] = x.y;
+                        }
+                    } else {
+#pragma unroll
+                        for (int q = 0; q < VW; ++q) pre[u][q] = (t < len && gi + q < r) ? src[q] : T(0);
+                    }
+                }
+            }
+        };
+        int64_t tile = wave;
+        if (tile < ntile) load_tile(tile * PT);
+        for (; tile < ntile; tile += 4) {
+            // stage the tile: stg[c * PLD + t]
+#pragma unroll
+            for (int u = 0; u < NA; ++u) {
+                const int e = lane + 64 * u;
+                if (!RW) {
+                    const int c = e / (PT / VW), tt = (e % (PT / VW)) * VW;
+#pragma unroll
+                    for (int q = 0; q < VW; ++q) stg[c * PLD + tt + q] = pre[u][q];
+                } else {
+                    const int c = (e % (NB2 / VW)) * VW, tt = e / (NB2 / VW);
+#pragma unroll
+                    for (int q = 0; q < VW; ++q) stg[(c + q) * PLD + tt] = pre[u][q];
+                }
+            }
+            // the wave's own LDS stores before its reads (LDS is in order per wave)
+            __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+            if (tile + 4 < ntile) load_tile((tile + 4) * PT);
+            AccT acc[NT];
+#pragma unroll
+            for (int ta = 0; ta < NT; ++ta) acc[ta] = zero4<AccT>();
 #pragma unroll 4
             for (int kk = 0; kk < NB2; kk += 4) {
+                const T b = stg[(kk + lg) * PLD + lr];                  // old[c][t]
 #pragma unroll
-                for (int j = 0; j < UPW; ++j) {
-                    const int q = wave * UPW + j, ta = q / (TC / 16), tt = q % (TC / 16);
-                    const T a = Qs[C::q_idx(ta * 16 + lr, kk + lg)];  // Q[c][a]
-                    const int rc = kk + lg;
-                    const T b = Ts[rc * LDP + sw(RW, rc, tt * 16 + lr)];  // old[c][t]
-                    uacc[j] = mfma(a, b, uacc[j]);
+                for (int ta = 0; ta < NT; ++ta) {
+                    const T q = Qs[C::q_idx(ta * 16 + lr, kk + lg)];   // Q[c][a]
+                    acc[ta] = RW ? mfma(b, q, acc[ta]) : mfma(q, b, acc[ta]);
                 }
             }
+            __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+            const int64_t t0 = tile * PT;
 #pragma unroll
-            for (int j = 0; j < UPW; ++j) {
-                const int q = wave * UPW + j, ta = q / (TC / 16), tt = q % (TC / 16);
+            for (int ta = 0; ta < NT; ++ta) {
 #pragma unroll
                 for (int v = 0; v < 4; ++v) {
-                    const int ro = ta * 16 + mfma_row<T>(lg, v);
-                    Ts2[ro * LDP + sw(RW, ro, tt * 16 + lr)] = uacc[j][v];
+                    if (!RW) {
+                        const int64_t gi = gidx(ta * 16 + mfma_row<T>(lg, v)), t = t0 + lr;
+                        if (gi < r && t < len) base[gi * vs + t] = acc[ta][v];
+                    } else {
+                        const int64_t gi = gidx(ta * 16 + lr), t = t0 + mfma_row<T>(lg, v);
+                        if (gi < r && t < len) base[gi + t * es] = acc[ta][v];
+                    }
                 }
             }
-            __syncthreads();
-            gstore(base, vs, es, RW, vec, c * TC, len);
         }
     };
-    gload(Ab, g.vs, g.es, ROWS, vec_a != 0, 0, L);
     update(std::integral_constant<bool, ROWS>(), Ab, g.vs, g.es, L, vec_a != 0);
-    gload(Wb, r, 1, false, vec_w != 0, 0, r);
     update(std::integral_constant<bool, false>(), Wb, r, 1, r, vec_w != 0);
 }
 
