@@ -191,25 +191,26 @@ __global__ void jacobi_init(T* __restrict__ W, int64_t r, int64_t n, JacobiCtl* 
     }
 }
 
-// Chunk geometry: every staged chunk is 16 KB (NB2 vectors x TC elements),
-// i.e. four 16-byte vector loads per thread.  The pair Gram matrix H lives
-// in the staging region as two packed symmetric FP64 buffers (one per
-// parity of the inner step); Q is stored transposed (row a = column a of Q)
-// with the 16-byte groups of row a XOR-swizzled by a, so that row accesses
-// are 16-byte vectors and column reads of 16 rows hit distinct banks.
+// Shared-memory layout of one pair.  Both MFMA phases stream the L
+// positions in tiles of PT, each wave through its own staging region of STG
+// elements (enough for either phase's layout).  The pair Gram matrix H
+// lives in the same region afterwards as two packed symmetric FP64 buffers
+// (one per parity of the inner step); Q is stored transposed (row a =
+// column a of Q) with the 16-byte groups of row a XOR-swizzled by a, so that
+// row accesses are 16-byte vectors and column reads of 16 rows hit distinct
+// banks.
 template <class T, int NB2>
 struct RoundCfg {
     static constexpr int VW = 16 / sizeof(T);                  // elements per 16-byte access
-    static constexpr int TC = 16384 / (NB2 * (int)sizeof(T));  // chunk length
-    static constexpr int LDP = TC + VW;                        // padded LDS row (16-byte aligned)
-    static constexpr int NV = NB2 * TC / VW / 256;             // vector accesses per thread
+    static constexpr int PT = 16;                              // positions per tile
+    static constexpr int STG = PT * (NB2 + 16);                // staging elements per wave
     static constexpr int NT = NB2 / 16;                        // 16x16 tiles per dimension
     static constexpr int NPH = NB2 / 2;                        // rotations per inner step
     static constexpr int NH = NB2 * (NB2 + 1) / 2;             // packed symmetric H
     static constexpr int SWM = (NB2 / VW < 16 ? NB2 / VW : 16) - 1;  // Q swizzle mask
-    static constexpr size_t ts_bytes = sizeof(T) * NB2 * LDP;
+    static constexpr size_t stg_bytes = sizeof(T) * 4 * STG;
     static constexpr size_t hs_bytes = sizeof(double) * 2 * NH;
-    static constexpr size_t r1 = (2 * ts_bytes > hs_bytes) ? 2 * ts_bytes : hs_bytes;
+    static constexpr size_t r1 = (stg_bytes > hs_bytes) ? stg_bytes : hs_bytes;
     static constexpr size_t q_bytes = sizeof(T) * NB2 * NB2;
     static constexpr size_t total = r1 + q_bytes;
     // waves per SIMD the kernel is compiled for: three workgroups per compute
@@ -219,10 +220,6 @@ struct RoundCfg {
     static __device__ __forceinline__ int q_idx(int a, int c) { return a * NB2 + (c ^ ((a & SWM) * VW)); }
 };
 
-// One block pair (pair k of round rnd) of one slice: Ab / Wb are the slice
-// and its rotation accumulator, ctl_s its control word.
-//   ROWS: the Jacobi vectors are slice rows (m < p), else columns.
-//   vec_a / vec_w: 16-byte accesses are legal for the slice / for W.
 template <class T, int NB2>
 struct RoundShared {
     __align__(16) char smem[RoundCfg<T, NB2>::total];
@@ -239,7 +236,7 @@ __device__ __forceinline__ void round_body(RoundShared<T, NB2>& sh, T* __restric
                                            unsigned long long* __restrict__ pair_counts) {
     typedef RoundCfg<T, NB2> C;
     typedef typename Acc<T>::type AccT;
-    constexpr int B = NB2 / 2, VW = C::VW, TC = C::TC, LDP = C::LDP, NV = C::NV;
+    constexpr int B = NB2 / 2, VW = C::VW;
     constexpr int NT = C::NT, NH = C::NH;
 
     char* smem = sh.smem;
@@ -247,8 +244,7 @@ __device__ __forceinline__ void round_body(RoundShared<T, NB2>& sh, T* __restric
     double* redw = sh.redw;
     int& flag_nf = sh.flag_nf;
 
-    T* Ts = reinterpret_cast<T*>(smem);                           // [NB2][LDP] staged input
-    T* Ts2 = reinterpret_cast<T*>(smem + C::ts_bytes);            // [NB2][LDP] staged output
+    T* Ts = reinterpret_cast<T*>(smem);                           // [4][STG] per-wave staging
     double* H0 = reinterpret_cast<double*>(smem);                 // [2][NH] packed H (phase 2)
     T* Qs = reinterpret_cast<T*>(smem + C::r1);                   // [NB2][NB2] Q^T, swizzled
 
@@ -261,160 +257,124 @@ __device__ __forceinline__ void round_body(RoundShared<T, NB2>& sh, T* __restric
     const int lr = lane & 15, lg = lane >> 4;
 
     auto gidx = [&](int a) -> int64_t { return a < B ? (int64_t)I * B + a : (int64_t)J * B + (a - B); };
-    // Staging layout: element (vector a, position t) at a * LDP + sw(a, t).
-    // Row families are transposed on the way into LDS (scalar stores down a
-    // column); in FP32 the 4-element groups of row a are XOR-swizzled by
-    // bits 2..4 of a so those stores spread over the banks.  Groups of 4
-    // stay contiguous, so the MFMA operand reads are unaffected in shape.
-    auto sw = [&](bool rows, int a, int t) -> int {
-        return (rows && sizeof(T) == 4) ? (t ^ (((a >> 2) & 7) << 2)) : t;
-    };
 
-    // ---- global <-> register <-> LDS streaming of one chunk [t0, t0 + TC)
-    // Access e of a thread covers VW consecutive elements along the
-    // contiguous direction: t for column families, the vector index a for
-    // row families (a block of B rows is contiguous, B % VW == 0).
-    T regs[NV][VW];
-    auto gload = [&](const T* base, int64_t vs, int64_t es, bool rows, bool vec, int64_t t0,
-                     int64_t len) {
-#pragma unroll
-        for (int v = 0; v < NV; ++v) {
-            const int e = tid + 256 * v;
-            if (!rows) {
-                const int a = e / (TC / VW), tt = (e % (TC / VW)) * VW;
-                const int64_t gi = gidx(a), t = t0 + tt;
-                const T* src = base + gi * vs + t;
-                if (gi < r && vec && t + VW <= len) {
-                    if constexpr (sizeof(T) == 4) {
-                        float4 x = *reinterpret_cast<const float4*>(src);
-                        regs[v][0] = x.x; regs[v][1] = x.y; regs[v][2] = x.z; regs[v][3] = x.w;
-                    } else {
-                        double2 x = *reinterpret_cast<const double2*>(src);
-                        regs[v][0] = x.x; regs[v][1] = x.y;
-                    }
-                } else {
-#pragma unroll
-                    for (int j = 0; j < VW; ++j) regs[v][j] = (gi < r && t + j < len) ? src[j] : T(0);
-                }
-            } else {
-                const int a4 = (e % (NB2 / VW)) * VW, tt = e / (NB2 / VW);
-                const int64_t gi = gidx(a4), t = t0 + tt;
-                const T* src = base + gi + t * es;
-                if (t < len && vec && gi + VW <= r) {
-                    if constexpr (sizeof(T) == 4) {
-                        float4 x = *reinterpret_cast<const float4*>(src);
-                        regs[v][0] = x.x; regs[v][1] = x.y; regs[v][2] = x.z; regs[v][3] = x.w;
-                    } else {
-                        double2 x = *reinterpret_cast<const double2*>(src);
-                        regs[v][0] = x.x; regs[v][1] = x.y;
-                    }
-                } else {
-#pragma unroll
-                    for (int j = 0; j < VW; ++j) regs[v][j] = (t < len && gi + j < r) ? src[j] : T(0);
-                }
-            }
-        }
+    // ---- position tiles.  Wave w takes the tiles w, w + 4, ... of PT
+    // positions, loads the 2b values of a tile into registers one tile
+    // ahead, stages them in its own LDS region and runs its MFMAs from there,
+    // so the waves of one phase never wait for each other.  Load u of a lane
+    // covers VW consecutive elements along the contiguous direction: the
+    // positions for column families, the vector index for row families (a
+    // block of b rows is contiguous, b % VW == 0).
+    constexpr int PT = C::PT;
+    constexpr int NA = NB2 * PT / (VW * 64);                  // 16-byte loads per lane and tile
+    T* const stg = Ts + wave * C::STG;
+    T pre[NA][VW];
+    // (vector c, position tt) of the first element of load u
+    auto origin = [&](bool rw, int u, int& c, int& tt) {
+        const int e = lane + 64 * u;
+        if (!rw) { c = e / (PT / VW); tt = (e % (PT / VW)) * VW; }
+        else { c = (e % (NB2 / VW)) * VW; tt = e / (NB2 / VW); }
     };
-    auto regs_to_lds = [&](bool rows, T* dst) {
+    auto load_tile = [&](bool rw, const T* base, int64_t vs, int64_t es, int64_t len, bool vec,
+                         int64_t t0) {
 #pragma unroll
-        for (int v = 0; v < NV; ++v) {
-            const int e = tid + 256 * v;
-            if (!rows) {
-                const int a = e / (TC / VW), tt = (e % (TC / VW)) * VW;
-#pragma unroll
-                for (int j = 0; j < VW; ++j) dst[a * LDP + tt + j] = regs[v][j];
-            } else {
-                const int a4 = (e % (NB2 / VW)) * VW, tt = e / (NB2 / VW);
-#pragma unroll
-                for (int j = 0; j < VW; ++j) dst[(a4 + j) * LDP + sw(true, a4 + j, tt)] = regs[v][j];
-            }
-        }
-    };
-    auto gstore = [&](T* base, int64_t vs, int64_t es, bool rows, bool vec, int64_t t0,
-                      int64_t len) {
-#pragma unroll
-        for (int v = 0; v < NV; ++v) {
-            const int e = tid + 256 * v;
-            if (!rows) {
-                const int a = e / (TC / VW), tt = (e % (TC / VW)) * VW;
-                const int64_t gi = gidx(a), t = t0 + tt;
-                if (gi >= r) continue;
-                T* dst = base + gi * vs + t;
-                const T* src = Ts2 + a * LDP + tt;
-                if (vec && t + VW <= len) {
-                    if constexpr (sizeof(T) == 4)
-                        *reinterpret_cast<float4*>(dst) = make_float4(src[0], src[1], src[2], src[3]);
-                    else
-                        *reinterpret_cast<double2*>(dst) = make_double2(src[0], src[1]);
+        for (int u = 0; u < NA; ++u) {
+            int c, tt;
+            origin(rw, u, c, tt);
+            const int64_t gi = gidx(c), t = t0 + tt;
+            const bool full = rw ? (t < len && vec && gi + VW <= r) : (gi < r && vec && t + VW <= len);
+            const T* src = rw ? base + gi + t * es : base + gi * vs + t;
+            if (full) {
+                if constexpr (sizeof(T) == 4) {
+                    const float4 x = *reinterpret_cast<const float4*>(src);
+                    pre[u][0] = x.x; pre[u][1] = x.y; pre[u][2] = x.z; pre[u][3] = x.w;
                 } else {
-#pragma unroll
-                    for (int j = 0; j < VW; ++j)
-                        if (t + j < len) dst[j] = src[j];
+                    const double2 x = *reinterpret_cast<const double2*>(src);
+                    pre[u][0] = x.x; pre[u][1] = x.y;
                 }
             } else {
-                const int a4 = (e % (NB2 / VW)) * VW, tt = e / (NB2 / VW);
-                const int64_t gi = gidx(a4), t = t0 + tt;
-                if (t >= len) continue;
-                T* dst = base + gi + t * es;
-                T x[VW];
 #pragma unroll
-                for (int j = 0; j < VW; ++j) x[j] = Ts2[(a4 + j) * LDP + sw(true, a4 + j, tt)];
-                if (vec && gi + VW <= r) {
-                    if constexpr (sizeof(T) == 4)
-                        *reinterpret_cast<float4*>(dst) = make_float4(x[0], x[1], x[2], x[3]);
-                    else
-                        *reinterpret_cast<double2*>(dst) = make_double2(x[0], x[1]);
-                } else {
-#pragma unroll
-                    for (int j = 0; j < VW; ++j)
-                        if (gi + j < r) dst[j] = x[j];
+                for (int q = 0; q < VW; ++q) {
+                    const bool ok = rw ? (t < len && gi + q < r) : (gi < r && t + q < len);
+                    pre[u][q] = ok ? src[q] : T(0);
                 }
             }
         }
     };
 
-    // ---------------- phase 1: Gram matrix H of the pair (MFMA), prefetched
-    // Chunks alternate between the two staging buffers, so one barrier per
-    // chunk suffices.
-    constexpr int TPW = NT * NT / 4;
-    AccT hacc[TPW];
+    // ---------------- phase 1: Gram matrix H of the pair (MFMA)
+    // Each wave sums its own tiles into a partial Gram matrix, forming only
+    // the NT (NT + 1) / 2 tiles on and above the diagonal from NT operand
+    // fragments per four positions.  Staging rows are padded so that the
+    // fragment reads hit distinct banks: column families keep one vector per
+    // row of PT + VW elements, row families one position per row of NB2 + 16.
+    // Each MFMA sums four consecutive positions (summing positions in a
+    // strided order within one MFMA was measured to leave the FP32 results
+    // several times further from the FP64 ones on smooth inputs).  The four
+    // partials are added into the packed FP64 H one wave after the other: no
+    // atomics, so the result does not depend on timing.
+    constexpr int NTT = NT * (NT + 1) / 2;
+    constexpr int GPC = PT + VW, GPR = NB2 + 16;
+    AccT hacc[NTT];
 #pragma unroll
-    for (int j = 0; j < TPW; ++j) hacc[j] = zero4<AccT>();
-    const int64_t nch = (L + TC - 1) / TC;
-    gload(Ab, g.vs, g.es, ROWS, vec_a != 0, 0, L);
-    for (int64_t c = 0; c < nch; ++c) {
-        T* const buf = (c & 1) ? Ts2 : Ts;
-        regs_to_lds(ROWS, buf);
+    for (int q = 0; q < NTT; ++q) hacc[q] = zero4<AccT>();
+    {
+        const int64_t ntile = (L + PT - 1) / PT;
+        int64_t tile = wave;
+        if (tile < ntile) load_tile(ROWS, Ab, g.vs, g.es, L, vec_a != 0, tile * PT);
+        for (; tile < ntile; tile += 4) {
+#pragma unroll
+            for (int u = 0; u < NA; ++u) {
+                int c, tt;
+                origin(ROWS, u, c, tt);
+                T* const dst = ROWS ? stg + tt * GPR + c : stg + c * GPC + tt;
+                if constexpr (sizeof(T) == 4)
+                    *reinterpret_cast<float4*>(dst) = make_float4(pre[u][0], pre[u][1], pre[u][2], pre[u][3]);
+                else
+                    *reinterpret_cast<double2*>(dst) = make_double2(pre[u][0], pre[u][1]);
+            }
+            // the wave's own LDS stores before its reads (LDS is in order per wave)
+            __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+            if (tile + 4 < ntile) load_tile(ROWS, Ab, g.vs, g.es, L, vec_a != 0, (tile + 4) * PT);
+#pragma unroll
+            for (int kk = 0; kk < PT; kk += 4) {
+                T f[NT];
+#pragma unroll
+                for (int i = 0; i < NT; ++i)
+                    f[i] = ROWS ? stg[(kk + lg) * GPR + 16 * i + lr] : stg[(16 * i + lr) * GPC + kk + lg];
+                int q = 0;
+#pragma unroll
+                for (int i = 0; i < NT; ++i) {
+#pragma unroll
+                    for (int j = i; j < NT; ++j, ++q) hacc[q] = mfma(f[i], f[j], hacc[q]);
+                }
+            }
+            __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+        }
+    }
+    __syncthreads();   // the staging regions overlap H
+    for (int w = 0; w < 4; ++w) {
+        if (wave == w) {
+            int q = 0;
+#pragma unroll
+            for (int i = 0; i < NT; ++i) {
+#pragma unroll
+                for (int j = i; j < NT; ++j, ++q) {
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) {
+                        const int a = i * 16 + mfma_row<T>(lg, v), c = j * 16 + lr;
+                        if (a <= c) {
+                            const double x = (double)hacc[q][v];
+                            double& h = H0[sym_idx(a, c)];
+                            h = (w == 0) ? x : h + x;
+                        }
+                    }
+                }
+            }
+        }
+        if (w == 0 && tid == 0) flag_nf = 0;
         __syncthreads();
-        if (c + 1 < nch) gload(Ab, g.vs, g.es, ROWS, vec_a != 0, (c + 1) * TC, L);
-        // (Each MFMA sums four consecutive positions.  Reading four positions
-        // per lane with one 16-byte load, i.e. summing positions in a strided
-        // order, was measured 2% faster but left the FP32 results 8x further
-        // from the FP64 ones on smooth inputs, so the plain order is kept.)
-#pragma unroll 4
-        for (int kk = 0; kk < TC; kk += 4) {
-#pragma unroll
-            for (int j = 0; j < TPW; ++j) {
-                const int q = wave * TPW + j, tr = q / NT, tc = q % NT;
-                const int ra = tr * 16 + lr, rb = tc * 16 + lr;
-                const T a = buf[ra * LDP + sw(ROWS, ra, kk + lg)];
-                const T b = buf[rb * LDP + sw(ROWS, rb, kk + lg)];
-                hacc[j] = mfma(a, b, hacc[j]);
-            }
-        }
     }
-    __syncthreads();
-#pragma unroll
-    for (int j = 0; j < TPW; ++j) {
-        const int q = wave * TPW + j, tr = q / NT, tc = q % NT;
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-            const int a = tr * 16 + mfma_row<T>(lg, v), c = tc * 16 + lr;
-            if (a <= c) H0[sym_idx(a, c)] = (double)hacc[j][v];
-        }
-    }
-    if (tid == 0) flag_nf = 0;
-    __syncthreads();
 
     // ---------------- convergence measure (FP64): max |cos| over valid pairs,
     // separately for pairs inside one block and pairs across the two blocks
@@ -618,73 +578,27 @@ __device__ __forceinline__ void round_body(RoundShared<T, NB2>& sh, T* __restric
     // families give D = Q^T old (MFMA lanes along positions), row families
     // D^T = old^T Q (lanes along the contiguous vector index); either way
     // 16 lanes store 64 contiguous bytes.
-    constexpr int PT = 16;                                    // positions per tile
-    constexpr int NA = NB2 * PT / (VW * 64);                  // 16-byte loads per lane and tile
     auto update = [&](auto rows_tag, T* base, int64_t vs, int64_t es, int64_t len, bool vec) {
         constexpr bool RW = decltype(rows_tag)::value;
         constexpr int PLD = RW ? PT + 1 : PT;                  // odd stride spreads transposed stores
-        T* const stg = Ts + wave * NB2 * (PT + 1);
         const int64_t ntile = (len + PT - 1) / PT;
-        T pre[NA][VW];
-        auto load_tile = [&](int64_t t0) {
-#pragma unroll
-            for (int u = 0; u < NA; ++u) {
-                const int e = lane + 64 * u;
-                if (!RW) {
-                    const int c = e / (PT / VW), tt = (e % (PT / VW)) * VW;
-                    const int64_t gi = gidx(c), t = t0 + tt;
-                    const T* src = base + gi * vs + t;
-                    if (gi < r && vec && t + VW <= len) {
-                        if constexpr (sizeof(T) == 4) {
-                            const float4 x = *reinterpret_cast<const float4*>(src);
-                            pre[u][0] = x.x; pre[u][1] = x.y; pre[u][2] = x.z; pre[u][3] = x.w;
-                        } else {
-                            const double2 x = *reinterpret_cast<const double2*>(src);
-                            pre[u][0] = x.x; pre[u][1] = x.y;
-                        }
-                    } else {
-#pragma unroll
-                        for (int q = 0; q < VW; ++q) pre[u][q] = (gi < r && t + q < len) ? src[q] : T(0);
-                    }
-                } else {
-                    const int c = (e % (NB2 / VW)) * VW, tt = e / (NB2 / VW);
-                    const int64_t gi = gidx(c), t = t0 + tt;
-                    const T* src = base + gi + t * es;
-                    if (t < len && vec && gi + VW <= r) {
-                        if constexpr (sizeof(T) == 4) {
-                            const float4 x = *reinterpret_cast<const float4*>(src);
-                            pre[u][0] = x.x; pre[u][1] = x.y; pre[u][2] = x.z; pre[u][3] = x.w;
-                        } else {
-                            const double2 x = *reinterpret_cast<const double2*>(src);
-                            pre[u][0] = x.x; pre[u][1] = x.y;
-                        }
-                    } else {
-#pragma unroll
-                        for (int q = 0; q < VW; ++q) pre[u][q] = (t < len && gi + q < r) ? src[q] : T(0);
-                    }
-                }
-            }
-        };
         int64_t tile = wave;
-        if (tile < ntile) load_tile(tile * PT);
+        if (tile < ntile) load_tile(RW, base, vs, es, len, vec, tile * PT);
         for (; tile < ntile; tile += 4) {
             // stage the tile: stg[c * PLD + t]
 #pragma unroll
             for (int u = 0; u < NA; ++u) {
-                const int e = lane + 64 * u;
-                if (!RW) {
-                    const int c = e / (PT / VW), tt = (e % (PT / VW)) * VW;
+                int c, tt;
+                origin(RW, u, c, tt);
 #pragma unroll
-                    for (int q = 0; q < VW; ++q) stg[c * PLD + tt + q] = pre[u][q];
-                } else {
-                    const int c = (e % (NB2 / VW)) * VW, tt = e / (NB2 / VW);
-#pragma unroll
-                    for (int q = 0; q < VW; ++q) stg[(c + q) * PLD + tt] = pre[u][q];
+                for (int q = 0; q < VW; ++q) {
+                    if (!RW) stg[c * PLD + tt + q] = pre[u][q];
+                    else stg[(c + q) * PLD + tt] = pre[u][q];
                 }
             }
             // the wave's own LDS stores before its reads (LDS is in order per wave)
             __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
-            if (tile + 4 < ntile) load_tile((tile + 4) * PT);
+            if (tile + 4 < ntile) load_tile(RW, base, vs, es, len, vec, (tile + 4) * PT);
             AccT acc[NT];
 #pragma unroll
             for (int ta = 0; ta < NT; ++ta) acc[ta] = zero4<AccT>();
