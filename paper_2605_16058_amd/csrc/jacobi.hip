@@ -195,7 +195,9 @@ __global__ void jacobi_init(T* __restrict__ W, int64_t r, int64_t n, JacobiCtl* 
 // positions in tiles of PT, each wave through its own staging region of STG
 // elements (enough for either phase's layout).  The pair Gram matrix H
 // lives in the same region afterwards as two packed symmetric FP64 buffers
-// (one per parity of the inner step); Q is stored transposed (row a =
+// (one per parity of the inner step); while the first is being written, the
+// partial Gram matrices of three waves sit right behind it.  Q is stored
+// transposed (row a =
 // column a of Q) with the 16-byte groups of row a XOR-swizzled by a, so that
 // row accesses are 16-byte vectors and column reads of 16 rows hit distinct
 // banks.
@@ -212,7 +214,11 @@ struct RoundCfg {
     static constexpr size_t hs_bytes = sizeof(double) * 2 * NH;
     static constexpr size_t r1 = (stg_bytes > hs_bytes) ? stg_bytes : hs_bytes;
     static constexpr size_t q_bytes = sizeof(T) * NB2 * NB2;
-    static constexpr size_t total = r1 + q_bytes;
+    // partial Gram matrices of three waves, parked behind the first H buffer
+    static constexpr int NTT = NT * (NT + 1) / 2;
+    static constexpr size_t rp_off = (sizeof(double) * NH + 15) / 16 * 16;
+    static constexpr size_t rp_end = rp_off + sizeof(T) * 3 * NTT * 256;
+    static constexpr size_t total = (r1 + q_bytes > rp_end) ? r1 + q_bytes : rp_end;
     // waves per SIMD the kernel is compiled for: three workgroups per compute
     // unit when the LDS allows it (FP32), else two
     static constexpr int WAVES = (3 * (total + 2048) <= 160 * 1024) ? 3 : 2;
@@ -224,7 +230,7 @@ template <class T, int NB2>
 struct RoundShared {
     __align__(16) char smem[RoundCfg<T, NB2>::total];
     double2 rot_cs[2][NB2 / 2];   // (c, s) of each rotation, per parity of the inner step
-    double red[4], redw[4];
+    double mc_cross, mc_within;   // convergence measure of the pair
     int flag_nf;
 };
 
@@ -240,8 +246,6 @@ __device__ __forceinline__ void round_body(RoundShared<T, NB2>& sh, T* __restric
     constexpr int NT = C::NT, NH = C::NH;
 
     char* smem = sh.smem;
-    double* red = sh.red;
-    double* redw = sh.redw;
     int& flag_nf = sh.flag_nf;
 
     T* Ts = reinterpret_cast<T*>(smem);                           // [4][STG] per-wave staging
@@ -306,15 +310,14 @@ __device__ __forceinline__ void round_body(RoundShared<T, NB2>& sh, T* __restric
     // Each wave sums its own tiles into a partial Gram matrix, forming only
     // the NT (NT + 1) / 2 tiles on and above the diagonal from NT operand
     // fragments per four positions.  Staging rows are padded so that the
-    // fragment reads hit distinct banks: column families keep one vector per
-    // row of PT + VW elements, row families one position per row of NB2 + 16.
+    // fragment reads of each half wave (a quarter wave for FP64) hit the 32
+    // LDS banks once: column families keep one vector per row of PT + 2
+    // (FP64: PT + 1) elements, row families one position per row of NB2 + 16.
     // Each MFMA sums four consecutive positions (summing positions in a
     // strided order within one MFMA was measured to leave the FP32 results
-    // several times further from the FP64 ones on smooth inputs).  The four
-    // partials are added into the packed FP64 H one wave after the other: no
-    // atomics, so the result does not depend on timing.
-    constexpr int NTT = NT * (NT + 1) / 2;
-    constexpr int GPC = PT + VW, GPR = NB2 + 16;
+    // several times further from the FP64 ones on smooth inputs).
+    constexpr int NTT = C::NTT;
+    constexpr int GPC = PT + (sizeof(T) == 4 ? 2 : 1), GPR = NB2 + 16;
     AccT hacc[NTT];
 #pragma unroll
     for (int q = 0; q < NTT; ++q) hacc[q] = zero4<AccT>();
@@ -327,11 +330,23 @@ __device__ __forceinline__ void round_body(RoundShared<T, NB2>& sh, T* __restric
             for (int u = 0; u < NA; ++u) {
                 int c, tt;
                 origin(ROWS, u, c, tt);
-                T* const dst = ROWS ? stg + tt * GPR + c : stg + c * GPC + tt;
-                if constexpr (sizeof(T) == 4)
-                    *reinterpret_cast<float4*>(dst) = make_float4(pre[u][0], pre[u][1], pre[u][2], pre[u][3]);
-                else
-                    *reinterpret_cast<double2*>(dst) = make_double2(pre[u][0], pre[u][1]);
+                if (ROWS) {
+                    T* const dst = stg + tt * GPR + c;
+                    if constexpr (sizeof(T) == 4)
+                        *reinterpret_cast<float4*>(dst) = make_float4(pre[u][0], pre[u][1], pre[u][2], pre[u][3]);
+                    else
+                        *reinterpret_cast<double2*>(dst) = make_double2(pre[u][0], pre[u][1]);
+                } else {
+                    // rows of PT + 2 floats are 8-byte aligned only
+                    T* const dst = stg + c * GPC + tt;
+                    if constexpr (sizeof(T) == 4) {
+                        *reinterpret_cast<float2*>(dst) = make_float2(pre[u][0], pre[u][1]);
+                        *reinterpret_cast<float2*>(dst + 2) = make_float2(pre[u][2], pre[u][3]);
+                    } else {
+                        dst[0] = pre[u][0];
+                        dst[1] = pre[u][1];
+                    }
+                }
             }
             // the wave's own LDS stores before its reads (LDS is in order per wave)
             __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
@@ -352,55 +367,93 @@ __device__ __forceinline__ void round_body(RoundShared<T, NB2>& sh, T* __restric
             __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
         }
     }
-    __syncthreads();   // the staging regions overlap H
-    for (int w = 0; w < 4; ++w) {
-        if (wave == w) {
-            int q = 0;
+    // Waves 1-3 park their partial sums in LDS in lane order (over the
+    // staging regions, hence the barrier first, and clear of the H buffer
+    // that wave 0 fills while it still reads them); wave 0 adds them to its own
+    // in wave order, so the result does not depend on timing, writes the
+    // packed FP64 H and forms the convergence measure from it: the largest
+    // |cos| = |h_ac| / (||a|| ||c||) over valid vector pairs, kept separately
+    // for pairs inside one block and pairs across the two blocks.  All its
+    // LDS reads are independent of each other, so they overlap.
+    T* const Rp = reinterpret_cast<T*>(smem + C::rp_off);         // [3][NTT][4][64]
+    __syncthreads();
+    if (wave > 0) {
+        T* const Rw = Rp + (wave - 1) * (NTT * 256);
 #pragma unroll
-            for (int i = 0; i < NT; ++i) {
+        for (int q = 0; q < NTT; ++q) {
 #pragma unroll
-                for (int j = i; j < NT; ++j, ++q) {
+            for (int v = 0; v < 4; ++v) Rw[(q * 4 + v) * 64 + lane] = hacc[q][v];
+        }
+    }
+    __syncthreads();
+    if (wave == 0) {
+        int q0 = 0;
 #pragma unroll
-                    for (int v = 0; v < 4; ++v) {
-                        const int a = i * 16 + mfma_row<T>(lg, v), c = j * 16 + lr;
-                        if (a <= c) {
-                            const double x = (double)hacc[q][v];
-                            double& h = H0[sym_idx(a, c)];
-                            h = (w == 0) ? x : h + x;
-                        }
-                    }
+        for (int i = 0; i < NT; ++i) {
+            T pw[3][NT][4];
+#pragma unroll
+            for (int w = 0; w < 3; ++w) {
+#pragma unroll
+                for (int j = i; j < NT; ++j) {
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) pw[w][j][v] = Rp[w * (NTT * 256) + ((q0 + j - i) * 4 + v) * 64 + lane];
+                }
+            }
+#pragma unroll
+            for (int j = i; j < NT; ++j) {
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int a = i * 16 + mfma_row<T>(lg, v), c = j * 16 + lr;
+                    double h = (double)hacc[q0 + j - i][v];
+                    h += (double)pw[0][j][v];
+                    h += (double)pw[1][j][v];
+                    h += (double)pw[2][j][v];
+                    if (a <= c) H0[sym_idx(a, c)] = h;
+                }
+            }
+            q0 += NT - i;
+        }
+        // the wave's own LDS stores before its reads (LDS is in order per wave)
+        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+        // 1 / ||vector a||, 0 for padding and zero vectors so they never
+        // count; norms below 2^-500 are scaled by a power of two first
+        auto rnorm = [&](int a) -> double {
+            const double d = H0[sym_idx(a, a)];
+            const bool tiny = d < 0x1p-1000;
+            const double y = rsq_nr(tiny ? d * 0x1p1000 : d) * (tiny ? 0x1p500 : 1.0);
+            return (gidx(a) < r && d > 0.0) ? y : 0.0;
+        };
+        double rc[NT], mx = 0.0, mw = 0.0;
+        bool nf = false;
+#pragma unroll
+        for (int j = 0; j < NT; ++j) rc[j] = rnorm(j * 16 + lr);
+#pragma unroll
+        for (int i = 0; i < NT; ++i) {
+            double ra[4];
+#pragma unroll
+            for (int v = 0; v < 4; ++v) ra[v] = rnorm(i * 16 + mfma_row<T>(lg, v));
+#pragma unroll
+            for (int j = i; j < NT; ++j) {
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int a = i * 16 + mfma_row<T>(lg, v), c = j * 16 + lr;
+                    const double h = H0[sym_idx(a, c)];
+                    nf = nf || (a <= c && !isfinite(h));
+                    const double cs = (a < c) ? fabs(h) * ra[v] * rc[j] : 0.0;
+                    if ((a < B) != (c < B)) mx = fmax(mx, cs);
+                    else mw = fmax(mw, cs);
                 }
             }
         }
-        if (w == 0 && tid == 0) flag_nf = 0;
-        __syncthreads();
-    }
-
-    // ---------------- convergence measure (FP64): max |cos| over valid pairs,
-    // separately for pairs inside one block and pairs across the two blocks
-    double mcx = 0.0, mcw = 0.0;
-    for (int e = tid; e < NB2 * NB2; e += 256) {
-        const int a = e / NB2, c = e % NB2;
-        if (a > c) continue;
-        const double h = H0[sym_idx(a, c)];
-        if (!isfinite(h)) flag_nf = 1;
-        if (a < c && gidx(a) < r && gidx(c) < r) {
-            const double d = fabs(H0[sym_idx(a, a)]) * fabs(H0[sym_idx(c, c)]);
-            if (d > 0.0) {
-                const double cs = fabs(h) / sqrt(d);
-                if ((a < B) != (c < B)) mcx = fmax(mcx, cs);
-                else mcw = fmax(mcw, cs);
-            }
+        for (int off = 32; off > 0; off >>= 1) {
+            mx = fmax(mx, __shfl_xor(mx, off));
+            mw = fmax(mw, __shfl_xor(mw, off));
         }
+        const bool any_nf = __any(nf);
+        if (lane == 0) { sh.mc_cross = mx; sh.mc_within = mw; flag_nf = any_nf ? 1 : 0; }
     }
-    for (int off = 32; off > 0; off >>= 1) {
-        mcx = fmax(mcx, __shfl_xor(mcx, off));
-        mcw = fmax(mcw, __shfl_xor(mcw, off));
-    }
-    if (lane == 0) { red[wave] = mcx; redw[wave] = mcw; }
     __syncthreads();
-    mcx = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
-    mcw = fmax(fmax(redw[0], redw[1]), fmax(redw[2], redw[3]));
+    const double mcx = sh.mc_cross, mcw = sh.mc_within;
     const double mc = fmax(mcx, mcw);
     const bool nonfinite = flag_nf != 0;
     const bool rotate = !nonfinite && (mc > tol);
@@ -446,7 +499,7 @@ __device__ __forceinline__ void round_body(RoundShared<T, NB2>& sh, T* __restric
     constexpr int TPP = 256 / NPH;                     // threads per Q row pair
     constexpr int EPT = NB2 / TPP;                     // Q entries per thread and row
     constexpr int GW = EPT < VW ? EPT : VW;            // Q entries per LDS access
-    constexpr int NG = EPT / GW;
+    constexpr int NG = EPT / GW;                       // accesses per row, TPP * GW entries apart
     typedef T QVec __attribute__((ext_vector_type(GW)));
     for (int e = tid; e < NB2 * NB2; e += 256) {
         const int a = e / NB2, c = e % NB2;
@@ -490,7 +543,7 @@ __device__ __forceinline__ void round_body(RoundShared<T, NB2>& sh, T* __restric
         sh.rot_cs[0][ka] = make_double2(c, sn);
     }
     // Q rows of pair qk: the vectors on its seats, advanced every step
-    const int qk = tid / TPP, qc0 = (tid % TPP) * EPT;
+    const int qk = tid / TPP, qc0 = (tid % TPP) * GW;
     const int qsa = qk, qsb = partner_seat<NB2>(cross, qk);
     int qp = qsa, qq = qsb;   // step 0: vector = seat
     const int nsteps = cross ? B : NB2 - 1;
@@ -551,15 +604,16 @@ __device__ __forceinline__ void round_body(RoundShared<T, NB2>& sh, T* __restric
                 Hn[rw[b][3] >> 16] = s1 * t1 + c1 * t3;
             }
         }
-        // ---- Q <- Q J: rows qp, qq of Q^T, entries [qc0, qc0 + EPT), one
-        // 16-byte group at a time (register budget)
+        // ---- Q <- Q J: rows qp, qq of Q^T, groups of GW entries at qc0,
+        // qc0 + TPP GW, ...; the TPP threads of a row pair cover consecutive
+        // groups at every access, so the accesses hit distinct banks
         {
             const double2 rq = rcs[qk];
             const T c = (T)rq.x, sn = (T)rq.y;
 #pragma unroll
             for (int g = 0; g < NG; ++g) {
-                QVec* const pp = reinterpret_cast<QVec*>(&Qs[C::q_idx(qp, qc0 + g * GW)]);
-                QVec* const pq = reinterpret_cast<QVec*>(&Qs[C::q_idx(qq, qc0 + g * GW)]);
+                QVec* const pp = reinterpret_cast<QVec*>(&Qs[C::q_idx(qp, qc0 + g * TPP * GW)]);
+                QVec* const pq = reinterpret_cast<QVec*>(&Qs[C::q_idx(qq, qc0 + g * TPP * GW)]);
                 const QVec vp = *pp, vq = *pq;
                 *pp = c * vp - sn * vq;
                 *pq = sn * vp + c * vq;
@@ -578,6 +632,18 @@ __device__ __forceinline__ void round_body(RoundShared<T, NB2>& sh, T* __restric
     // families give D = Q^T old (MFMA lanes along positions), row families
     // D^T = old^T Q (lanes along the contiguous vector index); either way
     // 16 lanes store 64 contiguous bytes.
+    // In FP32 the MFMA operand fragments of Q (Q[c][a] for c = kk + lg,
+    // a = 16 ta + lr) stay in registers for both products, NB2 / 4 x NT
+    // values a lane; FP64 reads them from LDS (its registers are full).
+    constexpr bool QREG = sizeof(T) == 4;
+    T qf[QREG ? NB2 / 4 : 1][NT];
+    if constexpr (QREG) {
+#pragma unroll
+        for (int kq = 0; kq < NB2 / 4; ++kq) {
+#pragma unroll
+            for (int ta = 0; ta < NT; ++ta) qf[kq][ta] = Qs[C::q_idx(ta * 16 + lr, 4 * kq + lg)];
+        }
+    }
     auto update = [&](auto rows_tag, T* base, int64_t vs, int64_t es, int64_t len, bool vec) {
         constexpr bool RW = decltype(rows_tag)::value;
         constexpr int PLD = RW ? PT + 1 : PT;                  // odd stride spreads transposed stores
@@ -590,10 +656,15 @@ __device__ __forceinline__ void round_body(RoundShared<T, NB2>& sh, T* __restric
             for (int u = 0; u < NA; ++u) {
                 int c, tt;
                 origin(RW, u, c, tt);
+                if (!RW) {
+                    T* const dst = stg + c * PLD + tt;
+                    if constexpr (sizeof(T) == 4)
+                        *reinterpret_cast<float4*>(dst) = make_float4(pre[u][0], pre[u][1], pre[u][2], pre[u][3]);
+                    else
+                        *reinterpret_cast<double2*>(dst) = make_double2(pre[u][0], pre[u][1]);
+                } else {
 #pragma unroll
-                for (int q = 0; q < VW; ++q) {
-                    if (!RW) stg[c * PLD + tt + q] = pre[u][q];
-                    else stg[(c + q) * PLD + tt] = pre[u][q];
+                    for (int q = 0; q < VW; ++q) stg[(c + q) * PLD + tt] = pre[u][q];
                 }
             }
             // the wave's own LDS stores before its reads (LDS is in order per wave)
@@ -602,12 +673,12 @@ __device__ __forceinline__ void round_body(RoundShared<T, NB2>& sh, T* __restric
             AccT acc[NT];
 #pragma unroll
             for (int ta = 0; ta < NT; ++ta) acc[ta] = zero4<AccT>();
-#pragma unroll 4
+#pragma unroll
             for (int kk = 0; kk < NB2; kk += 4) {
                 const T b = stg[(kk + lg) * PLD + lr];                  // old[c][t]
 #pragma unroll
                 for (int ta = 0; ta < NT; ++ta) {
-                    const T q = Qs[C::q_idx(ta * 16 + lr, kk + lg)];   // Q[c][a]
+                    const T q = QREG ? qf[QREG ? kk / 4 : 0][ta] : Qs[C::q_idx(ta * 16 + lr, kk + lg)];
                     acc[ta] = RW ? mfma(b, q, acc[ta]) : mfma(q, b, acc[ta]);
                 }
             }
@@ -634,6 +705,8 @@ __device__ __forceinline__ void round_body(RoundShared<T, NB2>& sh, T* __restric
 
 // FP32 pairs of 64 vectors keep three workgroups per 160 KB compute unit.
 static_assert(sizeof(RoundShared<float, 64>) <= 160 * 1024 / 3, "LDS budget of jacobi_round<float, 64>");
+// FP64 pairs of 64 vectors keep two.
+static_assert(sizeof(RoundShared<double, 64>) <= 160 * 1024 / 2, "LDS budget of jacobi_round<double, 64>");
 
 // One round for every (slice, pair) of a tensor of identical slices.
 template <class T, int NB2, bool ROWS>
