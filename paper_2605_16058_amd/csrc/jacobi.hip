@@ -226,10 +226,24 @@ struct RoundCfg {
     static __device__ __forceinline__ int q_idx(int a, int c) { return a * NB2 + (c ^ ((a & SWM) * VW)); }
 };
 
+// (c, s) of one rotation as the vectors see it: the angle is computed in
+// FP64 and rounded to the working precision, and the FP64 H is rotated with
+// the same rounded pair, so that H stays the Gram matrix of the vectors the
+// rotations actually produce.
+template <class T> struct Rot2;
+template <> struct Rot2<float> {
+    typedef float2 type;
+    static __device__ __forceinline__ float2 make(double c, double s) { return make_float2((float)c, (float)s); }
+};
+template <> struct Rot2<double> {
+    typedef double2 type;
+    static __device__ __forceinline__ double2 make(double c, double s) { return make_double2(c, s); }
+};
+
 template <class T, int NB2>
 struct RoundShared {
     __align__(16) char smem[RoundCfg<T, NB2>::total];
-    double2 rot_cs[2][NB2 / 2];   // (c, s) of each rotation, per parity of the inner step
+    typename Rot2<T>::type rot_cs[2][NB2 / 2];   // (c, s) of each rotation, per parity of the inner step
     double mc_cross, mc_within;   // convergence measure of the pair
     int flag_nf;
 };
@@ -540,7 +554,7 @@ __device__ __forceinline__ void round_body(RoundShared<T, NB2>& sh, T* __restric
         const int p = ka, q = partner_seat<NB2>(cross, ka);
         double c, sn;
         jacobi_angle(H0[sym_idx(p, p)], H0[sym_idx(q, q)], H0[sym_idx(p, q)], true, c, sn);
-        sh.rot_cs[0][ka] = make_double2(c, sn);
+        sh.rot_cs[0][ka] = Rot2<T>::make(c, sn);
     }
     // Q rows of pair qk: the vectors on its seats, advanced every step
     const int qk = tid / TPP, qc0 = (tid % TPP) * GW;
@@ -552,7 +566,17 @@ __device__ __forceinline__ void round_body(RoundShared<T, NB2>& sh, T* __restric
         const int cb = step & 1;
         const double* __restrict__ Hc = H0 + cb * NH;
         double* __restrict__ Hn = H0 + (cb ^ 1) * NH;
-        const double2* rcs = sh.rot_cs[cb];
+        typedef typename Rot2<T>::type R2;
+        const R2* rcs = sh.rot_cs[cb];
+        // ---- this thread's Q segments (rotated at the end of the step):
+        // loaded first, so that their latency overlaps the H work
+        QVec vp[NG], vq[NG];
+#pragma unroll
+        for (int g = 0; g < NG; ++g) {
+            vp[g] = *reinterpret_cast<const QVec*>(&Qs[C::q_idx(qp, qc0 + g * TPP * GW)]);
+            vq[g] = *reinterpret_cast<const QVec*>(&Qs[C::q_idx(qq, qc0 + g * TPP * GW)]);
+        }
+        const R2 rq = rcs[qk];
         // ---- rotations of step s+1 (angle threads, wave 3): first, so that
         // their registers are free again for the H blocks of waves 0-2
         if (angle_thread && step + 1 < nsteps) {
@@ -563,16 +587,16 @@ __device__ __forceinline__ void round_body(RoundShared<T, NB2>& sh, T* __restric
             h[3] = Hc[sym_idx(ya, ya)]; h[4] = Hc[sym_idx(ya, yb)]; h[5] = Hc[sym_idx(yb, yb)];
             h[6] = Hc[sym_idx(xa, ya)]; h[7] = Hc[sym_idx(xa, yb)];
             h[8] = Hc[sym_idx(xb, ya)]; h[9] = Hc[sym_idx(xb, yb)];
-            const double2 rx = rcs[akp], ry = rcs[akq];
+            const R2 rx = rcs[akp], ry = rcs[akq];
             // new vector = a0 * (first of its pair) + a1 * (second)
-            const double a0 = afp ? rx.x : rx.y, a1 = afp ? -rx.y : rx.x;
-            const double b0 = afq ? ry.x : ry.y, b1 = afq ? -ry.y : ry.x;
+            const double a0 = afp ? (double)rx.x : (double)rx.y, a1 = afp ? -(double)rx.y : (double)rx.x;
+            const double b0 = afq ? (double)ry.x : (double)ry.y, b1 = afq ? -(double)ry.y : (double)ry.x;
             const double app = a0 * (a0 * h[0] + a1 * h[1]) + a1 * (a0 * h[1] + a1 * h[2]);
             const double aqq = b0 * (b0 * h[3] + b1 * h[4]) + b1 * (b0 * h[4] + b1 * h[5]);
             const double apq = a0 * (b0 * h[6] + b1 * h[7]) + a1 * (b0 * h[8] + b1 * h[9]);
             double c, sn;
             jacobi_angle(app, aqq, apq, true, c, sn);
-            sh.rot_cs[cb ^ 1][ka] = make_double2(c, sn);
+            sh.rot_cs[cb ^ 1][ka] = Rot2<T>::make(c, sn);
         }
         // ---- H <- J^T H J on this thread's 2x2 blocks, written on the next
         // seats; two blocks in flight at a time (register budget)
@@ -580,7 +604,7 @@ __device__ __forceinline__ void round_body(RoundShared<T, NB2>& sh, T* __restric
 #pragma unroll
         for (int b0 = 0; b0 < HB; b0 += HG) {
             double hv[HG][4];
-            double2 r1[HG], r2[HG];
+            R2 r1[HG], r2[HG];
 #pragma unroll
             for (int u = 0; u < HG; ++u) {
                 const int b = b0 + u;
@@ -595,7 +619,7 @@ __device__ __forceinline__ void round_body(RoundShared<T, NB2>& sh, T* __restric
             for (int u = 0; u < HG; ++u) {
                 const int b = b0 + u;
                 if (b >= HB || bk1[b] < 0) continue;
-                const double c1 = r1[u].x, s1 = r1[u].y, c2 = r2[u].x, s2 = r2[u].y;
+                const double c1 = r1[u].x, s1 = r1[u].y, c2 = r2[u].x, s2 = r2[u].y;   // exact in FP64
                 const double t0 = c2 * hv[u][0] - s2 * hv[u][1], t1 = s2 * hv[u][0] + c2 * hv[u][1];
                 const double t2 = c2 * hv[u][2] - s2 * hv[u][3], t3 = s2 * hv[u][2] + c2 * hv[u][3];
                 Hn[rw[b][0] >> 16] = c1 * t0 - s1 * t2;
@@ -608,15 +632,11 @@ __device__ __forceinline__ void round_body(RoundShared<T, NB2>& sh, T* __restric
         // qc0 + TPP GW, ...; the TPP threads of a row pair cover consecutive
         // groups at every access, so the accesses hit distinct banks
         {
-            const double2 rq = rcs[qk];
-            const T c = (T)rq.x, sn = (T)rq.y;
+            const T c = rq.x, sn = rq.y;
 #pragma unroll
             for (int g = 0; g < NG; ++g) {
-                QVec* const pp = reinterpret_cast<QVec*>(&Qs[C::q_idx(qp, qc0 + g * TPP * GW)]);
-                QVec* const pq = reinterpret_cast<QVec*>(&Qs[C::q_idx(qq, qc0 + g * TPP * GW)]);
-                const QVec vp = *pp, vq = *pq;
-                *pp = c * vp - sn * vq;
-                *pq = sn * vp + c * vq;
+                *reinterpret_cast<QVec*>(&Qs[C::q_idx(qp, qc0 + g * TPP * GW)]) = c * vp[g] - sn * vq[g];
+                *reinterpret_cast<QVec*>(&Qs[C::q_idx(qq, qc0 + g * TPP * GW)]) = sn * vp[g] + c * vq[g];
             }
             qp = seat_vector<NB2>(cross, qsa, step + 1);
             qq = seat_vector<NB2>(cross, qsb, step + 1);
