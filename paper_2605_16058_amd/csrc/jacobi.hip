@@ -106,13 +106,6 @@ __device__ __forceinline__ int seat_pair(bool cross, int j, bool& first) {
     first = j < B;
     return first ? j : (cross ? j - B : NB2 - 1 - j);
 }
-// vector on seat j at step `step`
-template <int NB2>
-__device__ __forceinline__ int seat_vector(bool cross, int j, int step) {
-    constexpr int B = NB2 / 2;
-    if (cross) return j < B ? j : B + (j - B + step) % B;
-    return circle_player(j, step, NB2);
-}
 
 // FP64 reciprocal and reciprocal square root: the hardware estimates
 // refined by two Newton steps each (quadratic convergence from about 23
@@ -228,22 +221,18 @@ struct RoundCfg {
 
 // (c, s) of one rotation as the vectors see it: the angle is computed in
 // FP64 and rounded to the working precision, and the FP64 H is rotated with
-// the same rounded pair, so that H stays the Gram matrix of the vectors the
-// rotations actually produce.
-template <class T> struct Rot2;
-template <> struct Rot2<float> {
-    typedef float2 type;
-    static __device__ __forceinline__ float2 make(double c, double s) { return make_float2((float)c, (float)s); }
-};
-template <> struct Rot2<double> {
-    typedef double2 type;
-    static __device__ __forceinline__ double2 make(double c, double s) { return make_double2(c, s); }
-};
+// the same rounded pair (kept as exact doubles, so the H update converts
+// nothing), so that H stays the Gram matrix of the vectors the rotations
+// actually produce.
+template <class T>
+__device__ __forceinline__ double2 rot_make(double c, double s) {
+    return make_double2((double)(T)c, (double)(T)s);
+}
 
 template <class T, int NB2>
 struct RoundShared {
     __align__(16) char smem[RoundCfg<T, NB2>::total];
-    typename Rot2<T>::type rot_cs[2][NB2 / 2];   // (c, s) of each rotation, per parity of the inner step
+    double2 rot_cs[2][NB2 / 2];   // (c, s) of each rotation, per parity of the inner step
     double mc_cross, mc_within;   // convergence measure of the pair
     int flag_nf;
 };
@@ -522,8 +511,9 @@ __device__ __forceinline__ void round_body(RoundShared<T, NB2>& sh, T* __restric
     const bool cross = cross_only;
     const bool angle_thread = tid >= 256 - NPH;        // the upper lanes of wave 3
     const int ka = tid - (256 - NPH);
-    // this thread's H blocks: pairs k1 <= k2, read slot | write slot << 16
-    int bk1[HB], bk2[HB], rw[HB][4];
+    // this thread's H blocks: pairs k1 <= k2; byte offsets (read | write <<
+    // 16) into an H buffer and byte offsets of the two rotations
+    int bk1[HB], bk2[HB], rw[HB][4], ro1[HB], ro2[HB];
 #pragma unroll
     for (int b = 0; b < HB; ++b) {
         const int bi = tid + NBT * b;
@@ -539,10 +529,12 @@ __device__ __forceinline__ void round_body(RoundShared<T, NB2>& sh, T* __restric
         const int v0 = k2, v1 = partner_seat<NB2>(cross, k2);
         const int nu0 = next_seat<NB2>(cross, u0), nu1 = next_seat<NB2>(cross, u1);
         const int nv0 = next_seat<NB2>(cross, v0), nv1 = next_seat<NB2>(cross, v1);
-        rw[b][0] = sym_idx(u0, v0) | (sym_idx(nu0, nv0) << 16);
-        rw[b][1] = sym_idx(u0, v1) | (sym_idx(nu0, nv1) << 16);
-        rw[b][2] = sym_idx(u1, v0) | (sym_idx(nu1, nv0) << 16);
-        rw[b][3] = sym_idx(u1, v1) | (sym_idx(nu1, nv1) << 16);
+        rw[b][0] = 8 * sym_idx(u0, v0) | (8 * sym_idx(nu0, nv0) << 16);
+        rw[b][1] = 8 * sym_idx(u0, v1) | (8 * sym_idx(nu0, nv1) << 16);
+        rw[b][2] = 8 * sym_idx(u1, v0) | (8 * sym_idx(nu1, nv0) << 16);
+        rw[b][3] = 8 * sym_idx(u1, v1) | (8 * sym_idx(nu1, nv1) << 16);
+        ro1[b] = 16 * k1;
+        ro2[b] = 16 * k2;
     }
     // angle threads: where the two vectors of pair ka at step s+1 sat at step s
     int akp = 0, akq = 0;
@@ -554,20 +546,26 @@ __device__ __forceinline__ void round_body(RoundShared<T, NB2>& sh, T* __restric
         const int p = ka, q = partner_seat<NB2>(cross, ka);
         double c, sn;
         jacobi_angle(H0[sym_idx(p, p)], H0[sym_idx(q, q)], H0[sym_idx(p, q)], true, c, sn);
-        sh.rot_cs[0][ka] = Rot2<T>::make(c, sn);
+        sh.rot_cs[0][ka] = rot_make<T>(c, sn);
     }
-    // Q rows of pair qk: the vectors on its seats, advanced every step
+    // Q rows of pair qk: the vectors on its seats, advanced every step (the
+    // vector on a moving seat goes up by one, NB2-1 wrapping round to 1 in
+    // a full sweep, to b in a cross sweep)
     const int qk = tid / TPP, qc0 = (tid % TPP) * GW;
     const int qsa = qk, qsb = partner_seat<NB2>(cross, qk);
     int qp = qsa, qq = qsb;   // step 0: vector = seat
+    const bool qp_moves = cross ? false : qsa != 0;
+    auto advance = [&](int v) { return v == NB2 - 1 ? (cross ? B : 1) : v + 1; };
     const int nsteps = cross ? B : NB2 - 1;
     __syncthreads();
-    for (int step = 0; step < nsteps; ++step) {
-        const int cb = step & 1;
-        const double* __restrict__ Hc = H0 + cb * NH;
-        double* __restrict__ Hn = H0 + (cb ^ 1) * NH;
-        typedef typename Rot2<T>::type R2;
-        const R2* rcs = sh.rot_cs[cb];
+    // The step loop runs two steps per iteration, so that the buffer of
+    // each step is a compile-time offset of the LDS accesses.
+    auto one_step = [&](auto parity, int step) {
+        constexpr int cb = decltype(parity)::value;
+        const char* __restrict__ Hc = reinterpret_cast<const char*>(H0 + cb * NH);
+        char* __restrict__ Hn = reinterpret_cast<char*>(H0 + (cb ^ 1) * NH);
+        const double2* rcs = sh.rot_cs[cb];
+        const char* rcb = reinterpret_cast<const char*>(rcs);
         // ---- this thread's Q segments (rotated at the end of the step):
         // loaded first, so that their latency overlaps the H work
         QVec vp[NG], vq[NG];
@@ -576,27 +574,28 @@ __device__ __forceinline__ void round_body(RoundShared<T, NB2>& sh, T* __restric
             vp[g] = *reinterpret_cast<const QVec*>(&Qs[C::q_idx(qp, qc0 + g * TPP * GW)]);
             vq[g] = *reinterpret_cast<const QVec*>(&Qs[C::q_idx(qq, qc0 + g * TPP * GW)]);
         }
-        const R2 rq = rcs[qk];
+        const double2 rq = rcs[qk];
         // ---- rotations of step s+1 (angle threads, wave 3): first, so that
         // their registers are free again for the H blocks of waves 0-2
         if (angle_thread && step + 1 < nsteps) {
             const int xa = akp, xb = partner_seat<NB2>(cross, akp);
             const int ya = akq, yb = partner_seat<NB2>(cross, akq);
+            const double* Hd = reinterpret_cast<const double*>(Hc);
             double h[10];
-            h[0] = Hc[sym_idx(xa, xa)]; h[1] = Hc[sym_idx(xa, xb)]; h[2] = Hc[sym_idx(xb, xb)];
-            h[3] = Hc[sym_idx(ya, ya)]; h[4] = Hc[sym_idx(ya, yb)]; h[5] = Hc[sym_idx(yb, yb)];
-            h[6] = Hc[sym_idx(xa, ya)]; h[7] = Hc[sym_idx(xa, yb)];
-            h[8] = Hc[sym_idx(xb, ya)]; h[9] = Hc[sym_idx(xb, yb)];
-            const R2 rx = rcs[akp], ry = rcs[akq];
+            h[0] = Hd[sym_idx(xa, xa)]; h[1] = Hd[sym_idx(xa, xb)]; h[2] = Hd[sym_idx(xb, xb)];
+            h[3] = Hd[sym_idx(ya, ya)]; h[4] = Hd[sym_idx(ya, yb)]; h[5] = Hd[sym_idx(yb, yb)];
+            h[6] = Hd[sym_idx(xa, ya)]; h[7] = Hd[sym_idx(xa, yb)];
+            h[8] = Hd[sym_idx(xb, ya)]; h[9] = Hd[sym_idx(xb, yb)];
+            const double2 rx = rcs[akp], ry = rcs[akq];
             // new vector = a0 * (first of its pair) + a1 * (second)
-            const double a0 = afp ? (double)rx.x : (double)rx.y, a1 = afp ? -(double)rx.y : (double)rx.x;
-            const double b0 = afq ? (double)ry.x : (double)ry.y, b1 = afq ? -(double)ry.y : (double)ry.x;
+            const double a0 = afp ? rx.x : rx.y, a1 = afp ? -rx.y : rx.x;
+            const double b0 = afq ? ry.x : ry.y, b1 = afq ? -ry.y : ry.x;
             const double app = a0 * (a0 * h[0] + a1 * h[1]) + a1 * (a0 * h[1] + a1 * h[2]);
             const double aqq = b0 * (b0 * h[3] + b1 * h[4]) + b1 * (b0 * h[4] + b1 * h[5]);
             const double apq = a0 * (b0 * h[6] + b1 * h[7]) + a1 * (b0 * h[8] + b1 * h[9]);
             double c, sn;
             jacobi_angle(app, aqq, apq, true, c, sn);
-            sh.rot_cs[cb ^ 1][ka] = Rot2<T>::make(c, sn);
+            sh.rot_cs[cb ^ 1][ka] = rot_make<T>(c, sn);
         }
         // ---- H <- J^T H J on this thread's 2x2 blocks, written on the next
         // seats; two blocks in flight at a time (register budget)
@@ -604,44 +603,48 @@ __device__ __forceinline__ void round_body(RoundShared<T, NB2>& sh, T* __restric
 #pragma unroll
         for (int b0 = 0; b0 < HB; b0 += HG) {
             double hv[HG][4];
-            R2 r1[HG], r2[HG];
+            double2 r1[HG], r2[HG];
 #pragma unroll
             for (int u = 0; u < HG; ++u) {
                 const int b = b0 + u;
                 if (b < HB && bk1[b] >= 0) {
 #pragma unroll
-                    for (int e = 0; e < 4; ++e) hv[u][e] = Hc[rw[b][e] & 0xffff];
-                    r1[u] = rcs[bk1[b]];
-                    r2[u] = rcs[bk2[b]];
+                    for (int e = 0; e < 4; ++e) hv[u][e] = *reinterpret_cast<const double*>(Hc + (rw[b][e] & 0xffff));
+                    r1[u] = *reinterpret_cast<const double2*>(rcb + ro1[b]);
+                    r2[u] = *reinterpret_cast<const double2*>(rcb + ro2[b]);
                 }
             }
 #pragma unroll
             for (int u = 0; u < HG; ++u) {
                 const int b = b0 + u;
                 if (b >= HB || bk1[b] < 0) continue;
-                const double c1 = r1[u].x, s1 = r1[u].y, c2 = r2[u].x, s2 = r2[u].y;   // exact in FP64
+                const double c1 = r1[u].x, s1 = r1[u].y, c2 = r2[u].x, s2 = r2[u].y;
                 const double t0 = c2 * hv[u][0] - s2 * hv[u][1], t1 = s2 * hv[u][0] + c2 * hv[u][1];
                 const double t2 = c2 * hv[u][2] - s2 * hv[u][3], t3 = s2 * hv[u][2] + c2 * hv[u][3];
-                Hn[rw[b][0] >> 16] = c1 * t0 - s1 * t2;
-                Hn[rw[b][1] >> 16] = c1 * t1 - s1 * t3;
-                if (bk1[b] != bk2[b]) Hn[rw[b][2] >> 16] = s1 * t0 + c1 * t2;
-                Hn[rw[b][3] >> 16] = s1 * t1 + c1 * t3;
+                *reinterpret_cast<double*>(Hn + (rw[b][0] >> 16)) = c1 * t0 - s1 * t2;
+                *reinterpret_cast<double*>(Hn + (rw[b][1] >> 16)) = c1 * t1 - s1 * t3;
+                if (bk1[b] != bk2[b]) *reinterpret_cast<double*>(Hn + (rw[b][2] >> 16)) = s1 * t0 + c1 * t2;
+                *reinterpret_cast<double*>(Hn + (rw[b][3] >> 16)) = s1 * t1 + c1 * t3;
             }
         }
         // ---- Q <- Q J: rows qp, qq of Q^T, groups of GW entries at qc0,
         // qc0 + TPP GW, ...; the TPP threads of a row pair cover consecutive
         // groups at every access, so the accesses hit distinct banks
         {
-            const T c = rq.x, sn = rq.y;
+            const T c = (T)rq.x, sn = (T)rq.y;
 #pragma unroll
             for (int g = 0; g < NG; ++g) {
                 *reinterpret_cast<QVec*>(&Qs[C::q_idx(qp, qc0 + g * TPP * GW)]) = c * vp[g] - sn * vq[g];
                 *reinterpret_cast<QVec*>(&Qs[C::q_idx(qq, qc0 + g * TPP * GW)]) = sn * vp[g] + c * vq[g];
             }
-            qp = seat_vector<NB2>(cross, qsa, step + 1);
-            qq = seat_vector<NB2>(cross, qsb, step + 1);
+            if (qp_moves) qp = advance(qp);
+            qq = advance(qq);
         }
         __syncthreads();
+    };
+    for (int step = 0; step < nsteps; step += 2) {
+        one_step(std::integral_constant<int, 0>(), step);
+        if (step + 1 < nsteps) one_step(std::integral_constant<int, 1>(), step + 1);
     }
 
     // ---------------- phase 3: vectors <- Q^T vectors, W <- W Q (MFMA)
