@@ -114,13 +114,14 @@ def timed(fn, steps, torch):
 # climate (default)
 # ---------------------------------------------------------------------------
 
-def tune_single(a, Ad, M, precision, tuned):
+def tune_single(a, Ad, M, precision, tuned, transform="dense"):
     """(block, tile) for one tensor: --block if given, else the autotuner's."""
     if a.block or a.no_tune:
         return a.block, 0
     from paper_2605_16058_amd import autotune
     t0 = time.perf_counter()
-    ch = autotune.tune_tsvdm(Ad, M, mode="II", eps=a.eps, precision=precision)
+    ch = autotune.tune_tsvdm(Ad, M, mode="II", eps=a.eps, precision=precision,
+                             transform=transform)
     tuned[precision] = {"block": ch.block, "tile": ch.tile,
                         "seconds": round(time.perf_counter() - t0, 2),
                         "measured_ms": {k: {str(c): round(v, 3) for c, v in t.items()}
@@ -150,6 +151,32 @@ def cpu_baseline_climate(m, p, n_sample, eps):
             "seconds": round(dt, 3)}
 
 
+def transform_timing(a, Ad, M, torch, tf):
+    """Forward transform alone, FP32 in and out: the FFT DCT (HBM bound:
+    one read and one write of every element) beside the dense MFMA product,
+    HIP events on the current stream."""
+    from paper_2605_16058_amd import autotune, ops
+    m, p, n = Ad.shape
+    out = {}
+    Y = ops.colmajor_empty(m, p, n, torch.float32, Ad.device)
+    by = 2 * m * p * n * 4
+    if n >= 2 and n <= 1024 and (n & (n - 1)) == 0:
+        t = autotune.time_ms(lambda: ops.tsvdm_transform_dct(Ad, 3, compute="f32", out=Y), reps=5)
+        out["dct_fft_ms"] = round(t, 4)
+        out["dct_fft_GBs"] = round(by / (t * 1e-3) / 1e9, 1)
+        out["dct_fft_hbm_frac"] = round(by / (t * 1e-3) / 1e9 / PEAK["hbm_GBs"], 4)
+    Md = ops.device_matrix(M)
+    ws = ops.Workspace(Ad.device)
+    t = autotune.time_ms(lambda: ops.tsvdm_transform(Ad, Md, compute="f32", out_dtype=torch.float32,
+                                                     out=Y, ws=ws), reps=5)
+    out["dense_ttm_ms"] = round(t, 4)
+    out["dense_ttm_TFs"] = round(2.0 * m * p * n * n / (t * 1e-3) / 1e12, 1)
+    out["used"] = tf
+    del Y
+    log(f"transform timing: {out}")
+    return out
+
+
 def bench_climate(a, torch, lib):
     import numpy as np
 
@@ -165,10 +192,14 @@ def bench_climate(a, torch, lib):
     del A
     in_bytes = m * p * n * 4
 
+    # the DCT-II is applied by FFT (tsvdm_transform_dct) where the FFT covers
+    # the precision (FP32 / FP64); the BF16 forms are transform precisions of
+    # the dense product
+    tf = a.transform if a.precision == "f32" else "dense"
     tuned = {}
-    ch = tune_single(a, Ad, M, a.precision, tuned)
+    ch = tune_single(a, Ad, M, a.precision, tuned, tf)
     op_mix = TSVDM((m, p, n), M, mode="II", eps=a.eps, precision=a.precision, block=ch[0],
-                   tile=ch[1])
+                   tile=ch[1], transform=tf)
     log(f"mixed ({a.precision}) warmup {a.warmup}, steps {a.steps}")
     for _ in range(a.warmup):
         op_mix(Ad)
@@ -185,11 +216,14 @@ def bench_climate(a, torch, lib):
     if tr is not None:
         roof["traffic"] = tr
 
+    transform_info = transform_timing(a, Ad, M, torch, tf)
+
     out_f64 = {}
     if not a.no_f64:
-        ch64 = tune_single(a, Ad, M, "f64", tuned)
+        tf64 = a.transform
+        ch64 = tune_single(a, Ad, M, "f64", tuned, tf64)
         op64 = TSVDM((m, p, n), M, mode="II", eps=a.eps, precision="f64", block=ch64[0],
-                     tile=ch64[1])
+                     tile=ch64[1], transform=tf64)
         log(f"fp64 warmup {a.warmup}, steps {a.steps}")
         for _ in range(a.warmup):
             op64(Ad)
@@ -221,9 +255,11 @@ def bench_climate(a, torch, lib):
         "ms_per_step": round(ms_mix, 3), "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f32" if a.precision == "f32" else a.precision,
         "data": "synthetic",
-        "config": {"workload": f"climate-like {m}x{p}x{n} FP32, DCT-II, t-SVDM-II tol {a.eps}",
+        "config": {"workload": f"climate-like {m}x{p}x{n} FP32, DCT-II"
+                               f"{' (FFT)' if tf == 'dct' else ''}, t-SVDM-II tol {a.eps}",
                    "m": m, "p": p, "n": n, "eps": a.eps, "precision": a.precision,
-                   "autotune": tuned},
+                   "transform": tf, "autotune": tuned},
+        "transform": transform_info,
         "rel_error": res_mix.rel_error(),
         "sum_rho": int(res_mix.offsets[-1].item()),
         "svd_status": int(res_mix.svd_status.item()),
@@ -565,6 +601,8 @@ def main(argv=None):
     ap.add_argument("--precision", default="f32", choices=["f32", "bf16x3", "bf16"])
     ap.add_argument("--eps", type=float, default=1e-3)
     ap.add_argument("--shape", default="512,1024,256")
+    ap.add_argument("--transform", default="dct", choices=["dct", "dense"],
+                    help="climate: apply the DCT-II by FFT (dct) or as a dense MFMA product")
     ap.add_argument("--no-f64", action="store_true", help="skip the FP64 comparison path")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-n", type=int, default=32)

@@ -131,6 +131,25 @@ int tsvdm_transform_mode(const void* X, int x_dtype, void* Y, int y_dtype,
                          const double* M, int transpose, double scale,
                          int compute, int tile, void* ws, size_t ws_bytes, void* stream);
 
+/* Fast mode-k transform by the orthonormal DCT-II C (C_qj = s_q cos(pi q
+ * (2j + 1) / (2 n_k)), s_0 = sqrt(1/n_k), s_q = sqrt(2/n_k)): Y = X x_k C
+ * (inverse = 0) or Y = X x_k C^T = X x_k C^-1 (inverse = 1), computed by an
+ * FFT in O(log n_k) work per element instead of the dense product's O(n_k)
+ * (Section 2.2, choice of M: the DCT applies in O(n log n); Section 5,
+ * operator transforms for the TTM stage).  The result equals
+ * tsvdm_transform_mode with M = C (scale 1) up to rounding.
+ *   X, Y     device, column-major, prod(dims) elements, no aliasing.
+ *   d, dims, k  as in tsvdm_transform_mode (d = 3, k = 3: the 3-way case).
+ *   n_k      a power of two in [2, 1024]; the product of the dimensions
+ *            before mode k below 2^31.
+ *   compute  TSVDM_F64 or TSVDM_F32: the FFT's arithmetic (twiddles are
+ *            computed in FP64 and rounded once).
+ * No workspace.  Errors: TSVDM_E_SHAPE for an unsupported n_k, the others
+ * as in tsvdm_transform_mode. */
+int tsvdm_transform_dct(const void* X, int x_dtype, void* Y, int y_dtype,
+                        int32_t d, const int64_t* dims, int32_t k, int inverse,
+                        int compute, void* stream);
+
 /* --------------------------------------------------------------------- */
 /* slice SVDs (Algorithm 1; Section 3.2)                                 */
 /* --------------------------------------------------------------------- */

@@ -30,6 +30,7 @@ _SIGS = {
                                 c_double, c_int, c_int, _P, c_size_t, _P]),
     "tsvdm_transform_mode": (c_int, [_P, c_int, _P, c_int, c_int32, _P, c_int32, _P, c_int,
                                      c_double, c_int, c_int, _P, c_size_t, _P]),
+    "tsvdm_transform_dct": (c_int, [_P, c_int, _P, c_int, c_int32, _P, c_int32, c_int, c_int, _P]),
     "tsvdm_lowrank": (c_int, [_P, _P, c_int, c_int64, c_int64, c_int64, _P, _P, c_int64, _P, _P]),
     "tsvdm_slice_svd_workspace_size": (c_int, [c_int64, c_int64, c_int64, c_int, POINTER(c_size_t)]),
     "tsvdm_slice_svd": (c_int, [_P, c_int, c_int64, c_int64, c_int64, _P, _P, _P, c_int, c_int,

@@ -133,8 +133,11 @@ class Choice:
 
 
 def tune_tsvdm(A, M, mode="II", k=None, eps=None, precision="f32", cache=None, reps=2,
-               margin=0.03) -> Choice:
-    """Block width and tile shape for one tensor shape, timed on t-SVDM runs of A."""
+               margin=0.03, transform="dense") -> Choice:
+    """Block width and tile shape for one tensor shape, timed on t-SVDM runs of A.
+
+    With transform="dct" (the FFT transform, which has no tile shape) only the
+    block width is tuned, on runs with that transform."""
     from .pipeline import TSVDM
     m, p, n = A.shape
     c = _cache(cache)
@@ -145,12 +148,14 @@ def tune_tsvdm(A, M, mode="II", k=None, eps=None, precision="f32", cache=None, r
         t = {}
         for b in JACOBI_BLOCKS:
             op = TSVDM(A.shape, M, mode=mode, k=k, eps=eps, precision=precision, block=b,
-                       device=A.device)
+                       device=A.device, transform=transform)
             t[b] = time_ms(lambda: op(A), reps=reps)
         block = pick(t, default_block(m, p), margin)
         c.put("jacobi", precision, jb, block, t)
         times["jacobi"] = t
-    if tile is None:
+    if transform == "dct":
+        tile = 0
+    elif tile is None:
         from . import ops
         from .pipeline import PRECISIONS
         compute, dtype = PRECISIONS[precision]

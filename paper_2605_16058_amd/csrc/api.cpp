@@ -168,6 +168,37 @@ int tsvdm_transform_mode(const void* X, int x_dtype, void* Y, int y_dtype, int32
                         as_stream(stream));
 }
 
+int tsvdm_transform_dct(const void* X, int x_dtype, void* Y, int y_dtype, int32_t d,
+                        const int64_t* dims, int32_t k, int inverse, int compute, void* stream) {
+    clear_error();
+    TSVDM_REQUIRE(dims != nullptr, TSVDM_E_ARG, "dims is NULL");
+    TSVDM_REQUIRE(d >= 3 && d <= 32, TSVDM_E_SHAPE, "d must be in [3, 32]");
+    TSVDM_REQUIRE(k >= 3 && k <= d, TSVDM_E_ARG, "k must be in [3, d]");
+    int64_t R = 1, P = 1;
+    for (int i = 0; i < d; ++i) {
+        TSVDM_REQUIRE(dims[i] >= 1 && dims[i] < ((int64_t)1 << 31), TSVDM_E_SHAPE,
+                      "every dimension must be in [1, 2^31)");
+        int64_t& acc = (i + 1 < k) ? R : P;
+        if (i + 1 == k) continue;
+        TSVDM_REQUIRE(acc <= (((int64_t)1 << 46) / dims[i]), TSVDM_E_SHAPE, "tensor too large");
+        acc *= dims[i];
+    }
+    const int64_t n = dims[k - 1];
+    TSVDM_REQUIRE(n >= 2 && n <= 1024 && (n & (n - 1)) == 0, TSVDM_E_SHAPE,
+                  "n_k must be a power of two in [2, 1024]");
+    TSVDM_REQUIRE(R < ((int64_t)1 << 31), TSVDM_E_SHAPE,
+                  "the dimensions before mode k must multiply to below 2^31");
+    TSVDM_REQUIRE(R <= (((int64_t)1 << 46) / n) / P, TSVDM_E_SHAPE, "tensor too large");
+    TSVDM_REQUIRE(X && Y, TSVDM_E_ARG, "X and Y must be non-NULL");
+    TSVDM_REQUIRE(X != Y, TSVDM_E_ARG, "Y must not alias X");
+    TSVDM_REQUIRE(io_dtype(x_dtype) && io_dtype(y_dtype), TSVDM_E_UNSUPPORTED,
+                  "x_dtype and y_dtype must be F64 or F32");
+    TSVDM_REQUIRE(compute == TSVDM_F64 || compute == TSVDM_F32, TSVDM_E_UNSUPPORTED,
+                  "compute must be F64 or F32");
+    TSVDM_REQUIRE(inverse == 0 || inverse == 1, TSVDM_E_ARG, "inverse must be 0 or 1");
+    return run_dct_mode(X, x_dtype, Y, y_dtype, R, n, P, inverse, compute, as_stream(stream));
+}
+
 // ------------------------------------------------------------- slice SVD
 
 int tsvdm_slice_svd_workspace_size(int64_t m, int64_t p, int64_t n, int dtype, size_t* bytes) {

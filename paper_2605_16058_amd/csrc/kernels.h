@@ -90,6 +90,11 @@ int run_ttm(const void* X, int xdt, void* Y, int ydt, int64_t m, int64_t p, int6
             const double* M, int transpose, double scale, int compute, int tile, void* ws,
             hipStream_t st);
 // P consecutive blocks of R x n elements, each Y_b = X_b x_last (scale * op(M))
+// Fast orthonormal DCT-II (inverse: its transpose) along the middle index
+// of R x n x P (column-major); n a power of two in [2, 1024]; compute F32 or
+// F64 (the FFT arithmetic); inputs / outputs F32 or F64.
+int run_dct_mode(const void* X, int xdt, void* Y, int ydt, int64_t R, int64_t n, int64_t P,
+                 int inverse, int compute, hipStream_t st);
 int run_ttm_mode(const void* X, int xdt, void* Y, int ydt, int64_t R, int64_t n, int64_t P,
                  const double* M, int transpose, double scale, int compute, int tile, void* ws,
                  hipStream_t st);

@@ -161,6 +161,26 @@ def tsvdm_transform_mode(X, k, Mdev, transpose=False, scale=1.0, compute="f64", 
     return Y
 
 
+def tsvdm_transform_dct(X, k=3, inverse=False, compute="f64", out_dtype=None, out=None):
+    """Y = X x_k C (or C^T with inverse) for the orthonormal DCT-II C, by FFT.
+
+    X is a column-major tensor of order >= 3; n_k must be a power of two in
+    [2, 1024].  compute ("f64" or "f32") is the FFT's arithmetic."""
+    if compute not in ("f64", "f32"):
+        raise ValueError("compute must be 'f64' or 'f32'")
+    X = as_colmajor_nd(X)
+    dims = tuple(int(x) for x in X.shape)
+    odt = out_dtype or (torch.float64 if compute == "f64" else torch.float32)
+    Y = out if out is not None else colmajor_empty_nd(dims, odt, X.device)
+    if tuple(Y.shape) != dims or not is_colmajor_nd(Y):
+        raise ValueError("out must be a column-major tensor of the input's shape")
+    d = len(dims)
+    dims_c = (ctypes.c_int64 * d)(*dims)
+    _lib.call("tsvdm_transform_dct", _ptr(X), _dt(X), _ptr(Y), _dt(Y), d, dims_c, int(k),
+              int(bool(inverse)), _COMPUTE[compute], _stream())
+    return Y
+
+
 def tsvdm_lowrank(U_pk, G_pk, rho, offsets, capacity, shape, out=None):
     """C-hat with slice i = U_i G_i (transform domain, no back-transform)."""
     m, p, n = shape

@@ -9,6 +9,7 @@ stream.
 from __future__ import annotations
 
 from dataclasses import dataclass
+import numpy as np
 
 import torch
 
@@ -49,12 +50,15 @@ class TSVDM:
     mode "I" keeps rank k on every slice, mode "II" uses the global relative
     tolerance eps.  capacity="max" sizes the packed factors for r*n triplets
     (no host synchronisation); "exact" reads sum(rho) back first (one sync),
-    like the paper's exact-size allocation.
+    like the paper's exact-size allocation.  transform="dct" applies M, which
+    must then be the orthonormal DCT-II (or None), by FFT (tsvdm_transform_dct)
+    instead of the dense product: forward, and after the transform-domain
+    low-rank product (tsvdm_lowrank) backward; precision f64 or f32 only.
     """
 
     def __init__(self, shape, M, mode="II", k=None, eps=None, precision="f64",
                  block=0, max_sweeps=0, tol=0.0, host_poll=True, capacity="max",
-                 device="cuda", check_m=True, tile=0):
+                 device="cuda", check_m=True, tile=0, transform="dense"):
         self.m, self.p, self.n = (int(x) for x in shape)
         self.r = min(self.m, self.p)
         if mode not in ("I", "II"):
@@ -68,6 +72,23 @@ class TSVDM:
         self.mode, self.k, self.eps = mode, k, eps
         self.precision = precision
         self.ttm_compute, self.dtype = PRECISIONS[precision]
+        if transform not in ("dense", "dct"):
+            raise ValueError("transform must be 'dense' or 'dct'")
+        self.transform = transform
+        if transform == "dct":
+            if precision not in ("f64", "f32"):
+                raise ValueError("transform='dct' needs precision f64 or f32")
+            n = self.n
+            if n < 2 or n > 1024 or (n & (n - 1)) != 0:
+                raise ValueError("transform='dct' needs n a power of two in [2, 1024]")
+            q = np.arange(n)[:, None]
+            j = np.arange(n)[None, :]
+            C = np.sqrt(2.0 / n) * np.cos(np.pi * q * (2 * j + 1) / (2 * n))
+            C[0] /= np.sqrt(2.0)
+            if M is None:
+                M = C
+            elif np.max(np.abs(np.asarray(M, np.float64) - C)) > 1e-12:
+                raise ValueError("transform='dct' needs M to be the orthonormal DCT-II")
         self.c2 = ops.check_transform(M) if check_m else 1.0
         self.Mdev = ops.device_matrix(M, device)
         self.block, self.max_sweeps, self.tol, self.host_poll = block, max_sweeps, tol, host_poll
@@ -83,9 +104,13 @@ class TSVDM:
         m, p, n, r = self.m, self.p, self.n, self.r
         out_dt = self.dtype
         # 1. transform (FP32 -> FP64 up-cast fused into the TTM load)
-        A_hat = ops.tsvdm_transform(A, self.Mdev, transpose=False, scale=1.0,
-                                    compute=self.ttm_compute, out_dtype=self.dtype, ws=self.ws,
-                                    tile=self.tile)
+        if self.transform == "dct":
+            A_hat = ops.tsvdm_transform_dct(A, 3, inverse=False, compute=self.ttm_compute,
+                                            out_dtype=self.dtype)
+        else:
+            A_hat = ops.tsvdm_transform(A, self.Mdev, transpose=False, scale=1.0,
+                                        compute=self.ttm_compute, out_dtype=self.dtype, ws=self.ws,
+                                        tile=self.tile)
         # 2. slice SVDs
         W, s2, svd_status = ops.tsvdm_slice_svd(A_hat, self.block, self.max_sweeps, self.tol,
                                                 self.host_poll, ws=self.ws)
@@ -105,9 +130,14 @@ class TSVDM:
         U_pk, G_pk, S_pk, pack_status = ops.tsvdm_pack(A_hat, W, s2, rho, offsets, cap, ws=self.ws)
         # 5. reconstruct + back-transform (M^{-1} = M^T / c^2)
         back = self.ttm_compute if self.ttm_compute != "f64" else "f64"
-        A_rec = ops.tsvdm_reconstruct(U_pk, G_pk, rho, offsets, cap, self.Mdev, (m, p, n),
-                                      scale=1.0 / self.c2, out_dtype=out_dt, compute=back,
-                                      ws=self.ws, tile=self.tile)
+        if self.transform == "dct":
+            C_hat = ops.tsvdm_lowrank(U_pk, G_pk, rho, offsets, cap, (m, p, n))
+            A_rec = ops.tsvdm_transform_dct(C_hat, 3, inverse=True, compute=back, out_dtype=out_dt)
+            del C_hat
+        else:
+            A_rec = ops.tsvdm_reconstruct(U_pk, G_pk, rho, offsets, cap, self.Mdev, (m, p, n),
+                                          scale=1.0 / self.c2, out_dtype=out_dt, compute=back,
+                                          ws=self.ws, tile=self.tile)
         # 6. error report
         err = ops.tsvdm_error(A, A_rec, ws=self.ws)
         return Result(A_rec, rho, offsets, U_pk, G_pk, S_pk, s2, stats, err, svd_status,

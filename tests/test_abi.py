@@ -255,3 +255,25 @@ def test_transform_mode_validation(lib):
     assert lib.tsvdm_transform_mode(*a) == -4
     assert lib.tsvdm_lowrank(DUMMY, DUMMY, 0, 8, 6, 3, DUMMY, DUMMY, -1, DUMMY, None) == -1
     assert lib.tsvdm_lowrank(DUMMY, DUMMY, 5, 8, 6, 3, DUMMY, DUMMY, 4, DUMMY, None) == -8
+
+
+def test_transform_dct_validation(lib):
+    # every rejection happens on the host, before any launch
+    from ctypes import c_int64
+    dims = (c_int64 * 3)(5, 4, 16)
+    ok = [DUMMY, 1, c_void_p(512), 1, 3, dims, 3, 0, 1, None]
+    a = list(ok); a[7] = 2           # inverse must be 0 or 1
+    assert lib.tsvdm_transform_dct(*a) == -1
+    a = list(ok); a[8] = 2           # BF16 arithmetic is not offered
+    assert lib.tsvdm_transform_dct(*a) == -8
+    a = list(ok); a[6] = 4           # k > d
+    assert lib.tsvdm_transform_dct(*a) == -1
+    a = list(ok); a[2] = DUMMY       # Y aliases X
+    assert lib.tsvdm_transform_dct(*a) == -1
+    for n in (1, 12, 2048):          # not a power of two in [2, 1024]
+        a = list(ok); a[5] = (c_int64 * 3)(5, 4, n)
+        assert lib.tsvdm_transform_dct(*a) == -2
+    a = list(ok); a[5] = (c_int64 * 3)(1 << 16, 1 << 15, 2)   # rows before mode 3 >= 2^31
+    assert lib.tsvdm_transform_dct(*a) == -2
+    a = list(ok); a[5] = None
+    assert lib.tsvdm_transform_dct(*a) == -1
