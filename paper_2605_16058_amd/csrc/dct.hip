@@ -43,17 +43,18 @@ constexpr int bitrev(int x, int bits) {
 }
 
 // Geometry for n = 2^L: n1 = 2^ceil(L/2) threads per tube, n2 = n / n1; TB
-// tubes per workgroup, halved until the padded tile and the three twiddle
-// tables (5n values) fit in 64 KB of LDS.
+// tubes per workgroup (at most 512 threads; 32 tubes make every access of
+// a wave 128 contiguous bytes per index), halved until the padded tile and
+// the three twiddle tables (5n values) fit in 80 KB of LDS.
 template <class CT, int L>
 struct DctCfg {
     static constexpr int n = 1 << L;
     static constexpr int n1 = 1 << ((L + 1) / 2);
     static constexpr int n2 = n / n1;
     static constexpr size_t lds(int tb) { return ((size_t)tb * (n + 1) * 2 + (size_t)5 * n) * sizeof(CT); }
-    static constexpr int fit(int tb) { return (tb > 1 && lds(tb) > 65536) ? fit(tb / 2) : tb; }
-    static_assert(lds(1) <= 65536, "transform length too large for the LDS");
-    static constexpr int TB = fit(256 / n1);
+    static constexpr int fit(int tb) { return (tb > 1 && lds(tb) > 81920) ? fit(tb / 2) : tb; }
+    static_assert(lds(1) <= 81920, "transform length too large for the LDS");
+    static constexpr int TB = fit(512 / n1 < 32 ? 512 / n1 : 32);
     static constexpr int THREADS = TB * n1;
 };
 
