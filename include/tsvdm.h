@@ -185,6 +185,15 @@ int tsvdm_slice_svd(void* A_hat, int dtype, int64_t m, int64_t p, int64_t n,
                     int block, int max_sweeps, double tol, int host_poll,
                     void* ws, size_t ws_bytes, void* stream);
 
+/* Slice SVDs of a subset: as tsvdm_slice_svd, but only the slices with
+ * run[i] != 0 (run: device int32[n]) are computed; every other slice keeps
+ * its A_hat, W and s2 entries untouched, so several calls can fill one set
+ * of outputs.  Used by the certified t-SVDM-II selection below. */
+int tsvdm_slice_svd_subset(void* A_hat, int dtype, int64_t m, int64_t p, int64_t n,
+                           void* W, double* s2, int32_t* status, const int32_t* run,
+                           int block, int max_sweeps, double tol, int host_poll,
+                           void* ws, size_t ws_bytes, void* stream);
+
 /* --------------------------------------------------------------------- */
 /* truncation                                                            */
 /* --------------------------------------------------------------------- */
@@ -210,6 +219,34 @@ int tsvdm_truncate_tol_workspace_size(int64_t r, int64_t n, size_t* bytes);
 int tsvdm_truncate_tol(const double* s2, int64_t r, int64_t n, double eps,
                        int32_t* rho, int64_t* offsets, double* stats,
                        void* ws, size_t ws_bytes, void* stream);
+
+/* Certified t-SVDM-II selection (Algorithm 2; Section 4.1: t-SVDM-II
+ * discards many slices entirely).  A slice i without an SVD enters the
+ * selection as one value, its energy E_i = ||A_hat_i||_F^2 (all its squared
+ * singular values are <= E_i and sum to it).  If after tsvdm_truncate_tol
+ * every such E_i is strictly below tau, the selection, tau and every rank are
+ * exactly those of the full selection (totals agree to rounding: the
+ * energies stand in for sums of squared singular values) and those slices
+ * get rank 0; otherwise the slices with E_i >= tau need their SVD and the
+ * selection is repeated.  One round:
+ *   tsvdm_slice_svd_subset(run) -> tsvdm_certify_lump -> tsvdm_truncate_tol
+ *   -> tsvdm_certify_check (certified, or run = the slices to add).
+ * tsvdm_slice_energy: E[i] = sum of squares of slice i (device FP64[n]),
+ *   FP64, fixed summation order.
+ * tsvdm_certify_lump: s2[:, i] = (E_i, 0, ..., 0) for computed[i] == 0
+ *   (s2: device FP64 [r x n]; computed: device int32[n]).
+ * tsvdm_certify_check: certified (device int32[1]) = every E_i with
+ *   computed[i] == 0 is finite and < stats[0] (tau, from tsvdm_truncate_tol);
+ *   run_next[i] = 1 for those that are not, and computed[i] becomes 1 for
+ *   them.  force = 1 instead moves every uncomputed slice into run_next (and
+ *   computed) and reports certified = 0: the full computation. */
+int tsvdm_slice_energy(const void* A_hat, int dtype, int64_t m, int64_t p, int64_t n,
+                       double* E, void* stream);
+int tsvdm_certify_lump(const double* E, const int32_t* computed, double* s2,
+                       int64_t r, int64_t n, void* stream);
+int tsvdm_certify_check(const double* E, const double* stats, int32_t* computed,
+                        int32_t* run_next, int64_t n, int force, int32_t* certified,
+                        void* stream);
 
 /* --------------------------------------------------------------------- */
 /* factor emission (Algorithm 2's final loop; Section 3.4 packed layout) */

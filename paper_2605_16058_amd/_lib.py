@@ -35,6 +35,11 @@ _SIGS = {
     "tsvdm_slice_svd_workspace_size": (c_int, [c_int64, c_int64, c_int64, c_int, POINTER(c_size_t)]),
     "tsvdm_slice_svd": (c_int, [_P, c_int, c_int64, c_int64, c_int64, _P, _P, _P, c_int, c_int,
                                 c_double, c_int, _P, c_size_t, _P]),
+    "tsvdm_slice_svd_subset": (c_int, [_P, c_int, c_int64, c_int64, c_int64, _P, _P, _P, _P, c_int,
+                                       c_int, c_double, c_int, _P, c_size_t, _P]),
+    "tsvdm_slice_energy": (c_int, [_P, c_int, c_int64, c_int64, c_int64, _P, _P]),
+    "tsvdm_certify_lump": (c_int, [_P, _P, _P, c_int64, c_int64, _P]),
+    "tsvdm_certify_check": (c_int, [_P, _P, _P, _P, c_int64, c_int, _P, _P]),
     "tsvdm_truncate_rank": (c_int, [c_int64, c_int64, c_int64, _P, _P, _P]),
     "tsvdm_truncate_tol_workspace_size": (c_int, [c_int64, c_int64, POINTER(c_size_t)]),
     "tsvdm_truncate_tol": (c_int, [_P, c_int64, c_int64, c_double, _P, _P, _P, _P, c_size_t, _P]),

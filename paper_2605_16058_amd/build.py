@@ -21,7 +21,7 @@ BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libtsvdm.so")
 ROOT = os.path.dirname(HERE)
 
-SOURCES = ["api.cpp", "ttm.hip", "dct.hip", "jacobi.hip", "select.hip", "pack.hip", "reduce.hip",
+SOURCES = ["api.cpp", "ttm.hip", "dct.hip", "jacobi.hip", "certify.hip", "select.hip", "pack.hip", "reduce.hip",
            "backward.hip", "batch.cpp"]
 
 ARCH = "gfx950"

@@ -263,6 +263,59 @@ int tsvdm_truncate_tol(const double* s2, int64_t r, int64_t n, double eps, int32
     return run_truncate_tol(s2, r, n, eps, rho, offsets, stats, ws, as_stream(stream));
 }
 
+int tsvdm_slice_svd_subset(void* A_hat, int dtype, int64_t m, int64_t p, int64_t n, void* W,
+                           double* s2, int32_t* status, const int32_t* run, int block,
+                           int max_sweeps, double tol, int host_poll, void* ws, size_t ws_bytes,
+                           void* stream) {
+    clear_error();
+    TSVDM_REQUIRE(run != nullptr, TSVDM_E_ARG, "run must be non-NULL");
+    TSVDM_TRY(check_shape(m, p, n));
+    TSVDM_REQUIRE(A_hat && W && s2 && status, TSVDM_E_ARG, "A_hat, W, s2 and status must be non-NULL");
+    TSVDM_REQUIRE(io_dtype(dtype), TSVDM_E_UNSUPPORTED, "dtype must be F64 or F32");
+    TSVDM_REQUIRE(block == 0 || block == 16 || block == 32, TSVDM_E_ARG, "block must be 0, 16 or 32");
+    TSVDM_REQUIRE(max_sweeps >= 0 && max_sweeps <= 1000, TSVDM_E_ARG, "max_sweeps must be in [0, 1000]");
+    TSVDM_REQUIRE(tol >= 0.0 && tol < 1.0 && std::isfinite(tol), TSVDM_E_ARG, "tol must lie in [0, 1)");
+    TSVDM_REQUIRE(host_poll == 0 || host_poll == 1, TSVDM_E_ARG, "host_poll must be 0 or 1");
+    TSVDM_TRY(check_ws(ws, ws_bytes, jacobi_workspace_bytes(n)));
+    JacobiOpts o = jacobi_default_opts(m, p, dtype);
+    if (block) o.block = 2 * block;
+    if (max_sweeps) o.max_sweeps = max_sweeps;
+    if (tol > 0.0) o.tol = tol;
+    o.host_poll = host_poll;
+    o.run = run;
+    return run_jacobi(A_hat, dtype, m, p, n, W, s2, status, o, ws, as_stream(stream));
+}
+
+int tsvdm_slice_energy(const void* A_hat, int dtype, int64_t m, int64_t p, int64_t n, double* E,
+                       void* stream) {
+    clear_error();
+    TSVDM_TRY(check_shape(m, p, n));
+    TSVDM_REQUIRE(A_hat && E, TSVDM_E_ARG, "A_hat and E must be non-NULL");
+    TSVDM_REQUIRE(io_dtype(dtype), TSVDM_E_UNSUPPORTED, "dtype must be F64 or F32");
+    return run_slice_energy(A_hat, dtype, m, p, n, E, as_stream(stream));
+}
+
+int tsvdm_certify_lump(const double* E, const int32_t* computed, double* s2, int64_t r, int64_t n,
+                       void* stream) {
+    clear_error();
+    TSVDM_REQUIRE(E && computed && s2, TSVDM_E_ARG, "E, computed and s2 must be non-NULL");
+    TSVDM_REQUIRE(r >= 1 && n >= 1 && r <= (((int64_t)1 << 46) / n), TSVDM_E_SHAPE,
+                  "r and n must be positive (r*n below 2^46)");
+    return run_lump_s2(E, computed, s2, r, n, as_stream(stream));
+}
+
+int tsvdm_certify_check(const double* E, const double* stats, int32_t* computed, int32_t* run_next,
+                        int64_t n, int force, int32_t* certified, void* stream) {
+    clear_error();
+    TSVDM_REQUIRE(E && stats && computed && run_next && certified, TSVDM_E_ARG,
+                  "E, stats, computed, run_next and certified must be non-NULL");
+    TSVDM_REQUIRE(n >= 1, TSVDM_E_SHAPE, "n must be positive");
+    TSVDM_REQUIRE(force == 0 || force == 1, TSVDM_E_ARG, "force must be 0 or 1");
+    TSVDM_REQUIRE((const void*)computed != (const void*)run_next, TSVDM_E_ARG,
+                  "computed and run_next must be distinct");
+    return run_certify(E, stats, computed, run_next, n, force, certified, as_stream(stream));
+}
+
 // ------------------------------------------------------------- pack
 
 int tsvdm_pack_workspace_size(int64_t m, int64_t p, int64_t n, size_t* bytes) {

@@ -155,21 +155,24 @@ __device__ __forceinline__ int sym_idx(int a, int b) {
     return hi * (hi + 1) / 2 + lo;
 }
 
+// W = I and a clean control word per slice; slices outside `run` (when
+// given) keep their W and start as done, so no round touches them.
 template <class T>
 __global__ void jacobi_init(T* __restrict__ W, int64_t r, int64_t n, JacobiCtl* __restrict__ ctl,
                             int* __restrict__ remaining, int max_sweeps,
                             unsigned long long* __restrict__ pair_counts,
-                            int32_t* __restrict__ status) {
+                            int32_t* __restrict__ status, const int32_t* __restrict__ run) {
     const int64_t rr = r * r;
     const int64_t total = rr * n;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total; idx += stride) {
+        if (run && !run[idx / rr]) continue;
         int64_t e = idx % rr;
         W[idx] = (e % r == e / r) ? T(1) : T(0);
     }
     for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < n; idx += stride) {
         JacobiCtl c;
-        c.maxcos_bits = 0ull; c.done = 0; c.sweeps = 0; c.nonfinite = 0; c.pad = 0;
+        c.maxcos_bits = 0ull; c.done = (run && !run[idx]) ? 1 : 0; c.sweeps = 0; c.nonfinite = 0; c.pad = 0;
         ctl[idx] = c;
     }
     if (blockIdx.x == 0) {
@@ -864,11 +867,12 @@ __global__ void jacobi_sweep_end(JacobiCtl* __restrict__ ctl, int64_t n, double 
 // squared norms of the final vectors, FP64, fixed summation order
 template <class T>
 __global__ __launch_bounds__(256) void jacobi_norms_rows(const T* __restrict__ A, SliceGeom g,
-                                                         double* __restrict__ s2) {
+                                                         double* __restrict__ s2,
+                                                         const int32_t* __restrict__ run) {
     // rows case (vs = 1, es = m): thread per vector, coalesced across threads
     const int64_t s = blockIdx.y;
     const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (j >= g.r) return;
+    if (j >= g.r || (run && !run[s])) return;
     const T* Ab = A + s * g.m * g.p;
     double acc = 0.0;
     for (int64_t t = 0; t < g.L; ++t) {
@@ -881,12 +885,14 @@ __global__ __launch_bounds__(256) void jacobi_norms_rows(const T* __restrict__ A
 template <class T>
 __global__ __launch_bounds__(256) void jacobi_norms_cols(const T* __restrict__ A, SliceGeom g,
                                                          int64_t total_vectors,
-                                                         double* __restrict__ s2) {
+                                                         double* __restrict__ s2,
+                                                         const int32_t* __restrict__ run) {
     // columns case: one wavefront per contiguous vector
     const int64_t v = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
     if (v >= total_vectors) return;
     const int64_t s = v / g.r, j = v % g.r;
+    if (run && !run[s]) return;
     const T* x = A + s * g.m * g.p + j * g.vs;
     double acc = 0.0;
     for (int64_t t = lane; t < g.L; t += 64) {
@@ -927,7 +933,7 @@ int jacobi_impl(T* A, int64_t m, int64_t p, int64_t n, T* W, double* s2, int32_t
     if (gblocks > 65535 * 16) gblocks = 65535 * 16;
     if (gblocks < 1) gblocks = 1;
     jacobi_init<T><<<(unsigned)gblocks, 256, 0, st>>>(W, g.r, n, ctl, remaining, o.max_sweeps,
-                                                      pair_counts, status);
+                                                      pair_counts, status, o.run);
     TSVDM_LAUNCH_CHECK();
 
     constexpr int B = NB2 / 2;
@@ -974,10 +980,10 @@ int jacobi_impl(T* A, int64_t m, int64_t p, int64_t n, T* W, double* s2, int32_t
     }
     if (!g.rows) {
         const int64_t tv = g.r * n;
-        jacobi_norms_cols<T><<<(unsigned)((tv + 3) / 4), 256, 0, st>>>(A, g, tv, s2);
+        jacobi_norms_cols<T><<<(unsigned)((tv + 3) / 4), 256, 0, st>>>(A, g, tv, s2, o.run);
     } else {
         dim3 grid((unsigned)((g.r + 255) / 256), (unsigned)n);
-        jacobi_norms_rows<T><<<grid, 256, 0, st>>>(A, g, s2);
+        jacobi_norms_rows<T><<<grid, 256, 0, st>>>(A, g, s2, o.run);
     }
     TSVDM_LAUNCH_CHECK();
     jacobi_finish<<<1, 256, 0, st>>>(ctl, n, status);

@@ -89,12 +89,12 @@ int run_ttm_batch(const TtmProblem* probs, int nprob, const int4* tasks, const i
 int run_ttm(const void* X, int xdt, void* Y, int ydt, int64_t m, int64_t p, int64_t n,
             const double* M, int transpose, double scale, int compute, int tile, void* ws,
             hipStream_t st);
-// P consecutive blocks of R x n elements, each Y_b = X_b x_last (scale * op(M))
 // Fast orthonormal DCT-II (inverse: its transpose) along the middle index
 // of R x n x P (column-major); n a power of two in [2, 1024]; compute F32 or
 // F64 (the FFT arithmetic); inputs / outputs F32 or F64.
 int run_dct_mode(const void* X, int xdt, void* Y, int ydt, int64_t R, int64_t n, int64_t P,
                  int inverse, int compute, hipStream_t st);
+// P consecutive blocks of R x n elements, each Y_b = X_b x_last (scale * op(M))
 int run_ttm_mode(const void* X, int xdt, void* Y, int ydt, int64_t R, int64_t n, int64_t P,
                  const double* M, int transpose, double scale, int compute, int tile, void* ws,
                  hipStream_t st);
@@ -113,6 +113,9 @@ struct JacobiOpts {
     int max_sweeps;
     double tol;
     int host_poll;
+    // device int32[n] or null: slices with run[i] == 0 are left untouched
+    // (their A, W and s2 keep whatever they hold)
+    const int32_t* run = nullptr;
 };
 
 size_t jacobi_workspace_bytes(int64_t n);
@@ -124,6 +127,14 @@ void stats_get(int64_t* launches, double* ms, int64_t* pairs_gram, int64_t* pair
 int run_jacobi(void* A, int dt, int64_t m, int64_t p, int64_t n, void* W, double* s2,
                int32_t* status, const JacobiOpts& o, void* ws, hipStream_t st);
 JacobiOpts jacobi_default_opts(int64_t m, int64_t p, int dt);
+
+// ---- certified rank selection (certify.hip)
+int run_slice_energy(const void* A, int dt, int64_t m, int64_t p, int64_t n, double* E,
+                     hipStream_t st);
+int run_lump_s2(const double* E, const int32_t* computed, double* s2, int64_t r, int64_t n,
+                hipStream_t st);
+int run_certify(const double* E, const double* stats, int32_t* computed, int32_t* run_next,
+                int64_t n, int force, int32_t* certified, hipStream_t st);
 
 // ---- selection (select.hip)
 size_t select_workspace_bytes(int64_t r, int64_t n);

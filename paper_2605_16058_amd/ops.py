@@ -214,6 +214,54 @@ def tsvdm_truncate_rank(k, r, n, device="cuda"):
     return rho, offsets
 
 
+def tsvdm_slice_svd_outputs(A_hat):
+    """Uninitialised W (n, r, r), s2 (n, r) and a status word for A_hat."""
+    m, p, n = A_hat.shape
+    r = min(m, p)
+    W = torch.empty((n, r, r), dtype=A_hat.dtype, device=A_hat.device)
+    s2 = torch.empty((n, r), dtype=torch.float64, device=A_hat.device)
+    status = torch.zeros(1, dtype=torch.int32, device=A_hat.device)
+    return W, s2, status
+
+
+def tsvdm_slice_svd_subset(A_hat, run, W, s2, status, block=0, max_sweeps=0, tol=0.0,
+                           host_poll=True, ws=None):
+    """Jacobi on the slices with run[i] != 0 (device int32[n]); the others keep
+    their A_hat, W and s2 entries."""
+    if not is_colmajor(A_hat):
+        raise ValueError("A_hat must be column-major (it is overwritten in place)")
+    m, p, n = A_hat.shape
+    r = min(m, p)
+    if tuple(W.shape) != (n, r, r) or tuple(s2.shape) != (n, r) or run.numel() != n:
+        raise ValueError("W, s2 or run do not match A_hat")
+    w = _ws(ws)
+    wp, wn = w.args(_lib.workspace_size("tsvdm_slice_svd_workspace_size", m, p, n, _dt(A_hat)))
+    _lib.call("tsvdm_slice_svd_subset", _ptr(A_hat), _dt(A_hat), m, p, n, _ptr(W), _ptr(s2),
+              _ptr(status), _ptr(run), int(block), int(max_sweeps), float(tol),
+              int(bool(host_poll)), wp, wn, _stream())
+    return status
+
+
+def tsvdm_slice_energy(A_hat):
+    """E[i] = ||A_hat[:, :, i]||_F^2 in FP64."""
+    A_hat = as_colmajor(A_hat)
+    m, p, n = A_hat.shape
+    E = torch.empty(n, dtype=torch.float64, device=A_hat.device)
+    _lib.call("tsvdm_slice_energy", _ptr(A_hat), _dt(A_hat), m, p, n, _ptr(E), _stream())
+    return E
+
+
+def tsvdm_certify_lump(E, computed, s2):
+    n, r = s2.shape
+    _lib.call("tsvdm_certify_lump", _ptr(E), _ptr(computed), _ptr(s2), r, n, _stream())
+
+
+def tsvdm_certify_check(E, stats, computed, run_next, force, certified):
+    n = E.numel()
+    _lib.call("tsvdm_certify_check", _ptr(E), _ptr(stats), _ptr(computed), _ptr(run_next), n,
+              int(bool(force)), _ptr(certified), _stream())
+
+
 def tsvdm_truncate_tol(s2, eps, ws=None):
     """s2: (n, r) FP64 device tensor (slice-major).  Returns rho, offsets,
     stats = [tau, discarded, total, J]."""

@@ -38,6 +38,8 @@ class Result:
     svd_status: torch.Tensor
     pack_status: torch.Tensor
     capacity: int
+    computed: torch.Tensor | None = None   # certified selection: slices given an SVD
+    passes: int = 0                         # certified selection: SVD rounds
 
     def rel_error(self) -> float:
         e = self.err.double().cpu()
@@ -54,11 +56,23 @@ class TSVDM:
     must then be the orthonormal DCT-II (or None), by FFT (tsvdm_transform_dct)
     instead of the dense product: forward, and after the transform-domain
     low-rank product (tsvdm_lowrank) backward; precision f64 or f32 only.
+
+    certify=True (mode "II") runs the certified selection: only slices whose
+    energy could reach the threshold get an SVD.  The first round computes
+    the slices outside the lowest-energy set holding theta * eps^2 of the
+    total (theta = 0.5); every other slice enters the selection as its
+    energy, and if all those stand-ins fall strictly below the resulting tau,
+    the ranks are those of the full method (the skipped slices get rank 0).
+    Otherwise the stand-ins at or above tau get their SVD and the selection
+    is repeated, at most max_passes rounds before the remaining slices are
+    all computed.  Result.computed marks the slices given an SVD; s2 holds
+    the energy stand-ins for the others.
     """
 
     def __init__(self, shape, M, mode="II", k=None, eps=None, precision="f64",
                  block=0, max_sweeps=0, tol=0.0, host_poll=True, capacity="max",
-                 device="cuda", check_m=True, tile=0, transform="dense"):
+                 device="cuda", check_m=True, tile=0, transform="dense", certify=False,
+                 theta=0.5, max_passes=3):
         self.m, self.p, self.n = (int(x) for x in shape)
         self.r = min(self.m, self.p)
         if mode not in ("I", "II"):
@@ -93,6 +107,11 @@ class TSVDM:
         self.Mdev = ops.device_matrix(M, device)
         self.block, self.max_sweeps, self.tol, self.host_poll = block, max_sweeps, tol, host_poll
         self.tile = tile
+        if certify and mode != "II":
+            raise ValueError("certify applies to mode II")
+        if not (0.0 < float(theta) <= 1.0) or int(max_passes) < 1:
+            raise ValueError("theta must lie in (0, 1] and max_passes be >= 1")
+        self.certify, self.theta, self.max_passes = bool(certify), float(theta), int(max_passes)
         self.capacity_mode = capacity
         self.device = device
         self.ws = ops.Workspace(device)
@@ -111,15 +130,18 @@ class TSVDM:
             A_hat = ops.tsvdm_transform(A, self.Mdev, transpose=False, scale=1.0,
                                         compute=self.ttm_compute, out_dtype=self.dtype, ws=self.ws,
                                         tile=self.tile)
-        # 2. slice SVDs
-        W, s2, svd_status = ops.tsvdm_slice_svd(A_hat, self.block, self.max_sweeps, self.tol,
-                                                self.host_poll, ws=self.ws)
-        # 3. ranks
-        if self.mode == "I":
-            rho, offsets = ops.tsvdm_truncate_rank(self.k, r, n, self.device)
-            stats = torch.full((4,), float("nan"), dtype=torch.float64, device=self.device)
+        # 2. slice SVDs, 3. ranks
+        computed, passes = None, 0
+        if self.certify:
+            W, s2, svd_status, rho, offsets, stats, computed, passes = self._certified(A_hat)
         else:
-            rho, offsets, stats = ops.tsvdm_truncate_tol(s2, self.eps, ws=self.ws)
+            W, s2, svd_status = ops.tsvdm_slice_svd(A_hat, self.block, self.max_sweeps, self.tol,
+                                                    self.host_poll, ws=self.ws)
+            if self.mode == "I":
+                rho, offsets = ops.tsvdm_truncate_rank(self.k, r, n, self.device)
+                stats = torch.full((4,), float("nan"), dtype=torch.float64, device=self.device)
+            else:
+                rho, offsets, stats = ops.tsvdm_truncate_tol(s2, self.eps, ws=self.ws)
         if self.capacity_mode == "exact":
             cap = int(offsets[n].item())
         elif self.mode == "I":
@@ -141,7 +163,35 @@ class TSVDM:
         # 6. error report
         err = ops.tsvdm_error(A, A_rec, ws=self.ws)
         return Result(A_rec, rho, offsets, U_pk, G_pk, S_pk, s2, stats, err, svd_status,
-                      pack_status, cap)
+                      pack_status, cap, computed, passes)
+
+    def _certified(self, A_hat):
+        n = self.n
+        dev = A_hat.device
+        W, s2, svd_status = ops.tsvdm_slice_svd_outputs(A_hat)
+        E = ops.tsvdm_slice_energy(A_hat)
+        # round 1: everything outside the lowest-energy set holding theta eps^2
+        run, _, _ = ops.tsvdm_truncate_tol(E.view(n, 1), self.eps * self.theta ** 0.5, ws=self.ws)
+        computed = run.clone()
+        spare = torch.empty_like(run)
+        certified = torch.zeros(1, dtype=torch.int32, device=dev)
+        passes = 0
+        while True:
+            st = torch.zeros(1, dtype=torch.int32, device=dev)
+            ops.tsvdm_slice_svd_subset(A_hat, run, W, s2, st, self.block, self.max_sweeps, self.tol,
+                                       self.host_poll, ws=self.ws)
+            svd_status = torch.minimum(svd_status, st)
+            passes += 1
+            ops.tsvdm_certify_lump(E, computed, s2)
+            rho, offsets, stats = ops.tsvdm_truncate_tol(s2, self.eps, ws=self.ws)
+            if passes > self.max_passes:
+                break   # the forced round computed every remaining slice
+            ops.tsvdm_certify_check(E, stats, computed, spare, passes == self.max_passes,
+                                    certified)
+            if int(certified.item()):
+                break
+            run, spare = spare, run
+        return W, s2, svd_status, rho, offsets, stats, computed, passes
 
 
 def tsvdm(A, M, mode="II", k=None, eps=None, precision="f64", **kw) -> Result:
