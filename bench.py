@@ -270,6 +270,74 @@ def bench_climate(a, torch, lib):
 
 
 # ---------------------------------------------------------------------------
+# certified selection
+# ---------------------------------------------------------------------------
+
+def bench_certify(a, torch, lib):
+    """t-SVDM-II with the certified selection (slices provably below the
+    threshold skip their SVD) against the full selection, FP32 path, on the
+    climate-like recipe with a quieter field (--noise, default 1e-4 of the
+    RMS): same ranks required, both timed."""
+    import numpy as np
+
+    import synth
+    from paper_2605_16058_amd.pipeline import TSVDM, TSVDMd
+
+    if a.order6:
+        dims = (73, 144, 17, 4, 365, 2)
+        log(f"generating the order-6 climate-like tensor {dims}, noise {a.noise}")
+        A = synth.climate6_like(*dims[:3], days=dims[4], years=dims[5], noise=a.noise,
+                                rng=np.random.default_rng(12))
+        Ms = [synth.dct2_matrix(x) for x in dims[2:]]
+        Ad = to_device_nd(A, torch)
+        n = int(np.prod(dims[2:]))
+        desc = f"order-6 climate-like {'x'.join(map(str, dims))} FP32, DCT-II along modes 3-6"
+        block = a.block or 16
+        kw = dict(mode="II", eps=a.eps, precision="f32", block=block)
+        plain = TSVDMd(dims, Ms, **kw)
+        cert = TSVDMd(dims, Ms, certify=True, **kw)
+    else:
+        m, p, n = (int(x) for x in a.shape.split(","))
+        log(f"generating climate-like {m}x{p}x{n} FP32, noise {a.noise}")
+        A = synth.climate_like(m, p, n, noise=a.noise, rng=np.random.default_rng(2))
+        M = synth.dct2_matrix(n)
+        Ad = to_device(A, torch)
+        desc = f"climate-like {m}x{p}x{n} FP32, DCT-II (FFT)"
+        block = a.block or 32
+        kw = dict(mode="II", eps=a.eps, precision="f32", block=block, transform="dct")
+        plain = TSVDM((m, p, n), M, **kw)
+        cert = TSVDM((m, p, n), M, certify=True, **kw)
+    in_bytes = A.size * 4
+    del A
+    for _ in range(a.warmup):
+        plain(Ad)
+        cert(Ad)
+    r_plain, ms_plain = timed(lambda: plain(Ad), a.steps, torch)
+    r_cert, ms_cert = timed(lambda: cert(Ad), a.steps, torch)
+    same = bool(torch.equal(r_plain.rho.cpu(), r_cert.rho.cpu()))
+    computed = int(r_cert.computed.sum().item())
+    log(f"plain {ms_plain:.2f} ms, certified {ms_cert:.2f} ms ({computed}/{n} slices computed, "
+        f"{r_cert.passes} rounds), ranks equal {same}")
+    return {
+        "metric": "input GB/s through certified t-SVDM-II (FP32)",
+        "value": round(in_bytes / (ms_cert * 1e-3) / 1e9, 3),
+        "unit": "GB/s", "n_gpus": 1, "steps": a.steps, "warmup": a.warmup,
+        "ms_per_step": round(ms_cert, 3), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"{desc}, noise {a.noise} of the RMS, t-SVDM-II tol {a.eps}, "
+                               "certified selection",
+                   "block": block},
+        "plain_GBs": round(in_bytes / (ms_plain * 1e-3) / 1e9, 3),
+        "plain_ms_per_step": round(ms_plain, 3),
+        "speedup_vs_plain": round(ms_plain / ms_cert, 3),
+        "slices_computed": computed, "slices": n, "rounds": r_cert.passes,
+        "ranks_equal": same, "sum_rho": int(r_cert.offsets[-1].item()),
+        "rel_error": r_cert.rel_error(), "plain_rel_error": r_plain.rel_error(),
+        "roofline": None, "cpu_baseline": None,
+    }
+
+
+# ---------------------------------------------------------------------------
 # ragged batch
 # ---------------------------------------------------------------------------
 
@@ -597,12 +665,16 @@ def main(argv=None):
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="climate",
-                    choices=["climate", "ragged", "turbulence", "cayley", "climate6"])
+                    choices=["climate", "ragged", "turbulence", "cayley", "climate6", "certify"])
     ap.add_argument("--precision", default="f32", choices=["f32", "bf16x3", "bf16"])
     ap.add_argument("--eps", type=float, default=1e-3)
     ap.add_argument("--shape", default="512,1024,256")
     ap.add_argument("--transform", default="dct", choices=["dct", "dense"],
                     help="climate: apply the DCT-II by FFT (dct) or as a dense MFMA product")
+    ap.add_argument("--noise", type=float, default=1e-4,
+                    help="certify: relative noise of the climate-like field")
+    ap.add_argument("--order6", action="store_true",
+                    help="certify: the order-6 climate-like tensor instead of the 3-way one")
     ap.add_argument("--no-f64", action="store_true", help="skip the FP64 comparison path")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-n", type=int, default=32)
@@ -638,7 +710,7 @@ def main(argv=None):
 
     lib = _lib.load()
     fn = {"climate": bench_climate, "ragged": bench_ragged, "turbulence": bench_turbulence,
-          "cayley": bench_cayley, "climate6": bench_climate6}[a.workload]
+          "cayley": bench_cayley, "climate6": bench_climate6, "certify": bench_certify}[a.workload]
     line = fn(a, torch, lib)
     print(json.dumps(line), flush=True)
     return 0

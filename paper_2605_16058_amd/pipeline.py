@@ -166,32 +166,37 @@ class TSVDM:
                       pack_status, cap, computed, passes)
 
     def _certified(self, A_hat):
-        n = self.n
-        dev = A_hat.device
-        W, s2, svd_status = ops.tsvdm_slice_svd_outputs(A_hat)
-        E = ops.tsvdm_slice_energy(A_hat)
-        # round 1: everything outside the lowest-energy set holding theta eps^2
-        run, _, _ = ops.tsvdm_truncate_tol(E.view(n, 1), self.eps * self.theta ** 0.5, ws=self.ws)
-        computed = run.clone()
-        spare = torch.empty_like(run)
-        certified = torch.zeros(1, dtype=torch.int32, device=dev)
-        passes = 0
-        while True:
-            st = torch.zeros(1, dtype=torch.int32, device=dev)
-            ops.tsvdm_slice_svd_subset(A_hat, run, W, s2, st, self.block, self.max_sweeps, self.tol,
-                                       self.host_poll, ws=self.ws)
-            svd_status = torch.minimum(svd_status, st)
-            passes += 1
-            ops.tsvdm_certify_lump(E, computed, s2)
-            rho, offsets, stats = ops.tsvdm_truncate_tol(s2, self.eps, ws=self.ws)
-            if passes > self.max_passes:
-                break   # the forced round computed every remaining slice
-            ops.tsvdm_certify_check(E, stats, computed, spare, passes == self.max_passes,
-                                    certified)
-            if int(certified.item()):
-                break
-            run, spare = spare, run
-        return W, s2, svd_status, rho, offsets, stats, computed, passes
+        return certified_svd(A_hat, self.eps, self.theta, self.max_passes, self.block,
+                             self.max_sweeps, self.tol, self.host_poll, self.ws)
+
+
+def certified_svd(A_hat, eps, theta, max_passes, block, max_sweeps, tol, host_poll, ws):
+    """Slice SVDs and t-SVDM-II ranks with the certified selection (see
+    TSVDM): returns W, s2, status, rho, offsets, stats, computed, rounds."""
+    n = A_hat.shape[2]
+    dev = A_hat.device
+    W, s2, svd_status = ops.tsvdm_slice_svd_outputs(A_hat)
+    E = ops.tsvdm_slice_energy(A_hat)
+    # round 1: everything outside the lowest-energy set holding theta eps^2
+    run, _, _ = ops.tsvdm_truncate_tol(E.view(n, 1), eps * theta ** 0.5, ws=ws)
+    computed = run.clone()
+    spare = torch.empty_like(run)
+    certified = torch.zeros(1, dtype=torch.int32, device=dev)
+    passes = 0
+    while True:
+        st = torch.zeros(1, dtype=torch.int32, device=dev)
+        ops.tsvdm_slice_svd_subset(A_hat, run, W, s2, st, block, max_sweeps, tol, host_poll, ws=ws)
+        svd_status = torch.minimum(svd_status, st)
+        passes += 1
+        ops.tsvdm_certify_lump(E, computed, s2)
+        rho, offsets, stats = ops.tsvdm_truncate_tol(s2, eps, ws=ws)
+        if passes > max_passes:
+            break   # the forced round computed every remaining slice
+        ops.tsvdm_certify_check(E, stats, computed, spare, passes == max_passes, certified)
+        if int(certified.item()):
+            break
+        run, spare = spare, run
+    return W, s2, svd_status, rho, offsets, stats, computed, passes
 
 
 def tsvdm(A, M, mode="II", k=None, eps=None, precision="f64", **kw) -> Result:
@@ -213,8 +218,12 @@ class TSVDMd:
     """
 
     def __init__(self, dims, Ms, mode="II", k=None, eps=None, precision="f64", block=0,
-                 max_sweeps=0, tol=0.0, host_poll=True, device="cuda", tile=0):
+                 max_sweeps=0, tol=0.0, host_poll=True, device="cuda", tile=0, certify=False,
+                 theta=0.5, max_passes=3):
         self.dims = tuple(int(x) for x in dims)
+        if certify and mode != "II":
+            raise ValueError("certify applies to mode II")
+        self.certify, self.theta, self.max_passes = bool(certify), float(theta), int(max_passes)
         if len(self.dims) < 3:
             raise ValueError("order d >= 3")
         if len(Ms) != len(self.dims) - 2:
@@ -255,17 +264,23 @@ class TSVDMd:
                                      out_dtype=dt, out=out, ws=self.ws, tile=self.tile)
             cur = out
         A_hat = cur.permute(*range(d - 1, -1, -1)).reshape(N, p, m).permute(2, 1, 0)
-        # 2. slice SVDs over the N frontal slices
-        W, s2, svd_status = ops.tsvdm_slice_svd(A_hat, self.block, self.max_sweeps, self.tol,
-                                                self.host_poll, ws=self.ws)
-        # 3. ranks
-        if self.mode == "I":
-            rho, offsets = ops.tsvdm_truncate_rank(self.k, r, N, self.device)
-            stats = torch.full((4,), float("nan"), dtype=torch.float64, device=self.device)
-            cap = min(int(self.k), r) * N
-        else:
-            rho, offsets, stats = ops.tsvdm_truncate_tol(s2, self.eps, ws=self.ws)
+        # 2. slice SVDs over the N frontal slices, 3. ranks
+        computed, passes = None, 0
+        if self.certify:
+            W, s2, svd_status, rho, offsets, stats, computed, passes = certified_svd(
+                A_hat, self.eps, self.theta, self.max_passes, self.block, self.max_sweeps,
+                self.tol, self.host_poll, self.ws)
             cap = r * N
+        else:
+            W, s2, svd_status = ops.tsvdm_slice_svd(A_hat, self.block, self.max_sweeps, self.tol,
+                                                    self.host_poll, ws=self.ws)
+            if self.mode == "I":
+                rho, offsets = ops.tsvdm_truncate_rank(self.k, r, N, self.device)
+                stats = torch.full((4,), float("nan"), dtype=torch.float64, device=self.device)
+                cap = min(int(self.k), r) * N
+            else:
+                rho, offsets, stats = ops.tsvdm_truncate_tol(s2, self.eps, ws=self.ws)
+                cap = r * N
         # 4. factors
         U_pk, G_pk, S_pk, pack_status = ops.tsvdm_pack(A_hat, W, s2, rho, offsets, cap, ws=self.ws)
         # 5. transform-domain low-rank product, then back-transforms mode by mode
@@ -285,7 +300,7 @@ class TSVDMd:
         # 6. error report
         err = ops.tsvdm_error(A, A_rec, ws=self.ws)
         return Result(A_rec, rho, offsets, U_pk, G_pk, S_pk, s2, stats, err, svd_status,
-                      pack_status, cap)
+                      pack_status, cap, computed, passes)
 
 
 class BatchTSVDM:
