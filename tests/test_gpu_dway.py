@@ -83,6 +83,12 @@ def test_tsvdmd_order3_equals_tsvdm():
     assert torch.equal(a.rho, b.rho) and torch.equal(a.A_rec, b.A_rec)
 
 
+# Alg. 2 keeps the tail below eps exactly; the FP32 path's factors carry
+# its rounding, so its measured error is held to eps (1 + FP32_REL), the
+# FP32 reconstruction bound of the parity tests
+FP32_REL = 3e-5
+
+
 def _margin(S, tau):
     v = np.sort((S ** 2).ravel())
     if not np.isfinite(tau) or not np.any(v > tau):
@@ -122,7 +128,7 @@ def test_tsvdmd_matches_oracle(dims, mode, arg):
             assert rel(res.A_rec.double().cpu().numpy(), ref["A_rec"]) * \
                 np.linalg.norm(ref["A_rec"]) / np.linalg.norm(A) <= 3e-5
         if mode == "II":
-            assert res.rel_error() < arg
+            assert res.rel_error() < (arg if prec == "f64" else arg * (1 + FP32_REL))
 
 
 def test_climate6_small_matches_oracle():
@@ -143,4 +149,4 @@ def test_climate6_small_matches_oracle():
             assert d <= bound, (prec, d)
         else:
             assert prec == "f32" or _margin(ref["S"], ref["info"]["tau"]) <= 1e-10
-        assert res.rel_error() < w.eps
+        assert res.rel_error() < (w.eps if prec == "f64" else w.eps * (1 + FP32_REL))

@@ -27,6 +27,13 @@ pytestmark = [pytest.mark.gpu, pytest.mark.slow]
 torch = pytest.importorskip("torch")
 
 
+# Alg. 2 keeps the tail below eps exactly; the FP32 path's factors carry its
+# rounding (orthogonality to the Jacobi tolerance), so its measured error is
+# held to eps (1 + 3e-5), the FP32 reconstruction bound of the parity tests
+def eps_bound(eps, precision):
+    return eps if precision == "f64" else eps * (1 + 3e-5)
+
+
 def to_dev(A, dtype=torch.float32):
     out = torch.empty((A.shape[2], A.shape[1], A.shape[0]), dtype=dtype, device="cuda").permute(2, 1, 0)
     out.copy_(torch.from_numpy(np.asfortranarray(A)).to(dtype))
@@ -85,7 +92,9 @@ def check_single(res, A64, Ad, M, eps, idx, precision):
     # 2. the measured error against the predicted one (Eckart-Young) and eps
     rel_e = res.rel_error()
     pred = math.sqrt(info["discarded"] / info["total"])
-    assert rel_e < eps
+    print(f"{precision}: rel error {rel_e:.9e}, predicted {pred:.9e}, eps {eps}")
+    assert pred < eps
+    assert rel_e < eps_bound(eps, precision)
     assert abs(rel_e - pred) <= (1e-9 if fp64 else 1e-2) * pred
     # 3. sampled slices against the oracle
     Ah = sampled_slices(A64, M, idx)
@@ -161,7 +170,7 @@ def test_ragged_batch_full_size(ragged, precision):
     errs = b.rel_errors()
     for t, md in enumerate(w.mode):
         if md == "II":
-            assert errs[t] < w.eps[t], t
+            assert errs[t] < eps_bound(w.eps[t], precision), t
     fp64 = precision == "f64"
     for t in range(0, len(Ts), len(Ts) // 8):
         A64 = w.A[t].astype(np.float64)
@@ -280,7 +289,7 @@ def test_climate6_full_size():
         assert np.array_equal(rho, rho_o)
         rel_e = res.rel_error()
         pred = math.sqrt(info["discarded"] / info["total"])
-        assert rel_e < w.eps
+        assert rel_e < eps_bound(w.eps, prec)
         assert abs(rel_e - pred) <= (1e-9 if prec == "f64" else 1e-2) * pred
         # the run's own transforms, for the measured transform error of each sample
         comp, dt = PRECISIONS[prec]
