@@ -464,14 +464,16 @@ __device__ __forceinline__ void round_body(RoundShared<T, NB2>& sh, T* __restric
     const bool nonfinite = flag_nf != 0;
     const bool rotate = !nonfinite && (mc > tol);
     // A sweep over the b*b cross pairs only (b steps of b disjoint rotations
-    // instead of 2b-1 steps) when both blocks are orthogonal inside, or when
-    // their largest inside cosine is below the largest cross cosine: a
-    // threshold strategy that leaves the smaller inside pairs to a later
-    // meeting of the block.  Convergence is still declared only when every
-    // cosine of a sweep is below tol.  On Gaussian and low-rank-plus-noise
-    // slices (r = 96..512) this removes 30-45% of the inner steps for at
-    // most two more sweeps.
-    const bool cross_only = !(mcw > tol) || mcw < mcx;
+    // instead of 2b-1 steps) when both blocks are orthogonal inside, or, in
+    // slices of at least 12 blocks, when their largest inside cosine is
+    // below the largest cross cosine: a threshold strategy that leaves the
+    // smaller inside pairs to a later meeting of the block.  Convergence is
+    // still declared only when every cosine of a sweep is below tol.  With
+    // many blocks a block meets enough others per sweep that this removes
+    // 40-45% of the inner steps at the same sweep count (Gaussian and
+    // low-rank-plus-noise slices, 13-16 blocks); with 5-8 blocks it costs
+    // one or two more sweeps, which outweighs the saving.
+    const bool cross_only = !(mcw > tol) || (nbe >= 12 && mcw < mcx);
     if (tid == 0) {
         if (nonfinite) atomicExch(&ctl_s->nonfinite, 1);
         else atomicMax(&ctl_s->maxcos_bits, (unsigned long long)__double_as_longlong(mc));
