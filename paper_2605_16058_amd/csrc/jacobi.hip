@@ -494,6 +494,10 @@ __device__ __forceinline__ void round_body(RoundShared<T, NB2>& sh, T* __restric
         atomicAdd(&pair_counts[3], by);
     }
     if (!rotate) return;  // uniform across the block
+    // FP64: the first vector tile of the update is in flight during the
+    // inner sweep (FP32 has no registers to spare there)
+    constexpr bool EARLY = sizeof(T) == 8;
+    if (EARLY && wave < (L + PT - 1) / PT) load_tile(ROWS, Ab, g.vs, g.es, L, vec_a != 0, wave * PT);
 
     // ---------------- phase 2: one cyclic Jacobi sweep on H (FP64 angles)
     // H is kept in seat order (pair k on seats (k, partner_seat(k)) at every
@@ -678,12 +682,17 @@ __device__ __forceinline__ void round_body(RoundShared<T, NB2>& sh, T* __restric
             for (int ta = 0; ta < NT; ++ta) qf[kq][ta] = Qs[C::q_idx(ta * 16 + lr, 4 * kq + lg)];
         }
     }
-    auto update = [&](auto rows_tag, T* base, int64_t vs, int64_t es, int64_t len, bool vec) {
+    // The W columns follow the vectors: the last vector tile of a wave
+    // already loads the wave's first W tile (where registers allow), so
+    // that its latency overlaps the MFMAs of the vectors.
+    const int64_t ntile_a = (L + PT - 1) / PT, ntile_w = (r + PT - 1) / PT;
+    auto update = [&](auto rows_tag, T* base, int64_t vs, int64_t es, int64_t len, bool vec,
+                      bool preloaded, bool next_w) {
         constexpr bool RW = decltype(rows_tag)::value;
         constexpr int PLD = RW ? PT + 1 : PT;                  // odd stride spreads transposed stores
         const int64_t ntile = (len + PT - 1) / PT;
         int64_t tile = wave;
-        if (tile < ntile) load_tile(RW, base, vs, es, len, vec, tile * PT);
+        if (tile < ntile && !preloaded) load_tile(RW, base, vs, es, len, vec, tile * PT);
         for (; tile < ntile; tile += 4) {
             // stage the tile: stg[c * PLD + t]
 #pragma unroll
@@ -704,6 +713,7 @@ __device__ __forceinline__ void round_body(RoundShared<T, NB2>& sh, T* __restric
             // the wave's own LDS stores before its reads (LDS is in order per wave)
             __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
             if (tile + 4 < ntile) load_tile(RW, base, vs, es, len, vec, (tile + 4) * PT);
+            else if (next_w && wave < ntile_w) load_tile(false, Wb, r, 1, r, vec_w != 0, wave * PT);
             AccT acc[NT];
 #pragma unroll
             for (int ta = 0; ta < NT; ++ta) acc[ta] = zero4<AccT>();
@@ -733,8 +743,9 @@ __device__ __forceinline__ void round_body(RoundShared<T, NB2>& sh, T* __restric
             }
         }
     };
-    update(std::integral_constant<bool, ROWS>(), Ab, g.vs, g.es, L, vec_a != 0);
-    update(std::integral_constant<bool, false>(), Wb, r, 1, r, vec_w != 0);
+    constexpr bool NEXTW = ROWS || sizeof(T) == 8;   // FP32 column families: no registers to spare
+    update(std::integral_constant<bool, ROWS>(), Ab, g.vs, g.es, L, vec_a != 0, EARLY, NEXTW);
+    update(std::integral_constant<bool, false>(), Wb, r, 1, r, vec_w != 0, NEXTW && wave < ntile_a, false);
 }
 
 // FP32 pairs of 64 vectors keep three workgroups per 160 KB compute unit.
