@@ -192,7 +192,8 @@ __global__ void jacobi_init(T* __restrict__ W, int64_t r, int64_t n, JacobiCtl* 
 // elements (enough for either phase's layout).  The pair Gram matrix H
 // lives in the same region afterwards as two packed symmetric FP64 buffers
 // (one per parity of the inner step); while the first is being written, the
-// partial Gram matrices of three waves sit right behind it.  Q is stored
+// partial sums of every Gram tile from the three waves that do not own it
+// sit right behind it.  Q is stored
 // transposed (row a =
 // column a of Q) with the 16-byte groups of row a XOR-swizzled by a, so that
 // row accesses are 16-byte vectors and column reads of 16 rows hit distinct
@@ -210,7 +211,7 @@ struct RoundCfg {
     static constexpr size_t hs_bytes = sizeof(double) * 2 * NH;
     static constexpr size_t r1 = (stg_bytes > hs_bytes) ? stg_bytes : hs_bytes;
     static constexpr size_t q_bytes = sizeof(T) * NB2 * NB2;
-    // partial Gram matrices of three waves, parked behind the first H buffer
+    // three partial sums per Gram tile, parked behind the first H buffer
     static constexpr int NTT = NT * (NT + 1) / 2;
     static constexpr size_t rp_off = (sizeof(double) * NH + 15) / 16 * 16;
     static constexpr size_t rp_end = rp_off + sizeof(T) * 3 * NTT * 256;
@@ -236,8 +237,8 @@ template <class T, int NB2>
 struct RoundShared {
     __align__(16) char smem[RoundCfg<T, NB2>::total];
     double2 rot_cs[2][NB2 / 2];   // (c, s) of each rotation, per parity of the inner step
-    double mc_cross, mc_within;   // convergence measure of the pair
-    int flag_nf;
+    double red_mx[4], red_mw[4];  // per-wave convergence measure: across / inside the blocks
+    int red_nf[4];                // per-wave: a NaN or Inf was met
 };
 
 template <class T, int NB2, bool ROWS>
@@ -252,7 +253,6 @@ __device__ __forceinline__ void round_body(RoundShared<T, NB2>& sh, T* __restric
     constexpr int NT = C::NT, NH = C::NH;
 
     char* smem = sh.smem;
-    int& flag_nf = sh.flag_nf;
 
     T* Ts = reinterpret_cast<T*>(smem);                           // [4][STG] per-wave staging
     double* H0 = reinterpret_cast<double*>(smem);                 // [2][NH] packed H (phase 2)
@@ -373,54 +373,54 @@ __device__ __forceinline__ void round_body(RoundShared<T, NB2>& sh, T* __restric
             __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
         }
     }
-    // Waves 1-3 park their partial sums in LDS in lane order (over the
-    // staging regions, hence the barrier first, and clear of the H buffer
-    // that wave 0 fills while it still reads them); wave 0 adds them to its own
-    // in wave order, so the result does not depend on timing, writes the
-    // packed FP64 H and forms the convergence measure from it: the largest
-    // |cos| = |h_ac| / (||a|| ||c||) over valid vector pairs, kept separately
-    // for pairs inside one block and pairs across the two blocks.  All its
-    // LDS reads are independent of each other, so they overlap.
-    T* const Rp = reinterpret_cast<T*>(smem + C::rp_off);         // [3][NTT][4][64]
+    // Tile q of the Gram matrix belongs to wave q % 4.  Every wave parks its
+    // partial sums of the tiles it does not own in LDS in lane order (over
+    // the staging regions, hence the barrier first, and clear of the H
+    // buffer the owners fill while others still read them); each owner adds
+    // the four partials of its tiles in wave order 0..3, so the result does
+    // not depend on timing, writes them into the packed FP64 H and, once
+    // every diagonal is there, forms the convergence measure of its tiles:
+    // the largest |cos| = |h_ac| / (||a|| ||c||) over valid vector pairs,
+    // kept separately for pairs inside one block and pairs across the two
+    // blocks.  The four per-wave maxima meet in LDS.
+    T* const Rp = reinterpret_cast<T*>(smem + C::rp_off);         // [NTT][3][4][64]
+    auto slot = [&](int q, int w) {                               // w != q % 4
+        const int o = q & 3;
+        const int k = w - (w > o ? 1 : 0);
+        return Rp + (q * 3 + (k < 2 ? k : 2)) * 256;
+    };
     __syncthreads();
-    if (wave > 0) {
-        T* const Rw = Rp + (wave - 1) * (NTT * 256);
 #pragma unroll
-        for (int q = 0; q < NTT; ++q) {
+    for (int q = 0; q < NTT; ++q) {
+        if ((q & 3) == wave) continue;
+        T* const Rw = slot(q, wave);
 #pragma unroll
-            for (int v = 0; v < 4; ++v) Rw[(q * 4 + v) * 64 + lane] = hacc[q][v];
-        }
+        for (int v = 0; v < 4; ++v) Rw[v * 64 + lane] = hacc[q][v];
     }
     __syncthreads();
-    if (wave == 0) {
-        int q0 = 0;
+    {
+        int q = 0;
 #pragma unroll
         for (int i = 0; i < NT; ++i) {
-            T pw[3][NT][4];
 #pragma unroll
-            for (int w = 0; w < 3; ++w) {
-#pragma unroll
-                for (int j = i; j < NT; ++j) {
-#pragma unroll
-                    for (int v = 0; v < 4; ++v) pw[w][j][v] = Rp[w * (NTT * 256) + ((q0 + j - i) * 4 + v) * 64 + lane];
-                }
-            }
-#pragma unroll
-            for (int j = i; j < NT; ++j) {
+            for (int j = i; j < NT; ++j, ++q) {
+                if ((q & 3) != wave) continue;
 #pragma unroll
                 for (int v = 0; v < 4; ++v) {
                     const int a = i * 16 + mfma_row<T>(lg, v), c = j * 16 + lr;
-                    double h = (double)hacc[q0 + j - i][v];
-                    h += (double)pw[0][j][v];
-                    h += (double)pw[1][j][v];
-                    h += (double)pw[2][j][v];
+                    double h = 0.0;
+#pragma unroll
+                    for (int w = 0; w < 4; ++w) {
+                        const double x = (w == wave) ? (double)hacc[q][v] : (double)slot(q, w)[v * 64 + lane];
+                        h = (w == 0) ? x : h + x;
+                    }
                     if (a <= c) H0[sym_idx(a, c)] = h;
                 }
             }
-            q0 += NT - i;
         }
-        // the wave's own LDS stores before its reads (LDS is in order per wave)
-        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+    }
+    __syncthreads();
+    {
         // 1 / ||vector a||, 0 for padding and zero vectors so they never
         // count; norms below 2^-500 are scaled by a power of two first
         auto rnorm = [&](int a) -> double {
@@ -429,23 +429,21 @@ __device__ __forceinline__ void round_body(RoundShared<T, NB2>& sh, T* __restric
             const double y = rsq_nr(tiny ? d * 0x1p1000 : d) * (tiny ? 0x1p500 : 1.0);
             return (gidx(a) < r && d > 0.0) ? y : 0.0;
         };
-        double rc[NT], mx = 0.0, mw = 0.0;
+        double mx = 0.0, mw = 0.0;
         bool nf = false;
-#pragma unroll
-        for (int j = 0; j < NT; ++j) rc[j] = rnorm(j * 16 + lr);
+        int q = 0;
 #pragma unroll
         for (int i = 0; i < NT; ++i) {
-            double ra[4];
 #pragma unroll
-            for (int v = 0; v < 4; ++v) ra[v] = rnorm(i * 16 + mfma_row<T>(lg, v));
-#pragma unroll
-            for (int j = i; j < NT; ++j) {
+            for (int j = i; j < NT; ++j, ++q) {
+                if ((q & 3) != wave) continue;
+                const double rc = rnorm(j * 16 + lr);
 #pragma unroll
                 for (int v = 0; v < 4; ++v) {
                     const int a = i * 16 + mfma_row<T>(lg, v), c = j * 16 + lr;
                     const double h = H0[sym_idx(a, c)];
                     nf = nf || (a <= c && !isfinite(h));
-                    const double cs = (a < c) ? fabs(h) * ra[v] * rc[j] : 0.0;
+                    const double cs = (a < c) ? fabs(h) * rnorm(a) * rc : 0.0;
                     if ((a < B) != (c < B)) mx = fmax(mx, cs);
                     else mw = fmax(mw, cs);
                 }
@@ -456,12 +454,13 @@ __device__ __forceinline__ void round_body(RoundShared<T, NB2>& sh, T* __restric
             mw = fmax(mw, __shfl_xor(mw, off));
         }
         const bool any_nf = __any(nf);
-        if (lane == 0) { sh.mc_cross = mx; sh.mc_within = mw; flag_nf = any_nf ? 1 : 0; }
+        if (lane == 0) { sh.red_mx[wave] = mx; sh.red_mw[wave] = mw; sh.red_nf[wave] = any_nf ? 1 : 0; }
     }
     __syncthreads();
-    const double mcx = sh.mc_cross, mcw = sh.mc_within;
+    const double mcx = fmax(fmax(sh.red_mx[0], sh.red_mx[1]), fmax(sh.red_mx[2], sh.red_mx[3]));
+    const double mcw = fmax(fmax(sh.red_mw[0], sh.red_mw[1]), fmax(sh.red_mw[2], sh.red_mw[3]));
     const double mc = fmax(mcx, mcw);
-    const bool nonfinite = flag_nf != 0;
+    const bool nonfinite = (sh.red_nf[0] | sh.red_nf[1] | sh.red_nf[2] | sh.red_nf[3]) != 0;
     const bool rotate = !nonfinite && (mc > tol);
     // A sweep over the b*b cross pairs only (b steps of b disjoint rotations
     // instead of 2b-1 steps) when both blocks are orthogonal inside, or, in
