@@ -227,8 +227,17 @@ def bench_climate(a, torch, lib):
         log(f"fp64 warmup {a.warmup}, steps {a.steps}")
         for _ in range(a.warmup):
             op64(Ad)
+        lib.tsvdm_stats_reset()
+        lib.tsvdm_stats_enable(1)
         res64, ms64 = timed(lambda: op64(Ad), a.steps, torch)
-        log(f"fp64: {ms64:.2f} ms/step")
+        lib.tsvdm_stats_enable(0)
+        st64 = read_stats(lib)
+        log(f"fp64: {ms64:.2f} ms/step; jacobi stats {st64}")
+        roof64 = jacobi_roofline(st64, PEAK["f64_TF"])
+        roof64["src_sha"] = sha
+        tr64 = load_traffic(f"jacobi_round_f64_{m}x{p}x{n}", sha)
+        if tr64 is not None:
+            roof64["traffic"] = tr64
         d = ops.tsvdm_error(res64.A_rec, res_mix.A_rec).double().cpu()
         nA = float(res64.err[1].cpu())
         out_f64 = {
@@ -239,6 +248,7 @@ def bench_climate(a, torch, lib):
             "fp64_sum_rho": int(res64.offsets[-1].item()),
             "fp64_svd_status": int(res64.svd_status.item()),
             "mixed_vs_fp64_rel_diff": math.sqrt(float(d[0]) / nA) if nA > 0 else 0.0,
+            "fp64_roofline": roof64,
         }
         del res64, op64
         torch.cuda.empty_cache()
