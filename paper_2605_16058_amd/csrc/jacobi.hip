@@ -329,9 +329,8 @@ __device__ __forceinline__ void round_body(RoundShared<T, NB2>& sh, T* __restric
     for (int q = 0; q < NTT; ++q) hacc[q] = zero4<AccT>();
     {
         const int64_t ntile = (L + PT - 1) / PT;
-        int64_t tile = wave;
-        if (tile < ntile) load_tile(ROWS, Ab, g.vs, g.es, L, vec_a != 0, tile * PT);
-        for (; tile < ntile; tile += 4) {
+        // stage a tile from registers into the wave's LDS region
+        auto stage = [&](T (&cur)[NA][VW]) {
 #pragma unroll
             for (int u = 0; u < NA; ++u) {
                 int c, tt;
@@ -339,24 +338,25 @@ __device__ __forceinline__ void round_body(RoundShared<T, NB2>& sh, T* __restric
                 if (ROWS) {
                     T* const dst = stg + tt * GPR + c;
                     if constexpr (sizeof(T) == 4)
-                        *reinterpret_cast<float4*>(dst) = make_float4(pre[u][0], pre[u][1], pre[u][2], pre[u][3]);
+                        *reinterpret_cast<float4*>(dst) = make_float4(cur[u][0], cur[u][1], cur[u][2], cur[u][3]);
                     else
-                        *reinterpret_cast<double2*>(dst) = make_double2(pre[u][0], pre[u][1]);
+                        *reinterpret_cast<double2*>(dst) = make_double2(cur[u][0], cur[u][1]);
                 } else {
                     // rows of PT + 2 floats are 8-byte aligned only
                     T* const dst = stg + c * GPC + tt;
                     if constexpr (sizeof(T) == 4) {
-                        *reinterpret_cast<float2*>(dst) = make_float2(pre[u][0], pre[u][1]);
-                        *reinterpret_cast<float2*>(dst + 2) = make_float2(pre[u][2], pre[u][3]);
+                        *reinterpret_cast<float2*>(dst) = make_float2(cur[u][0], cur[u][1]);
+                        *reinterpret_cast<float2*>(dst + 2) = make_float2(cur[u][2], cur[u][3]);
                     } else {
-                        dst[0] = pre[u][0];
-                        dst[1] = pre[u][1];
+                        dst[0] = cur[u][0];
+                        dst[1] = cur[u][1];
                     }
                 }
             }
             // the wave's own LDS stores before its reads (LDS is in order per wave)
             __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
-            if (tile + 4 < ntile) load_tile(ROWS, Ab, g.vs, g.es, L, vec_a != 0, (tile + 4) * PT);
+        };
+        auto gram_mfma = [&]() {
 #pragma unroll
             for (int kk = 0; kk < PT; kk += 4) {
                 T f[NT];
@@ -371,6 +371,56 @@ __device__ __forceinline__ void round_body(RoundShared<T, NB2>& sh, T* __restric
                 }
             }
             __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+        };
+        int64_t tile = wave;
+        // Interior tiles of a pair of whole, 16-byte aligned blocks run a
+        // branch-free pipeline with two tiles in flight per wave: exactly NA
+        // unchecked 16-byte loads per tile (the prefetch index is clamped to
+        // the last interior tile, whose extra loads hit L2), so that the wait
+        // for a tile counts only the loads issued after it.
+        const int64_t nint = ((int64_t)I * B + B <= r && (int64_t)J * B + B <= r && vec_a != 0) ? L / PT : 0;
+        if (tile < nint) {
+            auto fast = [&](T (&dst)[NA][VW], int64_t tl) {
+                const int64_t t0 = (tl < nint ? tl : nint - 1) * PT;
+#pragma unroll
+                for (int u = 0; u < NA; ++u) {
+                    int c, tt;
+                    origin(ROWS, u, c, tt);
+                    const int64_t gi = gidx(c), t = t0 + tt;
+                    const T* src = ROWS ? Ab + gi + t * g.es : Ab + gi * g.vs + t;
+                    if constexpr (sizeof(T) == 4) {
+                        const float4 x = *reinterpret_cast<const float4*>(src);
+                        dst[u][0] = x.x; dst[u][1] = x.y; dst[u][2] = x.z; dst[u][3] = x.w;
+                    } else {
+                        const double2 x = *reinterpret_cast<const double2*>(src);
+                        dst[u][0] = x.x; dst[u][1] = x.y;
+                    }
+                }
+            };
+            T pre2[NA][VW];
+            fast(pre, tile);
+            fast(pre2, tile + 4);
+            for (; tile + 4 < nint; tile += 8) {
+                stage(pre);
+                fast(pre, tile + 8);
+                gram_mfma();
+                stage(pre2);
+                fast(pre2, tile + 12);
+                gram_mfma();
+            }
+            if (tile < nint) {
+                stage(pre);
+                gram_mfma();
+                tile += 4;
+            }
+        }
+        // the rest (a partial last tile, or every tile of a pair with a
+        // partial block): checked loads, one tile ahead
+        if (tile < ntile) load_tile(ROWS, Ab, g.vs, g.es, L, vec_a != 0, tile * PT);
+        for (; tile < ntile; tile += 4) {
+            stage(pre);
+            if (tile + 4 < ntile) load_tile(ROWS, Ab, g.vs, g.es, L, vec_a != 0, (tile + 4) * PT);
+            gram_mfma();
         }
     }
     // Tile q of the Gram matrix belongs to wave q % 4.  Every wave parks its
