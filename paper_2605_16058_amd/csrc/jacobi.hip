@@ -241,7 +241,10 @@ struct RoundShared {
     int red_nf[4];                // per-wave: a NaN or Inf was met
 };
 
-template <class T, int NB2, bool ROWS>
+// INT: every pair of the slice is interior (r a multiple of b with an even
+// block count, 16-byte aligned vectors and W columns, L and r multiples of
+// the tile), so that the MFMA phases need no checked loads or stores.
+template <class T, int NB2, bool ROWS, bool INT = false>
 __device__ __forceinline__ void round_body(RoundShared<T, NB2>& sh, T* __restrict__ Ab,
                                            T* __restrict__ Wb, const SliceGeom& g, int nbe, int rnd,
                                            int k, JacobiCtl* __restrict__ ctl_s, double tol,
@@ -378,7 +381,7 @@ __device__ __forceinline__ void round_body(RoundShared<T, NB2>& sh, T* __restric
         // unchecked 16-byte loads per tile (the prefetch index is clamped to
         // the last interior tile, whose extra loads hit L2), so that the wait
         // for a tile counts only the loads issued after it.
-        const int64_t nint = ((int64_t)I * B + B <= r && (int64_t)J * B + B <= r && vec_a != 0) ? L / PT : 0;
+        const int64_t nint = (INT || ((int64_t)I * B + B <= r && (int64_t)J * B + B <= r && vec_a != 0)) ? L / PT : 0;
         if (tile < nint) {
             auto fast = [&](T (&dst)[NA][VW], int64_t tl) {
                 const int64_t t0 = (tl < nint ? tl : nint - 1) * PT;
@@ -416,11 +419,13 @@ __device__ __forceinline__ void round_body(RoundShared<T, NB2>& sh, T* __restric
         }
         // the rest (a partial last tile, or every tile of a pair with a
         // partial block): checked loads, one tile ahead
-        if (tile < ntile) load_tile(ROWS, Ab, g.vs, g.es, L, vec_a != 0, tile * PT);
-        for (; tile < ntile; tile += 4) {
-            stage(pre);
-            if (tile + 4 < ntile) load_tile(ROWS, Ab, g.vs, g.es, L, vec_a != 0, (tile + 4) * PT);
-            gram_mfma();
+        if constexpr (!INT) {
+            if (tile < ntile) load_tile(ROWS, Ab, g.vs, g.es, L, vec_a != 0, tile * PT);
+            for (; tile < ntile; tile += 4) {
+                stage(pre);
+                if (tile + 4 < ntile) load_tile(ROWS, Ab, g.vs, g.es, L, vec_a != 0, (tile + 4) * PT);
+                gram_mfma();
+            }
         }
     }
     // Tile q of the Gram matrix belongs to wave q % 4.  Every wave parks its
@@ -734,13 +739,81 @@ __device__ __forceinline__ void round_body(RoundShared<T, NB2>& sh, T* __restric
     // The W columns follow the vectors: the last vector tile of a wave
     // already loads the wave's first W tile (where registers allow), so
     // that its latency overlaps the MFMAs of the vectors.
-    const int64_t ntile_a = (L + PT - 1) / PT, ntile_w = (r + PT - 1) / PT;
+    const int64_t ntile_w = (r + PT - 1) / PT;
+    // Returns whether the wave's first W tile is already in registers.
     auto update = [&](auto rows_tag, T* base, int64_t vs, int64_t es, int64_t len, bool vec,
-                      bool preloaded, bool next_w) {
+                      bool preloaded, bool next_w) -> bool {
         constexpr bool RW = decltype(rows_tag)::value;
         constexpr int PLD = RW ? PT + 1 : PT;                  // odd stride spreads transposed stores
         const int64_t ntile = (len + PT - 1) / PT;
         int64_t tile = wave;
+        const bool any = tile < ntile;
+        if constexpr (INT) {
+            // Interior slices: a branch-free loop with exactly NA unchecked
+            // 16-byte loads per iteration (the next tile, at the end an
+            // unused reload of the current one) and unchecked stores.  (The
+            // W tile prefetch of the checked loop does not fit the registers
+            // here.)
+            auto fast = [&](bool rw, const T* b, int64_t vs_, int64_t es_, int64_t t0) {
+#pragma unroll
+                for (int u = 0; u < NA; ++u) {
+                    int c, tt;
+                    origin(rw, u, c, tt);
+                    const int64_t gi = gidx(c), t = t0 + tt;
+                    const T* src = rw ? b + gi + t * es_ : b + gi * vs_ + t;
+                    if constexpr (sizeof(T) == 4) {
+                        const float4 x = *reinterpret_cast<const float4*>(src);
+                        pre[u][0] = x.x; pre[u][1] = x.y; pre[u][2] = x.z; pre[u][3] = x.w;
+                    } else {
+                        const double2 x = *reinterpret_cast<const double2*>(src);
+                        pre[u][0] = x.x; pre[u][1] = x.y;
+                    }
+                }
+            };
+            if (any && !preloaded) fast(RW, base, vs, es, tile * PT);
+            for (; tile < ntile; tile += 4) {
+#pragma unroll
+                for (int u = 0; u < NA; ++u) {
+                    int c, tt;
+                    origin(RW, u, c, tt);
+                    if (!RW) {
+                        T* const dst = stg + c * PLD + tt;
+                        if constexpr (sizeof(T) == 4)
+                            *reinterpret_cast<float4*>(dst) = make_float4(pre[u][0], pre[u][1], pre[u][2], pre[u][3]);
+                        else
+                            *reinterpret_cast<double2*>(dst) = make_double2(pre[u][0], pre[u][1]);
+                    } else {
+#pragma unroll
+                        for (int q = 0; q < VW; ++q) stg[(c + q) * PLD + tt] = pre[u][q];
+                    }
+                }
+                __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+                fast(RW, base, vs, es, (tile + 4 < ntile ? tile + 4 : tile) * PT);
+                AccT acc[NT];
+#pragma unroll
+                for (int ta = 0; ta < NT; ++ta) acc[ta] = zero4<AccT>();
+#pragma unroll
+                for (int kk = 0; kk < NB2; kk += 4) {
+                    const T b = stg[(kk + lg) * PLD + lr];
+#pragma unroll
+                    for (int ta = 0; ta < NT; ++ta) {
+                        const T q = QREG ? qf[QREG ? kk / 4 : 0][ta] : Qs[C::q_idx(ta * 16 + lr, kk + lg)];
+                        acc[ta] = RW ? mfma(b, q, acc[ta]) : mfma(q, b, acc[ta]);
+                    }
+                }
+                __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+                const int64_t t0 = tile * PT;
+#pragma unroll
+                for (int ta = 0; ta < NT; ++ta) {
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) {
+                        if (!RW) base[gidx(ta * 16 + mfma_row<T>(lg, v)) * vs + t0 + lr] = acc[ta][v];
+                        else base[gidx(ta * 16 + lr) + (t0 + mfma_row<T>(lg, v)) * es] = acc[ta][v];
+                    }
+                }
+            }
+            return false;
+        }
         if (tile < ntile && !preloaded) load_tile(RW, base, vs, es, len, vec, tile * PT);
         for (; tile < ntile; tile += 4) {
             // stage the tile: stg[c * PLD + t]
@@ -791,10 +864,11 @@ __device__ __forceinline__ void round_body(RoundShared<T, NB2>& sh, T* __restric
                 }
             }
         }
+        return next_w && any;
     };
     constexpr bool NEXTW = ROWS || sizeof(T) == 8;   // FP32 column families: no registers to spare
-    update(std::integral_constant<bool, ROWS>(), Ab, g.vs, g.es, L, vec_a != 0, EARLY, NEXTW);
-    update(std::integral_constant<bool, false>(), Wb, r, 1, r, vec_w != 0, NEXTW && wave < ntile_a, false);
+    const bool w_pre = update(std::integral_constant<bool, ROWS>(), Ab, g.vs, g.es, L, vec_a != 0, EARLY, NEXTW);
+    update(std::integral_constant<bool, false>(), Wb, r, 1, r, vec_w != 0, w_pre, false);
 }
 
 // FP32 pairs of 64 vectors keep three workgroups per 160 KB compute unit.
@@ -803,7 +877,7 @@ static_assert(sizeof(RoundShared<float, 64>) <= 160 * 1024 / 3, "LDS budget of j
 static_assert(sizeof(RoundShared<double, 64>) <= 160 * 1024 / 2, "LDS budget of jacobi_round<double, 64>");
 
 // One round for every (slice, pair) of a tensor of identical slices.
-template <class T, int NB2, bool ROWS>
+template <class T, int NB2, bool ROWS, bool INT>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(RoundCfg<T, NB2>::WAVES)))
 void jacobi_round(T* __restrict__ A, T* __restrict__ W, SliceGeom g,
                                                     int nbe, int rnd, JacobiCtl* __restrict__ ctl,
@@ -814,7 +888,7 @@ void jacobi_round(T* __restrict__ A, T* __restrict__ W, SliceGeom g,
     const int64_t s = blockIdx.x / npairs;
     const int k = blockIdx.x % npairs;
     if (ctl[s].done) return;
-    round_body<T, NB2, ROWS>(sh, A + s * g.m * g.p, W + s * g.r * g.r, g, nbe, rnd, k, ctl + s, tol,
+    round_body<T, NB2, ROWS, INT>(sh, A + s * g.m * g.p, W + s * g.r * g.r, g, nbe, rnd, k, ctl + s, tol,
                              vec_a, vec_w, pair_counts);
 }
 
@@ -1015,6 +1089,9 @@ int jacobi_impl(T* A, int64_t m, int64_t p, int64_t n, T* W, double* s2, int32_t
     const int vec_a = (g.m % VW == 0) ? 1 : 0;
     const int vec_w = (g.r % VW == 0) ? 1 : 0;
     TSVDM_REQUIRE(blocks < ((int64_t)1 << 31), TSVDM_E_SHAPE, "too many slice pairs for one launch");
+    // every pair interior: whole blocks, an even block count (no padding
+    // block), 16-byte aligned accesses, L and r multiples of the tile
+    const bool interior = g.r % B == 0 && nb % 2 == 0 && vec_a && vec_w && g.L % 16 == 0 && g.r % 16 == 0;
     int64_t launches = 0;
     for (int sweep = 0; sweep < o.max_sweeps; ++sweep) {
         if (stats) {
@@ -1026,11 +1103,17 @@ int jacobi_impl(T* A, int64_t m, int64_t p, int64_t n, T* W, double* s2, int32_t
             TSVDM_HIP_CHECK(hipEventRecord(e0, st));
         }
         for (int rnd = 0; rnd < nbe - 1; ++rnd) {
-            if (g.rows)
-                jacobi_round<T, NB2, true><<<(unsigned)blocks, 256, 0, st>>>(
+            if (g.rows && interior)
+                jacobi_round<T, NB2, true, true><<<(unsigned)blocks, 256, 0, st>>>(
+                    A, W, g, nbe, rnd, ctl, o.tol, vec_a, vec_w, pair_counts);
+            else if (g.rows)
+                jacobi_round<T, NB2, true, false><<<(unsigned)blocks, 256, 0, st>>>(
+                    A, W, g, nbe, rnd, ctl, o.tol, vec_a, vec_w, pair_counts);
+            else if (interior)
+                jacobi_round<T, NB2, false, true><<<(unsigned)blocks, 256, 0, st>>>(
                     A, W, g, nbe, rnd, ctl, o.tol, vec_a, vec_w, pair_counts);
             else
-                jacobi_round<T, NB2, false><<<(unsigned)blocks, 256, 0, st>>>(
+                jacobi_round<T, NB2, false, false><<<(unsigned)blocks, 256, 0, st>>>(
                     A, W, g, nbe, rnd, ctl, o.tol, vec_a, vec_w, pair_counts);
             TSVDM_LAUNCH_CHECK();
             ++launches;
