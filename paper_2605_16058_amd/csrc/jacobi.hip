@@ -770,8 +770,7 @@ __device__ __forceinline__ void round_body(RoundShared<T, NB2>& sh, T* __restric
                     }
                 }
             };
-            if (any && !preloaded) fast(RW, base, vs, es, tile * PT);
-            for (; tile < ntile; tile += 4) {
+            auto tile_step = [&](int64_t tile) {
 #pragma unroll
                 for (int u = 0; u < NA; ++u) {
                     int c, tt;
@@ -789,6 +788,8 @@ __device__ __forceinline__ void round_body(RoundShared<T, NB2>& sh, T* __restric
                 }
                 __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
                 fast(RW, base, vs, es, (tile + 4 < ntile ? tile + 4 : tile) * PT);
+                // keep the loads of the next tile ahead of this tile's MFMAs
+                __builtin_amdgcn_sched_barrier(0);
                 AccT acc[NT];
 #pragma unroll
                 for (int ta = 0; ta < NT; ++ta) acc[ta] = zero4<AccT>();
@@ -811,6 +812,14 @@ __device__ __forceinline__ void round_body(RoundShared<T, NB2>& sh, T* __restric
                         else base[gidx(ta * 16 + lr) + (t0 + mfma_row<T>(lg, v)) * es] = acc[ta][v];
                     }
                 }
+            };
+            // the first tile peeled off, so that the loop is entered only
+            // after a tile's loads and stores, like every later iteration:
+            // the wait at its top then counts the loads alone
+            if (any) {
+                if (!preloaded) fast(RW, base, vs, es, tile * PT);
+                tile_step(tile);
+                for (tile += 4; tile < ntile; tile += 4) tile_step(tile);
             }
             return false;
         }
