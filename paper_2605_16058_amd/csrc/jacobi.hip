@@ -406,9 +406,11 @@ __device__ __forceinline__ void round_body(RoundShared<T, NB2>& sh, T* __restric
             for (; tile + 4 < nint; tile += 8) {
                 stage(pre);
                 fast(pre, tile + 8);
+                __builtin_amdgcn_sched_barrier(0);   // loads ahead of the MFMAs
                 gram_mfma();
                 stage(pre2);
                 fast(pre2, tile + 12);
+                __builtin_amdgcn_sched_barrier(0);
                 gram_mfma();
             }
             if (tile < nint) {
@@ -845,6 +847,7 @@ __device__ __forceinline__ void round_body(RoundShared<T, NB2>& sh, T* __restric
             __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
             if (tile + 4 < ntile) load_tile(RW, base, vs, es, len, vec, (tile + 4) * PT);
             else if (next_w && wave < ntile_w) load_tile(false, Wb, r, 1, r, vec_w != 0, wave * PT);
+            __builtin_amdgcn_sched_barrier(0);   // loads ahead of the MFMAs
             AccT acc[NT];
 #pragma unroll
             for (int ta = 0; ta < NT; ++ta) acc[ta] = zero4<AccT>();
