@@ -669,7 +669,7 @@ __device__ __forceinline__ void round_body(RoundShared<T, NB2>& sh, T* __restric
             sh.rot_cs[cb ^ 1][ka] = rot_make<T>(c, sn);
         }
         // ---- H <- J^T H J on this thread's 2x2 blocks, written on the next
-        // seats; all of the thread's blocks (three) loaded before any is
+        // seats; all of the thread's blocks (up to three) loaded before any is
         // rotated, so that the step waits for LDS once
         constexpr int HG = 3;
 #pragma unroll
