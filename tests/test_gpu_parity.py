@@ -106,10 +106,12 @@ def _sorted_sigma(s2_row):
 
 # (300, 200) and (400, 720) / (720, 400) have at least 12 blocks of 16 and 32
 # vectors, where a pair may take the cross-only inner sweep while its inside
-# cosines are still above tol
+# cosines are still above tol; (256, 384) / (384, 256) have an even number of
+# whole blocks of both widths and tile-multiple lengths, so they run the
+# interior kernel instance (unchecked loads and stores)
 @pytest.mark.parametrize("shape", [(64, 48, 4), (48, 64, 4), (100, 37, 3), (37, 100, 3),
                                    (300, 200, 2), (5, 1, 3), (1, 6, 2), (129, 129, 2),
-                                   (400, 720, 2), (720, 400, 1)])
+                                   (400, 720, 2), (720, 400, 1), (256, 384, 2), (384, 256, 2)])
 @pytest.mark.parametrize("dtype,block", [(torch.float64, 16), (torch.float64, 32),
                                          (torch.float32, 16), (torch.float32, 32)])
 def test_slice_svd_matches_oracle(ops, shape, dtype, block):
@@ -134,13 +136,15 @@ def test_slice_svd_matches_oracle(ops, shape, dtype, block):
         Wi = Wn[i].T  # column-major r x r
         assert np.max(np.abs(Wi.T @ Wi - np.eye(r))) <= (1e-13 if fp64 else 1e-5) * max(1, r) ** 0.5
         Bi = Bn[:, :, i]
-        # factorisation: rows case A = W B, columns case A = B W^T.  FP32:
-        # every pair update rounds each vector element once after a sum of
-        # 2b terms; at most 16 sweeps of nb - 1 updates, accumulated as a
-        # random walk, with a factor 2 of margin
+        # factorisation: rows case A = W B, columns case A = B W^T.  A pair
+        # update applies Q, the product of up to 2b - 1 rotation steps
+        # rounded once each, to sums of 2b terms: an error of up to 2b unit
+        # roundoffs per update; at most 16 sweeps of nb - 1 updates,
+        # accumulated as a random walk, with a factor 2 of margin
         rec = Wi @ Bi if m < p else Bi @ Wi.T
         nb = -(-r // block)
-        rec_bound = 1e-13 if fp64 else 2 * 2.0 ** -24 * np.sqrt(2 * block * 16 * max(nb, 1))
+        u = 2.0 ** -53 if fp64 else 2.0 ** -24
+        rec_bound = 2 * u * (2 * block) * np.sqrt(16 * max(nb, 1))
         assert rel(rec, A[:, :, i]) <= rec_bound
         # squared norms are those of the final vectors
         vec_norm2 = np.sum(Bi * Bi, axis=1 if m < p else 0)
