@@ -976,29 +976,42 @@ __global__ void jacobi_init_batch(const BatchSlice* __restrict__ sl, JacobiCtl* 
 }
 
 // squared norms of every slice's final vectors, one workgroup per slice
+// Sum of squares of x[0], x[s], ..., x[(n - 1) s] in FP64, accumulated in
+// that order; eight loads are in flight at a time (a loop with one load per
+// iteration waits for every load).
+template <class T>
+__device__ __forceinline__ double sumsq_strided(const T* __restrict__ x, int64_t s, int64_t n) {
+    double acc = 0.0;
+    int64_t t = 0;
+    for (; t + 8 <= n; t += 8) {
+        T v[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) v[q] = x[(t + q) * s];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            const double e = (double)v[q];
+            acc = fma(e, e, acc);
+        }
+    }
+    for (; t < n; ++t) {
+        const double e = (double)x[t * s];
+        acc = fma(e, e, acc);
+    }
+    return acc;
+}
+
 template <class T>
 __global__ __launch_bounds__(256) void jacobi_norms_batch(const BatchSlice* __restrict__ sl) {
     const BatchSlice d = sl[blockIdx.x];
     const T* A = static_cast<const T*>(d.A);
     const SliceGeom g = d.g;
     if (g.rows) {
-        for (int64_t j = threadIdx.x; j < g.r; j += blockDim.x) {
-            double acc = 0.0;
-            for (int64_t t = 0; t < g.L; ++t) {
-                const double v = (double)A[j + t * g.es];
-                acc = fma(v, v, acc);
-            }
-            d.s2[j] = acc;
-        }
+        for (int64_t j = threadIdx.x; j < g.r; j += blockDim.x) d.s2[j] = sumsq_strided(A + j, g.es, g.L);
     } else {
         const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
         for (int64_t j = wave; j < g.r; j += 4) {
             const T* x = A + j * g.vs;
-            double acc = 0.0;
-            for (int64_t t = lane; t < g.L; t += 64) {
-                const double e = (double)x[t];
-                acc = fma(e, e, acc);
-            }
+            double acc = lane < g.L ? sumsq_strided(x + lane, 64, (g.L - lane + 63) / 64) : 0.0;
             for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
             if (lane == 0) d.s2[j] = acc;
         }
@@ -1029,12 +1042,7 @@ __global__ __launch_bounds__(256) void jacobi_norms_rows(const T* __restrict__ A
     const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= g.r || (run && !run[s])) return;
     const T* Ab = A + s * g.m * g.p;
-    double acc = 0.0;
-    for (int64_t t = 0; t < g.L; ++t) {
-        double v = (double)Ab[j + t * g.es];
-        acc = fma(v, v, acc);
-    }
-    s2[s * g.r + j] = acc;
+    s2[s * g.r + j] = sumsq_strided(Ab + j, g.es, g.L);
 }
 
 template <class T>
@@ -1049,11 +1057,7 @@ __global__ __launch_bounds__(256) void jacobi_norms_cols(const T* __restrict__ A
     const int64_t s = v / g.r, j = v % g.r;
     if (run && !run[s]) return;
     const T* x = A + s * g.m * g.p + j * g.vs;
-    double acc = 0.0;
-    for (int64_t t = lane; t < g.L; t += 64) {
-        double e = (double)x[t];
-        acc = fma(e, e, acc);
-    }
+    double acc = lane < g.L ? sumsq_strided(x + lane, 64, (g.L - lane + 63) / 64) : 0.0;
     for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
     if (lane == 0) s2[s * g.r + j] = acc;
 }
