@@ -118,19 +118,24 @@ __global__ __launch_bounds__(256) void pack_copy(const T* __restrict__ A, const 
 
 // C(:,:,s) = U_pk_s (m x rho_s) * G_pk_s (rho_s x p), computed as
 // C^T = G^T U^T so that MFMA output lanes run along the rows of C.
+// K chunk of the low-rank product staged in LDS.
+constexpr int LR_KC = 32;
 template <class T>
 struct LowrankShared {
-    T Us[16][64 + 1];  // [c][a]
-    T Gs[64][16 + 1];  // [b][c]
+    T Us[LR_KC][64 + 1];  // [c][a]
+    T Gs[64][LR_KC + 1];  // [b][c]
 };
 
 // Output tile (ta, tb) of one slice: Cb (m x p) = Ub (m x kr) * Gb (kr x p).
+// The next K chunk is loaded into registers while the MFMAs of the current
+// one run; the sums run over k in increasing order, four terms per MFMA.
 template <class T>
 __device__ __forceinline__ void lowrank_tile(LowrankShared<T>& sh, const T* __restrict__ Ub,
                                              const T* __restrict__ Gb, int64_t m, int64_t p,
                                              int64_t kr, T* __restrict__ Cb, int ta, int tb) {
     typedef typename Acc<T>::type AccT;
-    constexpr int KC = 16;
+    constexpr int KC = LR_KC;
+    constexpr int PER = KC * 64 / 256;  // elements of each operand per thread and chunk
     auto& Us = sh.Us;
     auto& Gs = sh.Gs;
     const int64_t a0 = (int64_t)ta * 64, b0 = (int64_t)tb * 64;
@@ -139,20 +144,27 @@ __device__ __forceinline__ void lowrank_tile(LowrankShared<T>& sh, const T* __re
     AccT acc[4];
 #pragma unroll
     for (int t = 0; t < 4; ++t) acc[t] = zero4<AccT>();
-    for (int64_t c0 = 0; c0 < kr; c0 += KC) {
-        for (int e = tid; e < KC * 64; e += 256) {
+    T ur[PER], gr[PER];
+    auto load = [&](int64_t c0) {
+#pragma unroll
+        for (int i = 0; i < PER; ++i) {
+            const int e = tid + 256 * i;
             const int a = e & 63, c = e >> 6;
-            T v = 0;
-            if (a0 + a < m && c0 + c < kr) v = Ub[(a0 + a) + (c0 + c) * m];
-            Us[c][a] = v;
+            ur[i] = (a0 + a < m && c0 + c < kr) ? Ub[(a0 + a) + (c0 + c) * m] : T(0);
+            const int cg = e % KC, b = e / KC;
+            gr[i] = (b0 + b < p && c0 + cg < kr) ? Gb[(c0 + cg) + (b0 + b) * kr] : T(0);
         }
-        for (int e = tid; e < KC * 64; e += 256) {
-            const int c = e % KC, b = e / KC;
-            T v = 0;
-            if (b0 + b < p && c0 + c < kr) v = Gb[(c0 + c) + (b0 + b) * kr];
-            Gs[b][c] = v;
+    };
+    if (kr > 0) load(0);
+    for (int64_t c0 = 0; c0 < kr; c0 += KC) {
+#pragma unroll
+        for (int i = 0; i < PER; ++i) {
+            const int e = tid + 256 * i;
+            Us[e >> 6][e & 63] = ur[i];
+            Gs[e / KC][e % KC] = gr[i];
         }
         __syncthreads();
+        if (c0 + KC < kr) load(c0 + KC);
 #pragma unroll
         for (int kk = 0; kk < KC; kk += 4) {
             T av = Gs[wave * 16 + lr][kk + lg];  // A = G^T : row b, k = c
