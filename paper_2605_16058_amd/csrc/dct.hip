@@ -77,19 +77,102 @@ __device__ __forceinline__ void dft_regs(Cx<CT> (&x)[N], const Cx<CT> (&w)[N / 2
     }
 }
 
-template <class IT, class OT, class CT, int L, bool INV>
-__global__ __launch_bounds__((DctCfg<CT, L>::THREADS)) void dct_kernel(const IT* __restrict__ X,
-                                                                     OT* __restrict__ Y, int64_t R,
-                                                                     int64_t b0) {
+// The stages of one workgroup's tube block.  Thread (tube, sub) loads and
+// transforms the step-1 inputs q = n2 j1 + sub (sub < n2) of its tube and
+// the step-4 outputs q = sub + n1 k2.
+template <class IT, class CT, int L, bool INV>
+struct DctStages {
     typedef DctCfg<CT, L> C;
-    constexpr int n = C::n, n1 = C::n1, n2 = C::n2, TB = C::TB;
-    __shared__ Cx<CT> buf[TB * (n + 1)];
-    __shared__ Cx<CT> tw[n];     // exp(-2 pi i q / n)
-    __shared__ Cx<CT> pw[n];     // forward: s_q exp(-i pi q / (2n)); inverse: exp(i pi q / (2n))
-    __shared__ CT isc[n];        // inverse: 1 / s_q
+    static constexpr int n = C::n, n1 = C::n1, n2 = C::n2;
+    // raw inputs per thread: x at the reordered positions (forward), or x_q
+    // and x_{n-q} (inverse; for q = 0 the second is x_0 and is not used)
+    static constexpr int NIN = INV ? 2 * n1 : n1;
 
-    const int tid = threadIdx.x;
-    for (int q = tid; q < n; q += C::THREADS) {
+    __device__ static __forceinline__ void load(IT (&raw)[NIN], const IT* __restrict__ in, int64_t R, int sub) {
+#pragma unroll
+        for (int j1 = 0; j1 < n1; ++j1) {
+            const int q = n2 * j1 + sub;
+            if (!INV) {
+                const int src = (q < n / 2) ? 2 * q : 2 * (n - 1 - q) + 1;
+                raw[j1] = in[(int64_t)src * R];
+            } else {
+                raw[j1] = in[(int64_t)q * R];
+                raw[n1 + j1] = in[(int64_t)((n - q) & (n - 1)) * R];
+            }
+        }
+    }
+
+    // step 1a: the inputs v[n2 j1 + sub] of the thread's length-n1 DFT as
+    // complex values, placed in bit-reversed order
+    __device__ static __forceinline__ void prep(const IT (&raw)[NIN], int sub, const Cx<CT>* pw,
+                                                const CT* isc, Cx<CT> (&x1)[n1]) {
+#pragma unroll
+        for (int j1 = 0; j1 < n1; ++j1) {
+            const int q = n2 * j1 + sub;
+            Cx<CT> v;
+            if (!INV) {
+                v = {(CT)raw[j1], CT(0)};
+            } else {
+                // conj(V_q) with V_q = pw_q (t_q - i t_{n-q})
+                const CT tq = (CT)raw[j1] * isc[q];
+                const CT tr = (q == 0) ? CT(0) : (CT)raw[n1 + j1] * isc[n - q];
+                const Cx<CT> p = pw[q];
+                const Cx<CT> V = {p.re * tq + p.im * tr, p.im * tq - p.re * tr};
+                v = {V.re, -V.im};
+            }
+            x1[bitrev(j1, ilog2(n1))] = v;
+        }
+    }
+
+    // step 1b: the DFT over j1 in registers, the twiddles, and the write
+    // into the LDS row
+    __device__ static __forceinline__ void first(Cx<CT> (&x1)[n1], int sub, const Cx<CT>* tw, Cx<CT>* row) {
+        Cx<CT> w1[n1 / 2 > 0 ? n1 / 2 : 1];
+#pragma unroll
+        for (int m = 0; m < n1 / 2; ++m) w1[m] = tw[m * n2];
+        dft_regs<CT, n1>(x1, w1);
+#pragma unroll
+        for (int k1 = 0; k1 < n1; ++k1) {
+            const Cx<CT> t = (sub * k1 == 0) ? x1[k1] : cmul(x1[k1], tw[(sub * k1) % n]);
+            row[sub * n1 + k1] = t;
+        }
+    }
+
+    // step 4 (all threads): DFT over j2 of the transposed row; output
+    // q = sub + n1 k2, then the DCT post-twiddle (forward) or the
+    // reordering (inverse) and the stores
+    template <class OT>
+    __device__ static __forceinline__ void second(int sub, const Cx<CT>* tw, const Cx<CT>* pw,
+                                                  const Cx<CT>* row, bool valid, OT* __restrict__ out,
+                                                  int64_t R) {
+        Cx<CT> w2[n2 / 2 > 0 ? n2 / 2 : 1];
+#pragma unroll
+        for (int m = 0; m < n2 / 2; ++m) w2[m] = tw[m * n1];
+        Cx<CT> x4[n2];
+#pragma unroll
+        for (int j2 = 0; j2 < n2; ++j2) x4[bitrev(j2, ilog2(n2))] = row[j2 * n1 + sub];
+        dft_regs<CT, n2>(x4, w2);
+        if (!valid) return;
+#pragma unroll
+        for (int k2 = 0; k2 < n2; ++k2) {
+            const int q = sub + n1 * k2;
+            if (!INV) {
+                const Cx<CT> p = pw[q];
+                out[(int64_t)q * R] = (OT)(p.re * x4[k2].re - p.im * x4[k2].im);
+            } else {
+                // v_q = Re(conj(DFT(conj V))_q) / n = Re(DFT(conj V)_q) / n
+                const int dst = (q < n / 2) ? 2 * q : 2 * (n - 1 - q) + 1;
+                out[(int64_t)dst * R] = (OT)(x4[k2].re * (CT(1) / CT(n)));
+            }
+        }
+    }
+};
+
+// Twiddle tables of one workgroup, FP64 sincospi rounded to CT.
+template <class CT, int L, bool INV>
+__device__ __forceinline__ void dct_tables(Cx<CT>* tw, Cx<CT>* pw, CT* isc) {
+    constexpr int n = 1 << L;
+    for (int q = threadIdx.x; q < n; q += (int)blockDim.x) {
         double s, c;
         sincospi(-2.0 * q / n, &s, &c);
         tw[q] = {(CT)c, (CT)s};
@@ -103,71 +186,43 @@ __global__ __launch_bounds__((DctCfg<CT, L>::THREADS)) void dct_kernel(const IT*
             isc[q] = (CT)(1.0 / sq);
         }
     }
+}
+
+// One tube block (TB tubes from row blockIdx.x TB) per workgroup, tubes
+// past R masked.  A thread issues all of its loads together before any
+// arithmetic (one branch on the tube's validity, none per element), so
+// that their latencies overlap.
+template <class IT, class OT, class CT, int L, bool INV>
+__global__ __launch_bounds__((DctCfg<CT, L>::THREADS)) void dct_kernel(const IT* __restrict__ X,
+                                                                     OT* __restrict__ Y, int64_t R,
+                                                                     int64_t b0) {
+    typedef DctCfg<CT, L> C;
+    typedef DctStages<IT, CT, L, INV> S;
+    constexpr int n = C::n, n2 = C::n2, TB = C::TB;
+    __shared__ Cx<CT> buf[TB * (n + 1)];
+    __shared__ Cx<CT> tw[n];     // exp(-2 pi i q / n)
+    __shared__ Cx<CT> pw[n];     // forward: s_q exp(-i pi q / (2n)); inverse: exp(i pi q / (2n))
+    __shared__ CT isc[n];        // inverse: 1 / s_q
+    dct_tables<CT, L, INV>(tw, pw, isc);
     __syncthreads();
 
+    const int tid = threadIdx.x;
     const int tube = tid % TB, sub = tid / TB;
     const int64_t a = (int64_t)blockIdx.x * TB + tube;
     const bool valid = a < R;
     const int64_t blk = b0 + blockIdx.y;
-    const IT* __restrict__ in = X + blk * R * n + a;
-    OT* __restrict__ out = Y + blk * R * n + a;
     Cx<CT>* const row = buf + tube * (n + 1);
-
-    // ---- step 1 (threads sub < n2): DFT over j1 of v[n2 j1 + sub], in
-    // registers, inputs placed in bit-reversed order; then the twiddles
     if (sub < n2) {
-        Cx<CT> w1[n1 / 2 > 0 ? n1 / 2 : 1];
+        IT raw[S::NIN];
 #pragma unroll
-        for (int m = 0; m < n1 / 2; ++m) w1[m] = tw[m * n2];
-        Cx<CT> x1[n1];
-#pragma unroll
-        for (int j1 = 0; j1 < n1; ++j1) {
-            const int q = n2 * j1 + sub;
-            Cx<CT> v;
-            if (!INV) {
-                const int src = (q < n / 2) ? 2 * q : 2 * (n - 1 - q) + 1;
-                v = {valid ? (CT)in[(int64_t)src * R] : CT(0), CT(0)};
-            } else {
-                // conj(V_q) with V_q = pw_q (t_q - i t_{n-q})
-                const CT tq = valid ? (CT)in[(int64_t)q * R] * isc[q] : CT(0);
-                const CT tr = (q == 0 || !valid) ? CT(0) : (CT)in[(int64_t)(n - q) * R] * isc[n - q];
-                const Cx<CT> p = pw[q];
-                const Cx<CT> V = {p.re * tq + p.im * tr, p.im * tq - p.re * tr};
-                v = {V.re, -V.im};
-            }
-            x1[bitrev(j1, ilog2(n1))] = v;
-        }
-        dft_regs<CT, n1>(x1, w1);
-#pragma unroll
-        for (int k1 = 0; k1 < n1; ++k1) {
-            const Cx<CT> t = (sub * k1 == 0) ? x1[k1] : cmul(x1[k1], tw[(sub * k1) % n]);
-            row[sub * n1 + k1] = t;
-        }
+        for (int i = 0; i < S::NIN; ++i) raw[i] = IT(0);
+        if (valid) S::load(raw, X + blk * R * n + a, R, sub);
+        Cx<CT> x1[C::n1];
+        S::prep(raw, sub, pw, isc, x1);
+        S::first(x1, sub, tw, row);
     }
     __syncthreads();
-
-    // ---- step 4 (threads sub < n1, i.e. all): DFT over j2 of the
-    // transposed tile; output q = sub + n1 k2
-    Cx<CT> w2[n2 / 2 > 0 ? n2 / 2 : 1];
-#pragma unroll
-    for (int m = 0; m < n2 / 2; ++m) w2[m] = tw[m * n1];
-    Cx<CT> x4[n2];
-#pragma unroll
-    for (int j2 = 0; j2 < n2; ++j2) x4[bitrev(j2, ilog2(n2))] = row[j2 * n1 + sub];
-    dft_regs<CT, n2>(x4, w2);
-    if (!valid) return;
-#pragma unroll
-    for (int k2 = 0; k2 < n2; ++k2) {
-        const int q = sub + n1 * k2;
-        if (!INV) {
-            const Cx<CT> p = pw[q];
-            out[(int64_t)q * R] = (OT)(p.re * x4[k2].re - p.im * x4[k2].im);
-        } else {
-            // v_q = Re(conj(DFT(conj V))_q) / n = Re(DFT(conj V)_q) / n
-            const int dst = (q < n / 2) ? 2 * q : 2 * (n - 1 - q) + 1;
-            out[(int64_t)dst * R] = (OT)(x4[k2].re * (CT(1) / CT(n)));
-        }
-    }
+    S::second(sub, tw, pw, row, valid, Y + blk * R * n + a, R);
 }
 
 template <class IT, class OT, class CT, int L, bool INV>
