@@ -1075,6 +1075,19 @@ __global__ void jacobi_finish(const JacobiCtl* __restrict__ ctl, int64_t n,
     if (threadIdx.x == 0) *status = nf ? TSVDM_E_NONFINITE : (nc ? TSVDM_E_NOCONV : TSVDM_OK);
 }
 
+// Pinned host slots for the per-sweep counts of unconverged slices: one set
+// per host thread, allocated on first use and kept for the life of the
+// process (nullptr if pinned memory is unavailable).
+int* poll_slots() {
+    static thread_local int* slots = nullptr;
+    static thread_local bool tried = false;
+    if (!tried) {
+        tried = true;
+        if (hipHostMalloc((void**)&slots, 1024 * sizeof(int), hipHostMallocDefault) != hipSuccess) slots = nullptr;
+    }
+    return slots;
+}
+
 template <class T, int NB2>
 int jacobi_impl(T* A, int64_t m, int64_t p, int64_t n, T* W, double* s2, int32_t* status,
                 const JacobiOpts& o, void* ws, hipStream_t st) {
@@ -1110,6 +1123,17 @@ int jacobi_impl(T* A, int64_t m, int64_t p, int64_t n, T* W, double* s2, int32_t
     // block), 16-byte aligned accesses, L and r multiples of the tile
     const bool interior = g.r % B == 0 && nb % 2 == 0 && vec_a && vec_w && g.L % 16 == 0 && g.r % 16 == 0;
     int64_t launches = 0;
+    // The host poll runs one sweep behind: sweep s's count is copied into
+    // pinned memory and read once sweep s + 1 is queued, so the GPU does not
+    // idle while the host waits.  A sweep queued after convergence finds
+    // every slice done; its launches return at once and change nothing.
+    int* poll = o.host_poll ? poll_slots() : nullptr;
+    hipEvent_t pev[2] = {nullptr, nullptr};
+    int last = -1;
+    if (poll) {
+        TSVDM_HIP_CHECK(hipEventCreateWithFlags(&pev[0], hipEventDisableTiming));
+        TSVDM_HIP_CHECK(hipEventCreateWithFlags(&pev[1], hipEventDisableTiming));
+    }
     for (int sweep = 0; sweep < o.max_sweeps; ++sweep) {
         if (stats) {
             hipEvent_t e0, e1;
@@ -1138,7 +1162,16 @@ int jacobi_impl(T* A, int64_t m, int64_t p, int64_t n, T* W, double* s2, int32_t
         if (stats) TSVDM_HIP_CHECK(hipEventRecord(evs.back(), st));
         jacobi_sweep_end<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(ctl, n, o.tol, remaining + sweep);
         TSVDM_LAUNCH_CHECK();
-        if (o.host_poll) {
+        if (poll) {
+            TSVDM_HIP_CHECK(hipMemcpyAsync(poll + sweep, remaining + sweep, sizeof(int),
+                                           hipMemcpyDeviceToHost, st));
+            TSVDM_HIP_CHECK(hipEventRecord(pev[sweep & 1], st));
+            last = sweep;
+            if (sweep >= 1) {
+                TSVDM_HIP_CHECK(hipEventSynchronize(pev[(sweep - 1) & 1]));
+                if (poll[sweep - 1] == 0) break;
+            }
+        } else if (o.host_poll) {
             int left = -1;
             TSVDM_HIP_CHECK(hipMemcpyAsync(&left, remaining + sweep, sizeof(int),
                                            hipMemcpyDeviceToHost, st));
@@ -1156,6 +1189,14 @@ int jacobi_impl(T* A, int64_t m, int64_t p, int64_t n, T* W, double* s2, int32_t
     TSVDM_LAUNCH_CHECK();
     jacobi_finish<<<1, 256, 0, st>>>(ctl, n, status);
     TSVDM_LAUNCH_CHECK();
+    if (poll) {
+        // no copy into the pinned slots may be in flight once this returns
+        // (the next call on this thread reuses them); the kernels queued
+        // above keep the GPU busy meanwhile
+        if (last >= 0) TSVDM_HIP_CHECK(hipEventSynchronize(pev[last & 1]));
+        (void)hipEventDestroy(pev[0]);
+        (void)hipEventDestroy(pev[1]);
+    }
     if (stats) {
         unsigned long long pc[4] = {0ull, 0ull, 0ull, 0ull};
         TSVDM_HIP_CHECK(hipMemcpyAsync(pc, pair_counts, sizeof(pc), hipMemcpyDeviceToHost, st));
