@@ -69,6 +69,9 @@ __global__ __launch_bounds__(1024) void pack_sort(const double* __restrict__ s2,
 }
 
 // Gather kept vectors into U_pk (m x rho) and G_pk (rho x p) of each slice.
+// Workgroup x of a slice takes the U columns c = x, x + gridDim.x, ... and
+// the G columns b = x, x + gridDim.x, ...; its threads run along the
+// column, so no element needs an index division.
 template <class T>
 __global__ __launch_bounds__(256) void pack_copy(const T* __restrict__ A, const T* __restrict__ W,
                                                  const double* __restrict__ s2, SliceGeom g,
@@ -84,34 +87,36 @@ __global__ __launch_bounds__(256) void pack_copy(const T* __restrict__ A, const 
     const int64_t m = g.m, p = g.p, r = g.r;
     const T* Ab = A + s * m * p;
     const T* Wb = W + s * r * r;
+    const double* s2b = s2 + s * r;
     const int32_t* pr = perm + s * r + first;
     const bool rows = g.rows != 0;  // m < p: vectors are rows, W holds U
-    const int64_t nu = kr * m, ng = kr * p;
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < nu + ng; e += stride) {
-        if (e < nu) {
-            const int64_t a = e % m, c = e / m;
-            const int64_t j = pr[c];
-            T v;
-            if (rows) {
-                v = Wb[j * r + a];
-            } else {
-                const double sg = sqrt(fmax(s2[s * r + j], 0.0));
-                v = sg > 0.0 ? static_cast<T>((double)Ab[a + j * m] / sg) : T(0);
-            }
-            U_pk[m * off + e] = v;
+    const int t = threadIdx.x;
+    T* const Uo = U_pk + m * off;
+    T* const Go = G_pk + p * off;
+    for (int64_t c = blockIdx.x; c < kr; c += gridDim.x) {
+        const int64_t j = pr[c];
+        T* const u = Uo + c * m;
+        if (rows) {
+            const T* w = Wb + j * r;
+            for (int64_t a = t; a < m; a += blockDim.x) u[a] = w[a];
         } else {
-            const int64_t f = e - nu;
-            const int64_t c = f % kr, b = f / kr;  // G_pk is kr x p, leading dim kr
-            const int64_t j = pr[c];
-            T v;
-            if (rows) {
-                v = Ab[j + b * m];
-            } else {
-                const double sg = sqrt(fmax(s2[s * r + j], 0.0));
-                v = static_cast<T>(sg * (double)Wb[b + j * r]);
+            const double sg = sqrt(fmax(s2b[j], 0.0));
+            const T* x = Ab + j * m;
+            for (int64_t a = t; a < m; a += blockDim.x)
+                u[a] = sg > 0.0 ? static_cast<T>((double)x[a] / sg) : T(0);
+        }
+    }
+    for (int64_t b = blockIdx.x; b < p; b += gridDim.x) {
+        T* const gcol = Go + b * kr;   // G_pk is kr x p, leading dim kr
+        if (rows) {
+            const T* x = Ab + b * m;
+            for (int64_t c = t; c < kr; c += blockDim.x) gcol[c] = x[pr[c]];
+        } else {
+            for (int64_t c = t; c < kr; c += blockDim.x) {
+                const int64_t j = pr[c];
+                const double sg = sqrt(fmax(s2b[j], 0.0));
+                gcol[c] = static_cast<T>(sg * (double)Wb[b + j * r]);
             }
-            G_pk[p * off + c + b * kr] = v;
         }
     }
 }
