@@ -168,6 +168,29 @@ def test_slice_svd_status_and_host_poll_equivalence(ops):
     assert torch.equal(s1, s3) and torch.equal(a1, a3)
 
 
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+@pytest.mark.parametrize("max_sweeps", [2, 6, 9, 40])
+def test_host_poll_one_sweep_behind_matches_every_sweep(ops, dtype, max_sweeps):
+    # The host reads each sweep's count of unconverged slices one sweep late;
+    # with slices that converge at different sweeps, and limits that stop
+    # before, at and after convergence, the bits and the status must equal
+    # a run that executes every sweep without reading.
+    rng = np.random.default_rng(11)
+    A = rng.standard_normal((96, 160, 5))
+    A[:, :, 1] = np.outer(rng.standard_normal(96), rng.standard_normal(160)) + 1e-3 * A[:, :, 1]
+    A[:, :, 2] *= np.logspace(0, -6, 160)[None, :]
+    a1, a2 = to_dev(A, dtype), to_dev(A, dtype)
+    W1, s1, st1 = ops.tsvdm_slice_svd(a1, max_sweeps=max_sweeps, host_poll=True)
+    W2, s2_, st2 = ops.tsvdm_slice_svd(a2, max_sweeps=max_sweeps, host_poll=False)
+    torch.cuda.synchronize()
+    assert int(st1.item()) == int(st2.item())
+    if max_sweeps == 2:
+        assert int(st1.item()) == -5
+    if max_sweeps == 40:
+        assert int(st1.item()) == 0
+    assert torch.equal(s1, s2_) and torch.equal(a1, a2) and torch.equal(W1, W2)
+
+
 def test_slice_svd_reports_nonconvergence(ops):
     A = np.random.default_rng(4).standard_normal((64, 64, 2))
     _W, _s2, st = ops.tsvdm_slice_svd(to_dev(A), max_sweeps=1)
