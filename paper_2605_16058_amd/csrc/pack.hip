@@ -125,37 +125,47 @@ __global__ __launch_bounds__(256) void pack_copy(const T* __restrict__ A, const 
 // C^T = G^T U^T so that MFMA output lanes run along the rows of C.
 // K chunk of the low-rank product staged in LDS.
 constexpr int LR_KC = 32;
-template <class T>
+template <class T, int BW>
 struct LowrankShared {
     T Us[LR_KC][64 + 1];  // [c][a]
-    T Gs[64][LR_KC + 1];  // [b][c]
+    T Gs[BW][LR_KC + 1];  // [b][c]
 };
 
-// Output tile (ta, tb) of one slice: Cb (m x p) = Ub (m x kr) * Gb (kr x p).
-// The next K chunk is loaded into registers while the MFMAs of the current
-// one run; the sums run over k in increasing order, four terms per MFMA.
-template <class T>
-__device__ __forceinline__ void lowrank_tile(LowrankShared<T>& sh, const T* __restrict__ Ub,
+// Output tile (ta, tb) of one slice, 64 rows by BW (64 or 128) columns:
+// Cb (m x p) = Ub (m x kr) * Gb (kr x p).  Each wave holds BW / 64 strips
+// of 16 columns against all 64 rows.  The next K chunk is loaded into
+// registers while the MFMAs of the current one run; every sum runs over k
+// in increasing order, four terms per MFMA, whatever BW is.
+template <class T, int BW>
+__device__ __forceinline__ void lowrank_tile(LowrankShared<T, BW>& sh, const T* __restrict__ Ub,
                                              const T* __restrict__ Gb, int64_t m, int64_t p,
                                              int64_t kr, T* __restrict__ Cb, int ta, int tb) {
     typedef typename Acc<T>::type AccT;
     constexpr int KC = LR_KC;
-    constexpr int PER = KC * 64 / 256;  // elements of each operand per thread and chunk
+    constexpr int NF = BW / 64;           // 16-column strips per wave
+    constexpr int PU = KC * 64 / 256;     // U elements per thread and chunk
+    constexpr int PG = KC * BW / 256;     // G elements per thread and chunk
     auto& Us = sh.Us;
     auto& Gs = sh.Gs;
-    const int64_t a0 = (int64_t)ta * 64, b0 = (int64_t)tb * 64;
+    const int64_t a0 = (int64_t)ta * 64, b0 = (int64_t)tb * BW;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int lr = lane & 15, lg = lane >> 4;
-    AccT acc[4];
+    AccT acc[NF][4];
 #pragma unroll
-    for (int t = 0; t < 4; ++t) acc[t] = zero4<AccT>();
-    T ur[PER], gr[PER];
+    for (int f = 0; f < NF; ++f)
+#pragma unroll
+        for (int t = 0; t < 4; ++t) acc[f][t] = zero4<AccT>();
+    T ur[PU], gr[PG];
     auto load = [&](int64_t c0) {
 #pragma unroll
-        for (int i = 0; i < PER; ++i) {
+        for (int i = 0; i < PU; ++i) {
             const int e = tid + 256 * i;
             const int a = e & 63, c = e >> 6;
             ur[i] = (a0 + a < m && c0 + c < kr) ? Ub[(a0 + a) + (c0 + c) * m] : T(0);
+        }
+#pragma unroll
+        for (int i = 0; i < PG; ++i) {
+            const int e = tid + 256 * i;
             const int cg = e % KC, b = e / KC;
             gr[i] = (b0 + b < p && c0 + cg < kr) ? Gb[(c0 + cg) + (b0 + b) * kr] : T(0);
         }
@@ -163,20 +173,27 @@ __device__ __forceinline__ void lowrank_tile(LowrankShared<T>& sh, const T* __re
     if (kr > 0) load(0);
     for (int64_t c0 = 0; c0 < kr; c0 += KC) {
 #pragma unroll
-        for (int i = 0; i < PER; ++i) {
+        for (int i = 0; i < PU; ++i) {
             const int e = tid + 256 * i;
             Us[e >> 6][e & 63] = ur[i];
+        }
+#pragma unroll
+        for (int i = 0; i < PG; ++i) {
+            const int e = tid + 256 * i;
             Gs[e / KC][e % KC] = gr[i];
         }
         __syncthreads();
         if (c0 + KC < kr) load(c0 + KC);
 #pragma unroll
         for (int kk = 0; kk < KC; kk += 4) {
-            T av = Gs[wave * 16 + lr][kk + lg];  // A = G^T : row b, k = c
+            T av[NF];
+#pragma unroll
+            for (int f = 0; f < NF; ++f) av[f] = Gs[(wave * NF + f) * 16 + lr][kk + lg];  // A = G^T
 #pragma unroll
             for (int t = 0; t < 4; ++t) {
                 T bv = Us[kk + lg][t * 16 + lr];  // B = U^T : k = c, col a
-                acc[t] = mfma(av, bv, acc[t]);
+#pragma unroll
+                for (int f = 0; f < NF; ++f) acc[f][t] = mfma(av[f], bv, acc[f][t]);
             }
         }
         __syncthreads();
@@ -186,39 +203,47 @@ __device__ __forceinline__ void lowrank_tile(LowrankShared<T>& sh, const T* __re
         const int64_t a = a0 + t * 16 + lr;
         if (a >= m) continue;
 #pragma unroll
-        for (int v = 0; v < 4; ++v) {
-            const int64_t b = b0 + wave * 16 + mfma_row<T>(lg, v);
-            if (b < p) Cb[a + b * m] = acc[t][v];
-        }
+        for (int f = 0; f < NF; ++f)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int64_t b = b0 + (wave * NF + f) * 16 + mfma_row<T>(lg, v);
+                if (b < p) Cb[a + b * m] = acc[f][t][v];
+            }
     }
 }
 
 template <class T>
-__global__ __launch_bounds__(256) void lowrank_gemm(const T* __restrict__ U_pk,
+struct LowrankCfg {
+    static constexpr int WAVES = sizeof(T) == 4 ? 2 : 1;   // waves per SIMD the registers allow
+};
+
+template <class T>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(LowrankCfg<T>::WAVES)))
+void lowrank_gemm(const T* __restrict__ U_pk,
                                                     const T* __restrict__ G_pk, int64_t m,
                                                     int64_t p, const int32_t* __restrict__ rho,
                                                     const int64_t* __restrict__ offsets,
                                                     int64_t capacity, T* __restrict__ C,
                                                     int tiles_a) {
-    __shared__ LowrankShared<T> sh;
+    __shared__ LowrankShared<T, 128> sh;
     const int64_t s = blockIdx.y;
     const int ta = blockIdx.x % tiles_a, tb = blockIdx.x / tiles_a;
     const int64_t off = offsets[s];
     const int64_t kr = (off + rho[s] <= capacity) ? rho[s] : 0;  // unwritten slices read as 0
-    lowrank_tile<T>(sh, U_pk + m * off, G_pk + p * off, m, p, kr, C + s * m * p, ta, tb);
+    lowrank_tile<T, 128>(sh, U_pk + m * off, G_pk + p * off, m, p, kr, C + s * m * p, ta, tb);
 }
 
 // Batched form: task = (slice, tile a, tile b) over PackSlice descriptors.
 template <class T>
 __global__ __launch_bounds__(256) void lowrank_gemm_batch(const PackSlice* __restrict__ ps,
                                                           const int4* __restrict__ tasks) {
-    __shared__ LowrankShared<T> sh;
+    __shared__ LowrankShared<T, 64> sh;
     const int4 tk = tasks[blockIdx.x];
     const PackSlice d = ps[tk.x];
     const int64_t m = d.g.m, p = d.g.p;
     const int64_t off = *d.off;
     const int64_t kr = (off + *d.rho <= d.capacity) ? *d.rho : 0;
-    lowrank_tile<T>(sh, static_cast<const T*>(d.U_pk) + m * off,
+    lowrank_tile<T, 64>(sh, static_cast<const T*>(d.U_pk) + m * off,
                     static_cast<const T*>(d.G_pk) + p * off, m, p, kr, static_cast<T*>(d.C),
                     tk.y, tk.z);
 }
@@ -349,7 +374,8 @@ int run_pack(const void* A, const void* W, const double* s2, int dt, int64_t m, 
 int run_lowrank_gemm(const void* U_pk, const void* G_pk, int dt, int64_t m, int64_t p,
                      int64_t n, const int32_t* rho, const int64_t* offsets, int64_t capacity,
                      void* C, hipStream_t st) {
-    const int ta = (int)((m + 63) / 64), tb = (int)((p + 63) / 64);
+    // 64 x 128 output tiles (rows a of m, columns b of p)
+    const int ta = (int)((m + 63) / 64), tb = (int)((p + 127) / 128);
     TSVDM_REQUIRE((int64_t)ta * tb < ((int64_t)1 << 31) && n < 65536, TSVDM_E_SHAPE,
                   "reconstruction grid too large");
     dim3 grid((unsigned)(ta * tb), (unsigned)n);
