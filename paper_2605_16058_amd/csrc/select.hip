@@ -72,53 +72,85 @@ __global__ void sel_bitonic_global(unsigned long long* __restrict__ keys, int64_
 
 constexpr int STHREADS = 1024;
 
+// Inclusive scan of the STHREADS double-double values (hi, lo) in LDS by
+// the whole workgroup: entry t becomes x_0 + ... + x_t, in a fixed tree
+// order (step d adds the entry d places earlier).
+__device__ void dd_block_scan(double* hi, double* lo, int t) {
+    for (int d = 1; d < STHREADS; d <<= 1) {
+        const bool has = t >= d;
+        dd u = {0.0, 0.0};
+        if (has) u = dd{hi[t - d], lo[t - d]};
+        const dd v = {hi[t], lo[t]};
+        __syncthreads();
+        if (has) {
+            const dd w = dd_add(u, v);
+            hi[t] = w.hi;
+            lo[t] = w.lo;
+        }
+        __syncthreads();
+    }
+}
+
 // Single-workgroup scan over the N sorted values (N <= a few million).
-// Scan of N ascending keys by one workgroup of STHREADS threads; writes
-// stats = {tau, discarded, W, J}.
+// Scan of N ascending keys by one workgroup of STHREADS threads, thread t
+// owning the t-th contiguous segment; writes stats = {tau, discarded, W, J}.
 __device__ void sel_scan_body(const unsigned long long* __restrict__ keys, int64_t N, double eps,
                               double* __restrict__ stats) {
     __shared__ double shi[STHREADS], slo[STHREADS];
-    __shared__ double phi[STHREADS], plo[STHREADS];
-    __shared__ long long cnt[STHREADS];
-    __shared__ double W_s, tau_s;
-    __shared__ long long J_s;
+    __shared__ unsigned long long J_acc;
+    __shared__ double tau_s;
     const int t = threadIdx.x;
     const int64_t seg = (N + STHREADS - 1) / STHREADS;
     const int64_t b0 = (int64_t)t * seg;
     const int64_t b1 = (b0 + seg < N) ? b0 + seg : N;
+    if (t == 0) J_acc = 0ull;
 
-    // pass 1: segment sums
+    // The segment loops load eight keys at a time and take them in order.
+    auto key = [&](int64_t j) { return __longlong_as_double((long long)keys[j]); };
+
+    // pass 1: segment sums, their prefix sums and the total W
     dd acc = {0.0, 0.0};
-    for (int64_t j = b0; j < b1; ++j) acc = dd_add_d(acc, __longlong_as_double((long long)keys[j]));
+    int64_t j = b0;
+    for (; j + 8 <= b1; j += 8) {
+        double v[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) v[q] = key(j + q);
+#pragma unroll
+        for (int q = 0; q < 8; ++q) acc = dd_add_d(acc, v[q]);
+    }
+    for (; j < b1; ++j) acc = dd_add_d(acc, key(j));
     shi[t] = acc.hi; slo[t] = acc.lo;
     __syncthreads();
-    if (t == 0) {
-        dd run = {0.0, 0.0};
-        for (int i = 0; i < STHREADS; ++i) {
-            phi[i] = run.hi; plo[i] = run.lo;
-            run = dd_add(run, dd{shi[i], slo[i]});
-        }
-        W_s = dd_round(run);
-    }
-    __syncthreads();
-    const double W = W_s;
+    dd_block_scan(shi, slo, t);
+    const dd pre = t > 0 ? dd{shi[t - 1], slo[t - 1]} : dd{0.0, 0.0};   // sum of earlier segments
+    const double W = dd_round(dd{shi[STHREADS - 1], slo[STHREADS - 1]});
     const double eps2 = eps * eps;
 
-    // pass 2: J = #{ j : w_j / W < eps^2 }  (w is non-decreasing)
+    // pass 2: J = #{ j : w_j / W < eps^2 }  (w is non-decreasing); an
+    // integer count, so the order of the additions does not matter
     long long c = 0;
-    if (W > 0.0) {
-        dd w = {phi[t], plo[t]};
-        for (int64_t j = b0; j < b1; ++j) {
-            w = dd_add_d(w, __longlong_as_double((long long)keys[j]));
-            if (dd_round(w) / W < eps2) ++c; else break;
+    bool go = W > 0.0;
+    dd w = pre;
+    for (j = b0; go && j + 8 <= b1; j += 8) {
+        double v[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) v[q] = key(j + q);
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            if (!go) break;
+            w = dd_add_d(w, v[q]);
+            if (dd_round(w) / W < eps2) ++c; else go = false;
         }
     }
-    cnt[t] = c;
+    for (; go && j < b1; ++j) {
+        w = dd_add_d(w, key(j));
+        if (dd_round(w) / W < eps2) ++c; else go = false;
+    }
+    for (int off = 32; off > 0; off >>= 1) c += __shfl_xor(c, off);
+    if ((t & 63) == 0 && c != 0) atomicAdd(&J_acc, (unsigned long long)c);
     __syncthreads();
+    const long long J = (long long)J_acc;
     if (t == 0) {
-        long long J = 0;
-        for (int i = 0; i < STHREADS; ++i) J += cnt[i];
-        J_s = J;
         double tau;
         if (W == 0.0) tau = 0.0;                         // zero tensor: drop everything
         else if (J == 0) tau = -__longlong_as_double(0x7ff0000000000000ll);  // keep everything
@@ -126,22 +158,33 @@ __device__ void sel_scan_body(const unsigned long long* __restrict__ keys, int64
         tau_s = tau;
     }
     __syncthreads();
-    // pass 3: discarded energy = sum of values <= tau (fixed order)
+    // pass 3: discarded energy = sum of values <= tau (segment sums, then
+    // the same tree as pass 1)
     const double tau = tau_s;
     dd d = {0.0, 0.0};
-    for (int64_t j = b0; j < b1; ++j) {
-        const double v = __longlong_as_double((long long)keys[j]);
-        if (v <= tau) d = dd_add_d(d, v); else break;
+    go = true;
+    for (j = b0; go && j + 8 <= b1; j += 8) {
+        double v[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) v[q] = key(j + q);
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            if (!go) break;
+            if (v[q] <= tau) d = dd_add_d(d, v[q]); else go = false;
+        }
+    }
+    for (; go && j < b1; ++j) {
+        const double v = key(j);
+        if (v <= tau) d = dd_add_d(d, v); else go = false;
     }
     shi[t] = d.hi; slo[t] = d.lo;
     __syncthreads();
+    dd_block_scan(shi, slo, t);
     if (t == 0) {
-        dd run = {0.0, 0.0};
-        for (int i = 0; i < STHREADS; ++i) run = dd_add(run, dd{shi[i], slo[i]});
         stats[0] = tau;
-        stats[1] = dd_round(run);
+        stats[1] = dd_round(dd{shi[STHREADS - 1], slo[STHREADS - 1]});
         stats[2] = W;
-        stats[3] = (double)J_s;
+        stats[3] = (double)J;
     }
     __syncthreads();
 }
