@@ -162,13 +162,15 @@ __global__ void jacobi_init(T* __restrict__ W, int64_t r, int64_t n, JacobiCtl* 
                             int* __restrict__ remaining, int max_sweeps,
                             unsigned long long* __restrict__ pair_counts,
                             int32_t* __restrict__ status, const int32_t* __restrict__ run) {
-    const int64_t rr = r * r;
-    const int64_t total = rr * n;
+    // W = I: workgroups take whole columns (one index division per column),
+    // threads run down the column
+    const int64_t cols = r * n;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total; idx += stride) {
-        if (run && !run[idx / rr]) continue;
-        int64_t e = idx % rr;
-        W[idx] = (e % r == e / r) ? T(1) : T(0);
+    for (int64_t col = blockIdx.x; col < cols; col += gridDim.x) {
+        const int64_t s = col / r, c = col - s * r;
+        if (run && !run[s]) continue;
+        T* const w = W + col * r;
+        for (int64_t row = threadIdx.x; row < r; row += blockDim.x) w[row] = (row == c) ? T(1) : T(0);
     }
     for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < n; idx += stride) {
         JacobiCtl c;
@@ -1099,8 +1101,7 @@ int jacobi_impl(T* A, int64_t m, int64_t p, int64_t n, T* W, double* s2, int32_t
     const bool stats = stats_enabled();
     std::vector<hipEvent_t> evs;
 
-    const int64_t initw = g.r * g.r * n;
-    int64_t gblocks = (initw + 255) / 256;
+    int64_t gblocks = g.r * n;   // one workgroup per column of W (grid-stride beyond the cap)
     if (gblocks < (n + 255) / 256) gblocks = (n + 255) / 256;
     if (gblocks > 65535 * 16) gblocks = 65535 * 16;
     if (gblocks < 1) gblocks = 1;
@@ -1236,6 +1237,16 @@ int jacobi_batch_impl(const BatchSlice* sl, int64_t nslices, const int2* tasks,
     }
     int64_t launches = 0;
     const unsigned sblocks = (unsigned)((nslices + 255) / 256);
+    // Poll every 4 steps, one poll behind (as in the single-tensor loop):
+    // poll k's count goes to pinned slot k mod 2 and is read once poll k + 1
+    // is queued; steps queued after convergence find every slice done.
+    int* poll = host_poll ? poll_slots() : nullptr;
+    hipEvent_t pev[2] = {nullptr, nullptr};
+    int lastk = -1;
+    if (poll) {
+        TSVDM_HIP_CHECK(hipEventCreateWithFlags(&pev[0], hipEventDisableTiming));
+        TSVDM_HIP_CHECK(hipEventCreateWithFlags(&pev[1], hipEventDisableTiming));
+    }
     for (int t = 0; t < max_steps; ++t) {
         // both pair widths see the same round counter t
         if (group[0] > 0) {
@@ -1251,8 +1262,17 @@ int jacobi_batch_impl(const BatchSlice* sl, int64_t nslices, const int2* tasks,
         }
         jacobi_sweep_end_batch<<<sblocks, 256, 0, st>>>(sl, nslices, t, ctl, remaining + t);
         TSVDM_LAUNCH_CHECK();
-        // poll every 4 steps: one synchronisation per few rounds
-        if (host_poll && (t % 4 == 3)) {
+        if (poll && (t % 4 == 3)) {
+            const int k = t / 4;
+            TSVDM_HIP_CHECK(hipMemcpyAsync(poll + (k & 1), remaining + t, sizeof(int),
+                                           hipMemcpyDeviceToHost, st));
+            TSVDM_HIP_CHECK(hipEventRecord(pev[k & 1], st));
+            lastk = k;
+            if (k >= 1) {
+                TSVDM_HIP_CHECK(hipEventSynchronize(pev[(k - 1) & 1]));
+                if (poll[(k - 1) & 1] == 0) break;
+            }
+        } else if (host_poll && (t % 4 == 3)) {
             int left = -1;
             TSVDM_HIP_CHECK(hipMemcpyAsync(&left, remaining + t, sizeof(int), hipMemcpyDeviceToHost, st));
             TSVDM_HIP_CHECK(hipStreamSynchronize(st));
@@ -1264,6 +1284,12 @@ int jacobi_batch_impl(const BatchSlice* sl, int64_t nslices, const int2* tasks,
     TSVDM_LAUNCH_CHECK();
     jacobi_finish<<<1, 256, 0, st>>>(ctl, nslices, status);
     TSVDM_LAUNCH_CHECK();
+    if (poll) {
+        // no copy into the pinned slots may be in flight once this returns
+        if (lastk >= 0) TSVDM_HIP_CHECK(hipEventSynchronize(pev[lastk & 1]));
+        (void)hipEventDestroy(pev[0]);
+        (void)hipEventDestroy(pev[1]);
+    }
     if (stats) {
         unsigned long long pc[4] = {0ull, 0ull, 0ull, 0ull};
         TSVDM_HIP_CHECK(hipMemcpyAsync(pc, pair_counts, sizeof(pc), hipMemcpyDeviceToHost, st));
