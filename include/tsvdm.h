@@ -172,10 +172,14 @@ int tsvdm_transform_dct(const void* X, int x_dtype, void* Y, int y_dtype,
  *   max_sweeps  sweep limit (0 = 40).
  *   tol      convergence threshold on |cos| between any two vectors, tested
  *            in FP64 (0 = default: 1e-14 for F64, 2e-6 for F32).
- *   host_poll   1: read a device flag after every sweep and stop early
- *            (synchronises the stream once per sweep); 0: launch max_sweeps
- *            sweeps whose kernels return at once after convergence
- *            (graph-capturable).
+ *   host_poll   1: read the count of unconverged slices after every sweep
+ *            and stop early; the host reads sweep s's count once sweep
+ *            s + 1 is queued (so at most one sweep that changes nothing
+ *            runs after convergence) and waits for the last count before
+ *            returning; not usable under stream capture.  0: launch
+ *            max_sweeps sweeps whose kernels return at once after
+ *            convergence (graph-capturable).  Results are the same bits
+ *            either way.
  * Rotation angles, the convergence test and s2 are computed in FP64 for
  * both dtypes. */
 int tsvdm_slice_svd_workspace_size(int64_t m, int64_t p, int64_t n, int dtype,
@@ -385,8 +389,10 @@ int tsvdm_batch_plan_create(const tsvdm_batch_item* items, int32_t count, int in
 /* Run the whole batch on `stream`: one launch per stage covers every tensor
  * (the Jacobi stage launches once per step of a global round counter; each
  * slice follows its own tournament).  host_poll = 1 reads a device counter
- * every 4 rounds and stops when all slices converged; host_poll = 0 runs the
- * fixed number of steps (kernels of converged slices return at once).
+ * every 4 rounds, one reading behind the queued work, and stops when all
+ * slices converged; host_poll = 0 runs the fixed number of steps (kernels
+ * of converged slices return at once).  Results are the same bits either
+ * way.
  * use_graph = 1 captures the run (host_poll forced to 0) into a hipGraph on
  * the first call for this (workspace, stream) and replays it afterwards.
  * status (device int32[1]): TSVDM_OK or the first device-side condition. */
