@@ -57,6 +57,30 @@ def test_batch_equals_single_tensor_calls(ragged, precision, dtype):
         assert np.allclose(e1, e2, rtol=1e-12, atol=1e-300), t
 
 
+@pytest.mark.parametrize("precision,dtype", [("f64", torch.float64), ("f32", torch.float32)])
+def test_batch_host_poll_matches_fixed_steps(ragged, precision, dtype):
+    # the host reads the count of unconverged slices one poll behind the
+    # queued steps; the result must equal running every step without reading
+    from paper_2605_16058_amd.pipeline import BatchTSVDM
+    w = ragged
+    n = 24
+    Ts = [to_dev(A, torch.float32) for A in w.A[:n]]
+    b = BatchTSVDM(Ts, w.M[:n], w.mode[:n], ks=w.k[:n], epss=w.eps[:n], precision=precision)
+    st = b.run(host_poll=True)
+    torch.cuda.synchronize()
+    assert int(st.item()) == 0
+    ref = [a.clone() for a in b.A_rec]
+    ref_rho = [r.clone() for r in b.rho]
+    for a in b.A_rec:
+        a.zero_()
+    st = b.run(host_poll=False)
+    torch.cuda.synchronize()
+    assert int(st.item()) == 0
+    for t in range(n):
+        assert torch.equal(b.rho[t], ref_rho[t]), t
+        assert torch.equal(b.A_rec[t], ref[t]), t
+
+
 def test_batch_fp64_matches_oracle(ragged):
     from paper_2605_16058_amd.pipeline import BatchTSVDM
     w = ragged
