@@ -90,7 +90,9 @@ def mode3(A, M):
     M = _f64(M)
     if A.shape[2] != M.shape[1]:
         raise ValueError("mode-3 size mismatch")
-    out = np.zeros(A.shape[:2] + (M.shape[0],))
+    # column-major like the tensors (slice i contiguous); the layout does
+    # not change any operation or its order
+    out = np.zeros(A.shape[:2] + (M.shape[0],), order="F")
     for i in range(M.shape[0]):
         for l in range(M.shape[1]):
             if M[i, l] != 0.0:
@@ -261,7 +263,7 @@ def truncated_factors(U, S, V, rho):
 def reconstruct(factors, M, shape):
     """C-hat_i = U_i G_i in the transform domain, then C = C-hat x_3 M^{-1}."""
     m, p, n = shape
-    C_hat = np.zeros((m, p, n))
+    C_hat = np.zeros((m, p, n), order="F")   # slice i contiguous; layout only
     for i, (Ui, _si, Gi) in enumerate(factors):
         if Ui.shape[1] > 0:
             C_hat[:, :, i] = Ui @ Gi
