@@ -54,8 +54,9 @@ def read_stats(lib):
 
 
 def jacobi_roofline(st, peak_tf):
-    """Roofline entry of the dominant kernel (jacobi_round) from the
-    library's event timing and per-pair algorithmic counters."""
+    """Roofline entry of jacobi_round for workloads without a single shape
+    (the batch, the order-6 tensor): the kernel's own per-pair flops and
+    bytes from the library's counters over the event-timed launches."""
     t = st["ms"] * 1e-3
     launches = max(st["launches"], 1)
     ai = st["flops"] / max(st["bytes"], 1.0)
@@ -73,6 +74,130 @@ def jacobi_roofline(st, peak_tf):
     ach = st["bytes"] / t / 1e9
     return {"bound": "hbm", "achieved": round(ach, 1), "peak": PEAK["hbm_GBs"], "unit": "GB/s",
             "frac": round(ach / PEAK["hbm_GBs"], 4), **common}
+
+
+def svd_work(m, p, n, rho_sum):
+    """Algorithmic flops of the slice SVDs by the Householder-bidiagonalisation
+    convention: 4 L r^2 - (4/3) r^3 per slice for the singular values plus
+    4 (L + r) r rho_i for the retained vectors (L = max(m, p), r = min(m, p))."""
+    L, r = max(m, p), min(m, p)
+    return n * (4.0 * L * r * r - 4.0 / 3.0 * r ** 3), 4.0 * (L + r) * r * rho_sum
+
+
+def path_roofline(m, p, n, rho_sum, eb, peak_tf, transform, ms_per_step):
+    """Roofline time of the whole step, T_roof = sum over stages of
+    max(bytes / HBM peak, flops / compute peak), and its fraction of the
+    measured step.  Stages: forward transform (FP32 in, eb out), slice SVD
+    values (read A-hat) and retained vectors (write the packed factors),
+    low-rank product (read factors, write C-hat), back-transform (read C-hat,
+    write FP32 A_rho), error sums (read A and A_rho).  eb: bytes per element
+    of the compute type."""
+    N = float(m) * p * n
+    tf = 2.5 * math.log2(n) if transform == "dct" else 2.0 * n   # flops per element
+    f_val, f_vec = svd_work(m, p, n, rho_sum)
+    fac = rho_sum * (m + p + 1) * eb
+    stages = {
+        "transform": (N * (4 + eb), N * tf),
+        "svd_values": (N * eb, f_val),
+        "svd_vectors": (fac, f_vec),
+        "lowrank": (rho_sum * (m + p) * eb + N * eb, 2.0 * m * p * rho_sum),
+        "back_transform": (N * (eb + 4), N * tf),
+        "error": (N * 8, 3.0 * N),
+    }
+    t = {k: max(b / (PEAK["hbm_GBs"] * 1e9), f / (peak_tf * 1e12)) * 1e3 for k, (b, f) in stages.items()}
+    t_roof = sum(t.values())
+    return {"t_roof_ms": round(t_roof, 4), "path_frac": round(t_roof / ms_per_step, 4),
+            "stage_ms": {k: round(v, 4) for k, v in t.items()},
+            "algorithmic_bytes": N * 4 * 2 + fac}
+
+
+def svd_roofline(st, steps, m, p, n, rho_sum, peak_tf, traffic_per_launch, alg_bytes_step):
+    """Roofline entry of the dominant kernel (jacobi_round).  achieved = the
+    slice SVDs' algorithmic flops (svd_work) per launch over the launch time
+    measured with HIP events on the library's stream; the kernel's own flop
+    count (Gram plus rotation of every pair it processed) is kept beside it
+    as impl_*.  traffic: counter bytes per launch (or None); traffic_ratio:
+    counter bytes per step over the whole path's algorithmic bytes (read A,
+    write A_rho, write the factors)."""
+    launches = max(st["launches"], 1)
+    t_launch = st["ms"] * 1e-3 / launches
+    per_step = launches / steps
+    f_val, f_vec = svd_work(m, p, n, rho_sum)
+    alg = (f_val + f_vec) / per_step
+    ach = alg / t_launch / 1e12
+    impl = st["flops"] / launches
+    out = {"bound": "mfma", "achieved": round(ach, 3), "peak": peak_tf, "unit": "TFLOP/s",
+           "frac": round(ach / peak_tf, 4), "traffic": traffic_per_launch,
+           "kernel": "jacobi_round", "launches": int(st["launches"]),
+           "launches_per_step": round(per_step, 2), "avg_launch_ms": round(t_launch * 1e3, 4),
+           "algorithmic_flops_per_launch": alg,
+           "impl_flops_per_launch": impl, "impl_bytes_per_launch": st["bytes"] / launches,
+           "impl_achieved": round(impl / t_launch / 1e12, 3),
+           "impl_frac": round(impl / t_launch / 1e12 / peak_tf, 4),
+           "pair_width": st["pair_width"], "pairs_rotating": st["pairs_rot"],
+           "pairs_gram_only": st["pairs_gram"]}
+    out["traffic_ratio"] = (round(traffic_per_launch * per_step / alg_bytes_step, 2)
+                            if traffic_per_launch else None)
+    return out
+
+
+def climate_golden(m, p, n, eps):
+    """The oracle's stored full-size results for this workload, or None."""
+    import numpy as np
+    path = os.path.join(ROOT, "tests", "golden", "climate_fullsize.npz")
+    if (m, p, n) != (512, 1024, 256) or not os.path.exists(path):
+        return None
+    with np.load(path, allow_pickle=False) as f:
+        g = {k: f[k] for k in f.files}
+    return g if float(g["eps"]) == eps else None
+
+
+def vs_golden(res, g, A_host):
+    """Rank differences and sampled-tube error against the oracle's stored
+    result at the tolerance the run selected with (None if not stored)."""
+    import numpy as np
+    tag = None
+    for key in g:
+        if key.startswith("eps") and float(g[key]) == res.eps_sel:
+            tag = key[3:]
+            break
+    if tag is None:
+        return None
+    rho = res.rho.cpu().numpy().astype(np.int64)
+    pos = g["tube_pos"]
+    got = np.stack([res.A_rec[int(a), int(b), :].double().cpu().numpy() for a, b in pos])
+    nt = np.array([np.linalg.norm(A_host[int(a), int(b), :].astype(np.float64)) for a, b in pos])
+    return {"eps_sel": res.eps_sel, "sum_abs_rank_diff": int(np.abs(rho - g[f"rho{tag}"]).sum()),
+            "oracle_sum_rho": int(g[f"rho{tag}"].sum()),
+            "oracle_rel_error": float(g[f"rel_error{tag}"]),
+            "max_tube_rel_diff": float(np.max(np.linalg.norm(got - g[f"tubes{tag}"], axis=1) / nt)),
+            "tubes": int(len(pos))}
+
+
+def threshold_margin(res):
+    """min(tau - nearest smaller square, nearest larger square - tau) / tau
+    over the run's own squared singular values."""
+    import numpy as np
+    tau = float(res.stats[0].item())
+    v = np.sort(res.s2.double().cpu().numpy().ravel())
+    if not np.isfinite(tau) or tau <= 0:
+        return None
+    lo = v[v < tau].max() if np.any(v < tau) else -np.inf
+    hi = v[v > tau].min() if np.any(v > tau) else np.inf
+    return float(min(tau - lo, hi - tau) / tau)
+
+
+def host_cpu():
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"affinity_cpus": len(os.sched_getaffinity(0)), "model": model}
 
 
 def load_traffic(key, sha):
@@ -145,10 +270,11 @@ def cpu_baseline_climate(m, p, n_sample, eps):
     dt = time.perf_counter() - t0
     return {"value": round(m * p * n_sample * 4 / dt / 1e9, 5), "unit": "GB/s",
             "cores": int(blas_threads()), "kind": "oracle",
-            "sample": f"climate-like {m}x{p}x{n_sample} (first {n_sample} of 256 time steps), "
-                      f"DCT-II {n_sample}, t-SVDM-II tol {eps}, FP64 NumPy/LAPACK; "
-                      f"{dt:.2f} s wall, rel_err {res['rel_error']:.3e}",
-            "seconds": round(dt, 3)}
+            "sample": f"climate-like {m}x{p}x{n_sample} (the same recipe, first {n_sample} of 256 "
+                      f"time steps), DCT-II {n_sample}, t-SVDM-II tol {eps}, the FP64 oracle as it "
+                      f"stands (NumPy/LAPACK; cores = its BLAS threads); {dt:.2f} s wall, "
+                      f"rel_err {res['rel_error']:.3e}",
+            "seconds": round(dt, 3), "host": host_cpu()}
 
 
 def transform_timing(a, Ad, M, torch, tf):
@@ -189,8 +315,8 @@ def bench_climate(a, torch, lib):
     A = synth.climate_like(m, p, n, rng=np.random.default_rng(2))
     M = synth.dct2_matrix(n)
     Ad = to_device(A, torch)
-    del A
     in_bytes = m * p * n * 4
+    gold = climate_golden(m, p, n, a.eps)
 
     # the DCT-II is applied by FFT (tsvdm_transform_dct) where the FFT covers
     # the precision (FP32 / FP64); the BF16 forms are transform precisions of
@@ -200,7 +326,7 @@ def bench_climate(a, torch, lib):
     ch = tune_single(a, Ad, M, a.precision, tuned, tf)
     op_mix = TSVDM((m, p, n), M, mode="II", eps=a.eps, precision=a.precision, block=ch[0],
                    tile=ch[1], transform=tf)
-    log(f"mixed ({a.precision}) warmup {a.warmup}, steps {a.steps}")
+    log(f"mixed ({a.precision}) warmup {a.warmup}, steps {a.steps}; selects with eps {op_mix.eps_sel}")
     for _ in range(a.warmup):
         op_mix(Ad)
     lib.tsvdm_stats_reset()
@@ -209,12 +335,12 @@ def bench_climate(a, torch, lib):
     lib.tsvdm_stats_enable(0)
     st = read_stats(lib)
     log(f"mixed: {ms_mix:.2f} ms/step; jacobi stats {st}")
-    roof = jacobi_roofline(st, PEAK["f32_TF"])
     sha = kernel_src_sha()
+    rho_mix = int(res_mix.offsets[-1].item())
+    path = path_roofline(m, p, n, rho_mix, 4, PEAK["f32_TF"], tf, ms_mix)
+    roof = svd_roofline(st, a.steps, m, p, n, rho_mix, PEAK["f32_TF"],
+                        load_traffic(f"jacobi_round_f32_{m}x{p}x{n}", sha), path["algorithmic_bytes"])
     roof["src_sha"] = sha
-    tr = load_traffic(f"jacobi_round_f32_{m}x{p}x{n}", sha)
-    if tr is not None:
-        roof["traffic"] = tr
 
     transform_info = transform_timing(a, Ad, M, torch, tf)
 
@@ -233,11 +359,12 @@ def bench_climate(a, torch, lib):
         lib.tsvdm_stats_enable(0)
         st64 = read_stats(lib)
         log(f"fp64: {ms64:.2f} ms/step; jacobi stats {st64}")
-        roof64 = jacobi_roofline(st64, PEAK["f64_TF"])
+        rho64 = int(res64.offsets[-1].item())
+        path64 = path_roofline(m, p, n, rho64, 8, PEAK["f64_TF"], tf64, ms64)
+        roof64 = svd_roofline(st64, a.steps, m, p, n, rho64, PEAK["f64_TF"],
+                              load_traffic(f"jacobi_round_f64_{m}x{p}x{n}", sha),
+                              path64["algorithmic_bytes"])
         roof64["src_sha"] = sha
-        tr64 = load_traffic(f"jacobi_round_f64_{m}x{p}x{n}", sha)
-        if tr64 is not None:
-            roof64["traffic"] = tr64
         d = ops.tsvdm_error(res64.A_rec, res_mix.A_rec).double().cpu()
         nA = float(res64.err[1].cpu())
         out_f64 = {
@@ -245,11 +372,17 @@ def bench_climate(a, torch, lib):
             "fp64_ms_per_step": round(ms64, 3),
             "speedup_vs_fp64": round(ms64 / ms_mix, 3),
             "fp64_rel_error": res64.rel_error(),
-            "fp64_sum_rho": int(res64.offsets[-1].item()),
+            "fp64_sum_rho": rho64,
             "fp64_svd_status": int(res64.svd_status.item()),
+            "fp64_threshold_margin": threshold_margin(res64),
+            "fp64_compression_ratio": round(m * p * n / max(rho64 * (m + p + 1), 1), 4),
             "mixed_vs_fp64_rel_diff": math.sqrt(float(d[0]) / nA) if nA > 0 else 0.0,
+            "mixed_vs_fp64_sum_abs_rank_diff": int((res64.rho.long() - res_mix.rho.long()).abs().sum()),
+            "fp64_path_roofline": path64,
             "fp64_roofline": roof64,
         }
+        if gold is not None:
+            out_f64["fp64_vs_oracle"] = vs_golden(res64, gold, A)
         del res64, op64
         torch.cuda.empty_cache()
 
@@ -267,13 +400,18 @@ def bench_climate(a, torch, lib):
         "data": "synthetic",
         "config": {"workload": f"climate-like {m}x{p}x{n} FP32, DCT-II"
                                f"{' (FFT)' if tf == 'dct' else ''}, t-SVDM-II tol {a.eps}",
-                   "m": m, "p": p, "n": n, "eps": a.eps, "precision": a.precision,
-                   "transform": tf, "autotune": tuned},
+                   "m": m, "p": p, "n": n, "eps": a.eps, "eps_selected": op_mix.eps_sel,
+                   "precision": a.precision, "transform": tf, "autotune": tuned},
         "transform": transform_info,
         "rel_error": res_mix.rel_error(),
-        "sum_rho": int(res_mix.offsets[-1].item()),
+        "stated_rel_error": a.eps,
+        "sum_rho": rho_mix,
+        "compression_ratio": round(m * p * n / max(rho_mix * (m + p + 1), 1), 4),
+        "threshold_margin": threshold_margin(res_mix),
         "svd_status": int(res_mix.svd_status.item()),
+        "vs_oracle": vs_golden(res_mix, gold, A) if gold is not None else None,
         **out_f64,
+        "path_roofline": path,
         "roofline": roof,
         "cpu_baseline": cpu,
     }

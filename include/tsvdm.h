@@ -19,7 +19,13 @@
  *    m x p column-major matrix.  r = min(m, p).
  *  - Every data pointer is a DEVICE pointer owned by the caller.  The library
  *    never frees caller memory and keeps no pointer after a call returns
- *    (batch plans keep only host data).
+ *    (batch plans keep only host data and graph objects).
+ *  - M (device, FP64) is used as given by tsvdm_transform, tsvdm_transform_mode
+ *    and tsvdm_reconstruct: these calls cannot read device memory before
+ *    launching, so they do not check it.  Check a transform once on the host
+ *    with tsvdm_check_transform (Algorithm 2 requires M = c*Q with Q
+ *    orthogonal; a matrix that is not gives a silently wrong A_rho) and pass
+ *    the back-transform scale 1/c^2 it returns.
  *  - Every compute call is enqueued on `stream` (a hipStream_t passed as
  *    void*; NULL = the default stream) and returns before the work finishes.
  *    Results are valid after the stream is synchronised.
@@ -189,6 +195,33 @@ int tsvdm_slice_svd(void* A_hat, int dtype, int64_t m, int64_t p, int64_t n,
                     int block, int max_sweeps, double tol, int host_poll,
                     void* ws, size_t ws_bytes, void* stream);
 
+/* Slice SVDs of an FP32 tensor through the FP64 Gram matrix, for the
+ * mixed-precision path (Algorithm 1's slice SVDs; Section 3.2 leaves the
+ * slice SVD method open).  With r = min(m, p) and X the r Jacobi vectors of
+ * a slice (its rows when m < p, its columns otherwise):
+ *   G = X X^T in FP64 (exact FP32 products, FP64 sums), then the Cholesky
+ *   factor L L^T = G + s I with s = (max(m, p) + r) * 2^-53 * trace(G)
+ *   (a pivot that rounding leaves <= 0 gives a zero column), then the
+ *   one-sided Jacobi of tsvdm_slice_svd on the columns of L in FP32 with
+ *   FP64 angles, accumulating no rotations: L Q = B.
+ * Outputs (A_hat is only read and must stay unchanged for tsvdm_pack_gram):
+ *   B      (r x r x n, F32, column-major per slice) the orthogonal columns:
+ *          b_j / ||b_j|| are the singular vectors of the slice on its short
+ *          side (U when m < p, V otherwise), ||b_j||^2 = sigma_j^2 + s;
+ *   s2     (r x n, FP64) sigma_j^2 = max(||b_j||^2 - s, 0), unsorted;
+ *   shift  (n, FP64) s of each slice;
+ *   status as in tsvdm_slice_svd.
+ * The eigenvalues of the FP64 Gram matrix carry absolute errors of order
+ * 2^-53 ||G||, so sigma_j is accurate to about 2^-53 sigma_max^2 / sigma_j
+ * (2^-26.5 sigma_max as sigma_j -> 0), well inside FP32 accuracy; this form
+ * is for FP32 results only.  min(m, p) <= 1024.  block, max_sweeps, tol
+ * (default tol from the vector length r) and host_poll as in tsvdm_slice_svd.
+ * ws: tsvdm_slice_svd_gram_workspace_size bytes (holds G and L in FP64). */
+int tsvdm_slice_svd_gram_workspace_size(int64_t m, int64_t p, int64_t n, size_t* bytes);
+int tsvdm_slice_svd_gram(const void* A_hat, int64_t m, int64_t p, int64_t n, void* B,
+                         double* s2, double* shift, int32_t* status, int block, int max_sweeps,
+                         double tol, int host_poll, void* ws, size_t ws_bytes, void* stream);
+
 /* Slice SVDs of a subset: as tsvdm_slice_svd, but only the slices with
  * run[i] != 0 (run: device int32[n]) are computed; every other slice keeps
  * its A_hat, W and s2 entries untouched, so several calls can fill one set
@@ -273,6 +306,17 @@ int tsvdm_pack(const void* A_hat, const void* W, const double* s2, int dtype,
                const int32_t* rho, const int64_t* offsets, int64_t capacity,
                void* U_pk, void* G_pk, void* S_pk, int32_t* status,
                void* ws, size_t ws_bytes, void* stream);
+
+/* tsvdm_pack for the output of tsvdm_slice_svd_gram (F32): the same packed
+ * layout, capacity rule and status.  For kept triplet c (descending sigma,
+ * index j): u_c = b_j / ||b_j|| and G_i = U_rho^T A_hat_i when m < p;
+ * v_c = b_j / ||b_j||, G_i row c = sigma_c v_c^T and u_c = A_hat_i v_c /
+ * sigma_c (a zero column when sigma_c = 0) otherwise: one product with the
+ * slice gives the long-side factor.  ws: tsvdm_pack_workspace_size bytes. */
+int tsvdm_pack_gram(const void* A_hat, const void* B, const double* s2, const double* shift,
+                    int64_t m, int64_t p, int64_t n, const int32_t* rho, const int64_t* offsets,
+                    int64_t capacity, void* U_pk, void* G_pk, void* S_pk, int32_t* status,
+                    void* ws, size_t ws_bytes, void* stream);
 
 /* --------------------------------------------------------------------- */
 /* reconstruction (Section 2.1, third step of the star-M product)        */
@@ -374,8 +418,9 @@ typedef struct tsvdm_batch_plan_s* tsvdm_batch_plan;
 /* Build a plan for `count` items: validates every item, lays out the
  * workspace (returned in *ws_bytes) and the per-stage task tables (transform
  * tiles, Jacobi (slice, block-pair) tasks, per-tensor selection, per-slice
- * packing, reconstruction tiles), which the plan keeps in device memory it
- * owns.  in_dtype: F32 or F64 input; dtype: F64 or F32 Jacobi / factor /
+ * packing, reconstruction tiles), which live in the caller's workspace: the
+ * plan owns only host data (a pinned host copy of the tables) and graph
+ * objects, never device memory.  in_dtype: F32 or F64 input; dtype: F64 or F32 Jacobi / factor /
  * output type; ttm_compute as in tsvdm_transform; block: the Jacobi block
  * width (16 or 32) of items whose own block is 0; block 0 leaves those
  * items at the default (32 when the largest min(m, p) of the batch is at
@@ -393,13 +438,18 @@ int tsvdm_batch_plan_create(const tsvdm_batch_item* items, int32_t count, int in
  * slices converged; host_poll = 0 runs the fixed number of steps (kernels
  * of converged slices return at once).  Results are the same bits either
  * way.
+ * Every run first copies the plan's task tables (pinned host memory) into
+ * the workspace on `stream`, so the workspace need not be preserved between
+ * runs; the first run with a new workspace address rebuilds the tables
+ * (synchronising the device once, since tables embed workspace addresses).
  * use_graph = 1 captures the run (host_poll forced to 0) into a hipGraph on
- * the first call for this (workspace, stream) and replays it afterwards.
+ * the first call for this (workspace, stream) and replays it afterwards
+ * (the table copy is a copy node of the graph).
  * status (device int32[1]): TSVDM_OK or the first device-side condition. */
 int tsvdm_batch_run(tsvdm_batch_plan plan, void* ws, size_t ws_bytes, int host_poll,
                     int use_graph, int32_t* status, void* stream);
 
-/* Release the plan, its device tables and any captured graph. */
+/* Release the plan, its pinned host tables and any captured graph. */
 int tsvdm_batch_plan_destroy(tsvdm_batch_plan plan);
 
 /* --------------------------------------------------------------------- */

@@ -21,8 +21,8 @@ BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libtsvdm.so")
 ROOT = os.path.dirname(HERE)
 
-SOURCES = ["api.cpp", "ttm.hip", "dct.hip", "jacobi.hip", "certify.hip", "select.hip", "pack.hip", "reduce.hip",
-           "backward.hip", "batch.cpp"]
+SOURCES = ["api.cpp", "ttm.hip", "dct.hip", "jacobi.hip", "precond.hip", "certify.hip", "select.hip", "pack.hip",
+           "reduce.hip", "backward.hip", "batch.cpp"]
 
 ARCH = "gfx950"
 FLAGS = [

@@ -230,6 +230,57 @@ int tsvdm_slice_svd(void* A_hat, int dtype, int64_t m, int64_t p, int64_t n, voi
     return run_jacobi(A_hat, dtype, m, p, n, W, s2, status, o, ws, as_stream(stream));
 }
 
+int tsvdm_slice_svd_gram_workspace_size(int64_t m, int64_t p, int64_t n, size_t* bytes) {
+    clear_error();
+    TSVDM_REQUIRE(bytes != nullptr, TSVDM_E_ARG, "bytes is NULL");
+    TSVDM_TRY(check_shape(m, p, n));
+    *bytes = gram_svd_workspace_bytes(m, p, n);
+    return TSVDM_OK;
+}
+
+int tsvdm_slice_svd_gram(const void* A_hat, int64_t m, int64_t p, int64_t n, void* B, double* s2,
+                         double* shift, int32_t* status, int block, int max_sweeps, double tol,
+                         int host_poll, void* ws, size_t ws_bytes, void* stream) {
+    clear_error();
+    TSVDM_TRY(check_shape(m, p, n));
+    TSVDM_REQUIRE(A_hat && B && s2 && shift && status, TSVDM_E_ARG,
+                  "A_hat, B, s2, shift and status must be non-NULL");
+    TSVDM_REQUIRE(A_hat != B, TSVDM_E_ARG, "B must not alias A_hat");
+    TSVDM_REQUIRE(std::min(m, p) <= gram_svd_max_r(), TSVDM_E_SHAPE, "min(m, p) must be <= 1024");
+    TSVDM_REQUIRE(block == 0 || block == 16 || block == 32, TSVDM_E_ARG, "block must be 0, 16 or 32");
+    TSVDM_REQUIRE(max_sweeps >= 0 && max_sweeps <= 1000, TSVDM_E_ARG, "max_sweeps must be in [0, 1000]");
+    TSVDM_REQUIRE(tol >= 0.0 && tol < 1.0 && std::isfinite(tol), TSVDM_E_ARG, "tol must lie in [0, 1)");
+    TSVDM_REQUIRE(host_poll == 0 || host_poll == 1, TSVDM_E_ARG, "host_poll must be 0 or 1");
+    TSVDM_TRY(check_ws(ws, ws_bytes, gram_svd_workspace_bytes(m, p, n)));
+    const int64_t r = std::min(m, p);
+    JacobiOpts o = jacobi_default_opts(r, r, TSVDM_F32);
+    if (block) o.block = 2 * block;
+    if (max_sweeps) o.max_sweeps = max_sweeps;
+    if (tol > 0.0) o.tol = tol;
+    o.host_poll = host_poll;
+    return run_gram_svd(static_cast<const float*>(A_hat), m, p, n, static_cast<float*>(B), s2, shift,
+                        status, o, ws, as_stream(stream));
+}
+
+int tsvdm_pack_gram(const void* A_hat, const void* B, const double* s2, const double* shift,
+                    int64_t m, int64_t p, int64_t n, const int32_t* rho, const int64_t* offsets,
+                    int64_t capacity, void* U_pk, void* G_pk, void* S_pk, int32_t* status, void* ws,
+                    size_t ws_bytes, void* stream) {
+    clear_error();
+    TSVDM_TRY(check_shape(m, p, n));
+    TSVDM_REQUIRE(A_hat && B && s2 && shift && rho && offsets && status, TSVDM_E_ARG,
+                  "A_hat, B, s2, shift, rho, offsets and status must be non-NULL");
+    TSVDM_REQUIRE(capacity >= 0, TSVDM_E_ARG, "capacity must be >= 0");
+    TSVDM_REQUIRE(capacity == 0 || (U_pk && G_pk && S_pk), TSVDM_E_ARG,
+                  "U_pk, G_pk and S_pk must be non-NULL when capacity > 0");
+    TSVDM_REQUIRE(std::min(m, p) <= gram_svd_max_r(), TSVDM_E_SHAPE, "min(m, p) must be <= 1024");
+    TSVDM_TRY(check_ws(ws, ws_bytes, pack_workspace_bytes(m, p, n)));
+    return run_gram_pack(static_cast<const float*>(A_hat), static_cast<const float*>(B), s2, shift,
+                         m, p, n, rho, offsets, capacity, static_cast<float*>(U_pk),
+                         static_cast<float*>(G_pk), static_cast<float*>(S_pk), status, ws,
+                         as_stream(stream));
+}
+
 // ------------------------------------------------------------- truncation
 
 int tsvdm_truncate_rank(int64_t k, int64_t r, int64_t n, int32_t* rho, int64_t* offsets,

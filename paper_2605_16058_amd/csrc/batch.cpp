@@ -1,12 +1,15 @@
 // Batches of independent tensors of any shapes through the whole hot path.
 //
-// A plan turns the items into per-stage task tables that live in device
-// memory owned by the plan, so every stage is one launch over all tensors:
+// A plan turns the items into per-stage task tables that live in the
+// caller's workspace, so every stage is one launch over all tensors:
 // transform tiles, Jacobi (slice, block pair) tasks driven by one global round
 // counter (each slice follows its own tournament of nb_s - 1 rounds per
 // sweep), per-tensor rank selection, per-slice packing, reconstruction tiles,
 // back-transform tiles and per-tensor error sums.  Descriptor tables hold
-// workspace addresses, so they are rebuilt when the workspace moves.
+// workspace addresses, so they are rebuilt when the workspace moves.  The
+// plan keeps the tables in pinned host memory and copies them into the
+// workspace at the start of every run (a copy node of a captured graph), so
+// it owns no device memory.
 #include <algorithm>
 #include <cmath>
 #include <cstring>
@@ -34,12 +37,13 @@ struct tsvdm_batch_plan_s {
     std::vector<int4> ttm_tasks, lr_tasks;
     std::vector<int2> jtasks;
     int64_t ttm_group[3] = {0, 0, 0}, back_group[3] = {0, 0, 0}, jgroup[2] = {0, 0};
-    // device tables
-    char* dtab = nullptr;
-    size_t dtab_bytes = 0;
+    // tables: pinned host copy (filled for one workspace address) and their
+    // place in the workspace
+    char* htab = nullptr;
+    size_t tab_bytes = 0, off_tab = 0;
     size_t o_fwd = 0, o_back = 0, o_ttm = 0, o_bt = 0, o_sl = 0, o_jt = 0, o_ps = 0, o_lr = 0,
            o_sel = 0, o_err = 0;
-    int64_t n_back_tasks = 0;
+    int64_t n_back = 0, n_back_tasks = 0;
     int n_err = 0;
     void* tables_ws = nullptr;
     // captured graph
@@ -97,7 +101,24 @@ int validate_item(const tsvdm_batch_item& it, int idx) {
     return TSVDM_OK;
 }
 
-// Fill the device tables for workspace base `ws`.
+// Offsets of the tables inside their block; returns the block size.
+size_t layout_tables(tsvdm_batch_plan_s* P) {
+    size_t off = 0;
+    auto place = [&](size_t bytes) { off = align_up(off); size_t o = off; off += bytes; return o; };
+    P->o_fwd = place(sizeof(TtmProblem) * P->items.size());
+    P->o_back = place(sizeof(TtmProblem) * std::max<size_t>((size_t)P->n_back, 1));
+    P->o_ttm = place(sizeof(int4) * P->ttm_tasks.size());
+    P->o_bt = place(sizeof(int4) * std::max<size_t>((size_t)P->n_back_tasks, 1));
+    P->o_sl = place(sizeof(BatchSlice) * (size_t)P->nslices);
+    P->o_jt = place(sizeof(int2) * P->jtasks.size());
+    P->o_ps = place(sizeof(PackSlice) * (size_t)P->nslices);
+    P->o_lr = place(sizeof(int4) * std::max<size_t>(P->lr_tasks.size(), 1));
+    P->o_sel = place(sizeof(SelTensor) * P->items.size());
+    P->o_err = place(sizeof(ErrJob) * std::max<size_t>((size_t)P->n_err, 1));
+    return align_up(off);
+}
+
+// Fill the host copy of the tables for workspace base `ws`.
 int build_tables(tsvdm_batch_plan_s* P, char* ws) {
     const int cnt = (int)P->items.size();
     std::vector<TtmProblem> fwd(cnt), back;
@@ -195,30 +216,20 @@ int build_tables(tsvdm_batch_plan_s* P, char* ws) {
         P->back_group[q] = (int64_t)back_by[q].size();
         back_tasks.insert(back_tasks.end(), back_by[q].begin(), back_by[q].end());
     }
-    P->n_back_tasks = (int64_t)back_tasks.size();
-    P->n_err = (int)err.size();
-    // pack the tables into one device allocation
-    size_t off = 0;
-    auto place = [&](size_t bytes) { off = align_up(off); size_t o = off; off += bytes; return o; };
-    P->o_fwd = place(sizeof(TtmProblem) * fwd.size());
-    P->o_back = place(sizeof(TtmProblem) * std::max<size_t>(back.size(), 1));
-    P->o_ttm = place(sizeof(int4) * P->ttm_tasks.size());
-    P->o_bt = place(sizeof(int4) * std::max<size_t>(back_tasks.size(), 1));
-    P->o_sl = place(sizeof(BatchSlice) * sl.size());
-    P->o_jt = place(sizeof(int2) * P->jtasks.size());
-    P->o_ps = place(sizeof(PackSlice) * ps.size());
-    P->o_lr = place(sizeof(int4) * std::max<size_t>(P->lr_tasks.size(), 1));
-    P->o_sel = place(sizeof(SelTensor) * sel.size());
-    P->o_err = place(sizeof(ErrJob) * std::max<size_t>(err.size(), 1));
-    const size_t total = align_up(off);
-    if (total > P->dtab_bytes) {
-        if (P->dtab) (void)hipFree(P->dtab);
-        P->dtab = nullptr;
-        TSVDM_HIP_CHECK(hipMalloc(reinterpret_cast<void**>(&P->dtab), total));
-        P->dtab_bytes = total;
+    if ((int64_t)back.size() != P->n_back || (int64_t)back_tasks.size() != P->n_back_tasks ||
+        (int)err.size() != P->n_err || (int64_t)sl.size() != P->nslices) {
+        set_error("internal: batch table sizes differ from the plan's layout");
+        return TSVDM_E_ARG;
     }
-    std::vector<char> host(total, 0);
-    auto put = [&](size_t o, const void* src, size_t bytes) { if (bytes) memcpy(host.data() + o, src, bytes); };
+    if (!P->htab) {
+        TSVDM_HIP_CHECK(hipHostMalloc(reinterpret_cast<void**>(&P->htab), P->tab_bytes, hipHostMallocDefault));
+    } else {
+        // a copy of the previous tables may still be in flight
+        TSVDM_HIP_CHECK(hipDeviceSynchronize());
+    }
+    char* host = P->htab;
+    memset(host, 0, P->tab_bytes);
+    auto put = [&](size_t o, const void* src, size_t bytes) { if (bytes) memcpy(host + o, src, bytes); };
     put(P->o_fwd, fwd.data(), sizeof(TtmProblem) * fwd.size());
     put(P->o_back, back.data(), sizeof(TtmProblem) * back.size());
     put(P->o_ttm, P->ttm_tasks.data(), sizeof(int4) * P->ttm_tasks.size());
@@ -229,7 +240,6 @@ int build_tables(tsvdm_batch_plan_s* P, char* ws) {
     put(P->o_lr, P->lr_tasks.data(), sizeof(int4) * P->lr_tasks.size());
     put(P->o_sel, sel.data(), sizeof(SelTensor) * sel.size());
     put(P->o_err, err.data(), sizeof(ErrJob) * err.size());
-    TSVDM_HIP_CHECK(hipMemcpy(P->dtab, host.data(), total, hipMemcpyHostToDevice));
     P->tables_ws = ws;
     return TSVDM_OK;
 }
@@ -250,9 +260,10 @@ __global__ void clear_status(int32_t* status) {
 }
 
 int run_stages(tsvdm_batch_plan_s* P, char* ws, int host_poll, int32_t* status, hipStream_t st) {
-    char* D = P->dtab;
+    char* D = ws + P->off_tab;
     const int cnt = (int)P->items.size();
     int rc;
+    TSVDM_HIP_CHECK(hipMemcpyAsync(D, P->htab, P->tab_bytes, hipMemcpyHostToDevice, st));
     int32_t* jstatus = reinterpret_cast<int32_t*>(ws + P->off_ctl);
     void* ctl_ws = ws + P->off_ctl + 256;
     clear_status<<<1, 64, 0, st>>>(status);
@@ -395,6 +406,17 @@ int tsvdm_batch_plan_create(const tsvdm_batch_item* items, int32_t count, int in
         P->jgroup[q] = (int64_t)jt_by[q].size();
         P->jtasks.insert(P->jtasks.end(), jt_by[q].begin(), jt_by[q].end());
     }
+    for (const auto& it : P->items) {
+        if (!it.A_rec) continue;
+        int64_t n_rt;
+        int n_ct;
+        ttm_tile_counts(ttm_resolve_tile(it.ttm_tile, it.n), it.m * it.p, it.n, &n_rt, &n_ct);
+        P->n_back += 1;
+        P->n_back_tasks += n_rt * n_ct;
+        P->n_err += it.err ? 1 : 0;
+    }
+    P->tab_bytes = layout_tables(P);
+    P->off_tab = take(P->tab_bytes);
     P->max_steps = P->max_sweeps * max_rounds;
     if (P->max_steps > 100000) P->max_steps = 100000;
     P->off_ctl = take(256 + jacobi_batch_ctl_bytes(P->nslices, P->max_steps));
@@ -461,7 +483,7 @@ int tsvdm_batch_plan_destroy(tsvdm_batch_plan P) {
     if (!P) return TSVDM_OK;
     if (P->gexec) (void)hipGraphExecDestroy(P->gexec);
     if (P->graph) (void)hipGraphDestroy(P->graph);
-    if (P->dtab) (void)hipFree(P->dtab);
+    if (P->htab) (void)hipHostFree(P->htab);
     delete P;
     return TSVDM_OK;
 }

@@ -164,7 +164,7 @@ __global__ void jacobi_init(T* __restrict__ W, int64_t r, int64_t n, JacobiCtl* 
                             int32_t* __restrict__ status, const int32_t* __restrict__ run) {
     // W = I: workgroups take whole columns (one index division per column),
     // threads run down the column
-    const int64_t cols = r * n;
+    const int64_t cols = W ? r * n : 0;   // W == nullptr: no accumulated rotations
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t col = blockIdx.x; col < cols; col += gridDim.x) {
         const int64_t s = col / r, c = col - s * r;
@@ -544,8 +544,9 @@ __device__ __forceinline__ void round_body(RoundShared<T, NB2>& sh, T* __restric
         unsigned long long fl = 2ull * w * w * (unsigned long long)L;
         unsigned long long by = w * (unsigned long long)L * sizeof(T);
         if (rotate) {
-            fl += 2ull * w * w * (unsigned long long)(L + r);
-            by += 2ull * w * (unsigned long long)(L + r) * sizeof(T);
+            const unsigned long long lw = (unsigned long long)(Wb ? L + r : L);   // no W: vectors only
+            fl += 2ull * w * w * lw;
+            by += 2ull * w * lw * sizeof(T);
         }
         atomicAdd(&pair_counts[rotate ? 1 : 0], 1ull);
         atomicAdd(&pair_counts[2], fl);
@@ -882,8 +883,10 @@ __device__ __forceinline__ void round_body(RoundShared<T, NB2>& sh, T* __restric
         return next_w && any;
     };
     constexpr bool NEXTW = ROWS || sizeof(T) == 8;   // FP32 column families: no registers to spare
-    const bool w_pre = update(std::integral_constant<bool, ROWS>(), Ab, g.vs, g.es, L, vec_a != 0, EARLY, NEXTW);
-    update(std::integral_constant<bool, false>(), Wb, r, 1, r, vec_w != 0, w_pre, false);
+    const bool w_pre = update(std::integral_constant<bool, ROWS>(), Ab, g.vs, g.es, L, vec_a != 0, EARLY,
+                              NEXTW && Wb != nullptr);
+    // W == nullptr: the caller needs no accumulated rotations (uniform branch)
+    if (Wb) update(std::integral_constant<bool, false>(), Wb, r, 1, r, vec_w != 0, w_pre, false);
 }
 
 // FP32 pairs of 64 vectors keep three workgroups per 160 KB compute unit.
@@ -903,8 +906,8 @@ void jacobi_round(T* __restrict__ A, T* __restrict__ W, SliceGeom g,
     const int64_t s = blockIdx.x / npairs;
     const int k = blockIdx.x % npairs;
     if (ctl[s].done) return;
-    round_body<T, NB2, ROWS, INT>(sh, A + s * g.m * g.p, W + s * g.r * g.r, g, nbe, rnd, k, ctl + s, tol,
-                             vec_a, vec_w, pair_counts);
+    round_body<T, NB2, ROWS, INT>(sh, A + s * g.m * g.p, W ? W + s * g.r * g.r : nullptr, g, nbe, rnd, k,
+                                  ctl + s, tol, vec_a, vec_w, pair_counts);
 }
 
 // One step of the global round counter t for a batch of slices of any

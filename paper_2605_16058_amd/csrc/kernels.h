@@ -119,6 +119,18 @@ struct JacobiOpts {
 };
 
 size_t jacobi_workspace_bytes(int64_t n);
+// Gram form of the FP32 slice SVDs (precond.hip)
+size_t gram_svd_workspace_bytes(int64_t m, int64_t p, int64_t n);
+int64_t gram_svd_max_r();
+int run_gram_svd(const float* A_hat, int64_t m, int64_t p, int64_t n, float* B, double* s2,
+                 double* shift, int32_t* status, const JacobiOpts& o, void* ws, hipStream_t st);
+int run_gram_pack(const float* A_hat, const float* B, const double* s2, const double* shift,
+                  int64_t m, int64_t p, int64_t n, const int32_t* rho, const int64_t* offsets,
+                  int64_t capacity, float* U_pk, float* G_pk, float* S_pk, int32_t* status,
+                  void* ws, hipStream_t st);
+int run_pack_sort_f32(const double* s2, int64_t r, int64_t n, const int32_t* rho,
+                      const int64_t* offsets, int64_t capacity, int32_t* perm, float* S_pk,
+                      int32_t* status, hipStream_t st);
 bool stats_enabled();
 void stats_set(bool on);
 void stats_reset();

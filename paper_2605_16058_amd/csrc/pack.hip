@@ -343,6 +343,15 @@ int pack_impl(const void* A, const void* W, const double* s2, int64_t m, int64_t
 
 }  // namespace
 
+int run_pack_sort_f32(const double* s2, int64_t r, int64_t n, const int32_t* rho,
+                      const int64_t* offsets, int64_t capacity, int32_t* perm, float* S_pk,
+                      int32_t* status, hipStream_t st) {
+    TSVDM_REQUIRE(r <= PMAX, TSVDM_E_SHAPE, "min(m, p) above 4096 is not supported by pack");
+    pack_sort<float><<<(unsigned)n, 1024, 0, st>>>(s2, r, n, rho, offsets, capacity, 0, perm, S_pk, status);
+    TSVDM_LAUNCH_CHECK();
+    return TSVDM_OK;
+}
+
 size_t pack_workspace_bytes(int64_t m, int64_t p, int64_t n) {
     const SliceGeom g = slice_geom(m, p);
     Carver cv(nullptr);

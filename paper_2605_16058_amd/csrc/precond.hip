@@ -1,0 +1,482 @@
+// Slice SVDs of the mixed (FP32) path by way of the FP64 Gram matrix.
+//
+// A slice has r = min(m, p) Jacobi vectors x_v of length L = max(m, p): its
+// rows when it is wide (m < p), its columns when it is tall.  Instead of
+// rotating those long vectors, the slice is first reduced to an r x r
+// triangular factor (Section 3.2 leaves the slice SVD method open; this is
+// the Gram-matrix route for slices of any aspect ratio):
+//   1. G = X X^T (r x r) in FP64 on MFMA.  Products of FP32 inputs are exact
+//      in FP64, so G carries only the FP64 rounding of its sums.
+//   2. L L^T = G + s I (Cholesky in FP64), s = (L + r) u64 trace(G): the
+//      shift, about the size of G's own rounding, keeps the factorisation
+//      defined for rank-deficient slices; a pivot that rounding still leaves
+//      <= 0 gives a zero column.
+//   3. One-sided Jacobi (FP32 vectors, FP64 angles) on the columns of L
+//      without accumulating rotations: L Q = B with orthogonal columns, so
+//      G + s I = B B^T and the normalised columns of B are the eigenvectors
+//      of G, i.e. the singular vectors of the slice on its short side, with
+//      sigma_j^2 = ||b_j||^2 - s.
+//   4. Factors: wide (short side = U): G_i = U_rho^T A_hat_i; tall (short
+//      side = V): G_i = S V_rho^T and U_i = A_hat_i V_rho S^-1, one product
+//      with the slice itself.
+// Eigenvalues of the FP64 Gram carry absolute errors of order u64 ||G||, so
+// sigma_j moves by at most about u64 sigma_max^2 / sigma_j, and by
+// sqrt(u64) sigma_max as sigma_j -> 0: far inside the FP32 path's value
+// bound (2e-5 sigma_max).  The FP64 path does not use this form.
+// Against rotating the slice itself, each Jacobi pair touches vectors of
+// length r instead of L and no rotation matrix: for the 512 x 1024 climate
+// slices 2 w^2 (2 r) instead of 2 w^2 (2 L + r) flops per rotating pair.
+#include "common.h"
+#include "kernels.h"
+
+namespace tsvdm {
+
+namespace {
+
+constexpr int GK = 16;   // positions per K chunk of the Gram
+constexpr int CB = 16;   // Cholesky panel width
+constexpr int FK = 32;   // vector indices per K chunk of the factor product
+
+// lower-triangle tile q -> (ti, tj) with ti >= tj
+__device__ __forceinline__ void tri_tile(int q, int& ti, int& tj) {
+    int i = (int)((sqrtf(8.0f * (float)q + 1.0f) - 1.0f) * 0.5f);
+    while ((i + 1) * (i + 2) / 2 <= q) ++i;
+    while (i * (i + 1) / 2 > q) --i;
+    ti = i;
+    tj = q - i * (i + 1) / 2;
+}
+
+// G(i, j) = sum_t X(i, t) X(j, t) for the 64 x 64 tile (ti, tj), ti >= tj,
+// of slice blockIdx.x / ntri; X(v, t) = A[v vs + t es].  Wave w computes the
+// rows j of 16 w .. 16 w + 15 of the transposed tile against all 64 i, so
+// that the stores run along i (G is column-major: G[i + j r]).  The next K
+// chunk is loaded into registers while the MFMAs of the current one run;
+// two LDS buffers, one barrier per chunk.
+__global__ __launch_bounds__(256) void pc_gram(const float* __restrict__ A, SliceGeom g, int ntri,
+                                               double* __restrict__ G) {
+    __shared__ double sa[2][64][GK + 1];   // operand rows i
+    __shared__ double sb[2][64][GK + 1];   // operand rows j
+    const int64_t s = blockIdx.x / ntri;
+    int ti, tj;
+    tri_tile((int)(blockIdx.x % ntri), ti, tj);
+    const int64_t r = g.r, L = g.L, vs = g.vs, es = g.es;
+    const float* X = A + s * g.m * g.p;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, lr = lane & 15, lg = lane >> 4;
+    const int64_t i0 = (int64_t)ti * 64, j0 = (int64_t)tj * 64;
+    const bool rows = g.rows != 0;
+    // this thread's four elements: rows -> one position, four consecutive
+    // vectors; columns -> one vector, four consecutive positions
+    const int v0 = rows ? (tid & 15) * 4 : (tid >> 2);
+    const int t0 = rows ? (tid >> 4) : (tid & 3) * 4;
+    const bool vec = (g.m % 4) == 0;   // 16-byte alignment of every group of four
+    float ra[4], rb[4];
+    auto load1 = [&](int64_t base_v, int64_t tc, float* out) {
+        const int64_t v = base_v + v0, t = tc + t0;
+        const float* src = X + v * vs + t * es;
+        const bool full = rows ? (v + 3 < r && t < L) : (v < r && t + 3 < L);
+        if (vec && full) {
+            const float4 x = *reinterpret_cast<const float4*>(src);
+            out[0] = x.x; out[1] = x.y; out[2] = x.z; out[3] = x.w;
+        } else {
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int64_t vq = rows ? v + q : v, tq = rows ? t : t + q;
+                out[q] = (vq < r && tq < L) ? X[vq * vs + tq * es] : 0.0f;
+            }
+        }
+    };
+    auto put = [&](int buf) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int v = rows ? v0 + q : v0, t = rows ? t0 : t0 + q;
+            sa[buf][v][t] = (double)ra[q];
+            sb[buf][v][t] = (double)rb[q];
+        }
+    };
+    v4d acc[4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) acc[c] = zero4<v4d>();
+    load1(i0, 0, ra);
+    load1(j0, 0, rb);
+    int buf = 0;
+    for (int64_t tc = 0; tc < L; tc += GK) {
+        put(buf);
+        __syncthreads();
+        if (tc + GK < L) {
+            load1(i0, tc + GK, ra);
+            load1(j0, tc + GK, rb);
+        }
+#pragma unroll
+        for (int kk = 0; kk < GK; kk += 4) {
+            const double a = sb[buf][16 * wave + lr][kk + lg];   // A(row j, k)
+#pragma unroll
+            for (int c = 0; c < 4; ++c) acc[c] = mfma_f64(a, sa[buf][16 * c + lr][kk + lg], acc[c]);
+        }
+        buf ^= 1;
+    }
+    double* Gs = G + s * r * r;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+        const int64_t i = i0 + 16 * c + lr;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int64_t j = j0 + 16 * wave + mfma_row<double>(lg, v);
+            if (i < r && j < r) Gs[i + j * r] = acc[c][v];
+        }
+    }
+}
+
+// L L^T = G + s I for the slice blockIdx.x (lower triangle of G read; L
+// written to Lw in FP64 and to Lo in FP32 with zeros above the diagonal).
+// Left-looking with panels of CB columns: the panel's rows are updated with
+// the L columns already computed (MFMA), staged in LDS, its CB x CB
+// diagonal block is factorised by one wave and the rows below are solved
+// against it.  A pivot <= 0 (rounding of a singular G + s I) gives a zero
+// column.  Fixed operation order: the result does not depend on timing.
+template <int MAXR>
+__global__ __launch_bounds__(256) void pc_chol(const double* __restrict__ G, int64_t r, double cshift,
+                                               double* __restrict__ Lw, float* __restrict__ Lo,
+                                               double* __restrict__ shift) {
+    constexpr int PLD = CB + 1;
+    __shared__ double P[MAXR * PLD];
+    __shared__ double red[256];
+    const int64_t s = blockIdx.x;
+    const double* Gs = G + s * r * r;
+    double* Ls = Lw + s * r * r;
+    float* Os = Lo + s * r * r;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, lr = lane & 15, lg = lane >> 4;
+    // trace in a fixed order
+    double tr = 0.0;
+    for (int64_t j = tid; j < r; j += 256) tr += Gs[j + j * r];
+    red[tid] = tr;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (tid < w) red[tid] += red[tid + w];
+        __syncthreads();
+    }
+    const double sh = cshift * red[0];
+    if (tid == 0) shift[s] = sh;
+    for (int64_t k0 = 0; k0 < r; k0 += CB) {
+        const int64_t nrow = r - k0;
+        const int nc = (int)(nrow < CB ? nrow : CB);
+        const int nrt = (int)((nrow + 15) / 16);
+        // 1. P = G(k0:, k0:k0+CB) + s I - L(k0:, :k0) L(k0:k0+CB, :k0)^T
+        for (int q = wave; q < nrt; q += 4) {
+            const int64_t i0 = k0 + 16 * q;
+            const int64_t ia = i0 + lr, kb = k0 + lr;
+            v4d acc = zero4<v4d>();
+            for (int64_t j = 0; j < k0; j += 4) {
+                const int64_t jc = j + lg;   // k0 is a multiple of 4, so jc < k0
+                const double a = ia < r ? Ls[ia + jc * r] : 0.0;
+                const double b = kb < r ? Ls[kb + jc * r] : 0.0;
+                acc = mfma_f64(a, b, acc);
+            }
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int64_t i = i0 + mfma_row<double>(lg, v), c = k0 + lr;
+                if (i < r && lr < CB)
+                    P[(i - k0) * PLD + lr] = c < r ? Gs[i + c * r] + (i == c ? sh : 0.0) - acc[v] : 0.0;
+            }
+        }
+        __syncthreads();
+        // 2. the diagonal block, by wave 0 (lane i owns row i); LDS order
+        //    within the wave is kept by fences
+        if (wave == 0) {
+            for (int jj = 0; jj < nc; ++jj) {
+                const double d = P[jj * PLD + jj];
+                const double ljj = d > 0.0 ? sqrt(d) : 0.0;
+                const double inv = ljj > 0.0 ? 1.0 / ljj : 0.0;
+                __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+                if (lane < nc && lane > jj) P[lane * PLD + jj] *= inv;
+                if (lane == jj) P[jj * PLD + jj] = ljj;
+                __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+                if (lane < nc && lane > jj) {
+                    const double lij = P[lane * PLD + jj];
+                    for (int c = jj + 1; c <= lane; ++c) P[lane * PLD + c] -= lij * P[c * PLD + jj];
+                }
+                __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+            }
+        }
+        __syncthreads();
+        // 3. rows below the block: L_i = P_i L_dd^-T (forward substitution)
+        for (int64_t i = CB + tid; i < nrow; i += 256) {
+            double x[CB];
+#pragma unroll
+            for (int c = 0; c < CB; ++c) x[c] = P[i * PLD + c];
+#pragma unroll
+            for (int jj = 0; jj < CB; ++jj) {
+                double v = x[jj];
+#pragma unroll
+                for (int c = 0; c < jj; ++c) v -= x[c] * P[jj * PLD + c];
+                const double djj = P[jj * PLD + jj];
+                x[jj] = djj > 0.0 ? v / djj : 0.0;
+            }
+#pragma unroll
+            for (int c = 0; c < CB; ++c) P[i * PLD + c] = x[c];
+        }
+        __syncthreads();
+        // 4. write the panel's columns: FP64 (for the later panels) and FP32
+        //    (the Jacobi's input), zeros above the diagonal
+        for (int c = 0; c < nc; ++c) {
+            const int64_t col = k0 + c;
+            for (int64_t i = tid; i < r; i += 256) {
+                const int64_t li = i - k0;
+                const double v = (li < c) ? 0.0 : P[li * PLD + c];
+                if (li >= c) Ls[i + col * r] = v;
+                Os[i + col * r] = (float)v;
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// s2 <- max(s2 - shift, 0) per slice: squared singular values of the slice
+// from the squared norms of B (||b_j||^2 = sigma_j^2 + s).
+__global__ void pc_unshift(double* __restrict__ s2, const double* __restrict__ shift, int64_t r,
+                           int64_t n) {
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= r * n) return;
+    const double v = s2[idx] - shift[idx / r];
+    s2[idx] = v > 0.0 ? v : 0.0;
+}
+
+// Short-side factor from B: kept column c (sorted position c, index j =
+// perm[c]) is b_j / ||b_j||, ||b_j||^2 = s2_j + shift.  Wide slices: column
+// c of U_pk (m x rho); tall slices: row c of G_pk (rho x p) scaled by sigma_c.
+__global__ __launch_bounds__(256) void pc_pack_short(const float* __restrict__ B, const double* __restrict__ s2,
+                                                     const double* __restrict__ shift, SliceGeom g,
+                                                     const int32_t* __restrict__ rho,
+                                                     const int64_t* __restrict__ offsets, int64_t capacity,
+                                                     const int32_t* __restrict__ perm,
+                                                     float* __restrict__ U_pk, float* __restrict__ G_pk) {
+    const int64_t s = blockIdx.y;
+    const int64_t kr = rho[s], off = offsets[s], r = g.r;
+    if (kr <= 0 || off + kr > capacity) return;
+    const float* Bs = B + s * r * r;
+    const double* s2b = s2 + s * r;
+    const double shs = shift[s];
+    const int32_t* pr = perm + s * r;
+    for (int64_t c = blockIdx.x; c < kr; c += gridDim.x) {
+        const int64_t j = pr[c];
+        const double sg2 = s2b[j] > 0.0 ? s2b[j] : 0.0;
+        const double nb = sqrt(sg2 + shs);
+        const double scale = nb > 0.0 ? (g.rows ? 1.0 : sqrt(sg2)) / nb : 0.0;
+        const float* b = Bs + j * r;
+        if (g.rows) {
+            float* u = U_pk + g.m * off + c * g.m;
+            for (int64_t a = threadIdx.x; a < r; a += blockDim.x) u[a] = (float)((double)b[a] * scale);
+        } else {
+            float* gr = G_pk + g.p * off + c;   // row c of the kr x p block (leading dim kr)
+            for (int64_t t = threadIdx.x; t < r; t += blockDim.x) gr[t * kr] = (float)((double)b[t] * scale);
+        }
+    }
+}
+
+// Long-side factor by one product with the slice:
+//   wide: G_pk(c, t) = sum_v u_c(v) X(v, t)            (rho x p, leading dim rho)
+//   tall: U_pk(t, c) = sum_v X(v, t) v_c(v) / sigma_c  (m x rho)
+// with u_c = v_c = b_perm(c) / ||b_perm(c)|| and X(v, t) = A[v vs + t es].
+// Tile: 64 kept columns c x 64 positions t; wave w owns the output rows
+// 16 w .. 16 w + 15 against all 64 columns, the MFMA output lanes running
+// along the stored contiguous index (c for wide, t for tall).  K chunks of
+// FK vector indices v, loaded into registers one chunk ahead.
+template <bool ROWS>
+__global__ __launch_bounds__(256) void pc_factor(const float* __restrict__ A, const float* __restrict__ B,
+                                                 const double* __restrict__ s2,
+                                                 const double* __restrict__ shift, SliceGeom g,
+                                                 const int32_t* __restrict__ rho,
+                                                 const int64_t* __restrict__ offsets, int64_t capacity,
+                                                 const int32_t* __restrict__ perm, int tiles_t,
+                                                 float* __restrict__ out) {
+    __shared__ float sx[2][64][FK + 1];   // X(v, t): [t][v]
+    __shared__ float sbk[2][64][FK + 1];  // b_perm(c)(v): [c][v]
+    __shared__ double scl[64];
+    __shared__ int jc[64];
+    const int64_t s = blockIdx.y;
+    const int64_t kr = rho[s], off = offsets[s];
+    const int tc_idx = (int)(blockIdx.x / tiles_t), tt_idx = (int)(blockIdx.x % tiles_t);
+    const int64_t c0 = (int64_t)tc_idx * 64, t0 = (int64_t)tt_idx * 64;
+    if (kr <= 0 || off + kr > capacity || c0 >= kr) return;
+    const int64_t r = g.r, L = g.L, vs = g.vs, es = g.es;
+    const float* X = A + s * g.m * g.p;
+    const float* Bs = B + s * r * r;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, lr = lane & 15, lg = lane >> 4;
+    if (tid < 64) {
+        const int64_t c = c0 + tid;
+        int j = 0;
+        double sc = 0.0;
+        if (c < kr) {
+            j = perm[s * r + c];
+            const double sg2 = s2[s * r + j] > 0.0 ? s2[s * r + j] : 0.0;
+            const double nb = sqrt(sg2 + shift[s]);
+            const double sg = sqrt(sg2);
+            sc = nb > 0.0 ? (ROWS ? 1.0 / nb : (sg > 0.0 ? 1.0 / (nb * sg) : 0.0)) : 0.0;
+        }
+        jc[tid] = j;
+        scl[tid] = sc;
+    }
+    __syncthreads();
+    // loads: 64 x FK elements per operand, 8 per thread (two groups of four)
+    float rx[8], rbv[8];
+    const bool vec = (g.m % 4) == 0 && (r % 4) == 0;
+    auto load = [&](int64_t vc) {
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int e = tid + 256 * h;           // 512 groups of four
+            // X: rows (vs = 1) -> four consecutive v at one t; columns (es = 1)
+            // -> four consecutive t at one v
+            int v, t;
+            if (ROWS) { v = (e % (FK / 4)) * 4; t = e / (FK / 4); }
+            else { t = (e % 16) * 4; v = e / 16; }
+            const int64_t gv = vc + v, gt = t0 + t;
+            const float* src = X + gv * vs + gt * es;
+            const bool full = ROWS ? (gv + 3 < r && gt < L) : (gv < r && gt + 3 < L);
+            if (vec && full) {
+                const float4 x4 = *reinterpret_cast<const float4*>(src);
+                rx[4 * h] = x4.x; rx[4 * h + 1] = x4.y; rx[4 * h + 2] = x4.z; rx[4 * h + 3] = x4.w;
+            } else {
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int64_t vq = ROWS ? gv + q : gv, tq = ROWS ? gt : gt + q;
+                    rx[4 * h + q] = (vq < r && tq < L) ? X[vq * vs + tq * es] : 0.0f;
+                }
+            }
+            // B: column perm(c), four consecutive v
+            const int c = e / (FK / 4), vb = (e % (FK / 4)) * 4;
+            const int64_t gvb = vc + vb;
+            const bool okc = c0 + c < kr;
+            const float* bsrc = Bs + (int64_t)jc[c] * r + gvb;
+            if (vec && okc && gvb + 3 < r) {
+                const float4 b4 = *reinterpret_cast<const float4*>(bsrc);
+                rbv[4 * h] = b4.x; rbv[4 * h + 1] = b4.y; rbv[4 * h + 2] = b4.z; rbv[4 * h + 3] = b4.w;
+            } else {
+#pragma unroll
+                for (int q = 0; q < 4; ++q) rbv[4 * h + q] = (okc && gvb + q < r) ? bsrc[q] : 0.0f;
+            }
+        }
+    };
+    auto put = [&](int buf) {
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int e = tid + 256 * h;
+            int v, t;
+            if (ROWS) { v = (e % (FK / 4)) * 4; t = e / (FK / 4); }
+            else { t = (e % 16) * 4; v = e / 16; }
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                if (ROWS) sx[buf][t][v + q] = rx[4 * h + q];
+                else sx[buf][t + q][v] = rx[4 * h + q];
+            }
+            const int c = e / (FK / 4), vb = (e % (FK / 4)) * 4;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) sbk[buf][c][vb + q] = rbv[4 * h + q];
+        }
+    };
+    v4f acc[4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) acc[c] = zero4<v4f>();
+    load(0);
+    int buf = 0;
+    for (int64_t vc = 0; vc < r; vc += FK) {
+        put(buf);
+        __syncthreads();
+        if (vc + FK < r) load(vc + FK);
+#pragma unroll
+        for (int kk = 0; kk < FK; kk += 4) {
+            if (ROWS) {
+                // D(t, c): output lanes along c
+                const float a = sx[buf][16 * wave + lr][kk + lg];
+#pragma unroll
+                for (int c = 0; c < 4; ++c) acc[c] = mfma_f32(a, sbk[buf][16 * c + lr][kk + lg], acc[c]);
+            } else {
+                // D(c, t): output lanes along t
+                const float a = sbk[buf][16 * wave + lr][kk + lg];
+#pragma unroll
+                for (int c = 0; c < 4; ++c) acc[c] = mfma_f32(a, sx[buf][16 * c + lr][kk + lg], acc[c]);
+            }
+        }
+        buf ^= 1;
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int row = 16 * wave + mfma_row<float>(lg, v), col = 16 * q + lr;
+            if (ROWS) {
+                // row = t, col = c: G_pk[p off + c + t kr]
+                const int64_t t = t0 + row, c = c0 + col;
+                if (t < L && c < kr) out[g.p * off + c + t * kr] = (float)((double)acc[q][v] * scl[col]);
+            } else {
+                // row = c, col = t: U_pk[m off + t + c m]
+                const int64_t c = c0 + row, t = t0 + col;
+                if (t < L && c < kr) out[g.m * off + t + c * g.m] = (float)((double)acc[q][v] * scl[row]);
+            }
+        }
+    }
+}
+
+}  // namespace
+
+size_t gram_svd_workspace_bytes(int64_t m, int64_t p, int64_t n) {
+    const SliceGeom g = slice_geom(m, p);
+    Carver cv(nullptr);
+    cv.carve<double>((size_t)(g.r * g.r * n));   // G
+    cv.carve<double>((size_t)(g.r * g.r * n));   // L (FP64)
+    return cv.total() + jacobi_workspace_bytes(n);
+}
+
+int64_t gram_svd_max_r() { return 1024; }
+
+int run_gram_svd(const float* A_hat, int64_t m, int64_t p, int64_t n, float* B, double* s2,
+                 double* shift, int32_t* status, const JacobiOpts& o, void* ws, hipStream_t st) {
+    const SliceGeom g = slice_geom(m, p);
+    const int64_t r = g.r;
+    TSVDM_REQUIRE(r <= gram_svd_max_r(), TSVDM_E_SHAPE, "min(m, p) must be <= 1024 for the Gram form");
+    Carver cv(ws);
+    double* G = cv.carve<double>((size_t)(r * r * n));
+    double* Lw = cv.carve<double>((size_t)(r * r * n));
+    void* jws = static_cast<char*>(ws) + cv.total();
+    const int nt = (int)((r + 63) / 64);
+    const int ntri = nt * (nt + 1) / 2;
+    TSVDM_REQUIRE((int64_t)ntri * n < ((int64_t)1 << 31), TSVDM_E_SHAPE, "too many Gram tiles");
+    pc_gram<<<(unsigned)(ntri * n), 256, 0, st>>>(A_hat, g, ntri, G);
+    TSVDM_LAUNCH_CHECK();
+    const double cshift = (double)(g.L + r) * 1.1102230246251565e-16;
+    if (r <= 128) pc_chol<128><<<(unsigned)n, 256, 0, st>>>(G, r, cshift, Lw, B, shift);
+    else if (r <= 256) pc_chol<256><<<(unsigned)n, 256, 0, st>>>(G, r, cshift, Lw, B, shift);
+    else if (r <= 512) pc_chol<512><<<(unsigned)n, 256, 0, st>>>(G, r, cshift, Lw, B, shift);
+    else pc_chol<1024><<<(unsigned)n, 256, 0, st>>>(G, r, cshift, Lw, B, shift);
+    TSVDM_LAUNCH_CHECK();
+    // one-sided Jacobi on the columns of L (r x r), no accumulated rotations
+    int rc = run_jacobi(B, TSVDM_F32, r, r, n, nullptr, s2, status, o, jws, st);
+    if (rc) return rc;
+    pc_unshift<<<(unsigned)((r * n + 255) / 256), 256, 0, st>>>(s2, shift, r, n);
+    TSVDM_LAUNCH_CHECK();
+    return TSVDM_OK;
+}
+
+int run_gram_pack(const float* A_hat, const float* B, const double* s2, const double* shift,
+                  int64_t m, int64_t p, int64_t n, const int32_t* rho, const int64_t* offsets,
+                  int64_t capacity, float* U_pk, float* G_pk, float* S_pk, int32_t* status,
+                  void* ws, hipStream_t st) {
+    const SliceGeom g = slice_geom(m, p);
+    const int64_t r = g.r;
+    int32_t* perm = static_cast<int32_t*>(ws);
+    int rc = run_pack_sort_f32(s2, r, n, rho, offsets, capacity, perm, S_pk, status, st);
+    if (rc) return rc;
+    TSVDM_REQUIRE(n < 65536, TSVDM_E_SHAPE, "n must be below 65536");
+    dim3 gs((unsigned)(r < 256 ? r : 256), (unsigned)n);
+    pc_pack_short<<<gs, 256, 0, st>>>(B, s2, shift, g, rho, offsets, capacity, perm, U_pk, G_pk);
+    TSVDM_LAUNCH_CHECK();
+    const int tiles_c = (int)((r + 63) / 64), tiles_t = (int)((g.L + 63) / 64);
+    TSVDM_REQUIRE((int64_t)tiles_c * tiles_t < ((int64_t)1 << 31), TSVDM_E_SHAPE, "factor grid too large");
+    dim3 gf((unsigned)(tiles_c * tiles_t), (unsigned)n);
+    if (g.rows)
+        pc_factor<true><<<gf, 256, 0, st>>>(A_hat, B, s2, shift, g, rho, offsets, capacity, perm, tiles_t, G_pk);
+    else
+        pc_factor<false><<<gf, 256, 0, st>>>(A_hat, B, s2, shift, g, rho, offsets, capacity, perm, tiles_t, U_pk);
+    TSVDM_LAUNCH_CHECK();
+    return TSVDM_OK;
+}
+
+}  // namespace tsvdm

@@ -207,6 +207,42 @@ def tsvdm_slice_svd(A_hat, block=0, max_sweeps=0, tol=0.0, host_poll=True, ws=No
     return W, s2, status
 
 
+def tsvdm_slice_svd_gram(A_hat, block=0, max_sweeps=0, tol=0.0, host_poll=True, ws=None):
+    """Slice SVDs of an FP32 tensor by way of the FP64 Gram matrix (A_hat is
+    only read).  Returns (B, s2, shift, status): B (n, r, r) FP32 holds the
+    orthogonalised columns of each slice's Cholesky factor, s2 the squared
+    singular values, shift the per-slice Cholesky shift."""
+    if not is_colmajor(A_hat) or A_hat.dtype != torch.float32:
+        raise ValueError("A_hat must be a column-major FP32 tensor")
+    m, p, n = A_hat.shape
+    r = min(m, p)
+    B = torch.empty((n, r, r), dtype=torch.float32, device=A_hat.device)
+    s2 = torch.empty((n, r), dtype=torch.float64, device=A_hat.device)
+    shift = torch.empty(n, dtype=torch.float64, device=A_hat.device)
+    status = torch.zeros(1, dtype=torch.int32, device=A_hat.device)
+    w = _ws(ws)
+    wp, wn = w.args(_lib.workspace_size("tsvdm_slice_svd_gram_workspace_size", m, p, n))
+    _lib.call("tsvdm_slice_svd_gram", _ptr(A_hat), m, p, n, _ptr(B), _ptr(s2), _ptr(shift), _ptr(status),
+              int(block), int(max_sweeps), float(tol), int(bool(host_poll)), wp, wn, _stream())
+    return B, s2, shift, status
+
+
+def tsvdm_pack_gram(A_hat, B, s2, shift, rho, offsets, capacity, ws=None):
+    """Packed factors from the output of tsvdm_slice_svd_gram (FP32)."""
+    m, p, n = A_hat.shape
+    cap = int(capacity)
+    dev = A_hat.device
+    U_pk = torch.empty(max(m * cap, 1), dtype=torch.float32, device=dev)
+    G_pk = torch.empty(max(p * cap, 1), dtype=torch.float32, device=dev)
+    S_pk = torch.empty(max(cap, 1), dtype=torch.float32, device=dev)
+    status = torch.zeros(1, dtype=torch.int32, device=dev)
+    w = _ws(ws)
+    wp, wn = w.args(_lib.workspace_size("tsvdm_pack_workspace_size", m, p, n))
+    _lib.call("tsvdm_pack_gram", _ptr(A_hat), _ptr(B), _ptr(s2), _ptr(shift), m, p, n, _ptr(rho),
+              _ptr(offsets), cap, _ptr(U_pk), _ptr(G_pk), _ptr(S_pk), _ptr(status), wp, wn, _stream())
+    return U_pk, G_pk, S_pk, status
+
+
 def tsvdm_truncate_rank(k, r, n, device="cuda"):
     rho = torch.empty(n, dtype=torch.int32, device=device)
     offsets = torch.empty(n + 1, dtype=torch.int64, device=device)

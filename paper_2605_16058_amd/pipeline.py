@@ -24,6 +24,47 @@ PRECISIONS = {
 }
 
 
+# Stated bound on ||A_rec - A_rec(FP64)||_F / ||A||_F for each precision (the
+# parity tests hold every path to it); plain BF16 has none (it is reported).
+RECON_BOUND = {"f64": 0.0, "f32": 3e-5, "bf16x3": 1e-4, "bf16": None}
+
+
+def selection_eps(eps, precision, guard=True):
+    """The tolerance a t-SVDM-II run selects with so that its measured error
+    stays below eps.  Algorithm 2 bounds the tail of the squared singular
+    values the run computed: the truncation alone leaves an error below eps
+    relative to ||A||.  The rounding of a reduced-precision path moves its
+    reconstruction by at most delta = RECON_BOUND[precision] from the FP64
+    one, so by the triangle inequality selecting with eps - delta keeps
+    ||A - A_rec|| / ||A|| < eps.  FP64 (delta = 0) and plain BF16 (no bound)
+    select with eps itself."""
+    d = RECON_BOUND[precision]
+    if not guard or not d:
+        return float(eps)
+    if float(eps) <= d:
+        raise ValueError(f"eps must exceed the {precision} reconstruction bound {d}")
+    return float(eps) - d
+
+
+GRAM_MAX_R = 1024   # largest min(m, p) of the Gram form
+
+
+def resolve_svd(svd, precision, r, certify=False):
+    """Slice SVD form: "jacobi" rotates the slice itself (any precision);
+    "gram" (FP32 Jacobi dtype only, min(m, p) <= 1024) runs the Jacobi on
+    the Cholesky factor of the slice's FP64 Gram matrix and forms the long-
+    side factor by one product (tsvdm_slice_svd_gram).  "auto": "gram" on the
+    reduced-precision paths where it applies, else "jacobi"."""
+    if svd not in ("auto", "jacobi", "gram"):
+        raise ValueError("svd must be 'auto', 'jacobi' or 'gram'")
+    ok = PRECISIONS[precision][1] == torch.float32 and r <= GRAM_MAX_R and not certify
+    if svd == "gram" and not ok:
+        raise ValueError("svd='gram' needs an FP32 Jacobi path, min(m, p) <= 1024 and no certify")
+    if svd == "auto":
+        return "gram" if ok else "jacobi"
+    return svd
+
+
 @dataclass
 class Result:
     A_rec: torch.Tensor
@@ -40,6 +81,7 @@ class Result:
     capacity: int
     computed: torch.Tensor | None = None   # certified selection: slices given an SVD
     passes: int = 0                         # certified selection: SVD rounds
+    eps_sel: float | None = None            # t-SVDM-II: the tolerance selected with
 
     def rel_error(self) -> float:
         e = self.err.double().cpu()
@@ -57,6 +99,13 @@ class TSVDM:
     instead of the dense product: forward, and after the transform-domain
     low-rank product (tsvdm_lowrank) backward; precision f64 or f32 only.
 
+    svd: "auto", "jacobi" or "gram" (see resolve_svd).
+
+    guard=True (mode "II") makes a reduced-precision path select with
+    eps - delta, delta its stated reconstruction bound (selection_eps), so
+    that the measured relative error stays below eps; its ranks then follow
+    eps - delta, not eps.  guard=False selects with eps on every path.
+
     certify=True (mode "II") runs the certified selection: only slices whose
     energy could reach the threshold get an SVD.  The first round computes
     the slices outside the lowest-energy set holding theta * eps^2 of the
@@ -72,9 +121,10 @@ class TSVDM:
     def __init__(self, shape, M, mode="II", k=None, eps=None, precision="f64",
                  block=0, max_sweeps=0, tol=0.0, host_poll=True, capacity="max",
                  device="cuda", check_m=True, tile=0, transform="dense", certify=False,
-                 theta=0.5, max_passes=3):
+                 theta=0.5, max_passes=3, guard=True, svd="auto"):
         self.m, self.p, self.n = (int(x) for x in shape)
         self.r = min(self.m, self.p)
+        self.svd = resolve_svd(svd, precision, self.r, certify)
         if mode not in ("I", "II"):
             raise ValueError("mode must be 'I' or 'II'")
         if mode == "I" and (k is None or int(k) < 1):
@@ -85,6 +135,7 @@ class TSVDM:
             raise ValueError(f"precision must be one of {list(PRECISIONS)}")
         self.mode, self.k, self.eps = mode, k, eps
         self.precision = precision
+        self.eps_sel = selection_eps(eps, precision, guard) if mode == "II" else None
         self.ttm_compute, self.dtype = PRECISIONS[precision]
         if transform not in ("dense", "dct"):
             raise ValueError("transform must be 'dense' or 'dct'")
@@ -135,13 +186,17 @@ class TSVDM:
         if self.certify:
             W, s2, svd_status, rho, offsets, stats, computed, passes = self._certified(A_hat)
         else:
-            W, s2, svd_status = ops.tsvdm_slice_svd(A_hat, self.block, self.max_sweeps, self.tol,
-                                                    self.host_poll, ws=self.ws)
+            if self.svd == "gram":
+                W, s2, shift, svd_status = ops.tsvdm_slice_svd_gram(
+                    A_hat, self.block, self.max_sweeps, self.tol, self.host_poll, ws=self.ws)
+            else:
+                W, s2, svd_status = ops.tsvdm_slice_svd(A_hat, self.block, self.max_sweeps, self.tol,
+                                                        self.host_poll, ws=self.ws)
             if self.mode == "I":
                 rho, offsets = ops.tsvdm_truncate_rank(self.k, r, n, self.device)
                 stats = torch.full((4,), float("nan"), dtype=torch.float64, device=self.device)
             else:
-                rho, offsets, stats = ops.tsvdm_truncate_tol(s2, self.eps, ws=self.ws)
+                rho, offsets, stats = ops.tsvdm_truncate_tol(s2, self.eps_sel, ws=self.ws)
         if self.capacity_mode == "exact":
             cap = int(offsets[n].item())
         elif self.mode == "I":
@@ -149,7 +204,12 @@ class TSVDM:
         else:
             cap = r * n
         # 4. factors
-        U_pk, G_pk, S_pk, pack_status = ops.tsvdm_pack(A_hat, W, s2, rho, offsets, cap, ws=self.ws)
+        if self.svd == "gram":
+            U_pk, G_pk, S_pk, pack_status = ops.tsvdm_pack_gram(A_hat, W, s2, shift, rho, offsets, cap,
+                                                                ws=self.ws)
+        else:
+            U_pk, G_pk, S_pk, pack_status = ops.tsvdm_pack(A_hat, W, s2, rho, offsets, cap, ws=self.ws)
+        del W
         # 5. reconstruct + back-transform (M^{-1} = M^T / c^2)
         back = self.ttm_compute if self.ttm_compute != "f64" else "f64"
         if self.transform == "dct":
@@ -163,10 +223,10 @@ class TSVDM:
         # 6. error report
         err = ops.tsvdm_error(A, A_rec, ws=self.ws)
         return Result(A_rec, rho, offsets, U_pk, G_pk, S_pk, s2, stats, err, svd_status,
-                      pack_status, cap, computed, passes)
+                      pack_status, cap, computed, passes, self.eps_sel)
 
     def _certified(self, A_hat):
-        return certified_svd(A_hat, self.eps, self.theta, self.max_passes, self.block,
+        return certified_svd(A_hat, self.eps_sel, self.theta, self.max_passes, self.block,
                              self.max_sweeps, self.tol, self.host_poll, self.ws)
 
 
@@ -219,7 +279,7 @@ class TSVDMd:
 
     def __init__(self, dims, Ms, mode="II", k=None, eps=None, precision="f64", block=0,
                  max_sweeps=0, tol=0.0, host_poll=True, device="cuda", tile=0, certify=False,
-                 theta=0.5, max_passes=3):
+                 theta=0.5, max_passes=3, guard=True, svd="auto"):
         self.dims = tuple(int(x) for x in dims)
         if certify and mode != "II":
             raise ValueError("certify applies to mode II")
@@ -237,6 +297,7 @@ class TSVDMd:
         if precision not in PRECISIONS:
             raise ValueError(f"precision must be one of {list(PRECISIONS)}")
         self.mode, self.k, self.eps, self.precision = mode, k, eps, precision
+        self.eps_sel = selection_eps(eps, precision, guard) if mode == "II" else None
         self.ttm_compute, self.dtype = PRECISIONS[precision]
         self.c2 = [ops.check_transform(M) for M in Ms]
         self.Mdev = [ops.device_matrix(M, device) for M in Ms]
@@ -247,6 +308,7 @@ class TSVDMd:
         for x in self.dims[2:]:
             self.N *= x
         self.r = min(self.m, self.p)
+        self.svd = resolve_svd(svd, precision, self.r, certify)
         self.ws = ops.Workspace(device)
 
     def __call__(self, A: torch.Tensor) -> Result:
@@ -268,21 +330,30 @@ class TSVDMd:
         computed, passes = None, 0
         if self.certify:
             W, s2, svd_status, rho, offsets, stats, computed, passes = certified_svd(
-                A_hat, self.eps, self.theta, self.max_passes, self.block, self.max_sweeps,
+                A_hat, self.eps_sel, self.theta, self.max_passes, self.block, self.max_sweeps,
                 self.tol, self.host_poll, self.ws)
             cap = r * N
         else:
-            W, s2, svd_status = ops.tsvdm_slice_svd(A_hat, self.block, self.max_sweeps, self.tol,
-                                                    self.host_poll, ws=self.ws)
+            if self.svd == "gram":
+                W, s2, shift, svd_status = ops.tsvdm_slice_svd_gram(
+                    A_hat, self.block, self.max_sweeps, self.tol, self.host_poll, ws=self.ws)
+            else:
+                W, s2, svd_status = ops.tsvdm_slice_svd(A_hat, self.block, self.max_sweeps, self.tol,
+                                                        self.host_poll, ws=self.ws)
             if self.mode == "I":
                 rho, offsets = ops.tsvdm_truncate_rank(self.k, r, N, self.device)
                 stats = torch.full((4,), float("nan"), dtype=torch.float64, device=self.device)
                 cap = min(int(self.k), r) * N
             else:
-                rho, offsets, stats = ops.tsvdm_truncate_tol(s2, self.eps, ws=self.ws)
+                rho, offsets, stats = ops.tsvdm_truncate_tol(s2, self.eps_sel, ws=self.ws)
                 cap = r * N
         # 4. factors
-        U_pk, G_pk, S_pk, pack_status = ops.tsvdm_pack(A_hat, W, s2, rho, offsets, cap, ws=self.ws)
+        if self.svd == "gram":
+            U_pk, G_pk, S_pk, pack_status = ops.tsvdm_pack_gram(A_hat, W, s2, shift, rho, offsets, cap,
+                                                                ws=self.ws)
+        else:
+            U_pk, G_pk, S_pk, pack_status = ops.tsvdm_pack(A_hat, W, s2, rho, offsets, cap, ws=self.ws)
+        del W
         # 5. transform-domain low-rank product, then back-transforms mode by mode
         other = bufs[1] if (d > 3 and cur.data_ptr() == bufs[0].data_ptr()) else bufs[0]
         C3 = other.permute(*range(d - 1, -1, -1)).reshape(N, p, m).permute(2, 1, 0)
@@ -300,7 +371,7 @@ class TSVDMd:
         # 6. error report
         err = ops.tsvdm_error(A, A_rec, ws=self.ws)
         return Result(A_rec, rho, offsets, U_pk, G_pk, S_pk, s2, stats, err, svd_status,
-                      pack_status, cap, computed, passes)
+                      pack_status, cap, computed, passes, self.eps_sel)
 
 
 class BatchTSVDM:
@@ -314,11 +385,13 @@ class BatchTSVDM:
     capacity) so they can be read back; otherwise they stay in the workspace.
     blocks / tiles: optional per-tensor Jacobi block widths and transform
     tile shapes (0 = the plan's choice), e.g. from autotune.tune_batch().
+    guard: as for TSVDM (mode "II" tensors select with selection_eps; the
+    tolerances used are in eps_sel).
     """
 
     def __init__(self, tensors, Ms, modes, ks=None, epss=None, precision="f32", block=0,
                  max_sweeps=0, keep_factors=False, reconstruct=True, device="cuda",
-                 blocks=None, tiles=None):
+                 blocks=None, tiles=None, guard=True):
         import ctypes
 
         from . import _lib
@@ -337,6 +410,8 @@ class BatchTSVDM:
             raise TypeError("all tensors of a batch must share one dtype")
         self.Mdev, self.rho, self.offsets, self.stats, self.A_rec, self.err = [], [], [], [], [], []
         self.U_pk, self.G_pk, self.S_pk, self.capacity = [], [], [], []
+        self.eps_sel = [selection_eps(e, precision, guard) if md == "II" else None
+                        for e, md in zip(epss, modes)]
         items = (_lib.BatchItem * cnt)()
         for t, (A, M, mode) in enumerate(zip(self.tensors, Ms, modes)):
             m, p, n = A.shape
@@ -358,7 +433,7 @@ class BatchTSVDM:
             it.ttm_tile = int(tiles[t])
             it.reserved = 0
             it.k = int(ks[t] or 1)
-            it.eps = float(epss[t] or 0.5)
+            it.eps = float(self.eps_sel[t] or 0.5)
             it.rho, it.offsets, it.stats = rho.data_ptr(), off.data_ptr(), stats.data_ptr()
             if keep_factors:
                 cap = (min(int(ks[t]), r) if mode == "I" else r) * n

@@ -151,6 +151,45 @@ def test_slice_svd_matches_oracle(ops, shape, dtype, block):
         assert np.allclose(vec_norm2, s2n[i], rtol=1e-12 if fp64 else 1e-5, atol=1e-300)
 
 
+# The FP32 path's Gram form: FP64 Gram, shifted Cholesky, Jacobi on the
+# factor's columns without accumulated rotations.  Its values carry the FP64
+# Gram's absolute error (about u64 sigma_max^2 / sigma) on top of the FP32
+# Jacobi's, so the FP32 value bound 2e-5 sigma_max applies unchanged.
+@pytest.mark.parametrize("shape", [(64, 48, 4), (48, 64, 4), (100, 37, 3), (37, 100, 3),
+                                   (300, 200, 2), (5, 1, 3), (1, 6, 2), (129, 129, 2),
+                                   (400, 720, 2), (720, 400, 1), (256, 384, 2), (384, 256, 2)])
+@pytest.mark.parametrize("block", [16, 32])
+def test_slice_svd_gram_matches_oracle(ops, shape, block):
+    m, p, n = shape
+    r = min(m, p)
+    g = np.random.default_rng(7 * m + p)
+    A = g.standard_normal(shape) * np.logspace(0, -4, p)[None, :, None]
+    if n >= 2:
+        A[:, :, 1] = 0.0                                          # zero slice
+    if n >= 3 and r >= 2:
+        A[:, :, 2] = np.outer(g.standard_normal(m), g.standard_normal(p))   # rank one
+    A = A.astype(np.float32).astype(np.float64)
+    Ad = to_dev(A, torch.float32)
+    B, s2, shift, st = ops.tsvdm_slice_svd_gram(Ad, block=block)
+    torch.cuda.synchronize()
+    assert int(st.item()) == 0
+    assert torch.equal(Ad, to_dev(A, torch.float32))             # the slices are only read
+    _U, S, _V = O.slice_svd(A)
+    s2n, Bn, shn = to_np(s2), to_np(B), to_np(shift)
+    for i in range(n):
+        smax = S[0, i]
+        assert np.max(np.abs(_sorted_sigma(s2n[i]) - S[:, i])) <= 2e-5 * smax + 1e-30
+        # the shift is (L + r) u64 trace(G) and the columns of B are orthogonal
+        assert abs(shn[i] - (max(m, p) + r) * 2.0 ** -53 * np.sum(S[:, i] ** 2)) <= 1e-6 * shn[i] + 1e-300
+        Bi = Bn[i].T                                              # column-major r x r
+        nb = np.sqrt(np.sum(Bi * Bi, axis=0))
+        ok = nb > 0
+        if ok.any():
+            Q = Bi[:, ok] / nb[ok]
+            assert np.max(np.abs(Q.T @ Q - np.eye(int(ok.sum())))) <= 2e-5 * max(1, r) ** 0.5
+        assert np.allclose(nb ** 2, np.maximum(s2n[i], 0) + shn[i], rtol=1e-5, atol=2 * shn[i] + 1e-300)
+
+
 def test_slice_svd_status_and_host_poll_equivalence(ops):
     A = np.random.default_rng(3).standard_normal((80, 60, 3))
     a1 = to_dev(A)
@@ -317,27 +356,67 @@ def test_tsvdm_ii_climate_fp64(ops, eps):
     _check_factors(res, ref, m, p, n, True)
 
 
-@pytest.mark.parametrize("precision,bound", [("f32", 3e-5), ("bf16x3", 5e-5), ("bf16", 2e-2)])
+@pytest.mark.parametrize("precision,bound", [("f32", 3e-5), ("bf16x3", 1e-4), ("bf16", 2e-2)])
 def test_tsvdm_ii_turbulence_mixed(ops, precision, bound):
-    """Mixed precision: the stated bound is on the reconstruction against
-    the oracle's, relative to ||A||; the error against A must stay below
-    eps up to that bound, and ranks differ from the oracle's only where
-    the perturbed squares cross the threshold."""
-    from paper_2605_16058_amd.pipeline import tsvdm
+    """Mixed precision: the stated bound (pipeline.RECON_BOUND; plain BF16:
+    2e-2, reported only) is on the reconstruction against the oracle's
+    truncation at the GPU's own ranks, relative to ||A||, asserted whatever
+    the ranks.  With the guard the path selects with eps - bound, and its
+    error against A stays below eps itself; the ranks differ from the
+    oracle's at that tolerance only where the perturbed squares cross the
+    threshold (sum |drho| printed)."""
+    from paper_2605_16058_amd.pipeline import RECON_BOUND, tsvdm
     w = synth.workload("turbulence", small=True)
     A = w.A.astype(np.float64)
     eps = 0.1
     res = tsvdm(to_dev(w.A, torch.float32), w.M, mode="II", eps=eps, precision=precision)
     torch.cuda.synchronize()
-    ref = O.tsvdm_ii(A, w.M, eps)
     assert int(res.svd_status.item()) == 0
-    d = rel(to_np(res.A_rec), ref["A_rec"]) * np.linalg.norm(ref["A_rec"]) / np.linalg.norm(A)
-    drho = int(np.abs(res.rho.cpu().numpy() - ref["rho"]).sum())
-    print(f"{precision}: |A_rec - A_rec_oracle|/|A| = {d:.3e}, sum|drho| = {drho}, "
-          f"rel_err = {res.rel_error():.6e} (oracle {ref['rel_error']:.6e})")
-    assert res.rel_error() < eps * (1 + bound)
-    if precision != "bf16":
-        assert d <= bound * 10 or drho > 0
+    if RECON_BOUND[precision]:
+        assert res.eps_sel == eps - RECON_BOUND[precision]
+    ref = O.tsvdm_ii(A, w.M, res.eps_sel)
+    rho = res.rho.cpu().numpy()
+    at_rho = O.reconstruct(O.truncated_factors(ref["U"], ref["S"], ref["V"], rho), w.M, A.shape)
+    d = rel(to_np(res.A_rec), at_rho) * np.linalg.norm(at_rho) / np.linalg.norm(A)
+    drho = int(np.abs(rho - ref["rho"]).sum())
+    print(f"{precision}: |A_rec - A_rec_oracle(rho)|/|A| = {d:.3e}, sum|drho| = {drho}, "
+          f"rel_err = {res.rel_error():.6e} (oracle {ref['rel_error']:.6e}, eps_sel {res.eps_sel})")
+    assert d <= bound
+    if RECON_BOUND[precision]:
+        assert res.rel_error() < eps
+
+
+@pytest.mark.parametrize("mode,arg", [("I", 5), ("II", 0.05)])
+@pytest.mark.parametrize("shape", [(70, 50, 9), (40, 90, 7)])
+def test_tsvdm_gram_form_matches_oracle(ops, mode, arg, shape):
+    """The FP32 path in its Gram form (the default for FP32) against the
+    oracle's truncation at the GPU's own ranks, within the FP32 bound, and
+    against the FP32 path that rotates the slices themselves."""
+    from paper_2605_16058_amd.pipeline import tsvdm
+    m, p, n = shape
+    g = np.random.default_rng(m * p)
+    A = g.standard_normal(shape) + 5.0 * np.einsum("a,b,c->abc", g.standard_normal(m), g.standard_normal(p),
+                                                   g.standard_normal(n))
+    A = A.astype(np.float32).astype(np.float64)
+    M = synth.haar_orthogonal(n, g)
+    kw = {"k": arg} if mode == "I" else {"eps": arg}
+    X = to_dev(A, torch.float32)
+    gr = tsvdm(X, M, mode=mode, precision="f32", svd="gram", **kw)
+    jc = tsvdm(X, M, mode=mode, precision="f32", svd="jacobi", **kw)
+    torch.cuda.synchronize()
+    for res in (gr, jc):
+        assert int(res.svd_status.item()) == 0 and int(res.pack_status.item()) == 0
+    ref = O.tsvdm_i(A, M, arg) if mode == "I" else O.tsvdm_ii(A, M, gr.eps_sel)
+    rho = gr.rho.cpu().numpy()
+    at_rho = O.reconstruct(O.truncated_factors(ref["U"], ref["S"], ref["V"], rho), M, A.shape)
+    nA = np.linalg.norm(A)
+    d = rel(to_np(gr.A_rec), at_rho) * np.linalg.norm(at_rho) / nA
+    print(f"gram form {shape} {mode}: |A_rec - oracle(rho)|/|A| = {d:.3e}, "
+          f"sum |drho| vs jacobi form {int(np.abs(rho - jc.rho.cpu().numpy()).sum())}")
+    assert d <= 3e-5
+    if mode == "II":
+        assert gr.rel_error() < arg
+    _check_factors(gr, {"S": ref["S"]}, m, p, n, False)
 
 
 def test_zero_tensor_and_degenerate_shapes(ops):
@@ -375,8 +454,24 @@ def test_pack_capacity_overflow_is_reported(ops):
 # adjoint
 # ---------------------------------------------------------------------------
 
-@pytest.mark.parametrize("dtype,bound", [(torch.float64, 1e-9), (torch.float32, 2e-4)])
-def test_backward_matches_oracle(ops, dtype, bound):
+def gradient_bounds(A, L_o, GM_o, delta, u):
+    """Relative bounds on dA and dM derived from the reconstruction bound
+    delta of the path (||A_k - A_k,oracle|| <= delta ||A||):
+      dA = 2 (A - A_k)          => |ddA| / |dA| <= delta |A| / |A - A_k| + u,
+      dM = 2 R_(3) A_(3)^T      => |ddM| <= 2 (delta |A| + sqrt(mp) u |R|) |A|,
+    with |A - A_k| = |R| = sqrt(L) and sqrt(mp) u the rounding of the
+    product's length-mp sums (random-walk model), u the unit roundoff."""
+    m, p, _n = A.shape
+    nA = float(np.linalg.norm(A.ravel()))
+    nR = math.sqrt(L_o)
+    b_dA = delta * nA / nR + u
+    b_dM = 2 * (delta * nA + math.sqrt(m * p) * u * nR) * nA / float(np.linalg.norm(GM_o))
+    return b_dA, b_dM
+
+
+@pytest.mark.parametrize("dtype,bound,delta", [(torch.float64, 1e-9, 1e-10),
+                                               (torch.float32, 2e-4, 3e-5)])
+def test_backward_matches_oracle(ops, dtype, bound, delta):
     w = synth.workload("cayley", small=True)
     A = w.A.astype(np.float64)
     K = w.extra["K0"]
@@ -386,9 +481,12 @@ def test_backward_matches_oracle(ops, dtype, bound):
     torch.cuda.synchronize()
     assert int(st.item()) == 0
     L_o, dA_o, GM_o = O.trunc_loss_grad(A, M, k)
+    b_dA, b_dM = gradient_bounds(A, L_o, GM_o, delta, 2.0 ** (-53 if dtype == torch.float64 else -24))
+    e_dA, e_dM = rel(to_np(dA), dA_o), rel(dM.cpu().numpy(), GM_o)
+    print(f"{dtype}: dA {e_dA:.3e} (bound {b_dA:.3e}), dM {e_dM:.3e} (bound {b_dM:.3e})")
     assert abs(float(loss.item()) - L_o) <= bound * L_o
-    assert rel(to_np(dA), dA_o) <= bound * 10
-    assert rel(dM.cpu().numpy(), GM_o) <= bound * 10
+    assert e_dA <= b_dA
+    assert e_dM <= b_dM
 
 
 def test_autograd_function(ops):
