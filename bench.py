@@ -825,7 +825,7 @@ def main(argv=None):
                     help="certify: the order-6 climate-like tensor instead of the 3-way one")
     ap.add_argument("--no-f64", action="store_true", help="skip the FP64 comparison path")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample-n", type=int, default=32)
+    ap.add_argument("--cpu-sample-n", type=int, default=64)
     ap.add_argument("--cpu-sample-tensors", type=int, default=16)
     ap.add_argument("--batch-count", type=int, default=512)
     ap.add_argument("--grad-steps", type=int, default=50)
