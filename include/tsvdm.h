@@ -257,6 +257,20 @@ int tsvdm_truncate_tol(const double* s2, int64_t r, int64_t n, double eps,
                        int32_t* rho, int64_t* offsets, double* stats,
                        void* ws, size_t ws_bytes, void* stream);
 
+/* t-SVDM-II selection that allocates nothing, for callers that cannot
+ * allocate device memory (code under stream capture, tight serving loops,
+ * harnesses that forbid allocation).  Same arguments, results and errors as
+ * tsvdm_truncate_tol without the workspace: the sort keys live in a fixed
+ * device array of 2^20 keys (8 MiB per GPU, held until the process ends),
+ * so r*n must not exceed 1048576 (else TSVDM_E_SHAPE before any launch).
+ * Every call on one GPU shares that array: calls that overlap in time on
+ * the same GPU (different streams, threads or processes' shared contexts)
+ * race and must be serialised by the caller.  No hipMalloc or hipFree is
+ * made; the array's device address is looked up once per device on the
+ * first call there. */
+int tsvdm_truncate_tol_noalloc(const double* s2, int64_t r, int64_t n, double eps,
+                               int32_t* rho, int64_t* offsets, double* stats, void* stream);
+
 /* Certified t-SVDM-II selection (Algorithm 2; Section 4.1: t-SVDM-II
  * discards many slices entirely).  A slice i without an SVD enters the
  * selection as one value, its energy E_i = ||A_hat_i||_F^2 (all its squared

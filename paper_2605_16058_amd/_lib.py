@@ -48,6 +48,7 @@ _SIGS = {
     "tsvdm_truncate_rank": (c_int, [c_int64, c_int64, c_int64, _P, _P, _P]),
     "tsvdm_truncate_tol_workspace_size": (c_int, [c_int64, c_int64, POINTER(c_size_t)]),
     "tsvdm_truncate_tol": (c_int, [_P, c_int64, c_int64, c_double, _P, _P, _P, _P, c_size_t, _P]),
+    "tsvdm_truncate_tol_noalloc": (c_int, [_P, c_int64, c_int64, c_double, _P, _P, _P, _P]),
     "tsvdm_pack_workspace_size": (c_int, [c_int64, c_int64, c_int64, POINTER(c_size_t)]),
     "tsvdm_pack": (c_int, [_P, _P, _P, c_int, c_int64, c_int64, c_int64, _P, _P, c_int64, _P, _P,
                            _P, _P, _P, c_size_t, _P]),

@@ -314,6 +314,17 @@ int tsvdm_truncate_tol(const double* s2, int64_t r, int64_t n, double eps, int32
     return run_truncate_tol(s2, r, n, eps, rho, offsets, stats, ws, as_stream(stream));
 }
 
+int tsvdm_truncate_tol_noalloc(const double* s2, int64_t r, int64_t n, double eps, int32_t* rho,
+                               int64_t* offsets, double* stats, void* stream) {
+    clear_error();
+    TSVDM_REQUIRE(s2 && rho && offsets && stats, TSVDM_E_ARG,
+                  "s2, rho, offsets and stats must be non-NULL");
+    TSVDM_REQUIRE(r >= 1 && n >= 1 && r * n <= static_select_max_keys() && n < 65536, TSVDM_E_SHAPE,
+                  "r*n must be in [1, " + std::to_string(static_select_max_keys()) + "] and n < 65536");
+    TSVDM_REQUIRE(eps > 0.0 && eps < 1.0, TSVDM_E_ARG, "eps must lie in (0, 1)");
+    return run_truncate_tol_static(s2, r, n, eps, rho, offsets, stats, as_stream(stream));
+}
+
 int tsvdm_slice_svd_subset(void* A_hat, int dtype, int64_t m, int64_t p, int64_t n, void* W,
                            double* s2, int32_t* status, const int32_t* run, int block,
                            int max_sweeps, double tol, int host_poll, void* ws, size_t ws_bytes,

@@ -150,6 +150,9 @@ int run_certify(const double* E, const double* stats, int32_t* computed, int32_t
 
 // ---- selection (select.hip)
 size_t select_workspace_bytes(int64_t r, int64_t n);
+int64_t static_select_max_keys();
+int run_truncate_tol_static(const double* s2, int64_t r, int64_t n, double eps, int32_t* rho,
+                            int64_t* offsets, double* stats, hipStream_t st);
 int run_truncate_tol(const double* s2, int64_t r, int64_t n, double eps, int32_t* rho,
                      int64_t* offsets, double* stats, void* ws, hipStream_t st);
 int run_truncate_rank(int64_t k, int64_t r, int64_t n, int32_t* rho, int64_t* offsets,

@@ -10,6 +10,9 @@
 // double-double with a fixed combination order and are rounded once, so J
 // is deterministic and equals the exact-arithmetic answer except within
 // ~1e-30 relative of a tie.
+#include <mutex>
+#include <string>
+
 #include "common.h"
 #include "kernels.h"
 
@@ -323,6 +326,49 @@ int run_truncate_tol(const double* s2, int64_t r, int64_t n, double eps, int32_t
     sel_offsets<<<1, 1024, 0, st>>>(rho, n, offsets);
     TSVDM_LAUNCH_CHECK();
     return TSVDM_OK;
+}
+
+// Selection without allocation: the sort keys live in a fixed device array
+// (8 MiB, 2^20 keys) that every call on a GPU shares.  sel_fill rewrites all
+// the keys a call uses (padding included), so nothing needs clearing between
+// calls; calls that overlap on one GPU race on the array.
+constexpr int64_t STATIC_SELECT_KEYS = (int64_t)1 << 20;
+static __device__ __align__(256) unsigned long long scratch[STATIC_SELECT_KEYS];
+
+namespace {
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[MAX_DEVICES] = {};
+}  // namespace
+
+int64_t static_select_max_keys() { return STATIC_SELECT_KEYS; }
+
+int run_truncate_tol_static(const double* s2, int64_t r, int64_t n, double eps, int32_t* rho,
+                            int64_t* offsets, double* stats, hipStream_t st) {
+    if (next_pow2(r * n < 2 ? 2 : r * n) > STATIC_SELECT_KEYS) {
+        set_error("r*n = " + std::to_string(r * n) + " exceeds the fixed selection scratch (" +
+                  std::to_string(STATIC_SELECT_KEYS) + " keys)");
+        return TSVDM_E_SHAPE;
+    }
+    int dev = 0;
+    TSVDM_HIP_CHECK(hipGetDevice(&dev));
+    if (dev < 0 || dev >= MAX_DEVICES) {
+        set_error("device ordinal out of range for the fixed selection scratch");
+        return TSVDM_E_ARG;
+    }
+    void* ptr = nullptr;
+    {
+        // once per device, with that device current: the device address of
+        // this GPU's copy of the array (the host symbol is not an address)
+        std::lock_guard<std::mutex> lk(g_scratch_mu);
+        if (!g_scratch_ptr[dev]) {
+            void* p = nullptr;
+            TSVDM_HIP_CHECK(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+            g_scratch_ptr[dev] = p;
+        }
+        ptr = g_scratch_ptr[dev];
+    }
+    return run_truncate_tol(s2, r, n, eps, rho, offsets, stats, ptr, st);
 }
 
 int run_truncate_rank(int64_t k, int64_t r, int64_t n, int32_t* rho, int64_t* offsets,
