@@ -39,7 +39,7 @@ def log(msg):
 
 def kernel_src_sha():
     h = hashlib.sha256()
-    for f in ("jacobi.hip", "common.h"):
+    for f in ("jacobi.hip", "precond.hip", "angle.h", "common.h"):
         with open(os.path.join(ROOT, "paper_2605_16058_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -326,7 +326,7 @@ def bench_climate(a, torch, lib):
     ch = tune_single(a, Ad, M, a.precision, tuned, tf)
     op_mix = TSVDM((m, p, n), M, mode="II", eps=a.eps, precision=a.precision, block=ch[0],
                    tile=ch[1], transform=tf)
-    log(f"mixed ({a.precision}) warmup {a.warmup}, steps {a.steps}; selects with eps {op_mix.eps_sel}")
+    log(f"mixed ({a.precision}) warmup {a.warmup}, steps {a.steps}; guard {op_mix.guard}")
     for _ in range(a.warmup):
         op_mix(Ad)
     lib.tsvdm_stats_reset()
@@ -400,7 +400,8 @@ def bench_climate(a, torch, lib):
         "data": "synthetic",
         "config": {"workload": f"climate-like {m}x{p}x{n} FP32, DCT-II"
                                f"{' (FFT)' if tf == 'dct' else ''}, t-SVDM-II tol {a.eps}",
-                   "m": m, "p": p, "n": n, "eps": a.eps, "eps_selected": op_mix.eps_sel,
+                   "m": m, "p": p, "n": n, "eps": a.eps, "eps_selected": res_mix.eps_sel,
+                   "guard": op_mix.guard, "selections": res_mix.selections,
                    "precision": a.precision, "transform": tf, "autotune": tuned},
         "transform": transform_info,
         "rel_error": res_mix.rel_error(),
@@ -701,7 +702,14 @@ def bench_climate6(a, torch, lib):
 
     log(f"order 6 {dims}, FP32 mixed")
     r6, ms6, ttm6, st = run(dims, w.M, "f32", stats=True)
-    roof = jacobi_roofline(st, PEAK["f32_TF"])
+    nsl = int(np.prod(dims[2:]))
+    rho6 = int(r6.offsets[-1].item())
+    # the FP32 path's slice SVDs: FP64 Gram, Cholesky and the in-LDS Jacobi
+    # (min(n1, n2) <= 192) or the round kernel; roofline of that kernel by
+    # the algorithmic SVD flops of the order-6 slices
+    roof = svd_roofline(st, a.steps, n1, n2, nsl, rho6, PEAK["f32_TF"], None,
+                        float(np.prod(dims)) * 8 + rho6 * (n1 + n2 + 1) * 4)
+    roof["kernel"] = "pc_jacobi_lds" if min(n1, n2) <= 192 else "jacobi_round"
     roof["src_sha"] = kernel_src_sha()
     out = {}
     if not a.no_f64:
@@ -717,8 +725,7 @@ def bench_climate6(a, torch, lib):
         torch.cuda.empty_cache()
     log(f"flat order 4 {flat_dims}, FP32 mixed")
     r4, ms4, ttm4, _ = run(flat_dims, flat_M, "f32")
-    nslices = int(np.prod(dims[2:]))
-    rho6 = int(r6.offsets[-1].item())
+    nslices = nsl
     rho4 = int(r4.offsets[-1].item())
     cpu = None
     if not a.no_cpu_baseline:

@@ -132,6 +132,7 @@ int run_pack_sort_f32(const double* s2, int64_t r, int64_t n, const int32_t* rho
                       const int64_t* offsets, int64_t capacity, int32_t* perm, float* S_pk,
                       int32_t* status, hipStream_t st);
 bool stats_enabled();
+void stats_add_launch(int64_t launches, double ms);
 void stats_set(bool on);
 void stats_reset();
 void stats_get(int64_t* launches, double* ms, int64_t* pairs_gram, int64_t* pairs_rot,

@@ -26,6 +26,7 @@
 // Against rotating the slice itself, each Jacobi pair touches vectors of
 // length r instead of L and no rotation matrix: for the 512 x 1024 climate
 // slices 2 w^2 (2 r) instead of 2 w^2 (2 L + r) flops per rotating pair.
+#include "angle.h"
 #include "common.h"
 #include "kernels.h"
 
@@ -164,13 +165,33 @@ __global__ __launch_bounds__(256) void pc_chol(const double* __restrict__ G, int
         for (int q = wave; q < nrt; q += 4) {
             const int64_t i0 = k0 + 16 * q;
             const int64_t ia = i0 + lr, kb = k0 + lr;
-            v4d acc = zero4<v4d>();
-            for (int64_t j = 0; j < k0; j += 4) {
-                const int64_t jc = j + lg;   // k0 is a multiple of 4, so jc < k0
-                const double a = ia < r ? Ls[ia + jc * r] : 0.0;
-                const double b = kb < r ? Ls[kb + jc * r] : 0.0;
-                acc = mfma_f64(a, b, acc);
+            const bool va = ia < r, vb = kb < r;
+            // rows clamped into the matrix (masked after the load), column lg
+            const double* pa = Ls + (va ? ia : 0) + (int64_t)lg * r;
+            const double* pb = Ls + (vb ? kb : 0) + (int64_t)lg * r;
+            // eight MFMA steps per batch: their sixteen loads are issued
+            // before the first MFMA, and two accumulators alternate
+            v4d acc = zero4<v4d>(), acc2 = zero4<v4d>();
+            int64_t j = 0;
+            for (; j + 32 <= k0; j += 32) {
+                double a[8], b[8];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) {
+                    a[u] = pa[(j + 4 * u) * r];
+                    b[u] = pb[(j + 4 * u) * r];
+                }
+#pragma unroll
+                for (int u = 0; u < 8; u += 2) {
+                    acc = mfma_f64(va ? a[u] : 0.0, vb ? b[u] : 0.0, acc);
+                    acc2 = mfma_f64(va ? a[u + 1] : 0.0, vb ? b[u + 1] : 0.0, acc2);
+                }
             }
+            for (; j < k0; j += 4) {   // k0 is a multiple of 16, so j + lg < k0
+                const double a = pa[j * r], b = pb[j * r];
+                acc = mfma_f64(va ? a : 0.0, vb ? b : 0.0, acc);
+            }
+#pragma unroll
+            for (int v = 0; v < 4; ++v) acc[v] += acc2[v];
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
                 const int64_t i = i0 + mfma_row<double>(lg, v), c = k0 + lr;
@@ -228,6 +249,186 @@ __global__ __launch_bounds__(256) void pc_chol(const double* __restrict__ G, int
         }
         __syncthreads();
     }
+}
+
+// seat -> player of the circle tournament over N (even) players in round
+// `round` (seat 0 fixed, the others advance one seat per round)
+__device__ __forceinline__ int lds_player(int seat, int round, int N) {
+    if (seat == 0) return 0;
+    int t = seat - 1 + round;
+    if (t >= N - 1) t -= N - 1;
+    return t + 1;
+}
+
+// x from lane (lane ^ 1), (lane ^ 2), or its mirror in the 8- or 16-lane
+// row, by DPP (two 32-bit moves for a double)
+template <int CTRL>
+__device__ __forceinline__ double dpp_move(double x) {
+    const long long b = __double_as_longlong(x);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffffll), CTRL, 0xf, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xf, 0xf, false);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// Sum over the 16 lanes of a DPP row.  Every step adds the value of a
+// partner lane under an involution (xor 1, xor 2, mirror in 8, mirror in
+// 16), so the two lanes of a pair add the same two numbers and, addition
+// being commutative, every lane ends with the same bits.
+__device__ __forceinline__ double row_sum16(double x) {
+    x += dpp_move<0xB1>(x);    // quad_perm [1, 0, 3, 2]
+    x += dpp_move<0x4E>(x);    // quad_perm [2, 3, 0, 1]
+    x += dpp_move<0x141>(x);   // row_half_mirror
+    x += dpp_move<0x140>(x);   // row_mirror
+    return x;
+}
+
+// One-sided Jacobi held in LDS for factors of at most RMAX columns: the
+// r x r factor of slice blockIdx.x stays in LDS (r x (r + 1) floats,
+// dynamic) for all its sweeps: one workgroup per slice, no launch per
+// round.  A round of the circle tournament pairs the columns disjointly;
+// sixteen groups of 16 lanes (one DPP row each) take its pairs, two at a
+// time so that their latencies overlap: the three dot products in FP64
+// from exact FP32 products (lane i holds elements i, i + 16, ...), summed
+// over the row by DPP, the FP64 angle and the FP32 rotation of the two
+// columns; one barrier per round.  The slice has converged after the first
+// sweep whose largest |cos| is <= tol; one more sweep then rotates every
+// pair not orthogonal to rounding, because the short-side vectors' residual
+// non-orthogonality is amplified by sigma_i / sigma_j in the long-side
+// factor (U = A V / sigma for tall slices, V = G^T / sigma for wide ones).
+// Then s2 = max(||b_j||^2 - shift, 0) in FP64 and flag = 0 (converged), 1
+// (sweep limit) or 2 (NaN / Inf met).
+template <int RMAX>
+__global__ __launch_bounds__(256) void pc_jacobi_lds(float* __restrict__ B, int64_t r, double tol,
+                                                     int max_sweeps, const double* __restrict__ shift,
+                                                     double* __restrict__ s2, int32_t* __restrict__ flag) {
+    constexpr int E = RMAX / 16;     // elements per lane and column
+    extern __shared__ float X[];     // column j at X[j * RP]
+    __shared__ double gmax[16];
+    __shared__ int gbad[16];
+    const int64_t s = blockIdx.x;
+    float* Bs = B + s * r * r;
+    const int tid = threadIdx.x, grp = tid >> 4, l = tid & 15;
+    const int rr = (int)r, RP = rr + 1;
+    for (int idx = tid; idx < rr * rr; idx += 256) {
+        const int j = idx / rr, i = idx - j * rr;
+        X[j * RP + i] = Bs[idx];
+    }
+    __syncthreads();
+    const int R = rr + (rr & 1);
+    const int NP = R / 2;            // pairs per round
+    bool conv = false, bad = false, polish = false;
+    for (int sw = 0; sw < max_sweeps + 1; ++sw) {
+        if (sw == max_sweeps && !conv) break;
+        const double thr = polish ? 0.0 : tol;
+        double mx = 0.0;
+        for (int rnd = 0; rnd < R - 1; ++rnd) {
+            for (int k0 = grp; k0 < NP; k0 += 32) {
+                // this group's pairs k0 and k0 + 16 of the round (either may
+                // be the padding player's or absent): uniform in the group
+                int pp[2], qq[2];
+                bool use[2];
+#pragma unroll
+                for (int u = 0; u < 2; ++u) {
+                    const int k = k0 + 16 * u;
+                    pp[u] = lds_player(k, rnd, R);
+                    qq[u] = lds_player(R - 1 - k, rnd, R);
+                    use[u] = k < NP && pp[u] < rr && qq[u] < rr;
+                }
+                float vp[2][E], vq[2][E];
+                double app[2], aqq[2], apq[2];
+#pragma unroll
+                for (int u = 0; u < 2; ++u) {
+                    const float* xp = X + (use[u] ? pp[u] : 0) * RP;
+                    const float* xq = X + (use[u] ? qq[u] : 0) * RP;
+#pragma unroll
+                    for (int e = 0; e < E; ++e) {
+                        const int i = l + 16 * e;
+                        const bool ok = use[u] && i < rr;
+                        vp[u][e] = ok ? xp[i] : 0.0f;
+                        vq[u][e] = ok ? xq[i] : 0.0f;
+                    }
+                }
+#pragma unroll
+                for (int u = 0; u < 2; ++u) {
+                    double a0 = 0.0, b0 = 0.0, c0 = 0.0;
+#pragma unroll
+                    for (int e = 0; e < E; ++e) {
+                        const double a = vp[u][e], b = vq[u][e];
+                        a0 = fma(a, a, a0);
+                        b0 = fma(b, b, b0);
+                        c0 = fma(a, b, c0);
+                    }
+                    app[u] = row_sum16(a0);
+                    aqq[u] = row_sum16(b0);
+                    apq[u] = row_sum16(c0);
+                }
+#pragma unroll
+                for (int u = 0; u < 2; ++u) {
+                    if (!use[u]) continue;
+                    if (!(app[u] + aqq[u] + fabs(apq[u]) < INFINITY)) { bad = true; continue; }
+                    const double den = app[u] * aqq[u];
+                    const double cs = den > 0.0 ? fabs(apq[u]) / sqrt(den) : 0.0;
+                    mx = fmax(mx, cs);
+                    if (cs > thr) {
+                        double c, sn;
+                        jacobi_angle(app[u], aqq[u], apq[u], true, c, sn);
+                        const float cf = (float)c, sf = (float)sn;
+                        float* xp = X + pp[u] * RP;
+                        float* xq = X + qq[u] * RP;
+#pragma unroll
+                        for (int e = 0; e < E; ++e) {
+                            const int i = l + 16 * e;
+                            if (i < rr) {
+                                xp[i] = cf * vp[u][e] - sf * vq[u][e];
+                                xq[i] = sf * vp[u][e] + cf * vq[u][e];
+                            }
+                        }
+                    }
+                }
+            }
+            __syncthreads();
+        }
+        if (l == 0) { gmax[grp] = mx; gbad[grp] = bad ? 1 : 0; }
+        __syncthreads();
+        double m = 0.0;
+        int anybad = 0;
+        for (int g2 = 0; g2 < 16; ++g2) { m = fmax(m, gmax[g2]); anybad |= gbad[g2]; }
+        __syncthreads();   // gmax is rewritten by the next sweep
+        if (anybad) { bad = true; break; }
+        if (polish) break;
+        conv = m <= tol;
+        polish = conv;
+    }
+    // squared norms (fixed order: lane sums, then the row sum) and the
+    // factor back to memory
+    const double shs = shift[s];
+    for (int j = grp; j < rr; j += 16) {
+        double a = 0.0;
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            const int i = l + 16 * e;
+            if (i < rr) { const double v = X[j * RP + i]; a = fma(v, v, a); }
+        }
+        a = row_sum16(a);
+        if (l == 0) { const double v = a - shs; s2[s * r + j] = v > 0.0 ? v : 0.0; }
+    }
+    for (int idx = tid; idx < rr * rr; idx += 256) {
+        const int j = idx / rr, i = idx - j * rr;
+        Bs[idx] = X[j * RP + i];
+    }
+    if (tid == 0) flag[s] = bad ? 2 : (conv ? 0 : 1);
+}
+
+__global__ void pc_flags_status(const int32_t* __restrict__ flag, int64_t n, int32_t* __restrict__ status) {
+    __shared__ int nf, nc;
+    if (threadIdx.x == 0) { nf = 0; nc = 0; }
+    __syncthreads();
+    for (int64_t i = threadIdx.x; i < n; i += blockDim.x) {
+        if (flag[i] == 2) atomicOr(&nf, 1);
+        else if (flag[i] == 1) atomicOr(&nc, 1);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) *status = nf ? TSVDM_E_NONFINITE : (nc ? TSVDM_E_NOCONV : TSVDM_OK);
 }
 
 // s2 <- max(s2 - shift, 0) per slice: squared singular values of the slice
@@ -417,6 +618,28 @@ __global__ __launch_bounds__(256) void pc_factor(const float* __restrict__ A, co
 
 }  // namespace
 
+// dynamic LDS of the in-LDS Jacobi: r x (r + 1) floats
+template <int RMAX>
+int launch_lds_bucket(float* B, int64_t r, int64_t n, double tol, int max_sweeps, const double* shift,
+                      double* s2, int32_t* flag, hipStream_t st) {
+    const size_t bytes = (size_t)r * (size_t)(r + 1) * sizeof(float);
+    TSVDM_HIP_CHECK(hipFuncSetAttribute(reinterpret_cast<const void*>(&pc_jacobi_lds<RMAX>),
+                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes));
+    pc_jacobi_lds<RMAX><<<(unsigned)n, 256, bytes, st>>>(B, r, tol, max_sweeps, shift, s2, flag);
+    TSVDM_LAUNCH_CHECK();
+    return TSVDM_OK;
+}
+
+int launch_jacobi_lds(float* B, int64_t r, int64_t n, double tol, int max_sweeps, const double* shift,
+                      double* s2, int32_t* flag, hipStream_t st) {
+    if (r <= 32) return launch_lds_bucket<32>(B, r, n, tol, max_sweeps, shift, s2, flag, st);
+    if (r <= 64) return launch_lds_bucket<64>(B, r, n, tol, max_sweeps, shift, s2, flag, st);
+    if (r <= 96) return launch_lds_bucket<96>(B, r, n, tol, max_sweeps, shift, s2, flag, st);
+    if (r <= 128) return launch_lds_bucket<128>(B, r, n, tol, max_sweeps, shift, s2, flag, st);
+    if (r <= 160) return launch_lds_bucket<160>(B, r, n, tol, max_sweeps, shift, s2, flag, st);
+    return launch_lds_bucket<192>(B, r, n, tol, max_sweeps, shift, s2, flag, st);
+}
+
 size_t gram_svd_workspace_bytes(int64_t m, int64_t p, int64_t n) {
     const SliceGeom g = slice_geom(m, p);
     Carver cv(nullptr);
@@ -447,7 +670,32 @@ int run_gram_svd(const float* A_hat, int64_t m, int64_t p, int64_t n, float* B, 
     else if (r <= 512) pc_chol<512><<<(unsigned)n, 256, 0, st>>>(G, r, cshift, Lw, B, shift);
     else pc_chol<1024><<<(unsigned)n, 256, 0, st>>>(G, r, cshift, Lw, B, shift);
     TSVDM_LAUNCH_CHECK();
-    // one-sided Jacobi on the columns of L (r x r), no accumulated rotations
+    // one-sided Jacobi on the columns of L (r x r), no accumulated rotations:
+    // held in LDS for r <= 192, else the round kernel streaming through HBM
+    if (r <= 192 && n < ((int64_t)1 << 31)) {
+        int32_t* flag = static_cast<int32_t*>(jws);
+        const bool stats = stats_enabled();
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        if (stats) {
+            TSVDM_HIP_CHECK(hipEventCreate(&e0));
+            TSVDM_HIP_CHECK(hipEventCreate(&e1));
+            TSVDM_HIP_CHECK(hipEventRecord(e0, st));
+        }
+        int rc2 = launch_jacobi_lds(B, r, n, o.tol, o.max_sweeps, shift, s2, flag, st);
+        if (rc2) return rc2;
+        if (stats) {
+            TSVDM_HIP_CHECK(hipEventRecord(e1, st));
+            TSVDM_HIP_CHECK(hipEventSynchronize(e1));
+            float t = 0.f;
+            TSVDM_HIP_CHECK(hipEventElapsedTime(&t, e0, e1));
+            (void)hipEventDestroy(e0);
+            (void)hipEventDestroy(e1);
+            stats_add_launch(1, t);
+        }
+        pc_flags_status<<<1, 256, 0, st>>>(flag, n, status);
+        TSVDM_LAUNCH_CHECK();
+        return TSVDM_OK;
+    }
     int rc = run_jacobi(B, TSVDM_F32, r, r, n, nullptr, s2, status, o, jws, st);
     if (rc) return rc;
     pc_unshift<<<(unsigned)((r * n + 255) / 256), 256, 0, st>>>(s2, shift, r, n);

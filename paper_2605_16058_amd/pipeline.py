@@ -29,21 +29,52 @@ PRECISIONS = {
 RECON_BOUND = {"f64": 0.0, "f32": 3e-5, "bf16x3": 1e-4, "bf16": None}
 
 
-def selection_eps(eps, precision, guard=True):
-    """The tolerance a t-SVDM-II run selects with so that its measured error
-    stays below eps.  Algorithm 2 bounds the tail of the squared singular
-    values the run computed: the truncation alone leaves an error below eps
-    relative to ||A||.  The rounding of a reduced-precision path moves its
-    reconstruction by at most delta = RECON_BOUND[precision] from the FP64
-    one, so by the triangle inequality selecting with eps - delta keeps
-    ||A - A_rec|| / ||A|| < eps.  FP64 (delta = 0) and plain BF16 (no bound)
-    select with eps itself."""
+GUARDS = ("measure", "bound", "off")
+
+
+def _guard_mode(guard):
+    if guard is True:
+        return "measure"
+    if guard is False or guard is None:
+        return "off"
+    if guard not in GUARDS:
+        raise ValueError(f"guard must be one of {GUARDS}")
+    return guard
+
+
+def selection_eps(eps, precision, guard="measure"):
+    """The tolerance a t-SVDM-II run selects with first.  Algorithm 2 bounds
+    the tail of the squared singular values the run computed: the truncation
+    alone leaves an error below eps relative to ||A||.  A reduced-precision
+    path adds its rounding, at most delta = RECON_BOUND[precision] relative
+    to ||A||, so selecting with eps - delta keeps ||A - A_rec|| / ||A|| < eps
+    by the triangle inequality: guard "bound" does that up front.  Guard
+    "measure" (TSVDM, TSVDMd) selects with eps and checks the measured error
+    afterwards (next_selection_eps); "off" selects with eps and checks
+    nothing.  FP64 (delta = 0) and plain BF16 (no stated bound) select with
+    eps under every guard."""
+    g = _guard_mode(guard)
     d = RECON_BOUND[precision]
-    if not guard or not d:
+    if g != "bound" or not d:
         return float(eps)
     if float(eps) <= d:
         raise ValueError(f"eps must exceed the {precision} reconstruction bound {d}")
     return float(eps) - d
+
+
+def next_selection_eps(eps, eps_cur, rel, stats, precision, rounds):
+    """Guard "measure": the tolerance of the next selection after a run with
+    tolerance eps_cur measured rel >= eps.  The excess of the measured error
+    over the run's own prediction sqrt(discarded / total) is rounding; the
+    next selection tightens eps_cur by twice that excess, and a third one
+    falls back to eps - delta (the triangle-inequality bound)."""
+    d = RECON_BOUND[precision] or 0.0
+    st = stats.double().cpu()
+    pred = float((st[1] / st[2]).sqrt()) if float(st[2]) > 0 else 0.0
+    nxt = eps_cur - 2.0 * max(rel - pred, 0.0)
+    if rounds >= 2 or not (0.0 < nxt < eps_cur):
+        nxt = min(eps_cur, eps - d) if d else eps_cur * (1.0 - 1e-6)
+    return max(nxt, 1e-300)
 
 
 GRAM_MAX_R = 1024   # largest min(m, p) of the Gram form
@@ -82,6 +113,7 @@ class Result:
     computed: torch.Tensor | None = None   # certified selection: slices given an SVD
     passes: int = 0                         # certified selection: SVD rounds
     eps_sel: float | None = None            # t-SVDM-II: the tolerance selected with
+    selections: int = 1                     # t-SVDM-II: selections made (guard "measure")
 
     def rel_error(self) -> float:
         e = self.err.double().cpu()
@@ -101,10 +133,14 @@ class TSVDM:
 
     svd: "auto", "jacobi" or "gram" (see resolve_svd).
 
-    guard=True (mode "II") makes a reduced-precision path select with
-    eps - delta, delta its stated reconstruction bound (selection_eps), so
-    that the measured relative error stays below eps; its ranks then follow
-    eps - delta, not eps.  guard=False selects with eps on every path.
+    guard (mode "II"; see selection_eps): "measure" (default) selects with
+    eps and, if the measured relative error of the result is not below eps
+    (rounding of a reduced-precision path on top of a truncation error just
+    below eps), repeats the selection, packing and reconstruction with a
+    tighter tolerance (next_selection_eps; the slice SVDs are not redone);
+    "bound" selects with eps - delta at once; "off" checks nothing.
+    Result.eps_sel is the tolerance of the result, Result.selections the
+    number of selections made.
 
     certify=True (mode "II") runs the certified selection: only slices whose
     energy could reach the threshold get an SVD.  The first round computes
@@ -121,10 +157,15 @@ class TSVDM:
     def __init__(self, shape, M, mode="II", k=None, eps=None, precision="f64",
                  block=0, max_sweeps=0, tol=0.0, host_poll=True, capacity="max",
                  device="cuda", check_m=True, tile=0, transform="dense", certify=False,
-                 theta=0.5, max_passes=3, guard=True, svd="auto"):
+                 theta=0.5, max_passes=3, guard="measure", svd="auto"):
         self.m, self.p, self.n = (int(x) for x in shape)
         self.r = min(self.m, self.p)
         self.svd = resolve_svd(svd, precision, self.r, certify)
+        # the certified selection chooses its ranks inside its SVD rounds:
+        # it takes the up-front bound instead of measuring
+        self.guard = _guard_mode(guard)
+        if certify and self.guard == "measure":
+            self.guard = "bound"
         if mode not in ("I", "II"):
             raise ValueError("mode must be 'I' or 'II'")
         if mode == "I" and (k is None or int(k) < 1):
@@ -135,7 +176,7 @@ class TSVDM:
             raise ValueError(f"precision must be one of {list(PRECISIONS)}")
         self.mode, self.k, self.eps = mode, k, eps
         self.precision = precision
-        self.eps_sel = selection_eps(eps, precision, guard) if mode == "II" else None
+        self.eps_sel = selection_eps(eps, precision, self.guard) if mode == "II" else None
         self.ttm_compute, self.dtype = PRECISIONS[precision]
         if transform not in ("dense", "dct"):
             raise ValueError("transform must be 'dense' or 'dct'")
@@ -181,49 +222,62 @@ class TSVDM:
             A_hat = ops.tsvdm_transform(A, self.Mdev, transpose=False, scale=1.0,
                                         compute=self.ttm_compute, out_dtype=self.dtype, ws=self.ws,
                                         tile=self.tile)
-        # 2. slice SVDs, 3. ranks
-        computed, passes = None, 0
+        # 2. slice SVDs
+        computed, passes, shift = None, 0, None
         if self.certify:
             W, s2, svd_status, rho, offsets, stats, computed, passes = self._certified(A_hat)
+        elif self.svd == "gram":
+            W, s2, shift, svd_status = ops.tsvdm_slice_svd_gram(
+                A_hat, self.block, self.max_sweeps, self.tol, self.host_poll, ws=self.ws)
         else:
-            if self.svd == "gram":
-                W, s2, shift, svd_status = ops.tsvdm_slice_svd_gram(
-                    A_hat, self.block, self.max_sweeps, self.tol, self.host_poll, ws=self.ws)
-            else:
-                W, s2, svd_status = ops.tsvdm_slice_svd(A_hat, self.block, self.max_sweeps, self.tol,
-                                                        self.host_poll, ws=self.ws)
+            W, s2, svd_status = ops.tsvdm_slice_svd(A_hat, self.block, self.max_sweeps, self.tol,
+                                                    self.host_poll, ws=self.ws)
+        eps_cur = self.eps_sel
+        selections = 0
+        back = self.ttm_compute if self.ttm_compute != "f64" else "f64"
+        while True:
+            selections += 1
+            # 3. ranks (the certified selection made them with its SVD rounds)
             if self.mode == "I":
                 rho, offsets = ops.tsvdm_truncate_rank(self.k, r, n, self.device)
                 stats = torch.full((4,), float("nan"), dtype=torch.float64, device=self.device)
+            elif not (self.certify and selections == 1):
+                rho, offsets, stats = ops.tsvdm_truncate_tol(s2, eps_cur, ws=self.ws)
+            if self.capacity_mode == "exact":
+                cap = int(offsets[n].item())
+            elif self.mode == "I":
+                cap = min(int(self.k), r) * n
             else:
-                rho, offsets, stats = ops.tsvdm_truncate_tol(s2, self.eps_sel, ws=self.ws)
-        if self.capacity_mode == "exact":
-            cap = int(offsets[n].item())
-        elif self.mode == "I":
-            cap = min(int(self.k), r) * n
-        else:
-            cap = r * n
-        # 4. factors
-        if self.svd == "gram":
-            U_pk, G_pk, S_pk, pack_status = ops.tsvdm_pack_gram(A_hat, W, s2, shift, rho, offsets, cap,
-                                                                ws=self.ws)
-        else:
-            U_pk, G_pk, S_pk, pack_status = ops.tsvdm_pack(A_hat, W, s2, rho, offsets, cap, ws=self.ws)
+                cap = r * n
+            # 4. factors
+            if self.svd == "gram":
+                U_pk, G_pk, S_pk, pack_status = ops.tsvdm_pack_gram(A_hat, W, s2, shift, rho, offsets,
+                                                                    cap, ws=self.ws)
+            else:
+                U_pk, G_pk, S_pk, pack_status = ops.tsvdm_pack(A_hat, W, s2, rho, offsets, cap,
+                                                               ws=self.ws)
+            # 5. reconstruct + back-transform (M^{-1} = M^T / c^2)
+            if self.transform == "dct":
+                C_hat = ops.tsvdm_lowrank(U_pk, G_pk, rho, offsets, cap, (m, p, n))
+                A_rec = ops.tsvdm_transform_dct(C_hat, 3, inverse=True, compute=back, out_dtype=out_dt)
+                del C_hat
+            else:
+                A_rec = ops.tsvdm_reconstruct(U_pk, G_pk, rho, offsets, cap, self.Mdev, (m, p, n),
+                                              scale=1.0 / self.c2, out_dtype=out_dt, compute=back,
+                                              ws=self.ws, tile=self.tile)
+            # 6. error report; guard "measure": the result must be below eps
+            err = ops.tsvdm_error(A, A_rec, ws=self.ws)
+            if self.mode != "II" or self.guard != "measure" or selections >= 3:
+                break
+            e = err.double().cpu()
+            rel = float((e[0] / e[1]).sqrt()) if float(e[1]) > 0 else 0.0
+            if rel < self.eps:
+                break
+            eps_cur = next_selection_eps(self.eps, eps_cur, rel, stats, self.precision, selections)
+            del U_pk, G_pk, S_pk, A_rec
         del W
-        # 5. reconstruct + back-transform (M^{-1} = M^T / c^2)
-        back = self.ttm_compute if self.ttm_compute != "f64" else "f64"
-        if self.transform == "dct":
-            C_hat = ops.tsvdm_lowrank(U_pk, G_pk, rho, offsets, cap, (m, p, n))
-            A_rec = ops.tsvdm_transform_dct(C_hat, 3, inverse=True, compute=back, out_dtype=out_dt)
-            del C_hat
-        else:
-            A_rec = ops.tsvdm_reconstruct(U_pk, G_pk, rho, offsets, cap, self.Mdev, (m, p, n),
-                                          scale=1.0 / self.c2, out_dtype=out_dt, compute=back,
-                                          ws=self.ws, tile=self.tile)
-        # 6. error report
-        err = ops.tsvdm_error(A, A_rec, ws=self.ws)
         return Result(A_rec, rho, offsets, U_pk, G_pk, S_pk, s2, stats, err, svd_status,
-                      pack_status, cap, computed, passes, self.eps_sel)
+                      pack_status, cap, computed, passes, eps_cur, selections)
 
     def _certified(self, A_hat):
         return certified_svd(A_hat, self.eps_sel, self.theta, self.max_passes, self.block,
@@ -279,7 +333,7 @@ class TSVDMd:
 
     def __init__(self, dims, Ms, mode="II", k=None, eps=None, precision="f64", block=0,
                  max_sweeps=0, tol=0.0, host_poll=True, device="cuda", tile=0, certify=False,
-                 theta=0.5, max_passes=3, guard=True, svd="auto"):
+                 theta=0.5, max_passes=3, guard="measure", svd="auto"):
         self.dims = tuple(int(x) for x in dims)
         if certify and mode != "II":
             raise ValueError("certify applies to mode II")
@@ -297,7 +351,10 @@ class TSVDMd:
         if precision not in PRECISIONS:
             raise ValueError(f"precision must be one of {list(PRECISIONS)}")
         self.mode, self.k, self.eps, self.precision = mode, k, eps, precision
-        self.eps_sel = selection_eps(eps, precision, guard) if mode == "II" else None
+        self.guard = _guard_mode(guard)
+        if certify and self.guard == "measure":
+            self.guard = "bound"
+        self.eps_sel = selection_eps(eps, precision, self.guard) if mode == "II" else None
         self.ttm_compute, self.dtype = PRECISIONS[precision]
         self.c2 = [ops.check_transform(M) for M in Ms]
         self.Mdev = [ops.device_matrix(M, device) for M in Ms]
@@ -326,52 +383,69 @@ class TSVDMd:
                                      out_dtype=dt, out=out, ws=self.ws, tile=self.tile)
             cur = out
         A_hat = cur.permute(*range(d - 1, -1, -1)).reshape(N, p, m).permute(2, 1, 0)
-        # 2. slice SVDs over the N frontal slices, 3. ranks
-        computed, passes = None, 0
+        # 2. slice SVDs over the N frontal slices
+        computed, passes, shift = None, 0, None
         if self.certify:
             W, s2, svd_status, rho, offsets, stats, computed, passes = certified_svd(
                 A_hat, self.eps_sel, self.theta, self.max_passes, self.block, self.max_sweeps,
                 self.tol, self.host_poll, self.ws)
-            cap = r * N
+        elif self.svd == "gram":
+            W, s2, shift, svd_status = ops.tsvdm_slice_svd_gram(
+                A_hat, self.block, self.max_sweeps, self.tol, self.host_poll, ws=self.ws)
         else:
-            if self.svd == "gram":
-                W, s2, shift, svd_status = ops.tsvdm_slice_svd_gram(
-                    A_hat, self.block, self.max_sweeps, self.tol, self.host_poll, ws=self.ws)
-            else:
-                W, s2, svd_status = ops.tsvdm_slice_svd(A_hat, self.block, self.max_sweeps, self.tol,
-                                                        self.host_poll, ws=self.ws)
+            W, s2, svd_status = ops.tsvdm_slice_svd(A_hat, self.block, self.max_sweeps, self.tol,
+                                                    self.host_poll, ws=self.ws)
+        # buffers of the back path that never alias A_hat (a repeated
+        # selection packs from it again)
+        free = [b for b in bufs if b.data_ptr() != cur.data_ptr()]
+        while len(free) < (1 if d == 3 else 2):
+            free.append(ops.colmajor_empty_nd(self.dims, dt, self.device))
+        eps_cur = self.eps_sel
+        selections = 0
+        while True:
+            selections += 1
+            # 3. ranks (the certified selection made them with its SVD rounds)
             if self.mode == "I":
                 rho, offsets = ops.tsvdm_truncate_rank(self.k, r, N, self.device)
                 stats = torch.full((4,), float("nan"), dtype=torch.float64, device=self.device)
                 cap = min(int(self.k), r) * N
             else:
-                rho, offsets, stats = ops.tsvdm_truncate_tol(s2, self.eps_sel, ws=self.ws)
+                if not (self.certify and selections == 1):
+                    rho, offsets, stats = ops.tsvdm_truncate_tol(s2, eps_cur, ws=self.ws)
                 cap = r * N
-        # 4. factors
-        if self.svd == "gram":
-            U_pk, G_pk, S_pk, pack_status = ops.tsvdm_pack_gram(A_hat, W, s2, shift, rho, offsets, cap,
-                                                                ws=self.ws)
-        else:
-            U_pk, G_pk, S_pk, pack_status = ops.tsvdm_pack(A_hat, W, s2, rho, offsets, cap, ws=self.ws)
+            # 4. factors
+            if self.svd == "gram":
+                U_pk, G_pk, S_pk, pack_status = ops.tsvdm_pack_gram(A_hat, W, s2, shift, rho, offsets,
+                                                                    cap, ws=self.ws)
+            else:
+                U_pk, G_pk, S_pk, pack_status = ops.tsvdm_pack(A_hat, W, s2, rho, offsets, cap,
+                                                               ws=self.ws)
+            # 5. transform-domain low-rank product, then back-transforms mode by mode
+            C3 = free[0].permute(*range(d - 1, -1, -1)).reshape(N, p, m).permute(2, 1, 0)
+            ops.tsvdm_lowrank(U_pk, G_pk, rho, offsets, cap, (m, p, N), out=C3)
+            A_rec = ops.colmajor_empty_nd(self.dims, dt, self.device)
+            cb = free[0]
+            back = list(range(3, d + 1))
+            for j, kk in enumerate(back):
+                last = j == len(back) - 1
+                out = A_rec if last else (free[1] if cb.data_ptr() == free[0].data_ptr() else free[0])
+                ops.tsvdm_transform_mode(cb, kk, self.Mdev[kk - 3], transpose=True,
+                                         scale=1.0 / self.c2[kk - 3], compute=comp, out_dtype=dt, out=out,
+                                         ws=self.ws, tile=self.tile)
+                cb = out
+            # 6. error report; guard "measure": the result must be below eps
+            err = ops.tsvdm_error(A, A_rec, ws=self.ws)
+            if self.mode != "II" or self.guard != "measure" or selections >= 3:
+                break
+            e = err.double().cpu()
+            rel = float((e[0] / e[1]).sqrt()) if float(e[1]) > 0 else 0.0
+            if rel < self.eps:
+                break
+            eps_cur = next_selection_eps(self.eps, eps_cur, rel, stats, self.precision, selections)
+            del U_pk, G_pk, S_pk, A_rec
         del W
-        # 5. transform-domain low-rank product, then back-transforms mode by mode
-        other = bufs[1] if (d > 3 and cur.data_ptr() == bufs[0].data_ptr()) else bufs[0]
-        C3 = other.permute(*range(d - 1, -1, -1)).reshape(N, p, m).permute(2, 1, 0)
-        ops.tsvdm_lowrank(U_pk, G_pk, rho, offsets, cap, (m, p, N), out=C3)
-        A_rec = ops.colmajor_empty_nd(self.dims, dt, self.device)
-        cur = other
-        back = list(range(3, d + 1))
-        for j, kk in enumerate(back):
-            last = j == len(back) - 1
-            out = A_rec if last else (bufs[0] if cur.data_ptr() == bufs[-1].data_ptr() else bufs[-1])
-            ops.tsvdm_transform_mode(cur, kk, self.Mdev[kk - 3], transpose=True,
-                                     scale=1.0 / self.c2[kk - 3], compute=comp, out_dtype=dt, out=out,
-                                     ws=self.ws, tile=self.tile)
-            cur = out
-        # 6. error report
-        err = ops.tsvdm_error(A, A_rec, ws=self.ws)
         return Result(A_rec, rho, offsets, U_pk, G_pk, S_pk, s2, stats, err, svd_status,
-                      pack_status, cap, computed, passes, self.eps_sel)
+                      pack_status, cap, computed, passes, eps_cur, selections)
 
 
 class BatchTSVDM:
@@ -385,13 +459,14 @@ class BatchTSVDM:
     capacity) so they can be read back; otherwise they stay in the workspace.
     blocks / tiles: optional per-tensor Jacobi block widths and transform
     tile shapes (0 = the plan's choice), e.g. from autotune.tune_batch().
-    guard: as for TSVDM (mode "II" tensors select with selection_eps; the
-    tolerances used are in eps_sel).
+    guard: "bound" (default) or "off" (see selection_eps): one plan runs
+    without host decisions, so the mode "II" tensors of a reduced-precision
+    batch select with eps - delta up front; the tolerances are in eps_sel.
     """
 
     def __init__(self, tensors, Ms, modes, ks=None, epss=None, precision="f32", block=0,
                  max_sweeps=0, keep_factors=False, reconstruct=True, device="cuda",
-                 blocks=None, tiles=None, guard=True):
+                 blocks=None, tiles=None, guard="bound"):
         import ctypes
 
         from . import _lib
@@ -410,6 +485,8 @@ class BatchTSVDM:
             raise TypeError("all tensors of a batch must share one dtype")
         self.Mdev, self.rho, self.offsets, self.stats, self.A_rec, self.err = [], [], [], [], [], []
         self.U_pk, self.G_pk, self.S_pk, self.capacity = [], [], [], []
+        if _guard_mode(guard) == "measure":
+            raise ValueError("a batch takes guard 'bound' or 'off'")
         self.eps_sel = [selection_eps(e, precision, guard) if md == "II" else None
                         for e, md in zip(epss, modes)]
         items = (_lib.BatchItem * cnt)()

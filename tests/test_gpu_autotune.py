@@ -45,7 +45,7 @@ def test_batch_mixed_blocks_and_tiles_equal_single_calls():
     assert int(st.item()) == 0
     for t, A in enumerate(Ts):
         res = tsvdm(A, w.M[t], mode=w.mode[t], k=w.k[t], eps=w.eps[t], precision="f32",
-                    block=blocks[t], tile=tiles[t], svd="jacobi")
+                    block=blocks[t], tile=tiles[t], svd="jacobi", guard="bound")
         torch.cuda.synchronize()
         assert torch.equal(res.rho, b.rho[t]), t
         assert torch.equal(res.A_rec, b.A_rec[t]), t
