@@ -214,13 +214,24 @@ int tsvdm_slice_svd(void* A_hat, int dtype, int64_t m, int64_t p, int64_t n,
  * The eigenvalues of the FP64 Gram matrix carry absolute errors of order
  * 2^-53 ||G||, so sigma_j is accurate to about 2^-53 sigma_max^2 / sigma_j
  * (2^-26.5 sigma_max as sigma_j -> 0), well inside FP32 accuracy; this form
- * is for FP32 results only.  min(m, p) <= 1024.  block, max_sweeps, tol
- * (default tol from the vector length r) and host_poll as in tsvdm_slice_svd.
+ * is for FP32 results only.  min(m, p) <= TSVDM_GRAM_MAX_R.  block,
+ * max_sweeps, tol (default tol from the vector length r) and host_poll as in
+ * tsvdm_slice_svd.  jacobi (tsvdm_gram_jacobi) places the Jacobi on L:
+ *   TSVDM_GRAM_ROUNDS  the block rounds of tsvdm_slice_svd, L in HBM;
+ *   TSVDM_GRAM_LDS     one workgroup per slice runs every sweep with L held
+ *                      in LDS, scalar pairs in a cyclic tournament (block
+ *                      unused); needs r <= TSVDM_GRAM_LDS_MAX_R;
+ *   TSVDM_GRAM_AUTO    LDS for r <= TSVDM_GRAM_LDS_MAX_R, else the rounds.
+ * The two placements give different rounding (both within the bound above).
  * ws: tsvdm_slice_svd_gram_workspace_size bytes (holds G and L in FP64). */
+#define TSVDM_GRAM_MAX_R 1024
+#define TSVDM_GRAM_LDS_MAX_R 128
+typedef enum { TSVDM_GRAM_AUTO = 0, TSVDM_GRAM_ROUNDS = 1, TSVDM_GRAM_LDS = 2 } tsvdm_gram_jacobi;
 int tsvdm_slice_svd_gram_workspace_size(int64_t m, int64_t p, int64_t n, size_t* bytes);
 int tsvdm_slice_svd_gram(const void* A_hat, int64_t m, int64_t p, int64_t n, void* B,
                          double* s2, double* shift, int32_t* status, int block, int max_sweeps,
-                         double tol, int host_poll, void* ws, size_t ws_bytes, void* stream);
+                         double tol, int jacobi, int host_poll, void* ws, size_t ws_bytes,
+                         void* stream);
 
 /* Slice SVDs of a subset: as tsvdm_slice_svd, but only the slices with
  * run[i] != 0 (run: device int32[n]) are computed; every other slice keeps
@@ -440,7 +451,14 @@ typedef struct tsvdm_batch_plan_s* tsvdm_batch_plan;
  * items at the default (32 when the largest min(m, p) of the batch is at
  * least 256, else 16).  Items of different widths run as two launches per
  * round step.  max_sweeps 0 = 40.  Host errors return before anything is
- * launched. */
+ * launched.
+ * In an F32 plan, items with min(m, p) <= TSVDM_GRAM_MAX_R take the Gram
+ * form of tsvdm_slice_svd_gram / tsvdm_pack_gram, every other item the
+ * block-rotation form of tsvdm_slice_svd / tsvdm_pack (F64 plans: the
+ * rotation form only).  The Gram form's Jacobi is TSVDM_GRAM_LDS when every
+ * item of the plan has min(m, p) <= TSVDM_GRAM_LDS_MAX_R, else
+ * TSVDM_GRAM_ROUNDS.  Each item's results equal those calls' bits at the
+ * item's block width and that placement. */
 int tsvdm_batch_plan_create(const tsvdm_batch_item* items, int32_t count, int in_dtype,
                             int dtype, int ttm_compute, int block, int max_sweeps,
                             tsvdm_batch_plan* plan, size_t* ws_bytes);

@@ -15,6 +15,11 @@ LIB_PATH = os.path.join(HERE, "libtsvdm.so")
 
 F64, F32, BF16, BF16X3 = 0, 1, 2, 3
 TILE_AUTO, TILE_64x64, TILE_128x32, TILE_256x16 = 0, 1, 2, 3
+# largest min(m, p) of the Gram form and of its in-LDS Jacobi
+# (TSVDM_GRAM_MAX_R, TSVDM_GRAM_LDS_MAX_R); placements of its Jacobi
+GRAM_MAX_R = 1024
+GRAM_LDS_MAX_R = 128
+GRAM_JACOBI = {"auto": 0, "rounds": 1, "lds": 2}
 STATUS = {
     0: "OK", -1: "E_ARG", -2: "E_SHAPE", -3: "E_NOT_ORTHO", -4: "E_WORKSPACE",
     -5: "E_NOCONV", -6: "E_NONFINITE", -7: "E_HIP", -8: "E_UNSUPPORTED", -9: "E_CAPACITY",
@@ -39,7 +44,7 @@ _SIGS = {
                                        c_int, c_double, c_int, _P, c_size_t, _P]),
     "tsvdm_slice_svd_gram_workspace_size": (c_int, [c_int64, c_int64, c_int64, POINTER(c_size_t)]),
     "tsvdm_slice_svd_gram": (c_int, [_P, c_int64, c_int64, c_int64, _P, _P, _P, _P, c_int, c_int, c_double,
-                                     c_int, _P, c_size_t, _P]),
+                                     c_int, c_int, _P, c_size_t, _P]),
     "tsvdm_pack_gram": (c_int, [_P, _P, _P, _P, c_int64, c_int64, c_int64, _P, _P, c_int64, _P, _P, _P, _P,
                                 _P, c_size_t, _P]),
     "tsvdm_slice_energy": (c_int, [_P, c_int, c_int64, c_int64, c_int64, _P, _P]),

@@ -240,17 +240,21 @@ int tsvdm_slice_svd_gram_workspace_size(int64_t m, int64_t p, int64_t n, size_t*
 
 int tsvdm_slice_svd_gram(const void* A_hat, int64_t m, int64_t p, int64_t n, void* B, double* s2,
                          double* shift, int32_t* status, int block, int max_sweeps, double tol,
-                         int host_poll, void* ws, size_t ws_bytes, void* stream) {
+                         int jacobi, int host_poll, void* ws, size_t ws_bytes, void* stream) {
     clear_error();
     TSVDM_TRY(check_shape(m, p, n));
     TSVDM_REQUIRE(A_hat && B && s2 && shift && status, TSVDM_E_ARG,
                   "A_hat, B, s2, shift and status must be non-NULL");
     TSVDM_REQUIRE(A_hat != B, TSVDM_E_ARG, "B must not alias A_hat");
-    TSVDM_REQUIRE(std::min(m, p) <= gram_svd_max_r(), TSVDM_E_SHAPE, "min(m, p) must be <= 1024");
+    TSVDM_REQUIRE(std::min(m, p) <= GRAM_MAX_R, TSVDM_E_SHAPE, "min(m, p) must be <= 1024");
     TSVDM_REQUIRE(block == 0 || block == 16 || block == 32, TSVDM_E_ARG, "block must be 0, 16 or 32");
     TSVDM_REQUIRE(max_sweeps >= 0 && max_sweeps <= 1000, TSVDM_E_ARG, "max_sweeps must be in [0, 1000]");
     TSVDM_REQUIRE(tol >= 0.0 && tol < 1.0 && std::isfinite(tol), TSVDM_E_ARG, "tol must lie in [0, 1)");
     TSVDM_REQUIRE(host_poll == 0 || host_poll == 1, TSVDM_E_ARG, "host_poll must be 0 or 1");
+    TSVDM_REQUIRE(jacobi == TSVDM_GRAM_AUTO || jacobi == TSVDM_GRAM_ROUNDS || jacobi == TSVDM_GRAM_LDS,
+                  TSVDM_E_ARG, "jacobi must be TSVDM_GRAM_AUTO, _ROUNDS or _LDS");
+    TSVDM_REQUIRE(jacobi != TSVDM_GRAM_LDS || std::min(m, p) <= GRAM_LDS_MAX_R, TSVDM_E_SHAPE,
+                  "TSVDM_GRAM_LDS needs min(m, p) <= 128");
     TSVDM_TRY(check_ws(ws, ws_bytes, gram_svd_workspace_bytes(m, p, n)));
     const int64_t r = std::min(m, p);
     JacobiOpts o = jacobi_default_opts(r, r, TSVDM_F32);
@@ -259,7 +263,7 @@ int tsvdm_slice_svd_gram(const void* A_hat, int64_t m, int64_t p, int64_t n, voi
     if (tol > 0.0) o.tol = tol;
     o.host_poll = host_poll;
     return run_gram_svd(static_cast<const float*>(A_hat), m, p, n, static_cast<float*>(B), s2, shift,
-                        status, o, ws, as_stream(stream));
+                        status, o, jacobi, ws, as_stream(stream));
 }
 
 int tsvdm_pack_gram(const void* A_hat, const void* B, const double* s2, const double* shift,
@@ -273,7 +277,7 @@ int tsvdm_pack_gram(const void* A_hat, const void* B, const double* s2, const do
     TSVDM_REQUIRE(capacity >= 0, TSVDM_E_ARG, "capacity must be >= 0");
     TSVDM_REQUIRE(capacity == 0 || (U_pk && G_pk && S_pk), TSVDM_E_ARG,
                   "U_pk, G_pk and S_pk must be non-NULL when capacity > 0");
-    TSVDM_REQUIRE(std::min(m, p) <= gram_svd_max_r(), TSVDM_E_SHAPE, "min(m, p) must be <= 1024");
+    TSVDM_REQUIRE(std::min(m, p) <= GRAM_MAX_R, TSVDM_E_SHAPE, "min(m, p) must be <= 1024");
     TSVDM_TRY(check_ws(ws, ws_bytes, pack_workspace_bytes(m, p, n)));
     return run_gram_pack(static_cast<const float*>(A_hat), static_cast<const float*>(B), s2, shift,
                          m, p, n, rho, offsets, capacity, static_cast<float*>(U_pk),

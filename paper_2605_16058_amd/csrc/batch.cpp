@@ -37,6 +37,22 @@ struct tsvdm_batch_plan_s {
     std::vector<int4> ttm_tasks, lr_tasks;
     std::vector<int2> jtasks;
     int64_t ttm_group[3] = {0, 0, 0}, back_group[3] = {0, 0, 0}, jgroup[2] = {0, 0};
+    // slice SVD form per item: FORM_ROT (rotation form), FORM_GRAM_ROUNDS
+    // (Gram form, Jacobi on the factor in the block rounds), FORM_GRAM_LDS
+    // (Gram form, in-LDS Jacobi).  Slices are numbered by form: rotation
+    // [0, n_rot), Gram in rounds [n_rot, n_jac), in LDS [n_jac, nslices);
+    // the batched Jacobi covers [0, n_jac), Gram slice gi is slice n_rot + gi
+    std::vector<char> form;
+    std::vector<int64_t> slice_base;
+    int64_t n_rot = 0, n_jac = 0, n_gram = 0, n_lds = 0;
+    std::vector<size_t> off_gG, off_gL, off_gsh, off_gfl, off_gperm;
+    std::vector<int2> gtasks;        // (Gram slice, lower-triangle tile)
+    std::vector<int4> ftasks;        // (Gram slice, kept-column tile, position tile)
+    std::vector<int> glists;         // Gram slices by Cholesky class, then in-LDS slices by class
+    int64_t chol_off[GRAM_CHOL_CLASSES] = {}, chol_cnt[GRAM_CHOL_CLASSES] = {};
+    int64_t lds_off[GRAM_LDS_CLASSES] = {}, lds_cnt[GRAM_LDS_CLASSES] = {};
+    int lds_maxr[GRAM_LDS_CLASSES] = {};
+    size_t o_gs = 0, o_gt = 0, o_gl = 0, o_gf = 0;
     // tables: pinned host copy (filled for one workspace address) and their
     // place in the workspace
     char* htab = nullptr;
@@ -55,6 +71,8 @@ struct tsvdm_batch_plan_s {
 };
 
 namespace {
+
+enum { FORM_ROT = 0, FORM_GRAM_ROUNDS = 1, FORM_GRAM_LDS = 2 };
 
 size_t esz(int dt) { return dt == TSVDM_F64 ? 8 : 4; }
 
@@ -109,12 +127,16 @@ size_t layout_tables(tsvdm_batch_plan_s* P) {
     P->o_back = place(sizeof(TtmProblem) * std::max<size_t>((size_t)P->n_back, 1));
     P->o_ttm = place(sizeof(int4) * P->ttm_tasks.size());
     P->o_bt = place(sizeof(int4) * std::max<size_t>((size_t)P->n_back_tasks, 1));
-    P->o_sl = place(sizeof(BatchSlice) * (size_t)P->nslices);
+    P->o_sl = place(sizeof(BatchSlice) * std::max<size_t>((size_t)P->n_jac, 1));
     P->o_jt = place(sizeof(int2) * P->jtasks.size());
     P->o_ps = place(sizeof(PackSlice) * (size_t)P->nslices);
     P->o_lr = place(sizeof(int4) * std::max<size_t>(P->lr_tasks.size(), 1));
     P->o_sel = place(sizeof(SelTensor) * P->items.size());
     P->o_err = place(sizeof(ErrJob) * std::max<size_t>((size_t)P->n_err, 1));
+    P->o_gs = place(sizeof(GramSlice) * std::max<size_t>((size_t)P->n_gram, 1));
+    P->o_gt = place(sizeof(int2) * std::max<size_t>(P->gtasks.size(), 1));
+    P->o_gl = place(sizeof(int) * std::max<size_t>(P->glists.size(), 1));
+    P->o_gf = place(sizeof(int4) * std::max<size_t>(P->ftasks.size(), 1));
     return align_up(off);
 }
 
@@ -122,16 +144,14 @@ size_t layout_tables(tsvdm_batch_plan_s* P) {
 int build_tables(tsvdm_batch_plan_s* P, char* ws) {
     const int cnt = (int)P->items.size();
     std::vector<TtmProblem> fwd(cnt), back;
-    std::vector<BatchSlice> sl;
-    std::vector<PackSlice> ps;
+    std::vector<BatchSlice> sl((size_t)P->n_jac);
+    std::vector<PackSlice> ps((size_t)P->nslices);
+    std::vector<GramSlice> gsl((size_t)P->n_gram);
     std::vector<SelTensor> sel(cnt);
     std::vector<ErrJob> err;
     std::vector<int4> back_by[3];
-    sl.reserve(P->nslices);
-    ps.reserve(P->nslices);
     const size_t e = esz(P->dt);
     const int VW = 16 / (int)e;
-    int64_t slice = 0;
     for (int t = 0; t < cnt; ++t) {
         const tsvdm_batch_item& it = P->items[t];
         const SliceGeom g = slice_geom(it.m, it.p);
@@ -148,7 +168,9 @@ int build_tables(tsvdm_batch_plan_s* P, char* ws) {
         const double ueps = P->dt == TSVDM_F64 ? 1.1102230246251565e-16 : 5.9604644775390625e-08;
         double tol = 8.0 * std::sqrt((double)std::max<int64_t>(g.L, 1)) * ueps;
         tol = P->dt == TSVDM_F64 ? std::max(tol, 1e-14) : std::max(tol, 2e-6);
-        for (int64_t i = 0; i < it.n; ++i, ++slice) {
+        const int form = P->form[t];
+        for (int64_t i = 0; i < it.n; ++i) {
+            const int64_t slice = P->slice_base[t] + i;
             BatchSlice d;
             d.A = ahat + (size_t)(i * it.m * it.p) * e;
             d.W = w + (size_t)(i * g.r * g.r) * e;
@@ -159,7 +181,34 @@ int build_tables(tsvdm_batch_plan_s* P, char* ws) {
             d.vec_w = (g.r % VW == 0) ? 1 : 0;
             d.tensor = t;
             d.tol = tol;
-            sl.push_back(d);
+            if (form != FORM_ROT) {
+                GramSlice gd;
+                gd.A = static_cast<const float*>(d.A);
+                gd.B = static_cast<float*>(d.W);
+                gd.G = reinterpret_cast<double*>(ws + P->off_gG[t]) + i * g.r * g.r;
+                gd.Lw = reinterpret_cast<double*>(ws + P->off_gL[t]) + i * g.r * g.r;
+                gd.s2 = d.s2;
+                gd.shift = reinterpret_cast<double*>(ws + P->off_gsh[t]) + i;
+                gd.flag = reinterpret_cast<int32_t*>(ws + P->off_gfl[t]) + i;
+                gd.perm = reinterpret_cast<int32_t*>(ws + P->off_gperm[t]) + i * g.r;
+                gd.g = g;
+                gd.tol = gram_tol(g.r);
+                gsl[(size_t)(slice - P->n_rot)] = gd;
+                if (form == FORM_GRAM_ROUNDS) {
+                    // the rounds orthogonalise the columns of the r x r
+                    // factor, accumulating no rotations
+                    BatchSlice f = d;
+                    f.A = gd.B;
+                    f.W = nullptr;
+                    f.g = slice_geom(g.r, g.r);
+                    f.vec_a = (g.r % VW == 0) ? 1 : 0;
+                    f.vec_w = 0;
+                    f.tol = gd.tol;
+                    sl[(size_t)slice] = f;
+                }
+            } else {
+                sl[(size_t)slice] = d;
+            }
             PackSlice q;
             q.A = d.A;
             q.W = d.W;
@@ -173,7 +222,7 @@ int build_tables(tsvdm_batch_plan_s* P, char* ws) {
             q.capacity = P->cap[t];
             q.C = d.A;  // the reconstruction overwrites A-hat, no longer needed
             q.status = nullptr;
-            ps.push_back(q);
+            ps[(size_t)slice] = q;
         }
         SelTensor s;
         s.s2 = s2;
@@ -217,7 +266,7 @@ int build_tables(tsvdm_batch_plan_s* P, char* ws) {
         back_tasks.insert(back_tasks.end(), back_by[q].begin(), back_by[q].end());
     }
     if ((int64_t)back.size() != P->n_back || (int64_t)back_tasks.size() != P->n_back_tasks ||
-        (int)err.size() != P->n_err || (int64_t)sl.size() != P->nslices) {
+        (int)err.size() != P->n_err || P->n_jac + P->n_gram - (P->n_jac - P->n_rot) != P->nslices) {
         set_error("internal: batch table sizes differ from the plan's layout");
         return TSVDM_E_ARG;
     }
@@ -240,6 +289,10 @@ int build_tables(tsvdm_batch_plan_s* P, char* ws) {
     put(P->o_lr, P->lr_tasks.data(), sizeof(int4) * P->lr_tasks.size());
     put(P->o_sel, sel.data(), sizeof(SelTensor) * sel.size());
     put(P->o_err, err.data(), sizeof(ErrJob) * err.size());
+    put(P->o_gs, gsl.data(), sizeof(GramSlice) * gsl.size());
+    put(P->o_gt, P->gtasks.data(), sizeof(int2) * P->gtasks.size());
+    put(P->o_gl, P->glists.data(), sizeof(int) * P->glists.size());
+    put(P->o_gf, P->ftasks.data(), sizeof(int4) * P->ftasks.size());
     P->tables_ws = ws;
     return TSVDM_OK;
 }
@@ -265,19 +318,40 @@ int run_stages(tsvdm_batch_plan_s* P, char* ws, int host_poll, int32_t* status, 
     int rc;
     TSVDM_HIP_CHECK(hipMemcpyAsync(D, P->htab, P->tab_bytes, hipMemcpyHostToDevice, st));
     int32_t* jstatus = reinterpret_cast<int32_t*>(ws + P->off_ctl);
+    int32_t* gstatus = reinterpret_cast<int32_t*>(ws + P->off_ctl + 64);
     void* ctl_ws = ws + P->off_ctl + 256;
     clear_status<<<1, 64, 0, st>>>(status);
+    TSVDM_LAUNCH_CHECK();
+    clear_status<<<1, 64, 0, st>>>(jstatus);
     TSVDM_LAUNCH_CHECK();
     // 1. transform
     rc = run_ttm_batch(reinterpret_cast<const TtmProblem*>(D + P->o_fwd), cnt,
                        reinterpret_cast<const int4*>(D + P->o_ttm), P->ttm_group,
                        P->in_dt, P->dt, P->ttm_compute, 0, st);
     if (rc) return rc;
-    // 2. slice SVDs
-    rc = run_jacobi_batch(P->dt, reinterpret_cast<const BatchSlice*>(D + P->o_sl), P->nslices,
-                          reinterpret_cast<const int2*>(D + P->o_jt), P->jgroup, P->max_steps,
-                          host_poll, ctl_ws, jstatus, st);
-    if (rc) return rc;
+    // 2. slice SVDs: FP64 Gram and Cholesky factor of the Gram-form slices;
+    //    the block rounds of the rotation-form slices and of the factors
+    //    whose Jacobi runs in the rounds; the in-LDS Jacobi of the others
+    const GramSlice* gs = reinterpret_cast<const GramSlice*>(D + P->o_gs);
+    const int* glists = reinterpret_cast<const int*>(D + P->o_gl);
+    if (P->n_gram > 0) {
+        rc = run_gram_prep_batch(gs, P->n_gram, reinterpret_cast<const int2*>(D + P->o_gt),
+                                 (int64_t)P->gtasks.size(), glists, P->chol_off, P->chol_cnt, st);
+        if (rc) return rc;
+    }
+    if (P->n_jac > 0) {
+        rc = run_jacobi_batch(P->dt, reinterpret_cast<const BatchSlice*>(D + P->o_sl), P->n_jac,
+                              reinterpret_cast<const int2*>(D + P->o_jt), P->jgroup, P->max_steps,
+                              host_poll, ctl_ws, jstatus, st);
+        if (rc) return rc;
+        rc = run_gram_unshift_batch(gs, P->n_jac - P->n_rot, st);
+        if (rc) return rc;
+    }
+    if (P->n_lds > 0) {
+        rc = run_gram_lds_batch(gs, glists, P->lds_off, P->lds_cnt, P->lds_maxr, P->max_sweeps,
+                                gs + (P->n_jac - P->n_rot), P->n_lds, gstatus, st);
+        if (rc) return rc;
+    }
     // 3. ranks
     rc = run_select_batch(reinterpret_cast<const SelTensor*>(D + P->o_sel), cnt, st);
     if (rc) return rc;
@@ -285,8 +359,15 @@ int run_stages(tsvdm_batch_plan_s* P, char* ws, int host_poll, int32_t* status, 
     set_pack_status<<<(unsigned)((P->nslices + 255) / 256), 256, 0, st>>>(
         reinterpret_cast<PackSlice*>(D + P->o_ps), P->nslices, status);
     TSVDM_LAUNCH_CHECK();
-    rc = run_pack_batch(P->dt, reinterpret_cast<const PackSlice*>(D + P->o_ps), P->nslices, st);
-    if (rc) return rc;
+    if (P->n_rot > 0) {
+        rc = run_pack_batch(P->dt, reinterpret_cast<const PackSlice*>(D + P->o_ps), P->n_rot, st);
+        if (rc) return rc;
+    }
+    if (P->n_gram > 0) {
+        rc = run_gram_pack_batch(gs, reinterpret_cast<const PackSlice*>(D + P->o_ps) + P->n_rot, P->n_gram,
+                                 reinterpret_cast<const int4*>(D + P->o_gf), (int64_t)P->ftasks.size(), st);
+        if (rc) return rc;
+    }
     // 5. reconstruction and back-transform
     if (!P->lr_tasks.empty()) {
         rc = run_lowrank_batch(P->dt, reinterpret_cast<const PackSlice*>(D + P->o_ps),
@@ -308,6 +389,10 @@ int run_stages(tsvdm_batch_plan_s* P, char* ws, int host_poll, int32_t* status, 
     }
     merge_status<<<1, 64, 0, st>>>(status, jstatus);
     TSVDM_LAUNCH_CHECK();
+    if (P->n_lds > 0) {
+        merge_status<<<1, 64, 0, st>>>(status, gstatus);
+        TSVDM_LAUNCH_CHECK();
+    }
     return TSVDM_OK;
 }
 
@@ -350,12 +435,51 @@ int tsvdm_batch_plan_create(const tsvdm_batch_item* items, int32_t count, int in
         wsoff += bytes;
         return o;
     };
+    // FP32 items with min(m, p) <= GRAM_MAX_R take the Gram form, the
+    // others the rotation form.  The Gram form's Jacobi runs in LDS only when
+    // every item is that small: the block rounds run for as many steps as
+    // the largest slice needs, and small slices then ride along at a lower
+    // cost than a separate in-LDS launch (latency bound, one workgroup per
+    // slice), even one overlapped on a second stream.
+    bool all_small = dtype == TSVDM_F32;
+    for (const auto& it : P->items) all_small = all_small && std::min(it.m, it.p) <= GRAM_LDS_MAX_R;
+    for (const auto& it : P->items) {
+        const int64_t r = std::min(it.m, it.p);
+        P->form.push_back(dtype != TSVDM_F32 || r > GRAM_MAX_R ? FORM_ROT
+                          : (all_small ? FORM_GRAM_LDS : FORM_GRAM_ROUNDS));
+    }
+    P->slice_base.assign(count, 0);
+    for (int pass = FORM_ROT; pass <= FORM_GRAM_LDS; ++pass)
+        for (int t = 0; t < count; ++t) {
+            if (P->form[t] != pass) continue;
+            P->slice_base[t] = P->nslices;
+            P->nslices += P->items[t].n;
+            if (pass == FORM_ROT) P->n_rot += P->items[t].n;
+            if (pass != FORM_GRAM_LDS) P->n_jac += P->items[t].n;
+            if (pass != FORM_ROT) P->n_gram += P->items[t].n;
+            if (pass == FORM_GRAM_LDS) P->n_lds += P->items[t].n;
+        }
+    std::vector<int> ccls[GRAM_CHOL_CLASSES], lcls[GRAM_LDS_CLASSES];
     int max_rounds = 1;
     std::vector<int4> ttm_by[3];
     std::vector<int2> jt_by[2];
     for (int t = 0; t < count; ++t) {
         const tsvdm_batch_item& it = P->items[t];
         const SliceGeom g = slice_geom(it.m, it.p);
+        const int form = P->form[t];
+        if (form != FORM_ROT) {
+            P->off_gG.push_back(take((size_t)(g.r * g.r * it.n) * 8));
+            P->off_gL.push_back(take((size_t)(g.r * g.r * it.n) * 8));
+            P->off_gsh.push_back(take((size_t)it.n * 8));
+            P->off_gfl.push_back(take((size_t)it.n * 4));
+            P->off_gperm.push_back(take((size_t)(g.r * it.n) * 4));
+        } else {
+            P->off_gG.push_back(0);
+            P->off_gL.push_back(0);
+            P->off_gsh.push_back(0);
+            P->off_gfl.push_back(0);
+            P->off_gperm.push_back(0);
+        }
         P->off_ahat.push_back(take((size_t)(it.m * it.p * it.n) * e));
         P->off_w.push_back(take((size_t)(g.r * g.r * it.n) * e));
         P->off_s2.push_back(take((size_t)(g.r * it.n) * 8));
@@ -379,7 +503,7 @@ int tsvdm_batch_plan_create(const tsvdm_batch_item* items, int32_t count, int in
         const int b = P->nb2[t] / 2;
         const int nb = (int)((g.r + b - 1) / b);
         const int nbe = nb + (nb & 1);
-        max_rounds = std::max(max_rounds, nbe - 1);
+        if (form != FORM_GRAM_LDS) max_rounds = std::max(max_rounds, nbe - 1);
         // task tables
         int64_t n_rt;
         int n_ct;
@@ -389,14 +513,38 @@ int tsvdm_batch_plan_create(const tsvdm_batch_item* items, int32_t count, int in
             for (int ct = 0; ct < n_ct; ++ct) ttm_by[shp - 1].push_back(int4{t, (int)rt, ct, 0});
         const int ta = (int)((it.m + 63) / 64), tb = (int)((it.p + 63) / 64);
         std::vector<int2>& jt = jt_by[P->nb2[t] == 64 ? 1 : 0];
+        const int nt = (int)((g.r + 63) / 64), ntri = nt * (nt + 1) / 2;
+        const int ntl = (int)((g.L + 63) / 64);
+        const int lcl = gram_lds_class(g.r), ccl = gram_chol_class(g.r);
         for (int64_t i = 0; i < it.n; ++i) {
-            const int s = (int)(P->nslices + i);
-            for (int k = 0; k < nbe / 2; ++k) jt.push_back(int2{s, k});
+            const int s = (int)(P->slice_base[t] + i);
+            if (form != FORM_ROT) {
+                const int gi = (int)(s - P->n_rot);
+                for (int q = 0; q < ntri; ++q) P->gtasks.push_back(int2{gi, q});
+                for (int tc = 0; tc < nt; ++tc)
+                    for (int tt = 0; tt < ntl; ++tt) P->ftasks.push_back(int4{gi, tc, tt, 0});
+                ccls[ccl].push_back(gi);
+            }
+            if (form == FORM_GRAM_LDS) {
+                lcls[lcl].push_back((int)(s - P->n_rot));
+                P->lds_maxr[lcl] = std::max(P->lds_maxr[lcl], (int)g.r);
+            } else {
+                for (int k = 0; k < nbe / 2; ++k) jt.push_back(int2{s, k});
+            }
             if (it.A_rec)
                 for (int y = 0; y < tb; ++y)
                     for (int x = 0; x < ta; ++x) P->lr_tasks.push_back(int4{s, x, y, 0});
         }
-        P->nslices += it.n;
+    }
+    for (int c = 0; c < GRAM_CHOL_CLASSES; ++c) {
+        P->chol_off[c] = (int64_t)P->glists.size();
+        P->chol_cnt[c] = (int64_t)ccls[c].size();
+        P->glists.insert(P->glists.end(), ccls[c].begin(), ccls[c].end());
+    }
+    for (int c = 0; c < GRAM_LDS_CLASSES; ++c) {
+        P->lds_off[c] = (int64_t)P->glists.size();
+        P->lds_cnt[c] = (int64_t)lcls[c].size();
+        P->glists.insert(P->glists.end(), lcls[c].begin(), lcls[c].end());
     }
     for (int q = 0; q < 3; ++q) {
         P->ttm_group[q] = (int64_t)ttm_by[q].size();
@@ -422,7 +570,8 @@ int tsvdm_batch_plan_create(const tsvdm_batch_item* items, int32_t count, int in
     P->off_ctl = take(256 + jacobi_batch_ctl_bytes(P->nslices, P->max_steps));
     P->ws_total = align_up(wsoff);
     if ((int64_t)P->jtasks.size() >= ((int64_t)1 << 31) || (int64_t)P->ttm_tasks.size() >= ((int64_t)1 << 31) ||
-        (int64_t)P->lr_tasks.size() >= ((int64_t)1 << 31)) {
+        (int64_t)P->lr_tasks.size() >= ((int64_t)1 << 31) || (int64_t)P->gtasks.size() >= ((int64_t)1 << 31) ||
+        (int64_t)P->ftasks.size() >= ((int64_t)1 << 31)) {
         delete P;
         set_error("batch too large for one launch per stage");
         return TSVDM_E_SHAPE;
@@ -445,6 +594,12 @@ int tsvdm_batch_run(tsvdm_batch_plan P, void* ws, size_t ws_bytes, int host_poll
     }
     hipStream_t st = as_stream(stream);
     char* base = static_cast<char*>(ws);
+    if (P->n_lds > 0) {
+        // the in-LDS Jacobi's dynamic LDS limit (a host attribute, set once
+        // per process, before any capture below)
+        const int rc = gram_lds_prepare();
+        if (rc) return rc;
+    }
     if (P->tables_ws != ws) {
         // tables embed workspace addresses; a captured graph of another
         // workspace is stale

@@ -920,7 +920,8 @@ __global__ void jacobi_sweep_end_batch(const BatchSlice* __restrict__ sl, int64_
     ctl[i] = c;
 }
 
-// W = I and a clean control word for every slice of a batch
+// W = I (slices that accumulate rotations) and a clean control word for
+// every slice of a batch
 template <class T>
 __global__ void jacobi_init_batch(const BatchSlice* __restrict__ sl, JacobiCtl* __restrict__ ctl,
                                   int* __restrict__ remaining, int max_steps,
@@ -929,7 +930,8 @@ __global__ void jacobi_init_batch(const BatchSlice* __restrict__ sl, JacobiCtl* 
     const BatchSlice d = sl[blockIdx.x];
     const int64_t r = d.g.r;
     T* W = static_cast<T*>(d.W);
-    for (int64_t e = threadIdx.x; e < r * r; e += blockDim.x) W[e] = (e % r == e / r) ? T(1) : T(0);
+    if (W)
+        for (int64_t e = threadIdx.x; e < r * r; e += blockDim.x) W[e] = (e % r == e / r) ? T(1) : T(0);
     if (threadIdx.x == 0) {
         JacobiCtl c;
         c.maxcos_bits = 0ull; c.done = 0; c.sweeps = 0; c.nonfinite = 0; c.pad = 0;

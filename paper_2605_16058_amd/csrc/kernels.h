@@ -19,7 +19,7 @@ struct TtmProblem {       // Y = X x_3 (scale * op(M)) for one tensor
 
 struct BatchSlice {       // one frontal slice for the batched Jacobi
     void* A;              // slice base (m*p elements)
-    void* W;              // r*r rotation accumulator
+    void* W;              // r*r rotation accumulator, or null (none kept)
     double* s2;           // r squared singular values
     SliceGeom g;
     int nbe;              // block count padded to even
@@ -42,6 +42,44 @@ struct PackSlice {        // one slice for batched packing and reconstruction
     void* C;              // reconstruction target slice (m*p)
     int32_t* status;
 };
+
+// Gram form (FP32): FP64 Gram, shifted Cholesky factor, one-sided Jacobi on
+// the factor.  min(m, p) <= GRAM_MAX_R; the Jacobi runs in LDS (one
+// workgroup per slice) for r <= GRAM_LDS_MAX_R, else in the block rounds.
+constexpr int GRAM_MAX_R = TSVDM_GRAM_MAX_R;
+constexpr int GRAM_LDS_MAX_R = TSVDM_GRAM_LDS_MAX_R;
+constexpr int GRAM_LDS_CLASSES = 4;    // in-LDS size classes (r <= 32, 64, 96, 128)
+constexpr int GRAM_CHOL_CLASSES = 4;   // Cholesky size classes (r <= 128, 256, 512, 1024)
+struct GramSlice {        // one slice of a batch on the Gram form
+    const float* A;       // A-hat slice (m x p), read only
+    float* B;             // r x r factor, then its orthogonalised columns
+    double* G;            // r x r FP64 Gram matrix (workspace)
+    double* Lw;           // r x r FP64 factor (workspace)
+    double* s2;           // r squared singular values
+    double* shift;        // the Cholesky shift of the slice
+    int32_t* flag;        // in-LDS Jacobi: 0 converged, 1 sweep limit, 2 NaN / Inf
+    int32_t* perm;        // r: descending order of s2
+    SliceGeom g;
+    double tol;           // convergence threshold on |cos|
+};
+// G and the Cholesky factor of every Gram slice; lists: Gram slice indices
+// grouped by Cholesky size class (host offsets and counts)
+int run_gram_prep_batch(const GramSlice* gs, int64_t ngram, const int2* gram_tasks, int64_t ntasks,
+                        const int* lists, const int64_t* class_off, const int64_t* class_cnt,
+                        hipStream_t st);
+// s2 <- max(s2 - shift, 0) for n Gram slices whose Jacobi ran in the rounds
+int run_gram_unshift_batch(const GramSlice* gs, int64_t n, hipStream_t st);
+// in-LDS Jacobi of the listed slices (grouped by in-LDS size class, with the
+// largest r per class); status from the flags of gs_lds[0, n_lds)
+int run_gram_lds_batch(const GramSlice* gs, const int* lists, const int64_t* class_off,
+                       const int64_t* class_cnt, const int* class_maxr, int max_sweeps,
+                       const GramSlice* gs_lds, int64_t n_lds, int32_t* status, hipStream_t st);
+int run_gram_pack_batch(const GramSlice* gs, const PackSlice* ps, int64_t ngram, const int4* ftasks,
+                        int64_t nft, hipStream_t st);
+int gram_lds_class(int64_t r);          // in-LDS size class of r (0..3)
+int gram_chol_class(int64_t r);         // Cholesky size class of r (0..3)
+int gram_lds_prepare();                 // allow the dynamic LDS of every class (host, not under capture)
+double gram_tol(int64_t r);             // default convergence threshold of the Gram form
 
 int run_pack_batch(int dt, const PackSlice* ps, int64_t nslices, hipStream_t st);
 int run_lowrank_batch(int dt, const PackSlice* ps, const int4* tasks, int64_t ntasks,
@@ -121,9 +159,10 @@ struct JacobiOpts {
 size_t jacobi_workspace_bytes(int64_t n);
 // Gram form of the FP32 slice SVDs (precond.hip)
 size_t gram_svd_workspace_bytes(int64_t m, int64_t p, int64_t n);
-int64_t gram_svd_max_r();
+// jacobi: TSVDM_GRAM_AUTO / ROUNDS / LDS (checked by the caller)
 int run_gram_svd(const float* A_hat, int64_t m, int64_t p, int64_t n, float* B, double* s2,
-                 double* shift, int32_t* status, const JacobiOpts& o, void* ws, hipStream_t st);
+                 double* shift, int32_t* status, const JacobiOpts& o, int jacobi, void* ws,
+                 hipStream_t st);
 int run_gram_pack(const float* A_hat, const float* B, const double* s2, const double* shift,
                   int64_t m, int64_t p, int64_t n, const int32_t* rho, const int64_t* offsets,
                   int64_t capacity, float* U_pk, float* G_pk, float* S_pk, int32_t* status,

@@ -26,6 +26,8 @@
 // Against rotating the slice itself, each Jacobi pair touches vectors of
 // length r instead of L and no rotation matrix: for the 512 x 1024 climate
 // slices 2 w^2 (2 r) instead of 2 w^2 (2 L + r) flops per rotating pair.
+#include <mutex>
+
 #include "angle.h"
 #include "common.h"
 #include "kernels.h"
@@ -53,15 +55,11 @@ __device__ __forceinline__ void tri_tile(int q, int& ti, int& tj) {
 // that the stores run along i (G is column-major: G[i + j r]).  The next K
 // chunk is loaded into registers while the MFMAs of the current one run;
 // two LDS buffers, one barrier per chunk.
-__global__ __launch_bounds__(256) void pc_gram(const float* __restrict__ A, SliceGeom g, int ntri,
-                                               double* __restrict__ G) {
+__device__ __forceinline__ void gram_tile(const float* __restrict__ X, const SliceGeom& g, int ti, int tj,
+                                          double* __restrict__ Gs) {
     __shared__ double sa[2][64][GK + 1];   // operand rows i
     __shared__ double sb[2][64][GK + 1];   // operand rows j
-    const int64_t s = blockIdx.x / ntri;
-    int ti, tj;
-    tri_tile((int)(blockIdx.x % ntri), ti, tj);
     const int64_t r = g.r, L = g.L, vs = g.vs, es = g.es;
-    const float* X = A + s * g.m * g.p;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, lr = lane & 15, lg = lane >> 4;
     const int64_t i0 = (int64_t)ti * 64, j0 = (int64_t)tj * 64;
     const bool rows = g.rows != 0;
@@ -115,7 +113,6 @@ __global__ __launch_bounds__(256) void pc_gram(const float* __restrict__ A, Slic
         }
         buf ^= 1;
     }
-    double* Gs = G + s * r * r;
 #pragma unroll
     for (int c = 0; c < 4; ++c) {
         const int64_t i = i0 + 16 * c + lr;
@@ -127,6 +124,24 @@ __global__ __launch_bounds__(256) void pc_gram(const float* __restrict__ A, Slic
     }
 }
 
+__global__ __launch_bounds__(256) void pc_gram(const float* __restrict__ A, SliceGeom g, int ntri,
+                                               double* __restrict__ G) {
+    const int64_t s = blockIdx.x / ntri;
+    int ti, tj;
+    tri_tile((int)(blockIdx.x % ntri), ti, tj);
+    gram_tile(A + s * g.m * g.p, g, ti, tj, G + s * g.r * g.r);
+}
+
+// batch: task (Gram slice, lower-triangle tile)
+__global__ __launch_bounds__(256) void pc_gram_batch(const GramSlice* __restrict__ gs,
+                                                     const int2* __restrict__ tasks) {
+    const int2 t = tasks[blockIdx.x];
+    const GramSlice d = gs[t.x];
+    int ti, tj;
+    tri_tile(t.y, ti, tj);
+    gram_tile(d.A, d.g, ti, tj, d.G);
+}
+
 // L L^T = G + s I for the slice blockIdx.x (lower triangle of G read; L
 // written to Lw in FP64 and to Lo in FP32 with zeros above the diagonal).
 // Left-looking with panels of CB columns: the panel's rows are updated with
@@ -135,16 +150,12 @@ __global__ __launch_bounds__(256) void pc_gram(const float* __restrict__ A, Slic
 // against it.  A pivot <= 0 (rounding of a singular G + s I) gives a zero
 // column.  Fixed operation order: the result does not depend on timing.
 template <int MAXR>
-__global__ __launch_bounds__(256) void pc_chol(const double* __restrict__ G, int64_t r, double cshift,
-                                               double* __restrict__ Lw, float* __restrict__ Lo,
-                                               double* __restrict__ shift) {
+__device__ __forceinline__ void chol_slice(const double* __restrict__ Gs, int64_t r, double cshift,
+                                           double* __restrict__ Ls, float* __restrict__ Os,
+                                           double* __restrict__ shift_out) {
     constexpr int PLD = CB + 1;
     __shared__ double P[MAXR * PLD];
     __shared__ double red[256];
-    const int64_t s = blockIdx.x;
-    const double* Gs = G + s * r * r;
-    double* Ls = Lw + s * r * r;
-    float* Os = Lo + s * r * r;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, lr = lane & 15, lg = lane >> 4;
     // trace in a fixed order
     double tr = 0.0;
@@ -156,7 +167,7 @@ __global__ __launch_bounds__(256) void pc_chol(const double* __restrict__ G, int
         __syncthreads();
     }
     const double sh = cshift * red[0];
-    if (tid == 0) shift[s] = sh;
+    if (tid == 0) *shift_out = sh;
     for (int64_t k0 = 0; k0 < r; k0 += CB) {
         const int64_t nrow = r - k0;
         const int nc = (int)(nrow < CB ? nrow : CB);
@@ -251,6 +262,23 @@ __global__ __launch_bounds__(256) void pc_chol(const double* __restrict__ G, int
     }
 }
 
+template <int MAXR>
+__global__ __launch_bounds__(256) void pc_chol(const double* __restrict__ G, int64_t r, double cshift,
+                                               double* __restrict__ Lw, float* __restrict__ Lo,
+                                               double* __restrict__ shift) {
+    const int64_t s = blockIdx.x;
+    chol_slice<MAXR>(G + s * r * r, r, cshift, Lw + s * r * r, Lo + s * r * r, shift + s);
+}
+
+// batch: one workgroup per Gram slice listed (one size class, r <= MAXR)
+template <int MAXR>
+__global__ __launch_bounds__(256) void pc_chol_batch(const GramSlice* __restrict__ gs,
+                                                     const int* __restrict__ list) {
+    const GramSlice d = gs[list[blockIdx.x]];
+    const double cshift = (double)(d.g.L + d.g.r) * 1.1102230246251565e-16;
+    chol_slice<MAXR>(d.G, d.g.r, cshift, d.Lw, d.B, d.shift);
+}
+
 // seat -> player of the circle tournament over N (even) players in round
 // `round` (seat 0 fixed, the others advance one seat per round)
 __device__ __forceinline__ int lds_player(int seat, int round, int N) {
@@ -298,17 +326,15 @@ __device__ __forceinline__ double row_sum16(double x) {
 // Then s2 = max(||b_j||^2 - shift, 0) in FP64 and flag = 0 (converged), 1
 // (sweep limit) or 2 (NaN / Inf met).
 template <int RMAX>
-__global__ __launch_bounds__(256) void pc_jacobi_lds(float* __restrict__ B, int64_t r, double tol,
-                                                     int max_sweeps, const double* __restrict__ shift,
-                                                     double* __restrict__ s2, int32_t* __restrict__ flag) {
+__device__ __forceinline__ void jacobi_lds_slice(float* __restrict__ Bs, int rr, double tol, int max_sweeps,
+                                                 double shs, double* __restrict__ s2s,
+                                                 int32_t* __restrict__ flag_out) {
     constexpr int E = RMAX / 16;     // elements per lane and column
     extern __shared__ float X[];     // column j at X[j * RP]
     __shared__ double gmax[16];
     __shared__ int gbad[16];
-    const int64_t s = blockIdx.x;
-    float* Bs = B + s * r * r;
     const int tid = threadIdx.x, grp = tid >> 4, l = tid & 15;
-    const int rr = (int)r, RP = rr + 1;
+    const int RP = rr + 1;
     for (int idx = tid; idx < rr * rr; idx += 256) {
         const int j = idx / rr, i = idx - j * rr;
         X[j * RP + i] = Bs[idx];
@@ -401,7 +427,6 @@ __global__ __launch_bounds__(256) void pc_jacobi_lds(float* __restrict__ B, int6
     }
     // squared norms (fixed order: lane sums, then the row sum) and the
     // factor back to memory
-    const double shs = shift[s];
     for (int j = grp; j < rr; j += 16) {
         double a = 0.0;
 #pragma unroll
@@ -410,13 +435,43 @@ __global__ __launch_bounds__(256) void pc_jacobi_lds(float* __restrict__ B, int6
             if (i < rr) { const double v = X[j * RP + i]; a = fma(v, v, a); }
         }
         a = row_sum16(a);
-        if (l == 0) { const double v = a - shs; s2[s * r + j] = v > 0.0 ? v : 0.0; }
+        if (l == 0) { const double v = a - shs; s2s[j] = v > 0.0 ? v : 0.0; }
     }
     for (int idx = tid; idx < rr * rr; idx += 256) {
         const int j = idx / rr, i = idx - j * rr;
         Bs[idx] = X[j * RP + i];
     }
-    if (tid == 0) flag[s] = bad ? 2 : (conv ? 0 : 1);
+    if (tid == 0) *flag_out = bad ? 2 : (conv ? 0 : 1);
+}
+
+template <int RMAX>
+__global__ __launch_bounds__(256) void pc_jacobi_lds(float* __restrict__ B, int64_t r, double tol,
+                                                     int max_sweeps, const double* __restrict__ shift,
+                                                     double* __restrict__ s2, int32_t* __restrict__ flag) {
+    const int64_t s = blockIdx.x;
+    jacobi_lds_slice<RMAX>(B + s * r * r, (int)r, tol, max_sweeps, shift[s], s2 + s * r, flag + s);
+}
+
+// batch: the Gram slices listed in `list` (one size class of r)
+template <int RMAX>
+__global__ __launch_bounds__(256) void pc_jacobi_lds_batch(const GramSlice* __restrict__ gs,
+                                                           const int* __restrict__ list, int max_sweeps) {
+    const GramSlice d = gs[list[blockIdx.x]];
+    jacobi_lds_slice<RMAX>(d.B, (int)d.g.r, d.tol, max_sweeps, *d.shift, d.s2, d.flag);
+}
+
+// batch: status word from the Gram slices' flags
+__global__ void pc_gram_status(const GramSlice* __restrict__ gs, int64_t n, int32_t* __restrict__ status) {
+    __shared__ int nf, nc;
+    if (threadIdx.x == 0) { nf = 0; nc = 0; }
+    __syncthreads();
+    for (int64_t i = threadIdx.x; i < n; i += blockDim.x) {
+        const int f = *gs[i].flag;
+        if (f == 2) atomicOr(&nf, 1);
+        else if (f == 1) atomicOr(&nc, 1);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) *status = nf ? TSVDM_E_NONFINITE : (nc ? TSVDM_E_NOCONV : TSVDM_OK);
 }
 
 __global__ void pc_flags_status(const int32_t* __restrict__ flag, int64_t n, int32_t* __restrict__ status) {
@@ -439,6 +494,17 @@ __global__ void pc_unshift(double* __restrict__ s2, const double* __restrict__ s
     if (idx >= r * n) return;
     const double v = s2[idx] - shift[idx / r];
     s2[idx] = v > 0.0 ? v : 0.0;
+}
+
+// batch: pc_unshift for Gram slices whose Jacobi ran in the block rounds,
+// one workgroup per slice
+__global__ __launch_bounds__(256) void pc_unshift_batch(const GramSlice* __restrict__ gs) {
+    const GramSlice d = gs[blockIdx.x];
+    const double sh = *d.shift;
+    for (int64_t j = threadIdx.x; j < d.g.r; j += blockDim.x) {
+        const double v = d.s2[j] - sh;
+        d.s2[j] = v > 0.0 ? v : 0.0;
+    }
 }
 
 // Short-side factor from B: kept column c (sorted position c, index j =
@@ -482,34 +548,27 @@ __global__ __launch_bounds__(256) void pc_pack_short(const float* __restrict__ B
 // along the stored contiguous index (c for wide, t for tall).  K chunks of
 // FK vector indices v, loaded into registers one chunk ahead.
 template <bool ROWS>
-__global__ __launch_bounds__(256) void pc_factor(const float* __restrict__ A, const float* __restrict__ B,
-                                                 const double* __restrict__ s2,
-                                                 const double* __restrict__ shift, SliceGeom g,
-                                                 const int32_t* __restrict__ rho,
-                                                 const int64_t* __restrict__ offsets, int64_t capacity,
-                                                 const int32_t* __restrict__ perm, int tiles_t,
-                                                 float* __restrict__ out) {
+__device__ __forceinline__ void factor_tile(const float* __restrict__ X, const float* __restrict__ Bs,
+                                            const double* __restrict__ s2s, double shs, const SliceGeom& g,
+                                            int64_t kr, int64_t off, int64_t capacity,
+                                            const int32_t* __restrict__ perm_s, int tc_idx, int tt_idx,
+                                            float* __restrict__ out) {
     __shared__ float sx[2][64][FK + 1];   // X(v, t): [t][v]
     __shared__ float sbk[2][64][FK + 1];  // b_perm(c)(v): [c][v]
     __shared__ double scl[64];
     __shared__ int jc[64];
-    const int64_t s = blockIdx.y;
-    const int64_t kr = rho[s], off = offsets[s];
-    const int tc_idx = (int)(blockIdx.x / tiles_t), tt_idx = (int)(blockIdx.x % tiles_t);
     const int64_t c0 = (int64_t)tc_idx * 64, t0 = (int64_t)tt_idx * 64;
     if (kr <= 0 || off + kr > capacity || c0 >= kr) return;
     const int64_t r = g.r, L = g.L, vs = g.vs, es = g.es;
-    const float* X = A + s * g.m * g.p;
-    const float* Bs = B + s * r * r;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, lr = lane & 15, lg = lane >> 4;
     if (tid < 64) {
         const int64_t c = c0 + tid;
         int j = 0;
         double sc = 0.0;
         if (c < kr) {
-            j = perm[s * r + c];
-            const double sg2 = s2[s * r + j] > 0.0 ? s2[s * r + j] : 0.0;
-            const double nb = sqrt(sg2 + shift[s]);
+            j = perm_s[c];
+            const double sg2 = s2s[j] > 0.0 ? s2s[j] : 0.0;
+            const double nb = sqrt(sg2 + shs);
             const double sg = sqrt(sg2);
             sc = nb > 0.0 ? (ROWS ? 1.0 / nb : (sg > 0.0 ? 1.0 / (nb * sg) : 0.0)) : 0.0;
         }
@@ -616,15 +675,129 @@ __global__ __launch_bounds__(256) void pc_factor(const float* __restrict__ A, co
     }
 }
 
-}  // namespace
+template <bool ROWS>
+__global__ __launch_bounds__(256) void pc_factor(const float* __restrict__ A, const float* __restrict__ B,
+                                                 const double* __restrict__ s2,
+                                                 const double* __restrict__ shift, SliceGeom g,
+                                                 const int32_t* __restrict__ rho,
+                                                 const int64_t* __restrict__ offsets, int64_t capacity,
+                                                 const int32_t* __restrict__ perm, int tiles_t,
+                                                 float* __restrict__ out) {
+    const int64_t s = blockIdx.y, r = g.r;
+    factor_tile<ROWS>(A + s * g.m * g.p, B + s * r * r, s2 + s * r, shift[s], g, rho[s], offsets[s],
+                      capacity, perm + s * r, (int)(blockIdx.x / tiles_t), (int)(blockIdx.x % tiles_t), out);
+}
 
-// dynamic LDS of the in-LDS Jacobi: r x (r + 1) floats
+// batch: task (Gram slice, output tile); wide slices write G_pk, tall U_pk
+__global__ __launch_bounds__(256) void pc_factor_batch(const GramSlice* __restrict__ gs,
+                                                       const PackSlice* __restrict__ ps,
+                                                       const int4* __restrict__ tasks) {
+    const int4 t = tasks[blockIdx.x];
+    const GramSlice d = gs[t.x];
+    const PackSlice q = ps[t.x];
+    if (d.g.rows)
+        factor_tile<true>(d.A, d.B, d.s2, *d.shift, d.g, *q.rho, *q.off, q.capacity, d.perm, t.y, t.z,
+                          static_cast<float*>(q.G_pk));
+    else
+        factor_tile<false>(d.A, d.B, d.s2, *d.shift, d.g, *q.rho, *q.off, q.capacity, d.perm, t.y, t.z,
+                           static_cast<float*>(q.U_pk));
+}
+
+// batch: per Gram slice, the descending order of its squared singular
+// values (ties by index, the order of pack_sort), its kept singular values
+// and short-side factor (as pc_pack_short); a slice whose block would pass
+// the capacity is not written and sets the status.
+__global__ __launch_bounds__(256) void pc_pack_batch(const GramSlice* __restrict__ gs,
+                                                     const PackSlice* __restrict__ ps) {
+    __shared__ unsigned long long key[GRAM_MAX_R];
+    __shared__ int idx[GRAM_MAX_R];
+    const GramSlice d = gs[blockIdx.x];
+    const PackSlice q = ps[blockIdx.x];
+    const int r = (int)d.g.r;
+    int np = 1;
+    while (np < r) np <<= 1;
+    for (int i = threadIdx.x; i < np; i += blockDim.x) {
+        if (i < r) {
+            double v = d.s2[i];
+            if (!(v >= 0.0)) v = 0.0;
+            v += 0.0;
+            key[i] = ~(unsigned long long)__double_as_longlong(v);   // ascending key = descending value
+        } else {
+            key[i] = ~0ull;
+        }
+        idx[i] = i;
+    }
+    __syncthreads();
+    for (int k = 2; k <= np; k <<= 1) {
+        for (int j = k >> 1; j > 0; j >>= 1) {
+            for (int t = threadIdx.x; t < np / 2; t += blockDim.x) {
+                const int i = 2 * j * (t / j) + (t % j);
+                const bool up = (i & k) == 0;
+                const unsigned long long ka = key[i], kb = key[i + j];
+                const int ia = idx[i], ib = idx[i + j];
+                const bool gt = (ka > kb) || (ka == kb && ia > ib);
+                if (gt == up) { key[i] = kb; key[i + j] = ka; idx[i] = ib; idx[i + j] = ia; }
+            }
+            __syncthreads();
+        }
+    }
+    for (int i = threadIdx.x; i < r; i += blockDim.x) d.perm[i] = idx[i];
+    const int64_t kr = *q.rho, off = *q.off;
+    if (kr <= 0) return;
+    if (off + kr > q.capacity) {
+        if (threadIdx.x == 0) atomicExch(q.status, (int32_t)TSVDM_E_CAPACITY);
+        return;
+    }
+    float* S = static_cast<float*>(q.S_pk) + off;
+    for (int c = threadIdx.x; c < kr; c += blockDim.x) {
+        const double v = d.s2[idx[c]];
+        S[c] = (float)sqrt(v > 0.0 ? v : 0.0);
+    }
+    const double shs = *d.shift;
+    for (int64_t c = 0; c < kr; ++c) {
+        const int j = idx[c];
+        const double sg2 = d.s2[j] > 0.0 ? d.s2[j] : 0.0;
+        const double nb = sqrt(sg2 + shs);
+        const double scale = nb > 0.0 ? (d.g.rows ? 1.0 : sqrt(sg2)) / nb : 0.0;
+        const float* b = d.B + (int64_t)j * r;
+        if (d.g.rows) {
+            float* u = static_cast<float*>(q.U_pk) + d.g.m * off + c * d.g.m;
+            for (int a = threadIdx.x; a < r; a += blockDim.x) u[a] = (float)((double)b[a] * scale);
+        } else {
+            float* gr = static_cast<float*>(q.G_pk) + d.g.p * off + c;
+            for (int t = threadIdx.x; t < r; t += blockDim.x) gr[t * kr] = (float)((double)b[t] * scale);
+        }
+    }
+}
+
+
+// The in-LDS Jacobi keeps r x (r + 1) floats of dynamic LDS; each size
+// class is allowed the most its largest r needs, once per process.
+constexpr int LDS_CLASSES = 4;
+constexpr int LDS_RMAX[LDS_CLASSES] = {32, 64, 96, 128};
+static_assert(GRAM_LDS_MAX_R <= LDS_RMAX[LDS_CLASSES - 1], "in-LDS limit beyond the largest class");
+static_assert(GRAM_LDS_CLASSES == LDS_CLASSES, "class count differs from the header");
+// the Cholesky's static LDS panel is sized by its class's largest r
+constexpr int CHOL_RMAX[GRAM_CHOL_CLASSES] = {128, 256, 512, 1024};
+static_assert(CHOL_RMAX[GRAM_CHOL_CLASSES - 1] == GRAM_MAX_R, "largest Cholesky class differs from the limit");
+
+template <int RMAX>
+hipError_t allow_lds() {
+    const int bytes = RMAX * (RMAX + 1) * (int)sizeof(float);
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&pc_jacobi_lds<RMAX>),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+    if (e != hipSuccess) return e;
+    return hipFuncSetAttribute(reinterpret_cast<const void*>(&pc_jacobi_lds_batch<RMAX>),
+                               hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+}
+
+std::mutex g_lds_mu;
+bool g_lds_ready = false;
+
 template <int RMAX>
 int launch_lds_bucket(float* B, int64_t r, int64_t n, double tol, int max_sweeps, const double* shift,
                       double* s2, int32_t* flag, hipStream_t st) {
     const size_t bytes = (size_t)r * (size_t)(r + 1) * sizeof(float);
-    TSVDM_HIP_CHECK(hipFuncSetAttribute(reinterpret_cast<const void*>(&pc_jacobi_lds<RMAX>),
-                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes));
     pc_jacobi_lds<RMAX><<<(unsigned)n, 256, bytes, st>>>(B, r, tol, max_sweeps, shift, s2, flag);
     TSVDM_LAUNCH_CHECK();
     return TSVDM_OK;
@@ -632,13 +805,109 @@ int launch_lds_bucket(float* B, int64_t r, int64_t n, double tol, int max_sweeps
 
 int launch_jacobi_lds(float* B, int64_t r, int64_t n, double tol, int max_sweeps, const double* shift,
                       double* s2, int32_t* flag, hipStream_t st) {
+    const int rc = gram_lds_prepare();
+    if (rc) return rc;
     if (r <= 32) return launch_lds_bucket<32>(B, r, n, tol, max_sweeps, shift, s2, flag, st);
     if (r <= 64) return launch_lds_bucket<64>(B, r, n, tol, max_sweeps, shift, s2, flag, st);
     if (r <= 96) return launch_lds_bucket<96>(B, r, n, tol, max_sweeps, shift, s2, flag, st);
-    if (r <= 128) return launch_lds_bucket<128>(B, r, n, tol, max_sweeps, shift, s2, flag, st);
-    if (r <= 160) return launch_lds_bucket<160>(B, r, n, tol, max_sweeps, shift, s2, flag, st);
-    return launch_lds_bucket<192>(B, r, n, tol, max_sweeps, shift, s2, flag, st);
+    return launch_lds_bucket<128>(B, r, n, tol, max_sweeps, shift, s2, flag, st);
 }
+
+}  // namespace
+
+int gram_lds_prepare() {
+    std::lock_guard<std::mutex> lk(g_lds_mu);
+    if (g_lds_ready) return TSVDM_OK;
+    TSVDM_HIP_CHECK(allow_lds<32>());
+    TSVDM_HIP_CHECK(allow_lds<64>());
+    TSVDM_HIP_CHECK(allow_lds<96>());
+    TSVDM_HIP_CHECK(allow_lds<128>());
+    g_lds_ready = true;
+    return TSVDM_OK;
+}
+
+int gram_lds_class(int64_t r) {
+    for (int c = 0; c < LDS_CLASSES; ++c)
+        if (r <= LDS_RMAX[c]) return c;
+    return -1;
+}
+
+int gram_chol_class(int64_t r) {
+    for (int c = 0; c < GRAM_CHOL_CLASSES; ++c)
+        if (r <= CHOL_RMAX[c]) return c;
+    return -1;
+}
+
+double gram_tol(int64_t r) { return jacobi_default_opts(r, r, TSVDM_F32).tol; }
+
+int run_gram_prep_batch(const GramSlice* gs, int64_t ngram, const int2* gram_tasks, int64_t ntasks,
+                        const int* lists, const int64_t* class_off, const int64_t* class_cnt,
+                        hipStream_t st) {
+    TSVDM_REQUIRE(ntasks < ((int64_t)1 << 31) && ngram < ((int64_t)1 << 31), TSVDM_E_SHAPE,
+                  "too many Gram slices for one launch");
+    if (ngram == 0) return TSVDM_OK;
+    pc_gram_batch<<<(unsigned)ntasks, 256, 0, st>>>(gs, gram_tasks);
+    TSVDM_LAUNCH_CHECK();
+    for (int c = 0; c < GRAM_CHOL_CLASSES; ++c) {
+        if (!class_cnt[c]) continue;
+        const int* list = lists + class_off[c];
+        const unsigned cnt = (unsigned)class_cnt[c];
+        switch (CHOL_RMAX[c]) {
+            case 128: pc_chol_batch<128><<<cnt, 256, 0, st>>>(gs, list); break;
+            case 256: pc_chol_batch<256><<<cnt, 256, 0, st>>>(gs, list); break;
+            case 512: pc_chol_batch<512><<<cnt, 256, 0, st>>>(gs, list); break;
+            default: pc_chol_batch<1024><<<cnt, 256, 0, st>>>(gs, list); break;
+        }
+        TSVDM_LAUNCH_CHECK();
+    }
+    return TSVDM_OK;
+}
+
+int run_gram_unshift_batch(const GramSlice* gs, int64_t n, hipStream_t st) {
+    TSVDM_REQUIRE(n < ((int64_t)1 << 31), TSVDM_E_SHAPE, "too many Gram slices for one launch");
+    if (n == 0) return TSVDM_OK;
+    pc_unshift_batch<<<(unsigned)n, 256, 0, st>>>(gs);
+    TSVDM_LAUNCH_CHECK();
+    return TSVDM_OK;
+}
+
+int run_gram_lds_batch(const GramSlice* gs, const int* lists, const int64_t* class_off,
+                       const int64_t* class_cnt, const int* class_maxr, int max_sweeps,
+                       const GramSlice* gs_lds, int64_t n_lds, int32_t* status, hipStream_t st) {
+    TSVDM_REQUIRE(n_lds < ((int64_t)1 << 31), TSVDM_E_SHAPE, "too many Gram slices for one launch");
+    if (n_lds == 0) return TSVDM_OK;
+    for (int c = 0; c < LDS_CLASSES; ++c) {
+        if (!class_cnt[c]) continue;
+        const size_t bytes = (size_t)class_maxr[c] * (size_t)(class_maxr[c] + 1) * sizeof(float);
+        const int* list = lists + class_off[c];
+        const unsigned cnt = (unsigned)class_cnt[c];
+        switch (LDS_RMAX[c]) {
+            case 32: pc_jacobi_lds_batch<32><<<cnt, 256, bytes, st>>>(gs, list, max_sweeps); break;
+            case 64: pc_jacobi_lds_batch<64><<<cnt, 256, bytes, st>>>(gs, list, max_sweeps); break;
+            case 96: pc_jacobi_lds_batch<96><<<cnt, 256, bytes, st>>>(gs, list, max_sweeps); break;
+            default: pc_jacobi_lds_batch<128><<<cnt, 256, bytes, st>>>(gs, list, max_sweeps); break;
+        }
+        TSVDM_LAUNCH_CHECK();
+    }
+    pc_gram_status<<<1, 256, 0, st>>>(gs_lds, n_lds, status);
+    TSVDM_LAUNCH_CHECK();
+    return TSVDM_OK;
+}
+
+int run_gram_pack_batch(const GramSlice* gs, const PackSlice* ps, int64_t ngram, const int4* ftasks,
+                        int64_t nft, hipStream_t st) {
+    TSVDM_REQUIRE(nft < ((int64_t)1 << 31) && ngram < ((int64_t)1 << 31), TSVDM_E_SHAPE,
+                  "too many Gram slices for one launch");
+    if (ngram == 0) return TSVDM_OK;
+    pc_pack_batch<<<(unsigned)ngram, 256, 0, st>>>(gs, ps);
+    TSVDM_LAUNCH_CHECK();
+    if (nft > 0) {
+        pc_factor_batch<<<(unsigned)nft, 256, 0, st>>>(gs, ps, ftasks);
+        TSVDM_LAUNCH_CHECK();
+    }
+    return TSVDM_OK;
+}
+
 
 size_t gram_svd_workspace_bytes(int64_t m, int64_t p, int64_t n) {
     const SliceGeom g = slice_geom(m, p);
@@ -648,13 +917,13 @@ size_t gram_svd_workspace_bytes(int64_t m, int64_t p, int64_t n) {
     return cv.total() + jacobi_workspace_bytes(n);
 }
 
-int64_t gram_svd_max_r() { return 1024; }
 
 int run_gram_svd(const float* A_hat, int64_t m, int64_t p, int64_t n, float* B, double* s2,
-                 double* shift, int32_t* status, const JacobiOpts& o, void* ws, hipStream_t st) {
+                 double* shift, int32_t* status, const JacobiOpts& o, int jacobi, void* ws,
+                 hipStream_t st) {
     const SliceGeom g = slice_geom(m, p);
     const int64_t r = g.r;
-    TSVDM_REQUIRE(r <= gram_svd_max_r(), TSVDM_E_SHAPE, "min(m, p) must be <= 1024 for the Gram form");
+    TSVDM_REQUIRE(r <= GRAM_MAX_R, TSVDM_E_SHAPE, "min(m, p) must be <= 1024 for the Gram form");
     Carver cv(ws);
     double* G = cv.carve<double>((size_t)(r * r * n));
     double* Lw = cv.carve<double>((size_t)(r * r * n));
@@ -671,8 +940,11 @@ int run_gram_svd(const float* A_hat, int64_t m, int64_t p, int64_t n, float* B, 
     else pc_chol<1024><<<(unsigned)n, 256, 0, st>>>(G, r, cshift, Lw, B, shift);
     TSVDM_LAUNCH_CHECK();
     // one-sided Jacobi on the columns of L (r x r), no accumulated rotations:
-    // held in LDS for r <= 192, else the round kernel streaming through HBM
-    if (r <= 192 && n < ((int64_t)1 << 31)) {
+    // held in LDS, or the block rounds streaming through HBM
+    const bool lds = jacobi == TSVDM_GRAM_LDS || (jacobi == TSVDM_GRAM_AUTO && r <= GRAM_LDS_MAX_R);
+    TSVDM_REQUIRE(!lds || r <= GRAM_LDS_MAX_R, TSVDM_E_SHAPE, "the in-LDS Jacobi needs min(m, p) <= 128");
+    TSVDM_REQUIRE(!lds || n < ((int64_t)1 << 31), TSVDM_E_SHAPE, "too many slices for one launch");
+    if (lds) {
         int32_t* flag = static_cast<int32_t*>(jws);
         const bool stats = stats_enabled();
         hipEvent_t e0 = nullptr, e1 = nullptr;

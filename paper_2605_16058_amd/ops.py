@@ -207,13 +207,16 @@ def tsvdm_slice_svd(A_hat, block=0, max_sweeps=0, tol=0.0, host_poll=True, ws=No
     return W, s2, status
 
 
-def tsvdm_slice_svd_gram(A_hat, block=0, max_sweeps=0, tol=0.0, host_poll=True, ws=None):
+def tsvdm_slice_svd_gram(A_hat, block=0, max_sweeps=0, tol=0.0, host_poll=True, ws=None, jacobi="auto"):
     """Slice SVDs of an FP32 tensor by way of the FP64 Gram matrix (A_hat is
     only read).  Returns (B, s2, shift, status): B (n, r, r) FP32 holds the
     orthogonalised columns of each slice's Cholesky factor, s2 the squared
-    singular values, shift the per-slice Cholesky shift."""
+    singular values, shift the per-slice Cholesky shift.  jacobi: "auto",
+    "rounds" or "lds", where the Jacobi on the factor runs."""
     if not is_colmajor(A_hat) or A_hat.dtype != torch.float32:
         raise ValueError("A_hat must be a column-major FP32 tensor")
+    if jacobi not in _lib.GRAM_JACOBI:
+        raise ValueError(f"jacobi must be one of {list(_lib.GRAM_JACOBI)}")
     m, p, n = A_hat.shape
     r = min(m, p)
     B = torch.empty((n, r, r), dtype=torch.float32, device=A_hat.device)
@@ -223,7 +226,8 @@ def tsvdm_slice_svd_gram(A_hat, block=0, max_sweeps=0, tol=0.0, host_poll=True, 
     w = _ws(ws)
     wp, wn = w.args(_lib.workspace_size("tsvdm_slice_svd_gram_workspace_size", m, p, n))
     _lib.call("tsvdm_slice_svd_gram", _ptr(A_hat), m, p, n, _ptr(B), _ptr(s2), _ptr(shift), _ptr(status),
-              int(block), int(max_sweeps), float(tol), int(bool(host_poll)), wp, wn, _stream())
+              int(block), int(max_sweeps), float(tol), _lib.GRAM_JACOBI[jacobi], int(bool(host_poll)), wp, wn,
+              _stream())
     return B, s2, shift, status
 
 

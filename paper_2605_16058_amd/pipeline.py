@@ -14,6 +14,7 @@ import numpy as np
 import torch
 
 from . import ops
+from ._lib import GRAM_JACOBI, GRAM_MAX_R
 
 PRECISIONS = {
     # name: (TTM compute, Jacobi dtype)
@@ -77,7 +78,6 @@ def next_selection_eps(eps, eps_cur, rel, stats, precision, rounds):
     return max(nxt, 1e-300)
 
 
-GRAM_MAX_R = 1024   # largest min(m, p) of the Gram form
 
 
 def resolve_svd(svd, precision, r, certify=False):
@@ -131,7 +131,9 @@ class TSVDM:
     instead of the dense product: forward, and after the transform-domain
     low-rank product (tsvdm_lowrank) backward; precision f64 or f32 only.
 
-    svd: "auto", "jacobi" or "gram" (see resolve_svd).
+    svd: "auto", "jacobi" or "gram" (see resolve_svd).  gram_jacobi: where
+    the Gram form's Jacobi on the factor runs, "auto" (in LDS for
+    min(m, p) <= 128, else the block rounds), "rounds" or "lds".
 
     guard (mode "II"; see selection_eps): "measure" (default) selects with
     eps and, if the measured relative error of the result is not below eps
@@ -157,10 +159,13 @@ class TSVDM:
     def __init__(self, shape, M, mode="II", k=None, eps=None, precision="f64",
                  block=0, max_sweeps=0, tol=0.0, host_poll=True, capacity="max",
                  device="cuda", check_m=True, tile=0, transform="dense", certify=False,
-                 theta=0.5, max_passes=3, guard="measure", svd="auto"):
+                 theta=0.5, max_passes=3, guard="measure", svd="auto", gram_jacobi="auto"):
         self.m, self.p, self.n = (int(x) for x in shape)
         self.r = min(self.m, self.p)
         self.svd = resolve_svd(svd, precision, self.r, certify)
+        if gram_jacobi not in GRAM_JACOBI:
+            raise ValueError(f"gram_jacobi must be one of {list(GRAM_JACOBI)}")
+        self.gram_jacobi = gram_jacobi
         # the certified selection chooses its ranks inside its SVD rounds:
         # it takes the up-front bound instead of measuring
         self.guard = _guard_mode(guard)
@@ -228,7 +233,8 @@ class TSVDM:
             W, s2, svd_status, rho, offsets, stats, computed, passes = self._certified(A_hat)
         elif self.svd == "gram":
             W, s2, shift, svd_status = ops.tsvdm_slice_svd_gram(
-                A_hat, self.block, self.max_sweeps, self.tol, self.host_poll, ws=self.ws)
+                A_hat, self.block, self.max_sweeps, self.tol, self.host_poll, ws=self.ws,
+                jacobi=self.gram_jacobi)
         else:
             W, s2, svd_status = ops.tsvdm_slice_svd(A_hat, self.block, self.max_sweeps, self.tol,
                                                     self.host_poll, ws=self.ws)
@@ -333,7 +339,7 @@ class TSVDMd:
 
     def __init__(self, dims, Ms, mode="II", k=None, eps=None, precision="f64", block=0,
                  max_sweeps=0, tol=0.0, host_poll=True, device="cuda", tile=0, certify=False,
-                 theta=0.5, max_passes=3, guard="measure", svd="auto"):
+                 theta=0.5, max_passes=3, guard="measure", svd="auto", gram_jacobi="auto"):
         self.dims = tuple(int(x) for x in dims)
         if certify and mode != "II":
             raise ValueError("certify applies to mode II")
@@ -366,6 +372,9 @@ class TSVDMd:
             self.N *= x
         self.r = min(self.m, self.p)
         self.svd = resolve_svd(svd, precision, self.r, certify)
+        if gram_jacobi not in GRAM_JACOBI:
+            raise ValueError(f"gram_jacobi must be one of {list(GRAM_JACOBI)}")
+        self.gram_jacobi = gram_jacobi
         self.ws = ops.Workspace(device)
 
     def __call__(self, A: torch.Tensor) -> Result:
@@ -391,7 +400,8 @@ class TSVDMd:
                 self.tol, self.host_poll, self.ws)
         elif self.svd == "gram":
             W, s2, shift, svd_status = ops.tsvdm_slice_svd_gram(
-                A_hat, self.block, self.max_sweeps, self.tol, self.host_poll, ws=self.ws)
+                A_hat, self.block, self.max_sweeps, self.tol, self.host_poll, ws=self.ws,
+                jacobi=self.gram_jacobi)
         else:
             W, s2, svd_status = ops.tsvdm_slice_svd(A_hat, self.block, self.max_sweeps, self.tol,
                                                     self.host_poll, ws=self.ws)

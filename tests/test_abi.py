@@ -32,6 +32,17 @@ def test_header_and_binding_agree():
     assert _header_functions() == sorted(_lib.exported_names())
 
 
+def test_header_constants_match_binding():
+    from paper_2605_16058_amd import _lib
+    src = open(HEADER).read()
+    m = re.search(r"#define TSVDM_GRAM_MAX_R (\d+)", src)
+    assert m and int(m.group(1)) == _lib.GRAM_MAX_R
+    m = re.search(r"#define TSVDM_GRAM_LDS_MAX_R (\d+)", src)
+    assert m and int(m.group(1)) == _lib.GRAM_LDS_MAX_R
+    for name, v in _lib.GRAM_JACOBI.items():
+        assert re.search(rf"TSVDM_GRAM_{name.upper()} = {v}\b", src), name
+
+
 def test_library_exports_every_declared_symbol(lib):
     for name in _header_functions():
         assert hasattr(lib, name), name
@@ -121,6 +132,24 @@ def test_slice_svd_validation(lib):
     assert lib.tsvdm_slice_svd(*a) == -1
     a = list(base); a[13] = 0
     assert lib.tsvdm_slice_svd(*a) == -4
+
+
+def test_slice_svd_gram_validation(lib):
+    D2 = c_void_p(256 + 4096)   # B must not alias A_hat
+    base = [DUMMY, 200, 150, 4, D2, DUMMY, DUMMY, DUMMY, 0, 0, 0.0, 0, 1, DUMMY, 1 << 30, None]
+    a = list(base); a[11] = 3            # unknown placement of the Jacobi
+    assert lib.tsvdm_slice_svd_gram(*a) == -1
+    assert b"jacobi" in lib.tsvdm_last_error()
+    a = list(base); a[11] = 2            # in LDS needs min(m, p) <= 128
+    assert lib.tsvdm_slice_svd_gram(*a) == -2
+    a = list(base); a[1] = 1030; a[2] = 1040
+    assert lib.tsvdm_slice_svd_gram(*a) == -2
+    a = list(base); a[4] = DUMMY
+    assert lib.tsvdm_slice_svd_gram(*a) == -1
+    a = list(base); a[8] = 7
+    assert lib.tsvdm_slice_svd_gram(*a) == -1
+    a = list(base); a[14] = 8
+    assert lib.tsvdm_slice_svd_gram(*a) == -4
 
 
 def test_truncation_validation(lib):

@@ -6,6 +6,7 @@ import numpy as np
 import pytest
 
 import synth
+from paper_2605_16058_amd._lib import GRAM_LDS_MAX_R, GRAM_MAX_R
 
 pytestmark = pytest.mark.gpu
 
@@ -16,6 +17,12 @@ def to_dev(A, dtype):
     out = torch.empty((A.shape[2], A.shape[1], A.shape[0]), dtype=dtype, device="cuda").permute(2, 1, 0)
     out.copy_(torch.from_numpy(np.asfortranarray(A)).to(dtype))
     return out
+
+def plan_gram_jacobi(shapes):
+    """Where a FP32 batch plan runs the Gram form's Jacobi: in LDS when every
+    tensor has min(m, p) <= GRAM_LDS_MAX_R, else in the block rounds."""
+    return "lds" if all(min(s[0], s[1]) <= GRAM_LDS_MAX_R for s in shapes) else "rounds"
+
 
 
 @pytest.mark.parametrize("shape", [(70, 50, 20), (33, 17, 5), (130, 3, 64), (300, 7, 33)])
@@ -43,9 +50,11 @@ def test_batch_mixed_blocks_and_tiles_equal_single_calls():
     st = b.run(host_poll=True)
     torch.cuda.synchronize()
     assert int(st.item()) == 0
+    gj = plan_gram_jacobi([A.shape for A in Ts])
     for t, A in enumerate(Ts):
+        svd = "gram" if min(A.shape[0], A.shape[1]) <= GRAM_MAX_R else "jacobi"
         res = tsvdm(A, w.M[t], mode=w.mode[t], k=w.k[t], eps=w.eps[t], precision="f32",
-                    block=blocks[t], tile=tiles[t], svd="jacobi", guard="bound")
+                    block=blocks[t], tile=tiles[t], svd=svd, guard="bound", gram_jacobi=gj)
         torch.cuda.synchronize()
         assert torch.equal(res.rho, b.rho[t]), t
         assert torch.equal(res.A_rec, b.A_rec[t]), t

@@ -14,6 +14,7 @@ import pytest
 
 import oracle as O
 import synth
+from paper_2605_16058_amd._lib import GRAM_LDS_MAX_R, GRAM_MAX_R
 
 pytestmark = pytest.mark.gpu
 
@@ -24,6 +25,12 @@ def to_dev(A, dtype):
     out = torch.empty((A.shape[2], A.shape[1], A.shape[0]), dtype=dtype, device="cuda").permute(2, 1, 0)
     out.copy_(torch.from_numpy(np.asfortranarray(A)).to(dtype))
     return out
+
+def plan_gram_jacobi(shapes):
+    """Where a FP32 batch plan runs the Gram form's Jacobi: in LDS when every
+    tensor has min(m, p) <= GRAM_LDS_MAX_R, else in the block rounds."""
+    return "lds" if all(min(s[0], s[1]) <= GRAM_LDS_MAX_R for s in shapes) else "rounds"
+
 
 
 def rel(a, b):
@@ -47,9 +54,13 @@ def test_batch_equals_single_tensor_calls(ragged, precision, dtype):
     st = b.run(host_poll=True)
     torch.cuda.synchronize()
     assert int(st.item()) == 0
+    gj = plan_gram_jacobi([A.shape for A in Ts])
     for t, A in enumerate(Ts):
+        # the plan's choice of slice SVD: the Gram form for FP32 slices with
+        # min(m, p) <= GRAM_MAX_R, the rotation form otherwise
+        svd = "gram" if precision == "f32" and min(A.shape[0], A.shape[1]) <= GRAM_MAX_R else "jacobi"
         res = tsvdm(A, w.M[t], mode=w.mode[t], k=w.k[t], eps=w.eps[t], precision=precision, block=16,
-                    svd="jacobi", guard="bound")
+                    svd=svd, guard="bound", gram_jacobi=gj)
         torch.cuda.synchronize()
         assert torch.equal(res.rho, b.rho[t]), t
         assert torch.equal(res.offsets, b.offsets[t]), t
@@ -147,3 +158,46 @@ def test_batch_graph_replays_equal_eager(ragged):
         torch.cuda.synchronize()
         for t in range(len(Ts)):
             assert torch.equal(b.A_rec[t], ref[t]), (rep, t)
+
+
+def test_batch_mixed_routes_equal_single_calls():
+    """FP32 batches whose tensors take every slice-SVD route (the Gram form
+    up to GRAM_MAX_R with the Jacobi in the block rounds, or in LDS when the
+    whole batch is small; the rotation form above GRAM_MAX_R) equal the
+    single-tensor calls of the same form bit for bit, and their FP32 errors
+    stay below eps."""
+    from paper_2605_16058_amd.pipeline import BatchTSVDM, tsvdm
+    g = np.random.default_rng(77)
+    shapes = [(40, 60, 5), (210, 230, 3), (150, 90, 4), (230, 200, 2), (129, 300, 2), (128, 128, 2),
+              (96, 180, 3), (GRAM_MAX_R + 6, GRAM_MAX_R + 12, 1)]
+    As, Ms, modes, ks, epss = [], [], [], [], []
+    for t, (m, p, n) in enumerate(shapes):
+        A = g.standard_normal((m, p, n)) + 3.0 * np.einsum("a,b,c->abc", g.standard_normal(m),
+                                                           g.standard_normal(p), g.standard_normal(n))
+        As.append(A.astype(np.float32))
+        Ms.append(synth.haar_orthogonal(n, g))
+        modes.append("I" if t % 2 == 0 else "II")
+        ks.append(7 if t % 2 == 0 else None)
+        epss.append(None if t % 2 == 0 else 0.3)
+    Ts = [to_dev(A, torch.float32) for A in As]
+    small = [t for t, (m, p, n) in enumerate(shapes) if min(m, p) <= GRAM_LDS_MAX_R]
+    for sel in (list(range(len(shapes))), small):
+        gj = plan_gram_jacobi([shapes[t] for t in sel])
+        print(f"batch of {len(sel)} tensors, Gram-form Jacobi: {gj}", flush=True)
+        b = BatchTSVDM([Ts[t] for t in sel], [Ms[t] for t in sel], [modes[t] for t in sel],
+                       ks=[ks[t] for t in sel], epss=[epss[t] for t in sel], precision="f32", block=16)
+        st = b.run(host_poll=True)
+        torch.cuda.synchronize()
+        assert int(st.item()) == 0
+        errs = b.rel_errors()
+        for i, t in enumerate(sel):
+            A = Ts[t]
+            svd = "gram" if min(A.shape[0], A.shape[1]) <= GRAM_MAX_R else "jacobi"
+            print(f"tensor {t} {tuple(A.shape)}: {svd} form, rel error {errs[i]:.6e}", flush=True)
+            res = tsvdm(A, Ms[t], mode=modes[t], k=ks[t], eps=epss[t], precision="f32", block=16, svd=svd,
+                        guard="bound", gram_jacobi=gj)
+            torch.cuda.synchronize()
+            assert torch.equal(res.rho, b.rho[i]), t
+            assert torch.equal(res.A_rec, b.A_rec[i]), t
+            if modes[t] == "II":
+                assert errs[i] < epss[t]
