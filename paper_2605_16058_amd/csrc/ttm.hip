@@ -43,23 +43,34 @@ __global__ void ttm_prep(const double* __restrict__ M, int n, int transpose,
 // KIND 0: plain MFMA in CT (double or float), K step 4.
 // KIND 1: BF16 operands, FP32 accumulate, K step 32.
 // KIND 2: split BF16 (hi*hi + hi*lo + lo*hi), FP32 accumulate, K step 32.
+// Two stages of the K chunk: the next chunk is loaded into registers while
+// the MFMAs consume the current one, then written to the other stage, so a
+// chunk costs one barrier.  X rows are padded by 16 floats / 8 doubles, so
+// that the two 16-lane row groups of an MFMA operand read hit disjoint banks.
 template <class CT, int KIND, int SHAPE>
 struct TtmShared {
     static constexpr int KC = (KIND == 0) ? 16 : 32;
-    CT Xs[KC][TileShape<SHAPE>::TR + 1];   // [l][row]
-    CT Ts[TileShape<SHAPE>::TI][KC + 1];   // [i][l]
+    static constexpr int TR = TileShape<SHAPE>::TR, TI = TileShape<SHAPE>::TI;
+    static constexpr int XLD = TR + (sizeof(CT) == 4 ? 16 : 8);
+    CT Xs[2][KC][XLD];        // [stage][l][row]
+    CT Ts[2][TI][KC + 1];     // [stage][i][l]
 };
 
-// Output tile (row tile rt, slice tile ct) of Y = X x_3 op(M).
-template <class CT, int KIND, int SHAPE>
-__device__ __forceinline__ void ttm_tile(TtmShared<CT, KIND, SHAPE>& sh, const void* __restrict__ X, int xdt,
+// Output tile (row tile rt, slice tile ct) of Y = X x_3 op(M); XT is the
+// input element type.  VEC: R is a multiple of the 16-byte vector and X is
+// 16-byte aligned, so that X loads as 16-byte vectors of consecutive rows.
+template <class CT, class XT, int KIND, int SHAPE, bool VEC>
+__device__ __forceinline__ void ttm_tile(TtmShared<CT, KIND, SHAPE>& sh, const XT* __restrict__ X,
                                          void* __restrict__ Y, int ydt, int64_t R, int n,
                                          const CT* __restrict__ Tt, int64_t rt, int ct) {
-    constexpr int KC = TtmShared<CT, KIND, SHAPE>::KC;
-    constexpr int TR = TileShape<SHAPE>::TR, TI = TileShape<SHAPE>::TI, WI = TileShape<SHAPE>::WI;
+    typedef TtmShared<CT, KIND, SHAPE> S;
+    constexpr int KC = S::KC, TR = S::TR, TI = S::TI;
+    constexpr int WI = TileShape<SHAPE>::WI;
+    constexpr int VW = VEC ? 16 / (int)sizeof(XT) : 1;     // X values per load
+    constexpr int NXE = KC * TR / (256 * VW);              // X loads per thread and chunk
+    constexpr int NTE = TI * KC / 256;                     // op(M) values per thread and chunk
+    static_assert(NXE >= 1 && NTE >= 1, "tile too small for the staging map");
     typedef typename Acc<CT>::type AccT;
-    auto& Xs = sh.Xs;
-    auto& Ts = sh.Ts;
     const int64_t row0 = rt * TR;
     const int i0 = ct * TI;
 
@@ -73,37 +84,112 @@ __device__ __forceinline__ void ttm_tile(TtmShared<CT, KIND, SHAPE>& sh, const v
 #pragma unroll
     for (int t = 0; t < 4; ++t) acc[t] = zero4<AccT>();
 
-    for (int l0 = 0; l0 < n; l0 += KC) {
-        // stage X[row0 .. row0+TR-1, l0 .. l0+KC-1], coalesced along rows
+    // This thread's staging elements: X load k covers rows r .. r + VW - 1
+    // of column l, consecutive threads along the rows; op(M) value k is
+    // (slice i, column l), consecutive threads along l.  Rows and slices
+    // outside the tensor are loaded from an index clamped into it (R >= VW)
+    // and zeroed only when stored, so that nothing waits for the loads
+    // before the MFMAs of the current chunk; the addresses are formed once
+    // and advanced by a scalar offset per chunk (columns are clamped only in
+    // a last, partial chunk).
+    const XT* xb[NXE];
+    const CT* tb[NTE];
+    bool xok[NXE], tok[NTE];
 #pragma unroll
-        for (int e = tid; e < KC * TR; e += 256) {
-            int r = e & (TR - 1), l = e / TR;
-            int64_t row = row0 + r;
-            int lg_ = l0 + l;
-            CT v = 0;
-            if (row < R && lg_ < n) v = ldg_as<CT>(X, row + (int64_t)lg_ * R, xdt);
-            Xs[l][r] = v;
-        }
-        // stage op(M) block [i0 .. i0+TI-1, l0 .. l0+KC-1]
+    for (int k = 0; k < NXE; ++k) {
+        const int e = tid + 256 * k;
+        const int l = e / (TR / VW), r = (e % (TR / VW)) * VW;
+        const int64_t row = row0 + r;
+        xok[k] = row < R;
+        xb[k] = X + (row < R ? row : R - VW) + (int64_t)l * R;
+    }
 #pragma unroll
-        for (int e = tid; e < KC * TI; e += 256) {
-            int l = e % KC, i = e / KC;
-            CT v = 0;
-            if (i0 + i < n && l0 + l < n) v = Tt[(int64_t)(i0 + i) * n + l0 + l];
-            Ts[i][l] = v;
+    for (int k = 0; k < NTE; ++k) {
+        const int e = tid + 256 * k;
+        const int l = e % KC, i = e / KC;
+        tok[k] = i0 + i < n;
+        tb[k] = Tt + (int64_t)(i0 + i < n ? i0 + i : n - 1) * n + l;
+    }
+    // every row and slice of the tile inside the tensor: only the columns
+    // of a partial last chunk are zeroed
+    const bool inner = row0 + TR <= R && i0 + TI <= n;
+    XT xv[NXE][VW];
+    CT tv[NTE];
+    bool lok[NXE], ltok[NTE];
+    auto load = [&](int l0) {
+        const bool full = l0 + KC <= n;
+#pragma unroll
+        for (int k = 0; k < NXE; ++k) {
+            const XT* src = xb[k] + (int64_t)l0 * R;
+            lok[k] = true;
+            if (!full) {
+                const int l = (tid + 256 * k) / (TR / VW);
+                lok[k] = l0 + l < n;
+                if (!lok[k]) src = xb[k] + (int64_t)(n - 1 - l) * R;
+            }
+            if constexpr (VW == 4) {
+                const float4 x = *reinterpret_cast<const float4*>(src);
+                xv[k][0] = x.x; xv[k][1] = x.y; xv[k][2] = x.z; xv[k][3] = x.w;
+            } else if constexpr (VW == 2) {
+                const double2 x = *reinterpret_cast<const double2*>(src);
+                xv[k][0] = x.x; xv[k][1] = x.y;
+            } else {
+                xv[k][0] = *src;
+            }
         }
-        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < NTE; ++k) {
+            const CT* src = tb[k] + l0;
+            ltok[k] = true;
+            if (!full) {
+                const int l = (tid + 256 * k) % KC;
+                ltok[k] = l0 + l < n;
+                if (!ltok[k]) src = tb[k] + (n - 1 - l);
+            }
+            tv[k] = *src;
+        }
+    };
+    auto store = [&](int stg) {
+#pragma unroll
+        for (int k = 0; k < NXE; ++k) {
+            const int e = tid + 256 * k;
+            CT* dst = &sh.Xs[stg][e / (TR / VW)][(e % (TR / VW)) * VW];
+            const bool ok = (inner || xok[k]) && lok[k];
+#pragma unroll
+            for (int q = 0; q < VW; ++q) dst[q] = ok ? static_cast<CT>(xv[k][q]) : CT(0);
+        }
+#pragma unroll
+        for (int k = 0; k < NTE; ++k) {
+            const int e = tid + 256 * k;
+            sh.Ts[stg][e / KC][e % KC] = ((inner || tok[k]) && ltok[k]) ? tv[k] : CT(0);
+        }
+    };
 
-        const int irow = wi * 16 + lr;  // output slice (A-operand row)
+    const int irow = wi * 16 + lr;  // output slice (A-operand row)
+    const int nchunk = (n + KC - 1) / KC;
+    load(0);
+    store(0);
+    __syncthreads();
+    for (int c = 0; c < nchunk; ++c) {
+        const int stg = c & 1;
+        if (c + 1 < nchunk) load((c + 1) * KC);
+        const auto& Xs = sh.Xs[stg];
+        const auto& Ts = sh.Ts[stg];
         if constexpr (KIND == 0) {
+            // every operand of the chunk read before the first MFMA, so that
+            // the LDS latency is paid once per chunk
+            CT af[KC / 4], bf[KC / 4][4];
 #pragma unroll
-            for (int kk = 0; kk < KC; kk += 4) {
-                CT a = Ts[irow][kk + lg];
+            for (int kq = 0; kq < KC / 4; ++kq) {
+                af[kq] = Ts[irow][4 * kq + lg];
 #pragma unroll
-                for (int t = 0; t < 4; ++t) {
-                    CT b = Xs[kk + lg][wr0 + t * 16 + lr];
-                    acc[t] = mfma(a, b, acc[t]);
-                }
+                for (int t = 0; t < 4; ++t) bf[kq][t] = Xs[4 * kq + lg][wr0 + t * 16 + lr];
+            }
+            __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+            for (int kq = 0; kq < KC / 4; ++kq) {
+#pragma unroll
+                for (int t = 0; t < 4; ++t) acc[t] = mfma(af[kq], bf[kq][t], acc[t]);
             }
         } else {
             v8bf ahi, alo;
@@ -131,6 +217,7 @@ __device__ __forceinline__ void ttm_tile(TtmShared<CT, KIND, SHAPE>& sh, const v
                 }
             }
         }
+        if (c + 1 < nchunk) store(stg ^ 1);
         __syncthreads();
     }
 
@@ -147,14 +234,14 @@ __device__ __forceinline__ void ttm_tile(TtmShared<CT, KIND, SHAPE>& sh, const v
     }
 }
 
-template <class CT, int KIND, int SHAPE>
+template <class CT, class XT, int KIND, int SHAPE, bool VEC>
 __global__ __launch_bounds__(256) void ttm_kernel(
-    const void* __restrict__ X, int xdt, void* __restrict__ Y, int ydt,
+    const XT* __restrict__ X, void* __restrict__ Y, int ydt,
     int64_t R, int n, const CT* __restrict__ Tt, int n_ct, int64_t n_rt) {
     __shared__ TtmShared<CT, KIND, SHAPE> sh;
     // block blockIdx.y of R x n elements
     const int64_t boff = (int64_t)blockIdx.y * R * n;
-    X = static_cast<const char*>(X) + boff * (xdt == TSVDM_F64 ? 8 : 4);
+    X += boff;
     Y = static_cast<char*>(Y) + boff * (ydt == TSVDM_F64 ? 8 : 4);
     // XCD-aware block mapping: the n_ct column tiles of one row tile share
     // blockIdx % 8 (the same XCD and L2) and are dispatched together.
@@ -163,19 +250,19 @@ __global__ __launch_bounds__(256) void ttm_kernel(
     const int64_t rt = (local / n_ct) * 8 + xcd;
     const int ct = (int)(local % n_ct);
     if (rt >= n_rt) return;
-    ttm_tile<CT, KIND, SHAPE>(sh, X, xdt, Y, ydt, R, n, Tt, rt, ct);
+    ttm_tile<CT, XT, KIND, SHAPE, VEC>(sh, X, Y, ydt, R, n, Tt, rt, ct);
 }
 
-// Batched form: task = (problem, row tile, slice tile), all of one shape.
-template <class CT, int KIND, int SHAPE>
+// Batched form: task = (problem, row tile, slice tile), all of one shape;
+// element loads (the problems' row counts and alignments differ).
+template <class CT, class XT, int KIND, int SHAPE>
 __global__ __launch_bounds__(256) void ttm_kernel_batch(const TtmProblem* __restrict__ probs,
-                                                        const int4* __restrict__ tasks,
-                                                        int xdt, int ydt) {
+                                                        const int4* __restrict__ tasks, int ydt) {
     __shared__ TtmShared<CT, KIND, SHAPE> sh;
     const int4 tk = tasks[blockIdx.x];
     const TtmProblem pr = probs[tk.x];
-    ttm_tile<CT, KIND, SHAPE>(sh, pr.X, xdt, pr.Y, ydt, pr.R, pr.n,
-                              static_cast<const CT*>(pr.Tt), (int64_t)tk.y, tk.z);
+    ttm_tile<CT, XT, KIND, SHAPE, false>(sh, static_cast<const XT*>(pr.X), pr.Y, ydt, pr.R, pr.n,
+                                  static_cast<const CT*>(pr.Tt), (int64_t)tk.y, tk.z);
 }
 
 template <class ST>
@@ -190,8 +277,8 @@ __global__ void ttm_prep_batch(const TtmProblem* __restrict__ probs, int nprob, 
     }
 }
 
-template <class CT, int KIND, int SHAPE>
-int launch_tiles(const void* X, int xdt, void* Y, int ydt, int64_t R, int n, int64_t P,
+template <class CT, class XT, int KIND, int SHAPE>
+int launch_tiles(const void* X, void* Y, int ydt, int64_t R, int n, int64_t P,
                  const CT* Tt, hipStream_t st) {
     constexpr int TR = TileShape<SHAPE>::TR, TI = TileShape<SHAPE>::TI;
     int n_ct = (n + TI - 1) / TI;
@@ -199,16 +286,33 @@ int launch_tiles(const void* X, int xdt, void* Y, int ydt, int64_t R, int n, int
     int64_t n_rt8 = (n_rt + 7) / 8 * 8;
     int64_t blocks = n_rt8 * n_ct;
     TSVDM_REQUIRE(blocks < (int64_t)1 << 31, TSVDM_E_SHAPE, "tensor too large for one launch");
-    const size_t xes = xdt == TSVDM_F64 ? 8 : 4, yes = ydt == TSVDM_F64 ? 8 : 4;
+    const size_t yes = ydt == TSVDM_F64 ? 8 : 4;
+    // every block of R x n elements starts 16-byte aligned when X does and R
+    // is a multiple of the vector
+    const bool vec = R % (int64_t)(16 / sizeof(XT)) == 0 && (reinterpret_cast<uintptr_t>(X) & 15) == 0;
     for (int64_t p0 = 0; p0 < P; p0 += 65535) {
         const int64_t pc = P - p0 < 65535 ? P - p0 : 65535;
-        const void* Xp = static_cast<const char*>(X) + (size_t)(p0 * R * n) * xes;
+        const XT* Xp = static_cast<const XT*>(X) + (size_t)(p0 * R * n);
         void* Yp = static_cast<char*>(Y) + (size_t)(p0 * R * n) * yes;
-        ttm_kernel<CT, KIND, SHAPE><<<dim3((unsigned)blocks, (unsigned)pc), 256, 0, st>>>(
-            Xp, xdt, Yp, ydt, R, n, Tt, n_ct, n_rt);
+        const dim3 grid((unsigned)blocks, (unsigned)pc);
+        if (vec)
+            ttm_kernel<CT, XT, KIND, SHAPE, true><<<grid, 256, 0, st>>>(Xp, Yp, ydt, R, n, Tt, n_ct, n_rt);
+        else
+            ttm_kernel<CT, XT, KIND, SHAPE, false><<<grid, 256, 0, st>>>(Xp, Yp, ydt, R, n, Tt, n_ct, n_rt);
         TSVDM_LAUNCH_CHECK();
     }
     return TSVDM_OK;
+}
+
+template <class CT, class XT, int KIND>
+int launch_shape(const void* X, void* Y, int ydt, int64_t R, int n, int64_t P, const CT* Tt,
+                 int tile, hipStream_t st) {
+    switch (tile ? tile : default_tile(n)) {
+        case 1: return launch_tiles<CT, XT, KIND, 1>(X, Y, ydt, R, n, P, Tt, st);
+        case 2: return launch_tiles<CT, XT, KIND, 2>(X, Y, ydt, R, n, P, Tt, st);
+        case 3: return launch_tiles<CT, XT, KIND, 3>(X, Y, ydt, R, n, P, Tt, st);
+        default: set_error("unknown transform tile shape"); return TSVDM_E_ARG;
+    }
 }
 
 template <class CT, int KIND>
@@ -219,29 +323,32 @@ int launch_ttm(const void* X, int xdt, void* Y, int ydt, int64_t R, int n, int64
     int64_t nn = (int64_t)n * n;
     ttm_prep<CT><<<(unsigned)((nn + 255) / 256), 256, 0, st>>>(M, n, transpose, scale, Tt);
     TSVDM_LAUNCH_CHECK();
-    switch (tile ? tile : default_tile(n)) {
-        case 1: return launch_tiles<CT, KIND, 1>(X, xdt, Y, ydt, R, n, P, Tt, st);
-        case 2: return launch_tiles<CT, KIND, 2>(X, xdt, Y, ydt, R, n, P, Tt, st);
-        case 3: return launch_tiles<CT, KIND, 3>(X, xdt, Y, ydt, R, n, P, Tt, st);
-        default: set_error("unknown transform tile shape"); return TSVDM_E_ARG;
-    }
+    if (xdt == TSVDM_F64) return launch_shape<CT, double, KIND>(X, Y, ydt, R, n, P, Tt, tile, st);
+    return launch_shape<CT, float, KIND>(X, Y, ydt, R, n, P, Tt, tile, st);
 }
 
-template <class CT, int KIND>
-int launch_batch(const TtmProblem* probs, const int4* tasks, const int64_t* group, int xdt,
-                 int ydt, hipStream_t st) {
+template <class CT, class XT, int KIND>
+int launch_batch_x(const TtmProblem* probs, const int4* tasks, const int64_t* group, int ydt,
+                   hipStream_t st) {
     int64_t o = 0;
     for (int sh = 1; sh <= 3; ++sh) {
         const int64_t cnt = group[sh - 1];
         if (cnt > 0) {
-            if (sh == 1) ttm_kernel_batch<CT, KIND, 1><<<(unsigned)cnt, 256, 0, st>>>(probs, tasks + o, xdt, ydt);
-            else if (sh == 2) ttm_kernel_batch<CT, KIND, 2><<<(unsigned)cnt, 256, 0, st>>>(probs, tasks + o, xdt, ydt);
-            else ttm_kernel_batch<CT, KIND, 3><<<(unsigned)cnt, 256, 0, st>>>(probs, tasks + o, xdt, ydt);
+            if (sh == 1) ttm_kernel_batch<CT, XT, KIND, 1><<<(unsigned)cnt, 256, 0, st>>>(probs, tasks + o, ydt);
+            else if (sh == 2) ttm_kernel_batch<CT, XT, KIND, 2><<<(unsigned)cnt, 256, 0, st>>>(probs, tasks + o, ydt);
+            else ttm_kernel_batch<CT, XT, KIND, 3><<<(unsigned)cnt, 256, 0, st>>>(probs, tasks + o, ydt);
             TSVDM_LAUNCH_CHECK();
         }
         o += cnt;
     }
     return TSVDM_OK;
+}
+
+template <class CT, int KIND>
+int launch_batch(const TtmProblem* probs, const int4* tasks, const int64_t* group, int xdt,
+                 int ydt, hipStream_t st) {
+    if (xdt == TSVDM_F64) return launch_batch_x<CT, double, KIND>(probs, tasks, group, ydt, st);
+    return launch_batch_x<CT, float, KIND>(probs, tasks, group, ydt, st);
 }
 
 }  // namespace
