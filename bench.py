@@ -55,8 +55,9 @@ def read_stats(lib):
 
 def jacobi_roofline(st, peak_tf):
     """Roofline entry of jacobi_round for workloads without a single shape
-    (the batch, the order-6 tensor): the kernel's own per-pair flops and
-    bytes from the library's counters over the event-timed launches."""
+    (the batch): the kernel's own per-pair flops and bytes from the
+    library's counters over the event-timed launches (the caller adds the
+    method's flops)."""
     t = st["ms"] * 1e-3
     launches = max(st["launches"], 1)
     ai = st["flops"] / max(st["bytes"], 1.0)
@@ -534,6 +535,23 @@ def bench_ragged(a, torch, lib):
         status = int(b.status.item())
         errs = b.rel_errors()
         res[prec] = (ms, status, errs, [r.clone() for r in b.rho])
+        if prec == a.precision:
+            # the method's SVD flops of one batch run (SURVEY 8(d) convention,
+            # ranks read back), spread over the launches of the timed runs
+            alg = 0.0
+            for x, rr in zip(w.A, b.rho):
+                m_, p_, n_ = x.shape
+                fv, fr = svd_work(m_, p_, n_, int(rr.sum().item()))
+                alg += fv + fr
+            rf = out["roofline"]
+            per = alg * a.steps / max(rf["launches"], 1)
+            t = rf["avg_launch_ms"] * 1e-3
+            ach = per / t / 1e12
+            rf.update({"impl_bound": rf["bound"], "impl_achieved": rf["achieved"],
+                       "impl_peak": rf["peak"], "impl_unit": rf["unit"], "impl_frac": rf["frac"],
+                       "bound": "mfma", "achieved": round(ach, 3), "peak": PEAK["f32_TF"],
+                       "unit": "TFLOP/s", "frac": round(ach / PEAK["f32_TF"], 4),
+                       "algorithmic_flops_per_launch": per})
         del b
         torch.cuda.empty_cache()
     ms_mix, status, errs, rho_mix = res[a.precision]
