@@ -621,7 +621,8 @@ def bench_turbulence(a, torch, lib):
         res, ms = timed(lambda: op(Ad), a.steps, torch)
         rec = {"ms_per_step": round(ms, 2), "GBs": round(in_bytes / (ms * 1e-3) / 1e9, 3),
                "rel_error": res.rel_error(), "sum_rho": int(res.offsets[-1].item()),
-               "svd_status": int(res.svd_status.item())}
+               "svd_status": int(res.svd_status.item()), "guard": op.guard,
+               "eps_selected": res.eps_sel, "selections": res.selections}
         if prec == "f64":
             ref = res
         else:
