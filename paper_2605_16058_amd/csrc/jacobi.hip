@@ -78,6 +78,21 @@ void stats_get(int64_t* launches, double* ms, int64_t* pg, int64_t* pr, int32_t*
 
 namespace {
 
+// Pair statistics (gram-only pairs, rotating pairs, flops, bytes) are summed
+// into PC_BINS bins one 128-byte line apart, bin = workgroup index mod
+// PC_BINS: a single set of counters, hit by every workgroup of a launch,
+// serialised the atomics and took a quarter of a launch of short pairs.
+// They are kept only while statistics are switched on.
+constexpr int PC_BINS = 64, PC_STRIDE = 16;
+constexpr int PC_WORDS = PC_BINS * PC_STRIDE;
+
+// sum the bins of a copied counter block
+void pc_sum(const unsigned long long* bins, unsigned long long* out) {
+    for (int k = 0; k < 4; ++k) out[k] = 0ull;
+    for (int b = 0; b < PC_BINS; ++b)
+        for (int k = 0; k < 4; ++k) out[k] += bins[b * PC_STRIDE + k];
+}
+
 __device__ __forceinline__ int circle_player(int seat, int round, int N) {
     return seat == 0 ? 0 : ((seat - 1 + round) % (N - 1)) + 1;
 }
@@ -146,13 +161,8 @@ __global__ void jacobi_init(T* __restrict__ W, int64_t r, int64_t n, JacobiCtl* 
     }
     if (blockIdx.x == 0) {
         for (int i = threadIdx.x; i < max_sweeps; i += blockDim.x) remaining[i] = 0;
-        if (threadIdx.x == 0) {
-            *status = TSVDM_OK;
-            pair_counts[0] = 0ull;
-            pair_counts[1] = 0ull;
-            pair_counts[2] = 0ull;
-            pair_counts[3] = 0ull;
-        }
+        for (int i = threadIdx.x; i < PC_WORDS; i += blockDim.x) pair_counts[i] = 0ull;
+        if (threadIdx.x == 0) *status = TSVDM_OK;
     }
 }
 
@@ -515,9 +525,12 @@ __device__ __forceinline__ void round_body(RoundShared<T, NB2>& sh, T* __restric
             fl += 2ull * w * w * lw;
             by += 2ull * w * lw * sizeof(T);
         }
-        atomicAdd(&pair_counts[rotate ? 1 : 0], 1ull);
-        atomicAdd(&pair_counts[2], fl);
-        atomicAdd(&pair_counts[3], by);
+        if (pair_counts) {
+            unsigned long long* const pc = pair_counts + (blockIdx.x % PC_BINS) * PC_STRIDE;
+            atomicAdd(&pc[rotate ? 1 : 0], 1ull);
+            atomicAdd(&pc[2], fl);
+            atomicAdd(&pc[3], by);
+        }
     }
     if (!rotate) return;  // uniform across the block
     // FP64: the first vector tile of the update is in flight during the
@@ -939,13 +952,8 @@ __global__ void jacobi_init_batch(const BatchSlice* __restrict__ sl, JacobiCtl* 
     }
     if (blockIdx.x == 0) {
         for (int i = threadIdx.x; i < max_steps; i += blockDim.x) remaining[i] = 0;
-        if (threadIdx.x == 0) {
-            *status = TSVDM_OK;
-            pair_counts[0] = 0ull;
-            pair_counts[1] = 0ull;
-            pair_counts[2] = 0ull;
-            pair_counts[3] = 0ull;
-        }
+        for (int i = threadIdx.x; i < PC_WORDS; i += blockDim.x) pair_counts[i] = 0ull;
+        if (threadIdx.x == 0) *status = TSVDM_OK;
     }
 }
 
@@ -1069,8 +1077,9 @@ int jacobi_impl(T* A, int64_t m, int64_t p, int64_t n, T* W, double* s2, int32_t
     Carver cv(ws);
     JacobiCtl* ctl = cv.carve<JacobiCtl>((size_t)n);
     int* remaining = cv.carve<int>((size_t)o.max_sweeps);
-    unsigned long long* pair_counts = cv.carve<unsigned long long>(4);
+    unsigned long long* pair_counts = cv.carve<unsigned long long>(PC_WORDS);
     const bool stats = stats_enabled();
+    unsigned long long* const pcount = stats ? pair_counts : nullptr;   // counted only for statistics
     std::vector<hipEvent_t> evs;
 
     int64_t gblocks = g.r * n;   // one workgroup per column of W (grid-stride beyond the cap)
@@ -1119,16 +1128,16 @@ int jacobi_impl(T* A, int64_t m, int64_t p, int64_t n, T* W, double* s2, int32_t
         for (int rnd = 0; rnd < nbe - 1; ++rnd) {
             if (g.rows && interior)
                 jacobi_round<T, NB2, true, true><<<(unsigned)blocks, 256, 0, st>>>(
-                    A, W, g, nbe, rnd, ctl, o.tol, vec_a, vec_w, pair_counts);
+                    A, W, g, nbe, rnd, ctl, o.tol, vec_a, vec_w, pcount);
             else if (g.rows)
                 jacobi_round<T, NB2, true, false><<<(unsigned)blocks, 256, 0, st>>>(
-                    A, W, g, nbe, rnd, ctl, o.tol, vec_a, vec_w, pair_counts);
+                    A, W, g, nbe, rnd, ctl, o.tol, vec_a, vec_w, pcount);
             else if (interior)
                 jacobi_round<T, NB2, false, true><<<(unsigned)blocks, 256, 0, st>>>(
-                    A, W, g, nbe, rnd, ctl, o.tol, vec_a, vec_w, pair_counts);
+                    A, W, g, nbe, rnd, ctl, o.tol, vec_a, vec_w, pcount);
             else
                 jacobi_round<T, NB2, false, false><<<(unsigned)blocks, 256, 0, st>>>(
-                    A, W, g, nbe, rnd, ctl, o.tol, vec_a, vec_w, pair_counts);
+                    A, W, g, nbe, rnd, ctl, o.tol, vec_a, vec_w, pcount);
             TSVDM_LAUNCH_CHECK();
             ++launches;
         }
@@ -1171,9 +1180,12 @@ int jacobi_impl(T* A, int64_t m, int64_t p, int64_t n, T* W, double* s2, int32_t
         (void)hipEventDestroy(pev[1]);
     }
     if (stats) {
-        unsigned long long pc[4] = {0ull, 0ull, 0ull, 0ull};
-        TSVDM_HIP_CHECK(hipMemcpyAsync(pc, pair_counts, sizeof(pc), hipMemcpyDeviceToHost, st));
+        std::vector<unsigned long long> bins(PC_WORDS);
+        unsigned long long pc[4];
+        TSVDM_HIP_CHECK(hipMemcpyAsync(bins.data(), pair_counts, sizeof(unsigned long long) * PC_WORDS,
+                                       hipMemcpyDeviceToHost, st));
         TSVDM_HIP_CHECK(hipStreamSynchronize(st));
+        pc_sum(bins.data(), pc);
         double ms = 0.0;
         for (size_t i = 0; i + 1 < evs.size(); i += 2) {
             float t = 0.f;
@@ -1193,7 +1205,7 @@ int jacobi_batch_impl(const BatchSlice* sl, int64_t nslices, const int2* tasks,
     Carver cv(ctl_ws);
     JacobiCtl* ctl = cv.carve<JacobiCtl>((size_t)nslices);
     int* remaining = cv.carve<int>((size_t)max_steps);
-    unsigned long long* pair_counts = cv.carve<unsigned long long>(4);
+    unsigned long long* pair_counts = cv.carve<unsigned long long>(PC_WORDS);
     TSVDM_REQUIRE(nslices < ((int64_t)1 << 31) && group[0] < ((int64_t)1 << 31) &&
                       group[1] < ((int64_t)1 << 31),
                   TSVDM_E_SHAPE, "batch too large for one launch");
@@ -1201,6 +1213,7 @@ int jacobi_batch_impl(const BatchSlice* sl, int64_t nslices, const int2* tasks,
                                                            pair_counts, status);
     TSVDM_LAUNCH_CHECK();
     const bool stats = stats_enabled();
+    unsigned long long* const pcount = stats ? pair_counts : nullptr;   // counted only for statistics
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (stats) {
         TSVDM_HIP_CHECK(hipEventCreate(&e0));
@@ -1222,13 +1235,13 @@ int jacobi_batch_impl(const BatchSlice* sl, int64_t nslices, const int2* tasks,
     for (int t = 0; t < max_steps; ++t) {
         // both pair widths see the same round counter t
         if (group[0] > 0) {
-            jacobi_round_batch<T, 32><<<(unsigned)group[0], 256, 0, st>>>(sl, tasks, t, ctl, pair_counts);
+            jacobi_round_batch<T, 32><<<(unsigned)group[0], 256, 0, st>>>(sl, tasks, t, ctl, pcount);
             TSVDM_LAUNCH_CHECK();
             ++launches;
         }
         if (group[1] > 0) {
             jacobi_round_batch<T, 64><<<(unsigned)group[1], 256, 0, st>>>(sl, tasks + group[0], t, ctl,
-                                                                         pair_counts);
+                                                                         pcount);
             TSVDM_LAUNCH_CHECK();
             ++launches;
         }
@@ -1263,9 +1276,12 @@ int jacobi_batch_impl(const BatchSlice* sl, int64_t nslices, const int2* tasks,
         (void)hipEventDestroy(pev[1]);
     }
     if (stats) {
-        unsigned long long pc[4] = {0ull, 0ull, 0ull, 0ull};
-        TSVDM_HIP_CHECK(hipMemcpyAsync(pc, pair_counts, sizeof(pc), hipMemcpyDeviceToHost, st));
+        std::vector<unsigned long long> bins(PC_WORDS);
+        unsigned long long pc[4];
+        TSVDM_HIP_CHECK(hipMemcpyAsync(bins.data(), pair_counts, sizeof(unsigned long long) * PC_WORDS,
+                                       hipMemcpyDeviceToHost, st));
         TSVDM_HIP_CHECK(hipStreamSynchronize(st));
+        pc_sum(bins.data(), pc);
         float ms = 0.f;
         TSVDM_HIP_CHECK(hipEventElapsedTime(&ms, e0, e1));
         (void)hipEventDestroy(e0);
@@ -1283,7 +1299,7 @@ size_t jacobi_batch_ctl_bytes(int64_t nslices, int max_steps) {
     Carver cv(nullptr);
     cv.carve<JacobiCtl>((size_t)nslices);
     cv.carve<int>((size_t)max_steps);
-    cv.carve<unsigned long long>(4);
+    cv.carve<unsigned long long>(PC_WORDS);
     return cv.total();
 }
 
@@ -1299,7 +1315,7 @@ size_t jacobi_workspace_bytes(int64_t n) {
     Carver cv(nullptr);
     cv.carve<JacobiCtl>((size_t)n);
     cv.carve<int>(1024);
-    cv.carve<unsigned long long>(4);
+    cv.carve<unsigned long long>(PC_WORDS);
     return cv.total();
 }
 
