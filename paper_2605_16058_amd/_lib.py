@@ -42,6 +42,9 @@ _SIGS = {
                                 c_double, c_int, _P, c_size_t, _P]),
     "tsvdm_slice_svd_subset": (c_int, [_P, c_int, c_int64, c_int64, c_int64, _P, _P, _P, _P, c_int,
                                        c_int, c_double, c_int, _P, c_size_t, _P]),
+    "tsvdm_slice_svd_precond_workspace_size": (c_int, [c_int64, c_int64, c_int64, c_int, POINTER(c_size_t)]),
+    "tsvdm_slice_svd_precond": (c_int, [_P, c_int, c_int64, c_int64, c_int64, _P, _P, _P, _P, c_int, c_int,
+                                        c_double, c_int, _P, c_size_t, _P]),
     "tsvdm_slice_svd_gram_workspace_size": (c_int, [c_int64, c_int64, c_int64, POINTER(c_size_t)]),
     "tsvdm_slice_svd_gram": (c_int, [_P, c_int64, c_int64, c_int64, _P, _P, _P, _P, c_int, c_int, c_double,
                                      c_int, c_int, _P, c_size_t, _P]),

@@ -230,6 +230,39 @@ int tsvdm_slice_svd(void* A_hat, int dtype, int64_t m, int64_t p, int64_t n, voi
     return run_jacobi(A_hat, dtype, m, p, n, W, s2, status, o, ws, as_stream(stream));
 }
 
+int tsvdm_slice_svd_precond_workspace_size(int64_t m, int64_t p, int64_t n, int dtype, size_t* bytes) {
+    clear_error();
+    TSVDM_REQUIRE(bytes != nullptr, TSVDM_E_ARG, "bytes is NULL");
+    TSVDM_TRY(check_shape(m, p, n));
+    TSVDM_REQUIRE(dtype == TSVDM_F64, TSVDM_E_UNSUPPORTED, "dtype must be F64");
+    TSVDM_REQUIRE(std::min(m, p) <= GRAM_MAX_R, TSVDM_E_SHAPE, "min(m, p) must be <= 1024");
+    *bytes = precond_svd_workspace_bytes(m, p, n, dtype);
+    return TSVDM_OK;
+}
+
+int tsvdm_slice_svd_precond(const void* A_hat, int dtype, int64_t m, int64_t p, int64_t n, void* X,
+                            void* W, double* s2, int32_t* status, int block, int max_sweeps,
+                            double tol, int host_poll, void* ws, size_t ws_bytes, void* stream) {
+    clear_error();
+    TSVDM_TRY(check_shape(m, p, n));
+    TSVDM_REQUIRE(A_hat && X && W && s2 && status, TSVDM_E_ARG, "A_hat, X, W, s2 and status must be non-NULL");
+    TSVDM_REQUIRE(A_hat != X, TSVDM_E_ARG, "X must not alias A_hat");
+    TSVDM_REQUIRE(dtype == TSVDM_F64, TSVDM_E_UNSUPPORTED, "dtype must be F64");
+    TSVDM_REQUIRE(std::min(m, p) <= GRAM_MAX_R, TSVDM_E_SHAPE, "min(m, p) must be <= 1024");
+    TSVDM_REQUIRE(n < 65536, TSVDM_E_SHAPE, "n must be below 65536");
+    TSVDM_REQUIRE(block == 0 || block == 16 || block == 32, TSVDM_E_ARG, "block must be 0, 16 or 32");
+    TSVDM_REQUIRE(max_sweeps >= 0 && max_sweeps <= 1000, TSVDM_E_ARG, "max_sweeps must be in [0, 1000]");
+    TSVDM_REQUIRE(tol >= 0.0 && tol < 1.0 && std::isfinite(tol), TSVDM_E_ARG, "tol must lie in [0, 1)");
+    TSVDM_REQUIRE(host_poll == 0 || host_poll == 1, TSVDM_E_ARG, "host_poll must be 0 or 1");
+    TSVDM_TRY(check_ws(ws, ws_bytes, precond_svd_workspace_bytes(m, p, n, dtype)));
+    JacobiOpts o = jacobi_default_opts(m, p, dtype);
+    if (block) o.block = 2 * block;
+    if (max_sweeps) o.max_sweeps = max_sweeps;
+    if (tol > 0.0) o.tol = tol;
+    o.host_poll = host_poll;
+    return run_precond_svd(A_hat, dtype, m, p, n, X, W, s2, status, o, ws, as_stream(stream));
+}
+
 int tsvdm_slice_svd_gram_workspace_size(int64_t m, int64_t p, int64_t n, size_t* bytes) {
     clear_error();
     TSVDM_REQUIRE(bytes != nullptr, TSVDM_E_ARG, "bytes is NULL");

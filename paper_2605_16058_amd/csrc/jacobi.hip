@@ -1086,8 +1086,8 @@ int jacobi_impl(T* A, int64_t m, int64_t p, int64_t n, T* W, double* s2, int32_t
     if (gblocks < (n + 255) / 256) gblocks = (n + 255) / 256;
     if (gblocks > 65535 * 16) gblocks = 65535 * 16;
     if (gblocks < 1) gblocks = 1;
-    jacobi_init<T><<<(unsigned)gblocks, 256, 0, st>>>(W, g.r, n, ctl, remaining, o.max_sweeps,
-                                                      pair_counts, status, o.run);
+    jacobi_init<T><<<(unsigned)gblocks, 256, 0, st>>>(o.w_given ? nullptr : W, g.r, n, ctl, remaining,
+                                                      o.max_sweeps, pair_counts, status, o.run);
     TSVDM_LAUNCH_CHECK();
 
     constexpr int B = NB2 / 2;

@@ -154,6 +154,8 @@ struct JacobiOpts {
     // device int32[n] or null: slices with run[i] == 0 are left untouched
     // (their A, W and s2 keep whatever they hold)
     const int32_t* run = nullptr;
+    // 1: W already holds the slices' starting rotation (not reset to I)
+    int w_given = 0;
 };
 
 size_t jacobi_workspace_bytes(int64_t n);
@@ -163,6 +165,11 @@ size_t gram_svd_workspace_bytes(int64_t m, int64_t p, int64_t n);
 int run_gram_svd(const float* A_hat, int64_t m, int64_t p, int64_t n, float* B, double* s2,
                  double* shift, int32_t* status, const JacobiOpts& o, int jacobi, void* ws,
                  hipStream_t st);
+// Preconditioned rotation form: the Gram form's vectors rotate the slice
+// (X = W^T A or A W) and the rotation form finishes on X from W
+size_t precond_svd_workspace_bytes(int64_t m, int64_t p, int64_t n, int dt);
+int run_precond_svd(const void* A_hat, int dt, int64_t m, int64_t p, int64_t n, void* X, void* W,
+                    double* s2, int32_t* status, const JacobiOpts& o, void* ws, hipStream_t st);
 int run_gram_pack(const float* A_hat, const float* B, const double* s2, const double* shift,
                   int64_t m, int64_t p, int64_t n, const int32_t* rho, const int64_t* offsets,
                   int64_t capacity, float* U_pk, float* G_pk, float* S_pk, int32_t* status,

@@ -55,7 +55,8 @@ __device__ __forceinline__ void tri_tile(int q, int& ti, int& tj) {
 // that the stores run along i (G is column-major: G[i + j r]).  The next K
 // chunk is loaded into registers while the MFMAs of the current one run;
 // two LDS buffers, one barrier per chunk.
-__device__ __forceinline__ void gram_tile(const float* __restrict__ X, const SliceGeom& g, int ti, int tj,
+template <class T>
+__device__ __forceinline__ void gram_tile(const T* __restrict__ X, const SliceGeom& g, int ti, int tj,
                                           double* __restrict__ Gs) {
     __shared__ double sa[2][64][GK + 1];   // operand rows i
     __shared__ double sb[2][64][GK + 1];   // operand rows j
@@ -68,19 +69,25 @@ __device__ __forceinline__ void gram_tile(const float* __restrict__ X, const Sli
     const int v0 = rows ? (tid & 15) * 4 : (tid >> 2);
     const int t0 = rows ? (tid >> 4) : (tid & 3) * 4;
     const bool vec = (g.m % 4) == 0;   // 16-byte alignment of every group of four
-    float ra[4], rb[4];
-    auto load1 = [&](int64_t base_v, int64_t tc, float* out) {
+    T ra[4], rb[4];
+    auto load1 = [&](int64_t base_v, int64_t tc, T* out) {
         const int64_t v = base_v + v0, t = tc + t0;
-        const float* src = X + v * vs + t * es;
+        const T* src = X + v * vs + t * es;
         const bool full = rows ? (v + 3 < r && t < L) : (v < r && t + 3 < L);
         if (vec && full) {
-            const float4 x = *reinterpret_cast<const float4*>(src);
-            out[0] = x.x; out[1] = x.y; out[2] = x.z; out[3] = x.w;
+            if constexpr (sizeof(T) == 4) {
+                const float4 x = *reinterpret_cast<const float4*>(src);
+                out[0] = x.x; out[1] = x.y; out[2] = x.z; out[3] = x.w;
+            } else {
+                const double2 x = *reinterpret_cast<const double2*>(src);
+                const double2 y = *reinterpret_cast<const double2*>(src + 2);
+                out[0] = x.x; out[1] = x.y; out[2] = y.x; out[3] = y.y;
+            }
         } else {
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
                 const int64_t vq = rows ? v + q : v, tq = rows ? t : t + q;
-                out[q] = (vq < r && tq < L) ? X[vq * vs + tq * es] : 0.0f;
+                out[q] = (vq < r && tq < L) ? X[vq * vs + tq * es] : T(0);
             }
         }
     };
@@ -124,7 +131,8 @@ __device__ __forceinline__ void gram_tile(const float* __restrict__ X, const Sli
     }
 }
 
-__global__ __launch_bounds__(256) void pc_gram(const float* __restrict__ A, SliceGeom g, int ntri,
+template <class T>
+__global__ __launch_bounds__(256) void pc_gram(const T* __restrict__ A, SliceGeom g, int ntri,
                                                double* __restrict__ G) {
     const int64_t s = blockIdx.x / ntri;
     int ti, tj;
@@ -149,9 +157,9 @@ __global__ __launch_bounds__(256) void pc_gram_batch(const GramSlice* __restrict
 // diagonal block is factorised by one wave and the rows below are solved
 // against it.  A pivot <= 0 (rounding of a singular G + s I) gives a zero
 // column.  Fixed operation order: the result does not depend on timing.
-template <int MAXR>
+template <int MAXR, class OT>
 __device__ __forceinline__ void chol_slice(const double* __restrict__ Gs, int64_t r, double cshift,
-                                           double* __restrict__ Ls, float* __restrict__ Os,
+                                           double* __restrict__ Ls, OT* __restrict__ Os,
                                            double* __restrict__ shift_out) {
     constexpr int PLD = CB + 1;
     __shared__ double P[MAXR * PLD];
@@ -255,19 +263,19 @@ __device__ __forceinline__ void chol_slice(const double* __restrict__ Gs, int64_
                 const int64_t li = i - k0;
                 const double v = (li < c) ? 0.0 : P[li * PLD + c];
                 if (li >= c) Ls[i + col * r] = v;
-                Os[i + col * r] = (float)v;
+                Os[i + col * r] = (OT)v;
             }
         }
         __syncthreads();
     }
 }
 
-template <int MAXR>
+template <int MAXR, class OT>
 __global__ __launch_bounds__(256) void pc_chol(const double* __restrict__ G, int64_t r, double cshift,
-                                               double* __restrict__ Lw, float* __restrict__ Lo,
+                                               double* __restrict__ Lw, OT* __restrict__ Lo,
                                                double* __restrict__ shift) {
     const int64_t s = blockIdx.x;
-    chol_slice<MAXR>(G + s * r * r, r, cshift, Lw + s * r * r, Lo + s * r * r, shift + s);
+    chol_slice<MAXR, OT>(G + s * r * r, r, cshift, Lw + s * r * r, Lo + s * r * r, shift + s);
 }
 
 // batch: one workgroup per Gram slice listed (one size class, r <= MAXR)
@@ -276,7 +284,7 @@ __global__ __launch_bounds__(256) void pc_chol_batch(const GramSlice* __restrict
                                                      const int* __restrict__ list) {
     const GramSlice d = gs[list[blockIdx.x]];
     const double cshift = (double)(d.g.L + d.g.r) * 1.1102230246251565e-16;
-    chol_slice<MAXR>(d.G, d.g.r, cshift, d.Lw, d.B, d.shift);
+    chol_slice<MAXR, float>(d.G, d.g.r, cshift, d.Lw, d.B, d.shift);
 }
 
 // seat -> player of the circle tournament over N (even) players in round
@@ -505,6 +513,52 @@ __global__ __launch_bounds__(256) void pc_unshift_batch(const GramSlice* __restr
         const double v = d.s2[j] - sh;
         d.s2[j] = v > 0.0 ? v : 0.0;
     }
+}
+
+// Preconditioned rotation form: W (r x r per slice) = the columns of B
+// scaled to unit norm, and Ut = W^T when asked (wide slices); a column of
+// zero or non-finite norm (a failed factorisation) sets *flag to
+// TSVDM_E_NONFINITE unless it already holds a condition.
+template <class T>
+__global__ __launch_bounds__(256) void pc_normalize(const T* __restrict__ B, int64_t r, T* __restrict__ W,
+                                                    T* __restrict__ Ut, int32_t* __restrict__ flag) {
+    __shared__ double red[256];
+    const int64_t j = blockIdx.x, s = blockIdx.y;
+    const T* b = B + s * r * r + j * r;
+    double acc = 0.0;
+    for (int64_t i = threadIdx.x; i < r; i += 256) {
+        const double x = (double)b[i];
+        acc = fma(x, x, acc);
+    }
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    const double n2 = red[0];
+    const bool ok = n2 > 0.0 && isfinite(n2);
+    if (!ok && threadIdx.x == 0) atomicCAS(flag, (int32_t)TSVDM_OK, (int32_t)TSVDM_E_NONFINITE);
+    const double inv = ok ? 1.0 / sqrt(n2) : 0.0;
+    T* w = W + s * r * r + j * r;
+    for (int64_t i = threadIdx.x; i < r; i += 256) {
+        const T v = (T)((double)b[i] * inv);
+        w[i] = v;
+        if (Ut) Ut[s * r * r + i * r + j] = v;
+    }
+}
+
+// rho[i] = r, off[i] = i r: every slice's full-rank block for the product
+// that applies W to the slice
+__global__ void pc_rank_full(int32_t* __restrict__ rho, int64_t* __restrict__ off, int64_t r, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) rho[i] = (int32_t)r;
+    if (i <= n) off[i] = i * r;
+}
+
+// status <- the first stage's condition when the second reported none
+__global__ void pc_merge_status(int32_t* __restrict__ status, const int32_t* __restrict__ first) {
+    if (threadIdx.x == 0 && blockIdx.x == 0 && *status == TSVDM_OK) *status = *first;
 }
 
 // Short-side factor from B: kept column c (sorted position c, index j =
@@ -918,6 +972,26 @@ size_t gram_svd_workspace_bytes(int64_t m, int64_t p, int64_t n) {
 }
 
 
+// G = X X^T (FP64) and the shifted Cholesky factor L L^T = G + s I of every
+// slice: L in FP64 (Lw) and in T (B, zeros above the diagonal), s per slice.
+template <class T>
+int gram_factor(const T* A_hat, const SliceGeom& g, int64_t n, double* G, double* Lw, T* B,
+                double* shift, hipStream_t st) {
+    const int64_t r = g.r;
+    const int nt = (int)((r + 63) / 64);
+    const int ntri = nt * (nt + 1) / 2;
+    TSVDM_REQUIRE((int64_t)ntri * n < ((int64_t)1 << 31), TSVDM_E_SHAPE, "too many Gram tiles");
+    pc_gram<T><<<(unsigned)(ntri * n), 256, 0, st>>>(A_hat, g, ntri, G);
+    TSVDM_LAUNCH_CHECK();
+    const double cshift = (double)(g.L + r) * 1.1102230246251565e-16;
+    if (r <= 128) pc_chol<128, T><<<(unsigned)n, 256, 0, st>>>(G, r, cshift, Lw, B, shift);
+    else if (r <= 256) pc_chol<256, T><<<(unsigned)n, 256, 0, st>>>(G, r, cshift, Lw, B, shift);
+    else if (r <= 512) pc_chol<512, T><<<(unsigned)n, 256, 0, st>>>(G, r, cshift, Lw, B, shift);
+    else pc_chol<1024, T><<<(unsigned)n, 256, 0, st>>>(G, r, cshift, Lw, B, shift);
+    TSVDM_LAUNCH_CHECK();
+    return TSVDM_OK;
+}
+
 int run_gram_svd(const float* A_hat, int64_t m, int64_t p, int64_t n, float* B, double* s2,
                  double* shift, int32_t* status, const JacobiOpts& o, int jacobi, void* ws,
                  hipStream_t st) {
@@ -928,17 +1002,8 @@ int run_gram_svd(const float* A_hat, int64_t m, int64_t p, int64_t n, float* B, 
     double* G = cv.carve<double>((size_t)(r * r * n));
     double* Lw = cv.carve<double>((size_t)(r * r * n));
     void* jws = static_cast<char*>(ws) + cv.total();
-    const int nt = (int)((r + 63) / 64);
-    const int ntri = nt * (nt + 1) / 2;
-    TSVDM_REQUIRE((int64_t)ntri * n < ((int64_t)1 << 31), TSVDM_E_SHAPE, "too many Gram tiles");
-    pc_gram<<<(unsigned)(ntri * n), 256, 0, st>>>(A_hat, g, ntri, G);
-    TSVDM_LAUNCH_CHECK();
-    const double cshift = (double)(g.L + r) * 1.1102230246251565e-16;
-    if (r <= 128) pc_chol<128><<<(unsigned)n, 256, 0, st>>>(G, r, cshift, Lw, B, shift);
-    else if (r <= 256) pc_chol<256><<<(unsigned)n, 256, 0, st>>>(G, r, cshift, Lw, B, shift);
-    else if (r <= 512) pc_chol<512><<<(unsigned)n, 256, 0, st>>>(G, r, cshift, Lw, B, shift);
-    else pc_chol<1024><<<(unsigned)n, 256, 0, st>>>(G, r, cshift, Lw, B, shift);
-    TSVDM_LAUNCH_CHECK();
+    const int rc0 = gram_factor<float>(A_hat, g, n, G, Lw, B, shift, st);
+    if (rc0) return rc0;
     // one-sided Jacobi on the columns of L (r x r), no accumulated rotations:
     // held in LDS, or the block rounds streaming through HBM
     const bool lds = jacobi == TSVDM_GRAM_LDS || (jacobi == TSVDM_GRAM_AUTO && r <= GRAM_LDS_MAX_R);
@@ -997,6 +1062,83 @@ int run_gram_pack(const float* A_hat, const float* B, const double* s2, const do
         pc_factor<false><<<gf, 256, 0, st>>>(A_hat, B, s2, shift, g, rho, offsets, capacity, perm, tiles_t, U_pk);
     TSVDM_LAUNCH_CHECK();
     return TSVDM_OK;
+}
+
+size_t precond_svd_workspace_bytes(int64_t m, int64_t p, int64_t n, int dt) {
+    const SliceGeom g = slice_geom(m, p);
+    const size_t e = dt == TSVDM_F64 ? 8 : 4;
+    const size_t rr = (size_t)(g.r * g.r * n);
+    Carver cv(nullptr);
+    cv.carve<double>(rr);                  // G
+    cv.carve<double>(rr);                  // L (FP64)
+    cv.carve<char>(rr * e);                // B
+    cv.carve<char>(g.rows ? rr * e : 1);   // W^T (wide slices)
+    cv.carve<double>((size_t)n);           // shifts
+    cv.carve<int32_t>((size_t)n);          // full ranks
+    cv.carve<int64_t>((size_t)n + 1);      // their offsets
+    cv.carve<int32_t>(1);                  // first-stage status
+    return cv.total() + jacobi_workspace_bytes(n);
+}
+
+namespace {
+
+template <class T>
+int precond_impl(const T* A_hat, int dt, int64_t m, int64_t p, int64_t n, T* X, T* W, double* s2,
+                 int32_t* status, const JacobiOpts& o, void* ws, hipStream_t st) {
+    const SliceGeom g = slice_geom(m, p);
+    const int64_t r = g.r;
+    TSVDM_REQUIRE(r <= GRAM_MAX_R, TSVDM_E_SHAPE, "min(m, p) must be <= 1024 for the preconditioned form");
+    TSVDM_REQUIRE(n < 65536, TSVDM_E_SHAPE, "n must be below 65536");
+    const size_t rr = (size_t)(r * r * n);
+    Carver cv(ws);
+    double* G = cv.carve<double>(rr);
+    double* Lw = cv.carve<double>(rr);
+    T* B = cv.carve<T>(rr);
+    T* Ut = cv.carve<T>(g.rows ? rr : 1);
+    double* shift = cv.carve<double>((size_t)n);
+    int32_t* rho = cv.carve<int32_t>((size_t)n);
+    int64_t* off = cv.carve<int64_t>((size_t)n + 1);
+    int32_t* s1 = cv.carve<int32_t>(1);
+    void* jws = static_cast<char*>(ws) + cv.total();
+    // 1. the Gram form's factor and its Jacobi (no accumulator): B's unit
+    //    columns are the short-side singular vectors to within the FP64
+    //    Gram's rounding
+    int rc = gram_factor<T>(A_hat, g, n, G, Lw, B, shift, st);
+    if (rc) return rc;
+    JacobiOpts o1 = jacobi_default_opts(r, r, dt);
+    o1.block = o.block;
+    o1.max_sweeps = o.max_sweeps;
+    o1.host_poll = o.host_poll;
+    rc = run_jacobi(B, dt, r, r, n, nullptr, s2, s1, o1, jws, st);
+    if (rc) return rc;
+    pc_normalize<T><<<dim3((unsigned)r, (unsigned)n), 256, 0, st>>>(B, r, W, g.rows ? Ut : nullptr, s1);
+    TSVDM_LAUNCH_CHECK();
+    // 2. the slice rotated by them: X = W^T A (wide) or A W (tall)
+    pc_rank_full<<<(unsigned)((n + 256) / 256), 256, 0, st>>>(rho, off, r, n);
+    TSVDM_LAUNCH_CHECK();
+    if (g.rows) rc = run_lowrank_gemm(Ut, A_hat, dt, m, p, n, rho, off, r * n, X, st);
+    else rc = run_lowrank_gemm(A_hat, W, dt, m, p, n, rho, off, r * n, X, st);
+    if (rc) return rc;
+    // 3. the rotation form on X, accumulating into W: its first sweeps find
+    //    the vectors nearly orthogonal already
+    JacobiOpts o2 = o;
+    o2.w_given = 1;
+    rc = run_jacobi(X, dt, m, p, n, W, s2, status, o2, jws, st);
+    if (rc) return rc;
+    pc_merge_status<<<1, 64, 0, st>>>(status, s1);
+    TSVDM_LAUNCH_CHECK();
+    return TSVDM_OK;
+}
+
+}  // namespace
+
+int run_precond_svd(const void* A_hat, int dt, int64_t m, int64_t p, int64_t n, void* X, void* W,
+                    double* s2, int32_t* status, const JacobiOpts& o, void* ws, hipStream_t st) {
+    if (dt == TSVDM_F64)
+        return precond_impl<double>(static_cast<const double*>(A_hat), dt, m, p, n, static_cast<double*>(X),
+                                    static_cast<double*>(W), s2, status, o, ws, st);
+    return precond_impl<float>(static_cast<const float*>(A_hat), dt, m, p, n, static_cast<float*>(X),
+                               static_cast<float*>(W), s2, status, o, ws, st);
 }
 
 }  // namespace tsvdm

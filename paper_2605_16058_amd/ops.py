@@ -207,6 +207,25 @@ def tsvdm_slice_svd(A_hat, block=0, max_sweeps=0, tol=0.0, host_poll=True, ws=No
     return W, s2, status
 
 
+def tsvdm_slice_svd_precond(A_hat, block=0, max_sweeps=0, tol=0.0, host_poll=True, ws=None):
+    """Rotation-form slice SVDs preconditioned by the Gram form (A_hat is only
+    read).  Returns (X, W, s2, status): X holds the orthogonalised vectors
+    that tsvdm_slice_svd would leave in A_hat, W and s2 as there."""
+    if not is_colmajor(A_hat):
+        raise ValueError("A_hat must be column-major")
+    m, p, n = A_hat.shape
+    r = min(m, p)
+    X = colmajor_empty(m, p, n, A_hat.dtype, A_hat.device)
+    W = torch.empty((n, r, r), dtype=A_hat.dtype, device=A_hat.device)
+    s2 = torch.empty((n, r), dtype=torch.float64, device=A_hat.device)
+    status = torch.zeros(1, dtype=torch.int32, device=A_hat.device)
+    w = _ws(ws)
+    wp, wn = w.args(_lib.workspace_size("tsvdm_slice_svd_precond_workspace_size", m, p, n, _dt(A_hat)))
+    _lib.call("tsvdm_slice_svd_precond", _ptr(A_hat), _dt(A_hat), m, p, n, _ptr(X), _ptr(W), _ptr(s2),
+              _ptr(status), int(block), int(max_sweeps), float(tol), int(bool(host_poll)), wp, wn, _stream())
+    return X, W, s2, status
+
+
 def tsvdm_slice_svd_gram(A_hat, block=0, max_sweeps=0, tol=0.0, host_poll=True, ws=None, jacobi="auto"):
     """Slice SVDs of an FP32 tensor by way of the FP64 Gram matrix (A_hat is
     only read).  Returns (B, s2, shift, status): B (n, r, r) FP32 holds the

@@ -84,15 +84,22 @@ def resolve_svd(svd, precision, r, certify=False):
     """Slice SVD form: "jacobi" rotates the slice itself (any precision);
     "gram" (FP32 Jacobi dtype only, min(m, p) <= 1024) runs the Jacobi on
     the Cholesky factor of the slice's FP64 Gram matrix and forms the long-
-    side factor by one product (tsvdm_slice_svd_gram).  "auto": "gram" on the
-    reduced-precision paths where it applies, else "jacobi"."""
-    if svd not in ("auto", "jacobi", "gram"):
-        raise ValueError("svd must be 'auto', 'jacobi' or 'gram'")
-    ok = PRECISIONS[precision][1] == torch.float32 and r <= GRAM_MAX_R and not certify
+    side factor by one product (tsvdm_slice_svd_gram); "precond" (FP64 path,
+    min(m, p) <= 1024) rotates the slice by the FP64 Gram form's vectors and
+    finishes with the rotation form, to its accuracy (tsvdm_slice_svd_precond).  "auto":
+    "gram" on the reduced-precision paths where it applies, "precond" on the
+    FP64 path where it applies, else "jacobi"."""
+    if svd not in ("auto", "jacobi", "gram", "precond"):
+        raise ValueError("svd must be 'auto', 'jacobi', 'gram' or 'precond'")
+    fits = r <= GRAM_MAX_R and not certify
+    ok = PRECISIONS[precision][1] == torch.float32 and fits
+    ok64 = PRECISIONS[precision][1] == torch.float64 and fits
     if svd == "gram" and not ok:
         raise ValueError("svd='gram' needs an FP32 Jacobi path, min(m, p) <= 1024 and no certify")
+    if svd == "precond" and not ok64:
+        raise ValueError("svd='precond' needs the FP64 path, min(m, p) <= 1024 and no certify")
     if svd == "auto":
-        return "gram" if ok else "jacobi"
+        return "gram" if ok else ("precond" if ok64 else "jacobi")
     return svd
 
 
@@ -131,7 +138,7 @@ class TSVDM:
     instead of the dense product: forward, and after the transform-domain
     low-rank product (tsvdm_lowrank) backward; precision f64 or f32 only.
 
-    svd: "auto", "jacobi" or "gram" (see resolve_svd).  gram_jacobi: where
+    svd: "auto", "jacobi", "gram" or "precond" (see resolve_svd).  gram_jacobi: where
     the Gram form's Jacobi on the factor runs, "auto" (in LDS for
     min(m, p) <= 128, else the block rounds), "rounds" or "lds".
 
@@ -235,6 +242,10 @@ class TSVDM:
             W, s2, shift, svd_status = ops.tsvdm_slice_svd_gram(
                 A_hat, self.block, self.max_sweeps, self.tol, self.host_poll, ws=self.ws,
                 jacobi=self.gram_jacobi)
+        elif self.svd == "precond":
+            # the orthogonalised vectors land in a new tensor, packed from below
+            A_hat, W, s2, svd_status = ops.tsvdm_slice_svd_precond(
+                A_hat, self.block, self.max_sweeps, self.tol, self.host_poll, ws=self.ws)
         else:
             W, s2, svd_status = ops.tsvdm_slice_svd(A_hat, self.block, self.max_sweeps, self.tol,
                                                     self.host_poll, ws=self.ws)
@@ -402,6 +413,10 @@ class TSVDMd:
             W, s2, shift, svd_status = ops.tsvdm_slice_svd_gram(
                 A_hat, self.block, self.max_sweeps, self.tol, self.host_poll, ws=self.ws,
                 jacobi=self.gram_jacobi)
+        elif self.svd == "precond":
+            # the orthogonalised vectors land in a new tensor, packed from below
+            A_hat, W, s2, svd_status = ops.tsvdm_slice_svd_precond(
+                A_hat, self.block, self.max_sweeps, self.tol, self.host_poll, ws=self.ws)
         else:
             W, s2, svd_status = ops.tsvdm_slice_svd(A_hat, self.block, self.max_sweeps, self.tol,
                                                     self.host_poll, ws=self.ws)

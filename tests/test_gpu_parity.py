@@ -151,6 +151,55 @@ def test_slice_svd_matches_oracle(ops, shape, dtype, block):
         assert np.allclose(vec_norm2, s2n[i], rtol=1e-12 if fp64 else 1e-5, atol=1e-300)
 
 
+# The FP64 rotation form preconditioned by the FP64 Gram form: the same
+# outputs (vectors, W, s2) to the rotation form's bounds, from a starting W
+# that is orthogonal to the first stage's FP64 tol.
+@pytest.mark.parametrize("shape", [(64, 48, 4), (48, 64, 4), (100, 37, 3), (37, 100, 3),
+                                   (300, 200, 2), (5, 1, 3), (1, 6, 2), (129, 129, 2),
+                                   (400, 720, 2), (720, 400, 1), (256, 384, 2), (384, 256, 2)])
+@pytest.mark.parametrize("block", [16, 32])
+def test_slice_svd_precond_matches_oracle(ops, shape, block):
+    m, p, n = shape
+    r = min(m, p)
+    g = np.random.default_rng(7 * m + p)
+    A = g.standard_normal(shape) * np.logspace(0, -4, p)[None, :, None]
+    Ad = to_dev(A, torch.float64)
+    X, W, s2, st = ops.tsvdm_slice_svd_precond(Ad, block=block)
+    torch.cuda.synchronize()
+    assert int(st.item()) == 0
+    assert torch.equal(Ad, to_dev(A, torch.float64))   # A_hat is only read
+    _U, S, _V = O.slice_svd(A)
+    s2n, Xn, Wn = to_np(s2), to_np(X), to_np(W)
+    for i in range(n):
+        smax = S[0, i]
+        assert np.max(np.abs(_sorted_sigma(s2n[i]) - S[:, i])) <= 1e-13 * smax
+        Wi = Wn[i].T
+        assert np.max(np.abs(Wi.T @ Wi - np.eye(r))) <= 1e-13 * max(1, r) ** 0.5
+        Xi = Xn[:, :, i]
+        rec = Wi @ Xi if m < p else Xi @ Wi.T
+        nb = -(-r // block)
+        rec_bound = 2 * 2.0 ** -53 * (2 * block) * np.sqrt(16 * max(nb, 1))
+        assert rel(rec, A[:, :, i]) <= rec_bound
+        vec_norm2 = np.sum(Xi * Xi, axis=1 if m < p else 0)
+        assert np.allclose(vec_norm2, s2n[i], rtol=1e-12, atol=1e-300)
+
+
+def test_tsvdm_precond_matches_oracle(ops):
+    """t-SVDM-II on the FP64 path with the preconditioned slice SVDs: ranks
+    bit-exact and the reconstruction within 1e-10 of the oracle's."""
+    from paper_2605_16058_amd.pipeline import tsvdm
+    g = np.random.default_rng(11)
+    A = g.standard_normal((96, 140, 12)) + 4.0 * np.einsum("a,b,c->abc", g.standard_normal(96),
+                                                           g.standard_normal(140), g.standard_normal(12))
+    M = synth.haar_orthogonal(12, g)
+    res = tsvdm(to_dev(A, torch.float64), M, mode="II", eps=0.2, precision="f64", svd="precond")
+    torch.cuda.synchronize()
+    ref = O.tsvdm_ii(A, M, 0.2)
+    assert int(res.svd_status.item()) == 0
+    assert np.array_equal(res.rho.cpu().numpy(), ref["rho"])
+    assert rel(to_np(res.A_rec), ref["A_rec"]) <= 1e-10
+
+
 # The FP32 path's Gram form: FP64 Gram, shifted Cholesky, Jacobi on the
 # factor's columns without accumulated rotations.  Its values carry the FP64
 # Gram's absolute error (about u64 sigma_max^2 / sigma) on top of the FP32
