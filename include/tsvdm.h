@@ -187,7 +187,11 @@ int tsvdm_transform_dct(const void* X, int x_dtype, void* Y, int y_dtype,
  *            convergence (graph-capturable).  Results are the same bits
  *            either way.
  * Rotation angles, the convergence test and s2 are computed in FP64 for
- * both dtypes. */
+ * both dtypes.  A block pair whose vectors measured every |cos| <= tol, and
+ * neither of whose blocks has rotated since, is skipped when it meets again
+ * (its Gram matrix would be the same bits, so it would not rotate); ws holds
+ * these records, (ceil(r / 16) rounded up to even)^2 int32 per slice, beside
+ * the per-slice control words. */
 int tsvdm_slice_svd_workspace_size(int64_t m, int64_t p, int64_t n, int dtype,
                                    size_t* bytes);
 int tsvdm_slice_svd(void* A_hat, int dtype, int64_t m, int64_t p, int64_t n,
@@ -525,7 +529,8 @@ int tsvdm_batch_plan_destroy(tsvdm_batch_plan plan);
  *   ms          summed event time over those launches (includes the small
  *               gaps between back-to-back launches),
  *   pairs_gram  block pairs that only formed their Gram matrix (converged),
- *   pairs_rot   block pairs that also rotated their vectors,
+ *   pairs_rot   block pairs that also rotated their vectors (pairs skipped
+ *               as unchanged since they last converged count in neither),
  *   pair_width  2b of the last call (the rows of each pair's Gram matrix;
  *               0 after a batch that mixed both widths),
  *   flops       algorithmic flops of those pairs over their w valid vectors:

@@ -206,7 +206,7 @@ int tsvdm_slice_svd_workspace_size(int64_t m, int64_t p, int64_t n, int dtype, s
     TSVDM_REQUIRE(bytes != nullptr, TSVDM_E_ARG, "bytes is NULL");
     TSVDM_TRY(check_shape(m, p, n));
     TSVDM_REQUIRE(io_dtype(dtype), TSVDM_E_UNSUPPORTED, "dtype must be F64 or F32");
-    *bytes = jacobi_workspace_bytes(n);
+    *bytes = jacobi_workspace_bytes(m < p ? m : p, n);
     return TSVDM_OK;
 }
 
@@ -221,7 +221,7 @@ int tsvdm_slice_svd(void* A_hat, int dtype, int64_t m, int64_t p, int64_t n, voi
     TSVDM_REQUIRE(max_sweeps >= 0 && max_sweeps <= 1000, TSVDM_E_ARG, "max_sweeps must be in [0, 1000]");
     TSVDM_REQUIRE(tol >= 0.0 && tol < 1.0 && std::isfinite(tol), TSVDM_E_ARG, "tol must lie in [0, 1)");
     TSVDM_REQUIRE(host_poll == 0 || host_poll == 1, TSVDM_E_ARG, "host_poll must be 0 or 1");
-    TSVDM_TRY(check_ws(ws, ws_bytes, jacobi_workspace_bytes(n)));
+    TSVDM_TRY(check_ws(ws, ws_bytes, jacobi_workspace_bytes(m < p ? m : p, n)));
     JacobiOpts o = jacobi_default_opts(m, p, dtype);
     if (block) o.block = 2 * block;
     if (max_sweeps) o.max_sweeps = max_sweeps;
@@ -375,7 +375,7 @@ int tsvdm_slice_svd_subset(void* A_hat, int dtype, int64_t m, int64_t p, int64_t
     TSVDM_REQUIRE(max_sweeps >= 0 && max_sweeps <= 1000, TSVDM_E_ARG, "max_sweeps must be in [0, 1000]");
     TSVDM_REQUIRE(tol >= 0.0 && tol < 1.0 && std::isfinite(tol), TSVDM_E_ARG, "tol must lie in [0, 1)");
     TSVDM_REQUIRE(host_poll == 0 || host_poll == 1, TSVDM_E_ARG, "host_poll must be 0 or 1");
-    TSVDM_TRY(check_ws(ws, ws_bytes, jacobi_workspace_bytes(n)));
+    TSVDM_TRY(check_ws(ws, ws_bytes, jacobi_workspace_bytes(m < p ? m : p, n)));
     JacobiOpts o = jacobi_default_opts(m, p, dtype);
     if (block) o.block = 2 * block;
     if (max_sweeps) o.max_sweeps = max_sweeps;

@@ -118,7 +118,7 @@ BwdLayout bwd_layout(void* ws, int64_t m, int64_t p, int64_t n, int dt) {
     L.Ahat = cv.carve<char>((size_t)(R * n) * es);
     L.W = cv.carve<char>((size_t)(g.r * g.r * n) * es);
     L.s2 = cv.carve<double>((size_t)(g.r * n));
-    L.jws = cv.carve<char>(jacobi_workspace_bytes(n));
+    L.jws = cv.carve<char>(jacobi_workspace_bytes(g.r, n));
     L.rho = cv.carve<int32_t>((size_t)n);
     L.offsets = cv.carve<int64_t>((size_t)n + 1);
     L.Upk = cv.carve<char>((size_t)(m * g.r * n) * es);

@@ -46,6 +46,7 @@ struct tsvdm_batch_plan_s {
     std::vector<int64_t> slice_base;
     int64_t n_rot = 0, n_jac = 0, n_gram = 0, n_lds = 0;
     std::vector<size_t> off_gG, off_gL, off_gsh, off_gfl, off_gperm;
+    std::vector<size_t> off_trk;     // Jacobi pair records (nbe^2 int32 per slice)
     std::vector<int2> gtasks;        // (Gram slice, lower-triangle tile)
     std::vector<int4> ftasks;        // (Gram slice, kept-column tile, position tile)
     std::vector<int> glists;         // Gram slices by Cholesky class, then in-LDS slices by class
@@ -181,6 +182,8 @@ int build_tables(tsvdm_batch_plan_s* P, char* ws) {
             d.vec_w = (g.r % VW == 0) ? 1 : 0;
             d.tensor = t;
             d.tol = tol;
+            d.track = form == FORM_GRAM_LDS ? nullptr
+                      : reinterpret_cast<int32_t*>(ws + P->off_trk[t]) + i * nbe * nbe;
             if (form != FORM_ROT) {
                 GramSlice gd;
                 gd.A = static_cast<const float*>(d.A);
@@ -479,6 +482,13 @@ int tsvdm_batch_plan_create(const tsvdm_batch_item* items, int32_t count, int in
             P->off_gsh.push_back(0);
             P->off_gfl.push_back(0);
             P->off_gperm.push_back(0);
+        }
+        if (form != FORM_GRAM_LDS) {
+            const int b = P->nb2[t] / 2;
+            const int64_t nb = (g.r + b - 1) / b, nbe = nb + (nb & 1);
+            P->off_trk.push_back(take((size_t)(nbe * nbe * it.n) * 4));
+        } else {
+            P->off_trk.push_back(0);
         }
         P->off_ahat.push_back(take((size_t)(it.m * it.p * it.n) * e));
         P->off_w.push_back(take((size_t)(g.r * g.r * it.n) * e));

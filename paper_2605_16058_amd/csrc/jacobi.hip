@@ -86,6 +86,15 @@ namespace {
 constexpr int PC_BINS = 64, PC_STRIDE = 16;
 constexpr int PC_WORDS = PC_BINS * PC_STRIDE;
 
+// Skipping pairs found orthogonal whose blocks have not changed since.
+// Per slice, trk[0, nbe) counts the rotations that changed each block, and
+// trk[nbe + 2 q], trk[nbe + 2 q + 1] hold the two blocks' counts when pair q
+// (blocks lo < hi, q = hi (hi - 1) / 2 + lo) last measured every cosine <=
+// tol (-1: never).  A pair whose counts still match has the same vectors,
+// so the same Gram matrix and the same outcome (no rotation): it returns at
+// once.  nbe^2 words per slice.
+__device__ __forceinline__ int track_pair(int lo, int hi) { return hi * (hi - 1) / 2 + lo; }
+
 // sum the bins of a copied counter block
 void pc_sum(const unsigned long long* bins, unsigned long long* out) {
     for (int k = 0; k < 4; ++k) out[k] = 0ull;
@@ -143,7 +152,8 @@ template <class T>
 __global__ void jacobi_init(T* __restrict__ W, int64_t r, int64_t n, JacobiCtl* __restrict__ ctl,
                             int* __restrict__ remaining, int max_sweeps,
                             unsigned long long* __restrict__ pair_counts,
-                            int32_t* __restrict__ status, const int32_t* __restrict__ run) {
+                            int32_t* __restrict__ status, const int32_t* __restrict__ run,
+                            int32_t* __restrict__ track, int nbe) {
     // W = I: workgroups take whole columns (one index division per column),
     // threads run down the column
     const int64_t cols = W ? r * n : 0;   // W == nullptr: no accumulated rotations
@@ -159,6 +169,10 @@ __global__ void jacobi_init(T* __restrict__ W, int64_t r, int64_t n, JacobiCtl* 
         c.maxcos_bits = 0ull; c.done = (run && !run[idx]) ? 1 : 0; c.sweeps = 0; c.nonfinite = 0; c.pad = 0;
         ctl[idx] = c;
     }
+    // pair records: every block unchanged (0), no pair found orthogonal yet
+    const int64_t tw = (int64_t)nbe * nbe;
+    for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < n * tw; idx += stride)
+        track[idx] = idx % tw < nbe ? 0 : -1;
     if (blockIdx.x == 0) {
         for (int i = threadIdx.x; i < max_sweeps; i += blockDim.x) remaining[i] = 0;
         for (int i = threadIdx.x; i < PC_WORDS; i += blockDim.x) pair_counts[i] = 0ull;
@@ -228,7 +242,8 @@ __device__ __forceinline__ void round_body(RoundShared<T, NB2>& sh, T* __restric
                                            T* __restrict__ Wb, const SliceGeom& g, int nbe, int rnd,
                                            int k, JacobiCtl* __restrict__ ctl_s, double tol,
                                            int vec_a, int vec_w,
-                                           unsigned long long* __restrict__ pair_counts) {
+                                           unsigned long long* __restrict__ pair_counts,
+                                           int32_t* __restrict__ trk) {
     typedef RoundCfg<T, NB2> C;
     typedef typename Acc<T>::type AccT;
     constexpr int B = NB2 / 2, VW = C::VW;
@@ -243,6 +258,11 @@ __device__ __forceinline__ void round_body(RoundShared<T, NB2>& sh, T* __restric
     const int I = circle_player(k, rnd, nbe);
     const int J = circle_player(nbe - 1 - k, rnd, nbe);
     const int64_t r = g.r, L = g.L;
+    // unchanged since this pair found its vectors orthogonal: nothing to do
+    const int blo = I < J ? I : J, bhi = I < J ? J : I;
+    int32_t* const trk_pair = trk + nbe + 2 * track_pair(blo, bhi);
+    const int32_t ver_lo = trk[blo], ver_hi = trk[bhi];
+    if (trk_pair[0] == ver_lo && trk_pair[1] == ver_hi) return;   // uniform across the block
 
     const int tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6;
@@ -532,7 +552,13 @@ __device__ __forceinline__ void round_body(RoundShared<T, NB2>& sh, T* __restric
             atomicAdd(&pc[3], by);
         }
     }
-    if (!rotate) return;  // uniform across the block
+    if (!rotate) {   // uniform across the block
+        if (!nonfinite && tid == 0) {
+            trk_pair[0] = ver_lo;
+            trk_pair[1] = ver_hi;
+        }
+        return;
+    }
     // FP64: the first vector tile of the update is in flight during the
     // inner sweep (FP32 has no registers to spare there)
     constexpr bool EARLY = sizeof(T) == 8;
@@ -867,6 +893,12 @@ __device__ __forceinline__ void round_body(RoundShared<T, NB2>& sh, T* __restric
                               NEXTW && Wb != nullptr);
     // W == nullptr: the caller needs no accumulated rotations (uniform branch)
     if (Wb) update(std::integral_constant<bool, false>(), Wb, r, 1, r, vec_w != 0, w_pre, false);
+    // both blocks changed (read by later launches only: each block belongs
+    // to one pair per round)
+    if (tid == 0) {
+        trk[blo] = ver_lo + 1;
+        trk[bhi] = ver_hi + 1;
+    }
 }
 
 // FP32 pairs of 64 vectors keep three workgroups per 160 KB compute unit.
@@ -880,14 +912,15 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(RoundCfg<T,
 void jacobi_round(T* __restrict__ A, T* __restrict__ W, SliceGeom g,
                                                     int nbe, int rnd, JacobiCtl* __restrict__ ctl,
                                                     double tol, int vec_a, int vec_w,
-                                                    unsigned long long* __restrict__ pair_counts) {
+                                                    unsigned long long* __restrict__ pair_counts,
+                                                    int32_t* __restrict__ track) {
     __shared__ RoundShared<T, NB2> sh;
     const int npairs = nbe / 2;
     const int64_t s = blockIdx.x / npairs;
     const int k = blockIdx.x % npairs;
     if (ctl[s].done) return;
     round_body<T, NB2, ROWS, INT>(sh, A + s * g.m * g.p, W ? W + s * g.r * g.r : nullptr, g, nbe, rnd, k,
-                                  ctl + s, tol, vec_a, vec_w, pair_counts);
+                                  ctl + s, tol, vec_a, vec_w, pair_counts, track + s * nbe * nbe);
 }
 
 // One step of the global round counter t for a batch of slices of any
@@ -906,10 +939,10 @@ void jacobi_round_batch(const BatchSlice* __restrict__ sl,
     const int rnd = t % (d.nbe - 1);
     if (d.g.rows)
         round_body<T, NB2, true>(sh, static_cast<T*>(d.A), static_cast<T*>(d.W), d.g, d.nbe, rnd,
-                                 tk.y, ctl + tk.x, d.tol, d.vec_a, d.vec_w, pair_counts);
+                                 tk.y, ctl + tk.x, d.tol, d.vec_a, d.vec_w, pair_counts, d.track);
     else
         round_body<T, NB2, false>(sh, static_cast<T*>(d.A), static_cast<T*>(d.W), d.g, d.nbe, rnd,
-                                  tk.y, ctl + tk.x, d.tol, d.vec_a, d.vec_w, pair_counts);
+                                  tk.y, ctl + tk.x, d.tol, d.vec_a, d.vec_w, pair_counts, d.track);
 }
 
 // end of a sweep for the slices whose tournament finished a sweep at step t;
@@ -945,6 +978,7 @@ __global__ void jacobi_init_batch(const BatchSlice* __restrict__ sl, JacobiCtl* 
     T* W = static_cast<T*>(d.W);
     if (W)
         for (int64_t e = threadIdx.x; e < r * r; e += blockDim.x) W[e] = (e % r == e / r) ? T(1) : T(0);
+    for (int e = threadIdx.x; e < d.nbe * d.nbe; e += blockDim.x) d.track[e] = e < d.nbe ? 0 : -1;
     if (threadIdx.x == 0) {
         JacobiCtl c;
         c.maxcos_bits = 0ull; c.done = 0; c.sweeps = 0; c.nonfinite = 0; c.pad = 0;
@@ -1073,26 +1107,29 @@ int* poll_slots() {
 template <class T, int NB2>
 int jacobi_impl(T* A, int64_t m, int64_t p, int64_t n, T* W, double* s2, int32_t* status,
                 const JacobiOpts& o, void* ws, hipStream_t st) {
+    static_assert(NB2 >= 32, "the workspace holds pair records for blocks of 16 vectors or more");
     const SliceGeom g = slice_geom(m, p);
     Carver cv(ws);
     JacobiCtl* ctl = cv.carve<JacobiCtl>((size_t)n);
     int* remaining = cv.carve<int>((size_t)o.max_sweeps);
     unsigned long long* pair_counts = cv.carve<unsigned long long>(PC_WORDS);
+    constexpr int B = NB2 / 2;
+    const int nb = (int)((g.r + B - 1) / B);
+    const int nbe = nb + (nb & 1);
+    int32_t* track = cv.carve<int32_t>((size_t)(n * nbe * nbe));
     const bool stats = stats_enabled();
     unsigned long long* const pcount = stats ? pair_counts : nullptr;   // counted only for statistics
     std::vector<hipEvent_t> evs;
 
     int64_t gblocks = g.r * n;   // one workgroup per column of W (grid-stride beyond the cap)
-    if (gblocks < (n + 255) / 256) gblocks = (n + 255) / 256;
+    if (gblocks < (n * nbe * nbe + 255) / 256) gblocks = (n * nbe * nbe + 255) / 256;
     if (gblocks > 65535 * 16) gblocks = 65535 * 16;
     if (gblocks < 1) gblocks = 1;
     jacobi_init<T><<<(unsigned)gblocks, 256, 0, st>>>(o.w_given ? nullptr : W, g.r, n, ctl, remaining,
-                                                      o.max_sweeps, pair_counts, status, o.run);
+                                                      o.max_sweeps, pair_counts, status, o.run,
+                                                      track, nbe);
     TSVDM_LAUNCH_CHECK();
 
-    constexpr int B = NB2 / 2;
-    const int nb = (int)((g.r + B - 1) / B);
-    const int nbe = nb + (nb & 1);
     const int npairs = nbe / 2;
     const int64_t blocks = n * npairs;
     constexpr int VW = 16 / (int)sizeof(T);
@@ -1128,16 +1165,16 @@ int jacobi_impl(T* A, int64_t m, int64_t p, int64_t n, T* W, double* s2, int32_t
         for (int rnd = 0; rnd < nbe - 1; ++rnd) {
             if (g.rows && interior)
                 jacobi_round<T, NB2, true, true><<<(unsigned)blocks, 256, 0, st>>>(
-                    A, W, g, nbe, rnd, ctl, o.tol, vec_a, vec_w, pcount);
+                    A, W, g, nbe, rnd, ctl, o.tol, vec_a, vec_w, pcount, track);
             else if (g.rows)
                 jacobi_round<T, NB2, true, false><<<(unsigned)blocks, 256, 0, st>>>(
-                    A, W, g, nbe, rnd, ctl, o.tol, vec_a, vec_w, pcount);
+                    A, W, g, nbe, rnd, ctl, o.tol, vec_a, vec_w, pcount, track);
             else if (interior)
                 jacobi_round<T, NB2, false, true><<<(unsigned)blocks, 256, 0, st>>>(
-                    A, W, g, nbe, rnd, ctl, o.tol, vec_a, vec_w, pcount);
+                    A, W, g, nbe, rnd, ctl, o.tol, vec_a, vec_w, pcount, track);
             else
                 jacobi_round<T, NB2, false, false><<<(unsigned)blocks, 256, 0, st>>>(
-                    A, W, g, nbe, rnd, ctl, o.tol, vec_a, vec_w, pcount);
+                    A, W, g, nbe, rnd, ctl, o.tol, vec_a, vec_w, pcount, track);
             TSVDM_LAUNCH_CHECK();
             ++launches;
         }
@@ -1311,11 +1348,14 @@ int run_jacobi_batch(int dt, const BatchSlice* sl, int64_t nslices, const int2* 
     return jacobi_batch_impl<float>(sl, nslices, tasks, group, max_steps, host_poll, ctl_ws, status, st);
 }
 
-size_t jacobi_workspace_bytes(int64_t n) {
+size_t jacobi_workspace_bytes(int64_t r, int64_t n) {
+    // the pair records are sized for the narrowest block (16 vectors)
+    const int64_t nb = (r + 15) / 16, nbe = nb + (nb & 1);
     Carver cv(nullptr);
     cv.carve<JacobiCtl>((size_t)n);
     cv.carve<int>(1024);
     cv.carve<unsigned long long>(PC_WORDS);
+    cv.carve<int32_t>((size_t)(n * nbe * nbe));
     return cv.total();
 }
 

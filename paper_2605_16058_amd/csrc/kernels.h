@@ -26,6 +26,7 @@ struct BatchSlice {       // one frontal slice for the batched Jacobi
     int vec_a, vec_w;
     int tensor;
     double tol;           // convergence threshold on |cos|
+    int32_t* track;       // nbe^2 pair records (changed blocks, orthogonal pairs)
 };
 
 struct PackSlice {        // one slice for batched packing and reconstruction
@@ -158,7 +159,7 @@ struct JacobiOpts {
     int w_given = 0;
 };
 
-size_t jacobi_workspace_bytes(int64_t n);
+size_t jacobi_workspace_bytes(int64_t r, int64_t n);   // r = min(m, p)
 // Gram form of the FP32 slice SVDs (precond.hip)
 size_t gram_svd_workspace_bytes(int64_t m, int64_t p, int64_t n);
 // jacobi: TSVDM_GRAM_AUTO / ROUNDS / LDS (checked by the caller)

@@ -968,7 +968,7 @@ size_t gram_svd_workspace_bytes(int64_t m, int64_t p, int64_t n) {
     Carver cv(nullptr);
     cv.carve<double>((size_t)(g.r * g.r * n));   // G
     cv.carve<double>((size_t)(g.r * g.r * n));   // L (FP64)
-    return cv.total() + jacobi_workspace_bytes(n);
+    return cv.total() + jacobi_workspace_bytes(g.r, n);
 }
 
 
@@ -1077,7 +1077,7 @@ size_t precond_svd_workspace_bytes(int64_t m, int64_t p, int64_t n, int dt) {
     cv.carve<int32_t>((size_t)n);          // full ranks
     cv.carve<int64_t>((size_t)n + 1);      // their offsets
     cv.carve<int32_t>(1);                  // first-stage status
-    return cv.total() + jacobi_workspace_bytes(n);
+    return cv.total() + jacobi_workspace_bytes(g.r, n);
 }
 
 namespace {
