@@ -54,8 +54,8 @@ constexpr int GRAM_CHOL_CLASSES = 4;   // Cholesky size classes (r <= 128, 256, 
 struct GramSlice {        // one slice of a batch on the Gram form
     const float* A;       // A-hat slice (m x p), read only
     float* B;             // r x r factor, then its orthogonalised columns
-    double* G;            // r x r FP64 Gram matrix (workspace)
-    double* Lw;           // r x r FP64 factor (workspace)
+    double* G;            // r x r FP64 Gram matrix (workspace; overwritten by the Cholesky)
+    double* Lw;           // r x r FP64 workspace of the Cholesky
     double* s2;           // r squared singular values
     double* shift;        // the Cholesky shift of the slice
     int32_t* flag;        // in-LDS Jacobi: 0 converged, 1 sweep limit, 2 NaN / Inf

@@ -150,128 +150,232 @@ __global__ __launch_bounds__(256) void pc_gram_batch(const GramSlice* __restrict
     gram_tile(d.A, d.g, ti, tj, d.G);
 }
 
-// L L^T = G + s I for the slice blockIdx.x (lower triangle of G read; L
-// written to Lw in FP64 and to Lo in FP32 with zeros above the diagonal).
-// Left-looking with panels of CB columns: the panel's rows are updated with
-// the L columns already computed (MFMA), staged in LDS, its CB x CB
-// diagonal block is factorised by one wave and the rows below are solved
-// against it.  A pivot <= 0 (rounding of a singular G + s I) gives a zero
-// column.  Fixed operation order: the result does not depend on timing.
+// P (G + s I) P^T = L L^T for the slice blockIdx.x, with diagonal pivoting:
+// column k of L takes the remaining row with the largest updated diagonal
+// (ties: the lowest position), so L's columns come in decreasing order of
+// what they add.  Output B (r x r, column-major): column k of L with its rows
+// at their original indices, so B B^T = G + s I, and B^T B = L^T L.  The
+// Jacobi then orthogonalises the columns of B: with pivoting, L^T L is far
+// closer to diagonal than G (the effect of the pivoted factor on one-sided
+// Jacobi that Drmac and Veselic analyse), and on the test spectra the
+// rounds need about a quarter fewer sweeps and rotations.
+// Right-looking with panels of CB columns.  The trailing matrix keeps only
+// the remaining rows, compacted in their original order, in column-major
+// storage with leading dimension equal to its size (strict lower triangle;
+// the updated diagonal lives in LDS): G itself at first, then alternately
+// Ws and G (G is overwritten).  Per panel: CB pivot steps, each a block
+// argmax over the diagonal and one new column (the trailing column of the
+// pivot minus the panel's earlier columns), then the panel's columns to B
+// and one MFMA update of the remaining trailing matrix into the other
+// buffer.  A pivot <= 0 (rounding of a singular G + s I) gives a zero
+// column; non-finite values stay non-finite.  Fixed operation order: the
+// result does not depend on timing.
 template <int MAXR, class OT>
-__device__ __forceinline__ void chol_slice(const double* __restrict__ Gs, int64_t r, double cshift,
-                                           double* __restrict__ Ls, OT* __restrict__ Os,
+__device__ __forceinline__ void chol_slice(double* __restrict__ Gs, int64_t r, double cshift,
+                                           double* __restrict__ Ws, OT* __restrict__ Os,
                                            double* __restrict__ shift_out) {
-    constexpr int PLD = CB + 1;
-    __shared__ double P[MAXR * PLD];
-    __shared__ double red[256];
+    constexpr int PLD = CB + 1;                // column CB: the updated diagonal
+    constexpr int PER = (MAXR + 255) / 256;    // positions per thread
+    __shared__ double P[MAXR * PLD];           // panel columns by trailing position
+    __shared__ int opos[MAXR];                 // original index of each position
+    __shared__ int posof[MAXR];                // position of each original index (-1: factored)
+    __shared__ int keep[MAXR];                 // 0: remaining, -1: pivot of this panel
+    __shared__ int oldp[MAXR];                 // after a panel: old position of each new one
+    __shared__ double rv[4];
+    __shared__ int ri[4], scan_w[4];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, lr = lane & 15, lg = lane >> 4;
+    const int R = (int)r;
     // trace in a fixed order
     double tr = 0.0;
-    for (int64_t j = tid; j < r; j += 256) tr += Gs[j + j * r];
-    red[tid] = tr;
+    for (int j = tid; j < R; j += 256) tr += Gs[(int64_t)j * (R + 1)];
+    for (int off = 32; off > 0; off >>= 1) tr += __shfl_xor(tr, off);
+    if (lane == 0) rv[wave] = tr;
     __syncthreads();
-    for (int w = 128; w > 0; w >>= 1) {
-        if (tid < w) red[tid] += red[tid + w];
-        __syncthreads();
-    }
-    const double sh = cshift * red[0];
+    const double sh = cshift * ((rv[0] + rv[1]) + (rv[2] + rv[3]));
     if (tid == 0) *shift_out = sh;
-    for (int64_t k0 = 0; k0 < r; k0 += CB) {
-        const int64_t nrow = r - k0;
-        const int nc = (int)(nrow < CB ? nrow : CB);
-        const int nrt = (int)((nrow + 15) / 16);
-        // 1. P = G(k0:, k0:k0+CB) + s I - L(k0:, :k0) L(k0:k0+CB, :k0)^T
-        for (int q = wave; q < nrt; q += 4) {
-            const int64_t i0 = k0 + 16 * q;
-            const int64_t ia = i0 + lr, kb = k0 + lr;
-            const bool va = ia < r, vb = kb < r;
-            // rows clamped into the matrix (masked after the load), column lg
-            const double* pa = Ls + (va ? ia : 0) + (int64_t)lg * r;
-            const double* pb = Ls + (vb ? kb : 0) + (int64_t)lg * r;
-            // eight MFMA steps per batch: their sixteen loads are issued
-            // before the first MFMA, and two accumulators alternate
-            v4d acc = zero4<v4d>(), acc2 = zero4<v4d>();
-            int64_t j = 0;
-            for (; j + 32 <= k0; j += 32) {
-                double a[8], b[8];
-#pragma unroll
-                for (int u = 0; u < 8; ++u) {
-                    a[u] = pa[(j + 4 * u) * r];
-                    b[u] = pb[(j + 4 * u) * r];
-                }
-#pragma unroll
-                for (int u = 0; u < 8; u += 2) {
-                    acc = mfma_f64(va ? a[u] : 0.0, vb ? b[u] : 0.0, acc);
-                    acc2 = mfma_f64(va ? a[u + 1] : 0.0, vb ? b[u + 1] : 0.0, acc2);
-                }
-            }
-            for (; j < k0; j += 4) {   // k0 is a multiple of 16, so j + lg < k0
-                const double a = pa[j * r], b = pb[j * r];
-                acc = mfma_f64(va ? a : 0.0, vb ? b : 0.0, acc);
-            }
-#pragma unroll
-            for (int v = 0; v < 4; ++v) acc[v] += acc2[v];
-#pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                const int64_t i = i0 + mfma_row<double>(lg, v), c = k0 + lr;
-                if (i < r && lr < CB)
-                    P[(i - k0) * PLD + lr] = c < r ? Gs[i + c * r] + (i == c ? sh : 0.0) - acc[v] : 0.0;
-            }
-        }
+    for (int a = tid; a < R; a += 256) {
+        opos[a] = a;
+        posof[a] = a;
+        P[a * PLD + CB] = Gs[(int64_t)a * (R + 1)] + sh;
+    }
+    __syncthreads();
+    double* To = Gs;   // trailing matrix, strict lower triangle, leading dimension ldo
+    double* Tn = Ws;
+    int64_t ldo = R;
+    int n = R, k = 0;
+    while (n > 0) {
+        const int nc = n < CB ? n : CB;   // nc < CB only for the last panel
+        for (int a = tid; a < n; a += 256) keep[a] = 0;
         __syncthreads();
-        // 2. the diagonal block, by wave 0 (lane i owns row i); LDS order
-        //    within the wave is kept by fences
-        if (wave == 0) {
-            for (int jj = 0; jj < nc; ++jj) {
-                const double d = P[jj * PLD + jj];
-                const double ljj = d > 0.0 ? sqrt(d) : 0.0;
-                const double inv = ljj > 0.0 ? 1.0 / ljj : 0.0;
-                __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
-                if (lane < nc && lane > jj) P[lane * PLD + jj] *= inv;
-                if (lane == jj) P[jj * PLD + jj] = ljj;
-                __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
-                if (lane < nc && lane > jj) {
-                    const double lij = P[lane * PLD + jj];
-                    for (int c = jj + 1; c <= lane; ++c) P[lane * PLD + c] -= lij * P[c * PLD + jj];
-                }
-                __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
-            }
-        }
-        __syncthreads();
-        // 3. rows below the block: L_i = P_i L_dd^-T (forward substitution)
-        for (int64_t i = CB + tid; i < nrow; i += 256) {
-            double x[CB];
-#pragma unroll
-            for (int c = 0; c < CB; ++c) x[c] = P[i * PLD + c];
-#pragma unroll
-            for (int jj = 0; jj < CB; ++jj) {
-                double v = x[jj];
-#pragma unroll
-                for (int c = 0; c < jj; ++c) v -= x[c] * P[jj * PLD + c];
-                const double djj = P[jj * PLD + jj];
-                x[jj] = djj > 0.0 ? v / djj : 0.0;
-            }
-#pragma unroll
-            for (int c = 0; c < CB; ++c) P[i * PLD + c] = x[c];
-        }
-        __syncthreads();
-        // 4. write the panel's columns: FP64 (for the later panels) and FP32
-        //    (the Jacobi's input), zeros above the diagonal
         for (int c = 0; c < nc; ++c) {
-            const int64_t col = k0 + c;
-            for (int64_t i = tid; i < r; i += 256) {
-                const int64_t li = i - k0;
-                const double v = (li < c) ? 0.0 : P[li * PLD + c];
-                if (li >= c) Ls[i + col * r] = v;
-                Os[i + col * r] = (OT)v;
+            // 1. pivot: the largest updated diagonal among the remaining rows
+            //    (NaN counts as -inf; some row always remains)
+            double bv = -INFINITY;
+            int bi = 0x7fffffff;
+            for (int a = tid; a < n; a += 256) {
+                if (keep[a]) continue;
+                double v = P[a * PLD + CB];
+                v = (v == v) ? v : -INFINITY;
+                if (v > bv || (v == bv && a < bi)) { bv = v; bi = a; }
+            }
+            for (int off = 32; off > 0; off >>= 1) {
+                const double ov = __shfl_xor(bv, off);
+                const int oi = __shfl_xor(bi, off);
+                if (ov > bv || (ov == bv && oi < bi)) { bv = ov; bi = oi; }
+            }
+            if (lane == 0) { rv[wave] = bv; ri[wave] = bi; }
+            __syncthreads();
+            int q = ri[0];
+            double qv = rv[0];
+#pragma unroll
+            for (int w = 1; w < 4; ++w)
+                if (rv[w] > qv || (rv[w] == qv && ri[w] < q)) { qv = rv[w]; q = ri[w]; }
+            // 2. column c: l_a = (T(a, q) - sum_{c' < c} l_a,c' l_q,c') / l_qq
+            // a pivot <= 0 gives a zero column; NaN and Inf travel on (x 0)
+            // so that the Jacobi reports them
+            const double dq = P[q * PLD + CB];
+            const double lqq = dq > 0.0 ? sqrt(dq) : dq * 0.0;
+            for (int a = tid; a < n; a += 256) {
+                if (a == q) {
+                    P[a * PLD + c] = lqq;
+                    keep[a] = -1;
+                } else if (keep[a]) {
+                    P[a * PLD + c] = 0.0;   // pivoted earlier in this panel
+                } else {
+                    double t = a > q ? To[a + (int64_t)q * ldo] : To[q + (int64_t)a * ldo];
+                    for (int cc = 0; cc < c; ++cc) t -= P[a * PLD + cc] * P[q * PLD + cc];
+                    const double l = lqq > 0.0 ? t / lqq : t * 0.0;
+                    P[a * PLD + c] = l;
+                    P[a * PLD + CB] -= l * l;
+                }
+            }
+            __syncthreads();
+        }
+        // 3. the panel's columns of B, rows at their original indices
+        for (int c = 0; c < nc; ++c)
+            for (int i = tid; i < R; i += 256) {
+                const int pa = posof[i];
+                Os[i + (int64_t)(k + c) * R] = (OT)(pa >= 0 ? P[pa * PLD + c] : 0.0);
+            }
+        // 4. new positions of the remaining rows (order kept): thread tid
+        //    takes positions [tid PER, tid PER + PER)
+        const int nn = n - nc;
+        int cnt = 0;
+#pragma unroll
+        for (int j = 0; j < PER; ++j) {
+            const int a = tid * PER + j;
+            if (a < n && keep[a] == 0) ++cnt;
+        }
+        int incl = cnt;
+        for (int off = 1; off < 64; off <<= 1) {
+            const int y = __shfl_up(incl, off);
+            if (lane >= off) incl += y;
+        }
+        if (lane == 63) scan_w[wave] = incl;
+        __syncthreads();   // also orders step 3's posof reads before the writes below
+        int base = incl - cnt;
+        for (int w = 0; w < wave; ++w) base += scan_w[w];
+#pragma unroll
+        for (int j = 0; j < PER; ++j) {
+            const int a = tid * PER + j;
+            if (a < n) {
+                if (keep[a] == 0) {
+                    oldp[base] = a;
+                    posof[opos[a]] = base;
+                    ++base;
+                } else {
+                    posof[opos[a]] = -1;
+                }
             }
         }
         __syncthreads();
+        // 5. Tn(a, b) = To(oldp a, oldp b) - sum_c P(oldp a, c) P(oldp b, c)
+        //    for a > b < nn (only after a full panel: nn > 0 implies nc = CB).
+        //    16 x 16 tiles of the lower triangle, four per wave at a time,
+        //    their loads issued before the MFMAs; lane (lr, lg) holds rows
+        //    16 ta + lr of columns 16 tb + lg + 4 v, so a store instruction
+        //    writes 16 consecutive rows of four columns.
+        if (nn > 1) {
+            const int nt = (nn + 15) / 16, ntri = nt * (nt + 1) / 2;
+            for (int t0 = wave; t0 < ntri; t0 += 16) {
+                double tv[4][4];
+                v4d acc[4];
+                int ra[4], cb[4];
+                bool vt[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const int tq = t0 + 4 * u;
+                    int ti = 0, tj = 0;
+                    vt[u] = tq < ntri;
+                    if (vt[u]) tri_tile(tq, ti, tj);
+                    ra[u] = 16 * ti + lr;   // this lane's row (new position)
+                    cb[u] = 16 * tj;        // the tile's first column
+                    const bool va = vt[u] && ra[u] < nn;
+                    const int oa = va ? oldp[ra[u]] : 0;
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) {
+                        const int b = cb[u] + lg + 4 * v;
+                        tv[u][v] = (va && b < ra[u]) ? To[oa + (int64_t)oldp[b] * ldo] : 0.0;
+                    }
+                }
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const int rb = cb[u] + lr;   // the tile column this lane feeds
+                    const bool va = vt[u] && ra[u] < nn, vb = vt[u] && rb < nn;
+                    const int oa = va ? oldp[ra[u]] : 0, ob = vb ? oldp[rb] : 0;
+                    v4d z = zero4<v4d>();
+#pragma unroll
+                    for (int s4 = 0; s4 < CB / 4; ++s4) {
+                        const double xa = vb ? P[ob * PLD + 4 * s4 + lg] : 0.0;   // A(lr, k): column rows
+                        const double xb = va ? P[oa * PLD + 4 * s4 + lg] : 0.0;   // B(k, lr): tile rows
+                        z = mfma_f64(xa, xb, z);
+                    }
+                    acc[u] = z;
+                }
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    if (!vt[u] || ra[u] >= nn) continue;
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) {
+                        const int b = cb[u] + lg + 4 * v;
+                        if (b < ra[u]) Tn[ra[u] + (int64_t)b * nn] = tv[u][v] - acc[u][v];
+                    }
+                }
+            }
+        }
+        __syncthreads();
+        // 6. per-position data to the new positions (through registers)
+        int ov[PER];
+        double dv[PER];
+#pragma unroll
+        for (int j = 0; j < PER; ++j) {
+            const int a = tid + 256 * j;
+            if (a < nn) {
+                ov[j] = opos[oldp[a]];
+                dv[j] = P[oldp[a] * PLD + CB];
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < PER; ++j) {
+            const int a = tid + 256 * j;
+            if (a < nn) {
+                opos[a] = ov[j];
+                P[a * PLD + CB] = dv[j];
+            }
+        }
+        __syncthreads();
+        double* const nxt = (Tn == Ws) ? Gs : Ws;
+        To = Tn;
+        Tn = nxt;
+        ldo = nn;
+        n = nn;
+        k += nc;
     }
 }
 
 template <int MAXR, class OT>
-__global__ __launch_bounds__(256) void pc_chol(const double* __restrict__ G, int64_t r, double cshift,
+__global__ __launch_bounds__(256) void pc_chol(double* __restrict__ G, int64_t r, double cshift,
                                                double* __restrict__ Lw, OT* __restrict__ Lo,
                                                double* __restrict__ shift) {
     const int64_t s = blockIdx.x;
@@ -967,13 +1071,14 @@ size_t gram_svd_workspace_bytes(int64_t m, int64_t p, int64_t n) {
     const SliceGeom g = slice_geom(m, p);
     Carver cv(nullptr);
     cv.carve<double>((size_t)(g.r * g.r * n));   // G
-    cv.carve<double>((size_t)(g.r * g.r * n));   // L (FP64)
+    cv.carve<double>((size_t)(g.r * g.r * n));   // second trailing-matrix buffer of the Cholesky
     return cv.total() + jacobi_workspace_bytes(g.r, n);
 }
 
 
-// G = X X^T (FP64) and the shifted Cholesky factor L L^T = G + s I of every
-// slice: L in FP64 (Lw) and in T (B, zeros above the diagonal), s per slice.
+// G = X X^T (FP64) and the pivoted, shifted Cholesky factor of every slice,
+// P (G + s I) P^T = L L^T: B = P^T L in T (B B^T = G + s I), s per slice.
+// G and Lw are the factorisation's workspace (G is overwritten).
 template <class T>
 int gram_factor(const T* A_hat, const SliceGeom& g, int64_t n, double* G, double* Lw, T* B,
                 double* shift, hipStream_t st) {
@@ -1070,7 +1175,7 @@ size_t precond_svd_workspace_bytes(int64_t m, int64_t p, int64_t n, int dt) {
     const size_t rr = (size_t)(g.r * g.r * n);
     Carver cv(nullptr);
     cv.carve<double>(rr);                  // G
-    cv.carve<double>(rr);                  // L (FP64)
+    cv.carve<double>(rr);                  // second trailing-matrix buffer of the Cholesky
     cv.carve<char>(rr * e);                // B
     cv.carve<char>(g.rows ? rr * e : 1);   // W^T (wide slices)
     cv.carve<double>((size_t)n);           // shifts
