@@ -26,8 +26,17 @@ from dataclasses import dataclass, field
 
 import torch
 
-TTM_TILES = (1, 2, 3)       # 64x64, 128x32, 256x16 (rows x slices)
+# transform tiles (rows x slices): 64x64, 128x32, 256x16 (16 slices per
+# wave), 128x64, 256x32 (32), 128x128, 256x64 (64); the FP64 form has no
+# registers for waves of more than 32 slices
+TTM_TILES = (1, 2, 3, 4, 5, 6, 7)
+TTM_TILES_F64 = (1, 2, 3, 4)
 JACOBI_BLOCKS = (16, 32)
+
+
+def ttm_tiles(precision: str) -> tuple:
+    """Transform tile candidates for one precision."""
+    return TTM_TILES_F64 if precision == "f64" else TTM_TILES
 
 
 def _pow2_ceil(x: int) -> int:
@@ -49,9 +58,16 @@ def default_block(m: int, p: int) -> int:
     return 32 if min(m, p) >= 256 else 16
 
 
-def default_tile(n: int) -> int:
-    """The library's choice for tile = 0."""
-    return 3 if n <= 16 else (2 if n <= 32 else 1)
+def default_tile(n: int, precision: str = "f64") -> int:
+    """The library's choice for tile = 0: by n, and for the FP32-operand
+    precisions wider waves once n > 32."""
+    if n <= 16:
+        return 3
+    if n <= 32:
+        return 2
+    if precision == "f64":
+        return 1
+    return 4 if n <= 64 else 6
 
 
 class Cache:
@@ -162,10 +178,10 @@ def tune_tsvdm(A, M, mode="II", k=None, eps=None, precision="f32", cache=None, r
         Md = ops.device_matrix(M, A.device)
         Y = ops.colmajor_empty(m, p, n, dtype, A.device)
         t = {}
-        for s in TTM_TILES:
+        for s in ttm_tiles(precision):
             t[s] = time_ms(lambda: ops.tsvdm_transform(A, Md, compute=compute, out_dtype=dtype,
                                                        out=Y, tile=s), reps=max(reps, 5))
-        tile = pick(t, default_tile(n), margin)
+        tile = pick(t, default_tile(n, precision), margin)
         c.put("ttm", precision, tb, tile, t)
         times["ttm"] = t
     return Choice(block, tile, times)
@@ -212,7 +228,7 @@ def tune_batch(tensors, Ms, modes, ks=None, epss=None, precision="f32", cache=No
     for b in todo_j:
         jchoice[b] = plan_block
     for b in todo_t:
-        tchoice[b] = default_tile(int(b[1:]))
+        tchoice[b] = default_tile(int(b[1:]), precision)
     report = {}
 
     def run_time():
@@ -240,10 +256,10 @@ def tune_batch(tensors, Ms, modes, ks=None, epss=None, precision="f32", cache=No
         if not any(tb[i] == b for i in idx):
             continue
         t = {}
-        for cand in TTM_TILES:
+        for cand in ttm_tiles(precision):
             tchoice[b] = cand
             t[cand] = run_time()
-        tchoice[b] = pick(t, default_tile(int(b[1:])), margin)
+        tchoice[b] = pick(t, default_tile(int(b[1:]), precision), margin)
         c.put("ttm", precision, b, tchoice[b], t)
         report[b] = t
     blocks = [jchoice.get(jb[i]) or plan_block for i in range(cnt)]

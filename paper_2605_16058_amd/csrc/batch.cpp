@@ -36,7 +36,7 @@ struct tsvdm_batch_plan_s {
     // sorted by tile shape and Jacobi tasks by pair width
     std::vector<int4> ttm_tasks, lr_tasks;
     std::vector<int2> jtasks;
-    int64_t ttm_group[3] = {0, 0, 0}, back_group[3] = {0, 0, 0}, jgroup[2] = {0, 0};
+    int64_t ttm_group[TTM_SHAPES] = {}, back_group[TTM_SHAPES] = {}, jgroup[2] = {0, 0};
     // slice SVD form per item: FORM_ROT (rotation form), FORM_GRAM_ROUNDS
     // (Gram form, Jacobi on the factor in the block rounds), FORM_GRAM_LDS
     // (Gram form, in-LDS Jacobi).  Slices are numbered by form: rotation
@@ -99,8 +99,8 @@ int validate_item(const tsvdm_batch_item& it, int idx) {
         set_error(where + "block must be 0, 16 or 32");
         return TSVDM_E_ARG;
     }
-    if (it.ttm_tile < 0 || it.ttm_tile > 3) {
-        set_error(where + "ttm_tile must be 0, 1, 2 or 3");
+    if (it.ttm_tile < 0 || it.ttm_tile > TTM_SHAPES) {
+        set_error(where + "ttm_tile must be in [0, 7]");
         return TSVDM_E_ARG;
     }
     if (it.mode == 1) {
@@ -150,7 +150,7 @@ int build_tables(tsvdm_batch_plan_s* P, char* ws) {
     std::vector<GramSlice> gsl((size_t)P->n_gram);
     std::vector<SelTensor> sel(cnt);
     std::vector<ErrJob> err;
-    std::vector<int4> back_by[3];
+    std::vector<int4> back_by[TTM_SHAPES];
     const size_t e = esz(P->dt);
     const int VW = 16 / (int)e;
     for (int t = 0; t < cnt; ++t) {
@@ -248,7 +248,7 @@ int build_tables(tsvdm_batch_plan_s* P, char* ws) {
             back.push_back(bk);
             int64_t n_rt;
             int n_ct;
-            const int shp = ttm_resolve_tile(it.ttm_tile, it.n);
+            const int shp = ttm_resolve_tile(it.ttm_tile, it.n, P->ttm_compute);
             ttm_tile_counts(shp, it.m * it.p, it.n, &n_rt, &n_ct);
             for (int64_t rt = 0; rt < n_rt; ++rt)
                 for (int ct = 0; ct < n_ct; ++ct) back_by[shp - 1].push_back(int4{bi, (int)rt, ct, 0});
@@ -264,7 +264,7 @@ int build_tables(tsvdm_batch_plan_s* P, char* ws) {
         }
     }
     std::vector<int4> back_tasks;
-    for (int q = 0; q < 3; ++q) {
+    for (int q = 0; q < TTM_SHAPES; ++q) {
         P->back_group[q] = (int64_t)back_by[q].size();
         back_tasks.insert(back_tasks.end(), back_by[q].begin(), back_by[q].end());
     }
@@ -464,7 +464,7 @@ int tsvdm_batch_plan_create(const tsvdm_batch_item* items, int32_t count, int in
         }
     std::vector<int> ccls[GRAM_CHOL_CLASSES], lcls[GRAM_LDS_CLASSES];
     int max_rounds = 1;
-    std::vector<int4> ttm_by[3];
+    std::vector<int4> ttm_by[TTM_SHAPES];
     std::vector<int2> jt_by[2];
     for (int t = 0; t < count; ++t) {
         const tsvdm_batch_item& it = P->items[t];
@@ -517,7 +517,7 @@ int tsvdm_batch_plan_create(const tsvdm_batch_item* items, int32_t count, int in
         // task tables
         int64_t n_rt;
         int n_ct;
-        const int shp = ttm_resolve_tile(it.ttm_tile, it.n);
+        const int shp = ttm_resolve_tile(it.ttm_tile, it.n, P->ttm_compute);
         ttm_tile_counts(shp, it.m * it.p, it.n, &n_rt, &n_ct);
         for (int64_t rt = 0; rt < n_rt; ++rt)
             for (int ct = 0; ct < n_ct; ++ct) ttm_by[shp - 1].push_back(int4{t, (int)rt, ct, 0});
@@ -556,7 +556,7 @@ int tsvdm_batch_plan_create(const tsvdm_batch_item* items, int32_t count, int in
         P->lds_cnt[c] = (int64_t)lcls[c].size();
         P->glists.insert(P->glists.end(), lcls[c].begin(), lcls[c].end());
     }
-    for (int q = 0; q < 3; ++q) {
+    for (int q = 0; q < TTM_SHAPES; ++q) {
         P->ttm_group[q] = (int64_t)ttm_by[q].size();
         P->ttm_tasks.insert(P->ttm_tasks.end(), ttm_by[q].begin(), ttm_by[q].end());
     }
@@ -568,7 +568,7 @@ int tsvdm_batch_plan_create(const tsvdm_batch_item* items, int32_t count, int in
         if (!it.A_rec) continue;
         int64_t n_rt;
         int n_ct;
-        ttm_tile_counts(ttm_resolve_tile(it.ttm_tile, it.n), it.m * it.p, it.n, &n_rt, &n_ct);
+        ttm_tile_counts(ttm_resolve_tile(it.ttm_tile, it.n, P->ttm_compute), it.m * it.p, it.n, &n_rt, &n_ct);
         P->n_back += 1;
         P->n_back_tasks += n_rt * n_ct;
         P->n_err += it.err ? 1 : 0;

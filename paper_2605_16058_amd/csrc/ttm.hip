@@ -8,9 +8,10 @@
 // R = n_1 ... n_{k-1} rows (Section 3.1, middle-mode TTM), blockIdx.y
 // selecting the block.  Each workgroup computes a TR-row x TI-slice
 // tile of Y in the transposed orientation Y^T = op(M) X^T so that the MFMA
-// output lanes run along tensor rows and the stores coalesce.  Three tile
-// shapes share one body (64x64, 128x32, 256x16: every wave owns 16 slices
-// and four 16-row MFMA tiles); narrow shapes waste less work when n is small.
+// output lanes run along tensor rows and the stores coalesce.  Seven tile
+// shapes share one body (every wave owns four 16-row MFMA tiles and 16, 32
+// or 64 slices): narrow shapes waste less work when n is small, and wider
+// waves read each LDS operand value once for more MFMAs.
 #include "common.h"
 #include "kernels.h"
 
@@ -18,16 +19,36 @@ namespace tsvdm {
 
 namespace {
 
-// tile shape codes of the C ABI: 1 = 64x64, 2 = 128x32, 3 = 256x16
+// tile shape codes of the C ABI (output slices x rows per workgroup, slices
+// per wave; every wave owns 64 rows): 1 = 64x64, 2 = 32x128, 3 = 16x256 (16
+// slices per wave), 4 = 64x128, 5 = 32x256 (32), 6 = 128x128, 7 = 64x256
+// (64).  A wider wave reads each LDS operand value once for more MFMAs.
+__host__ __device__ constexpr int shape_ti(int s) {
+    return s == 1 ? 64 : s == 2 ? 32 : s == 3 ? 16 : s == 4 ? 64 : s == 5 ? 32 : s == 6 ? 128 : 64;
+}
+__host__ __device__ constexpr int shape_tr(int s) {
+    return s == 1 ? 64 : s == 2 ? 128 : s == 3 ? 256 : s == 4 ? 128 : s == 5 ? 256 : s == 6 ? 128 : 256;
+}
+__host__ __device__ constexpr int shape_ws(int s) { return s <= 3 ? 16 : s <= 5 ? 32 : 64; }
 template <int SHAPE>
 struct TileShape {
-    static constexpr int TI = 64 >> (SHAPE - 1);  // output slices per workgroup
-    static constexpr int TR = 64 << (SHAPE - 1);  // rows of the unfolding per workgroup
-    static constexpr int WI = TI / 16;            // waves along slices
-    static constexpr int WROWS = TR / (4 / WI);   // rows per wave (always 64)
+    static constexpr int TI = shape_ti(SHAPE);        // output slices per workgroup
+    static constexpr int TR = shape_tr(SHAPE);        // rows of the unfolding per workgroup
+    static constexpr int WS = shape_ws(SHAPE);        // slices per wave
+    static constexpr int NS = WS / 16;                // 16-slice MFMA tiles per wave
+    static constexpr int WI = TI / WS;                // waves along slices
+    static constexpr int WROWS = TR / (4 / WI);       // rows per wave (always 64)
+    static_assert(WROWS == 64 && WI * (TR / WROWS) == 4, "four waves of 64 rows");
 };
 
-int default_tile(int64_t n) { return n <= 16 ? 3 : (n <= 32 ? 2 : 1); }
+// tile = 0: by n; FP32-operand forms take the wide waves once n > 32 (the
+// FP64 form has no registers for them)
+int default_tile(int64_t n, int compute) {
+    if (n <= 16) return 3;
+    if (n <= 32) return 2;
+    if (compute == TSVDM_F64) return 1;
+    return n <= 64 ? 4 : 6;
+}
 
 // Tt[i*n + l] = scale * op(M)[i, l], stored in the LDS staging type.
 template <class ST>
@@ -65,7 +86,7 @@ __device__ __forceinline__ void ttm_tile(TtmShared<CT, KIND, SHAPE>& sh, const X
                                          const CT* __restrict__ Tt, int64_t rt, int ct) {
     typedef TtmShared<CT, KIND, SHAPE> S;
     constexpr int KC = S::KC, TR = S::TR, TI = S::TI;
-    constexpr int WI = TileShape<SHAPE>::WI;
+    constexpr int WI = TileShape<SHAPE>::WI, WS = TileShape<SHAPE>::WS, NS = TileShape<SHAPE>::NS;
     constexpr int VW = VEC ? 16 / (int)sizeof(XT) : 1;     // X values per load
     constexpr int NXE = KC * TR / (256 * VW);              // X loads per thread and chunk
     constexpr int NTE = TI * KC / 256;                     // op(M) values per thread and chunk
@@ -80,9 +101,11 @@ __device__ __forceinline__ void ttm_tile(TtmShared<CT, KIND, SHAPE>& sh, const X
     const int wi = wave % WI;                                // slice group of this wave
     const int wr0 = (wave / WI) * TileShape<SHAPE>::WROWS;  // first tile row of this wave
 
-    AccT acc[4];
+    AccT acc[NS][4];
 #pragma unroll
-    for (int t = 0; t < 4; ++t) acc[t] = zero4<AccT>();
+    for (int u = 0; u < NS; ++u)
+#pragma unroll
+        for (int t = 0; t < 4; ++t) acc[u][t] = zero4<AccT>();
 
     // This thread's staging elements: X load k covers rows r .. r + VW - 1
     // of column l, consecutive threads along the rows; op(M) value k is
@@ -165,7 +188,7 @@ __device__ __forceinline__ void ttm_tile(TtmShared<CT, KIND, SHAPE>& sh, const X
         }
     };
 
-    const int irow = wi * 16 + lr;  // output slice (A-operand row)
+    const int irow = wi * WS + lr;  // output slice (A-operand row) of the wave's first slice tile
     const int nchunk = (n + KC - 1) / KC;
     load(0);
     store(0);
@@ -178,10 +201,11 @@ __device__ __forceinline__ void ttm_tile(TtmShared<CT, KIND, SHAPE>& sh, const X
         if constexpr (KIND == 0) {
             // every operand of the chunk read before the first MFMA, so that
             // the LDS latency is paid once per chunk
-            CT af[KC / 4], bf[KC / 4][4];
+            CT af[KC / 4][NS], bf[KC / 4][4];
 #pragma unroll
             for (int kq = 0; kq < KC / 4; ++kq) {
-                af[kq] = Ts[irow][4 * kq + lg];
+#pragma unroll
+                for (int u = 0; u < NS; ++u) af[kq][u] = Ts[irow + 16 * u][4 * kq + lg];
 #pragma unroll
                 for (int t = 0; t < 4; ++t) bf[kq][t] = Xs[4 * kq + lg][wr0 + t * 16 + lr];
             }
@@ -189,17 +213,21 @@ __device__ __forceinline__ void ttm_tile(TtmShared<CT, KIND, SHAPE>& sh, const X
 #pragma unroll
             for (int kq = 0; kq < KC / 4; ++kq) {
 #pragma unroll
-                for (int t = 0; t < 4; ++t) acc[t] = mfma(af[kq], bf[kq][t], acc[t]);
+                for (int u = 0; u < NS; ++u)
+#pragma unroll
+                    for (int t = 0; t < 4; ++t) acc[u][t] = mfma(af[kq][u], bf[kq][t], acc[u][t]);
             }
         } else {
-            v8bf ahi, alo;
+            v8bf ahi[NS], alo[NS];
 #pragma unroll
-            for (int e = 0; e < 8; ++e) {
-                float x = Ts[irow][lg * 8 + e];
-                __bf16 h = to_bf16(x);
-                ahi[e] = h;
-                alo[e] = to_bf16(x - static_cast<float>(h));
-            }
+            for (int u = 0; u < NS; ++u)
+#pragma unroll
+                for (int e = 0; e < 8; ++e) {
+                    float x = Ts[irow + 16 * u][lg * 8 + e];
+                    __bf16 h = to_bf16(x);
+                    ahi[u][e] = h;
+                    alo[u][e] = to_bf16(x - static_cast<float>(h));
+                }
 #pragma unroll
             for (int t = 0; t < 4; ++t) {
                 v8bf bhi, blo;
@@ -210,10 +238,13 @@ __device__ __forceinline__ void ttm_tile(TtmShared<CT, KIND, SHAPE>& sh, const X
                     bhi[e] = h;
                     blo[e] = to_bf16(x - static_cast<float>(h));
                 }
-                acc[t] = mfma_bf16(ahi, bhi, acc[t]);
-                if constexpr (KIND == 2) {
-                    acc[t] = mfma_bf16(ahi, blo, acc[t]);
-                    acc[t] = mfma_bf16(alo, bhi, acc[t]);
+#pragma unroll
+                for (int u = 0; u < NS; ++u) {
+                    acc[u][t] = mfma_bf16(ahi[u], bhi, acc[u][t]);
+                    if constexpr (KIND == 2) {
+                        acc[u][t] = mfma_bf16(ahi[u], blo, acc[u][t]);
+                        acc[u][t] = mfma_bf16(alo[u], bhi, acc[u][t]);
+                    }
                 }
             }
         }
@@ -221,16 +252,18 @@ __device__ __forceinline__ void ttm_tile(TtmShared<CT, KIND, SHAPE>& sh, const X
         __syncthreads();
     }
 
-    // D lane layout: slice i0 + 16*wi + mfma row, row row0 + wr0 + 16*t + lr
+    // D lane layout: slice i0 + WS*wi + 16*u + mfma row, row row0 + wr0 + 16*t + lr
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
         int64_t row = row0 + wr0 + t * 16 + lr;
         if (row >= R) continue;
 #pragma unroll
-        for (int v = 0; v < 4; ++v) {
-            int i = i0 + wi * 16 + mfma_row<CT>(lg, v);
-            if (i < n) stg_as(Y, row + (int64_t)i * R, ydt, (double)acc[t][v]);
-        }
+        for (int u = 0; u < NS; ++u)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                int i = i0 + wi * WS + 16 * u + mfma_row<CT>(lg, v);
+                if (i < n) stg_as(Y, row + (int64_t)i * R, ydt, (double)acc[u][t][v]);
+            }
     }
 }
 
@@ -307,10 +340,15 @@ int launch_tiles(const void* X, void* Y, int ydt, int64_t R, int n, int64_t P,
 template <class CT, class XT, int KIND>
 int launch_shape(const void* X, void* Y, int ydt, int64_t R, int n, int64_t P, const CT* Tt,
                  int tile, hipStream_t st) {
-    switch (tile ? tile : default_tile(n)) {
+    const int compute = KIND == 1 ? TSVDM_BF16 : KIND == 2 ? TSVDM_BF16X3 : sizeof(CT) == 8 ? TSVDM_F64 : TSVDM_F32;
+    switch (tile ? tile : default_tile(n, compute)) {
         case 1: return launch_tiles<CT, XT, KIND, 1>(X, Y, ydt, R, n, P, Tt, st);
         case 2: return launch_tiles<CT, XT, KIND, 2>(X, Y, ydt, R, n, P, Tt, st);
         case 3: return launch_tiles<CT, XT, KIND, 3>(X, Y, ydt, R, n, P, Tt, st);
+        case 4: return launch_tiles<CT, XT, KIND, 4>(X, Y, ydt, R, n, P, Tt, st);
+        case 5: return launch_tiles<CT, XT, KIND, 5>(X, Y, ydt, R, n, P, Tt, st);
+        case 6: return launch_tiles<CT, XT, KIND, 6>(X, Y, ydt, R, n, P, Tt, st);
+        case 7: return launch_tiles<CT, XT, KIND, 7>(X, Y, ydt, R, n, P, Tt, st);
         default: set_error("unknown transform tile shape"); return TSVDM_E_ARG;
     }
 }
@@ -331,12 +369,19 @@ template <class CT, class XT, int KIND>
 int launch_batch_x(const TtmProblem* probs, const int4* tasks, const int64_t* group, int ydt,
                    hipStream_t st) {
     int64_t o = 0;
-    for (int sh = 1; sh <= 3; ++sh) {
+    for (int sh = 1; sh <= TTM_SHAPES; ++sh) {
         const int64_t cnt = group[sh - 1];
         if (cnt > 0) {
-            if (sh == 1) ttm_kernel_batch<CT, XT, KIND, 1><<<(unsigned)cnt, 256, 0, st>>>(probs, tasks + o, ydt);
-            else if (sh == 2) ttm_kernel_batch<CT, XT, KIND, 2><<<(unsigned)cnt, 256, 0, st>>>(probs, tasks + o, ydt);
-            else ttm_kernel_batch<CT, XT, KIND, 3><<<(unsigned)cnt, 256, 0, st>>>(probs, tasks + o, ydt);
+            const unsigned g = (unsigned)cnt;
+            switch (sh) {
+                case 1: ttm_kernel_batch<CT, XT, KIND, 1><<<g, 256, 0, st>>>(probs, tasks + o, ydt); break;
+                case 2: ttm_kernel_batch<CT, XT, KIND, 2><<<g, 256, 0, st>>>(probs, tasks + o, ydt); break;
+                case 3: ttm_kernel_batch<CT, XT, KIND, 3><<<g, 256, 0, st>>>(probs, tasks + o, ydt); break;
+                case 4: ttm_kernel_batch<CT, XT, KIND, 4><<<g, 256, 0, st>>>(probs, tasks + o, ydt); break;
+                case 5: ttm_kernel_batch<CT, XT, KIND, 5><<<g, 256, 0, st>>>(probs, tasks + o, ydt); break;
+                case 6: ttm_kernel_batch<CT, XT, KIND, 6><<<g, 256, 0, st>>>(probs, tasks + o, ydt); break;
+                default: ttm_kernel_batch<CT, XT, KIND, 7><<<g, 256, 0, st>>>(probs, tasks + o, ydt); break;
+            }
             TSVDM_LAUNCH_CHECK();
         }
         o += cnt;
@@ -379,19 +424,19 @@ int run_ttm(const void* X, int xdt, void* Y, int ydt, int64_t m, int64_t p, int6
     return run_ttm_mode(X, xdt, Y, ydt, m * p, n, 1, M, transpose, scale, compute, tile, ws, st);
 }
 
-int ttm_resolve_tile(int tile, int64_t n) { return tile ? tile : default_tile(n); }
+int ttm_resolve_tile(int tile, int64_t n, int compute) { return tile ? tile : default_tile(n, compute); }
 
-void ttm_tile_counts(int tile, int64_t R, int64_t n, int64_t* n_rt, int* n_ct) {
-    const int sh = ttm_resolve_tile(tile, n);
-    const int ti = 64 >> (sh - 1), tr = 64 << (sh - 1);
+void ttm_tile_counts(int shape, int64_t R, int64_t n, int64_t* n_rt, int* n_ct) {
+    const int ti = shape_ti(shape), tr = shape_tr(shape);
     *n_rt = (R + tr - 1) / tr;
     *n_ct = (int)((n + ti - 1) / ti);
 }
 
 int run_ttm_batch(const TtmProblem* probs, int nprob, const int4* tasks, const int64_t* group,
                   int xdt, int ydt, int compute, int transpose, hipStream_t st) {
-    TSVDM_REQUIRE(group[0] + group[1] + group[2] < ((int64_t)1 << 31), TSVDM_E_SHAPE,
-                  "too many transform tiles");
+    int64_t total = 0;
+    for (int s = 0; s < TTM_SHAPES; ++s) total += group[s];
+    TSVDM_REQUIRE(total < ((int64_t)1 << 31), TSVDM_E_SHAPE, "too many transform tiles");
     switch (compute) {
         case TSVDM_F64:
             ttm_prep_batch<double><<<nprob, 256, 0, st>>>(probs, nprob, transpose);
