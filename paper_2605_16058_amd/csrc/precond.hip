@@ -620,15 +620,15 @@ __global__ __launch_bounds__(256) void pc_unshift_batch(const GramSlice* __restr
 }
 
 // Preconditioned rotation form: W (r x r per slice) = the columns of B
-// scaled to unit norm, and Ut = W^T when asked (wide slices); a column of
-// zero or non-finite norm (a failed factorisation) sets *flag to
-// TSVDM_E_NONFINITE unless it already holds a condition.
-template <class T>
-__global__ __launch_bounds__(256) void pc_normalize(const T* __restrict__ B, int64_t r, T* __restrict__ W,
-                                                    T* __restrict__ Ut, int32_t* __restrict__ flag) {
+// scaled to unit norm; a column of zero or non-finite norm (a failed
+// factorisation) sets *flag to TSVDM_E_NONFINITE unless it already holds a
+// condition.
+template <class BT, class T>
+__global__ __launch_bounds__(256) void pc_normalize(const BT* __restrict__ B, int64_t r, T* __restrict__ W,
+                                                    int32_t* __restrict__ flag) {
     __shared__ double red[256];
     const int64_t j = blockIdx.x, s = blockIdx.y;
-    const T* b = B + s * r * r + j * r;
+    const BT* b = B + s * r * r + j * r;
     double acc = 0.0;
     for (int64_t i = threadIdx.x; i < r; i += 256) {
         const double x = (double)b[i];
@@ -645,11 +645,32 @@ __global__ __launch_bounds__(256) void pc_normalize(const T* __restrict__ B, int
     if (!ok && threadIdx.x == 0) atomicCAS(flag, (int32_t)TSVDM_OK, (int32_t)TSVDM_E_NONFINITE);
     const double inv = ok ? 1.0 / sqrt(n2) : 0.0;
     T* w = W + s * r * r + j * r;
-    for (int64_t i = threadIdx.x; i < r; i += 256) {
-        const T v = (T)((double)b[i] * inv);
-        w[i] = v;
-        if (Ut) Ut[s * r * r + i * r + j] = v;
-    }
+    for (int64_t i = threadIdx.x; i < r; i += 256) w[i] = (T)((double)b[i] * inv);
+}
+
+// In place on C = W^T W (lower triangle read): S = (3 I - C) / 2 in both
+// triangles.  One Newton-Schulz step W <- W S maps W^T W = I + E to
+// I - (3/4) E^2 + O(E^3): W converges quadratically to the orthogonal polar
+// factor of the starting W.  Thread (i >= j) reads only its own element.
+__global__ void pc_ns_coef(double* __restrict__ C, int64_t r, int64_t n) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= r * r * n) return;
+    const int64_t s = e / (r * r), rem = e - s * r * r, j = rem / r, i = rem - j * r;
+    if (i < j) return;
+    double* c = C + s * r * r;
+    const double v = c[i + j * r];
+    const double out = i == j ? 0.5 * (3.0 - v) : -0.5 * v;
+    c[i + j * r] = out;
+    c[j + i * r] = out;
+}
+
+// Ut = W^T per r x r slice
+template <class T>
+__global__ void pc_transpose(const T* __restrict__ W, int64_t r, int64_t n, T* __restrict__ Ut) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= r * r * n) return;
+    const int64_t s = e / (r * r), rem = e - s * r * r, j = rem / r, i = rem - j * r;
+    Ut[s * r * r + j + i * r] = W[e];
 }
 
 // rho[i] = r, off[i] = i r: every slice's full-rank block for the product
@@ -1077,10 +1098,10 @@ size_t gram_svd_workspace_bytes(int64_t m, int64_t p, int64_t n) {
 
 
 // G = X X^T (FP64) and the pivoted, shifted Cholesky factor of every slice,
-// P (G + s I) P^T = L L^T: B = P^T L in T (B B^T = G + s I), s per slice.
+// P (G + s I) P^T = L L^T: B = P^T L in OT (B B^T = G + s I), s per slice.
 // G and Lw are the factorisation's workspace (G is overwritten).
-template <class T>
-int gram_factor(const T* A_hat, const SliceGeom& g, int64_t n, double* G, double* Lw, T* B,
+template <class T, class OT>
+int gram_factor(const T* A_hat, const SliceGeom& g, int64_t n, double* G, double* Lw, OT* B,
                 double* shift, hipStream_t st) {
     const int64_t r = g.r;
     const int nt = (int)((r + 63) / 64);
@@ -1089,10 +1110,10 @@ int gram_factor(const T* A_hat, const SliceGeom& g, int64_t n, double* G, double
     pc_gram<T><<<(unsigned)(ntri * n), 256, 0, st>>>(A_hat, g, ntri, G);
     TSVDM_LAUNCH_CHECK();
     const double cshift = (double)(g.L + r) * 1.1102230246251565e-16;
-    if (r <= 128) pc_chol<128, T><<<(unsigned)n, 256, 0, st>>>(G, r, cshift, Lw, B, shift);
-    else if (r <= 256) pc_chol<256, T><<<(unsigned)n, 256, 0, st>>>(G, r, cshift, Lw, B, shift);
-    else if (r <= 512) pc_chol<512, T><<<(unsigned)n, 256, 0, st>>>(G, r, cshift, Lw, B, shift);
-    else pc_chol<1024, T><<<(unsigned)n, 256, 0, st>>>(G, r, cshift, Lw, B, shift);
+    if (r <= 128) pc_chol<128, OT><<<(unsigned)n, 256, 0, st>>>(G, r, cshift, Lw, B, shift);
+    else if (r <= 256) pc_chol<256, OT><<<(unsigned)n, 256, 0, st>>>(G, r, cshift, Lw, B, shift);
+    else if (r <= 512) pc_chol<512, OT><<<(unsigned)n, 256, 0, st>>>(G, r, cshift, Lw, B, shift);
+    else pc_chol<1024, OT><<<(unsigned)n, 256, 0, st>>>(G, r, cshift, Lw, B, shift);
     TSVDM_LAUNCH_CHECK();
     return TSVDM_OK;
 }
@@ -1107,7 +1128,7 @@ int run_gram_svd(const float* A_hat, int64_t m, int64_t p, int64_t n, float* B, 
     double* G = cv.carve<double>((size_t)(r * r * n));
     double* Lw = cv.carve<double>((size_t)(r * r * n));
     void* jws = static_cast<char*>(ws) + cv.total();
-    const int rc0 = gram_factor<float>(A_hat, g, n, G, Lw, B, shift, st);
+    const int rc0 = gram_factor<float, float>(A_hat, g, n, G, Lw, B, shift, st);
     if (rc0) return rc0;
     // one-sided Jacobi on the columns of L (r x r), no accumulated rotations:
     // held in LDS, or the block rounds streaming through HBM
@@ -1174,9 +1195,9 @@ size_t precond_svd_workspace_bytes(int64_t m, int64_t p, int64_t n, int dt) {
     const size_t e = dt == TSVDM_F64 ? 8 : 4;
     const size_t rr = (size_t)(g.r * g.r * n);
     Carver cv(nullptr);
-    cv.carve<double>(rr);                  // G
-    cv.carve<double>(rr);                  // second trailing-matrix buffer of the Cholesky
-    cv.carve<char>(rr * e);                // B
+    cv.carve<double>(rr);                  // G, then W^T W and S
+    cv.carve<double>(rr);                  // second Cholesky buffer, then the Newton-Schulz iterate
+    cv.carve<float>(rr);                   // B (FP32 factor)
     cv.carve<char>(g.rows ? rr * e : 1);   // W^T (wide slices)
     cv.carve<double>((size_t)n);           // shifts
     cv.carve<int32_t>((size_t)n);          // full ranks
@@ -1187,9 +1208,11 @@ size_t precond_svd_workspace_bytes(int64_t m, int64_t p, int64_t n, int dt) {
 
 namespace {
 
+// FP64 slices (T = double)
 template <class T>
 int precond_impl(const T* A_hat, int dt, int64_t m, int64_t p, int64_t n, T* X, T* W, double* s2,
                  int32_t* status, const JacobiOpts& o, void* ws, hipStream_t st) {
+    static_assert(sizeof(T) == 8, "the preconditioned form runs FP64 slices");
     const SliceGeom g = slice_geom(m, p);
     const int64_t r = g.r;
     TSVDM_REQUIRE(r <= GRAM_MAX_R, TSVDM_E_SHAPE, "min(m, p) must be <= 1024 for the preconditioned form");
@@ -1198,33 +1221,65 @@ int precond_impl(const T* A_hat, int dt, int64_t m, int64_t p, int64_t n, T* X, 
     Carver cv(ws);
     double* G = cv.carve<double>(rr);
     double* Lw = cv.carve<double>(rr);
-    T* B = cv.carve<T>(rr);
+    float* B = cv.carve<float>(rr);
     T* Ut = cv.carve<T>(g.rows ? rr : 1);
     double* shift = cv.carve<double>((size_t)n);
     int32_t* rho = cv.carve<int32_t>((size_t)n);
     int64_t* off = cv.carve<int64_t>((size_t)n + 1);
     int32_t* s1 = cv.carve<int32_t>(1);
     void* jws = static_cast<char*>(ws) + cv.total();
-    // 1. the Gram form's factor and its Jacobi (no accumulator): B's unit
-    //    columns are the short-side singular vectors to within the FP64
-    //    Gram's rounding
-    int rc = gram_factor<T>(A_hat, g, n, G, Lw, B, shift, st);
+    // 1. the FP32 Gram form's factor and its Jacobi (no accumulator): B's
+    //    unit columns are the short-side singular vectors to the FP32
+    //    Jacobi's tolerance (and the FP64 Gram's rounding)
+    int rc = gram_factor<T, float>(A_hat, g, n, G, Lw, B, shift, st);
     if (rc) return rc;
-    JacobiOpts o1 = jacobi_default_opts(r, r, dt);
+    JacobiOpts o1 = jacobi_default_opts(r, r, TSVDM_F32);
     o1.block = o.block;
     o1.max_sweeps = o.max_sweeps;
     o1.host_poll = o.host_poll;
-    rc = run_jacobi(B, dt, r, r, n, nullptr, s2, s1, o1, jws, st);
+    rc = run_jacobi(B, TSVDM_F32, r, r, n, nullptr, s2, s1, o1, jws, st);
     if (rc) return rc;
-    pc_normalize<T><<<dim3((unsigned)r, (unsigned)n), 256, 0, st>>>(B, r, W, g.rows ? Ut : nullptr, s1);
+    // (into Lw, so that the third Newton-Schulz step below ends in W)
+    pc_normalize<float, double><<<dim3((unsigned)r, (unsigned)n), 256, 0, st>>>(B, r, Lw, s1);
     TSVDM_LAUNCH_CHECK();
-    // 2. the slice rotated by them: X = W^T A (wide) or A W (tall)
+    // 2. W orthonormal to the working precision: its cosines are <= the
+    //    FP32 tol (~1e-5), so ||W^T W - I|| <= r tol < 0.02 and three
+    //    Newton-Schulz steps take it below 1e-18 (0.02 -> 3e-4 -> 7e-8 ->
+    //    4e-15 at worst, then rounding); the rotation form in step 4 then
+    //    applies an orthogonal W, so its result keeps its own accuracy.
+    //    W^T W by the Gram kernel (the columns of W as vectors), W S by the
+    //    factor product with every slice at full rank.
     pc_rank_full<<<(unsigned)((n + 256) / 256), 256, 0, st>>>(rho, off, r, n);
     TSVDM_LAUNCH_CHECK();
+    {
+        const SliceGeom gw = slice_geom(r, r);
+        const int nt = (int)((r + 63) / 64);
+        const int ntri = nt * (nt + 1) / 2;
+        TSVDM_REQUIRE((int64_t)ntri * n < ((int64_t)1 << 31), TSVDM_E_SHAPE, "too many Gram tiles");
+        const unsigned eb = (unsigned)((r * r * n + 255) / 256);
+        double* cur = Lw;
+        double* nxt = W;
+        for (int it = 0; it < 3; ++it) {   // Lw -> W -> Lw -> W
+            pc_gram<double><<<(unsigned)(ntri * n), 256, 0, st>>>(cur, gw, ntri, G);
+            TSVDM_LAUNCH_CHECK();
+            pc_ns_coef<<<eb, 256, 0, st>>>(G, r, n);
+            TSVDM_LAUNCH_CHECK();
+            rc = run_lowrank_gemm(cur, G, TSVDM_F64, r, r, n, rho, off, r * n, nxt, st);
+            if (rc) return rc;
+            double* const t = cur;
+            cur = nxt;
+            nxt = t;
+        }
+        if (g.rows) {
+            pc_transpose<double><<<eb, 256, 0, st>>>(W, r, n, Ut);
+            TSVDM_LAUNCH_CHECK();
+        }
+    }
+    // 3. the slice rotated by W: X = W^T A (wide) or A W (tall)
     if (g.rows) rc = run_lowrank_gemm(Ut, A_hat, dt, m, p, n, rho, off, r * n, X, st);
     else rc = run_lowrank_gemm(A_hat, W, dt, m, p, n, rho, off, r * n, X, st);
     if (rc) return rc;
-    // 3. the rotation form on X, accumulating into W: its first sweeps find
+    // 4. the rotation form on X, accumulating into W: its first sweeps find
     //    the vectors nearly orthogonal already
     JacobiOpts o2 = o;
     o2.w_given = 1;
@@ -1239,11 +1294,9 @@ int precond_impl(const T* A_hat, int dt, int64_t m, int64_t p, int64_t n, T* X, 
 
 int run_precond_svd(const void* A_hat, int dt, int64_t m, int64_t p, int64_t n, void* X, void* W,
                     double* s2, int32_t* status, const JacobiOpts& o, void* ws, hipStream_t st) {
-    if (dt == TSVDM_F64)
-        return precond_impl<double>(static_cast<const double*>(A_hat), dt, m, p, n, static_cast<double*>(X),
-                                    static_cast<double*>(W), s2, status, o, ws, st);
-    return precond_impl<float>(static_cast<const float*>(A_hat), dt, m, p, n, static_cast<float*>(X),
-                               static_cast<float*>(W), s2, status, o, ws, st);
+    TSVDM_REQUIRE(dt == TSVDM_F64, TSVDM_E_UNSUPPORTED, "the preconditioned form runs FP64 slices");
+    return precond_impl<double>(static_cast<const double*>(A_hat), dt, m, p, n, static_cast<double*>(X),
+                                static_cast<double*>(W), s2, status, o, ws, st);
 }
 
 }  // namespace tsvdm
