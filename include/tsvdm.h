@@ -210,17 +210,18 @@ int tsvdm_slice_svd(void* A_hat, int dtype, int64_t m, int64_t p, int64_t n,
 /* Slice SVDs by the rotation form, preconditioned by the Gram form
  * (Algorithm 1's slice SVDs; Section 3.2 leaves their method open), in FP64
  * with the rotation form's accuracy.  With r = min(m, p):
- *   1. the Gram form of tsvdm_slice_svd_gram in FP64 (FP64 Gram matrix,
- *      shifted Cholesky factor, Jacobi on its columns to the FP64 tol):
- *      unit columns W (r x r), orthogonal to that tol, approximating the
- *      short-side singular vectors to within the Gram's rounding;
- *   2. X = W^T A_hat (m < p) or A_hat W (m >= p), one GEMM per slice;
- *   3. the one-sided Jacobi of tsvdm_slice_svd on X with W as its starting
+ *   1. the Gram form of tsvdm_slice_svd_gram (FP64 Gram matrix, pivoted
+ *      shifted Cholesky factor, FP32 Jacobi on its columns to the FP32
+ *      tol): unit columns W (r x r, FP64), approximating the short-side
+ *      singular vectors, with cosines <= that tol;
+ *   2. W made orthonormal to FP64 rounding by three Newton-Schulz steps
+ *      W <- W (3 I - W^T W) / 2 (quadratic from ||W^T W - I|| <= r tol);
+ *   3. X = W^T A_hat (m < p) or A_hat W (m >= p), one GEMM per slice;
+ *   4. the one-sided Jacobi of tsvdm_slice_svd on X with W as its starting
  *      accumulator: X and W then hold exactly what tsvdm_slice_svd leaves
  *      in A_hat and W (the same layouts, the same convergence test on the
  *      vectors themselves), in fewer sweeps of the long vectors.
- * dtype: TSVDM_F64 only (an FP32 first stage would leave W orthogonal only
- * to the FP32 tol, and the final W inherits it).
+ * dtype: TSVDM_F64 only.
  * A_hat is only read; X (m x p x n, dtype) receives the orthogonalised
  * vectors, W (r x r x n) the accumulated rotation, s2 (r x n, FP64) the
  * squared singular values (unsorted), status TSVDM_OK, TSVDM_E_NOCONV or
