@@ -85,8 +85,9 @@ def resolve_svd(svd, precision, r, certify=False):
     "gram" (FP32 Jacobi dtype only, min(m, p) <= 1024) runs the Jacobi on
     the Cholesky factor of the slice's FP64 Gram matrix and forms the long-
     side factor by one product (tsvdm_slice_svd_gram); "precond" (FP64 path,
-    min(m, p) <= 1024) rotates the slice by the FP64 Gram form's vectors and
-    finishes with the rotation form, to its accuracy (tsvdm_slice_svd_precond).  "auto":
+    min(m, p) <= 1024) rotates the slice by the Gram form's vectors, made
+    orthonormal in FP64, and finishes with the rotation form, to its
+    accuracy (tsvdm_slice_svd_precond).  "auto":
     "gram" on the reduced-precision paths where it applies, "precond" on the
     FP64 path where it applies, else "jacobi"."""
     if svd not in ("auto", "jacobi", "gram", "precond"):
