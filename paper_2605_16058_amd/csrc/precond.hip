@@ -163,26 +163,29 @@ __global__ __launch_bounds__(256) void pc_gram_batch(const GramSlice* __restrict
 // the remaining rows, compacted in their original order, in column-major
 // storage with leading dimension equal to its size (strict lower triangle;
 // the updated diagonal lives in LDS): G itself at first, then alternately
-// Ws and G (G is overwritten).  Per panel: CB pivot steps, each a block
-// argmax over the diagonal and one new column (the trailing column of the
-// pivot minus the panel's earlier columns), then the panel's columns to B
-// and one MFMA update of the remaining trailing matrix into the other
-// buffer.  A pivot <= 0 (rounding of a singular G + s I) gives a zero
+// Ws and G (G is overwritten).  Per panel: CB pivot steps, then the panel's
+// columns to B and one MFMA update of the remaining trailing matrix into
+// the other buffer.  A pivot step is one barrier: every wave finds the
+// pivot itself (an argmax over the whole diagonal, the same order in every
+// wave), then the threads compute the new column (the trailing column of
+// the pivot minus the panel's earlier columns).  So that a wave still
+// searching never sees the step's own writes, the diagonal alternates
+// between two LDS buffers and a pivot's mark carries its step.  A pivot <= 0 (rounding of a singular G + s I) gives a zero
 // column; non-finite values stay non-finite.  Fixed operation order: the
 // result does not depend on timing.
 template <int MAXR, class OT>
 __device__ __forceinline__ void chol_slice(double* __restrict__ Gs, int64_t r, double cshift,
                                            double* __restrict__ Ws, OT* __restrict__ Os,
                                            double* __restrict__ shift_out) {
-    constexpr int PLD = CB + 1;                // column CB: the updated diagonal
+    constexpr int PLD = CB + 1;                // column CB: the updated diagonal (even steps)
     constexpr int PER = (MAXR + 255) / 256;    // positions per thread
     __shared__ double P[MAXR * PLD];           // panel columns by trailing position
+    __shared__ double dodd[MAXR];              // the updated diagonal after odd steps
     __shared__ int opos[MAXR];                 // original index of each position
-    __shared__ int posof[MAXR];                // position of each original index (-1: factored)
-    __shared__ int keep[MAXR];                 // 0: remaining, -1: pivot of this panel
+    __shared__ int keep[MAXR];                 // 0: remaining, c + 1: pivot of step c of this panel
     __shared__ int oldp[MAXR];                 // after a panel: old position of each new one
     __shared__ double rv[4];
-    __shared__ int ri[4], scan_w[4];
+    __shared__ int scan_w[4];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, lr = lane & 15, lg = lane >> 4;
     const int R = (int)r;
     // trace in a fixed order
@@ -195,9 +198,10 @@ __device__ __forceinline__ void chol_slice(double* __restrict__ Gs, int64_t r, d
     if (tid == 0) *shift_out = sh;
     for (int a = tid; a < R; a += 256) {
         opos[a] = a;
-        posof[a] = a;
         P[a * PLD + CB] = Gs[(int64_t)a * (R + 1)] + sh;
     }
+    // B starts at zero: a panel writes only the rows still remaining
+    for (int64_t e = tid; e < (int64_t)R * R; e += 256) Os[e] = OT(0);
     __syncthreads();
     double* To = Gs;   // trailing matrix, strict lower triangle, leading dimension ldo
     double* Tn = Ws;
@@ -208,13 +212,21 @@ __device__ __forceinline__ void chol_slice(double* __restrict__ Gs, int64_t r, d
         for (int a = tid; a < n; a += 256) keep[a] = 0;
         __syncthreads();
         for (int c = 0; c < nc; ++c) {
-            // 1. pivot: the largest updated diagonal among the remaining rows
-            //    (NaN counts as -inf; some row always remains)
+            // the updated diagonal: read from one buffer, written to the other
+            const double* dcur = (c & 1) ? dodd : P + CB;
+            double* dnxt = (c & 1) ? P + CB : dodd;
+            const int dst = (c & 1) ? 1 : PLD;   // stride of dcur
+            const int dsn = (c & 1) ? PLD : 1;   // stride of dnxt
+            // 1. pivot, in every wave: the largest updated diagonal among the
+            //    remaining rows (ties: the lowest position; NaN counts as
+            //    -inf; some row always remains).  A mark c + 1 is this
+            //    step's own pivot, set by a faster wave: still a candidate.
             double bv = -INFINITY;
             int bi = 0x7fffffff;
-            for (int a = tid; a < n; a += 256) {
-                if (keep[a]) continue;
-                double v = P[a * PLD + CB];
+            for (int a = lane; a < n; a += 64) {
+                const int kp = keep[a];
+                if (kp != 0 && kp <= c) continue;
+                double v = dcur[a * dst];
                 v = (v == v) ? v : -INFINITY;
                 if (v > bv || (v == bv && a < bi)) { bv = v; bi = a; }
             }
@@ -223,22 +235,16 @@ __device__ __forceinline__ void chol_slice(double* __restrict__ Gs, int64_t r, d
                 const int oi = __shfl_xor(bi, off);
                 if (ov > bv || (ov == bv && oi < bi)) { bv = ov; bi = oi; }
             }
-            if (lane == 0) { rv[wave] = bv; ri[wave] = bi; }
-            __syncthreads();
-            int q = ri[0];
-            double qv = rv[0];
-#pragma unroll
-            for (int w = 1; w < 4; ++w)
-                if (rv[w] > qv || (rv[w] == qv && ri[w] < q)) { qv = rv[w]; q = ri[w]; }
+            const int q = bi;
             // 2. column c: l_a = (T(a, q) - sum_{c' < c} l_a,c' l_q,c') / l_qq
             // a pivot <= 0 gives a zero column; NaN and Inf travel on (x 0)
             // so that the Jacobi reports them
-            const double dq = P[q * PLD + CB];
+            const double dq = dcur[q * dst];
             const double lqq = dq > 0.0 ? sqrt(dq) : dq * 0.0;
             for (int a = tid; a < n; a += 256) {
                 if (a == q) {
                     P[a * PLD + c] = lqq;
-                    keep[a] = -1;
+                    keep[a] = c + 1;
                 } else if (keep[a]) {
                     P[a * PLD + c] = 0.0;   // pivoted earlier in this panel
                 } else {
@@ -246,17 +252,15 @@ __device__ __forceinline__ void chol_slice(double* __restrict__ Gs, int64_t r, d
                     for (int cc = 0; cc < c; ++cc) t -= P[a * PLD + cc] * P[q * PLD + cc];
                     const double l = lqq > 0.0 ? t / lqq : t * 0.0;
                     P[a * PLD + c] = l;
-                    P[a * PLD + CB] -= l * l;
+                    dnxt[a * dsn] = dcur[a * dst] - l * l;
                 }
             }
             __syncthreads();
         }
-        // 3. the panel's columns of B, rows at their original indices
+        // 3. the panel's columns of B, rows at their original indices (the
+        //    rows factored in earlier panels keep their zeros)
         for (int c = 0; c < nc; ++c)
-            for (int i = tid; i < R; i += 256) {
-                const int pa = posof[i];
-                Os[i + (int64_t)(k + c) * R] = (OT)(pa >= 0 ? P[pa * PLD + c] : 0.0);
-            }
+            for (int a = tid; a < n; a += 256) Os[opos[a] + (int64_t)(k + c) * R] = (OT)P[a * PLD + c];
         // 4. new positions of the remaining rows (order kept): thread tid
         //    takes positions [tid PER, tid PER + PER)
         const int nn = n - nc;
@@ -272,7 +276,7 @@ __device__ __forceinline__ void chol_slice(double* __restrict__ Gs, int64_t r, d
             if (lane >= off) incl += y;
         }
         if (lane == 63) scan_w[wave] = incl;
-        __syncthreads();   // also orders step 3's posof reads before the writes below
+        __syncthreads();
         int base = incl - cnt;
         for (int w = 0; w < wave; ++w) base += scan_w[w];
 #pragma unroll
@@ -281,10 +285,7 @@ __device__ __forceinline__ void chol_slice(double* __restrict__ Gs, int64_t r, d
             if (a < n) {
                 if (keep[a] == 0) {
                     oldp[base] = a;
-                    posof[opos[a]] = base;
                     ++base;
-                } else {
-                    posof[opos[a]] = -1;
                 }
             }
         }
