@@ -108,11 +108,12 @@ int tsvdm_check_transform(const double* M_host, int64_t n, double tol,
  *   tile     workgroup tile of the (mp) x n output, rows x slices:
  *            TSVDM_TILE_64x64, TSVDM_TILE_128x32, TSVDM_TILE_256x16 (16
  *            slices per wave), TSVDM_TILE_128x64, TSVDM_TILE_256x32 (32),
- *            TSVDM_TILE_128x128, TSVDM_TILE_256x64 (64), or TSVDM_TILE_AUTO:
- *            256x16 for n <= 16, 128x32 for n <= 32, else 64x64 for F64
- *            and, for the FP32-operand forms, 128x64 up to n = 64 and
- *            128x128 above.  Every tile gives the same result; only the
- *            speed differs.
+ *            TSVDM_TILE_128x128, TSVDM_TILE_256x64 (64),
+ *            TSVDM_TILE_64x64_2x2 (four waves of 32 rows x 32 slices), or
+ *            TSVDM_TILE_AUTO: 256x16 for n <= 16, 128x32 for n <= 32, else
+ *            64x64_2x2 for F64 and, for the FP32-operand forms, 128x64 up
+ *            to n = 64 and 128x128 above.  Every tile gives the same
+ *            result; only the speed differs.
  * ws: tsvdm_transform_workspace_size bytes (holds op(M) in compute type). */
 enum {
     TSVDM_TILE_AUTO = 0,
@@ -122,7 +123,8 @@ enum {
     TSVDM_TILE_128x64 = 4,
     TSVDM_TILE_256x32 = 5,
     TSVDM_TILE_128x128 = 6,
-    TSVDM_TILE_256x64 = 7
+    TSVDM_TILE_256x64 = 7,
+    TSVDM_TILE_64x64_2x2 = 8
 };
 int tsvdm_transform_workspace_size(int64_t n, size_t* bytes);
 int tsvdm_transform(const void* X, int x_dtype, void* Y, int y_dtype,

@@ -27,10 +27,10 @@ from dataclasses import dataclass, field
 import torch
 
 # transform tiles (rows x slices): 64x64, 128x32, 256x16 (16 slices per
-# wave), 128x64, 256x32 (32), 128x128, 256x64 (64); the FP64 form has no
-# registers for waves of more than 32 slices
-TTM_TILES = (1, 2, 3, 4, 5, 6, 7)
-TTM_TILES_F64 = (1, 2, 3, 4)
+# wave), 128x64, 256x32 (32), 128x128, 256x64 (64), 64x64 as 2 x 2 waves of
+# 32 x 32 (8); the FP64 form has no registers for waves of more than 32 slices
+TTM_TILES = (1, 2, 3, 4, 5, 6, 7, 8)
+TTM_TILES_F64 = (1, 2, 3, 4, 8)
 JACOBI_BLOCKS = (16, 32)
 
 
@@ -66,7 +66,7 @@ def default_tile(n: int, precision: str = "f64") -> int:
     if n <= 32:
         return 2
     if precision == "f64":
-        return 1
+        return 8
     return 4 if n <= 64 else 6
 
 

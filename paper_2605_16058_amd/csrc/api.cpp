@@ -126,7 +126,7 @@ int tsvdm_transform(const void* X, int x_dtype, void* Y, int y_dtype, int64_t m,
                   "BF16 compute writes F32 output only");
     TSVDM_REQUIRE(transpose == 0 || transpose == 1, TSVDM_E_ARG, "transpose must be 0 or 1");
     TSVDM_REQUIRE(std::isfinite(scale), TSVDM_E_ARG, "scale must be finite");
-    TSVDM_REQUIRE(tile >= 0 && tile <= TTM_SHAPES, TSVDM_E_ARG, "tile must be in [0, 7]");
+    TSVDM_REQUIRE(tile >= 0 && tile <= TTM_SHAPES, TSVDM_E_ARG, "tile must be in [0, 8]");
     TSVDM_TRY(check_ws(ws, ws_bytes, ttm_workspace_bytes(n)));
     return run_ttm(X, x_dtype, Y, y_dtype, m, p, n, M, transpose, scale, compute, tile, ws,
                    as_stream(stream));
@@ -162,7 +162,7 @@ int tsvdm_transform_mode(const void* X, int x_dtype, void* Y, int y_dtype, int32
                   "BF16 compute writes F32 output only");
     TSVDM_REQUIRE(transpose == 0 || transpose == 1, TSVDM_E_ARG, "transpose must be 0 or 1");
     TSVDM_REQUIRE(std::isfinite(scale), TSVDM_E_ARG, "scale must be finite");
-    TSVDM_REQUIRE(tile >= 0 && tile <= TTM_SHAPES, TSVDM_E_ARG, "tile must be in [0, 7]");
+    TSVDM_REQUIRE(tile >= 0 && tile <= TTM_SHAPES, TSVDM_E_ARG, "tile must be in [0, 8]");
     TSVDM_TRY(check_ws(ws, ws_bytes, ttm_workspace_bytes(n)));
     return run_ttm_mode(X, x_dtype, Y, y_dtype, R, n, P, M, transpose, scale, compute, tile, ws,
                         as_stream(stream));
@@ -472,7 +472,7 @@ int tsvdm_reconstruct(const void* U_pk, const void* G_pk, int dtype, int64_t m, 
     TSVDM_REQUIRE(!(compute >= TSVDM_BF16 && out_dtype != TSVDM_F32), TSVDM_E_UNSUPPORTED,
                   "BF16 compute writes F32 output only");
     TSVDM_REQUIRE(std::isfinite(scale), TSVDM_E_ARG, "scale must be finite");
-    TSVDM_REQUIRE(tile >= 0 && tile <= TTM_SHAPES, TSVDM_E_ARG, "tile must be in [0, 7]");
+    TSVDM_REQUIRE(tile >= 0 && tile <= TTM_SHAPES, TSVDM_E_ARG, "tile must be in [0, 8]");
     const size_t need = reconstruct_bytes(m, p, n, dtype);
     TSVDM_TRY(check_ws(ws, ws_bytes, need));
     Carver cv(ws);

@@ -100,7 +100,7 @@ int validate_item(const tsvdm_batch_item& it, int idx) {
         return TSVDM_E_ARG;
     }
     if (it.ttm_tile < 0 || it.ttm_tile > TTM_SHAPES) {
-        set_error(where + "ttm_tile must be in [0, 7]");
+        set_error(where + "ttm_tile must be in [0, 8]");
         return TSVDM_E_ARG;
     }
     if (it.mode == 1) {

@@ -120,8 +120,9 @@ int run_jacobi_batch(int dt, const BatchSlice* sl, int64_t nslices, const int2* 
 // ---- transform (ttm.hip)
 size_t ttm_workspace_bytes(int64_t n);
 // tile: 1 = 64 rows x 64 slices, 2 = 128 x 32, 3 = 256 x 16, 4 = 128 x 64,
-// 5 = 256 x 32, 6 = 128 x 128, 7 = 256 x 64, 0 = by n and compute type
-constexpr int TTM_SHAPES = 7;
+// 5 = 256 x 32, 6 = 128 x 128, 7 = 256 x 64, 8 = 64 x 64 in 2 x 2 waves,
+// 0 = by n and compute type
+constexpr int TTM_SHAPES = 8;
 int ttm_resolve_tile(int tile, int64_t n, int compute);
 void ttm_tile_counts(int shape, int64_t R, int64_t n, int64_t* n_rt, int* n_ct);
 // tasks sorted by tile shape; group[s] = task count of shape s + 1 (TTM_SHAPES entries)

@@ -12,6 +12,8 @@
 // shapes share one body (every wave owns four 16-row MFMA tiles and 16, 32
 // or 64 slices): narrow shapes waste less work when n is small, and wider
 // waves read each LDS operand value once for more MFMAs.
+#include <type_traits>
+
 #include "common.h"
 #include "kernels.h"
 
@@ -20,16 +22,18 @@ namespace tsvdm {
 namespace {
 
 // tile shape codes of the C ABI (output slices x rows per workgroup, slices
-// per wave; every wave owns 64 rows): 1 = 64x64, 2 = 32x128, 3 = 16x256 (16
-// slices per wave), 4 = 64x128, 5 = 32x256 (32), 6 = 128x128, 7 = 64x256
-// (64).  A wider wave reads each LDS operand value once for more MFMAs.
+// per wave; the waves own 64 rows each but in shape 8): 1 = 64x64, 2 =
+// 32x128, 3 = 16x256 (16 slices per wave), 4 = 64x128, 5 = 32x256 (32), 6 =
+// 128x128, 7 = 64x256 (64), 8 = 64x64 as 2 x 2 waves of 32 slices x 32
+// rows.  A wider wave reads each LDS operand value once for more MFMAs.
 __host__ __device__ constexpr int shape_ti(int s) {
     return s == 1 ? 64 : s == 2 ? 32 : s == 3 ? 16 : s == 4 ? 64 : s == 5 ? 32 : s == 6 ? 128 : 64;
 }
 __host__ __device__ constexpr int shape_tr(int s) {
-    return s == 1 ? 64 : s == 2 ? 128 : s == 3 ? 256 : s == 4 ? 128 : s == 5 ? 256 : s == 6 ? 128 : 256;
+    return s == 1 ? 64 : s == 2 ? 128 : s == 3 ? 256 : s == 4 ? 128 : s == 5 ? 256 : s == 6 ? 128 : s == 7 ? 256 : 64;
 }
-__host__ __device__ constexpr int shape_ws(int s) { return s <= 3 ? 16 : s <= 5 ? 32 : 64; }
+__host__ __device__ constexpr int shape_ws(int s) { return s <= 3 ? 16 : s <= 5 ? 32 : s <= 7 ? 64 : 32; }
+__host__ __device__ constexpr int shape_wr(int s) { return s == 8 ? 32 : 64; }
 template <int SHAPE>
 struct TileShape {
     static constexpr int TI = shape_ti(SHAPE);        // output slices per workgroup
@@ -37,16 +41,17 @@ struct TileShape {
     static constexpr int WS = shape_ws(SHAPE);        // slices per wave
     static constexpr int NS = WS / 16;                // 16-slice MFMA tiles per wave
     static constexpr int WI = TI / WS;                // waves along slices
-    static constexpr int WROWS = TR / (4 / WI);       // rows per wave (always 64)
-    static_assert(WROWS == 64 && WI * (TR / WROWS) == 4, "four waves of 64 rows");
+    static constexpr int WROWS = shape_wr(SHAPE);     // rows per wave
+    static constexpr int NR = WROWS / 16;             // 16-row MFMA tiles per wave
+    static_assert(WI * (TR / WROWS) == 4, "four waves");
 };
 
-// tile = 0: by n; FP32-operand forms take the wide waves once n > 32 (the
-// FP64 form has no registers for them)
+// tile = 0: by n; FP32-operand forms take the wide waves once n > 32, the
+// FP64 form (no registers for them) the 2 x 2 waves of 32 x 32
 int default_tile(int64_t n, int compute) {
     if (n <= 16) return 3;
     if (n <= 32) return 2;
-    if (compute == TSVDM_F64) return 1;
+    if (compute == TSVDM_F64) return 8;
     return n <= 64 ? 4 : 6;
 }
 
@@ -101,11 +106,12 @@ __device__ __forceinline__ void ttm_tile(TtmShared<CT, KIND, SHAPE>& sh, const X
     const int wi = wave % WI;                                // slice group of this wave
     const int wr0 = (wave / WI) * TileShape<SHAPE>::WROWS;  // first tile row of this wave
 
-    AccT acc[NS][4];
+    constexpr int NR = TileShape<SHAPE>::NR;
+    AccT acc[NS][NR];
 #pragma unroll
     for (int u = 0; u < NS; ++u)
 #pragma unroll
-        for (int t = 0; t < 4; ++t) acc[u][t] = zero4<AccT>();
+        for (int t = 0; t < NR; ++t) acc[u][t] = zero4<AccT>();
 
     // This thread's staging elements: X load k covers rows r .. r + VW - 1
     // of column l, consecutive threads along the rows; op(M) value k is
@@ -136,78 +142,81 @@ __device__ __forceinline__ void ttm_tile(TtmShared<CT, KIND, SHAPE>& sh, const X
     // every row and slice of the tile inside the tensor: only the columns
     // of a partial last chunk are zeroed
     const bool inner = row0 + TR <= R && i0 + TI <= n;
-    XT xv[NXE][VW];
-    CT tv[NTE];
-    bool lok[NXE], ltok[NTE];
-    auto load = [&](int l0) {
+    // FP64: two register sets, chunk c + 2 loaded while chunk c + 1 waits to
+    // be stored, so each load has a whole chunk of MFMAs to arrive (FP32 has
+    // no registers to spare for it: its wide tiles would lose waves)
+    constexpr int PF = sizeof(CT) == 8 ? 2 : 1;
+    XT xv[PF][NXE][VW];
+    CT tv[PF][NTE];
+    bool lok[PF][NXE], ltok[PF][NTE];
+    auto load = [&](auto S, int l0) {
+        constexpr int s = decltype(S)::value;
         const bool full = l0 + KC <= n;
 #pragma unroll
         for (int k = 0; k < NXE; ++k) {
             const XT* src = xb[k] + (int64_t)l0 * R;
-            lok[k] = true;
+            lok[s][k] = true;
             if (!full) {
                 const int l = (tid + 256 * k) / (TR / VW);
-                lok[k] = l0 + l < n;
-                if (!lok[k]) src = xb[k] + (int64_t)(n - 1 - l) * R;
+                lok[s][k] = l0 + l < n;
+                if (!lok[s][k]) src = xb[k] + (int64_t)(n - 1 - l) * R;
             }
             if constexpr (VW == 4) {
                 const float4 x = *reinterpret_cast<const float4*>(src);
-                xv[k][0] = x.x; xv[k][1] = x.y; xv[k][2] = x.z; xv[k][3] = x.w;
+                xv[s][k][0] = x.x; xv[s][k][1] = x.y; xv[s][k][2] = x.z; xv[s][k][3] = x.w;
             } else if constexpr (VW == 2) {
                 const double2 x = *reinterpret_cast<const double2*>(src);
-                xv[k][0] = x.x; xv[k][1] = x.y;
+                xv[s][k][0] = x.x; xv[s][k][1] = x.y;
             } else {
-                xv[k][0] = *src;
+                xv[s][k][0] = *src;
             }
         }
 #pragma unroll
         for (int k = 0; k < NTE; ++k) {
             const CT* src = tb[k] + l0;
-            ltok[k] = true;
+            ltok[s][k] = true;
             if (!full) {
                 const int l = (tid + 256 * k) % KC;
-                ltok[k] = l0 + l < n;
-                if (!ltok[k]) src = tb[k] + (n - 1 - l);
+                ltok[s][k] = l0 + l < n;
+                if (!ltok[s][k]) src = tb[k] + (n - 1 - l);
             }
-            tv[k] = *src;
+            tv[s][k] = *src;
         }
     };
-    auto store = [&](int stg) {
+    auto store = [&](auto S, int stg) {
+        constexpr int s = decltype(S)::value;
 #pragma unroll
         for (int k = 0; k < NXE; ++k) {
             const int e = tid + 256 * k;
             CT* dst = &sh.Xs[stg][e / (TR / VW)][(e % (TR / VW)) * VW];
-            const bool ok = (inner || xok[k]) && lok[k];
+            const bool ok = (inner || xok[k]) && lok[s][k];
 #pragma unroll
-            for (int q = 0; q < VW; ++q) dst[q] = ok ? static_cast<CT>(xv[k][q]) : CT(0);
+            for (int q = 0; q < VW; ++q) dst[q] = ok ? static_cast<CT>(xv[s][k][q]) : CT(0);
         }
 #pragma unroll
         for (int k = 0; k < NTE; ++k) {
             const int e = tid + 256 * k;
-            sh.Ts[stg][e / KC][e % KC] = ((inner || tok[k]) && ltok[k]) ? tv[k] : CT(0);
+            sh.Ts[stg][e / KC][e % KC] = ((inner || tok[k]) && ltok[s][k]) ? tv[s][k] : CT(0);
         }
     };
 
     const int irow = wi * WS + lr;  // output slice (A-operand row) of the wave's first slice tile
     const int nchunk = (n + KC - 1) / KC;
-    load(0);
-    store(0);
-    __syncthreads();
-    for (int c = 0; c < nchunk; ++c) {
-        const int stg = c & 1;
-        if (c + 1 < nchunk) load((c + 1) * KC);
+    typedef std::integral_constant<int, 0> S0;
+    typedef std::integral_constant<int, 1> S1;
+    auto compute = [&](int stg) {
         const auto& Xs = sh.Xs[stg];
         const auto& Ts = sh.Ts[stg];
         if constexpr (KIND == 0) {
             // every operand of the chunk read before the first MFMA, so that
             // the LDS latency is paid once per chunk
-            CT af[KC / 4][NS], bf[KC / 4][4];
+            CT af[KC / 4][NS], bf[KC / 4][NR];
 #pragma unroll
             for (int kq = 0; kq < KC / 4; ++kq) {
 #pragma unroll
                 for (int u = 0; u < NS; ++u) af[kq][u] = Ts[irow + 16 * u][4 * kq + lg];
 #pragma unroll
-                for (int t = 0; t < 4; ++t) bf[kq][t] = Xs[4 * kq + lg][wr0 + t * 16 + lr];
+                for (int t = 0; t < NR; ++t) bf[kq][t] = Xs[4 * kq + lg][wr0 + t * 16 + lr];
             }
             __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
@@ -215,7 +224,7 @@ __device__ __forceinline__ void ttm_tile(TtmShared<CT, KIND, SHAPE>& sh, const X
 #pragma unroll
                 for (int u = 0; u < NS; ++u)
 #pragma unroll
-                    for (int t = 0; t < 4; ++t) acc[u][t] = mfma(af[kq][u], bf[kq][t], acc[u][t]);
+                    for (int t = 0; t < NR; ++t) acc[u][t] = mfma(af[kq][u], bf[kq][t], acc[u][t]);
             }
         } else {
             v8bf ahi[NS], alo[NS];
@@ -229,7 +238,7 @@ __device__ __forceinline__ void ttm_tile(TtmShared<CT, KIND, SHAPE>& sh, const X
                     alo[u][e] = to_bf16(x - static_cast<float>(h));
                 }
 #pragma unroll
-            for (int t = 0; t < 4; ++t) {
+            for (int t = 0; t < NR; ++t) {
                 v8bf bhi, blo;
 #pragma unroll
                 for (int e = 0; e < 8; ++e) {
@@ -248,13 +257,38 @@ __device__ __forceinline__ void ttm_tile(TtmShared<CT, KIND, SHAPE>& sh, const X
                 }
             }
         }
-        if (c + 1 < nchunk) store(stg ^ 1);
+    };
+    // chunk c in LDS stage c & 1
+    load(S0{}, 0);
+    store(S0{}, 0);
+    if constexpr (PF == 2) {
+        // register set s holds chunk c + 1 during step c when c & 1 == s
+        if (nchunk > 1) load(S0{}, KC);
         __syncthreads();
+        auto step = [&](auto S, int c) {
+            constexpr int s = decltype(S)::value;
+            if (c + 2 < nchunk) load(std::integral_constant<int, 1 - s>{}, (c + 2) * KC);
+            compute(c & 1);
+            if (c + 1 < nchunk) store(S, (c + 1) & 1);
+            __syncthreads();
+        };
+        for (int c = 0; c < nchunk; c += 2) {
+            step(S0{}, c);
+            if (c + 1 < nchunk) step(S1{}, c + 1);
+        }
+    } else {
+        __syncthreads();
+        for (int c = 0; c < nchunk; ++c) {
+            if (c + 1 < nchunk) load(S0{}, (c + 1) * KC);
+            compute(c & 1);
+            if (c + 1 < nchunk) store(S0{}, (c + 1) & 1);
+            __syncthreads();
+        }
     }
 
     // D lane layout: slice i0 + WS*wi + 16*u + mfma row, row row0 + wr0 + 16*t + lr
 #pragma unroll
-    for (int t = 0; t < 4; ++t) {
+    for (int t = 0; t < NR; ++t) {
         int64_t row = row0 + wr0 + t * 16 + lr;
         if (row >= R) continue;
 #pragma unroll
@@ -349,6 +383,7 @@ int launch_shape(const void* X, void* Y, int ydt, int64_t R, int n, int64_t P, c
         case 5: return launch_tiles<CT, XT, KIND, 5>(X, Y, ydt, R, n, P, Tt, st);
         case 6: return launch_tiles<CT, XT, KIND, 6>(X, Y, ydt, R, n, P, Tt, st);
         case 7: return launch_tiles<CT, XT, KIND, 7>(X, Y, ydt, R, n, P, Tt, st);
+        case 8: return launch_tiles<CT, XT, KIND, 8>(X, Y, ydt, R, n, P, Tt, st);
         default: set_error("unknown transform tile shape"); return TSVDM_E_ARG;
     }
 }
@@ -380,7 +415,8 @@ int launch_batch_x(const TtmProblem* probs, const int4* tasks, const int64_t* gr
                 case 4: ttm_kernel_batch<CT, XT, KIND, 4><<<g, 256, 0, st>>>(probs, tasks + o, ydt); break;
                 case 5: ttm_kernel_batch<CT, XT, KIND, 5><<<g, 256, 0, st>>>(probs, tasks + o, ydt); break;
                 case 6: ttm_kernel_batch<CT, XT, KIND, 6><<<g, 256, 0, st>>>(probs, tasks + o, ydt); break;
-                default: ttm_kernel_batch<CT, XT, KIND, 7><<<g, 256, 0, st>>>(probs, tasks + o, ydt); break;
+                case 7: ttm_kernel_batch<CT, XT, KIND, 7><<<g, 256, 0, st>>>(probs, tasks + o, ydt); break;
+                default: ttm_kernel_batch<CT, XT, KIND, 8><<<g, 256, 0, st>>>(probs, tasks + o, ydt); break;
             }
             TSVDM_LAUNCH_CHECK();
         }

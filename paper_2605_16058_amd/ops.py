@@ -130,8 +130,8 @@ def device_matrix(M, device="cuda") -> torch.Tensor:
 def tsvdm_transform(X, Mdev, transpose=False, scale=1.0, compute="f64", out_dtype=None,
                     out=None, ws=None, tile=0):
     """Y = X x_3 (scale * op(M)); Mdev from device_matrix().  tile: 0 = by n
-    and compute, 1..7 = 64x64, 128x32, 256x16, 128x64, 256x32, 128x128,
-    256x64 (rows x slices)."""
+    and compute, 1..8 = 64x64, 128x32, 256x16, 128x64, 256x32, 128x128,
+    256x64 (rows x slices), 64x64 in 2 x 2 waves."""
     X = as_colmajor(X)
     m, p, n = X.shape
     odt = out_dtype or (torch.float64 if compute == "f64" else torch.float32)

@@ -112,7 +112,7 @@ def test_transform_validation(lib):
     a = list(ok); a[2] = a[0]
     assert lib.tsvdm_transform(*a) == -1
     # unknown tile shape
-    for tile in (-1, 8):
+    for tile in (-1, 9):
         a = list(ok); a[11] = tile
         assert lib.tsvdm_transform(*a) == -1
         assert b"tile" in lib.tsvdm_last_error()
@@ -253,7 +253,7 @@ def test_batch_plan_validation_and_layout(lib):
     a, b = _item(), _item(300, 280, 12, 1)
     a.block, b.block, a.ttm_tile, b.ttm_tile = 16, 32, 3, 1
     assert create([a, b])[0] == 0
-    for field, bad in (("block", 8), ("block", 64), ("ttm_tile", 8), ("ttm_tile", -1), ("reserved", 1)):
+    for field, bad in (("block", 8), ("block", 64), ("ttm_tile", 9), ("ttm_tile", -1), ("reserved", 1)):
         it = _item()
         setattr(it, field, bad)
         assert create([it])[0] == -1, field

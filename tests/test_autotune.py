@@ -14,7 +14,7 @@ def test_buckets():
 
 def test_defaults_match_library_rules():
     assert T.default_block(255, 4000) == 16 and T.default_block(256, 256) == 32
-    assert [T.default_tile(n) for n in (1, 16, 17, 32, 33, 256)] == [3, 3, 2, 2, 1, 1]
+    assert [T.default_tile(n) for n in (1, 16, 17, 32, 33, 256)] == [3, 3, 2, 2, 8, 8]
     assert [T.default_tile(n, "f32") for n in (1, 16, 17, 32, 33, 64, 65, 256)] == [3, 3, 2, 2, 4, 4, 6, 6]
 
 

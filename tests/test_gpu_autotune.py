@@ -33,9 +33,9 @@ def test_transform_tiles_bit_identical(shape, compute, dt):
     g = np.random.default_rng(7 + shape[2])
     A = to_dev(g.standard_normal(shape), dt)
     Md = ops.device_matrix(synth.haar_orthogonal(shape[2], g))
-    outs = [ops.tsvdm_transform(A, Md, compute=compute, out_dtype=dt, tile=t) for t in range(8)]
+    outs = [ops.tsvdm_transform(A, Md, compute=compute, out_dtype=dt, tile=t) for t in range(9)]
     torch.cuda.synchronize()
-    for t in range(1, 8):
+    for t in range(1, 9):
         assert torch.equal(outs[0], outs[t]), t
 
 
@@ -45,7 +45,7 @@ def test_batch_mixed_blocks_and_tiles_equal_single_calls():
     Ts = [to_dev(A, torch.float32) for A in w.A]
     cnt = len(Ts)
     blocks = [16 if t % 3 else 32 for t in range(cnt)]
-    tiles = [1 + t % 7 for t in range(cnt)]
+    tiles = [1 + t % 8 for t in range(cnt)]
     b = BatchTSVDM(Ts, w.M, w.mode, ks=w.k, epss=w.eps, precision="f32", blocks=blocks, tiles=tiles)
     st = b.run(host_poll=True)
     torch.cuda.synchronize()
@@ -69,7 +69,7 @@ def test_tune_batch_choices_are_valid_and_cached(tmp_path):
     blocks, tiles, report = autotune.tune_batch(Ts, w.M, w.mode, ks=w.k, epss=w.eps,
                                                 precision="f32", cache=path, sample=12, reps=1)
     assert len(blocks) == len(Ts) and len(tiles) == len(Ts)
-    assert set(blocks) <= {16, 32} and set(tiles) <= set(range(8))
+    assert set(blocks) <= {16, 32} and set(tiles) <= set(range(9))
     assert report
     # a second call is served from the cache: no timing, same answer
     b2, t2, rep2 = autotune.tune_batch(Ts, w.M, w.mode, ks=w.k, epss=w.eps, precision="f32",
@@ -89,6 +89,6 @@ def test_tune_tsvdm_single_tensor(tmp_path):
     A = to_dev(w.A, torch.float32)
     ch = autotune.tune_tsvdm(A, w.M, mode="II", eps=1e-2, precision="f32",
                              cache=str(tmp_path / "t.json"), reps=1)
-    assert ch.block in (16, 32) and ch.tile in range(1, 8)
+    assert ch.block in (16, 32) and ch.tile in range(1, 9)
     res = tsvdm(A, w.M, mode="II", eps=1e-2, precision="f32", block=ch.block, tile=ch.tile)
     assert int(res.svd_status.item()) == 0
