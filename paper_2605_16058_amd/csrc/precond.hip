@@ -248,8 +248,17 @@ __device__ __forceinline__ void chol_slice(double* __restrict__ Gs, int64_t r, d
                 } else if (keep[a]) {
                     P[a * PLD + c] = 0.0;   // pivoted earlier in this panel
                 } else {
-                    double t = a > q ? To[a + (int64_t)q * ldo] : To[q + (int64_t)a * ldo];
-                    for (int cc = 0; cc < c; ++cc) t -= P[a * PLD + cc] * P[q * PLD + cc];
+                    // the trailing entry's load is issued first and the
+                    // panel's dot product (two chains) runs while it travels
+                    const double tq = a > q ? To[a + (int64_t)q * ldo] : To[q + (int64_t)a * ldo];
+                    double d0 = 0.0, d1 = 0.0;
+                    int cc = 0;
+                    for (; cc + 1 < c; cc += 2) {
+                        d0 = fma(P[a * PLD + cc], P[q * PLD + cc], d0);
+                        d1 = fma(P[a * PLD + cc + 1], P[q * PLD + cc + 1], d1);
+                    }
+                    if (cc < c) d0 = fma(P[a * PLD + cc], P[q * PLD + cc], d0);
+                    const double t = tq - (d0 + d1);
                     const double l = lqq > 0.0 ? t / lqq : t * 0.0;
                     P[a * PLD + c] = l;
                     dnxt[a * dsn] = dcur[a * dst] - l * l;
