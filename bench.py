@@ -362,9 +362,12 @@ def bench_climate(a, torch, lib):
         log(f"fp64: {ms64:.2f} ms/step; jacobi stats {st64}")
         rho64 = int(res64.offsets[-1].item())
         path64 = path_roofline(m, p, n, rho64, 8, PEAK["f64_TF"], tf64, ms64)
-        roof64 = svd_roofline(st64, a.steps, m, p, n, rho64, PEAK["f64_TF"],
-                              load_traffic(f"jacobi_round_f64_{m}x{p}x{n}", sha),
+        # the FP64 path's round launches are of two instances (the FP32
+        # first stage on the Gram factors, the FP64 rotation form on the
+        # rotated slices); their counter traffic is in the profile summary
+        roof64 = svd_roofline(st64, a.steps, m, p, n, rho64, PEAK["f64_TF"], None,
                               path64["algorithmic_bytes"])
+        roof64["kernel"] = "jacobi_round (FP32 first stage + FP64 rotation form)"
         roof64["src_sha"] = sha
         d = ops.tsvdm_error(res64.A_rec, res_mix.A_rec).double().cpu()
         nA = float(res64.err[1].cpu())
