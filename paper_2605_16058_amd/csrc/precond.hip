@@ -630,9 +630,10 @@ __global__ __launch_bounds__(256) void pc_unshift_batch(const GramSlice* __restr
 }
 
 // Preconditioned rotation form: W (r x r per slice) = the columns of B
-// scaled to unit norm; a column of zero or non-finite norm (a failed
-// factorisation) sets *flag to TSVDM_E_NONFINITE unless it already holds a
-// condition.
+// scaled to unit norm.  A zero column comes only from a zero slice (the
+// shift then is 0 and so is every column): it becomes the unit vector e_j,
+// so that W = I there.  A non-finite norm sets *flag to TSVDM_E_NONFINITE
+// unless it already holds a condition.
 template <class BT, class T>
 __global__ __launch_bounds__(256) void pc_normalize(const BT* __restrict__ B, int64_t r, T* __restrict__ W,
                                                     int32_t* __restrict__ flag) {
@@ -652,10 +653,13 @@ __global__ __launch_bounds__(256) void pc_normalize(const BT* __restrict__ B, in
     }
     const double n2 = red[0];
     const bool ok = n2 > 0.0 && isfinite(n2);
-    if (!ok && threadIdx.x == 0) atomicCAS(flag, (int32_t)TSVDM_OK, (int32_t)TSVDM_E_NONFINITE);
+    if (!isfinite(n2) && threadIdx.x == 0) atomicCAS(flag, (int32_t)TSVDM_OK, (int32_t)TSVDM_E_NONFINITE);
     const double inv = ok ? 1.0 / sqrt(n2) : 0.0;
     T* w = W + s * r * r + j * r;
-    for (int64_t i = threadIdx.x; i < r; i += 256) w[i] = (T)((double)b[i] * inv);
+    if (n2 == 0.0)
+        for (int64_t i = threadIdx.x; i < r; i += 256) w[i] = i == j ? T(1) : T(0);
+    else
+        for (int64_t i = threadIdx.x; i < r; i += 256) w[i] = (T)((double)b[i] * inv);
 }
 
 // In place on C = W^T W (lower triangle read): S = (3 I - C) / 2 in both
