@@ -676,23 +676,27 @@ def bench_climate6(a, torch, lib):
     n1, n2 = dims[0], dims[1]
     flat_dims = (n1, n2, dims[2], int(np.prod(dims[3:])))
     flat_M = [w.M[0], synth.dct2_matrix(flat_dims[3])]
-    block = a.block
+    # the Jacobi block width of each path, timed on that path (the FP64
+    # path's slice SVDs run other kernels than the FP32 path's)
+    blocks = {"f32": a.block, "f64": a.block}
     tuned = {}
-    if not block and not a.no_tune:
+    for prec in ("f32",) + (() if a.no_f64 else ("f64",)):
+        if blocks[prec] or a.no_tune:
+            continue
         t = {}
         for b in (16, 32):
-            op = TSVDMd(dims, w.M, mode="II", eps=eps, precision="f32", block=b)
+            op = TSVDMd(dims, w.M, mode="II", eps=eps, precision=prec, block=b)
             op(Ad)
             torch.cuda.synchronize()
             _, ms = timed(lambda: op(Ad), 1, torch)
             t[b] = round(ms, 2)
             del op
-        block = min(t, key=t.get)
-        tuned = {"block": block, "measured_ms": t}
-        log(f"block widths {t}: using {block}")
+        blocks[prec] = min(t, key=t.get)
+        tuned[prec] = {"block": blocks[prec], "measured_ms": t}
+        log(f"{prec} block widths {t}: using {blocks[prec]}")
 
     def run(d_, Ms, prec, stats=False):
-        op = TSVDMd(d_, Ms, mode="II", eps=eps, precision=prec, block=block)
+        op = TSVDMd(d_, Ms, mode="II", eps=eps, precision=prec, block=blocks[prec])
         # the same bytes viewed with other dimensions (column-major reshape)
         X = Ad.permute(*range(len(dims) - 1, -1, -1)).reshape(*reversed(d_)).permute(
             *range(len(d_) - 1, -1, -1))
