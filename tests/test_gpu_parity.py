@@ -237,6 +237,14 @@ def test_slice_svd_gram_matches_oracle(ops, shape, block):
             Q = Bi[:, ok] / nb[ok]
             assert np.max(np.abs(Q.T @ Q - np.eye(int(ok.sum())))) <= 2e-5 * max(1, r) ** 0.5
         assert np.allclose(nb ** 2, np.maximum(s2n[i], 0) + shn[i], rtol=1e-5, atol=2 * shn[i] + 1e-300)
+        # B B^T = G + s I with the rows of B at the slice's own (unpivoted)
+        # indices: the pivoted factor's rows go back to where they came from.
+        # FP32 entries of B and FP32 rotations: r-term sums of FP32 products,
+        # bounded by 64 r u32 (sigma_max^2 + s); a misplaced row is an O(1) error.
+        X = A[:, :, i] if m < p else A[:, :, i].T
+        G = X @ X.T
+        err = np.max(np.abs(Bi @ Bi.T - G - shn[i] * np.eye(r)))
+        assert err <= 64 * r * 2.0 ** -24 * (smax ** 2 + shn[i]) + 1e-300, (i, err)
 
 
 @pytest.mark.parametrize("shape", [(40, 60, 3), (260, 300, 2)])   # factor in LDS / streamed
