@@ -678,6 +678,43 @@ __global__ void pc_ns_coef(double* __restrict__ C, int64_t r, int64_t n) {
     c[j + i * r] = out;
 }
 
+// Before the last Newton-Schulz step: rho[s] = r where max |C - I| (lower
+// triangle of C = W^T W) exceeds thr, else 0 (the step's product then
+// leaves that slice to pc_ns_keep); one workgroup per slice.
+__global__ __launch_bounds__(256) void pc_ns_check(const double* __restrict__ C, int64_t r, double thr,
+                                                   int32_t* __restrict__ rho) {
+    __shared__ double red[4];
+    const int64_t s = blockIdx.x;
+    const double* c = C + s * r * r;
+    double mx = 0.0;
+    for (int64_t e = threadIdx.x; e < r * r; e += 256) {
+        const int64_t j = e / r, i = e - j * r;
+        if (i >= j) {
+            const double d = fabs(c[e] - (i == j ? 1.0 : 0.0));
+            mx = (d > mx || d != d) ? d : mx;   // NaN wins: the step then runs and keeps it
+        }
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+        const double o = __shfl_xor(mx, off);
+        mx = (o > mx || o != o) ? o : mx;
+    }
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = mx;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double m = red[0];
+        for (int w = 1; w < 4; ++w) m = (red[w] > m || red[w] != red[w]) ? red[w] : m;
+        rho[s] = (m > thr || m != m) ? (int32_t)r : 0;
+    }
+}
+
+// W_next = W_cur for the slices whose last step was skipped (rho[s] == 0)
+__global__ void pc_ns_keep(const double* __restrict__ cur, double* __restrict__ nxt,
+                           const int32_t* __restrict__ rho, int64_t r, int64_t n) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= r * r * n) return;
+    if (rho[e / (r * r)] == 0) nxt[e] = cur[e];
+}
+
 // Ut = W^T per r x r slice
 template <class T>
 __global__ void pc_transpose(const T* __restrict__ W, int64_t r, int64_t n, T* __restrict__ Ut) {
@@ -1262,7 +1299,11 @@ int precond_impl(const T* A_hat, int dt, int64_t m, int64_t p, int64_t n, T* X, 
     //    4e-15 at worst, then rounding); the rotation form in step 4 then
     //    applies an orthogonal W, so its result keeps its own accuracy.
     //    W^T W by the Gram kernel (the columns of W as vectors), W S by the
-    //    factor product with every slice at full rank.
+    //    factor product with every slice at full rank.  The third step runs
+    //    only on the slices whose max |W^T W - I| still exceeds 32 sqrt(r)
+    //    u64, the size of the FP64 rounding of W^T W itself (a step cannot
+    //    go below it); the usual FP32 tolerances leave every slice there
+    //    after two.
     pc_rank_full<<<(unsigned)((n + 256) / 256), 256, 0, st>>>(rho, off, r, n);
     TSVDM_LAUNCH_CHECK();
     {
@@ -1273,17 +1314,29 @@ int precond_impl(const T* A_hat, int dt, int64_t m, int64_t p, int64_t n, T* X, 
         const unsigned eb = (unsigned)((r * r * n + 255) / 256);
         double* cur = Lw;
         double* nxt = W;
+        const double thr = 32.0 * sqrt((double)r) * 1.1102230246251565e-16;
         for (int it = 0; it < 3; ++it) {   // Lw -> W -> Lw -> W
             pc_gram<double><<<(unsigned)(ntri * n), 256, 0, st>>>(cur, gw, ntri, G);
             TSVDM_LAUNCH_CHECK();
+            if (it == 2) {
+                pc_ns_check<<<(unsigned)n, 256, 0, st>>>(G, r, thr, rho);
+                TSVDM_LAUNCH_CHECK();
+            }
             pc_ns_coef<<<eb, 256, 0, st>>>(G, r, n);
             TSVDM_LAUNCH_CHECK();
             rc = run_lowrank_gemm(cur, G, TSVDM_F64, r, r, n, rho, off, r * n, nxt, st);
             if (rc) return rc;
+            if (it == 2) {
+                pc_ns_keep<<<eb, 256, 0, st>>>(cur, nxt, rho, r, n);
+                TSVDM_LAUNCH_CHECK();
+            }
             double* const t = cur;
             cur = nxt;
             nxt = t;
         }
+        // every slice at full rank again for the product with the slice
+        pc_rank_full<<<(unsigned)((n + 256) / 256), 256, 0, st>>>(rho, off, r, n);
+        TSVDM_LAUNCH_CHECK();
         if (g.rows) {
             pc_transpose<double><<<eb, 256, 0, st>>>(W, r, n, Ut);
             TSVDM_LAUNCH_CHECK();
