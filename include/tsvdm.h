@@ -216,8 +216,9 @@ int tsvdm_slice_svd(void* A_hat, int dtype, int64_t m, int64_t p, int64_t n,
  *      shifted Cholesky factor, FP32 Jacobi on its columns to the FP32
  *      tol): unit columns W (r x r, FP64), approximating the short-side
  *      singular vectors, with cosines <= that tol;
- *   2. W made orthonormal to FP64 rounding by three Newton-Schulz steps
- *      W <- W (3 I - W^T W) / 2 (quadratic from ||W^T W - I|| <= r tol);
+ *   2. W made orthonormal to FP64 rounding by Newton-Schulz steps
+ *      W <- W (3 I - W^T W) / 2 (quadratic from ||W^T W - I|| <= r tol):
+ *      two, and a third on the slices still above the rounding level;
  *   3. X = W^T A_hat (m < p) or A_hat W (m >= p), one GEMM per slice;
  *   4. the one-sided Jacobi of tsvdm_slice_svd on X with W as its starting
  *      accumulator: X and W then hold exactly what tsvdm_slice_svd leaves
