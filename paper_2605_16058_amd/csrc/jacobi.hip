@@ -183,8 +183,10 @@ __global__ void jacobi_init(T* __restrict__ W, int64_t r, int64_t n, JacobiCtl* 
 // Shared-memory layout of one pair.  Both MFMA phases stream the L
 // positions in tiles of PT, each wave through its own staging region of STG
 // elements (enough for either phase's layout).  The pair Gram matrix H
-// lives in the same region afterwards as two packed symmetric FP64 buffers
-// (one per parity of the inner step); while the first is being written, the
+// lives in the same region afterwards as two packed symmetric buffers (one
+// per parity of the inner step; FP32 for FP32 vectors, which keeps a
+// workgroup under 40 KB so that four share a compute unit, FP64 otherwise);
+// while the first is being written, the
 // partial sums of every Gram tile from the three waves that do not own it
 // sit right behind it.  Q is stored
 // transposed (row a =
@@ -200,27 +202,46 @@ struct RoundCfg {
     static constexpr int NPH = NB2 / 2;                        // rotations per inner step
     static constexpr int NH = NB2 * (NB2 + 1) / 2;             // packed symmetric H
     static constexpr int SWM = (NB2 / VW < 16 ? NB2 / VW : 16) - 1;  // Q swizzle mask
+    // storage type of H between the steps of the inner sweep (the
+    // arithmetic on it is FP64 either way)
+    typedef typename std::conditional<sizeof(T) == 4, float, double>::type HT;
     static constexpr size_t stg_bytes = sizeof(T) * 4 * STG;
-    static constexpr size_t hs_bytes = sizeof(double) * 2 * NH;
+    static constexpr size_t hs_bytes = sizeof(HT) * 2 * NH;
     static constexpr size_t r1 = (stg_bytes > hs_bytes) ? stg_bytes : hs_bytes;
     static constexpr size_t q_bytes = sizeof(T) * NB2 * NB2;
     // three partial sums per Gram tile, parked behind the first H buffer
     static constexpr int NTT = NT * (NT + 1) / 2;
-    static constexpr size_t rp_off = (sizeof(double) * NH + 15) / 16 * 16;
+    static constexpr size_t rp_off = (sizeof(HT) * NH + 15) / 16 * 16;
     static constexpr size_t rp_end = rp_off + sizeof(T) * 3 * NTT * 256;
     static constexpr size_t total = (r1 + q_bytes > rp_end) ? r1 + q_bytes : rp_end;
-    // waves per SIMD the kernel is compiled for: three workgroups per compute
-    // unit when the LDS allows it (FP32), else two
-    static constexpr int WAVES = (3 * (total + 2048) <= 160 * 1024) ? 3 : 2;
+    // LDS of one workgroup (the region above plus the rotations and the
+    // reductions, in 512-byte allocation units) and the waves per SIMD the
+    // kernel is compiled for: three workgroups per compute unit when the LDS
+    // allows it, else two; four for the interior FP32 pairs of 64 vectors
+    // (OCC4 below)
+    static constexpr size_t lds_bytes = ((total + 15) / 16 * 16 + NB2 * 16 + 80 + 511) / 512 * 512;
+    static constexpr int WAVES = (3 * lds_bytes <= 160 * 1024) ? 3 : 2;
     // Q^T[a][c] = Q[c][a]
     static __device__ __forceinline__ int q_idx(int a, int c) { return a * NB2 + (c ^ ((a & SWM) * VW)); }
 };
 
+// Interior FP32 pairs of 64 vectors run four workgroups per compute unit:
+// their 40 KB of LDS allow it, and with Q read from LDS in the vector update
+// and one H block in registers at a time in the inner sweep they fit the 128
+// registers a lane then has.  The checked loads of the other instances need
+// more registers; they keep three workgroups, Q in registers and three H
+// blocks per load group.
+template <class T, int NB2, bool INT>
+struct RoundOcc {
+    static constexpr bool OCC4 = sizeof(T) == 4 && NB2 == 64 && INT;
+    static constexpr int WAVES = OCC4 ? 4 : RoundCfg<T, NB2>::WAVES;
+};
+
 // (c, s) of one rotation as the vectors see it: the angle is computed in
-// FP64 and rounded to the working precision, and the FP64 H is rotated with
-// the same rounded pair (kept as exact doubles, so the H update converts
-// nothing), so that H stays the Gram matrix of the vectors the rotations
-// actually produce.
+// FP64 and rounded to the working precision, and H is rotated in FP64 with
+// the same rounded pair (kept as exact doubles), so that H stays the Gram
+// matrix of the vectors the rotations actually produce, up to the rounding
+// of its storage (FP32 for FP32 vectors, whose own rounding is as large).
 template <class T>
 __device__ __forceinline__ double2 rot_make(double c, double s) {
     return make_double2((double)(T)c, (double)(T)s);
@@ -252,7 +273,8 @@ __device__ __forceinline__ void round_body(RoundShared<T, NB2>& sh, T* __restric
     char* smem = sh.smem;
 
     T* Ts = reinterpret_cast<T*>(smem);                           // [4][STG] per-wave staging
-    double* H0 = reinterpret_cast<double*>(smem);                 // [2][NH] packed H (phase 2)
+    typedef typename C::HT HT;
+    HT* H0 = reinterpret_cast<HT*>(smem);                         // [2][NH] packed H (phase 2)
     T* Qs = reinterpret_cast<T*>(smem + C::r1);                   // [NB2][NB2] Q^T, swizzled
 
     const int I = circle_player(k, rnd, nbe);
@@ -434,7 +456,7 @@ __device__ __forceinline__ void round_body(RoundShared<T, NB2>& sh, T* __restric
     // the staging regions, hence the barrier first, and clear of the H
     // buffer the owners fill while others still read them); each owner adds
     // the four partials of its tiles in wave order 0..3, so the result does
-    // not depend on timing, writes them into the packed FP64 H and, once
+    // not depend on timing, writes them into the packed H and, once
     // every diagonal is there, forms the convergence measure of its tiles:
     // the largest |cos| = |h_ac| / (||a|| ||c||) over valid vector pairs,
     // kept separately for pairs inside one block and pairs across the two
@@ -593,6 +615,7 @@ __device__ __forceinline__ void round_body(RoundShared<T, NB2>& sh, T* __restric
     const int ka = tid - (256 - NPH);
     // this thread's H blocks: pairs k1 <= k2; byte offsets (read | write <<
     // 16) into an H buffer and byte offsets of the two rotations
+    constexpr int HS = sizeof(HT);
     int bk1[HB], bk2[HB], rw[HB][4], ro1[HB], ro2[HB];
 #pragma unroll
     for (int b = 0; b < HB; ++b) {
@@ -609,10 +632,10 @@ __device__ __forceinline__ void round_body(RoundShared<T, NB2>& sh, T* __restric
         const int v0 = k2, v1 = partner_seat<NB2>(cross, k2);
         const int nu0 = next_seat<NB2>(cross, u0), nu1 = next_seat<NB2>(cross, u1);
         const int nv0 = next_seat<NB2>(cross, v0), nv1 = next_seat<NB2>(cross, v1);
-        rw[b][0] = 8 * sym_idx(u0, v0) | (8 * sym_idx(nu0, nv0) << 16);
-        rw[b][1] = 8 * sym_idx(u0, v1) | (8 * sym_idx(nu0, nv1) << 16);
-        rw[b][2] = 8 * sym_idx(u1, v0) | (8 * sym_idx(nu1, nv0) << 16);
-        rw[b][3] = 8 * sym_idx(u1, v1) | (8 * sym_idx(nu1, nv1) << 16);
+        rw[b][0] = HS * sym_idx(u0, v0) | (HS * sym_idx(nu0, nv0) << 16);
+        rw[b][1] = HS * sym_idx(u0, v1) | (HS * sym_idx(nu0, nv1) << 16);
+        rw[b][2] = HS * sym_idx(u1, v0) | (HS * sym_idx(nu1, nv0) << 16);
+        rw[b][3] = HS * sym_idx(u1, v1) | (HS * sym_idx(nu1, nv1) << 16);
         ro1[b] = 16 * k1;
         ro2[b] = 16 * k2;
     }
@@ -660,7 +683,7 @@ __device__ __forceinline__ void round_body(RoundShared<T, NB2>& sh, T* __restric
         if (angle_thread && step + 1 < nsteps) {
             const int xa = akp, xb = partner_seat<NB2>(cross, akp);
             const int ya = akq, yb = partner_seat<NB2>(cross, akq);
-            const double* Hd = reinterpret_cast<const double*>(Hc);
+            const HT* Hd = reinterpret_cast<const HT*>(Hc);
             double h[10];
             h[0] = Hd[sym_idx(xa, xa)]; h[1] = Hd[sym_idx(xa, xb)]; h[2] = Hd[sym_idx(xb, xb)];
             h[3] = Hd[sym_idx(ya, ya)]; h[4] = Hd[sym_idx(ya, yb)]; h[5] = Hd[sym_idx(yb, yb)];
@@ -680,7 +703,7 @@ __device__ __forceinline__ void round_body(RoundShared<T, NB2>& sh, T* __restric
         // ---- H <- J^T H J on this thread's 2x2 blocks, written on the next
         // seats; all of the thread's blocks (up to three) loaded before any is
         // rotated, so that the step waits for LDS once
-        constexpr int HG = 3;
+        constexpr int HG = RoundOcc<T, NB2, INT>::OCC4 ? 1 : 3;
 #pragma unroll
         for (int b0 = 0; b0 < HB; b0 += HG) {
             double hv[HG][4];
@@ -690,7 +713,7 @@ __device__ __forceinline__ void round_body(RoundShared<T, NB2>& sh, T* __restric
                 const int b = b0 + u;
                 if (b < HB && bk1[b] >= 0) {
 #pragma unroll
-                    for (int e = 0; e < 4; ++e) hv[u][e] = *reinterpret_cast<const double*>(Hc + (rw[b][e] & 0xffff));
+                    for (int e = 0; e < 4; ++e) hv[u][e] = *reinterpret_cast<const HT*>(Hc + (rw[b][e] & 0xffff));
                     r1[u] = *reinterpret_cast<const double2*>(rcb + ro1[b]);
                     r2[u] = *reinterpret_cast<const double2*>(rcb + ro2[b]);
                 }
@@ -702,10 +725,10 @@ __device__ __forceinline__ void round_body(RoundShared<T, NB2>& sh, T* __restric
                 const double c1 = r1[u].x, s1 = r1[u].y, c2 = r2[u].x, s2 = r2[u].y;
                 const double t0 = c2 * hv[u][0] - s2 * hv[u][1], t1 = s2 * hv[u][0] + c2 * hv[u][1];
                 const double t2 = c2 * hv[u][2] - s2 * hv[u][3], t3 = s2 * hv[u][2] + c2 * hv[u][3];
-                *reinterpret_cast<double*>(Hn + (rw[b][0] >> 16)) = c1 * t0 - s1 * t2;
-                *reinterpret_cast<double*>(Hn + (rw[b][1] >> 16)) = c1 * t1 - s1 * t3;
-                if (bk1[b] != bk2[b]) *reinterpret_cast<double*>(Hn + (rw[b][2] >> 16)) = s1 * t0 + c1 * t2;
-                *reinterpret_cast<double*>(Hn + (rw[b][3] >> 16)) = s1 * t1 + c1 * t3;
+                *reinterpret_cast<HT*>(Hn + (rw[b][0] >> 16)) = c1 * t0 - s1 * t2;
+                *reinterpret_cast<HT*>(Hn + (rw[b][1] >> 16)) = c1 * t1 - s1 * t3;
+                if (bk1[b] != bk2[b]) *reinterpret_cast<HT*>(Hn + (rw[b][2] >> 16)) = s1 * t0 + c1 * t2;
+                *reinterpret_cast<HT*>(Hn + (rw[b][3] >> 16)) = s1 * t1 + c1 * t3;
             }
         }
         // ---- Q <- Q J: rows qp, qq of Q^T, groups of GW entries at qc0,
@@ -739,7 +762,7 @@ __device__ __forceinline__ void round_body(RoundShared<T, NB2>& sh, T* __restric
     // In FP32 the MFMA operand fragments of Q (Q[c][a] for c = kk + lg,
     // a = 16 ta + lr) stay in registers for both products, NB2 / 4 x NT
     // values a lane; FP64 reads them from LDS (its registers are full).
-    constexpr bool QREG = sizeof(T) == 4;
+    constexpr bool QREG = sizeof(T) == 4 && !RoundOcc<T, NB2, INT>::OCC4;
     T qf[QREG ? NB2 / 4 : 1][NT];
     if constexpr (QREG) {
 #pragma unroll
@@ -901,14 +924,22 @@ __device__ __forceinline__ void round_body(RoundShared<T, NB2>& sh, T* __restric
     }
 }
 
-// FP32 pairs of 64 vectors keep three workgroups per 160 KB compute unit.
-static_assert(sizeof(RoundShared<float, 64>) <= 160 * 1024 / 3, "LDS budget of jacobi_round<float, 64>");
-// FP64 pairs of 64 vectors keep two.
-static_assert(sizeof(RoundShared<double, 64>) <= 160 * 1024 / 2, "LDS budget of jacobi_round<double, 64>");
+// The LDS of a workgroup is what the waves-per-SIMD figure assumes: FP32
+// pairs of 64 vectors run four workgroups per 160 KB compute unit, FP64 pairs
+// of 64 vectors two.
+template <class T, int NB2>
+constexpr bool lds_fits() {
+    return sizeof(RoundShared<T, NB2>) <= RoundCfg<T, NB2>::lds_bytes &&
+           RoundOcc<T, NB2, true>::WAVES * RoundCfg<T, NB2>::lds_bytes <= 160 * 1024;
+}
+static_assert(lds_fits<float, 32>() && lds_fits<float, 64>() && lds_fits<double, 32>() && lds_fits<double, 64>(),
+              "LDS budget of jacobi_round");
+static_assert(RoundOcc<float, 64, true>::WAVES == 4 && RoundCfg<float, 64>::WAVES == 3 &&
+              RoundCfg<double, 64>::WAVES == 2, "workgroups per compute unit");
 
 // One round for every (slice, pair) of a tensor of identical slices.
 template <class T, int NB2, bool ROWS, bool INT>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(RoundCfg<T, NB2>::WAVES)))
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(RoundOcc<T, NB2, INT>::WAVES)))
 void jacobi_round(T* __restrict__ A, T* __restrict__ W, SliceGeom g,
                                                     int nbe, int rnd, JacobiCtl* __restrict__ ctl,
                                                     double tol, int vec_a, int vec_w,
