@@ -217,7 +217,7 @@ struct RoundCfg {
     // LDS of one workgroup (the region above plus the rotations and the
     // reductions, in 512-byte allocation units) and the waves per SIMD the
     // kernel is compiled for: three workgroups per compute unit when the LDS
-    // allows it, else two; four for the interior FP32 pairs of 64 vectors
+    // allows it, else two; four for the FP32 pairs of 64 vectors
     // (OCC4 below)
     static constexpr size_t lds_bytes = ((total + 15) / 16 * 16 + NB2 * 16 + 80 + 511) / 512 * 512;
     static constexpr int WAVES = (3 * lds_bytes <= 160 * 1024) ? 3 : 2;
@@ -225,15 +225,15 @@ struct RoundCfg {
     static __device__ __forceinline__ int q_idx(int a, int c) { return a * NB2 + (c ^ ((a & SWM) * VW)); }
 };
 
-// Interior FP32 pairs of 64 vectors run four workgroups per compute unit:
-// their 40 KB of LDS allow it, and with Q read from LDS in the vector update
-// and one H block in registers at a time in the inner sweep they fit the 128
-// registers a lane then has.  The checked loads of the other instances need
-// more registers; they keep three workgroups, Q in registers and three H
-// blocks per load group.
-template <class T, int NB2, bool INT>
+// FP32 pairs of 64 vectors run four workgroups per compute unit: their
+// 40 KB of LDS allow it, and with Q read from LDS in the vector update and
+// one H block in registers at a time in the inner sweep the interior
+// instances fit the 128 registers a lane then has.  The instances with
+// checked loads spill a few registers at that budget and still gain from
+// the fourth workgroup.
+template <class T, int NB2>
 struct RoundOcc {
-    static constexpr bool OCC4 = sizeof(T) == 4 && NB2 == 64 && INT;
+    static constexpr bool OCC4 = sizeof(T) == 4 && NB2 == 64;
     static constexpr int WAVES = OCC4 ? 4 : RoundCfg<T, NB2>::WAVES;
 };
 
@@ -703,7 +703,7 @@ __device__ __forceinline__ void round_body(RoundShared<T, NB2>& sh, T* __restric
         // ---- H <- J^T H J on this thread's 2x2 blocks, written on the next
         // seats; all of the thread's blocks (up to three) loaded before any is
         // rotated, so that the step waits for LDS once
-        constexpr int HG = RoundOcc<T, NB2, INT>::OCC4 ? 1 : 3;
+        constexpr int HG = RoundOcc<T, NB2>::OCC4 ? 1 : 3;
 #pragma unroll
         for (int b0 = 0; b0 < HB; b0 += HG) {
             double hv[HG][4];
@@ -762,7 +762,7 @@ __device__ __forceinline__ void round_body(RoundShared<T, NB2>& sh, T* __restric
     // In FP32 the MFMA operand fragments of Q (Q[c][a] for c = kk + lg,
     // a = 16 ta + lr) stay in registers for both products, NB2 / 4 x NT
     // values a lane; FP64 reads them from LDS (its registers are full).
-    constexpr bool QREG = sizeof(T) == 4 && !RoundOcc<T, NB2, INT>::OCC4;
+    constexpr bool QREG = sizeof(T) == 4 && !RoundOcc<T, NB2>::OCC4;
     T qf[QREG ? NB2 / 4 : 1][NT];
     if constexpr (QREG) {
 #pragma unroll
@@ -930,16 +930,16 @@ __device__ __forceinline__ void round_body(RoundShared<T, NB2>& sh, T* __restric
 template <class T, int NB2>
 constexpr bool lds_fits() {
     return sizeof(RoundShared<T, NB2>) <= RoundCfg<T, NB2>::lds_bytes &&
-           RoundOcc<T, NB2, true>::WAVES * RoundCfg<T, NB2>::lds_bytes <= 160 * 1024;
+           RoundOcc<T, NB2>::WAVES * RoundCfg<T, NB2>::lds_bytes <= 160 * 1024;
 }
 static_assert(lds_fits<float, 32>() && lds_fits<float, 64>() && lds_fits<double, 32>() && lds_fits<double, 64>(),
               "LDS budget of jacobi_round");
-static_assert(RoundOcc<float, 64, true>::WAVES == 4 && RoundCfg<float, 64>::WAVES == 3 &&
+static_assert(RoundOcc<float, 64>::WAVES == 4 && RoundCfg<float, 64>::WAVES == 3 &&
               RoundCfg<double, 64>::WAVES == 2, "workgroups per compute unit");
 
 // One round for every (slice, pair) of a tensor of identical slices.
 template <class T, int NB2, bool ROWS, bool INT>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(RoundOcc<T, NB2, INT>::WAVES)))
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(RoundOcc<T, NB2>::WAVES)))
 void jacobi_round(T* __restrict__ A, T* __restrict__ W, SliceGeom g,
                                                     int nbe, int rnd, JacobiCtl* __restrict__ ctl,
                                                     double tol, int vec_a, int vec_w,
@@ -958,7 +958,7 @@ void jacobi_round(T* __restrict__ A, T* __restrict__ W, SliceGeom g,
 // shapes: task = (slice, pair); slice s is in round t mod (nbe_s - 1) of its
 // own tournament, so slices with fewer blocks simply run more sweeps.
 template <class T, int NB2>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(RoundCfg<T, NB2>::WAVES)))
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(RoundOcc<T, NB2>::WAVES)))
 void jacobi_round_batch(const BatchSlice* __restrict__ sl,
                                                           const int2* __restrict__ tasks, int t,
                                                           JacobiCtl* __restrict__ ctl,
