@@ -436,8 +436,11 @@ __device__ __forceinline__ double row_sum16(double x) {
 // r x r factor of slice blockIdx.x stays in LDS (r x (r + 1) floats,
 // dynamic) for all its sweeps: one workgroup per slice, no launch per
 // round.  A round of the circle tournament pairs the columns disjointly;
-// sixteen groups of 16 lanes (one DPP row each) take its pairs, two at a
-// time so that their latencies overlap: the three dot products in FP64
+// sixteen groups of 16 lanes (one DPP row each) take its pairs, group g
+// the pairs g, g + 16, ..., two at a time so that their latencies overlap
+// (a wave skips the pair slots none of its four groups has, so that at
+// r = 73, 37 pairs, two waves work on three pairs and two on two): the
+// three dot products in FP64
 // from exact FP32 products (lane i holds elements i, i + 16, ...), summed
 // over the row by DPP, the FP64 angle and the FP32 rotation of the two
 // columns; one barrier per round.  The slice has converged after the first
@@ -456,6 +459,7 @@ __device__ __forceinline__ void jacobi_lds_slice(float* __restrict__ Bs, int rr,
     __shared__ double gmax[16];
     __shared__ int gbad[16];
     const int tid = threadIdx.x, grp = tid >> 4, l = tid & 15;
+    const int grp0 = grp & ~3;       // first group of this wave
     const int RP = rr + 1;
     for (int idx = tid; idx < rr * rr; idx += 256) {
         const int j = idx / rr, i = idx - j * rr;
@@ -470,14 +474,16 @@ __device__ __forceinline__ void jacobi_lds_slice(float* __restrict__ Bs, int rr,
         const double thr = polish ? 0.0 : tol;
         double mx = 0.0;
         for (int rnd = 0; rnd < R - 1; ++rnd) {
-            for (int k0 = grp; k0 < NP; k0 += 32) {
-                // this group's pairs k0 and k0 + 16 of the round (either may
-                // be the padding player's or absent): uniform in the group
+            for (int k0 = 0; grp0 + k0 < NP; k0 += 32) {
+                // this group's pairs grp + k0 and grp + k0 + 16 of the round
+                // (either may be the padding player's or absent): uniform in
+                // the group; slot u is worked on by the wave when one of its
+                // groups has it
                 int pp[2], qq[2];
                 bool use[2];
 #pragma unroll
                 for (int u = 0; u < 2; ++u) {
-                    const int k = k0 + 16 * u;
+                    const int k = grp + k0 + 16 * u;
                     pp[u] = lds_player(k, rnd, R);
                     qq[u] = lds_player(R - 1 - k, rnd, R);
                     use[u] = k < NP && pp[u] < rr && qq[u] < rr;
@@ -486,6 +492,7 @@ __device__ __forceinline__ void jacobi_lds_slice(float* __restrict__ Bs, int rr,
                 double app[2], aqq[2], apq[2];
 #pragma unroll
                 for (int u = 0; u < 2; ++u) {
+                    if (grp0 + k0 + 16 * u >= NP) continue;
                     const float* xp = X + (use[u] ? pp[u] : 0) * RP;
                     const float* xq = X + (use[u] ? qq[u] : 0) * RP;
 #pragma unroll
@@ -498,6 +505,7 @@ __device__ __forceinline__ void jacobi_lds_slice(float* __restrict__ Bs, int rr,
                 }
 #pragma unroll
                 for (int u = 0; u < 2; ++u) {
+                    if (grp0 + k0 + 16 * u >= NP) continue;
                     double a0 = 0.0, b0 = 0.0, c0 = 0.0;
 #pragma unroll
                     for (int e = 0; e < E; ++e) {
