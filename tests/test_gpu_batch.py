@@ -160,12 +160,14 @@ def test_batch_graph_replays_equal_eager(ragged):
             assert torch.equal(b.A_rec[t], ref[t]), (rep, t)
 
 
-def test_batch_mixed_routes_equal_single_calls():
+@pytest.mark.parametrize("block", [16, 32])
+def test_batch_mixed_routes_equal_single_calls(block):
     """FP32 batches whose tensors take every slice-SVD route (the Gram form
     up to GRAM_MAX_R with the Jacobi in the block rounds, or in LDS when the
     whole batch is small; the rotation form above GRAM_MAX_R) equal the
     single-tensor calls of the same form bit for bit, and their FP32 errors
-    stay below eps."""
+    stay below eps.  Block 32 (pairs of 64 vectors) runs the batched round
+    instance with checked loads at four workgroups per compute unit."""
     from paper_2605_16058_amd.pipeline import BatchTSVDM, tsvdm
     g = np.random.default_rng(77)
     shapes = [(40, 60, 5), (210, 230, 3), (150, 90, 4), (230, 200, 2), (129, 300, 2), (128, 128, 2),
@@ -185,7 +187,7 @@ def test_batch_mixed_routes_equal_single_calls():
         gj = plan_gram_jacobi([shapes[t] for t in sel])
         print(f"batch of {len(sel)} tensors, Gram-form Jacobi: {gj}", flush=True)
         b = BatchTSVDM([Ts[t] for t in sel], [Ms[t] for t in sel], [modes[t] for t in sel],
-                       ks=[ks[t] for t in sel], epss=[epss[t] for t in sel], precision="f32", block=16)
+                       ks=[ks[t] for t in sel], epss=[epss[t] for t in sel], precision="f32", block=block)
         st = b.run(host_poll=True)
         torch.cuda.synchronize()
         assert int(st.item()) == 0
@@ -194,7 +196,7 @@ def test_batch_mixed_routes_equal_single_calls():
             A = Ts[t]
             svd = "gram" if min(A.shape[0], A.shape[1]) <= GRAM_MAX_R else "jacobi"
             print(f"tensor {t} {tuple(A.shape)}: {svd} form, rel error {errs[i]:.6e}", flush=True)
-            res = tsvdm(A, Ms[t], mode=modes[t], k=ks[t], eps=epss[t], precision="f32", block=16, svd=svd,
+            res = tsvdm(A, Ms[t], mode=modes[t], k=ks[t], eps=epss[t], precision="f32", block=block, svd=svd,
                         guard="bound", gram_jacobi=gj)
             torch.cuda.synchronize()
             assert torch.equal(res.rho, b.rho[i]), t
