@@ -173,20 +173,25 @@ __global__ __launch_bounds__(256) void pc_gram_batch(const GramSlice* __restrict
 // between two LDS buffers and a pivot's mark carries its step.  A pivot <= 0 (rounding of a singular G + s I) gives a zero
 // column; non-finite values stay non-finite.  Fixed operation order: the
 // result does not depend on timing.
-// Threads of a Cholesky workgroup.  A launch has one workgroup per slice,
-// often no more than the compute units, so the waves of one workgroup are
-// what hides the latency of the trailing update's loads: sixteen of them
-// (0.68 ms less than four over 256 slices of 512, 7.2 ms less over 64 of
-// 1024; the trace keeps its four-wave summation order, so the results are
-// the same bits).
-constexpr int CHOL_THREADS = 1024;
+// Threads of a Cholesky workgroup (one workgroup per slice).  A launch of
+// few slices, no more than the compute units can hold at once, relies on
+// the waves of one workgroup to hide the latency of the trailing update's
+// loads: sixteen waves for fewer than CHOL_WIDE_MAX slices of more than 256
+// rows (0.68 ms less than four over 256 slices of 512, 7.2 ms less over 64
+// of 1024).  A launch of many slices has the workgroups for that, and four
+// waves keep its idle lanes and redundant pivot searches down (sixteen cost
+// 4.2 ms over 3,566 slices of 257-384 rows, 18 ms over 49,640 of 73).  The
+// trace keeps its four-wave summation order either way: the results are
+// the same bits.
+constexpr int64_t CHOL_WIDE_MAX = 512;
+constexpr bool chol_wide(int64_t r, int64_t slices) { return r > 256 && slices < CHOL_WIDE_MAX; }
 
-template <int MAXR, class OT>
+template <int MAXR, class OT, int NT>
 __device__ __forceinline__ void chol_slice(double* __restrict__ Gs, int64_t r, double cshift,
                                            double* __restrict__ Ws, OT* __restrict__ Os,
                                            double* __restrict__ shift_out) {
     constexpr int PLD = CB + 1;                // column CB: the updated diagonal (even steps)
-    constexpr int NT = CHOL_THREADS, NW = NT / 64;
+    constexpr int NW = NT / 64;
     constexpr int PER = (MAXR + NT - 1) / NT;  // positions per thread
     __shared__ double P[MAXR * PLD];           // panel columns by trailing position
     __shared__ double dodd[MAXR];              // the updated diagonal after odd steps
@@ -396,21 +401,21 @@ __device__ __forceinline__ void chol_slice(double* __restrict__ Gs, int64_t r, d
     }
 }
 
-template <int MAXR, class OT>
-__global__ __launch_bounds__(CHOL_THREADS) void pc_chol(double* __restrict__ G, int64_t r, double cshift,
+template <int MAXR, class OT, int NT>
+__global__ __launch_bounds__(NT) void pc_chol(double* __restrict__ G, int64_t r, double cshift,
                                                double* __restrict__ Lw, OT* __restrict__ Lo,
                                                double* __restrict__ shift) {
     const int64_t s = blockIdx.x;
-    chol_slice<MAXR, OT>(G + s * r * r, r, cshift, Lw + s * r * r, Lo + s * r * r, shift + s);
+    chol_slice<MAXR, OT, NT>(G + s * r * r, r, cshift, Lw + s * r * r, Lo + s * r * r, shift + s);
 }
 
 // batch: one workgroup per Gram slice listed (one size class, r <= MAXR)
-template <int MAXR>
-__global__ __launch_bounds__(CHOL_THREADS) void pc_chol_batch(const GramSlice* __restrict__ gs,
+template <int MAXR, int NT>
+__global__ __launch_bounds__(NT) void pc_chol_batch(const GramSlice* __restrict__ gs,
                                                      const int* __restrict__ list) {
     const GramSlice d = gs[list[blockIdx.x]];
     const double cshift = (double)(d.g.L + d.g.r) * 1.1102230246251565e-16;
-    chol_slice<MAXR, float>(d.G, d.g.r, cshift, d.Lw, d.B, d.shift);
+    chol_slice<MAXR, float, NT>(d.G, d.g.r, cshift, d.Lw, d.B, d.shift);
 }
 
 // seat -> player of the circle tournament over N (even) players in round
@@ -1103,10 +1108,16 @@ int run_gram_prep_batch(const GramSlice* gs, int64_t ngram, const int2* gram_tas
         const int* list = lists + class_off[c];
         const unsigned cnt = (unsigned)class_cnt[c];
         switch (CHOL_RMAX[c]) {
-            case 128: pc_chol_batch<128><<<cnt, CHOL_THREADS, 0, st>>>(gs, list); break;
-            case 256: pc_chol_batch<256><<<cnt, CHOL_THREADS, 0, st>>>(gs, list); break;
-            case 512: pc_chol_batch<512><<<cnt, CHOL_THREADS, 0, st>>>(gs, list); break;
-            default: pc_chol_batch<1024><<<cnt, CHOL_THREADS, 0, st>>>(gs, list); break;
+            case 128: pc_chol_batch<128, 256><<<cnt, 256, 0, st>>>(gs, list); break;
+            case 256: pc_chol_batch<256, 256><<<cnt, 256, 0, st>>>(gs, list); break;
+            case 512:
+                if (chol_wide(512, cnt)) pc_chol_batch<512, 1024><<<cnt, 1024, 0, st>>>(gs, list);
+                else pc_chol_batch<512, 256><<<cnt, 256, 0, st>>>(gs, list);
+                break;
+            default:
+                if (chol_wide(1024, cnt)) pc_chol_batch<1024, 1024><<<cnt, 1024, 0, st>>>(gs, list);
+                else pc_chol_batch<1024, 256><<<cnt, 256, 0, st>>>(gs, list);
+                break;
         }
         TSVDM_LAUNCH_CHECK();
     }
@@ -1181,10 +1192,13 @@ int gram_factor(const T* A_hat, const SliceGeom& g, int64_t n, double* G, double
     pc_gram<T><<<(unsigned)(ntri * n), 256, 0, st>>>(A_hat, g, ntri, G);
     TSVDM_LAUNCH_CHECK();
     const double cshift = (double)(g.L + r) * 1.1102230246251565e-16;
-    if (r <= 128) pc_chol<128, OT><<<(unsigned)n, CHOL_THREADS, 0, st>>>(G, r, cshift, Lw, B, shift);
-    else if (r <= 256) pc_chol<256, OT><<<(unsigned)n, CHOL_THREADS, 0, st>>>(G, r, cshift, Lw, B, shift);
-    else if (r <= 512) pc_chol<512, OT><<<(unsigned)n, CHOL_THREADS, 0, st>>>(G, r, cshift, Lw, B, shift);
-    else pc_chol<1024, OT><<<(unsigned)n, CHOL_THREADS, 0, st>>>(G, r, cshift, Lw, B, shift);
+    const bool wide = chol_wide(r, n);
+    if (r <= 128) pc_chol<128, OT, 256><<<(unsigned)n, 256, 0, st>>>(G, r, cshift, Lw, B, shift);
+    else if (r <= 256) pc_chol<256, OT, 256><<<(unsigned)n, 256, 0, st>>>(G, r, cshift, Lw, B, shift);
+    else if (r <= 512 && wide) pc_chol<512, OT, 1024><<<(unsigned)n, 1024, 0, st>>>(G, r, cshift, Lw, B, shift);
+    else if (r <= 512) pc_chol<512, OT, 256><<<(unsigned)n, 256, 0, st>>>(G, r, cshift, Lw, B, shift);
+    else if (wide) pc_chol<1024, OT, 1024><<<(unsigned)n, 1024, 0, st>>>(G, r, cshift, Lw, B, shift);
+    else pc_chol<1024, OT, 256><<<(unsigned)n, 256, 0, st>>>(G, r, cshift, Lw, B, shift);
     TSVDM_LAUNCH_CHECK();
     return TSVDM_OK;
 }
