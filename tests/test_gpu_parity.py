@@ -247,6 +247,24 @@ def test_slice_svd_gram_matches_oracle(ops, shape, block):
         assert err <= 64 * r * 2.0 ** -24 * (smax ** 2 + shn[i]) + 1e-300, (i, err)
 
 
+# The pivoted Cholesky of slices of more than 256 rows runs 1024 threads per
+# workgroup in launches of fewer than 512 slices and 256 in larger ones.
+# Both forms take the same operations in the same order, and the Jacobi
+# treats every slice on its own, so a slice's factor, values and shift are
+# the same bits in a launch of 520 slices and in one of 8.
+def test_slice_svd_gram_cholesky_launch_forms_agree(ops):
+    m, p, n, k = 300, 320, 520, 8
+    g = np.random.default_rng(31)
+    A = (g.standard_normal((m, p, n)) * np.logspace(0, -3, p)[None, :, None]).astype(np.float32)
+    B, s2, sh, st = ops.tsvdm_slice_svd_gram(to_dev(A, torch.float32))
+    Bk, s2k, shk, stk = ops.tsvdm_slice_svd_gram(to_dev(A[:, :, :k], torch.float32))
+    torch.cuda.synchronize()
+    assert int(st.item()) == 0 and int(stk.item()) == 0
+    assert torch.equal(sh[:k], shk)
+    assert torch.equal(s2[:k], s2k)
+    assert torch.equal(B[:k], Bk)
+
+
 @pytest.mark.parametrize("shape", [(40, 60, 3), (260, 300, 2)])   # factor in LDS / streamed
 def test_slice_svd_gram_status(ops, shape):
     g = np.random.default_rng(sum(shape))
