@@ -304,6 +304,34 @@ def transform_timing(a, Ad, M, torch, tf):
     return out
 
 
+def transform_only(a):
+    """The dense transform Y = A x_3 M alone, back to back: the rate of the
+    kernel by itself, for comparison with the stand-alone timing inside a
+    benchmark run (which follows the timed steps)."""
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_2605_16058_amd import autotune, ops
+    m, p, n = (int(x) for x in a.shape.split(","))
+    g = np.random.default_rng(5)
+    Ad = ops.colmajor_empty(m, p, n, torch.float32, "cuda")
+    Ad.copy_(torch.from_numpy(g.standard_normal((m, p, n)).astype(np.float32)))
+    Md = ops.device_matrix(synth.haar_orthogonal(n, g))
+    ws = ops.Workspace(Ad.device)
+    out = {"workload": f"dense mode-3 transform {m}x{p}x{n}, Haar M, default tiles"}
+    flops = 2.0 * m * p * n * n
+    for compute, dt, peak in (("f32", torch.float32, PEAK["f32_TF"]), ("f64", torch.float64, PEAK["f64_TF"])):
+        Y = ops.colmajor_empty(m, p, n, dt, "cuda")
+        t = autotune.time_ms(lambda: ops.tsvdm_transform(Ad, Md, compute=compute, out_dtype=dt, out=Y, ws=ws),
+                             reps=10, warmup=2)
+        out[compute] = {"ms": round(t, 4), "TFLOP_s": round(flops / (t * 1e-3) / 1e12, 1),
+                        "frac": round(flops / (t * 1e-3) / 1e12 / peak, 4)}
+        del Y
+    print(json.dumps(out), flush=True)
+    return 0
+
+
 def bench_climate(a, torch, lib):
     import numpy as np
 
@@ -867,6 +895,9 @@ def main(argv=None):
     ap.add_argument("--no-tune", action="store_true", help="library defaults, no autotuner")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB device copy (for scaling HBM counters)")
+    ap.add_argument("--transform-only", action="store_true",
+                    help="only time the dense mode-3 transform on --shape (Haar M, default tiles, "
+                         "FP32 and FP64, 10 calls each), as a kernel measured by itself")
     a = ap.parse_args(argv)
 
     if a.calibrate_copy:
@@ -878,6 +909,9 @@ def main(argv=None):
         torch.cuda.synchronize()
         print(json.dumps({"copy_bytes": x.numel() * 4, "repeats": 3}), flush=True)
         return 0
+
+    if a.transform_only:
+        return transform_only(a)
 
     if a.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {a.gpus}); every box here has a "
